@@ -1,0 +1,101 @@
+"""CPU oracle for Expected Force (ctypes over ``liboracle.so``, built from
+``ef_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY. It may be imported by ``tests/``, by
+``__graft_entry__.smoke()`` and by the CPU-baseline leg of ``bench.py``;
+nothing in the GPU library imports, links or calls it, and it shares no code
+with that library.
+
+What it computes is the plain definition: per seed, every ordered pair of
+transmission events, the degree of the resulting three-node cluster (edges
+leaving it), the histogram of those degrees and the entropy of Eq. 1 of
+"Scaling Expected Force" (Sec. 3.3), in double precision, with the
+multiplicities of Algorithm 1. See ``ef_oracle.c`` for the exact statement.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+SRC_PATH = os.path.join(_HERE, "ef_oracle.c")
+
+_lib = None
+
+
+def build():
+    tmp = LIB_PATH + ".tmp"
+    subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", SRC_PATH,
+                    "-lm", "-o", tmp], check=True)
+    os.replace(tmp, LIB_PATH)
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        build()
+    lib = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    lib.oracle_ef.argtypes = [ctypes.c_int32, vp, vp, vp, ctypes.c_int32, vp, vp, vp,
+                              ctypes.c_int32]
+    lib.oracle_ef.restype = ctypes.c_int
+    lib.oracle_histogram.argtypes = [ctypes.c_int32, vp, vp, ctypes.c_int32, vp, vp,
+                                     ctypes.c_int64]
+    lib.oracle_histogram.restype = ctypes.c_int64
+    _lib = lib
+    return lib
+
+
+def _csr(row_ptr, col_idx):
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    if ci.size == 0:
+        ci = np.zeros(1, np.int32)
+    return rp, ci
+
+
+def ef(row_ptr, col_idx, seeds=None, threads: int = 1):
+    """Returns (N, D, EF) as int64, int64, float64 arrays aligned with `seeds`
+    (all nodes when seeds is None)."""
+    rp, ci = _csr(row_ptr, col_idx)
+    n = rp.size - 1
+    if seeds is None:
+        cnt = n
+        sp = None
+    else:
+        sd = np.ascontiguousarray(seeds, dtype=np.int32)
+        cnt = sd.size
+        sp = sd.ctypes.data if cnt else None
+    N = np.zeros(max(cnt, 1), np.int64)
+    D = np.zeros(max(cnt, 1), np.int64)
+    E = np.zeros(max(cnt, 1), np.float64)
+    if cnt:
+        st = _load().oracle_ef(n, rp.ctypes.data, ci.ctypes.data, sp, cnt, N.ctypes.data,
+                               D.ctypes.data, E.ctypes.data, int(threads))
+        if st != 0:
+            raise RuntimeError(f"oracle_ef failed with status {st}")
+    return N[:cnt], D[:cnt], E[:cnt]
+
+
+def histogram(row_ptr, col_idx, s: int):
+    """H_s as a dict {cluster degree: number of event sequences}."""
+    rp, ci = _csr(row_ptr, col_idx)
+    n = rp.size - 1
+    lib = _load()
+    cap = 64
+    while True:
+        d = np.zeros(cap, np.int64)
+        c = np.zeros(cap, np.int64)
+        m = lib.oracle_histogram(n, rp.ctypes.data, ci.ctypes.data, int(s), d.ctypes.data,
+                                 c.ctypes.data, cap)
+        if m < 0:
+            raise RuntimeError("oracle_histogram failed")
+        if m <= cap:
+            return {int(a): int(b) for a, b in zip(d[:m], c[:m])}
+        cap = int(m)

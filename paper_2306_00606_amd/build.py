@@ -1,0 +1,80 @@
+"""Build steps for the native parts, run in-tree.
+
+* ``libefgen.so``  - seeded graph generators (g++, OpenMP)
+* ``libef.so``     - the Expected Force library: HIP kernels for gfx950 plus the
+                     C-ABI host code (hipcc)
+* ``oracle/liboracle.so`` - the CPU oracle (gcc); built here only so that the
+                     tests can load it, never called from the library.
+"""
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+HIPCC = shutil.which("hipcc") or os.path.join(ROCM, "bin", "hipcc")
+ARCH = "gfx950"
+
+# Packed FP32 instructions are kept out of every device build.
+HIP_FLAGS = [
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall", "-Wno-unused-function",
+]
+
+
+def _run(cmd, cwd=None):
+    r = subprocess.run(cmd, cwd=cwd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError(f"build step failed: {' '.join(cmd)}")
+    return r
+
+
+def build_gen():
+    src = os.path.join(PKG, "gen", "gen.cpp")
+    out = os.path.join(PKG, "gen", "libefgen.so")
+    _run(["g++", "-O3", "-std=c++17", "-fPIC", "-shared", "-fopenmp", src, "-o", out + ".tmp"])
+    os.replace(out + ".tmp", out)
+    return out
+
+
+def build_oracle():
+    src = os.path.join(ROOT, "oracle", "ef_oracle.c")
+    out = os.path.join(ROOT, "oracle", "liboracle.so")
+    _run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", src, "-lm",
+          "-o", out + ".tmp"])
+    os.replace(out + ".tmp", out)
+    return out
+
+
+def lib_sources():
+    d = os.path.join(PKG, "csrc")
+    return sorted(os.path.join(d, f) for f in os.listdir(d)
+                  if f.endswith(".hip") or f.endswith(".cpp"))
+
+
+def build_lib():
+    out = os.path.join(PKG, "libef.so")
+    srcs = lib_sources()
+    if not srcs:
+        return None
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(PKG, "csrc")]
+    _run([HIPCC] + HIP_FLAGS + inc + srcs + ["-o", out + ".tmp"])
+    os.replace(out + ".tmp", out)
+    return out
+
+
+def build_all():
+    build_gen()
+    build_oracle()
+    build_lib()
+
+
+if __name__ == "__main__":
+    build_all()
+    print("built")
