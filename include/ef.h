@@ -1,0 +1,167 @@
+/*
+ * ef.h - Expected Force (EF) on AMD Instinct MI355X (gfx950).
+ *
+ * Expected Force of a node s (Sylos Labini et al., "Scaling Expected Force:
+ * Efficient Identification of Key Nodes in Network-based Epidemic Models",
+ * Sec. 3.3, Eq. 1): list every infected cluster reachable from s by two
+ * transmission events (s infects a neighbour y, then s or y infects a still
+ * susceptible neighbour z); a cluster's degree d is the number of edges that
+ * leave it; EF(s) = -sum_c p_c ln p_c with p_c = d_c / sum_c d_c. Clusters are
+ * counted with the multiplicities of the paper's Algorithm 1 (a star y-s-z is
+ * reached twice, a path s-y-z once; a triangle lowers d by 2).
+ *
+ * Per seed the library also returns the exact integers
+ *   N(s) = number of event sequences (clusters with multiplicity) and
+ *   D(s) = sum of their degrees.
+ *
+ * Conventions for every entry point:
+ *   - Each returns an ef_status; none throws, aborts or exits. On failure
+ *     ef_last_error() returns a thread-local, human-readable message.
+ *   - Node ids are the caller's ids, 0..n-1, in inputs and outputs.
+ *   - The graph is simple and undirected, given as int32 CSR: row_ptr[n+1]
+ *     offsets, col_idx[nnz] neighbour ids, each edge stored in both rows,
+ *     rows sorted ascending, no self-loops, no duplicates, nnz < 2^31.
+ *   - Ownership: the caller owns every buffer it passes. Handles are opaque
+ *     and released only by the matching *_free. A handle must not be used by
+ *     two threads at once.
+ *   - hip_stream is a hipStream_t passed as void* (NULL = the null stream).
+ *     With host output pointers a call returns after its results are on the
+ *     host. With EF_OUT_DEVICE the outputs are device pointers and the call
+ *     is asynchronous on hip_stream.
+ */
+#ifndef EF_H_
+#define EF_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  EF_OK = 0,
+  EF_ERR_ARG = 1,            /* null pointer, negative size, bad enum or flag */
+  EF_ERR_NOT_SYMMETRIC = 2,  /* an arc u->v without v->u */
+  EF_ERR_SELF_LOOP = 3,      /* an arc u->u */
+  EF_ERR_DUPLICATE = 4,      /* an arc listed twice in a row */
+  EF_ERR_UNSORTED = 5,       /* a row not ascending, or row_ptr decreasing */
+  EF_ERR_RANGE = 6,          /* a neighbour id outside 0..n-1, or row_ptr[0] != 0 */
+  EF_ERR_OVERFLOW = 7,       /* nnz >= 2^31, or an int64 result could overflow */
+  EF_ERR_NOMEM = 8,          /* device allocation failed or exceeds EF_MAX_DEVICE_BYTES */
+  EF_ERR_DEVICE = 9,         /* no usable gfx950 device, or a HIP runtime error */
+  EF_ERR_STATE = 10          /* call not valid for this handle */
+} ef_status;
+
+/* The two exact formulations (both return identical N and D):
+ *   EF_ALGO_CLUSTER  - cluster-centric, Algorithm 1: every cluster is scored
+ *                      once and credited to its three nodes.
+ *   EF_ALGO_PER_SEED - the original per-seed formulation (Sec. 4): each seed
+ *                      visits all of its own clusters (stars around it, and
+ *                      paths through each neighbour). */
+typedef enum { EF_ALGO_CLUSTER = 0, EF_ALGO_PER_SEED = 1 } ef_algo;
+
+/* Precision of the cluster-degree logarithms and their sums:
+ *   EF_PREC_FP64  - every term and sum in double precision.
+ *   EF_PREC_FP32C - terms in single precision with compensated (double-float)
+ *                   sums; the final EF of seeds with more than 2^24 clusters is
+ *                   formed in double precision; seeds whose EF would lose
+ *                   accuracy to cancellation are recomputed from non-negative
+ *                   terms (see ef_run_stats.promoted). */
+typedef enum { EF_PREC_FP64 = 0, EF_PREC_FP32C = 1 } ef_prec;
+
+/* flags */
+#define EF_VALIDATE     0x1u  /* load: check that the CSR is simple and symmetric */
+#define EF_DEVICE_PTRS  0x2u  /* load: row_ptr/col_idx are device pointers, borrowed
+                                 (they must outlive the graph handle) */
+#define EF_OUT_DEVICE   0x4u  /* compute/topk: outputs are device pointers, async */
+#define EF_PROFILE      0x8u  /* compute: time each phase with HIP events
+                                 (read back with ef_stats) */
+
+typedef struct ef_graph ef_graph;
+
+typedef struct {
+  int32_t n;              /* nodes */
+  int64_t nnz;            /* arcs = 2 * undirected edges */
+  int32_t max_degree;
+  int64_t clusters;       /* W = sum_v k_v (k_v - 1) / 2: the cluster set of Algorithm 1 */
+  int64_t sum_sq_degree;  /* sum_v k_v^2 (the per-seed formulation's 2-hop stream length) */
+  int64_t up_arcs;        /* arcs oriented from lower to higher (degree, id) rank = nnz / 2 */
+  int64_t wedge_checks;   /* membership tests of the triangle pass: sum_w up(w) * down(w) */
+} ef_graph_info;
+
+/* Timings of the last ef_compute that ran with EF_PROFILE (milliseconds, from
+ * HIP events on the call's stream), and counters of the last ef_compute. */
+typedef struct {
+  double t_bin_ms;        /* degree binning and work-list construction */
+  double t_pairs_ms;      /* cluster generation and scoring (all pair-loop kernels) */
+  double t_pairs_small_ms;/* pair loop, centres with k <= 64 (one wavefront each) */
+  double t_pairs_mid_ms;  /* pair loop, centres with 64 < k <= 1024 (one workgroup each) */
+  double t_pairs_big_ms;  /* pair loop, 1024x1024 super-tiles of centres with k > 1024 */
+  double t_reduce_ms;     /* per-arc reduction of super-tile partial sums */
+  double t_triangles_ms;  /* triangle pass (cluster-centric) */
+  double t_stream_ms;     /* 2-hop path stream (per-seed) */
+  double t_finalize_ms;   /* per-seed sums and Eq. 1 */
+  double t_pass2_ms;      /* recomputation of cancellation-prone seeds (FP32C) */
+  double t_total_ms;      /* first to last event of the call */
+  int64_t pairs_small;    /* clusters scored by each pair-loop kernel */
+  int64_t pairs_mid;
+  int64_t pairs_big;
+  int64_t pair_tiles;     /* super-tiles launched for centres with k > 1024 */
+  int64_t promoted;       /* FP32C seeds recomputed from non-negative terms */
+  int64_t fp64_finalized; /* FP32C seeds with more than 2^24 clusters */
+  int64_t seeds;          /* seeds computed */
+} ef_run_stats;
+
+/* Text of the last error on this thread ("" when none). Never NULL. */
+const char *ef_last_error(void);
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int32_t ef_version(void);
+
+/* Number of visible gfx950 devices (0 is not an error). */
+ef_status ef_device_count(int32_t *count);
+
+/* Check on the host that (n, nnz, row_ptr, col_idx) is a simple undirected
+ * graph in the CSR form described above. Returns the first violation found
+ * (EF_ERR_RANGE, EF_ERR_UNSORTED, EF_ERR_DUPLICATE, EF_ERR_SELF_LOOP,
+ * EF_ERR_NOT_SYMMETRIC, EF_ERR_OVERFLOW) and names the row in ef_last_error().
+ * Needs no device. Input for Algorithm 1 is such a graph (Sec. 4). */
+ef_status ef_validate_csr(int32_t n, int64_t nnz, const int32_t *row_ptr,
+                          const int32_t *col_idx);
+
+/* Load a graph (Algorithm 1's input, Sec. 4). Without EF_DEVICE_PTRS the
+ * arrays are host memory and are copied; with it they are device memory and
+ * are borrowed. EF_VALIDATE runs ef_validate_csr first (device inputs are
+ * copied to the host for it). The library allocates its own device arrays
+ * (degrees, arc sources, reverse arcs, the degree-oriented half adjacency)
+ * and keeps them until ef_graph_free. */
+ef_status ef_graph_load_csr(int32_t n, int64_t nnz, const int32_t *row_ptr,
+                            const int32_t *col_idx, uint32_t flags, void *hip_stream,
+                            ef_graph **out);
+
+/* Build and load a graph from m host edges (src[i], dst[i]) over nodes
+ * 0..n-1, in either orientation; self-loops are dropped, duplicates merged. */
+ef_status ef_graph_from_edges(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                              void *hip_stream, ef_graph **out);
+
+ef_status ef_graph_free(ef_graph *g);
+
+ef_status ef_graph_info_get(const ef_graph *g, ef_graph_info *out);
+
+/* Expected Force (Eq. 1) of all nodes (seeds == NULL: outputs indexed by node
+ * id, length n) or of seeds[0..n_seeds) (outputs position-aligned with seeds;
+ * duplicates allowed). ef receives EF as double; D and N (nullable) receive
+ * the exact int64 sums. Selected seeds always use the per-seed formulation.
+ * Flags: EF_OUT_DEVICE, EF_PROFILE. */
+ef_status ef_compute(ef_graph *g, ef_algo algo, ef_prec prec, const int32_t *seeds,
+                     int32_t n_seeds, double *ef, int64_t *D, int64_t *N, uint32_t flags,
+                     void *hip_stream);
+
+/* Counters and (with EF_PROFILE) phase times of the last ef_compute on g. */
+ef_status ef_stats(const ef_graph *g, ef_run_stats *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EF_H_ */

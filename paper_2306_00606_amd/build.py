@@ -58,13 +58,31 @@ def lib_sources():
                   if f.endswith(".hip") or f.endswith(".cpp"))
 
 
+def hip_runtime_dir():
+    """Directory of the HIP runtime to link against. When PyTorch-ROCm is
+    installed, its bundled libamdhip64.so is used, so that a Python process
+    holds a single HIP runtime shared by torch (memory, streams) and this
+    library; otherwise the ROCm installation's."""
+    import importlib.util
+
+    spec = importlib.util.find_spec("torch")
+    if spec and spec.submodule_search_locations:
+        d = os.path.join(spec.submodule_search_locations[0], "lib")
+        if os.path.exists(os.path.join(d, "libamdhip64.so")):
+            return d
+    return os.path.join(ROCM, "lib")
+
+
 def build_lib():
     out = os.path.join(PKG, "libef.so")
     srcs = lib_sources()
     if not srcs:
         return None
     inc = ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(PKG, "csrc")]
-    _run([HIPCC] + HIP_FLAGS + inc + srcs + ["-o", out + ".tmp"])
+    rt = hip_runtime_dir()
+    link = ["-no-hip-rt", "-L", rt, "-l:libamdhip64.so", f"-Wl,-rpath,{rt}",
+            f"-Wl,-rpath,{os.path.join(ROCM, 'lib')}"]
+    _run([HIPCC] + HIP_FLAGS + inc + srcs + link + ["-o", out + ".tmp"])
     os.replace(out + ".tmp", out)
     return out
 

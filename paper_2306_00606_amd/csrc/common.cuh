@@ -1,0 +1,108 @@
+// Device helpers shared by the kernel translation units.
+#pragma once
+
+#include "ef_internal.h"
+
+namespace efi {
+
+__device__ __forceinline__ bool rank_less_d(int32_t a, int32_t ka, int32_t b, int32_t kb) {
+  return ka < kb || (ka == kb && a < b);
+}
+
+// double-float accumulator (FP32 path)
+struct DFv {
+  float hi, lo;
+  __device__ __forceinline__ void add(float x) {
+    float s = hi + x;
+    float bb = s - hi;
+    float e = (hi - (s - bb)) + (x - bb);
+    hi = s;
+    lo += e;
+  }
+  __device__ __forceinline__ void add(DFv o) {
+    add(o.hi);
+    add(o.lo);
+  }
+  __device__ __forceinline__ double value() const { return (double)hi + (double)lo; }
+};
+
+template <typename T> struct SumT;
+template <> struct SumT<float> {
+  using type = DFv;
+  __device__ static void add_stored(DFv &a, const void *p, int64_t i) {
+    float2 x = reinterpret_cast<const float2 *>(p)[i];
+    a.add(x.x);
+    a.add(x.y);
+  }
+  __device__ static void store(const DFv &a, void *p, int64_t i) {
+    float h = a.hi + a.lo;
+    reinterpret_cast<float2 *>(p)[i] = make_float2(h, a.lo - (h - a.hi));
+  }
+  __device__ static void add_term(DFv &a, float x) { a.add(x); }
+  __device__ static double value(const DFv &a) { return a.value(); }
+};
+template <> struct SumT<double> {
+  using type = double;
+  __device__ static void add_stored(double &a, const void *p, int64_t i) {
+    a += reinterpret_cast<const double *>(p)[i];
+  }
+  __device__ static void store(const double &a, void *p, int64_t i) {
+    reinterpret_cast<double *>(p)[i] = a;
+  }
+  __device__ static void add_term(double &a, double x) { a += x; }
+  __device__ static double value(const double &a) { return a; }
+};
+
+// wavefront reductions with a fixed butterfly order
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t x) {
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+__device__ __forceinline__ double wave_sum_f64(double x) {
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+__device__ __forceinline__ DFv wave_sum_df(DFv x) {
+  for (int off = 32; off > 0; off >>= 1) {
+    DFv o;
+    o.hi = __shfl_xor(x.hi, off, 64);
+    o.lo = __shfl_xor(x.lo, off, 64);
+    x.add(o);
+  }
+  return x;
+}
+__device__ __forceinline__ DFv wave_sum(DFv x) { return wave_sum_df(x); }
+__device__ __forceinline__ void acc_merge(DFv &a, DFv b) { a.add(b); }
+__device__ __forceinline__ void acc_merge(double &a, double b) { a += b; }
+__device__ __forceinline__ double wave_sum(double x) { return wave_sum_f64(x); }
+
+// Cluster score g(d) = d log d and the triangle adjustment
+//   delta(sigma) = g(sigma - 6) - g(sigma - 4)
+// evaluated as a * log1p(-2/b) - 2 log b with a = sigma-6, b = sigma-4, a
+// sum of two non-positive terms (no cancellation). FP32: log2 units.
+__device__ __forceinline__ float score_f(float d) { return d * __builtin_amdgcn_logf(d); }
+__device__ __forceinline__ double score_d(double d) { return d * log(d); }
+
+__device__ __forceinline__ float tri_delta_f(int32_t sigma) {
+  const float a = (float)(sigma - 6), b = (float)(sigma - 4);
+  return a * (log1pf(-2.0f / b) * 1.4426950408889634f) - 2.0f * log2f(b);
+}
+__device__ __forceinline__ double tri_delta_d(int32_t sigma) {
+  const double a = (double)(sigma - 6), b = (double)(sigma - 4);
+  return a * log1p(-2.0 / b) - 2.0 * log(b);
+}
+
+template <typename T> __device__ __forceinline__ T score_t(int32_t d);
+template <> __device__ __forceinline__ float score_t<float>(int32_t d) {
+  return d > 0 ? score_f((float)d) : 0.0f;
+}
+template <> __device__ __forceinline__ double score_t<double>(int32_t d) {
+  return d > 0 ? score_d((double)d) : 0.0;
+}
+template <typename T> __device__ __forceinline__ T tri_delta(int32_t sigma);
+template <> __device__ __forceinline__ float tri_delta<float>(int32_t s) { return tri_delta_f(s); }
+template <> __device__ __forceinline__ double tri_delta<double>(int32_t s) { return tri_delta_d(s); }
+
+__device__ __forceinline__ uint32_t hash32(uint32_t x) { return x * 2654435761u; }
+
+}  // namespace efi

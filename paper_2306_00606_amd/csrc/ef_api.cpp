@@ -1,0 +1,804 @@
+// C-ABI of the Expected Force library: argument checks, CSR validation, graph
+// loading, workspace management and the launch sequence of each entry point.
+// All arithmetic of the method runs in the kernels of the .hip files.
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "ef_internal.h"
+
+struct ef_graph {
+  efi::Graph g;
+};
+
+namespace efi {
+
+static thread_local std::string t_err;
+
+void set_error(const char *fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  t_err = buf;
+}
+
+ef_status hip_status(hipError_t e, const char *what) {
+  if (e == hipSuccess) return EF_OK;
+  set_error("%s: HIP error %d (%s)", what, (int)e, hipGetErrorString(e));
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return EF_ERR_NOMEM;
+  return EF_ERR_DEVICE;
+}
+
+static int64_t max_device_bytes() {
+  const char *s = std::getenv("EF_MAX_DEVICE_BYTES");
+  if (!s || !*s) return INT64_MAX;
+  char *end = nullptr;
+  long long v = std::strtoll(s, &end, 10);
+  return v > 0 ? (int64_t)v : INT64_MAX;
+}
+
+// allocation accounted against EF_MAX_DEVICE_BYTES
+static ef_status dev_alloc(Graph &g, void **p, size_t bytes, const char *what) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 8;
+  if (g.owned_bytes + (int64_t)bytes > max_device_bytes()) {
+    set_error("%s: %zu bytes would exceed EF_MAX_DEVICE_BYTES", what, bytes);
+    return EF_ERR_NOMEM;
+  }
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    set_error("%s: device allocation of %zu bytes failed", what, bytes);
+    return EF_ERR_NOMEM;
+  }
+  g.owned_bytes += (int64_t)bytes;
+  return EF_OK;
+}
+
+static void dev_free(Graph &g, void *p, size_t bytes) {
+  if (!p) return;
+  (void)hipFree(p);
+  g.owned_bytes -= (int64_t)(bytes ? bytes : 8);
+}
+
+static ef_status ws_ensure(Graph &g, int slot, size_t bytes, const char *what) {
+  DevBuf &b = g.ws[slot];
+  if (b.bytes >= bytes && b.p) return EF_OK;
+  if (b.p) {
+    dev_free(g, b.p, b.bytes);
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  size_t want = std::max<size_t>(bytes, 256);
+  ef_status s = dev_alloc(g, &b.p, want, what);
+  if (s != EF_OK) return s;
+  b.bytes = want;
+  return EF_OK;
+}
+
+static ef_status check_device(int *dev) {
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || count <= 0) {
+    (void)hipGetLastError();
+    set_error("no HIP device visible");
+    return EF_ERR_DEVICE;
+  }
+  e = hipGetDevice(dev);
+  if (e != hipSuccess) return hip_status(e, "hipGetDevice");
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, *dev);
+  if (e != hipSuccess) return hip_status(e, "hipGetDeviceProperties");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+    set_error("device %d is %s; this library is built for gfx950", *dev, prop.gcnArchName);
+    return EF_ERR_DEVICE;
+  }
+  return EF_OK;
+}
+
+static inline bool rank_less_h(int32_t a, int32_t ka, int32_t b, int32_t kb) {
+  return ka < kb || (ka == kb && a < b);
+}
+
+// Largest degree for which every cluster degree (< 3 k_max) is exact in
+// FP32 and every D(s) (< 6 k_max^3) fits in int64.
+constexpr int32_t kMaxDegree = 1000000;
+
+}  // namespace efi
+
+using namespace efi;
+
+extern "C" {
+
+const char *ef_last_error(void) { return t_err.c_str(); }
+
+int32_t ef_version(void) { return 10000; }
+
+ef_status ef_device_count(int32_t *count) {
+  if (!count) {
+    set_error("ef_device_count: null output");
+    return EF_ERR_ARG;
+  }
+  *count = 0;
+  int c = 0;
+  if (hipGetDeviceCount(&c) != hipSuccess) {
+    (void)hipGetLastError();
+    return EF_OK;
+  }
+  int32_t ok = 0;
+  for (int i = 0; i < c; ++i) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, i) == hipSuccess &&
+        std::strncmp(prop.gcnArchName, "gfx950", 6) == 0)
+      ++ok;
+  }
+  *count = ok;
+  return EF_OK;
+}
+
+ef_status ef_validate_csr(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx) {
+  if (n < 0 || nnz < 0) {
+    set_error("ef_validate_csr: negative size (n=%d, nnz=%lld)", n, (long long)nnz);
+    return EF_ERR_ARG;
+  }
+  if (nnz >= (int64_t)INT32_MAX) {
+    set_error("ef_validate_csr: nnz=%lld does not fit int32 offsets", (long long)nnz);
+    return EF_ERR_OVERFLOW;
+  }
+  if (!row_ptr || (nnz > 0 && !col_idx)) {
+    set_error("ef_validate_csr: null array");
+    return EF_ERR_ARG;
+  }
+  if (row_ptr[0] != 0) {
+    set_error("row_ptr[0] = %d, expected 0", row_ptr[0]);
+    return EF_ERR_RANGE;
+  }
+  for (int32_t v = 0; v < n; ++v) {
+    if (row_ptr[v + 1] < row_ptr[v]) {
+      set_error("row_ptr decreases at row %d", v);
+      return EF_ERR_UNSORTED;
+    }
+  }
+  if ((int64_t)row_ptr[n] != nnz) {
+    set_error("row_ptr[n] = %d but nnz = %lld", row_ptr[n], (long long)nnz);
+    return EF_ERR_RANGE;
+  }
+  for (int32_t v = 0; v < n; ++v) {
+    for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+      const int32_t x = col_idx[e];
+      if (x < 0 || x >= n) {
+        set_error("row %d: neighbour %d out of range [0, %d)", v, x, n);
+        return EF_ERR_RANGE;
+      }
+      if (x == v) {
+        set_error("row %d: self-loop", v);
+        return EF_ERR_SELF_LOOP;
+      }
+      if (e > row_ptr[v]) {
+        if (col_idx[e - 1] == x) {
+          set_error("row %d: neighbour %d listed twice", v, x);
+          return EF_ERR_DUPLICATE;
+        }
+        if (col_idx[e - 1] > x) {
+          set_error("row %d: neighbours not ascending at position %d", v, e - row_ptr[v]);
+          return EF_ERR_UNSORTED;
+        }
+      }
+    }
+  }
+  for (int32_t v = 0; v < n; ++v) {
+    for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+      const int32_t x = col_idx[e];
+      if (!std::binary_search(col_idx + row_ptr[x], col_idx + row_ptr[x + 1], v)) {
+        set_error("arc %d->%d has no reverse arc %d->%d", v, x, x, v);
+        return EF_ERR_NOT_SYMMETRIC;
+      }
+    }
+  }
+  return EF_OK;
+}
+
+ef_status ef_graph_free(ef_graph *h) {
+  if (!h) {
+    set_error("ef_graph_free: null handle");
+    return EF_ERR_ARG;
+  }
+  Graph &g = h->g;
+  if (!g.borrowed) {
+    (void)hipFree(g.row_ptr);
+    (void)hipFree(g.col_idx);
+  }
+  void *arrays[] = {g.deg, g.src, g.rev, g.adj2, g.asum, g.up_ptr, g.up_col, g.tslot,
+                    g.tri_small, g.tri_large, g.tri_long, g.d_counters};
+  for (void *p : arrays)
+    if (p) (void)hipFree(p);
+  for (auto &b : g.ws)
+    if (b.p) (void)hipFree(b.p);
+  if (g.ev_ready)
+    for (auto &e : g.ev) (void)hipEventDestroy(e);
+  delete h;
+  return EF_OK;
+}
+
+ef_status ef_graph_load_csr(int32_t n, int64_t nnz, const int32_t *row_ptr,
+                            const int32_t *col_idx, uint32_t flags, void *hip_stream,
+                            ef_graph **out) {
+  if (!out) {
+    set_error("ef_graph_load_csr: null output handle");
+    return EF_ERR_ARG;
+  }
+  *out = nullptr;
+  if (n < 0 || nnz < 0 || !row_ptr || (nnz > 0 && !col_idx)) {
+    set_error("ef_graph_load_csr: bad arguments (n=%d, nnz=%lld)", n, (long long)nnz);
+    return EF_ERR_ARG;
+  }
+  if (flags & ~(EF_VALIDATE | EF_DEVICE_PTRS)) {
+    set_error("ef_graph_load_csr: unknown flags 0x%x", flags);
+    return EF_ERR_ARG;
+  }
+  if (nnz >= (int64_t)INT32_MAX) {
+    set_error("ef_graph_load_csr: nnz=%lld does not fit int32 offsets", (long long)nnz);
+    return EF_ERR_OVERFLOW;
+  }
+  int dev = 0;
+  ef_status st = check_device(&dev);
+  if (st != EF_OK) return st;
+  hipStream_t stream = (hipStream_t)hip_stream;
+  const bool devptr = (flags & EF_DEVICE_PTRS) != 0;
+
+  // host view of the CSR (needed for validation and for sizing work lists)
+  std::vector<int32_t> h_rp, h_ci;
+  const int32_t *hrp = row_ptr, *hci = col_idx;
+  if (devptr) {
+    h_rp.resize((size_t)n + 1);
+    hipError_t e = hipMemcpy(h_rp.data(), row_ptr, sizeof(int32_t) * ((size_t)n + 1),
+                             hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_status(e, "copy row_ptr to host");
+    hrp = h_rp.data();
+    if (flags & EF_VALIDATE) {
+      h_ci.resize((size_t)std::max<int64_t>(nnz, 1));
+      if (nnz > 0) {
+        e = hipMemcpy(h_ci.data(), col_idx, sizeof(int32_t) * (size_t)nnz, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_status(e, "copy col_idx to host");
+      }
+      hci = h_ci.data();
+    }
+  }
+  if (flags & EF_VALIDATE) {
+    st = ef_validate_csr(n, nnz, hrp, hci);
+    if (st != EF_OK) return st;
+  } else if (hrp[0] != 0 || (int64_t)hrp[n] != nnz) {
+    set_error("row_ptr[0] must be 0 and row_ptr[n] must equal nnz");
+    return EF_ERR_RANGE;
+  }
+  int32_t kmax = 0;
+  for (int32_t v = 0; v < n; ++v) kmax = std::max(kmax, hrp[v + 1] - hrp[v]);
+  if (kmax > kMaxDegree) {
+    set_error("max degree %d exceeds %d (exact cluster degrees / int64 sums)", kmax, kMaxDegree);
+    return EF_ERR_OVERFLOW;
+  }
+
+  ef_graph *h = new (std::nothrow) ef_graph();
+  if (!h) {
+    set_error("host allocation failed");
+    return EF_ERR_NOMEM;
+  }
+  Graph &g = h->g;
+  g.dev = dev;
+  g.n = n;
+  g.nnz = nnz;
+  g.borrowed = devptr;
+  const size_t N1 = (size_t)n + 1, NNZ = (size_t)std::max<int64_t>(nnz, 1);
+  const size_t NUP = (size_t)std::max<int64_t>(nnz / 2, 1);
+#define ALLOC(ptr, bytes, what)                                   \
+  do {                                                            \
+    st = dev_alloc(g, (void **)&(ptr), (bytes), what);            \
+    if (st != EF_OK) { ef_graph_free(h); return st; }             \
+  } while (0)
+  if (devptr) {
+    g.row_ptr = const_cast<int32_t *>(row_ptr);
+    g.col_idx = const_cast<int32_t *>(col_idx);
+  } else {
+    ALLOC(g.row_ptr, sizeof(int32_t) * N1, "row_ptr");
+    ALLOC(g.col_idx, sizeof(int32_t) * NNZ, "col_idx");
+    hipError_t e = hipMemcpyAsync(g.row_ptr, row_ptr, sizeof(int32_t) * N1,
+                                  hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess && nnz > 0)
+      e = hipMemcpyAsync(g.col_idx, col_idx, sizeof(int32_t) * (size_t)nnz,
+                         hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) {
+      ef_graph_free(h);
+      return hip_status(e, "copy CSR to device");
+    }
+  }
+  ALLOC(g.deg, sizeof(int32_t) * std::max<size_t>(n, 1), "deg");
+  ALLOC(g.src, sizeof(int32_t) * NNZ, "src");
+  ALLOC(g.rev, sizeof(int32_t) * NNZ, "rev");
+  ALLOC(g.adj2, sizeof(int2) * NNZ, "adj2");
+  ALLOC(g.asum, sizeof(int64_t) * std::max<size_t>(n, 1), "asum");
+  ALLOC(g.up_ptr, sizeof(int32_t) * N1, "up_ptr");
+  ALLOC(g.up_col, sizeof(int32_t) * NUP, "up_col");
+  ALLOC(g.tslot, sizeof(int32_t) * NNZ, "tslot");
+  ALLOC(g.d_counters, sizeof(int32_t) * 64, "counters");
+  {
+    int32_t *tmp = nullptr;
+    const size_t tmp_bytes = sizeof(int32_t) * (2 * NNZ + (size_t)scan_tmp_len((int64_t)NNZ));
+    ALLOC(tmp, tmp_bytes, "preprocessing scratch");
+    hipError_t e = launch_graph_prep(g, tmp, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    dev_free(g, tmp, tmp_bytes);
+    if (e != hipSuccess) {
+      ef_graph_free(h);
+      return hip_status(e, "graph preprocessing");
+    }
+  }
+  // host copies: degrees and |up(u)|
+  g.h_deg.resize((size_t)n);
+  for (int32_t v = 0; v < n; ++v) g.h_deg[v] = hrp[v + 1] - hrp[v];
+  std::vector<int32_t> h_up_ptr(N1);
+  {
+    hipError_t e = hipMemcpy(h_up_ptr.data(), g.up_ptr, sizeof(int32_t) * N1,
+                             hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      ef_graph_free(h);
+      return hip_status(e, "copy up_ptr to host");
+    }
+  }
+  g.h_up_len.resize((size_t)n);
+  ef_graph_info &inf = g.info;
+  inf.n = n;
+  inf.nnz = nnz;
+  inf.max_degree = kmax;
+  inf.up_arcs = nnz / 2;
+  std::vector<int32_t> ts, tl, tg;
+  for (int32_t v = 0; v < n; ++v) {
+    const int64_t k = g.h_deg[v];
+    const int32_t up = h_up_ptr[v + 1] - h_up_ptr[v];
+    g.h_up_len[v] = up;
+    inf.clusters += k * (k - 1) / 2;
+    inf.sum_sq_degree += k * k;
+    inf.wedge_checks += (int64_t)up * (k - up);
+    if (k >= 2 && k <= kSmallMax) {
+      g.all_small++;
+      g.all_pairs_small += k * (k - 1) / 2;
+    } else if (k > kSmallMax && k <= kSuper) {
+      g.all_mid++;
+      g.all_pairs_mid += k * (k - 1) / 2;
+    } else if (k > kSuper) {
+      const int64_t ns = (k + kSuper - 1) / kSuper;
+      g.all_big++;
+      g.all_tiles += ns * (ns + 1) / 2;
+      g.all_pairs_big += k * (k - 1) / 2;
+    }
+    if (up >= 2 && up <= kTriHashMax) ts.push_back(v);
+    else if (up > kTriHashMax && up <= 4096) tl.push_back(v);
+    else if (up > 4096) tg.push_back(v);
+  }
+  // longest lists first
+  auto by_up = [&](int32_t a, int32_t b) {
+    return g.h_up_len[a] != g.h_up_len[b] ? g.h_up_len[a] > g.h_up_len[b] : a < b;
+  };
+  std::sort(ts.begin(), ts.end(), by_up);
+  std::sort(tl.begin(), tl.end(), by_up);
+  std::sort(tg.begin(), tg.end(), by_up);
+  g.n_tri_small = (int64_t)ts.size();
+  g.n_tri_large = (int64_t)tl.size();
+  g.n_tri_long = (int64_t)tg.size();
+  ALLOC(g.tri_small, sizeof(int32_t) * std::max<size_t>(ts.size(), 1), "triangle list");
+  ALLOC(g.tri_large, sizeof(int32_t) * std::max<size_t>(tl.size(), 1), "triangle list");
+  ALLOC(g.tri_long, sizeof(int32_t) * std::max<size_t>(tg.size(), 1), "triangle list");
+#undef ALLOC
+  hipError_t e = hipSuccess;
+  if (!ts.empty()) e = hipMemcpy(g.tri_small, ts.data(), sizeof(int32_t) * ts.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !tl.empty())
+    e = hipMemcpy(g.tri_large, tl.data(), sizeof(int32_t) * tl.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !tg.empty())
+    e = hipMemcpy(g.tri_long, tg.data(), sizeof(int32_t) * tg.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    ef_graph_free(h);
+    return hip_status(e, "upload triangle lists");
+  }
+  *out = h;
+  return EF_OK;
+}
+
+ef_status ef_graph_from_edges(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                              void *hip_stream, ef_graph **out) {
+  if (!out || n < 0 || m < 0 || (m > 0 && (!src || !dst))) {
+    set_error("ef_graph_from_edges: bad arguments");
+    return EF_ERR_ARG;
+  }
+  std::vector<int64_t> cnt((size_t)n + 1, 0);
+  for (int64_t i = 0; i < m; ++i) {
+    const int32_t u = src[i], v = dst[i];
+    if (u < 0 || u >= n || v < 0 || v >= n) {
+      set_error("edge %lld: endpoint out of range [0, %d)", (long long)i, n);
+      return EF_ERR_RANGE;
+    }
+    if (u == v) continue;
+    cnt[u + 1]++;
+    cnt[v + 1]++;
+  }
+  for (int32_t v = 0; v < n; ++v) cnt[v + 1] += cnt[v];
+  if (cnt[n] >= (int64_t)INT32_MAX) {
+    set_error("ef_graph_from_edges: too many arcs");
+    return EF_ERR_OVERFLOW;
+  }
+  std::vector<int32_t> col((size_t)cnt[n]);
+  std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+  for (int64_t i = 0; i < m; ++i) {
+    const int32_t u = src[i], v = dst[i];
+    if (u == v) continue;
+    col[pos[u]++] = v;
+    col[pos[v]++] = u;
+  }
+  std::vector<int32_t> rp((size_t)n + 1, 0);
+  int64_t w = 0;
+  for (int32_t v = 0; v < n; ++v) {
+    auto b = col.begin() + cnt[v], e = col.begin() + cnt[v + 1];
+    std::sort(b, e);
+    auto last = std::unique(b, e);
+    for (auto it = b; it != last; ++it) col[w++] = *it;
+    rp[v + 1] = (int32_t)w;
+  }
+  return ef_graph_load_csr(n, w, rp.data(), col.data(), 0, hip_stream, out);
+}
+
+ef_status ef_graph_info_get(const ef_graph *h, ef_graph_info *out) {
+  if (!h || !out) {
+    set_error("ef_graph_info_get: null argument");
+    return EF_ERR_ARG;
+  }
+  *out = h->g.info;
+  return EF_OK;
+}
+
+ef_status ef_stats(const ef_graph *h, ef_run_stats *out) {
+  if (!h || !out) {
+    set_error("ef_stats: null argument");
+    return EF_ERR_ARG;
+  }
+  *out = h->g.stats;
+  return EF_OK;
+}
+
+}  // extern "C"
+
+namespace efi {
+
+// workspace slots
+enum {
+  WS_R = 0, WS_REC, WS_Y, WS_YT, WS_Z, WS_ZT, WS_YACC, WS_FLAG, WS_BINS, WS_OUT, WS_BITMAP,
+  WS_SEEDS, WS_UOUT
+};
+
+static void host_bins(const Graph &g, const int32_t *centres, int64_t count, Bins &b) {
+  b.n_small = b.n_mid = b.n_big = b.n_tiles = 0;
+  b.pairs_small = b.pairs_mid = b.pairs_big = 0;
+  for (int64_t i = 0; i < count; ++i) {
+    const int64_t k = g.h_deg[centres ? centres[i] : i];
+    if (k < 2) continue;
+    if (k <= kSmallMax) {
+      b.n_small++;
+      b.pairs_small += k * (k - 1) / 2;
+    } else if (k <= kSuper) {
+      b.n_mid++;
+      b.pairs_mid += k * (k - 1) / 2;
+    } else {
+      const int64_t ns = (k + kSuper - 1) / kSuper;
+      b.n_big++;
+      b.n_tiles += ns * (ns + 1) / 2;
+      b.pairs_big += k * (k - 1) / 2;
+    }
+  }
+}
+
+static ef_status alloc_bins(Graph &g, Bins &b) {
+  const size_t bytes = sizeof(int32_t) * (size_t)(b.n_small + b.n_mid + 8) +
+                       sizeof(BigCentre) * (size_t)(b.n_big + 1) +
+                       sizeof(TileItem) * (size_t)(b.n_tiles + 1) + 1024;
+  ef_status s = ws_ensure(g, WS_BINS, bytes, "work lists");
+  if (s != EF_OK) return s;
+  char *p = (char *)g.ws[WS_BINS].p;
+  auto take = [&](size_t n) {
+    char *r = p;
+    p += (n + 255) & ~(size_t)255;
+    return r;
+  };
+  b.counters = (int32_t *)take(sizeof(int32_t) * 8);
+  b.small = (int32_t *)take(sizeof(int32_t) * (size_t)(b.n_small + 1));
+  b.mid = (int32_t *)take(sizeof(int32_t) * (size_t)(b.n_mid + 1));
+  b.big = (BigCentre *)take(sizeof(BigCentre) * (size_t)(b.n_big + 1));
+  b.tiles = (TileItem *)take(sizeof(TileItem) * (size_t)(b.n_tiles + 1));
+  return EF_OK;
+}
+
+struct Prof {
+  Graph &g;
+  bool on;
+  hipStream_t st;
+  int used = 0;
+  int idx[16];
+  Prof(Graph &gg, bool o, hipStream_t s) : g(gg), on(o), st(s) {}
+  ef_status init() {
+    if (!on || g.ev_ready) return EF_OK;
+    for (auto &e : g.ev) {
+      hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return hip_status(r, "hipEventCreate");
+    }
+    g.ev_ready = true;
+    return EF_OK;
+  }
+  hipEvent_t ev(int i) { return on ? g.ev[i] : nullptr; }
+  void mark(int i) {
+    if (on) (void)hipEventRecord(g.ev[i], st);
+  }
+  double ms(int a, int b) {
+    float t = 0.f;
+    if (!on) return 0.0;
+    if (hipEventElapsedTime(&t, g.ev[a], g.ev[b]) != hipSuccess) {
+      (void)hipGetLastError();
+      return 0.0;
+    }
+    return (double)t;
+  }
+};
+
+}  // namespace efi
+
+extern "C" ef_status ef_compute(ef_graph *h, ef_algo algo, ef_prec prec, const int32_t *seeds,
+                                int32_t n_seeds, double *ef, int64_t *D, int64_t *N,
+                                uint32_t flags, void *hip_stream) {
+  if (!h || !ef) {
+    set_error("ef_compute: null handle or output");
+    return EF_ERR_ARG;
+  }
+  if ((algo != EF_ALGO_CLUSTER && algo != EF_ALGO_PER_SEED) ||
+      (prec != EF_PREC_FP64 && prec != EF_PREC_FP32C)) {
+    set_error("ef_compute: bad algorithm or precision");
+    return EF_ERR_ARG;
+  }
+  if (flags & ~(EF_OUT_DEVICE | EF_PROFILE)) {
+    set_error("ef_compute: unknown flags 0x%x", flags);
+    return EF_ERR_ARG;
+  }
+  Graph &g = h->g;
+  if (seeds && n_seeds < 0) {
+    set_error("ef_compute: negative n_seeds");
+    return EF_ERR_ARG;
+  }
+  if (seeds && n_seeds == 0) return EF_OK;
+  if (seeds) {
+    for (int32_t i = 0; i < n_seeds; ++i)
+      if (seeds[i] < 0 || seeds[i] >= g.n) {
+        set_error("ef_compute: seed %d at position %d out of range [0, %d)", seeds[i], i, g.n);
+        return EF_ERR_RANGE;
+      }
+  }
+  if (!seeds && g.n == 0) return EF_OK;
+  hipStream_t st = (hipStream_t)hip_stream;
+  const bool out_dev = (flags & EF_OUT_DEVICE) != 0;
+  Prof prof(g, (flags & EF_PROFILE) != 0, st);
+  ef_status s = prof.init();
+  if (s != EF_OK) return s;
+  g.stats = ef_run_stats{};
+  const size_t tsz = prec == EF_PREC_FP64 ? sizeof(double) : sizeof(float2);
+  const int64_t nnz = std::max<int64_t>(g.nnz, 1), nup = std::max<int64_t>(g.nnz / 2, 1);
+
+  // seeds: unique sorted list + inverse map
+  const bool all = seeds == nullptr;
+  std::vector<int32_t> useeds, inv;
+  int32_t n_out = all ? g.n : n_seeds;
+  if (!all) {
+    useeds.assign(seeds, seeds + n_seeds);
+    std::sort(useeds.begin(), useeds.end());
+    useeds.erase(std::unique(useeds.begin(), useeds.end()), useeds.end());
+    inv.resize((size_t)n_seeds);
+    for (int32_t i = 0; i < n_seeds; ++i)
+      inv[i] = (int32_t)(std::lower_bound(useeds.begin(), useeds.end(), seeds[i]) - useeds.begin());
+  }
+  const bool per_seed = !all || algo == EF_ALGO_PER_SEED;
+  const int32_t n_work = all ? g.n : (int32_t)useeds.size();
+
+  // work lists of the pair loop
+  Bins b;
+  if (all) {
+    b.n_small = g.all_small;
+    b.n_mid = g.all_mid;
+    b.n_big = g.all_big;
+    b.n_tiles = g.all_tiles;
+    b.pairs_small = g.all_pairs_small;
+    b.pairs_mid = g.all_pairs_mid;
+    b.pairs_big = g.all_pairs_big;
+  } else {
+    host_bins(g, useeds.data(), (int64_t)useeds.size(), b);
+  }
+  if ((s = alloc_bins(g, b)) != EF_OK) return s;
+  if ((s = ws_ensure(g, WS_R, tsz * (size_t)nnz, "arc sums")) != EF_OK) return s;
+  if ((s = ws_ensure(g, WS_REC, tsz * (size_t)kRecEntries * (size_t)std::max<int64_t>(b.n_tiles, 1),
+                     "super-tile records")) != EF_OK)
+    return s;
+  if ((s = ws_ensure(g, WS_FLAG, sizeof(int32_t) * (size_t)std::max<int32_t>(n_work, 1),
+                     "flag list")) != EF_OK)
+    return s;
+  // outputs of the unique work list: straight into the caller's device arrays
+  // when possible, else into staging
+  double *ef_w = nullptr;
+  int64_t *D_w = nullptr, *N_w = nullptr;
+  const size_t out_bytes = (sizeof(double) + 2 * sizeof(int64_t)) * (size_t)std::max(n_work, 1);
+  if ((s = ws_ensure(g, WS_UOUT, out_bytes, "output staging")) != EF_OK) return s;
+  {
+    char *p = (char *)g.ws[WS_UOUT].p;
+    ef_w = (double *)p;
+    D_w = (int64_t *)(p + sizeof(double) * (size_t)std::max(n_work, 1));
+    N_w = D_w + std::max(n_work, 1);
+    if (all && out_dev) {
+      ef_w = ef;
+      if (D) D_w = D;
+      if (N) N_w = N;
+    }
+  }
+  int32_t *cnt = g.d_counters;  // [0] flagged, [1] fp64-finalised
+  hipError_t e = hipMemsetAsync(cnt, 0, sizeof(int32_t) * 4, st);
+  if (e != hipSuccess) return hip_status(e, "clear counters");
+  int32_t *flagged = (int32_t *)g.ws[WS_FLAG].p;
+
+  // device seed arrays
+  int32_t *d_useeds = nullptr, *d_inv = nullptr, *d_bigseeds = nullptr, *d_bigslot = nullptr;
+  std::vector<int32_t> bigseeds, bigslot;
+  if (per_seed) {
+    const std::vector<int32_t> *work = &useeds;
+    std::vector<int32_t> iota;
+    if (all) {
+      iota.resize((size_t)g.n);
+      std::iota(iota.begin(), iota.end(), 0);
+      work = &iota;
+    }
+    bigslot.assign(work->size(), -1);
+    for (size_t i = 0; i < work->size(); ++i)
+      if (g.h_deg[(*work)[i]] > kSeedHashMax) {
+        bigslot[i] = (int32_t)bigseeds.size();
+        bigseeds.push_back((*work)[i]);
+      }
+    const size_t cnt_all = work->size() * 2 + bigseeds.size() + inv.size() + 4;
+    if ((s = ws_ensure(g, WS_SEEDS, sizeof(int32_t) * cnt_all, "seed lists")) != EF_OK) return s;
+    d_useeds = (int32_t *)g.ws[WS_SEEDS].p;
+    d_bigslot = d_useeds + work->size();
+    d_bigseeds = d_bigslot + work->size();
+    d_inv = d_bigseeds + bigseeds.size();
+    e = hipMemcpyAsync(d_useeds, work->data(), sizeof(int32_t) * work->size(),
+                       hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(d_bigslot, bigslot.data(), sizeof(int32_t) * bigslot.size(),
+                         hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !bigseeds.empty())
+      e = hipMemcpyAsync(d_bigseeds, bigseeds.data(), sizeof(int32_t) * bigseeds.size(),
+                         hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !inv.empty())
+      e = hipMemcpyAsync(d_inv, inv.data(), sizeof(int32_t) * inv.size(), hipMemcpyHostToDevice,
+                         st);
+    if (e != hipSuccess) return hip_status(e, "upload seeds");
+    if (!bigseeds.empty()) {
+      const size_t words = ((size_t)g.n + 31) / 32;
+      const size_t need = sizeof(uint32_t) * words * bigseeds.size();
+      const bool fresh = g.ws[WS_BITMAP].bytes < need;
+      if ((s = ws_ensure(g, WS_BITMAP, need, "membership bitmaps")) != EF_OK) return s;
+      if (fresh) {
+        e = hipMemsetAsync(g.ws[WS_BITMAP].p, 0, g.ws[WS_BITMAP].bytes, st);
+        if (e != hipSuccess) return hip_status(e, "clear bitmaps");
+      }
+    }
+  }
+
+  prof.mark(0);
+  e = launch_bin_centres(g, per_seed ? d_useeds : nullptr, n_work, b, st);
+  if (e != hipSuccess) return hip_status(e, "binning");
+  prof.mark(1);
+  e = launch_pairs(g, prec, b, g.ws[WS_R].p, g.ws[WS_REC].p, st, prof.ev(2), prof.ev(3),
+                   prof.ev(4));
+  if (e != hipSuccess) return hip_status(e, "pair loop");
+  prof.mark(5);
+  if (!per_seed) {
+    if ((s = ws_ensure(g, WS_Y, tsz * (size_t)nup, "triangle slots")) != EF_OK) return s;
+    if ((s = ws_ensure(g, WS_YT, sizeof(int32_t) * (size_t)nup, "triangle counts")) != EF_OK) return s;
+    if ((s = ws_ensure(g, WS_Z, tsz * (size_t)std::max(g.n, 1), "triangle node sums")) != EF_OK) return s;
+    if ((s = ws_ensure(g, WS_ZT, sizeof(int64_t) * (size_t)std::max(g.n, 1), "triangle node counts")) != EF_OK)
+      return s;
+    void *yacc = nullptr;
+    if (g.n_tri_long > 0) {
+      if ((s = ws_ensure(g, WS_YACC, tsz * (size_t)nup, "triangle scratch")) != EF_OK) return s;
+      yacc = g.ws[WS_YACC].p;
+    }
+    e = launch_triangles_ex(g, prec, g.tri_small, g.n_tri_small, g.tri_large, g.n_tri_large,
+                            g.tri_long, g.n_tri_long, g.ws[WS_Y].p, (int32_t *)g.ws[WS_YT].p,
+                            g.ws[WS_Z].p, (int64_t *)g.ws[WS_ZT].p, yacc, st);
+    if (e != hipSuccess) return hip_status(e, "triangle pass");
+    prof.mark(6);
+    e = launch_finalize_cluster(g, prec, g.ws[WS_R].p, g.ws[WS_Y].p, (int32_t *)g.ws[WS_YT].p,
+                                g.ws[WS_Z].p, (int64_t *)g.ws[WS_ZT].p, ef_w, D_w, N_w, flagged,
+                                cnt, cnt + 1, st);
+    if (e != hipSuccess) return hip_status(e, "finalize");
+    prof.mark(7);
+  } else {
+    e = launch_per_seed(g, prec, d_useeds, n_work, g.ws[WS_R].p, (uint32_t *)g.ws[WS_BITMAP].p,
+                        d_bigseeds, d_bigslot, (int32_t)bigseeds.size(), ef_w, D_w, N_w, flagged,
+                        cnt, cnt + 1, st, prof.ev(6));
+    if (e != hipSuccess) return hip_status(e, "per-seed stream");
+    prof.mark(7);
+  }
+  if (prec == EF_PREC_FP32C) {
+    e = launch_pass2(g, per_seed ? d_useeds : nullptr, flagged, cnt, n_work, ef_w, D_w, st);
+    if (e != hipSuccess) return hip_status(e, "pass 2");
+  }
+  prof.mark(8);
+
+  // deliver outputs
+  if (!all) {
+    if (out_dev) {
+      e = launch_gather_outputs(d_inv, n_seeds, ef_w, D_w, N_w, ef, D, N, st);
+      if (e != hipSuccess) return hip_status(e, "scatter outputs");
+    } else {
+      std::vector<double> hef((size_t)n_work);
+      std::vector<int64_t> hD((size_t)n_work), hN((size_t)n_work);
+      e = hipMemcpyAsync(hef.data(), ef_w, sizeof(double) * n_work, hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(hD.data(), D_w, sizeof(int64_t) * n_work, hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(hN.data(), N_w, sizeof(int64_t) * n_work, hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) return hip_status(e, "copy outputs");
+      for (int32_t i = 0; i < n_seeds; ++i) {
+        ef[i] = hef[inv[i]];
+        if (D) D[i] = hD[inv[i]];
+        if (N) N[i] = hN[inv[i]];
+      }
+    }
+  } else if (!out_dev) {
+    e = hipMemcpyAsync(ef, ef_w, sizeof(double) * (size_t)n_out, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && D)
+      e = hipMemcpyAsync(D, D_w, sizeof(int64_t) * (size_t)n_out, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && N)
+      e = hipMemcpyAsync(N, N_w, sizeof(int64_t) * (size_t)n_out, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_status(e, "copy outputs");
+  }
+  g.stats.pair_tiles = b.n_tiles;
+  g.stats.pairs_small = b.pairs_small;
+  g.stats.pairs_mid = b.pairs_mid;
+  g.stats.pairs_big = b.pairs_big;
+  g.stats.seeds = n_work;
+  if (prof.on || !out_dev) {
+    int32_t hc[2] = {0, 0};
+    e = hipMemcpyAsync(hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_status(e, "read counters");
+    g.stats.promoted = hc[0];
+    g.stats.fp64_finalized = hc[1];
+  }
+  if (prof.on) {
+    g.stats.t_bin_ms = prof.ms(0, 1);
+    g.stats.t_pairs_small_ms = prof.ms(1, 2);
+    g.stats.t_pairs_mid_ms = prof.ms(2, 3);
+    g.stats.t_pairs_big_ms = prof.ms(3, 4);
+    g.stats.t_pairs_ms = prof.ms(1, 4);
+    g.stats.t_reduce_ms = prof.ms(4, 5);
+    if (!per_seed) {
+      g.stats.t_triangles_ms = prof.ms(5, 6);
+      g.stats.t_finalize_ms = prof.ms(6, 7);
+    } else {
+      g.stats.t_stream_ms = prof.ms(5, 7);
+    }
+    g.stats.t_pass2_ms = prof.ms(7, 8);
+    g.stats.t_total_ms = prof.ms(0, 8);
+  }
+  return EF_OK;
+}

@@ -1,0 +1,170 @@
+// Internal declarations shared by the host orchestration (ef_api.cpp) and the
+// kernel translation units (*.hip). Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "ef.h"
+
+namespace efi {
+
+// ---------------------------------------------------------------------------
+// Work decomposition constants.
+//
+// Centres (nodes with k >= 2) are binned by degree k:
+//   small  2 <= k <= 64      one wavefront per centre, one 64x64 diagonal tile
+//   mid    64 < k <= 1024    one 16-wavefront workgroup per centre
+//   big    k > 1024          the pair triangle is cut into super-tiles of
+//                            1024 x 1024 neighbours, one workgroup each
+// ---------------------------------------------------------------------------
+constexpr int kWave = 64;
+constexpr int kSmallMax = 64;
+constexpr int kSuper = 1024;          // neighbours per super-block
+constexpr int kBlocksPerSuper = 16;   // 64-wide blocks per super-block
+constexpr int kRecEntries = 2 * kSuper;  // row part + column part per super-tile record
+
+// Triangle pass: nodes whose degree-oriented out-list up(u) has at most
+// kTriHashMax entries use an LDS hash; longer lists search global memory.
+constexpr int kTriHashMax = 512;
+constexpr int kTriHashSlots = 1024;
+
+// Per-seed stream: seeds with k <= kSeedHashMax use an LDS hash of N(s);
+// larger seeds a bitmap over all node ids in device memory.
+constexpr int kSeedHashMax = 2048;
+constexpr int kSeedHashSlots = 4096;
+
+// FP32C: seeds whose estimated cancellation factor (S/D)/EF exceeds this are
+// recomputed from non-negative terms.
+constexpr float kKappaMax = 16.0f;
+
+struct BigCentre {
+  int32_t v;         // node id
+  int32_t ns;        // number of super-blocks, ceil(k / 1024)
+  int64_t rec_base;  // first super-tile record of this centre
+};
+
+struct TileItem {
+  int32_t big;  // index into the big-centre list
+  int32_t P, Q; // super-block row / column, P <= Q
+};
+
+// Device buffer that only grows.
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+struct Graph {
+  int dev = 0;
+  int32_t n = 0;
+  int64_t nnz = 0;
+  bool borrowed = false;
+  // device arrays
+  int32_t *row_ptr = nullptr;
+  int32_t *col_idx = nullptr;
+  int32_t *deg = nullptr;      // k_v
+  int32_t *src = nullptr;      // source node of every arc
+  int32_t *rev = nullptr;      // index of the reverse arc
+  int2 *adj2 = nullptr;        // (neighbour id, neighbour degree) per arc
+  int64_t *asum = nullptr;     // sum of neighbour degrees per node
+  int32_t *up_ptr = nullptr;   // degree-oriented half adjacency: u -> {w : rank(w) > rank(u)}
+  int32_t *up_col = nullptr;
+  int32_t *tslot = nullptr;    // for every arc: slot of its undirected edge in up_col
+  // host copies used for sizing work lists
+  std::vector<int32_t> h_deg;
+  std::vector<int32_t> h_up_len;
+  // triangle-pass node lists (device) by |up(u)|
+  int32_t *tri_small = nullptr, *tri_large = nullptr, *tri_long = nullptr;
+  int64_t n_tri_small = 0, n_tri_large = 0, n_tri_long = 0;
+  // bin counts for the all-nodes centre set
+  int64_t all_small = 0, all_mid = 0, all_big = 0, all_tiles = 0;
+  int64_t all_pairs_small = 0, all_pairs_mid = 0, all_pairs_big = 0;
+  int64_t owned_bytes = 0;  // device bytes held by this handle
+  int32_t *d_counters = nullptr;  // persistent small counters (flag counts etc.)
+  ef_graph_info info{};
+  ef_run_stats stats{};
+  // workspace (grow-only, reused across calls)
+  DevBuf ws[16];
+  // events for EF_PROFILE
+  hipEvent_t ev[16] = {};
+  bool ev_ready = false;
+};
+
+// error text (thread-local)
+void set_error(const char *fmt, ...);
+ef_status hip_status(hipError_t e, const char *what);
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (defined in the .hip files). All are asynchronous on `st`
+// and return hipSuccess or the launch error.
+// ---------------------------------------------------------------------------
+
+// graph preprocessing
+hipError_t launch_graph_prep(Graph &g, int32_t *flags_scan_tmp, hipStream_t st);
+hipError_t launch_exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t count,
+                                     int32_t *block_tmp, int64_t block_tmp_len, hipStream_t st);
+int64_t scan_tmp_len(int64_t count);
+
+// work lists
+struct Bins {
+  int32_t *small = nullptr;      // centre ids
+  int32_t *mid = nullptr;
+  BigCentre *big = nullptr;
+  TileItem *tiles = nullptr;
+  int32_t *counters = nullptr;   // [0] small, [1] mid, [2] big, [3] tiles (device)
+  int64_t n_small = 0, n_mid = 0, n_big = 0, n_tiles = 0;  // host-known counts
+  int64_t pairs_small = 0, pairs_mid = 0, pairs_big = 0;     // clusters per bin
+};
+hipError_t launch_bin_centres(const Graph &g, const int32_t *centres, int32_t n_centres,
+                              Bins &b, hipStream_t st);
+
+// pair loop: writes R (per arc, base cluster scores without triangle
+// correction) for the arcs of every centre in the bins; big centres go via
+// super-tile records and a per-arc reduction.
+// ev_small / ev_mid / ev_big (nullable) are recorded after the small, mid and
+// super-tile kernels.
+hipError_t launch_pairs(const Graph &g, ef_prec prec, const Bins &b, void *R, void *records,
+                        hipStream_t st, hipEvent_t ev_small, hipEvent_t ev_mid,
+                        hipEvent_t ev_big);
+
+// triangle pass (cluster-centric): Y/YT per up-arc slot, Z/ZT per node.
+// Node lists by |up(u)|: small (2..512), large (513..4096), long (> 4096).
+hipError_t launch_triangles_ex(const Graph &g, ef_prec prec, const int32_t *small,
+                               int64_t n_small, const int32_t *large, int64_t n_large,
+                               const int32_t *lng, int64_t n_long, void *Y, int32_t *YT,
+                               void *Z, int64_t *ZT, void *Yacc_tmp, hipStream_t st);
+
+// per-node sums + Eq. 1 (cluster-centric). Appends cancellation-prone seeds to
+// `flagged` (count in *flag_count).
+hipError_t launch_finalize_cluster(const Graph &g, ef_prec prec, const void *R, const void *Y,
+                                   const int32_t *YT, const void *Z, const int64_t *ZT,
+                                   double *ef, int64_t *D, int64_t *N, int32_t *flagged,
+                                   int32_t *flag_count, int32_t *fp64_count, hipStream_t st);
+
+// per-seed formulation: star sums from R of the seed's own arcs, 2-hop stream,
+// then Eq. 1. seeds[i] (unique) are processed; outputs at position i.
+// Seeds with k > kSeedHashMax use the bitmaps; big_seeds lists them and
+// big_slot[i] gives seed i's bitmap (or -1).
+hipError_t launch_per_seed(const Graph &g, ef_prec prec, const int32_t *seeds, int32_t n_seeds,
+                           const void *R, uint32_t *bitmaps, const int32_t *big_seeds,
+                           const int32_t *big_slot, int32_t n_big_seeds, double *ef, int64_t *D,
+                           int64_t *N, int32_t *flagged, int32_t *flag_count,
+                           int32_t *fp64_count, hipStream_t st, hipEvent_t ev_stream_done);
+
+// FP32C pass 2: recompute EF of flagged positions from non-negative terms.
+// seeds[pos] gives the node of output position pos (NULL: pos is the node).
+hipError_t launch_pass2(const Graph &g, const int32_t *seeds, const int32_t *flagged,
+                        const int32_t *flag_count, int32_t max_flagged, double *ef,
+                        const int64_t *D, hipStream_t st);
+
+// scatter outputs of unique seeds back to the caller's positions
+hipError_t launch_gather_outputs(const int32_t *inv, int32_t count, const double *ef_u,
+                                 const int64_t *D_u, const int64_t *N_u, double *ef,
+                                 int64_t *D, int64_t *N, hipStream_t st);
+
+}  // namespace efi

@@ -1,0 +1,424 @@
+// Cluster generation and scoring: the pair loop of Algorithm 1.
+//
+// For a centre v with neighbours a_0 < ... < a_{k-1} (degrees k_p), every
+// unordered pair p < q is a cluster (a_p, v, a_q) (Algorithm 1, Phase 1). Its
+// degree before the triangle adjustment is d = k_v + k_p + k_q - 4 (Phase 2);
+// the triangle adjustment is applied afterwards by the triangle pass. The
+// score g(d) = d log d is credited to both ends, so per arc v->a_p we form
+//   R[v->a_p] = sum_{q != p} g(k_v + k_p + k_q - 4)
+// and every cluster's score is evaluated exactly once.
+//
+// Layout on a wavefront: lane l holds row p = 64*rb + l of a 64x64 tile and
+// keeps the row sum in a register; the column index rotates through the
+// wavefront with a DPP wave rotate, together with a rotating column
+// accumulator, so after 64 steps each lane holds one column sum. Tiles on the
+// diagonal of the pair triangle take 32 steps (each unordered pair once).
+//
+// Work bins:
+//   small (k <= 64)   one wavefront per centre: one diagonal tile
+//   mid   (k <= 1024) one 16-wavefront workgroup per centre: block pairs are
+//                     dealt round-robin so every wavefront gets the same load
+//   big   (k > 1024)  1024x1024 super-tiles, one workgroup each, written as
+//                     records and summed per arc in a fixed order afterwards.
+// Column partials cross wavefronts through LDS; every sum has a fixed order,
+// so results are bitwise reproducible.
+#include "ef_internal.h"
+
+namespace efi {
+
+constexpr float kNegF = -1.0e9f;
+
+// ---------------------------------------------------------------------------
+// wave rotate: lane l receives the value of lane (l + 1) mod 64
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int rot1i(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, 0x134, 0xf, 0xf, false);
+}
+__device__ __forceinline__ float rot1(float x) { return __int_as_float(rot1i(__float_as_int(x))); }
+__device__ __forceinline__ double rot1(double x) {
+  long long b = __double_as_longlong(x);
+  int lo = rot1i((int)(b & 0xffffffffLL));
+  int hi = rot1i((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// score of a cluster degree: FP32 path in log2 units (one v_log_f32), FP64
+// path in natural-log units.
+__device__ __forceinline__ float score(float d) { return d * __builtin_amdgcn_logf(d); }
+__device__ __forceinline__ double score(double d) { return d * log(d); }
+
+template <typename T>
+__device__ __forceinline__ T score_masked(T d) {
+  return d > T(0) ? score(d) : T(0);
+}
+
+// ---------------------------------------------------------------------------
+// double-float accumulation for the FP32 path
+// ---------------------------------------------------------------------------
+struct DF {
+  float hi, lo;
+};
+__device__ __forceinline__ void df_add(DF &a, float x) {
+  float s = a.hi + x;
+  float bb = s - a.hi;
+  float e = (a.hi - (s - bb)) + (x - bb);
+  a.hi = s;
+  a.lo += e;
+}
+__device__ __forceinline__ DF df_norm(DF a) {
+  float h = a.hi + a.lo;
+  return DF{h, a.lo - (h - a.hi)};
+}
+
+template <typename T> struct Acc;
+template <> struct Acc<float> {
+  DF v{0.f, 0.f};
+  __device__ void add(float x) { df_add(v, x); }
+  __device__ void store(void *R, int64_t i) const {
+    DF n = df_norm(v);
+    reinterpret_cast<float2 *>(R)[i] = make_float2(n.hi, n.lo);
+  }
+  __device__ void add_stored(const void *R, int64_t i) {
+    float2 x = reinterpret_cast<const float2 *>(R)[i];
+    df_add(v, x.x);
+    df_add(v, x.y);
+  }
+};
+template <> struct Acc<double> {
+  double v = 0.0;
+  __device__ void add(double x) { v += x; }
+  __device__ void store(void *R, int64_t i) const { reinterpret_cast<double *>(R)[i] = v; }
+  __device__ void add_stored(const void *R, int64_t i) { v += reinterpret_cast<const double *>(R)[i]; }
+};
+
+// ---------------------------------------------------------------------------
+// one 64x64 tile on a wavefront
+//   cp : k_v + k_p - 4 for this lane's row (kNegF if the row is past k)
+//   kq : degree of this lane's column at step 0 (kNegF if past k)
+// DIAG: the tile's rows and columns are the same block; steps 1..32, the
+//   last step only on lanes 0..31. On return C holds the partial of column
+//   (lane + 32) & 63.
+// otherwise steps 0..63; on return C holds the partial of column (lane+63)&63.
+// MASKED: some rows/columns may be invalid, or d may be 0.
+// ---------------------------------------------------------------------------
+template <typename T, bool DIAG, bool MASKED>
+__device__ __forceinline__ void tile(T cp, T kq, T &Rt, T &C) {
+  const int lane = threadIdx.x & 63;
+  Rt = T(0);
+  C = T(0);
+  if (DIAG) {
+#pragma unroll 4
+    for (int s = 1; s <= 32; ++s) {
+      kq = rot1(kq);
+      T d = cp + kq;
+      T g = score_masked(d);
+      if (s == 32) g = lane < 32 ? g : T(0);
+      Rt += g;
+      C = rot1(C) + g;
+    }
+  } else {
+#pragma unroll 8
+    for (int s = 0; s < 64; ++s) {
+      T d = cp + kq;
+      T g = MASKED ? score_masked(d) : score(d);
+      Rt += g;
+      C = rot1(C) + g;
+      kq = rot1(kq);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// small centres: one wavefront per centre (k <= 64)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_pairs_small(const int32_t *__restrict__ row_ptr,
+                                                     const int32_t *__restrict__ deg,
+                                                     const int2 *__restrict__ adj2,
+                                                     const int32_t *__restrict__ list,
+                                                     int64_t count, void *__restrict__ R) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t it = wave; it < count; it += nwaves) {
+    const int32_t v = list[it];
+    const int32_t k = deg[v];
+    const int32_t base = row_ptr[v];
+    const bool valid = lane < k;
+    const T kp = valid ? (T)adj2[base + lane].y : T(0);
+    const T cp = valid ? (T)(k - 4) + kp : (T)kNegF;
+    const T kq = valid ? kp : (T)kNegF;
+    T Rt, C;
+    tile<T, true, true>(cp, kq, Rt, C);
+    // column (lane+32)&63 is in C of lane; bring column `lane` home
+    T Cl = __shfl_xor(C, 32, 64);
+    if (valid) {
+      Acc<T> a;
+      a.add(Rt);
+      a.add(Cl);
+      a.store(R, base + lane);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// shared pieces of the 16-wavefront kernels
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T col_degree(const int2 *adj2, int32_t base, int32_t k, int32_t q) {
+  return q < k ? (T)adj2[base + q].y : (T)kNegF;
+}
+
+// Diagonal block of blocks (a centre's whole pair triangle for mid centres,
+// or a diagonal super-tile for big centres). Blocks blk0 .. blk0+nb-1 of the
+// centre's neighbour list; wavefront w owns row block blk0 + w.
+// parts[c][delta][64]: column partials, zeroed by the caller.
+// On return (after the final barrier), wavefront w's lanes hold in `out` the
+// complete sum for index 64*(blk0+w)+lane over all pairs inside this range.
+template <typename T>
+__device__ void diag_super(const int2 *adj2, int32_t base, int32_t k, T kv4, int blk0, int nb,
+                           T (*parts)[9][64], Acc<T> &out) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (w < nb) {
+    const int32_t p = 64 * (blk0 + w) + lane;
+    const bool rvalid = p < k;
+    const T kp = rvalid ? (T)adj2[base + p].y : T(0);
+    const T cp = rvalid ? kv4 + kp : (T)kNegF;
+    const int half = nb >> 1;
+    const bool ragged = (k & 63) != 0;
+    for (int dl = 0; dl <= half; ++dl) {
+      if (dl > 0 && dl == half && (nb & 1) == 0 && w >= half) break;
+      const int c = (w + dl) % nb;
+      T Rt, C;
+      if (dl == 0) {
+        const T kq = rvalid ? kp : (T)kNegF;
+        tile<T, true, true>(cp, kq, Rt, C);
+        parts[c][0][(lane + 32) & 63] = C;
+      } else {
+        const int32_t q = 64 * (blk0 + c) + lane;
+        const T kq = col_degree<T>(adj2, base, k, q);
+        const bool masked = ragged && (c == nb - 1 || w == nb - 1) && (blk0 + nb) * 64 > k;
+        if (masked) tile<T, false, true>(cp, kq, Rt, C);
+        else tile<T, false, false>(cp, kq, Rt, C);
+        parts[c][dl][(lane + 63) & 63] = C;
+      }
+      out.add(Rt);
+    }
+  }
+  __syncthreads();
+  if (w < nb) {
+    const int half = nb >> 1;
+    for (int dl = 0; dl <= half; ++dl) out.add(parts[w][dl][lane]);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void zero_parts(T *p, int count) {
+  for (int i = threadIdx.x; i < count; i += blockDim.x) p[i] = T(0);
+}
+
+// ---------------------------------------------------------------------------
+// mid centres: one 16-wavefront workgroup per centre (64 < k <= 1024)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(1024) void k_pairs_mid(const int32_t *__restrict__ row_ptr,
+                                                    const int32_t *__restrict__ deg,
+                                                    const int2 *__restrict__ adj2,
+                                                    const int32_t *__restrict__ list,
+                                                    int64_t count, void *__restrict__ R) {
+  __shared__ T parts[kBlocksPerSuper][9][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int64_t it = blockIdx.x; it < count; it += gridDim.x) {
+    const int32_t v = list[it];
+    const int32_t k = deg[v];
+    const int32_t base = row_ptr[v];
+    const int nb = (k + 63) >> 6;
+    zero_parts(&parts[0][0][0], nb * 9 * 64);
+    __syncthreads();
+    Acc<T> out;
+    diag_super<T>(adj2, base, k, (T)(k - 4), 0, nb, parts, out);
+    const int32_t p = 64 * w + lane;
+    if (w < nb && p < k) out.store(R, base + p);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// big centres: one workgroup per 1024x1024 super-tile (P, Q), P <= Q.
+// record layout: [0, 1024) row part (for P == Q: complete in-range sums),
+//                [1024, 2048) column part (P < Q only).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(1024) void k_pairs_big(const int32_t *__restrict__ row_ptr,
+                                                    const int32_t *__restrict__ deg,
+                                                    const int2 *__restrict__ adj2,
+                                                    const BigCentre *__restrict__ big,
+                                                    const TileItem *__restrict__ tiles,
+                                                    int64_t count, void *__restrict__ rec) {
+  __shared__ T parts[kBlocksPerSuper][kBlocksPerSuper][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int64_t it = blockIdx.x; it < count; it += gridDim.x) {
+    const TileItem ti = tiles[it];
+    const BigCentre bc = big[ti.big];
+    const int32_t v = bc.v, k = deg[v], base = row_ptr[v], ns = bc.ns;
+    const int P = ti.P, Q = ti.Q;
+    const int64_t tile_idx = bc.rec_base + (int64_t)P * ns - (int64_t)P * (P - 1) / 2 + (Q - P);
+    const int64_t rbase = tile_idx * kRecEntries;
+    const int nbQ = min(kBlocksPerSuper, (k - kSuper * Q + 63) >> 6);
+    const T kv4 = (T)(k - 4);
+    if (P == Q) {
+      zero_parts(&parts[0][0][0], kBlocksPerSuper * 9 * 64);
+      __syncthreads();
+      Acc<T> out;
+      diag_super<T>(adj2, base, k, kv4, kBlocksPerSuper * P, nbQ,
+                    reinterpret_cast<T(*)[9][64]>(&parts[0][0][0]), out);
+      if (w < nbQ) out.store(rec, rbase + 64 * w + lane);
+    } else {
+      // P < Q: all 16 row blocks of P are full
+      const int32_t p = kSuper * P + 64 * w + lane;
+      const T cp = kv4 + (T)adj2[base + p].y;
+      const bool ragged_q = (kSuper * Q + 64 * nbQ) > k;
+      Acc<T> out;
+      for (int dl = 0; dl < nbQ; ++dl) {
+        const int c = (w + dl) % nbQ;
+        const int32_t q = kSuper * Q + 64 * c + lane;
+        const T kq = col_degree<T>(adj2, base, k, q);
+        T Rt, C;
+        if (ragged_q && c == nbQ - 1) tile<T, false, true>(cp, kq, Rt, C);
+        else tile<T, false, false>(cp, kq, Rt, C);
+        parts[c][w][(lane + 63) & 63] = C;
+        out.add(Rt);
+      }
+      out.store(rec, rbase + 64 * w + lane);
+      __syncthreads();
+      {
+        const int c = threadIdx.x >> 6, j = threadIdx.x & 63;
+        if (c < nbQ) {
+          Acc<T> col;
+          for (int ww = 0; ww < kBlocksPerSuper; ++ww) col.add(parts[c][ww][j]);
+          col.store(rec, rbase + kSuper + 64 * c + j);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Per-arc sum of the super-tile records of big centres, fixed order:
+// R[p] = sum_{Q >= b} row part of (b, Q)  +  sum_{P < b} column part of (P, b)
+template <typename T>
+__global__ __launch_bounds__(256) void k_arc_reduce(const int32_t *__restrict__ row_ptr,
+                                                    const int32_t *__restrict__ deg,
+                                                    const BigCentre *__restrict__ big,
+                                                    int64_t nbig, const void *__restrict__ rec,
+                                                    void *__restrict__ R) {
+  for (int64_t bi = blockIdx.x; bi < nbig; bi += gridDim.x) {
+    const BigCentre bc = big[bi];
+    const int32_t k = deg[bc.v], base = row_ptr[bc.v], ns = bc.ns;
+    for (int32_t p = threadIdx.x; p < k; p += blockDim.x) {
+      const int b = p >> 10, j = p & (kSuper - 1);
+      Acc<T> a;
+      for (int Q = b; Q < ns; ++Q) {
+        const int64_t t = bc.rec_base + (int64_t)b * ns - (int64_t)b * (b - 1) / 2 + (Q - b);
+        a.add_stored(rec, t * kRecEntries + j);
+      }
+      for (int P = 0; P < b; ++P) {
+        const int64_t t = bc.rec_base + (int64_t)P * ns - (int64_t)P * (P - 1) / 2 + (b - P);
+        a.add_stored(rec, t * kRecEntries + kSuper + j);
+      }
+      a.store(R, base + p);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// binning: classify centres by degree and build the work lists
+// counters: [0] small, [1] mid, [2] big, [3] super-tile records
+// ---------------------------------------------------------------------------
+__global__ void k_bin(const int32_t *__restrict__ deg, const int32_t *__restrict__ centres,
+                      int32_t n_centres, int32_t *__restrict__ small, int32_t *__restrict__ mid,
+                      BigCentre *__restrict__ big, int32_t *__restrict__ counters) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_centres;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = centres ? centres[i] : (int32_t)i;
+    const int32_t k = deg[v];
+    if (k < 2) continue;
+    if (k <= kSmallMax) {
+      small[atomicAdd(&counters[0], 1)] = v;
+    } else if (k <= kSuper) {
+      mid[atomicAdd(&counters[1], 1)] = v;
+    } else {
+      const int32_t ns = (k + kSuper - 1) / kSuper;
+      const int32_t nt = ns * (ns + 1) / 2;
+      const int32_t slot = atomicAdd(&counters[2], 1);
+      const int32_t rb = atomicAdd(&counters[3], nt);
+      big[slot] = BigCentre{v, ns, (int64_t)rb};
+    }
+  }
+}
+
+// one workgroup per big centre: its super-tile items (in record order)
+__global__ void k_expand_tiles(const BigCentre *__restrict__ big, const int32_t *__restrict__ counters,
+                               TileItem *__restrict__ tiles) {
+  const int32_t nbig = counters[2];
+  for (int32_t bi = blockIdx.x; bi < nbig; bi += gridDim.x) {
+    const BigCentre bc = big[bi];
+    const int32_t nt = bc.ns * (bc.ns + 1) / 2;
+    for (int32_t t = threadIdx.x; t < nt; t += blockDim.x) {
+      // invert t = P*ns - P*(P-1)/2 + (Q-P)
+      int32_t P = 0, rem = t;
+      while (rem >= bc.ns - P) { rem -= bc.ns - P; ++P; }
+      tiles[bc.rec_base + t] = TileItem{bi, P, P + rem};
+    }
+  }
+}
+
+static unsigned capped(int64_t blocks, int64_t cap) {
+  if (blocks < 1) blocks = 1;
+  return (unsigned)(blocks < cap ? blocks : cap);
+}
+
+hipError_t launch_bin_centres(const Graph &g, const int32_t *centres, int32_t n_centres,
+                              Bins &b, hipStream_t st) {
+  hipError_t e = hipMemsetAsync(b.counters, 0, 4 * sizeof(int32_t), st);
+  if (e != hipSuccess) return e;
+  if (n_centres <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bin, dim3(capped((n_centres + 255) / 256, 65536)), dim3(256), 0, st,
+                     g.deg, centres, n_centres, b.small, b.mid, b.big, b.counters);
+  if (b.n_big > 0)
+    hipLaunchKernelGGL(k_expand_tiles, dim3(capped(b.n_big, 65536)), dim3(256), 0, st, b.big,
+                       b.counters, b.tiles);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t pairs_impl(const Graph &g, const Bins &b, void *R, void *records,
+                             hipStream_t st, hipEvent_t ev_small, hipEvent_t ev_mid,
+                             hipEvent_t ev_big) {
+  if (b.n_small > 0)
+    hipLaunchKernelGGL(k_pairs_small<T>, dim3(capped((b.n_small + 3) / 4, 1 << 20)), dim3(256),
+                       0, st, g.row_ptr, g.deg, g.adj2, b.small, b.n_small, R);
+  if (ev_small) (void)hipEventRecord(ev_small, st);
+  if (b.n_mid > 0)
+    hipLaunchKernelGGL(k_pairs_mid<T>, dim3(capped(b.n_mid, 1 << 20)), dim3(1024), 0, st,
+                       g.row_ptr, g.deg, g.adj2, b.mid, b.n_mid, R);
+  if (ev_mid) (void)hipEventRecord(ev_mid, st);
+  if (b.n_tiles > 0)
+    hipLaunchKernelGGL(k_pairs_big<T>, dim3(capped(b.n_tiles, 1 << 20)), dim3(1024), 0, st,
+                       g.row_ptr, g.deg, g.adj2, b.big, b.tiles, b.n_tiles, records);
+  if (ev_big) (void)hipEventRecord(ev_big, st);
+  if (b.n_big > 0)
+    hipLaunchKernelGGL(k_arc_reduce<T>, dim3(capped(b.n_big, 1 << 20)), dim3(256), 0, st,
+                       g.row_ptr, g.deg, b.big, b.n_big, records, R);
+  return hipGetLastError();
+}
+
+hipError_t launch_pairs(const Graph &g, ef_prec prec, const Bins &b, void *R, void *records,
+                        hipStream_t st, hipEvent_t ev_small, hipEvent_t ev_mid,
+                        hipEvent_t ev_big) {
+  if (prec == EF_PREC_FP64)
+    return pairs_impl<double>(g, b, R, records, st, ev_small, ev_mid, ev_big);
+  return pairs_impl<float>(g, b, R, records, st, ev_small, ev_mid, ev_big);
+}
+
+}  // namespace efi

@@ -1,0 +1,244 @@
+"""Python binding of ``libef.so`` (the C-ABI declared in ``include/ef.h``).
+
+Argument marshalling only: every step of the computation runs in the
+library's HIP kernels. PyTorch, when given, only supplies device memory and
+the current HIP stream. There is no CPU fallback: if the library is missing or
+no gfx950 device is visible, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libef.so")
+
+# status codes (ef_status)
+EF_OK = 0
+STATUS_NAMES = {
+    0: "EF_OK", 1: "EF_ERR_ARG", 2: "EF_ERR_NOT_SYMMETRIC", 3: "EF_ERR_SELF_LOOP",
+    4: "EF_ERR_DUPLICATE", 5: "EF_ERR_UNSORTED", 6: "EF_ERR_RANGE", 7: "EF_ERR_OVERFLOW",
+    8: "EF_ERR_NOMEM", 9: "EF_ERR_DEVICE", 10: "EF_ERR_STATE",
+}
+ALGO = {"cluster": 0, "per_seed": 1}
+PREC = {"fp64": 0, "fp32c": 1}
+EF_VALIDATE = 0x1
+EF_DEVICE_PTRS = 0x2
+EF_OUT_DEVICE = 0x4
+EF_PROFILE = 0x8
+
+# every entry point declared in include/ef.h
+EXPORTS = [
+    "ef_last_error", "ef_version", "ef_device_count", "ef_validate_csr", "ef_graph_load_csr",
+    "ef_graph_from_edges", "ef_graph_free", "ef_graph_info_get", "ef_compute", "ef_stats",
+]
+
+
+class EFError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        self.status = status
+        self.name = STATUS_NAMES.get(status, str(status))
+        super().__init__(f"{self.name}: {message}")
+
+
+class GraphInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64), ("max_degree", ctypes.c_int32),
+                ("clusters", ctypes.c_int64), ("sum_sq_degree", ctypes.c_int64),
+                ("up_arcs", ctypes.c_int64), ("wedge_checks", ctypes.c_int64)]
+
+
+class RunStats(ctypes.Structure):
+    _fields_ = [("t_bin_ms", ctypes.c_double), ("t_pairs_ms", ctypes.c_double),
+                ("t_pairs_small_ms", ctypes.c_double), ("t_pairs_mid_ms", ctypes.c_double),
+                ("t_pairs_big_ms", ctypes.c_double), ("t_reduce_ms", ctypes.c_double),
+                ("t_triangles_ms", ctypes.c_double), ("t_stream_ms", ctypes.c_double),
+                ("t_finalize_ms", ctypes.c_double), ("t_pass2_ms", ctypes.c_double),
+                ("t_total_ms", ctypes.c_double), ("pairs_small", ctypes.c_int64),
+                ("pairs_mid", ctypes.c_int64), ("pairs_big", ctypes.c_int64),
+                ("pair_tiles", ctypes.c_int64), ("promoted", ctypes.c_int64),
+                ("fp64_finalized", ctypes.c_int64), ("seeds", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def _preload_hip_runtime():
+    """Load PyTorch's HIP runtime (by path, globally) before libef.so, so that
+    torch and this library share one runtime in the process: the same device
+    allocations and the same stream objects."""
+    import importlib.util
+
+    spec = importlib.util.find_spec("torch")
+    if spec and spec.submodule_search_locations:
+        rt = os.path.join(spec.submodule_search_locations[0], "lib", "libamdhip64.so")
+        if os.path.exists(rt):
+            ctypes.CDLL(rt, mode=ctypes.RTLD_GLOBAL)
+
+
+def lib():
+    """Load libef.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "(there is no CPU fallback)")
+    _preload_hip_runtime()
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    L.ef_last_error.restype = ctypes.c_char_p
+    L.ef_last_error.argtypes = []
+    L.ef_version.restype = i32
+    L.ef_device_count.argtypes = [ctypes.POINTER(i32)]
+    L.ef_validate_csr.argtypes = [i32, i64, vp, vp]
+    L.ef_graph_load_csr.argtypes = [i32, i64, vp, vp, u32, vp, ctypes.POINTER(vp)]
+    L.ef_graph_from_edges.argtypes = [i32, i64, vp, vp, vp, ctypes.POINTER(vp)]
+    L.ef_graph_free.argtypes = [vp]
+    L.ef_graph_info_get.argtypes = [vp, ctypes.POINTER(GraphInfo)]
+    L.ef_compute.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, i32, vp, vp, vp, u32, vp]
+    L.ef_stats.argtypes = [vp, ctypes.POINTER(RunStats)]
+    for name in EXPORTS[2:]:
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return lib().ef_last_error().decode()
+
+
+def _check(status: int):
+    if status != EF_OK:
+        raise EFError(status, last_error())
+
+
+def device_count() -> int:
+    c = ctypes.c_int32(0)
+    _check(lib().ef_device_count(ctypes.byref(c)))
+    return int(c.value)
+
+
+def validate_csr(row_ptr, col_idx):
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    n = rp.size - 1
+    _check(lib().ef_validate_csr(n, int(ci.size), rp.ctypes.data,
+                                 ci.ctypes.data if ci.size else None))
+
+
+def _is_torch(x):
+    return type(x).__module__.startswith("torch")
+
+
+def _stream_ptr(stream):
+    if stream is not None:
+        return ctypes.c_void_p(int(stream))
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except Exception:
+        pass
+    return None
+
+
+class Graph:
+    """A graph loaded into device memory (opaque handle ``ef_graph``)."""
+
+    def __init__(self, row_ptr, col_idx, validate: bool = True, stream=None):
+        self._h = ctypes.c_void_p()
+        flags = EF_VALIDATE if validate else 0
+        if _is_torch(row_ptr) and row_ptr.is_cuda:
+            # borrowed device arrays: keep references alive
+            self._keep = (row_ptr.contiguous(), col_idx.contiguous())
+            rp, ci = self._keep
+            assert rp.dtype == ci.dtype and str(rp.dtype) == "torch.int32"
+            n, nnz = rp.numel() - 1, ci.numel()
+            flags |= EF_DEVICE_PTRS
+            _check(lib().ef_graph_load_csr(n, nnz, rp.data_ptr(), ci.data_ptr() if nnz else None,
+                                           flags, _stream_ptr(stream), ctypes.byref(self._h)))
+        else:
+            rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+            ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+            n, nnz = rp.size - 1, ci.size
+            _check(lib().ef_graph_load_csr(n, nnz, rp.ctypes.data,
+                                           ci.ctypes.data if nnz else None, flags,
+                                           _stream_ptr(stream), ctypes.byref(self._h)))
+        self.n = n
+        self.nnz = nnz
+
+    @classmethod
+    def from_edges(cls, n, src, dst, stream=None):
+        self = cls.__new__(cls)
+        self._h = ctypes.c_void_p()
+        s = np.ascontiguousarray(src, dtype=np.int32)
+        d = np.ascontiguousarray(dst, dtype=np.int32)
+        _check(lib().ef_graph_from_edges(int(n), int(s.size), s.ctypes.data, d.ctypes.data,
+                                         _stream_ptr(stream), ctypes.byref(self._h)))
+        self.n = int(n)
+        self.nnz = self.info()["nnz"]
+        return self
+
+    def info(self) -> dict:
+        inf = GraphInfo()
+        _check(lib().ef_graph_info_get(self._h, ctypes.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in GraphInfo._fields_}
+
+    def stats(self) -> dict:
+        st = RunStats()
+        _check(lib().ef_stats(self._h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def compute(self, algo: str = "cluster", prec: str = "fp32c", seeds=None,
+                out=None, profile: bool = False, stream=None):
+        """EF (and exact D, N) of all nodes or of `seeds`.
+
+        Host mode (out=None): returns numpy (ef float64, D int64, N int64).
+        Device mode: `out` = (ef, D, N) torch CUDA tensors (D, N may be None);
+        the call is asynchronous on `stream` (default: torch's current stream).
+        """
+        flags = EF_PROFILE if profile else 0
+        if seeds is not None:
+            sd = np.ascontiguousarray(seeds, dtype=np.int32)
+            ns = sd.size
+            sp = sd.ctypes.data if ns else None
+        else:
+            sd, ns, sp = None, 0, None
+        count = ns if seeds is not None else self.n
+        if out is None:
+            ef = np.zeros(max(count, 1), np.float64)
+            D = np.zeros(max(count, 1), np.int64)
+            N = np.zeros(max(count, 1), np.int64)
+            _check(lib().ef_compute(self._h, ALGO[algo], PREC[prec], sp, ns, ef.ctypes.data,
+                                    D.ctypes.data, N.ctypes.data, flags, _stream_ptr(stream)))
+            return ef[:count], D[:count], N[:count]
+        ef, D, N = out
+        flags |= EF_OUT_DEVICE
+        _check(lib().ef_compute(self._h, ALGO[algo], PREC[prec], sp, ns, ef.data_ptr(),
+                                D.data_ptr() if D is not None else None,
+                                N.data_ptr() if N is not None else None, flags,
+                                _stream_ptr(stream)))
+        return ef, D, N
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().ef_graph_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

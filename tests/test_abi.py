@@ -1,0 +1,102 @@
+"""The C-ABI library on the host (no GPU needed): it loads, exports every
+entry point that include/ef.h declares, validates CSR input with the
+documented status codes, and reports missing devices instead of failing."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2306_00606_amd import efgpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ef.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ef_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = efgpu.lib()
+    names = declared_functions()
+    assert names, "no declarations parsed"
+    for name in names:
+        assert hasattr(L, name), f"{name} declared in ef.h but not exported"
+    assert sorted(efgpu.EXPORTS) == names
+
+
+def test_version_and_error_text():
+    assert efgpu.lib().ef_version() >= 10000
+    assert isinstance(efgpu.last_error(), str)
+
+
+def _valid():
+    # path 0-1-2 plus isolated node 3
+    return np.array([0, 1, 3, 4, 4], np.int32), np.array([1, 0, 2, 1], np.int32)
+
+
+CASES = [
+    ("self_loop", [0, 2, 3, 4], [0, 1, 0, 1], "EF_ERR_SELF_LOOP"),
+    ("duplicate", [0, 2, 4], [1, 1, 0, 0], "EF_ERR_DUPLICATE"),
+    ("unsorted", [0, 2, 3, 4], [2, 1, 0, 0], "EF_ERR_UNSORTED"),
+    ("row_ptr_decreasing", [0, 2, 1, 2], [1, 2], "EF_ERR_UNSORTED"),
+    ("out_of_range", [0, 1, 2], [1, 5], "EF_ERR_RANGE"),
+    ("negative_id", [0, 1, 2], [1, -1], "EF_ERR_RANGE"),
+    ("row_ptr_start", [1, 2, 3], [1, 0], "EF_ERR_RANGE"),
+    ("not_symmetric", [0, 1, 1, 1], [1], "EF_ERR_NOT_SYMMETRIC"),
+]
+
+
+def test_valid_csr_passes():
+    efgpu.validate_csr(*_valid())
+    efgpu.validate_csr(np.zeros(1, np.int32), np.zeros(0, np.int32))  # empty graph
+
+
+@pytest.mark.parametrize("name,rp,ci,code", CASES, ids=[c[0] for c in CASES])
+def test_malformed_csr_reports_specific_status(name, rp, ci, code):
+    with pytest.raises(efgpu.EFError) as ei:
+        efgpu.validate_csr(np.array(rp, np.int32), np.array(ci, np.int32))
+    assert ei.value.name == code
+    assert efgpu.last_error()
+
+
+def test_overflow_and_null_arguments():
+    L = efgpu.lib()
+    rp = np.zeros(2, np.int32)
+    assert L.ef_validate_csr(1, 2 ** 31, rp.ctypes.data, rp.ctypes.data) == 7  # EF_ERR_OVERFLOW
+    assert L.ef_validate_csr(1, 0, None, None) == 1  # EF_ERR_ARG
+    assert L.ef_validate_csr(-1, 0, rp.ctypes.data, None) == 1
+    assert L.ef_graph_free(None) == 1
+    assert L.ef_stats(None, None) == 1
+    assert L.ef_compute(None, 0, 0, None, 0, None, None, None, 0, None) == 1
+    assert L.ef_device_count(None) == 1
+
+
+def test_graph_info_struct_layout_matches_header():
+    # the ctypes mirrors of the two structs must match the C declarations
+    text = open(HEADER).read()
+    for struct, fields in (("ef_graph_info", efgpu.GraphInfo._fields_),
+                           ("ef_run_stats", efgpu.RunStats._fields_)):
+        body = re.search(r"typedef struct \{([^}]*)\}\s*" + struct + ";", text).group(1)
+        body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+        names = re.findall(r"\b([a-z0-9_]+)\s*;", body)
+        assert names == [f for f, _ in fields], struct
+
+
+def _has_gpu():
+    try:
+        return efgpu.device_count() > 0
+    except Exception:
+        return False
+
+
+@pytest.mark.skipif(_has_gpu(), reason="checks the no-device path")
+def test_no_device_is_reported_not_fatal():
+    assert efgpu.device_count() == 0
+    with pytest.raises(efgpu.EFError) as ei:
+        efgpu.Graph(*_valid())
+    assert ei.value.name == "EF_ERR_DEVICE"
