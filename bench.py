@@ -25,12 +25,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "clusters/s & EF nodes/s (R-MAT 42M edges), % HBM peak; surrogate vs exact"
 
-# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = peak VALU lane-instruction
-# issue rate for non-packed 32-bit operations.
-VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
+# MI355X FP32 vector peak 157.3 TFLOP/s counts an FMA as two flops: 78.6e12
+# FP32 lane operations per second (256 CUs x 128 lanes x 2.4 GHz). On the box,
+# non-packed FMA chains reach 5.8e13/s and a v_log_f32 costs about 4 FMA slots.
+VALU_LANE_OPS_PEAK = 256 * 128 * 2.4e9
 # Algorithmic VALU cost of scoring one cluster in the FP32 pair loop, in
-# lane-instruction slots: the degree d = c_p + k_q (1), g = d log2 d
-# (v_log_f32, transcendental at a quarter of the issue rate: 4; multiply: 1),
+# FP32 lane-operation slots: the degree d = c_p + k_q (1), g = d log2 d
+# (v_log_f32, a transcendental at a quarter of the FMA rate: 4; multiply: 1),
 # credit to the row sum (1) and to the column sum (1).
 OPS_PER_CLUSTER = 8
 
@@ -82,6 +83,8 @@ def main():
     ap.add_argument("--scale", type=int, default=22)
     ap.add_argument("--edge-factor", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--per-seed-steps", type=int, default=2,
+                    help="also time the per-seed formulation (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -138,6 +141,30 @@ def main():
     else:
         roofline = None
 
+    per_seed = None
+    if args.algo == "cluster" and args.per_seed_steps > 0:
+        log(f"per-seed formulation: {args.per_seed_steps} steps")
+        g.compute(algo="per_seed", prec=args.prec, out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.per_seed_steps):
+            g.compute(algo="per_seed", prec=args.prec, out=out)
+        torch.cuda.synchronize()
+        ps_ms = 1e3 * (time.perf_counter() - t0) / args.per_seed_steps
+        g.compute(algo="per_seed", prec=args.prec, out=out, profile=True)
+        pst = g.stats()
+        # algorithmic bytes of the 2-hop stream: one (id, degree) pair of 8 B per
+        # entry of every neighbour's row, sum_a k_a^2 entries in total
+        b_stream = 8.0 * info["sum_sq_degree"]
+        per_seed = {"ms_per_step": ps_ms, "clusters_per_s": W / (ps_ms * 1e-3),
+                    "phases_ms": {k[2:-3]: round(pst[k], 4) for k in pst if k.startswith("t_")},
+                    "stream_bytes": b_stream,
+                    "stream_GBps": b_stream / (pst["t_stream_ms"] * 1e-3) / 1e9
+                    if pst["t_stream_ms"] > 0 else None,
+                    "stream_frac_hbm_peak": b_stream / (pst["t_stream_ms"] * 1e-3) / 8.0e12
+                    if pst["t_stream_ms"] > 0 else None}
+        log(f"per-seed {ps_ms:.1f} ms/step; stream {pst['t_stream_ms']:.1f} ms")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample")
@@ -166,6 +193,7 @@ def main():
         "fp64_finalized_seeds": int(st["fp64_finalized"]),
         "ef_checksum": float(np.sum(ef_h)),
         "roofline": roofline,
+        "per_seed": per_seed,
         "cpu_baseline": cpu,
     }
     g.close()

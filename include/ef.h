@@ -157,6 +157,57 @@ ef_status ef_compute(ef_graph *g, ef_algo algo, ef_prec prec, const int32_t *see
                      int32_t n_seeds, double *ef, int64_t *D, int64_t *N, uint32_t flags,
                      void *hip_stream);
 
+/* The k nodes of largest EF ("key nodes", the paper's title and Sec. 1):
+ * computes EF of all nodes with `algo` / `prec`, then writes nodes[0..k) and
+ * (nullable) ef[0..k) in EF-descending order, ties by node id ascending.
+ * 0 <= k <= n, else EF_ERR_ARG. Flags: EF_OUT_DEVICE (nodes / ef are device
+ * pointers, asynchronous on hip_stream), EF_PROFILE. */
+ef_status ef_topk(ef_graph *g, ef_algo algo, ef_prec prec, int32_t k, int32_t *nodes,
+                  double *ef, uint32_t flags, void *hip_stream);
+
+/* ---------------------------------------------------------------------------
+ * Batches: many graphs computed together. The caller concatenates the graphs
+ * into one disjoint union: graph i owns nodes node_off[i] .. node_off[i+1]-1,
+ * row_ptr / col_idx are the union's CSR (global ids, host memory, copied).
+ * EF of a node of the union equals its EF in its own graph, since a cluster
+ * never spans two components (Sec. 3.3). One call computes every graph: each
+ * phase of the exact path runs once over the whole batch, the launch sequence
+ * is captured into a HIP graph on the first call and replayed afterwards, and
+ * the small-degree bin thresholds are tuned on the batch on first use.
+ * Outputs are per node of the union, in union order (cluster-centric).
+ * ------------------------------------------------------------------------- */
+typedef struct ef_batch ef_batch;
+
+typedef struct {
+  int32_t n_graphs;
+  int32_t n;              /* nodes of the union */
+  int64_t nnz;            /* arcs of the union */
+  int64_t clusters;       /* W of the union */
+  double replay_ms;       /* last graph replay (set when called with EF_PROFILE) */
+  float tune_ms[8];       /* eager pass time of each threshold candidate */
+  int32_t tuned_choice;   /* index of the chosen candidate */
+  int32_t thr8, thr16, thr32; /* chosen small-bin thresholds */
+} ef_batch_stats;
+
+/* EF_VALIDATE also checks that no arc leaves its graph (EF_ERR_RANGE). */
+ef_status ef_batch_create(int32_t n_graphs, const int32_t *node_off, int64_t nnz,
+                          const int32_t *row_ptr, const int32_t *col_idx, uint32_t flags,
+                          void *hip_stream, ef_batch **out);
+
+/* Time each candidate set of small-bin thresholds on this batch (eager
+ * passes) and keep the fastest; drops any captured graph. */
+ef_status ef_batch_autotune(ef_batch *b, ef_prec prec);
+
+/* EF, D, N (D, N nullable) of every node of the union. Host outputs: returns
+ * after the copy. EF_OUT_DEVICE: asynchronous on hip_stream. EF_PROFILE:
+ * records the replay time (ef_batch_stats_get). */
+ef_status ef_batch_compute(ef_batch *b, ef_prec prec, double *ef, int64_t *D, int64_t *N,
+                           uint32_t flags, void *hip_stream);
+
+ef_status ef_batch_stats_get(const ef_batch *b, ef_batch_stats *out);
+
+ef_status ef_batch_free(ef_batch *b);
+
 /* Counters and (with EF_PROFILE) phase times of the last ef_compute on g. */
 ef_status ef_stats(const ef_graph *g, ef_run_stats *out);
 

@@ -13,9 +13,6 @@
 
 #include "ef_internal.h"
 
-struct ef_graph {
-  efi::Graph g;
-};
 
 namespace efi {
 
@@ -218,7 +215,7 @@ ef_status ef_graph_free(ef_graph *h) {
     (void)hipFree(g.col_idx);
   }
   void *arrays[] = {g.deg, g.src, g.rev, g.adj2, g.asum, g.up_ptr, g.up_col, g.tslot,
-                    g.tri_small, g.tri_large, g.tri_long, g.d_counters};
+                    g.tri_list[0], g.tri_list[1], g.tri_list[2], g.tri_list[3], g.d_counters};
   for (void *p : arrays)
     if (p) (void)hipFree(p);
   for (auto &b : g.ws)
@@ -359,7 +356,7 @@ ef_status ef_graph_load_csr(int32_t n, int64_t nnz, const int32_t *row_ptr,
   inf.nnz = nnz;
   inf.max_degree = kmax;
   inf.up_arcs = nnz / 2;
-  std::vector<int32_t> ts, tl, tg;
+  std::vector<int32_t> tri[4];
   for (int32_t v = 0; v < n; ++v) {
     const int64_t k = g.h_deg[v];
     const int32_t up = h_up_ptr[v + 1] - h_up_ptr[v];
@@ -369,6 +366,7 @@ ef_status ef_graph_load_csr(int32_t n, int64_t nnz, const int32_t *row_ptr,
     inf.wedge_checks += (int64_t)up * (k - up);
     if (k >= 2 && k <= kSmallMax) {
       g.all_small++;
+      g.all_small_deg[k]++;
       g.all_pairs_small += k * (k - 1) / 2;
     } else if (k > kSmallMax && k <= kSuper) {
       g.all_mid++;
@@ -378,31 +376,28 @@ ef_status ef_graph_load_csr(int32_t n, int64_t nnz, const int32_t *row_ptr,
       g.all_big++;
       g.all_tiles += ns * (ns + 1) / 2;
       g.all_pairs_big += k * (k - 1) / 2;
+      g.all_sblocks += ns;
     }
-    if (up >= 2 && up <= kTriHashMax) ts.push_back(v);
-    else if (up > kTriHashMax && up <= 4096) tl.push_back(v);
-    else if (up > 4096) tg.push_back(v);
+    if (up >= 2) {
+      const int bin = up <= kTriBin0 ? 0 : up <= kTriBin1 ? 1 : up <= kTriBin2 ? 2 : 3;
+      tri[bin].push_back(v);
+    }
   }
   // longest lists first
   auto by_up = [&](int32_t a, int32_t b) {
     return g.h_up_len[a] != g.h_up_len[b] ? g.h_up_len[a] > g.h_up_len[b] : a < b;
   };
-  std::sort(ts.begin(), ts.end(), by_up);
-  std::sort(tl.begin(), tl.end(), by_up);
-  std::sort(tg.begin(), tg.end(), by_up);
-  g.n_tri_small = (int64_t)ts.size();
-  g.n_tri_large = (int64_t)tl.size();
-  g.n_tri_long = (int64_t)tg.size();
-  ALLOC(g.tri_small, sizeof(int32_t) * std::max<size_t>(ts.size(), 1), "triangle list");
-  ALLOC(g.tri_large, sizeof(int32_t) * std::max<size_t>(tl.size(), 1), "triangle list");
-  ALLOC(g.tri_long, sizeof(int32_t) * std::max<size_t>(tg.size(), 1), "triangle list");
+  for (int bin = 0; bin < 4; ++bin) {
+    std::sort(tri[bin].begin(), tri[bin].end(), by_up);
+    g.n_tri[bin] = (int64_t)tri[bin].size();
+    ALLOC(g.tri_list[bin], sizeof(int32_t) * std::max<size_t>(tri[bin].size(), 1), "triangle list");
+  }
 #undef ALLOC
   hipError_t e = hipSuccess;
-  if (!ts.empty()) e = hipMemcpy(g.tri_small, ts.data(), sizeof(int32_t) * ts.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess && !tl.empty())
-    e = hipMemcpy(g.tri_large, tl.data(), sizeof(int32_t) * tl.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess && !tg.empty())
-    e = hipMemcpy(g.tri_long, tg.data(), sizeof(int32_t) * tg.size(), hipMemcpyHostToDevice);
+  for (int bin = 0; bin < 4 && e == hipSuccess; ++bin)
+    if (!tri[bin].empty())
+      e = hipMemcpy(g.tri_list[bin], tri[bin].data(), sizeof(int32_t) * tri[bin].size(),
+                    hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     ef_graph_free(h);
     return hip_status(e, "upload triangle lists");
@@ -478,17 +473,20 @@ namespace efi {
 // workspace slots
 enum {
   WS_R = 0, WS_REC, WS_Y, WS_YT, WS_Z, WS_ZT, WS_YACC, WS_FLAG, WS_BINS, WS_OUT, WS_BITMAP,
-  WS_SEEDS, WS_UOUT
+  WS_SEEDS, WS_UOUT, WS_TOPK
 };
 
 static void host_bins(const Graph &g, const int32_t *centres, int64_t count, Bins &b) {
   b.n_small = b.n_mid = b.n_big = b.n_tiles = 0;
   b.pairs_small = b.pairs_mid = b.pairs_big = 0;
+  b.n_sblocks = 0;
+  for (auto &c : b.n_smallb) c = 0;
   for (int64_t i = 0; i < count; ++i) {
     const int64_t k = g.h_deg[centres ? centres[i] : i];
     if (k < 2) continue;
     if (k <= kSmallMax) {
       b.n_small++;
+      b.n_smallb[small_bin((int32_t)k, b.thr)]++;
       b.pairs_small += k * (k - 1) / 2;
     } else if (k <= kSuper) {
       b.n_mid++;
@@ -498,14 +496,16 @@ static void host_bins(const Graph &g, const int32_t *centres, int64_t count, Bin
       b.n_big++;
       b.n_tiles += ns * (ns + 1) / 2;
       b.pairs_big += k * (k - 1) / 2;
+      b.n_sblocks += ns;
     }
   }
 }
 
 static ef_status alloc_bins(Graph &g, Bins &b) {
-  const size_t bytes = sizeof(int32_t) * (size_t)(b.n_small + b.n_mid + 8) +
+  const size_t bytes = sizeof(int32_t) * (size_t)(b.n_small + b.n_mid + 8) + 4 * 256 +
                        sizeof(BigCentre) * (size_t)(b.n_big + 1) +
-                       sizeof(TileItem) * (size_t)(b.n_tiles + 1) + 1024;
+                       sizeof(TileItem) * (size_t)(b.n_tiles + 1) +
+                       sizeof(int2) * (size_t)(b.n_sblocks + 1) + 2048;
   ef_status s = ws_ensure(g, WS_BINS, bytes, "work lists");
   if (s != EF_OK) return s;
   char *p = (char *)g.ws[WS_BINS].p;
@@ -515,10 +515,12 @@ static ef_status alloc_bins(Graph &g, Bins &b) {
     return r;
   };
   b.counters = (int32_t *)take(sizeof(int32_t) * 8);
-  b.small = (int32_t *)take(sizeof(int32_t) * (size_t)(b.n_small + 1));
+  for (int i = 0; i < 4; ++i)
+    b.small[i] = (int32_t *)take(sizeof(int32_t) * (size_t)(b.n_smallb[i] + 1));
   b.mid = (int32_t *)take(sizeof(int32_t) * (size_t)(b.n_mid + 1));
   b.big = (BigCentre *)take(sizeof(BigCentre) * (size_t)(b.n_big + 1));
   b.tiles = (TileItem *)take(sizeof(TileItem) * (size_t)(b.n_tiles + 1));
+  b.sblocks = (int2 *)take(sizeof(int2) * (size_t)(b.n_sblocks + 1));
   return EF_OK;
 }
 
@@ -567,7 +569,7 @@ extern "C" ef_status ef_compute(ef_graph *h, ef_algo algo, ef_prec prec, const i
     set_error("ef_compute: bad algorithm or precision");
     return EF_ERR_ARG;
   }
-  if (flags & ~(EF_OUT_DEVICE | EF_PROFILE)) {
+  if (flags & ~(EF_OUT_DEVICE | EF_PROFILE | kInternalNoReadback)) {
     set_error("ef_compute: unknown flags 0x%x", flags);
     return EF_ERR_ARG;
   }
@@ -612,14 +614,18 @@ extern "C" ef_status ef_compute(ef_graph *h, ef_algo algo, ef_prec prec, const i
   // work lists of the pair loop
   Bins b;
   if (all) {
+    b.thr = g.thr;
     b.n_small = g.all_small;
+    for (int k = 2; k <= kSmallMax; ++k) b.n_smallb[small_bin(k, b.thr)] += g.all_small_deg[k];
     b.n_mid = g.all_mid;
     b.n_big = g.all_big;
     b.n_tiles = g.all_tiles;
     b.pairs_small = g.all_pairs_small;
     b.pairs_mid = g.all_pairs_mid;
     b.pairs_big = g.all_pairs_big;
+    b.n_sblocks = g.all_sblocks;
   } else {
+    b.thr = g.thr;
     host_bins(g, useeds.data(), (int64_t)useeds.size(), b);
   }
   if ((s = alloc_bins(g, b)) != EF_OK) return s;
@@ -648,7 +654,7 @@ extern "C" ef_status ef_compute(ef_graph *h, ef_algo algo, ef_prec prec, const i
     }
   }
   int32_t *cnt = g.d_counters;  // [0] flagged, [1] fp64-finalised
-  hipError_t e = hipMemsetAsync(cnt, 0, sizeof(int32_t) * 4, st);
+  hipError_t e = launch_zero_i32(cnt, 4, st);
   if (e != hipSuccess) return hip_status(e, "clear counters");
   int32_t *flagged = (int32_t *)g.ws[WS_FLAG].p;
 
@@ -708,22 +714,17 @@ extern "C" ef_status ef_compute(ef_graph *h, ef_algo algo, ef_prec prec, const i
   if (e != hipSuccess) return hip_status(e, "pair loop");
   prof.mark(5);
   if (!per_seed) {
-    if ((s = ws_ensure(g, WS_Y, tsz * (size_t)nup, "triangle slots")) != EF_OK) return s;
+    if ((s = ws_ensure(g, WS_Y, sizeof(long long) * (size_t)nup, "triangle slots")) != EF_OK) return s;
     if ((s = ws_ensure(g, WS_YT, sizeof(int32_t) * (size_t)nup, "triangle counts")) != EF_OK) return s;
     if ((s = ws_ensure(g, WS_Z, tsz * (size_t)std::max(g.n, 1), "triangle node sums")) != EF_OK) return s;
     if ((s = ws_ensure(g, WS_ZT, sizeof(int64_t) * (size_t)std::max(g.n, 1), "triangle node counts")) != EF_OK)
       return s;
-    void *yacc = nullptr;
-    if (g.n_tri_long > 0) {
-      if ((s = ws_ensure(g, WS_YACC, tsz * (size_t)nup, "triangle scratch")) != EF_OK) return s;
-      yacc = g.ws[WS_YACC].p;
-    }
-    e = launch_triangles_ex(g, prec, g.tri_small, g.n_tri_small, g.tri_large, g.n_tri_large,
-                            g.tri_long, g.n_tri_long, g.ws[WS_Y].p, (int32_t *)g.ws[WS_YT].p,
-                            g.ws[WS_Z].p, (int64_t *)g.ws[WS_ZT].p, yacc, st);
+    e = launch_triangles(g, prec, (long long *)g.ws[WS_Y].p, (int32_t *)g.ws[WS_YT].p,
+                         g.ws[WS_Z].p, (int64_t *)g.ws[WS_ZT].p, st);
     if (e != hipSuccess) return hip_status(e, "triangle pass");
     prof.mark(6);
-    e = launch_finalize_cluster(g, prec, g.ws[WS_R].p, g.ws[WS_Y].p, (int32_t *)g.ws[WS_YT].p,
+    e = launch_finalize_cluster(g, prec, g.ws[WS_R].p, (const long long *)g.ws[WS_Y].p,
+                                (int32_t *)g.ws[WS_YT].p,
                                 g.ws[WS_Z].p, (int64_t *)g.ws[WS_ZT].p, ef_w, D_w, N_w, flagged,
                                 cnt, cnt + 1, st);
     if (e != hipSuccess) return hip_status(e, "finalize");
@@ -776,7 +777,7 @@ extern "C" ef_status ef_compute(ef_graph *h, ef_algo algo, ef_prec prec, const i
   g.stats.pairs_mid = b.pairs_mid;
   g.stats.pairs_big = b.pairs_big;
   g.stats.seeds = n_work;
-  if (prof.on || !out_dev) {
+  if ((prof.on || !out_dev) && !(flags & kInternalNoReadback)) {
     int32_t hc[2] = {0, 0};
     e = hipMemcpyAsync(hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -799,6 +800,57 @@ extern "C" ef_status ef_compute(ef_graph *h, ef_algo algo, ef_prec prec, const i
     }
     g.stats.t_pass2_ms = prof.ms(7, 8);
     g.stats.t_total_ms = prof.ms(0, 8);
+  }
+  return EF_OK;
+}
+
+extern "C" ef_status ef_topk(ef_graph *h, ef_algo algo, ef_prec prec, int32_t k, int32_t *nodes,
+                             double *ef, uint32_t flags, void *hip_stream) {
+  if (!h || !nodes) {
+    set_error("ef_topk: null handle or output");
+    return EF_ERR_ARG;
+  }
+  Graph &g = h->g;
+  if (k < 0 || k > g.n) {
+    set_error("ef_topk: k=%d outside [0, n=%d]", k, g.n);
+    return EF_ERR_ARG;
+  }
+  if (flags & ~(EF_OUT_DEVICE | EF_PROFILE)) {
+    set_error("ef_topk: unknown flags 0x%x", flags);
+    return EF_ERR_ARG;
+  }
+  if (k == 0) return EF_OK;
+  hipStream_t st = (hipStream_t)hip_stream;
+  const size_t n = (size_t)g.n;
+  ef_status s = ws_ensure(g, WS_OUT, sizeof(double) * n + 2 * sizeof(int64_t) * n + 2048,
+                          "all-node outputs");
+  if (s != EF_OK) return s;
+  double *ef_all = (double *)g.ws[WS_OUT].p;
+  int64_t *D_all = (int64_t *)(ef_all + n);
+  int64_t *N_all = D_all + n;
+  s = ef_compute(h, algo, prec, nullptr, 0, ef_all, D_all, N_all,
+                 EF_OUT_DEVICE | (flags & EF_PROFILE), hip_stream);
+  if (s != EF_OK) return s;
+  const size_t scratch = topk_scratch_bytes(g.n) + sizeof(int32_t) * (size_t)k +
+                         sizeof(double) * (size_t)k + 1024;
+  if ((s = ws_ensure(g, WS_TOPK, scratch, "top-k scratch")) != EF_OK) return s;
+  const bool out_dev = (flags & EF_OUT_DEVICE) != 0;
+  int32_t *nodes_d = nodes;
+  double *ef_d = ef;
+  char *base = (char *)g.ws[WS_TOPK].p;
+  const size_t sort_bytes = topk_scratch_bytes(g.n);
+  if (!out_dev) {
+    nodes_d = (int32_t *)(base + sort_bytes);
+    ef_d = (double *)(base + sort_bytes + ((sizeof(int32_t) * (size_t)k + 255) & ~(size_t)255));
+  }
+  hipError_t e = launch_topk(ef_all, g.n, k, base, sort_bytes, nodes_d, ef ? ef_d : nullptr, st);
+  if (e != hipSuccess) return hip_status(e, "top-k");
+  if (!out_dev) {
+    e = hipMemcpyAsync(nodes, nodes_d, sizeof(int32_t) * (size_t)k, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && ef)
+      e = hipMemcpyAsync(ef, ef_d, sizeof(double) * (size_t)k, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_status(e, "copy top-k");
   }
   return EF_OK;
 }

@@ -28,10 +28,11 @@ constexpr int kSuper = 1024;          // neighbours per super-block
 constexpr int kBlocksPerSuper = 16;   // 64-wide blocks per super-block
 constexpr int kRecEntries = 2 * kSuper;  // row part + column part per super-tile record
 
-// Triangle pass: nodes whose degree-oriented out-list up(u) has at most
-// kTriHashMax entries use an LDS hash; longer lists search global memory.
-constexpr int kTriHashMax = 512;
-constexpr int kTriHashSlots = 1024;
+// Triangle pass: nodes are binned by the length of their degree-oriented
+// out-list up(u): 2..64, 65..512, 513..2048 use an LDS hash of up(u) sized
+// for the bin; longer lists search global memory.
+constexpr int kTriBin0 = 64, kTriBin1 = 512, kTriBin2 = 2048;
+constexpr int kTriLongMin = kTriBin2 + 1;
 
 // Per-seed stream: seeds with k <= kSeedHashMax use an LDS hash of N(s);
 // larger seeds a bitmap over all node ids in device memory.
@@ -41,6 +42,16 @@ constexpr int kSeedHashSlots = 4096;
 // FP32C: seeds whose estimated cancellation factor (S/D)/EF exceeds this are
 // recomputed from non-negative terms.
 constexpr float kKappaMax = 16.0f;
+
+// Segment-size thresholds of the small bin: a centre of degree k <= 64 is
+// scored on segments of 8, 16, 32 or 64 lanes: the first S with k <= t[S]
+// (t8 <= 8, t16 <= 16, t32 <= 32; 0 disables a segment size).
+struct SmallThr {
+  int32_t t8 = 8, t16 = 16, t32 = 32;
+};
+__host__ __device__ inline int small_bin(int32_t k, SmallThr t) {
+  return k <= t.t8 ? 0 : k <= t.t16 ? 1 : k <= t.t32 ? 2 : 3;
+}
 
 struct BigCentre {
   int32_t v;         // node id
@@ -78,12 +89,15 @@ struct Graph {
   // host copies used for sizing work lists
   std::vector<int32_t> h_deg;
   std::vector<int32_t> h_up_len;
-  // triangle-pass node lists (device) by |up(u)|
-  int32_t *tri_small = nullptr, *tri_large = nullptr, *tri_long = nullptr;
-  int64_t n_tri_small = 0, n_tri_large = 0, n_tri_long = 0;
+  // triangle-pass node lists (device) by |up(u)|: 2..64, 65..512, 513..4096, >4096
+  int32_t *tri_list[4] = {nullptr, nullptr, nullptr, nullptr};
+  int64_t n_tri[4] = {0, 0, 0, 0};
   // bin counts for the all-nodes centre set
   int64_t all_small = 0, all_mid = 0, all_big = 0, all_tiles = 0;
+  int64_t all_small_deg[kSmallMax + 1] = {};  // centres of each degree <= 64
+  SmallThr thr;                               // current small-bin thresholds
   int64_t all_pairs_small = 0, all_pairs_mid = 0, all_pairs_big = 0;
+  int64_t all_sblocks = 0;  // sum of super-blocks over big centres
   int64_t owned_bytes = 0;  // device bytes held by this handle
   int32_t *d_counters = nullptr;  // persistent small counters (flag counts etc.)
   ef_graph_info info{};
@@ -94,6 +108,10 @@ struct Graph {
   hipEvent_t ev[16] = {};
   bool ev_ready = false;
 };
+
+// ef_compute flag reserved for the library: launch only, no host read-back
+// (the call is being captured into a HIP graph)
+constexpr uint32_t kInternalNoReadback = 0x80000000u;
 
 // error text (thread-local)
 void set_error(const char *fmt, ...);
@@ -110,15 +128,22 @@ hipError_t launch_exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t co
                                      int32_t *block_tmp, int64_t block_tmp_len, hipStream_t st);
 int64_t scan_tmp_len(int64_t count);
 
+// zero a small int32 array with a kernel (usable under stream capture)
+hipError_t launch_zero_i32(int32_t *p, int32_t count, hipStream_t st);
+
 // work lists
 struct Bins {
-  int32_t *small = nullptr;      // centre ids
+  SmallThr thr;
+  int32_t *small[4] = {nullptr, nullptr, nullptr, nullptr};  // centre ids per segment size
+  int64_t n_smallb[4] = {0, 0, 0, 0};
   int32_t *mid = nullptr;
   BigCentre *big = nullptr;
   TileItem *tiles = nullptr;
-  int32_t *counters = nullptr;   // [0] small, [1] mid, [2] big, [3] tiles (device)
+  int2 *sblocks = nullptr;       // (big-centre index, super-block) reduction items
+  int32_t *counters = nullptr;   // [0..3] small, [4] mid, [5] big, [6] tiles, [7] sblocks
   int64_t n_small = 0, n_mid = 0, n_big = 0, n_tiles = 0;  // host-known counts
   int64_t pairs_small = 0, pairs_mid = 0, pairs_big = 0;     // clusters per bin
+  int64_t n_sblocks = 0;
 };
 hipError_t launch_bin_centres(const Graph &g, const int32_t *centres, int32_t n_centres,
                               Bins &b, hipStream_t st);
@@ -132,17 +157,15 @@ hipError_t launch_pairs(const Graph &g, ef_prec prec, const Bins &b, void *R, vo
                         hipStream_t st, hipEvent_t ev_small, hipEvent_t ev_mid,
                         hipEvent_t ev_big);
 
-// triangle pass (cluster-centric): Y/YT per up-arc slot, Z/ZT per node.
-// Node lists by |up(u)|: small (2..512), large (513..4096), long (> 4096).
-hipError_t launch_triangles_ex(const Graph &g, ef_prec prec, const int32_t *small,
-                               int64_t n_small, const int32_t *large, int64_t n_large,
-                               const int32_t *lng, int64_t n_long, void *Y, int32_t *YT,
-                               void *Z, int64_t *ZT, void *Yacc_tmp, hipStream_t st);
+// triangle pass (cluster-centric): Y (64-bit fixed point, 2^-40 units) and
+// YT per up-arc slot, Z / ZT per node.
+hipError_t launch_triangles(const Graph &g, ef_prec prec, long long *Y, int32_t *YT, void *Z,
+                            int64_t *ZT, hipStream_t st);
 
 // per-node sums + Eq. 1 (cluster-centric). Appends cancellation-prone seeds to
 // `flagged` (count in *flag_count).
-hipError_t launch_finalize_cluster(const Graph &g, ef_prec prec, const void *R, const void *Y,
-                                   const int32_t *YT, const void *Z, const int64_t *ZT,
+hipError_t launch_finalize_cluster(const Graph &g, ef_prec prec, const void *R,
+                                   const long long *Y, const int32_t *YT, const void *Z, const int64_t *ZT,
                                    double *ef, int64_t *D, int64_t *N, int32_t *flagged,
                                    int32_t *flag_count, int32_t *fp64_count, hipStream_t st);
 
@@ -162,9 +185,18 @@ hipError_t launch_pass2(const Graph &g, const int32_t *seeds, const int32_t *fla
                         const int32_t *flag_count, int32_t max_flagged, double *ef,
                         const int64_t *D, hipStream_t st);
 
+// top-k by EF (descending, ties by id ascending) over ef[0..n)
+size_t topk_scratch_bytes(int32_t n);
+hipError_t launch_topk(const double *ef, int32_t n, int32_t k, void *scratch,
+                       size_t scratch_bytes, int32_t *nodes, double *ef_out, hipStream_t st);
+
 // scatter outputs of unique seeds back to the caller's positions
 hipError_t launch_gather_outputs(const int32_t *inv, int32_t count, const double *ef_u,
                                  const int64_t *D_u, const int64_t *N_u, double *ef,
                                  int64_t *D, int64_t *N, hipStream_t st);
 
 }  // namespace efi
+
+struct ef_graph {
+  efi::Graph g;
+};

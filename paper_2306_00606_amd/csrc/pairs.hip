@@ -129,34 +129,71 @@ __device__ __forceinline__ void tile(T cp, T kq, T &Rt, T &C) {
 }
 
 // ---------------------------------------------------------------------------
-// small centres: one wavefront per centre (k <= 64)
+// small centres: segments of S lanes (S = 8, 16, 32, 64), one centre of
+// degree k <= S per segment, 64/S centres per wavefront. The diagonal tile of
+// a segment takes S/2 rotation steps (the last on half of the lanes), so each
+// unordered neighbour pair is scored once.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <int S>
+__device__ __forceinline__ int rot_seg_i(int x) {
+  if constexpr (S == 64) {
+    return __builtin_amdgcn_update_dpp(0, x, 0x134, 0xf, 0xf, false);  // wave_rol:1
+  } else if constexpr (S == 16) {
+    return __builtin_amdgcn_update_dpp(0, x, 0x12F, 0xf, 0xf, false);  // row_ror:15
+  } else {
+    const int lane = threadIdx.x & 63;
+    const int src = (lane & ~(S - 1)) | ((lane + 1) & (S - 1));
+    return __builtin_amdgcn_ds_bpermute(src << 2, x);
+  }
+}
+template <int S> __device__ __forceinline__ float rot_seg(float x) {
+  return __int_as_float(rot_seg_i<S>(__float_as_int(x)));
+}
+template <int S> __device__ __forceinline__ double rot_seg(double x) {
+  long long b = __double_as_longlong(x);
+  int lo = rot_seg_i<S>((int)(b & 0xffffffffLL));
+  int hi = rot_seg_i<S>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <typename T, int S>
 __global__ __launch_bounds__(256) void k_pairs_small(const int32_t *__restrict__ row_ptr,
                                                      const int32_t *__restrict__ deg,
                                                      const int2 *__restrict__ adj2,
                                                      const int32_t *__restrict__ list,
                                                      int64_t count, void *__restrict__ R) {
+  constexpr int PER = 64 / S;
   const int lane = threadIdx.x & 63;
+  const int seg = lane / S, j = lane & (S - 1);
   const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  for (int64_t it = wave; it < count; it += nwaves) {
-    const int32_t v = list[it];
-    const int32_t k = deg[v];
-    const int32_t base = row_ptr[v];
-    const bool valid = lane < k;
-    const T kp = valid ? (T)adj2[base + lane].y : T(0);
+  const int64_t groups = (count + PER - 1) / PER;
+  for (int64_t gi = wave; gi < groups; gi += nwaves) {
+    const int64_t it = gi * PER + seg;
+    const bool have = it < count;
+    const int32_t v = have ? list[it] : 0;
+    const int32_t k = have ? deg[v] : 0;
+    const int32_t base = have ? row_ptr[v] : 0;
+    const bool valid = j < k;
+    const T kp = valid ? (T)adj2[base + j].y : T(0);
     const T cp = valid ? (T)(k - 4) + kp : (T)kNegF;
-    const T kq = valid ? kp : (T)kNegF;
-    T Rt, C;
-    tile<T, true, true>(cp, kq, Rt, C);
-    // column (lane+32)&63 is in C of lane; bring column `lane` home
-    T Cl = __shfl_xor(C, 32, 64);
+    T kq = valid ? kp : (T)kNegF;
+    T Rt = T(0), C = T(0);
+#pragma unroll 4
+    for (int s = 1; s <= S / 2; ++s) {
+      kq = rot_seg<S>(kq);
+      T g = score_masked(cp + kq);
+      if (s == S / 2) g = j < S / 2 ? g : T(0);
+      Rt += g;
+      C = rot_seg<S>(C) + g;
+    }
+    // column (j + S/2) mod S is in C of this lane; bring column j home
+    const T Cl = __shfl_xor(C, S / 2, 64);
     if (valid) {
       Acc<T> a;
       a.add(Rt);
       a.add(Cl);
-      a.store(R, base + lane);
+      a.store(R, base + j);
     }
   }
 }
@@ -306,17 +343,22 @@ __global__ __launch_bounds__(1024) void k_pairs_big(const int32_t *__restrict__ 
 
 // Per-arc sum of the super-tile records of big centres, fixed order:
 // R[p] = sum_{Q >= b} row part of (b, Q)  +  sum_{P < b} column part of (P, b)
+// One workgroup per (big centre, super-block b): the 1024 arcs of block b.
 template <typename T>
 __global__ __launch_bounds__(256) void k_arc_reduce(const int32_t *__restrict__ row_ptr,
                                                     const int32_t *__restrict__ deg,
                                                     const BigCentre *__restrict__ big,
-                                                    int64_t nbig, const void *__restrict__ rec,
+                                                    const int2 *__restrict__ items,
+                                                    int64_t nitems, const void *__restrict__ rec,
                                                     void *__restrict__ R) {
-  for (int64_t bi = blockIdx.x; bi < nbig; bi += gridDim.x) {
-    const BigCentre bc = big[bi];
+  for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int2 item = items[it];
+    const BigCentre bc = big[item.x];
+    const int b = item.y;
     const int32_t k = deg[bc.v], base = row_ptr[bc.v], ns = bc.ns;
-    for (int32_t p = threadIdx.x; p < k; p += blockDim.x) {
-      const int b = p >> 10, j = p & (kSuper - 1);
+    for (int j = threadIdx.x; j < kSuper; j += blockDim.x) {
+      const int32_t p = kSuper * b + j;
+      if (p >= k) break;
       Acc<T> a;
       for (int Q = b; Q < ns; ++Q) {
         const int64_t t = bc.rec_base + (int64_t)b * ns - (int64_t)b * (b - 1) / 2 + (Q - b);
@@ -332,38 +374,71 @@ __global__ __launch_bounds__(256) void k_arc_reduce(const int32_t *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// binning: classify centres by degree and build the work lists
-// counters: [0] small, [1] mid, [2] big, [3] super-tile records
+// binning: classify centres by degree and build the work lists.
+// counters: [0..3] small lists (segments of 8, 16, 32, 64 lanes), [4] mid,
+// [5] big, [6] super-tile records, [7] super-block reduction items.
+// A small centre of degree k goes to the first segment size S with
+// k <= thr[S] (thr[64] = 64), so the thresholds pick the segment size.
 // ---------------------------------------------------------------------------
+// append to a global list with one atomic per wavefront (ballot + rank)
+__device__ __forceinline__ int32_t wave_append(int32_t *counter, bool pred) {
+  const unsigned long long mask = __ballot(pred);
+  if (!mask) return -1;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((long long)mask) - 1;
+  int32_t base = 0;
+  if (lane == leader) base = atomicAdd(counter, __popcll(mask));
+  base = __shfl(base, leader, 64);
+  const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  return pred ? base + __popcll(mask & below) : -1;
+}
+
 __global__ void k_bin(const int32_t *__restrict__ deg, const int32_t *__restrict__ centres,
-                      int32_t n_centres, int32_t *__restrict__ small, int32_t *__restrict__ mid,
+                      int32_t n_centres, SmallThr thr, int32_t *__restrict__ small0,
+                      int32_t *__restrict__ small1, int32_t *__restrict__ small2,
+                      int32_t *__restrict__ small3, int32_t *__restrict__ mid,
                       BigCentre *__restrict__ big, int32_t *__restrict__ counters) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_centres;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t v = centres ? centres[i] : (int32_t)i;
-    const int32_t k = deg[v];
-    if (k < 2) continue;
-    if (k <= kSmallMax) {
-      small[atomicAdd(&counters[0], 1)] = v;
-    } else if (k <= kSuper) {
-      mid[atomicAdd(&counters[1], 1)] = v;
-    } else {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  // every lane of a wavefront runs the same number of iterations (ballots)
+  const int64_t rounds = (n_centres + stride - 1) / stride;
+  for (int64_t r = 0; r < rounds; ++r) {
+    const int64_t i = r * stride + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int32_t v = 0, k = 0;
+    if (i < n_centres) {
+      v = centres ? centres[i] : (int32_t)i;
+      k = deg[v];
+    }
+    const int b = (k < 2) ? -1 : k <= kSmallMax ? small_bin(k, thr) : k <= kSuper ? 4 : 5;
+    int32_t *lists[4] = {small0, small1, small2, small3};
+    for (int q = 0; q < 5; ++q) {
+      const int32_t pos = wave_append(&counters[q], b == q);
+      if (pos >= 0) {
+        if (q < 4) lists[q][pos] = v;
+        else mid[pos] = v;
+      }
+    }
+    if (b == 5) {
       const int32_t ns = (k + kSuper - 1) / kSuper;
       const int32_t nt = ns * (ns + 1) / 2;
-      const int32_t slot = atomicAdd(&counters[2], 1);
-      const int32_t rb = atomicAdd(&counters[3], nt);
+      const int32_t slot = atomicAdd(&counters[5], 1);
+      const int32_t rb = atomicAdd(&counters[6], nt);
       big[slot] = BigCentre{v, ns, (int64_t)rb};
     }
   }
 }
 
 // one workgroup per big centre: its super-tile items (in record order)
-__global__ void k_expand_tiles(const BigCentre *__restrict__ big, const int32_t *__restrict__ counters,
-                               TileItem *__restrict__ tiles) {
-  const int32_t nbig = counters[2];
+__global__ void k_expand_tiles(const BigCentre *__restrict__ big, int32_t *__restrict__ counters,
+                               TileItem *__restrict__ tiles, int2 *__restrict__ sblocks) {
+  const int32_t nbig = counters[5];
   for (int32_t bi = blockIdx.x; bi < nbig; bi += gridDim.x) {
     const BigCentre bc = big[bi];
     const int32_t nt = bc.ns * (bc.ns + 1) / 2;
+    __shared__ int32_t sb0;
+    if (threadIdx.x == 0) sb0 = atomicAdd(&counters[7], bc.ns);
+    __syncthreads();
+    for (int32_t b = threadIdx.x; b < bc.ns; b += blockDim.x) sblocks[sb0 + b] = make_int2(bi, b);
+    __syncthreads();
     for (int32_t t = threadIdx.x; t < nt; t += blockDim.x) {
       // invert t = P*ns - P*(P-1)/2 + (Q-P)
       int32_t P = 0, rem = t;
@@ -373,6 +448,15 @@ __global__ void k_expand_tiles(const BigCentre *__restrict__ big, const int32_t 
   }
 }
 
+__global__ void k_zero_i32(int32_t *__restrict__ p, int32_t count) {
+  for (int32_t i = threadIdx.x; i < count; i += blockDim.x) p[i] = 0;
+}
+
+hipError_t launch_zero_i32(int32_t *p, int32_t count, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(256), 0, st, p, count);
+  return hipGetLastError();
+}
+
 static unsigned capped(int64_t blocks, int64_t cap) {
   if (blocks < 1) blocks = 1;
   return (unsigned)(blocks < cap ? blocks : cap);
@@ -380,14 +464,14 @@ static unsigned capped(int64_t blocks, int64_t cap) {
 
 hipError_t launch_bin_centres(const Graph &g, const int32_t *centres, int32_t n_centres,
                               Bins &b, hipStream_t st) {
-  hipError_t e = hipMemsetAsync(b.counters, 0, 4 * sizeof(int32_t), st);
-  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, b.counters, 8);
   if (n_centres <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_bin, dim3(capped((n_centres + 255) / 256, 65536)), dim3(256), 0, st,
-                     g.deg, centres, n_centres, b.small, b.mid, b.big, b.counters);
+                     g.deg, centres, n_centres, b.thr, b.small[0], b.small[1], b.small[2],
+                     b.small[3], b.mid, b.big, b.counters);
   if (b.n_big > 0)
     hipLaunchKernelGGL(k_expand_tiles, dim3(capped(b.n_big, 65536)), dim3(256), 0, st, b.big,
-                       b.counters, b.tiles);
+                       b.counters, b.tiles, b.sblocks);
   return hipGetLastError();
 }
 
@@ -395,9 +479,18 @@ template <typename T>
 static hipError_t pairs_impl(const Graph &g, const Bins &b, void *R, void *records,
                              hipStream_t st, hipEvent_t ev_small, hipEvent_t ev_mid,
                              hipEvent_t ev_big) {
-  if (b.n_small > 0)
-    hipLaunchKernelGGL(k_pairs_small<T>, dim3(capped((b.n_small + 3) / 4, 1 << 20)), dim3(256),
-                       0, st, g.row_ptr, g.deg, g.adj2, b.small, b.n_small, R);
+  if (b.n_smallb[0] > 0)
+    hipLaunchKernelGGL((k_pairs_small<T, 8>), dim3(capped((b.n_smallb[0] + 31) / 32, 1 << 20)),
+                       dim3(256), 0, st, g.row_ptr, g.deg, g.adj2, b.small[0], b.n_smallb[0], R);
+  if (b.n_smallb[1] > 0)
+    hipLaunchKernelGGL((k_pairs_small<T, 16>), dim3(capped((b.n_smallb[1] + 15) / 16, 1 << 20)),
+                       dim3(256), 0, st, g.row_ptr, g.deg, g.adj2, b.small[1], b.n_smallb[1], R);
+  if (b.n_smallb[2] > 0)
+    hipLaunchKernelGGL((k_pairs_small<T, 32>), dim3(capped((b.n_smallb[2] + 7) / 8, 1 << 20)),
+                       dim3(256), 0, st, g.row_ptr, g.deg, g.adj2, b.small[2], b.n_smallb[2], R);
+  if (b.n_smallb[3] > 0)
+    hipLaunchKernelGGL((k_pairs_small<T, 64>), dim3(capped((b.n_smallb[3] + 3) / 4, 1 << 20)),
+                       dim3(256), 0, st, g.row_ptr, g.deg, g.adj2, b.small[3], b.n_smallb[3], R);
   if (ev_small) (void)hipEventRecord(ev_small, st);
   if (b.n_mid > 0)
     hipLaunchKernelGGL(k_pairs_mid<T>, dim3(capped(b.n_mid, 1 << 20)), dim3(1024), 0, st,
@@ -407,9 +500,9 @@ static hipError_t pairs_impl(const Graph &g, const Bins &b, void *R, void *recor
     hipLaunchKernelGGL(k_pairs_big<T>, dim3(capped(b.n_tiles, 1 << 20)), dim3(1024), 0, st,
                        g.row_ptr, g.deg, g.adj2, b.big, b.tiles, b.n_tiles, records);
   if (ev_big) (void)hipEventRecord(ev_big, st);
-  if (b.n_big > 0)
-    hipLaunchKernelGGL(k_arc_reduce<T>, dim3(capped(b.n_big, 1 << 20)), dim3(256), 0, st,
-                       g.row_ptr, g.deg, b.big, b.n_big, records, R);
+  if (b.n_sblocks > 0)
+    hipLaunchKernelGGL(k_arc_reduce<T>, dim3(capped(b.n_sblocks, 1 << 20)), dim3(256), 0, st,
+                       g.row_ptr, g.deg, b.big, b.sblocks, b.n_sblocks, records, R);
   return hipGetLastError();
 }
 

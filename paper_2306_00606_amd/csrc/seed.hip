@@ -67,7 +67,7 @@ __global__ __launch_bounds__(256) void k_finalize_cluster(
     const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ deg,
     const int2 *__restrict__ adj2, const int32_t *__restrict__ rev,
     const int32_t *__restrict__ tslot, const int64_t *__restrict__ asum,
-    const void *__restrict__ R, const void *__restrict__ Y, const int32_t *__restrict__ YT,
+    const void *__restrict__ R, const long long *__restrict__ Y, const int32_t *__restrict__ YT,
     const void *__restrict__ Z, const int64_t *__restrict__ ZT, int32_t n,
     double *__restrict__ ef, int64_t *__restrict__ Dout, int64_t *__restrict__ Nout,
     int32_t *__restrict__ flagged, int32_t *__restrict__ flag_count,
@@ -80,7 +80,8 @@ __global__ __launch_bounds__(256) void k_finalize_cluster(
   for (int64_t v = wave; v < n; v += nwaves) {
     const int32_t k = deg[v], base = row_ptr[v];
     const int64_t As = asum[v];
-    Acc sacc = Acc(), tacc = Acc();
+    Acc sacc = Acc();
+    double tfix = 0.0;  // triangle credits, 2^-40 fixed-point units
     int64_t Nn = 0, Dd = 0, Tc = 0;
     for (int32_t e = base + lane; e < base + k; e += 64) {
       const int2 ad = adj2[e];
@@ -93,19 +94,21 @@ __global__ __launch_bounds__(256) void k_finalize_cluster(
             (asum[a] - k);
       if (rank_less_d(a, ka, (int32_t)v, k)) {
         const int32_t sl = tslot[e];
-        S::add_stored(tacc, Y, sl);
+        tfix += (double)Y[sl];
         Tc += YT[sl];
       }
     }
     sacc = wave_sum(sacc);
-    tacc = wave_sum(tacc);
+    tfix = wave_sum_f64(tfix);
     Nn = wave_sum_i64(Nn);
     Dd = wave_sum_i64(Dd);
     Tc = wave_sum_i64(Tc);
     if (lane == 0) {
-      S::add_stored(tacc, Z, v);
+      Acc z = Acc();
+      S::add_stored(z, Z, v);
       Tc += ZT[v];
-      const double Stot = S::value(sacc) + 4.0 * S::value(tacc);
+      const double tri = tfix * (1.0 / 1099511627776.0) + S::value(z);
+      const double Stot = S::value(sacc) + 4.0 * tri;
       Dd -= 8 * Tc;
       ef[v] = finish_ef<T>(Nn, Dd, Stot, (int32_t)v, flagged, flag_count, fp64_count);
       Dout[v] = Dd;
@@ -119,8 +122,8 @@ static unsigned cap_blocks(int64_t b, int64_t cap) {
   return (unsigned)(b < cap ? b : cap);
 }
 
-hipError_t launch_finalize_cluster(const Graph &g, ef_prec prec, const void *R, const void *Y,
-                                   const int32_t *YT, const void *Z, const int64_t *ZT,
+hipError_t launch_finalize_cluster(const Graph &g, ef_prec prec, const void *R,
+                                   const long long *Y, const int32_t *YT, const void *Z, const int64_t *ZT,
                                    double *ef, int64_t *D, int64_t *N, int32_t *flagged,
                                    int32_t *flag_count, int32_t *fp64_count, hipStream_t st) {
   const unsigned blocks = cap_blocks(((int64_t)g.n * 64 + 255) / 256, 1 << 20);

@@ -33,7 +33,9 @@ EF_PROFILE = 0x8
 # every entry point declared in include/ef.h
 EXPORTS = [
     "ef_last_error", "ef_version", "ef_device_count", "ef_validate_csr", "ef_graph_load_csr",
-    "ef_graph_from_edges", "ef_graph_free", "ef_graph_info_get", "ef_compute", "ef_stats",
+    "ef_graph_from_edges", "ef_graph_free", "ef_graph_info_get", "ef_compute", "ef_topk",
+    "ef_stats", "ef_batch_create", "ef_batch_autotune", "ef_batch_compute",
+    "ef_batch_stats_get", "ef_batch_free",
 ]
 
 
@@ -63,6 +65,18 @@ class RunStats(ctypes.Structure):
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class BatchStats(ctypes.Structure):
+    _fields_ = [("n_graphs", ctypes.c_int32), ("n", ctypes.c_int32), ("nnz", ctypes.c_int64),
+                ("clusters", ctypes.c_int64), ("replay_ms", ctypes.c_double),
+                ("tune_ms", ctypes.c_float * 8), ("tuned_choice", ctypes.c_int32),
+                ("thr8", ctypes.c_int32), ("thr16", ctypes.c_int32), ("thr32", ctypes.c_int32)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["tune_ms"] = list(self.tune_ms)
+        return d
 
 
 _lib = None
@@ -103,6 +117,12 @@ def lib():
     L.ef_graph_info_get.argtypes = [vp, ctypes.POINTER(GraphInfo)]
     L.ef_compute.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, i32, vp, vp, vp, u32, vp]
     L.ef_stats.argtypes = [vp, ctypes.POINTER(RunStats)]
+    L.ef_topk.argtypes = [vp, ctypes.c_int, ctypes.c_int, i32, vp, vp, u32, vp]
+    L.ef_batch_create.argtypes = [i32, vp, i64, vp, vp, u32, vp, ctypes.POINTER(vp)]
+    L.ef_batch_autotune.argtypes = [vp, ctypes.c_int]
+    L.ef_batch_compute.argtypes = [vp, ctypes.c_int, vp, vp, vp, u32, vp]
+    L.ef_batch_stats_get.argtypes = [vp, ctypes.POINTER(BatchStats)]
+    L.ef_batch_free.argtypes = [vp]
     for name in EXPORTS[2:]:
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -226,9 +246,104 @@ class Graph:
                                 _stream_ptr(stream)))
         return ef, D, N
 
+    def topk(self, k: int, algo: str = "cluster", prec: str = "fp32c", out=None,
+             profile: bool = False, stream=None):
+        """The k nodes of largest EF (descending; ties by id ascending).
+        Host mode returns numpy (nodes int32, ef float64); device mode writes
+        `out` = (nodes, ef) torch CUDA tensors asynchronously."""
+        flags = EF_PROFILE if profile else 0
+        if out is None:
+            nodes = np.zeros(max(k, 1), np.int32)
+            ef = np.zeros(max(k, 1), np.float64)
+            _check(lib().ef_topk(self._h, ALGO[algo], PREC[prec], int(k), nodes.ctypes.data,
+                                 ef.ctypes.data, flags, _stream_ptr(stream)))
+            return nodes[:k], ef[:k]
+        nodes, ef = out
+        _check(lib().ef_topk(self._h, ALGO[algo], PREC[prec], int(k), nodes.data_ptr(),
+                             ef.data_ptr() if ef is not None else None, flags | EF_OUT_DEVICE,
+                             _stream_ptr(stream)))
+        return nodes, ef
+
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
             lib().ef_graph_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def union_csr(graphs):
+    """Disjoint union of [(row_ptr, col_idx), ...]: (node_off, row_ptr, col_idx)."""
+    node_off = np.zeros(len(graphs) + 1, np.int64)
+    for i, (rp, _) in enumerate(graphs):
+        node_off[i + 1] = node_off[i] + (len(rp) - 1)
+    nnz = sum(int(rp[-1]) for rp, _ in graphs)
+    rp_u = np.zeros(int(node_off[-1]) + 1, np.int64)
+    ci_u = np.zeros(nnz, np.int32)
+    arc = 0
+    for i, (rp, ci) in enumerate(graphs):
+        n0, n1 = int(node_off[i]), int(node_off[i + 1])
+        rp_u[n0 + 1:n1 + 1] = arc + rp[1:].astype(np.int64)
+        ci_u[arc:arc + ci.size] = ci + n0
+        arc += ci.size
+    return node_off.astype(np.int32), rp_u.astype(np.int32), ci_u
+
+
+class Batch:
+    """Many graphs computed together (handle ``ef_batch``): one disjoint union,
+    one captured HIP graph replayed per call."""
+
+    def __init__(self, graphs, validate: bool = False, stream=None):
+        node_off, rp, ci = union_csr(graphs)
+        self.node_off = node_off
+        self.n = int(node_off[-1])
+        self._h = ctypes.c_void_p()
+        _check(lib().ef_batch_create(len(graphs), node_off.ctypes.data, int(ci.size),
+                                     rp.ctypes.data, ci.ctypes.data if ci.size else None,
+                                     EF_VALIDATE if validate else 0, _stream_ptr(stream),
+                                     ctypes.byref(self._h)))
+
+    def autotune(self, prec: str = "fp32c"):
+        _check(lib().ef_batch_autotune(self._h, PREC[prec]))
+
+    def compute(self, prec: str = "fp32c", out=None, profile: bool = False, stream=None):
+        flags = EF_PROFILE if profile else 0
+        if out is None:
+            ef = np.zeros(max(self.n, 1), np.float64)
+            D = np.zeros(max(self.n, 1), np.int64)
+            N = np.zeros(max(self.n, 1), np.int64)
+            _check(lib().ef_batch_compute(self._h, PREC[prec], ef.ctypes.data, D.ctypes.data,
+                                          N.ctypes.data, flags, _stream_ptr(stream)))
+            return ef[:self.n], D[:self.n], N[:self.n]
+        ef, D, N = out
+        _check(lib().ef_batch_compute(self._h, PREC[prec], ef.data_ptr(),
+                                      D.data_ptr() if D is not None else None,
+                                      N.data_ptr() if N is not None else None,
+                                      flags | EF_OUT_DEVICE, _stream_ptr(stream)))
+        return ef, D, N
+
+    def split(self, arr):
+        """Per-graph views of a per-node array of the union."""
+        return [arr[self.node_off[i]:self.node_off[i + 1]] for i in range(len(self.node_off) - 1)]
+
+    def stats(self) -> dict:
+        st = BatchStats()
+        _check(lib().ef_batch_stats_get(self._h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().ef_batch_free(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

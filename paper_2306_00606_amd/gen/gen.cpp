@@ -15,7 +15,6 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
-#include <unordered_set>
 #include <vector>
 
 #ifdef _OPENMP
@@ -262,28 +261,36 @@ efgen_csr *efgen_rmat(int32_t scale, int32_t edge_factor, double a, double b, do
 efgen_csr *efgen_ws(int32_t n, int32_t k, double p, uint64_t seed) {
   if (n < 3 || k < 2 || (k & 1) || k >= n || !(p >= 0.0) || p > 1.0) return nullptr;
   Rng rng(seed);
-  auto key = [](int64_t u, int64_t v) -> uint64_t {
-    if (u > v) std::swap(u, v);
-    return ((uint64_t)u << 32) | (uint64_t)v;
+  // adjacency as small per-node lists (degrees stay near k)
+  std::vector<std::vector<int32_t>> adj((size_t)n);
+  for (int32_t i = 0; i < n; ++i) adj[i].reserve((size_t)k + 4);
+  auto has = [&](int32_t u, int32_t w) {
+    const auto &a = adj[u];
+    return std::find(a.begin(), a.end(), w) != a.end();
   };
-  std::unordered_set<uint64_t> E;
-  E.reserve((size_t)n * k);
+  auto drop = [&](int32_t u, int32_t w) {
+    auto &a = adj[u];
+    a.erase(std::find(a.begin(), a.end(), w));
+  };
   std::vector<std::pair<int32_t, int32_t>> edges;
   edges.reserve((size_t)n * k / 2);
   for (int32_t j = 1; j <= k / 2; ++j)
     for (int32_t i = 0; i < n; ++i) {
       int32_t w = (int32_t)(((int64_t)i + j) % n);
       edges.emplace_back(i, w);
-      E.insert(key(i, w));
+      adj[i].push_back(w);
+      adj[w].push_back(i);
     }
   for (auto &ed : edges) {
     if (rng.uniform() < p) {
-      int32_t u = ed.first;
+      const int32_t u = ed.first;
       for (int32_t tries = 0; tries < n; ++tries) {
-        int32_t w = (int32_t)rng.below((uint64_t)n);
-        if (w == u || E.count(key(u, w))) continue;
-        E.erase(key(u, ed.second));
-        E.insert(key(u, w));
+        const int32_t w = (int32_t)rng.below((uint64_t)n);
+        if (w == u || has(u, w)) continue;
+        drop(u, ed.second);
+        drop(ed.second, u);
+        adj[u].push_back(w);
+        adj[w].push_back(u);
         ed.second = w;
         break;
       }

@@ -100,3 +100,17 @@ def test_no_device_is_reported_not_fatal():
     with pytest.raises(efgpu.EFError) as ei:
         efgpu.Graph(*_valid())
     assert ei.value.name == "EF_ERR_DEVICE"
+
+
+def test_union_and_batch_validation_on_host():
+    rp, ci = (np.array([0, 1, 2], np.int32), np.array([1, 0], np.int32))
+    node_off, rpu, ciu = efgpu.union_csr([(rp, ci), (rp, ci)])
+    assert node_off.tolist() == [0, 2, 4]
+    assert rpu.tolist() == [0, 1, 2, 3, 4] and ciu.tolist() == [1, 0, 3, 2]
+    # a symmetric edge list whose arcs 0-2 and 1-3 cross between the graphs
+    h = ctypes.c_void_p()
+    bad = np.array([2, 3, 0, 1], np.int32)
+    st = efgpu.lib().ef_batch_create(2, node_off.ctypes.data, 4, rpu.ctypes.data, bad.ctypes.data,
+                                     efgpu.EF_VALIDATE, None, ctypes.byref(h))
+    assert st == 6  # EF_ERR_RANGE
+    assert "leaves graph" in efgpu.last_error()

@@ -261,3 +261,31 @@ def test_config3_rmat22_full_size_sampled():
     oN, oD, oE = oracle.ef(rp, ci, seeds=seeds, threads=16)
     worst = assert_parity(ef[seeds], D[seeds], N[seeds], oN, oD, oE, "fp32c", "R-MAT 22 sample")
     sys.stderr.write(f"[parity] R-MAT 22 sample of {seeds.size}: max rel err {worst:.3e}\n")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_topk_matches_oracle(prec):
+    """Top-k: EF descending, ties by id ascending. Compared with the oracle as a
+    set, nodes whose oracle EF lies within the tolerance of the k-th value being
+    interchangeable; the returned order must follow the returned EF."""
+    rp, ci = GRAPHS["rmat13_ef16"]()
+    oN, oD, oE = oracle_all("rmat13_ef16")
+    tol = REL[prec]
+    with efgpu.Graph(rp, ci) as g:
+        ef_all, _, _ = g.compute(algo="cluster", prec=prec)
+        for k in (1, 10, 100, 1000):
+            nodes, ef = g.topk(k, prec=prec)
+            assert nodes.size == k and np.array_equal(ef, ef_all[nodes])
+            # order: descending EF, ties by id ascending
+            for a, b, ea, eb in zip(nodes[:-1], nodes[1:], ef[:-1], ef[1:]):
+                assert ea > eb or (ea == eb and a < b)
+            kth = np.sort(oE)[::-1][k - 1]
+            sure_in = np.flatnonzero(oE > kth * (1 + 2 * tol))
+            assert set(sure_in.tolist()) <= set(nodes.tolist())
+            assert np.all(oE[nodes] >= kth * (1 - 2 * tol))
+        # k = 0 and k = n
+        n = rp.size - 1
+        nodes, ef = g.topk(n, prec=prec)
+        assert np.array_equal(np.sort(nodes), np.arange(n))
+        with pytest.raises(efgpu.EFError):
+            g.topk(n + 1)
