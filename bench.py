@@ -12,7 +12,14 @@ Eq. 1, FP32 recomputation of cancellation-prone seeds. Cluster-centric
 formulation (Algorithm 1), FP32 terms with compensated sums.
 
 Prints one JSON line. value = clusters/s where clusters = sum_v k_v(k_v-1)/2
-(Algorithm 1's cluster set) per step.
+(Algorithm 1's cluster set) per step. Two further workloads are reported
+beside it in the same line (they are not the headline value):
+  batch     - 512 small graphs (half Watts-Strogatz, half configuration model
+              with power-law degrees, n uniform in 1e3..1e5) computed as one
+              disjoint union by a replayed HIP graph, against 512 separate calls;
+  surrogate - the MLP surrogate trained on exact EF of generator graphs and
+              evaluated on a held-out Barabasi-Albert graph (n = 4M, m = 8):
+              rank agreement with exact EF, and its speed against the exact path.
 """
 import argparse
 import json
@@ -73,6 +80,80 @@ def cpu_baseline(rp, ci, budget_s=15.0):
                       f"clusters/s = sequences/s / 4"}
 
 
+def bench_batch(steps):
+    """Config of 512 uneven graphs in one replayed HIP graph vs separate calls."""
+    import numpy as np
+    import torch
+
+    from paper_2306_00606_amd import efgpu, gen
+
+    dev = torch.device("cuda:0")
+    log("batch: generating 512 graphs")
+    graphs = gen.batch_512()
+    b = efgpu.Batch(graphs)
+    n = b.n
+    out = (torch.empty(n, dtype=torch.float64, device=dev),
+           torch.empty(n, dtype=torch.int64, device=dev),
+           torch.empty(n, dtype=torch.int64, device=dev))
+    b.autotune("fp32c")
+    b.compute(out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.compute(out=out)
+    torch.cuda.synchronize()
+    replay_ms = 1e3 * (time.perf_counter() - t0) / steps
+    bst = b.stats()
+    b.close()
+    # the same work as 512 separate calls (graphs loaded beforehand, device outputs)
+    gs = [efgpu.Graph(rp, ci, validate=False) for rp, ci in graphs]
+    outs = [(torch.empty(g.n, dtype=torch.float64, device=dev),
+             torch.empty(g.n, dtype=torch.int64, device=dev),
+             torch.empty(g.n, dtype=torch.int64, device=dev)) for g in gs]
+    for g, o in zip(gs, outs):
+        g.compute(out=o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for g, o in zip(gs, outs):
+        g.compute(out=o)
+    torch.cuda.synchronize()
+    sep_ms = 1e3 * (time.perf_counter() - t0)
+    for g in gs:
+        g.close()
+    W = int(bst["clusters"])
+    log(f"batch: replay {replay_ms:.2f} ms, separate calls {sep_ms:.1f} ms")
+    return {"workload": "batch512_ws_cm", "graphs": len(graphs), "nodes": n,
+            "arcs": int(bst["nnz"]), "clusters": W, "ms_per_batch": replay_ms,
+            "graphs_per_s": len(graphs) / (replay_ms * 1e-3),
+            "clusters_per_s": W / (replay_ms * 1e-3),
+            "separate_calls_ms": sep_ms, "speedup_vs_separate": sep_ms / replay_ms,
+            "tuned_thresholds": [int(bst["thr8"]), int(bst["thr16"]), int(bst["thr32"])]}
+
+
+def bench_surrogate():
+    """Train the MLP surrogate on exact EF of generator graphs; evaluate it on a
+    held-out Barabasi-Albert graph (n = 4,000,000, m = 8, seed 99)."""
+    from paper_2306_00606_amd import efgpu, gen, surrogate
+
+    log("surrogate: labelling training graphs with the exact kernel")
+    t0 = time.perf_counter()
+    graphs = surrogate.training_graphs(seed=0, count=18)
+    X, y = surrogate.labelled_rows(graphs)
+    t_label = time.perf_counter() - t0
+    sur = efgpu.Surrogate(seed=0)
+    rep = sur.train(X, y, lr=3e-3, epochs=20, batch=8192, seed=0, val_fraction=0.05,
+                    patience=4)
+    log(f"surrogate: trained on {len(y)} rows: {rep}")
+    rp, ci = gen.barabasi_albert(4_000_000, 8, 99)
+    with efgpu.Graph(rp, ci, validate=False) as g:
+        res = surrogate.evaluate(sur, g)
+    sur.close()
+    log(f"surrogate: {res}")
+    res.update({"workload": "ba4m_m8_heldout", "train_rows": int(len(y)),
+                "train_graphs": len(graphs), "label_s": t_label, "train": rep})
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +166,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--per-seed-steps", type=int, default=2,
                     help="also time the per-seed formulation (0 = skip)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 512-graph batch")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -165,6 +248,16 @@ def main():
                     if pst["t_stream_ms"] > 0 else None}
         log(f"per-seed {ps_ms:.1f} ms/step; stream {pst['t_stream_ms']:.1f} ms")
 
+    # whole-step algorithmic HBM bytes: CSR in (row_ptr, col_idx), the triangle
+    # pass's walk over up(w) lists (4 B per wedge check), outputs (EF, D, N)
+    step_bytes = (4.0 * (n + 1) + 4.0 * info["nnz"] + 4.0 * info["wedge_checks"] + 24.0 * n)
+    hbm = {"algorithmic_bytes_per_step": step_bytes,
+           "GBps": step_bytes / (ms * 1e-3) / 1e9,
+           "frac_hbm_peak": step_bytes / (ms * 1e-3) / 8.0e12}
+
+    batch = None if args.no_batch else bench_batch(max(3, args.steps))
+    sur = None if args.no_surrogate else bench_surrogate()
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample")
@@ -194,6 +287,9 @@ def main():
         "ef_checksum": float(np.sum(ef_h)),
         "roofline": roofline,
         "per_seed": per_seed,
+        "hbm": hbm,
+        "batch": batch,
+        "surrogate": sur,
         "cpu_baseline": cpu,
     }
     g.close()

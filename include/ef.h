@@ -208,6 +208,92 @@ ef_status ef_batch_stats_get(const ef_batch *b, ef_batch_stats *out);
 
 ef_status ef_batch_free(ef_batch *b);
 
+/* ---------------------------------------------------------------------------
+ * Learned surrogate. A small MLP (16 features -> 64 -> GELU -> 64 -> GELU -> 1;
+ * BF16 weights and activations, FP32 accumulation on the matrix cores) that
+ * predicts the residual ln N(s) - EF(s) from cheap per-node features; it is
+ * trained on the GPU on exact EF from this library, and the exact kernel
+ * rescores its candidates, judges its rank agreement and stands in for it
+ * when the agreement is too low. The surrogate is not part of the paper's
+ * method; it is a production pattern around the exact path.
+ * ------------------------------------------------------------------------- */
+typedef struct ef_surrogate ef_surrogate;
+
+typedef struct {
+  float lr;            /* Adam step size */
+  int32_t epochs;      /* maximum passes over the training rows */
+  int32_t batch;       /* rows per step (>= 32) */
+  uint64_t seed;       /* shuffling and split */
+  float weight_decay;  /* decoupled weight decay per step (0 = none) */
+  float val_fraction;  /* held-out share for early stopping, in [0, 0.9) */
+  int32_t patience;    /* epochs without validation improvement before stopping */
+} ef_train_cfg;
+
+typedef struct {
+  int32_t epochs_run;
+  float train_loss;    /* mean squared error on the training rows (final weights) */
+  float val_loss;      /* best validation mean squared error */
+  float train_ms;      /* GPU time of the training loop */
+  int64_t rows, val_rows;
+} ef_train_report;
+
+typedef struct {
+  int32_t candidates;  /* nodes rescored exactly */
+  int32_t sample;      /* nodes in the judge's random sample */
+  float spearman;      /* rank correlation of surrogate and exact EF on the sample */
+  int32_t fallback;    /* 1 if the exact top-k of the whole graph was returned */
+  float t_predict_ms, t_rescore_ms, t_judge_ms;
+} ef_judge_report;
+
+/* A surrogate with random (He-normal) weights and identity standardisation. */
+ef_status ef_surrogate_create(uint64_t seed, ef_surrogate **out);
+ef_status ef_surrogate_free(ef_surrogate *s);
+/* params: 5313 FP32 values (W1 16x64, b1 64, W2 64x64, b2 64, w3 64, b3;
+ * row-major, input index first); mean / inv_std: 16 values each. Any may be
+ * NULL. set_params resets the optimiser state. */
+ef_status ef_surrogate_get_params(ef_surrogate *s, float *params, float *mean, float *inv_std);
+ef_status ef_surrogate_set_params(ef_surrogate *s, const float *params, const float *mean,
+                                  const float *inv_std);
+ef_status ef_surrogate_save(ef_surrogate *s, const char *path);
+ef_status ef_surrogate_load(ef_surrogate *s, const char *path);
+
+/* The 16 raw per-node features (row-major n x 16) and ln N(s) per node:
+ * ln(1+k), ln(1+A), ln(1+B), ln(1+T), clustering, ln(1+A-k), ln(1+N),
+ * ln(1+D), ln(D/N), max/min/mean/std of ln(neighbour degree), ln(1+Q),
+ * share of degree-1 neighbours, ln(1+max neighbour-degree sum); A, B = sums
+ * of neighbour degrees and of their squares, T = triangles, Q = sum over
+ * neighbours of their neighbour-degree sums, N and D in closed form.
+ * EF_OUT_DEVICE: X and lnN are device pointers. */
+ef_status ef_features(ef_graph *g, float *X, float *lnN, uint32_t flags, void *hip_stream);
+
+/* Gradient of the mean squared error of the network on (X, y) (host, rows x
+ * 16 inputs used as given) into grad[5313]; loss = the mean squared error.
+ * For checking the training kernels against a CPU reference. */
+ef_status ef_surrogate_gradients(ef_surrogate *s, const float *X, const float *y, int64_t rows,
+                                 float *grad, float *loss, void *hip_stream);
+
+/* Train on host rows: X raw features (rows x 16), y targets (ln N - exact EF).
+ * Standardises the features (stored with the surrogate), then runs Adam on the
+ * GPU with early stopping on a held-out share. */
+ef_status ef_surrogate_train(ef_surrogate *s, const float *X, const float *y, int64_t rows,
+                             const ef_train_cfg *cfg, ef_train_report *rep, void *hip_stream);
+
+/* Predicted EF of every node of g (double, length n). EF_OUT_DEVICE: device
+ * output, asynchronous. */
+ef_status ef_surrogate_predict(ef_surrogate *s, ef_graph *g, double *ef_pred, uint32_t flags,
+                               void *hip_stream);
+
+/* Top-k by the surrogate with exact rescoring: the rerank_factor * k best
+ * nodes by predicted EF are rescored by the exact per-seed kernel and the k
+ * best by exact EF returned (host arrays nodes[k], ef_exact[k] nullable).
+ * The judge compares surrogate and exact EF on judge_sample random nodes
+ * (seeded); if their Spearman correlation is below min_spearman, the exact
+ * top-k of the whole graph is returned instead (rep->fallback = 1). */
+ef_status ef_topk_surrogate(ef_graph *g, ef_surrogate *s, int32_t k, int32_t rerank_factor,
+                            int32_t judge_sample, float min_spearman, uint64_t seed,
+                            int32_t *nodes, double *ef_exact, ef_judge_report *rep,
+                            void *hip_stream);
+
 /* Counters and (with EF_PROFILE) phase times of the last ef_compute on g. */
 ef_status ef_stats(const ef_graph *g, ef_run_stats *out);
 

@@ -76,21 +76,12 @@ __device__ __forceinline__ void acc_merge(DFv &a, DFv b) { a.add(b); }
 __device__ __forceinline__ void acc_merge(double &a, double b) { a += b; }
 __device__ __forceinline__ double wave_sum(double x) { return wave_sum_f64(x); }
 
-// Cluster score g(d) = d log d and the triangle adjustment
-//   delta(sigma) = g(sigma - 6) - g(sigma - 4)
-// evaluated as a * log1p(-2/b) - 2 log b with a = sigma-6, b = sigma-4, a
-// sum of two non-positive terms (no cancellation). FP32: log2 units.
+// Cluster score g(d) = d log d (FP32: log2 units, from v_log_f32) and the
+// triangle adjustment delta(sigma) = g(sigma - 6) - g(sigma - 4), taken as the
+// difference of two scores: its rounding error is that of scoring the
+// triangle cluster itself, the same as every pair term.
 __device__ __forceinline__ float score_f(float d) { return d * __builtin_amdgcn_logf(d); }
 __device__ __forceinline__ double score_d(double d) { return d * log(d); }
-
-__device__ __forceinline__ float tri_delta_f(int32_t sigma) {
-  const float a = (float)(sigma - 6), b = (float)(sigma - 4);
-  return a * (log1pf(-2.0f / b) * 1.4426950408889634f) - 2.0f * log2f(b);
-}
-__device__ __forceinline__ double tri_delta_d(int32_t sigma) {
-  const double a = (double)(sigma - 6), b = (double)(sigma - 4);
-  return a * log1p(-2.0 / b) - 2.0 * log(b);
-}
 
 template <typename T> __device__ __forceinline__ T score_t(int32_t d);
 template <> __device__ __forceinline__ float score_t<float>(int32_t d) {
@@ -99,9 +90,9 @@ template <> __device__ __forceinline__ float score_t<float>(int32_t d) {
 template <> __device__ __forceinline__ double score_t<double>(int32_t d) {
   return d > 0 ? score_d((double)d) : 0.0;
 }
-template <typename T> __device__ __forceinline__ T tri_delta(int32_t sigma);
-template <> __device__ __forceinline__ float tri_delta<float>(int32_t s) { return tri_delta_f(s); }
-template <> __device__ __forceinline__ double tri_delta<double>(int32_t s) { return tri_delta_d(s); }
+template <typename T> __device__ __forceinline__ T tri_delta(int32_t sigma) {
+  return score_t<T>(sigma - 6) - score_t<T>(sigma - 4);
+}
 
 __device__ __forceinline__ uint32_t hash32(uint32_t x) { return x * 2654435761u; }
 

@@ -108,7 +108,6 @@ static inline bool rank_less_h(int32_t a, int32_t ka, int32_t b, int32_t kb) {
 
 // Largest degree for which every cluster degree (< 3 k_max) is exact in
 // FP32 and every D(s) (< 6 k_max^3) fits in int64.
-constexpr int32_t kMaxDegree = 1000000;
 
 }  // namespace efi
 
@@ -473,8 +472,15 @@ namespace efi {
 // workspace slots
 enum {
   WS_R = 0, WS_REC, WS_Y, WS_YT, WS_Z, WS_ZT, WS_YACC, WS_FLAG, WS_BINS, WS_OUT, WS_BITMAP,
-  WS_SEEDS, WS_UOUT, WS_TOPK
+  WS_SEEDS, WS_UOUT, WS_TOPK, WS_SURR
 };
+
+// scratch for other translation units (kept in the handle, grow-only)
+ef_status graph_scratch(Graph &g, size_t bytes, void **out) {
+  ef_status s = ws_ensure(g, WS_SURR, bytes, "scratch");
+  *out = s == EF_OK ? g.ws[WS_SURR].p : nullptr;
+  return s;
+}
 
 static void host_bins(const Graph &g, const int32_t *centres, int64_t count, Bins &b) {
   b.n_small = b.n_mid = b.n_big = b.n_tiles = 0;

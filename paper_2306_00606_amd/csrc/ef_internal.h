@@ -31,6 +31,10 @@ constexpr int kRecEntries = 2 * kSuper;  // row part + column part per super-til
 // Triangle pass: nodes are binned by the length of their degree-oriented
 // out-list up(u): 2..64, 65..512, 513..2048 use an LDS hash of up(u) sized
 // for the bin; longer lists search global memory.
+// Largest node degree accepted by the loader: cluster degrees (< 3 * kMaxDegree)
+// stay exact in int32, and a degree fits the 20-bit field of the packed
+// (degree, position) words of the triangle pass.
+constexpr int32_t kMaxDegree = 1000000;
 constexpr int kTriBin0 = 64, kTriBin1 = 512, kTriBin2 = 2048;
 constexpr int kTriLongMin = kTriBin2 + 1;
 
@@ -112,6 +116,10 @@ struct Graph {
 // ef_compute flag reserved for the library: launch only, no host read-back
 // (the call is being captured into a HIP graph)
 constexpr uint32_t kInternalNoReadback = 0x80000000u;
+
+// grow-only device scratch held by the graph handle (one slot shared by the
+// surrogate entry points)
+ef_status graph_scratch(Graph &g, size_t bytes, void **out);
 
 // error text (thread-local)
 void set_error(const char *fmt, ...);

@@ -1,0 +1,501 @@
+// Learned surrogate for Expected Force: per-node features, and a small MLP
+// (16 -> 64 -> GELU -> 64 -> GELU -> 1) with BF16 operands and FP32
+// accumulation on the gfx950 matrix cores (v_mfma_f32_32x32x16_bf16), trained
+// on the GPU by its own forward and backward kernels and an Adam step.
+//
+// The network predicts the residual y = ln N(s) - EF(s) >= 0 (EF is at most
+// ln N, with equality when all clusters of s have the same degree); the
+// predicted EF is max(0, ln N - y).
+//
+// MFMA operand layouts (wave64, 32x32x16): lane l holds
+//   A[i][k]  for i = l % 32, k = 8 (l / 32) + j          (8 bf16, j = 0..7)
+//   B[k][n]  for n = l % 32, k = 8 (l / 32) + j          (8 bf16)
+//   C[i][n]  for n = l % 32, i = 8 (r / 4) + 4 (l / 32) + r % 4  (16 fp32, r = 0..15)
+// Weights are kept as FP32 masters and re-packed into the B layout (bf16)
+// after every optimiser step.
+#include "common.cuh"
+
+namespace efi {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kF = 16, kH = 64;
+// flat parameter vector
+constexpr int kOffW1 = 0, kOffB1 = 1024, kOffW2 = 1088, kOffB2 = 5184, kOffW3 = 5248,
+              kOffB3 = 5312, kParams = 5313;
+// packed bf16 B-operand blocks (64 lanes x 8 values each)
+constexpr int kPackW1 = 0;                  // kb 1 x nb 2
+constexpr int kPackW2 = 2;                  // kb 4 x nb 2
+constexpr int kPackW3 = 10;                 // kb 4 x nb 1 (column 0 = w3)
+constexpr int kPackW2T = 14;                // kb 4 x nb 2 (W2 transposed)
+constexpr int kPackBlocks = 22;
+
+__device__ __forceinline__ int c_row(int r, int lane) {
+  return ((r >> 2) << 3) + ((lane >> 5) << 2) + (r & 3);
+}
+__device__ __forceinline__ f32x16 mfma(bf16x8 a, bf16x8 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ float gelu(float z) {
+  return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
+}
+__device__ __forceinline__ float gelu_grad(float z) {
+  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) +
+         z * 0.39894228040143268f * expf(-0.5f * z * z);
+}
+__device__ __forceinline__ float bf(float x) { return (float)(__bf16)x; }
+
+// ---------------------------------------------------------------------------
+// features: one wavefront per node
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_features(
+    const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ deg,
+    const int2 *__restrict__ adj2, const int64_t *__restrict__ asum,
+    const int32_t *__restrict__ tslot, const int32_t *__restrict__ YT,
+    const int64_t *__restrict__ ZT, int32_t n, const float *__restrict__ mean,
+    const float *__restrict__ inv_std, float *__restrict__ X, float *__restrict__ lnN) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t v = wave; v < n; v += nwaves) {
+    const int32_t k = deg[v], base = row_ptr[v];
+    int64_t B = 0, Q = 0, T = 0, c1 = 0, smax = 0;
+    float mx = -1e30f, mn = 1e30f;
+    double s1 = 0.0, s2 = 0.0;
+    for (int32_t e = base + lane; e < base + k; e += 64) {
+      const int2 ad = adj2[e];
+      const int64_t ka = ad.y, sa = asum[ad.x];
+      B += ka * ka;
+      Q += sa;
+      smax = sa > smax ? sa : smax;
+      c1 += ka == 1;
+      const float lk = logf((float)ka);
+      mx = fmaxf(mx, lk);
+      mn = fminf(mn, lk);
+      s1 += lk;
+      s2 += (double)lk * lk;
+      if (rank_less_d(ad.x, ad.y, (int32_t)v, k)) T += YT[tslot[e]];
+    }
+    B = wave_sum_i64(B);
+    Q = wave_sum_i64(Q);
+    T = wave_sum_i64(T);
+    c1 = wave_sum_i64(c1);
+    s1 = wave_sum_f64(s1);
+    s2 = wave_sum_f64(s2);
+    for (int off = 32; off > 0; off >>= 1) {
+      mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+      mn = fminf(mn, __shfl_xor(mn, off, 64));
+      const int64_t o = __shfl_xor(smax, off, 64);
+      smax = o > smax ? o : smax;
+    }
+    if (lane == 0) {
+      T += ZT[v];
+      const int64_t kk = k, A = asum[v];
+      const int64_t Ns = kk * kk - 2 * kk + A;
+      const int64_t Ds = kk * (kk - 1) * (kk - 4) + 2 * (kk - 1) * A + (kk - 4) * (A - kk) +
+                         (B - A) + (Q - kk * kk) - 8 * T;
+      float f[kF];
+      f[0] = logf(1.0f + (float)kk);
+      f[1] = logf(1.0f + (float)A);
+      f[2] = logf(1.0f + (float)B);
+      f[3] = logf(1.0f + (float)T);
+      f[4] = kk >= 2 ? (float)(2.0 * (double)T / (double)(kk * (kk - 1))) : 0.0f;
+      f[5] = logf(1.0f + (float)(A - kk));
+      f[6] = logf(1.0f + (float)Ns);
+      f[7] = logf(1.0f + (float)Ds);
+      f[8] = (Ns > 0 && Ds > 0) ? (float)log((double)Ds / (double)Ns) : 0.0f;
+      const double mean_lk = k > 0 ? s1 / k : 0.0;
+      f[9] = k > 0 ? mx : 0.0f;
+      f[10] = k > 0 ? mn : 0.0f;
+      f[11] = (float)mean_lk;
+      f[12] = k > 0 ? (float)sqrt(fmax(s2 / k - mean_lk * mean_lk, 0.0)) : 0.0f;
+      f[13] = logf(1.0f + (float)Q);
+      f[14] = k > 0 ? (float)c1 / (float)k : 0.0f;
+      f[15] = logf(1.0f + (float)smax);
+      for (int i = 0; i < kF; ++i) {
+        float x = f[i];
+        if (mean) x = (x - mean[i]) * inv_std[i];
+        X[v * kF + i] = x;
+      }
+      lnN[v] = Ns > 0 ? logf((float)Ns) : 0.0f;
+    }
+  }
+}
+
+hipError_t launch_features(const Graph &g, const int32_t *YT, const int64_t *ZT,
+                           const float *mean, const float *inv_std, float *X, float *lnN,
+                           hipStream_t st) {
+  const int64_t blocks = std::min<int64_t>(((int64_t)g.n * 64 + 255) / 256, 1 << 20);
+  hipLaunchKernelGGL(k_features, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st,
+                     g.row_ptr, g.deg, g.adj2, g.asum, g.tslot, YT, ZT, g.n, mean, inv_std, X,
+                     lnN);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// MLP on one 32-row tile per wavefront
+// ---------------------------------------------------------------------------
+struct TileLds {
+  __bf16 x[32][kF];
+  __bf16 h1[32][kH];
+  __bf16 h2[32][kH];
+  __bf16 dz[32][kH];
+  float dy[32];
+};
+
+__device__ __forceinline__ bf16x8 lds_a(const __bf16 *rowmajor, int ld, int kb) {
+  // A fragment: row lane % 32, columns 16 kb + 8 (lane / 32) .. + 7
+  const int lane = threadIdx.x & 63;
+  return *reinterpret_cast<const bf16x8 *>(rowmajor + (lane & 31) * ld + kb * 16 +
+                                           ((lane >> 5) << 3));
+}
+// B fragment from a row-major [K][ld] LDS matrix: column nb*32 + lane%32,
+// rows 16 kb + 8 (lane / 32) .. + 7
+__device__ __forceinline__ bf16x8 lds_b(const __bf16 *rowmajor, int ld, int kb, int nb) {
+  const int lane = threadIdx.x & 63;
+  bf16x8 v;
+  const int r0 = kb * 16 + ((lane >> 5) << 3), c = nb * 32 + (lane & 31);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) v[j] = rowmajor[(r0 + j) * ld + c];
+  return v;
+}
+// A fragment of the transpose of a row-major [K][ld] LDS matrix: A[m][kk] =
+// M[kk][m], m = mb*32 + lane%32 (zero when m >= mlim), kk = 16 kb + 8 (lane/32) + j
+__device__ __forceinline__ bf16x8 lds_at(const __bf16 *rowmajor, int ld, int kb, int mb,
+                                         int mlim) {
+  const int lane = threadIdx.x & 63;
+  bf16x8 v;
+  const int r0 = kb * 16 + ((lane >> 5) << 3), m = mb * 32 + (lane & 31);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) v[j] = m < mlim ? rowmajor[(r0 + j) * ld + m] : (__bf16)0.0f;
+  return v;
+}
+__device__ __forceinline__ bf16x8 wpack(const __bf16 *pack, int block) {
+  return reinterpret_cast<const bf16x8 *>(pack)[block * 64 + (threadIdx.x & 63)];
+}
+
+// Forward of one tile. Rows r0 .. r0+31 of X (row index through `perm` when
+// given); rows at or past `rows` are zero. Leaves z1, z2 (pre-activations,
+// C layout) in registers and x, h1, h2 (bf16) in LDS; returns y for the rows
+// held by lanes 0 and 32 (C layout of column 0) in yv.
+__device__ void tile_forward(const float *__restrict__ X, const int32_t *__restrict__ perm,
+                             int64_t r0, int64_t rows, const float *__restrict__ P,
+                             const __bf16 *__restrict__ pack, TileLds &t, f32x16 z1[2],
+                             f32x16 z2[2], f32x16 &yv) {
+  const int lane = threadIdx.x & 63;
+  {
+    const int i = lane & 31, c0 = (lane >> 5) * 8;
+    const int64_t row = r0 + i;
+    float xv[8];
+    if (row < rows) {
+      const int64_t src = perm ? perm[row] : row;
+      const float4 a = *reinterpret_cast<const float4 *>(X + src * kF + c0);
+      const float4 b = *reinterpret_cast<const float4 *>(X + src * kF + c0 + 4);
+      xv[0] = a.x; xv[1] = a.y; xv[2] = a.z; xv[3] = a.w;
+      xv[4] = b.x; xv[5] = b.y; xv[6] = b.z; xv[7] = b.w;
+    } else {
+      for (int j = 0; j < 8; ++j) xv[j] = 0.0f;
+    }
+    for (int j = 0; j < 8; ++j) t.x[i][c0 + j] = (__bf16)xv[j];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  const bf16x8 ax = lds_a(&t.x[0][0], kF, 0);
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb) {
+    f32x16 c = {};
+    c = mfma(ax, wpack(pack, kPackW1 + nb), c);
+    const float b1 = P[kOffB1 + nb * 32 + (lane & 31)];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      c[r] += b1;
+      t.h1[c_row(r, lane)][nb * 32 + (lane & 31)] = (__bf16)gelu(c[r]);
+    }
+    z1[nb] = c;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb) {
+    f32x16 c = {};
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb)
+      c = mfma(lds_a(&t.h1[0][0], kH, kb), wpack(pack, kPackW2 + kb * 2 + nb), c);
+    const float b2 = P[kOffB2 + nb * 32 + (lane & 31)];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      c[r] += b2;
+      t.h2[c_row(r, lane)][nb * 32 + (lane & 31)] = (__bf16)gelu(c[r]);
+    }
+    z2[nb] = c;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  f32x16 c = {};
+#pragma unroll
+  for (int kb = 0; kb < 4; ++kb) c = mfma(lds_a(&t.h2[0][0], kH, kb), wpack(pack, kPackW3 + kb), c);
+  const float b3 = P[kOffB3];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) c[r] += b3;
+  yv = c;
+}
+
+// inference: y for rows [0, rows); out_ef = max(0, lnN - y) when lnN given
+__global__ __launch_bounds__(256) void k_mlp_forward(const float *__restrict__ X, int64_t rows,
+                                                     const float *__restrict__ P,
+                                                     const __bf16 *__restrict__ pack,
+                                                     const float *__restrict__ lnN,
+                                                     float *__restrict__ y_out,
+                                                     double *__restrict__ ef_out) {
+  __shared__ TileLds tl[4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t tiles = (rows + 31) / 32;
+  for (int64_t tile = (int64_t)blockIdx.x * 4 + wv; tile < tiles; tile += (int64_t)gridDim.x * 4) {
+    f32x16 z1[2], z2[2], yv;
+    tile_forward(X, nullptr, tile * 32, rows, P, pack, tl[wv], z1, z2, yv);
+    if ((lane & 31) == 0) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t row = tile * 32 + c_row(r, lane);
+        if (row < rows) {
+          if (y_out) y_out[row] = yv[r];
+          if (ef_out) {
+            const float e = lnN[row] - yv[r];
+            ef_out[row] = e > 0.0f ? (double)e : 0.0;
+          }
+        }
+      }
+    }
+  }
+}
+
+// Training: gradients of the mean squared error over the rows perm[b0 .. b0+nb)
+// (scale = 2 / nb), accumulated per wavefront into part[wave][kParams]; the
+// squared-error sum per wavefront into part_loss[wave].
+__global__ __launch_bounds__(256) void k_mlp_grad(const float *__restrict__ X,
+                                                  const float *__restrict__ Yt,
+                                                  const int32_t *__restrict__ perm, int64_t b0,
+                                                  int64_t nrows, const float *__restrict__ P,
+                                                  const __bf16 *__restrict__ pack,
+                                                  float *__restrict__ part,
+                                                  float *__restrict__ part_loss) {
+  __shared__ TileLds tl[4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  TileLds &t = tl[wv];
+  const int64_t wave = (int64_t)blockIdx.x * 4 + wv;
+  const int64_t nwaves = (int64_t)gridDim.x * 4;
+  const int64_t tiles = (nrows + 31) / 32;
+  const float scale = 2.0f / (float)nrows;
+  const int col = lane & 31;
+  f32x16 gW2[2][2] = {}, gW1[2] = {};
+  float gb1[2] = {0.f, 0.f}, gb2[2] = {0.f, 0.f}, gw3[2] = {0.f, 0.f}, gb3 = 0.f, lsum = 0.f;
+  float w3b[2];
+  for (int nb = 0; nb < 2; ++nb) w3b[nb] = bf(P[kOffW3 + nb * 32 + col]);
+  const int32_t *pr = perm + b0;
+  for (int64_t tile = wave; tile < tiles; tile += nwaves) {
+    f32x16 z1[2], z2[2], yv;
+    tile_forward(X, pr, tile * 32, nrows, P, pack, t, z1, z2, yv);
+    if (col == 0) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int i = c_row(r, lane);
+        const int64_t row = tile * 32 + i;
+        float d = 0.f;
+        if (row < nrows) {
+          const float res = yv[r] - Yt[pr[row]];
+          lsum += res * res;
+          d = scale * res;
+        }
+        t.dy[i] = d;
+        gb3 += d;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    // layer 3 and dz2 = dy w3 * gelu'(z2)
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int i = c_row(r, lane);
+        const float d = t.dy[i];
+        gw3[nb] += (float)t.h2[i][nb * 32 + col] * d;
+        const float dz = d * w3b[nb] * gelu_grad(z2[nb][r]);
+        gb2[nb] += dz;
+        t.dz[i][nb * 32 + col] = (__bf16)dz;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    // dW2 += h1^T dz2 ; dh1 = dz2 W2^T
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb) {
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb) {
+        const bf16x8 a = lds_at(&t.h1[0][0], kH, kb, mb, kH);
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) gW2[mb][nb] = mfma(a, lds_b(&t.dz[0][0], kH, kb, nb), gW2[mb][nb]);
+      }
+    }
+    f32x16 dh1[2];
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) {
+      f32x16 c = {};
+#pragma unroll
+      for (int kb = 0; kb < 4; ++kb)
+        c = mfma(lds_a(&t.dz[0][0], kH, kb), wpack(pack, kPackW2T + kb * 2 + nb), c);
+      dh1[nb] = c;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    // dz1 = dh1 * gelu'(z1)
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float dz = dh1[nb][r] * gelu_grad(z1[nb][r]);
+        gb1[nb] += dz;
+        t.dz[c_row(r, lane)][nb * 32 + col] = (__bf16)dz;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    // dW1 += x^T dz1 (rows 16..31 of the A operand are zero)
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb) {
+      const bf16x8 a = lds_at(&t.x[0][0], kF, kb, 0, kF);
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) gW1[nb] = mfma(a, lds_b(&t.dz[0][0], kH, kb, nb), gW1[nb]);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  }
+  // write this wavefront's partial gradient
+  float *g = part + wave * kParams;
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int m = c_row(r, lane);
+      if (m < kF) g[kOffW1 + m * kH + nb * 32 + col] = gW1[nb][r];
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb) g[kOffW2 + (mb * 32 + m) * kH + nb * 32 + col] = gW2[mb][nb][r];
+    }
+    const float b1 = gb1[nb] + __shfl_xor(gb1[nb], 32, 64);
+    const float b2 = gb2[nb] + __shfl_xor(gb2[nb], 32, 64);
+    const float w3 = gw3[nb] + __shfl_xor(gw3[nb], 32, 64);
+    if (lane < 32) {
+      g[kOffB1 + nb * 32 + col] = b1;
+      g[kOffB2 + nb * 32 + col] = b2;
+      g[kOffW3 + nb * 32 + col] = w3;
+    }
+  }
+  const float b3 = gb3 + __shfl_xor(gb3, 32, 64);
+  const float ls = lsum + __shfl_xor(lsum, 32, 64);
+  if (lane == 0) {
+    g[kOffB3] = b3;
+    part_loss[wave] = ls;
+  }
+}
+
+// grad[p] = sum over wavefronts (fixed order); loss = sum of part_loss
+__global__ void k_grad_reduce(const float *__restrict__ part, const float *__restrict__ part_loss,
+                              int32_t nwaves, float *__restrict__ grad, float *__restrict__ loss) {
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p <= kParams; p += gridDim.x * blockDim.x) {
+    if (p < kParams) {
+      double s = 0.0;
+      for (int w = 0; w < nwaves; ++w) s += part[(int64_t)w * kParams + p];
+      grad[p] = (float)s;
+    } else {
+      double s = 0.0;
+      for (int w = 0; w < nwaves; ++w) s += part_loss[w];
+      *loss = (float)s;
+    }
+  }
+}
+
+// Re-pack the BF16 B-operand blocks from the FP32 masters.
+__global__ void k_pack(const float *__restrict__ P, __bf16 *__restrict__ pack) {
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < kPackBlocks * 64 * 8;
+       idx += gridDim.x * blockDim.x) {
+    const int block = idx / 512, lane = (idx / 8) % 64, j = idx % 8;
+    const int kin = (lane >> 5) * 8 + j, n = lane & 31;
+    float v = 0.f;
+    if (block < kPackW2) {  // W1: kb 0, nb = block
+      v = P[kOffW1 + kin * kH + block * 32 + n];
+    } else if (block < kPackW3) {  // W2: (kb, nb)
+      const int b = block - kPackW2, kb = b / 2, nb = b % 2;
+      v = P[kOffW2 + (kb * 16 + kin) * kH + nb * 32 + n];
+    } else if (block < kPackW2T) {  // w3 as column 0
+      const int kb = block - kPackW3;
+      v = n == 0 ? P[kOffW3 + kb * 16 + kin] : 0.f;
+    } else {  // W2^T: B[k][n] = W2[n][k]
+      const int b = block - kPackW2T, kb = b / 2, nb = b % 2;
+      v = P[kOffW2 + (nb * 32 + n) * kH + kb * 16 + kin];
+    }
+    pack[idx] = (__bf16)v;
+  }
+}
+
+// Adam (Kingma and Ba, 2015) on the FP32 masters: step t (1-based)
+__global__ void k_adam(float *__restrict__ P, float *__restrict__ M, float *__restrict__ V,
+                       const float *__restrict__ grad, float lr, float b1, float b2, float eps,
+                       float wd, int32_t t) {
+  const float c1 = 1.0f - powf(b1, (float)t), c2 = 1.0f - powf(b2, (float)t);
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < kParams; p += gridDim.x * blockDim.x) {
+    const float g = grad[p];
+    const float m = b1 * M[p] + (1.0f - b1) * g;
+    const float v = b2 * V[p] + (1.0f - b2) * g * g;
+    M[p] = m;
+    V[p] = v;
+    P[p] -= lr * ((m / c1) / (sqrtf(v / c2) + eps) + wd * P[p]);
+  }
+}
+
+hipError_t launch_mlp_pack(const float *P, __bf16 *pack, hipStream_t st) {
+  hipLaunchKernelGGL(k_pack, dim3(22), dim3(512), 0, st, P, pack);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward(const float *X, int64_t rows, const float *P, const __bf16 *pack,
+                              const float *lnN, float *y, double *ef, hipStream_t st) {
+  if (rows <= 0) return hipSuccess;
+  const int64_t tiles = (rows + 31) / 32;
+  const unsigned blocks = (unsigned)std::min<int64_t>((tiles + 3) / 4, 1 << 16);
+  hipLaunchKernelGGL(k_mlp_forward, dim3(blocks), dim3(256), 0, st, X, rows, P, pack, lnN, y, ef);
+  return hipGetLastError();
+}
+
+// gradient of the mean squared error over perm[b0 .. b0+nrows) with `nblocks`
+// workgroups of 4 wavefronts; part has room for nblocks*4 partials
+hipError_t launch_mlp_grad(const float *X, const float *Yt, const int32_t *perm, int64_t b0,
+                           int64_t nrows, const float *P, const __bf16 *pack, float *part,
+                           float *part_loss, int32_t nblocks, float *grad, float *loss,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_mlp_grad, dim3(nblocks), dim3(256), 0, st, X, Yt, perm, b0, nrows, P, pack,
+                     part, part_loss);
+  hipLaunchKernelGGL(k_grad_reduce, dim3((kParams + 256) / 256), dim3(256), 0, st, part,
+                     part_loss, nblocks * 4, grad, loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(float *P, float *M, float *V, const float *grad, float lr, float b1,
+                       float b2, float eps, float wd, int32_t t, hipStream_t st) {
+  hipLaunchKernelGGL(k_adam, dim3((kParams + 255) / 256), dim3(256), 0, st, P, M, V, grad, lr, b1,
+                     b2, eps, wd, t);
+  return hipGetLastError();
+}
+
+int32_t mlp_param_count() { return kParams; }
+int32_t mlp_pack_count() { return kPackBlocks * 64 * 8; }
+
+}  // namespace efi

@@ -8,24 +8,33 @@
 //   sequences on that node set, so per member the score sum S changes by
 //   4 * delta(sigma), delta(sigma) = g(sigma - 6) - g(sigma - 4), and the
 //   degree sum D by -8.
-// delta is evaluated in registers at each hit (no dependent memory access).
 //
 // Listing: nodes are ranked by (degree, id); a triangle u < w < x (by rank) is
 // found once, at u, as x in up(u) and up(w), where up(.) is the rank-oriented
-// out-list. One wavefront per u: up(u) is hashed in LDS (id -> position) and
-// the lists up(w), w in up(u), are walked as one concatenated sequence, 64
-// consecutive entries per step. Credits:
+// out-list. up(u) is hashed in LDS (id -> degree, position) and the lists
+// up(w), w in up(u), are walked as one concatenated sequence ("segments"),
+// 64 consecutive entries per wavefront step. Short up(u): one wavefront per u.
+// Longer up(u): one workgroup per u, each wavefront walking a contiguous
+// share of the sequence. Credits:
 //   u  - lane registers (floating point), reduced at the end  -> Z[u], ZT[u]
 //   w  - LDS add at w's position in up(u)
 //   x  - LDS add at x's position in up(u)
-// The LDS credit slots hold 64-bit fixed point (2^-40 units), so concurrent
-// adds are exact and order-independent: results are bitwise reproducible.
-// The slots are written to Y[slot], YT[slot] for the up-arc slots of u.
+// The LDS credit slots are integers (see Credit), so concurrent adds are exact
+// and order-independent: results are bitwise reproducible. The slots are
+// written to Y[slot], YT[slot] for the up-arc slots of u.
 #include "common.cuh"
 
 namespace efi {
 
 constexpr double kFix = 1099511627776.0;  // 2^40
+constexpr int kPosBits = 12;              // position in up(u) < 4096
+static_assert(kTriBin2 <= (1 << kPosBits), "position field too narrow");
+static_assert(kMaxDegree < (1u << (32 - kPosBits)), "degree field too narrow");
+
+__device__ __forceinline__ int32_t pack_kp(int32_t k, int32_t pos) {
+  return (int32_t)(((uint32_t)k << kPosBits) | (uint32_t)pos);
+}
+__device__ __forceinline__ int32_t unpack_k(int32_t v) { return (int32_t)((uint32_t)v >> kPosBits); }
 
 template <typename T> __device__ __forceinline__ long long to_fix(T v) {
   return __double2ll_rn((double)v * kFix);
@@ -37,136 +46,296 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// SLOTS: hash slots per wavefront, MAXM: largest |up(u)|, WPB: wavefronts
-// per workgroup (each with its own LDS region and its own u).
-//
-// The lists up(w), w in up(u), are processed as one concatenated sequence:
-// non-empty lists are compacted into segments (start in up_col, k_w, w's
-// position in up(u)) with an exclusive prefix of their lengths; each step the
-// 64 lanes take 64 consecutive entries (coalesced loads, no divergence across
-// list lengths) and find their segment by binary search in the prefix.
+// Integer credit slots, 2^-40 units on output.
+// FP32: delta < 0 is a float with 2 <= |delta| < 2^7 (log2 units, degrees
+//   below kMaxDegree), so its ulp is >= 2^-22 and |delta| * 2^24 is an exact
+//   integer below 2^31. A slot holds one word, count << 44 plus the sum of
+//   those integers; at most kTriBin2 = 2^11 credits land in a slot, so the
+//   sum stays below 2^42 and one 64-bit add records credit and count.
+// FP64: the credit rounded to 2^-40 in one 64-bit slot, the count in a
+//   separate 32-bit slot.
+template <typename T> struct Credit;
+template <> struct Credit<float> {
+  static constexpr bool kPacked = true;
+  __device__ static void add(unsigned long long *acc, int32_t *, int32_t slot, float dl) {
+    atomicAdd(&acc[slot], (1ull << 44) + (unsigned long long)(uint32_t)(-dl * 16777216.0f));
+  }
+  __device__ static void load(const unsigned long long *acc, const int32_t *, int32_t slot,
+                              long long &y, int32_t &yt) {
+    const unsigned long long w = acc[slot];
+    y = -(long long)((w & ((1ull << 44) - 1)) << 16);
+    yt = (int32_t)(w >> 44);
+  }
+};
+template <> struct Credit<double> {
+  static constexpr bool kPacked = false;
+  __device__ static void add(unsigned long long *acc, int32_t *cnt, int32_t slot, double dl) {
+    atomicAdd(&acc[slot], (unsigned long long)to_fix(dl));
+    atomicAdd(&cnt[slot], 1);
+  }
+  __device__ static void load(const unsigned long long *acc, const int32_t *cnt, int32_t slot,
+                              long long &y, int32_t &yt) {
+    y = (long long)acc[slot];
+    yt = cnt[slot];
+  }
+};
+
+// LDS state of one u:
+//   htab[SLOTS]   {x, k_x << kPosBits | position of x in up(u)}, x = -1 empty
+//   seg[MAXM]     per non-empty up(w): {first index of up(w) in up_col minus
+//                 its first index in the concatenated sequence,
+//                 k_w << kPosBits | position of w in up(u)}
+//   segp[MAXM+1]  first concatenated index of each segment; segp[nseg] = total
+//   acc, cnt      credit slots by position in up(u)
+//   flg[64]       per wavefront: segment-start flags of the current step
+template <typename T, int SLOTS, int MAXM> struct TriLds {
+  int2 htab[SLOTS];
+  int2 seg[MAXM];
+  int32_t segp[MAXM + 1];
+  unsigned long long acc[MAXM];
+  int32_t cnt[Credit<T>::kPacked ? 1 : MAXM];
+};
+
+// Build the hash of up(u) and the segment table with NT threads (one
+// wavefront, or the workgroup); `part` holds 2 * NT/64 ints of scratch.
+// Returns the segment count and the sequence length.
+template <int SLOTS, int NT>
+__device__ __forceinline__ void tri_setup(const int32_t *__restrict__ up_ptr,
+                                          const int32_t *__restrict__ up_col,
+                                          const int32_t *__restrict__ deg, int32_t u0, int32_t m,
+                                          int tid, int2 *htab, int2 *seg, int32_t *segp,
+                                          int32_t *part, int32_t &nseg_out, int32_t &total_out) {
+  constexpr int kShift = 32 - __builtin_ctz(SLOTS);
+  constexpr int NW = NT / 64;
+  const int lane = tid & 63, wv = tid >> 6;
+  const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  int32_t nseg = 0, run = 0;
+  for (int c = 0; c < m; c += NT) {
+    const int i = c + tid;
+    int32_t x = 0, w0 = 0, len = 0, kx = 0;
+    if (i < m) {
+      x = up_col[u0 + i];
+      w0 = up_ptr[x];
+      len = up_ptr[x + 1] - w0;
+      kx = deg[x];
+      uint32_t h = hash32((uint32_t)x) >> kShift;
+      while (atomicCAS(&htab[h].x, -1, x) != -1) h = (h + 1) & (SLOTS - 1);
+      htab[h].y = pack_kp(kx, i);
+    }
+    const unsigned long long nz = __ballot(len > 0);
+    int32_t incl = len;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int32_t y = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += y;
+    }
+    int32_t pre_n = 0, pre_l = 0, tot_n, tot_l;
+    if constexpr (NW == 1) {
+      tot_n = __popcll(nz);
+      tot_l = __shfl(incl, 63, 64);
+    } else {
+      if (lane == 63) {
+        part[2 * wv] = __popcll(nz);
+        part[2 * wv + 1] = incl;
+      }
+      __syncthreads();
+      tot_n = 0;
+      tot_l = 0;
+      for (int w = 0; w < NW; ++w) {
+        const int32_t a = part[2 * w], b = part[2 * w + 1];
+        if (w < wv) {
+          pre_n += a;
+          pre_l += b;
+        }
+        tot_n += a;
+        tot_l += b;
+      }
+    }
+    if (len > 0) {
+      const int32_t slot = nseg + pre_n + __popcll(nz & lt_mask);
+      const int32_t start = run + pre_l + incl - len;
+      seg[slot] = make_int2(w0 - start, pack_kp(kx, i));
+      segp[slot] = start;
+    }
+    nseg += tot_n;
+    run += tot_l;
+    if constexpr (NW > 1) __syncthreads();
+  }
+  if (tid == 0) segp[nseg] = run;
+  nseg_out = nseg;
+  total_out = run;
+}
+
+// Walk entries [beg, end) of the concatenated sequence with one wavefront,
+// 64 consecutive entries per step. The segment of each lane comes from the
+// segment starts inside the step, flagged in LDS and read back as a ballot.
+template <typename T, int SLOTS, int MAXM>
+__device__ __forceinline__ void tri_walk(const int32_t *__restrict__ up_col,
+                                         TriLds<T, SLOTS, MAXM> &L, int32_t *flg, int32_t nseg,
+                                         int32_t beg, int32_t end, int32_t ku,
+                                         typename SumT<T>::type &accu, int64_t &cntu) {
+  using S = SumT<T>;
+  constexpr int kShift = 32 - __builtin_ctz(SLOTS);
+  constexpr int32_t kPosMask = (1 << kPosBits) - 1;
+  if (beg >= end) return;
+  const int lane = threadIdx.x & 63;
+  const unsigned long long le_mask = ~0ull >> (63 - lane);
+  // s0: segment holding entry beg (largest s with segp[s] <= beg)
+  int32_t s0 = 0;
+  {
+    int32_t hi = nseg;
+    while (hi - s0 > 1) {
+      const int32_t mid = (s0 + hi) >> 1;
+      if (L.segp[mid] <= beg) s0 = mid; else hi = mid;
+    }
+  }
+  for (int32_t c = beg; c < end; c += 64) {
+    // flag the starts of segments s0+1 .. s0+64 that fall inside this step;
+    // segp[nseg] = total closes the last segment. p == 64 means a segment
+    // starts at the next step; lanes past nseg take p = 65 (no segment).
+    const int32_t s = s0 + 1 + lane;
+    const int32_t p = (s <= nseg) ? L.segp[s] - c : 65;
+    if (p < 64) flg[p] = 1;
+    wave_sync();
+    const int32_t f = flg[lane];
+    flg[lane] = 0;
+    const unsigned long long starts = __ballot(f != 0);
+    const int32_t sg = s0 + __popcll(starts & le_mask);
+    s0 += __popcll(starts) + (int32_t)(__ballot(p == 64) != 0ull);
+    const int32_t idx = c + lane;
+    if (idx < end) {
+      const int2 sv = L.seg[sg];
+      const int32_t x = up_col[sv.x + idx];
+      uint32_t h = hash32((uint32_t)x) >> kShift;
+      int2 e;
+      while ((e = L.htab[h]).x != x && e.x != -1) h = (h + 1) & (SLOTS - 1);
+      if (e.x == x) {
+        const T dl = tri_delta<T>(ku + unpack_k(sv.y) + unpack_k(e.y));
+        S::add_term(accu, dl);
+        ++cntu;
+        Credit<T>::add(L.acc, L.cnt, e.y & kPosMask, dl);
+        Credit<T>::add(L.acc, L.cnt, sv.y & kPosMask, dl);
+      }
+    }
+    wave_sync();
+  }
+}
+
+template <typename T, int SLOTS, int MAXM>
+__device__ __forceinline__ void tri_clear(TriLds<T, SLOTS, MAXM> &L, int32_t m, int tid, int nt) {
+  for (int i = tid; i < SLOTS; i += nt) L.htab[i] = make_int2(-1, 0);
+  for (int i = tid; i < m; i += nt) {
+    L.acc[i] = 0ull;
+    if constexpr (!Credit<T>::kPacked) L.cnt[i] = 0;
+  }
+}
+
+template <typename T, int SLOTS, int MAXM>
+__device__ __forceinline__ void tri_store(const TriLds<T, SLOTS, MAXM> &L, int32_t u0, int32_t m,
+                                          int tid, int nt, long long *Y, int32_t *YT) {
+  for (int i = tid; i < m; i += nt) {
+    long long y;
+    int32_t yt;
+    Credit<T>::load(L.acc, L.cnt, i, y, yt);
+    Y[u0 + i] = y;
+    YT[u0 + i] = yt;
+  }
+}
+
+// One node u per wavefront (short up(u)); WPB wavefronts per workgroup, each
+// with its own LDS state.
 template <typename T, int SLOTS, int MAXM, int WPB>
-__global__ __launch_bounds__(64 * WPB) void k_tri_hash(
+__global__ __launch_bounds__(64 * WPB) void k_tri_wave(
     const int32_t *__restrict__ up_ptr, const int32_t *__restrict__ up_col,
     const int32_t *__restrict__ deg, const int32_t *__restrict__ nodes, int64_t count,
     long long *__restrict__ Y, int32_t *__restrict__ YT, void *__restrict__ Z,
     int64_t *__restrict__ ZT) {
   using S = SumT<T>;
   using Acc = typename S::type;
-  constexpr int U = 4;  // entries per lane per step (independent loads in flight)
-  __shared__ int32_t hkey_s[WPB][SLOTS];
-  __shared__ int2 hval_s[WPB][SLOTS];  // (position in up(u), degree)
-  __shared__ int32_t seg_w0_s[WPB][MAXM];
-  __shared__ int32_t seg_kw_s[WPB][MAXM];
-  __shared__ int32_t seg_pos_s[WPB][MAXM];
-  __shared__ int32_t seg_p_s[WPB][MAXM + 1];
-  __shared__ unsigned long long acc_s[WPB][MAXM];
-  __shared__ int32_t accT_s[WPB][MAXM];
+  __shared__ TriLds<T, SLOTS, MAXM> lds[WPB];
+  __shared__ int32_t flg_s[WPB][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  int32_t *hkey = hkey_s[wv];
-  int2 *hval = hval_s[wv];
-  int32_t *seg_w0 = seg_w0_s[wv], *seg_kw = seg_kw_s[wv], *seg_pos = seg_pos_s[wv];
-  int32_t *seg_p = seg_p_s[wv];
-  unsigned long long *acc = acc_s[wv];
-  int32_t *accT = accT_s[wv];
-  constexpr int kShift = 32 - __builtin_ctz(SLOTS);
-  const unsigned long long lane_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const int64_t wave = (int64_t)blockIdx.x * WPB + wv;
+  TriLds<T, SLOTS, MAXM> &L = lds[wv];
+  int32_t *flg = flg_s[wv];
+  flg[lane] = 0;
   const int64_t nwaves = (int64_t)gridDim.x * WPB;
-  for (int64_t it = wave; it < count; it += nwaves) {
+  for (int64_t it = (int64_t)blockIdx.x * WPB + wv; it < count; it += nwaves) {
     const int32_t u = nodes[it];
     const int32_t u0 = up_ptr[u], m = up_ptr[u + 1] - u0, ku = deg[u];
-    for (int i = lane; i < SLOTS; i += 64) hkey[i] = -1;
-    for (int i = lane; i < m; i += 64) {
-      acc[i] = 0ull;
-      accT[i] = 0;
-    }
+    tri_clear(L, m, lane, 64);
     wave_sync();
-    // hash up(u) with each neighbour's degree; compact the non-empty up(w)
-    // lists into segments
-    int32_t nseg = 0, run = 0;
-    for (int c = 0; c < m; c += 64) {
-      const int i = c + lane;
-      int32_t x = 0, w0 = 0, len = 0, kx = 0;
-      if (i < m) {
-        x = up_col[u0 + i];
-        w0 = up_ptr[x];
-        len = up_ptr[x + 1] - w0;
-        kx = deg[x];
-        uint32_t h = hash32((uint32_t)x) >> kShift;
-        while (atomicCAS(&hkey[h], -1, x) != -1) h = (h + 1) & (SLOTS - 1);
-        hval[h] = make_int2(i, kx);
-      }
-      const unsigned long long nz = __ballot(len > 0);
-      int32_t incl = len;
-      for (int off = 1; off < 64; off <<= 1) {
-        const int32_t y = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += y;
-      }
-      if (len > 0) {
-        const int slot = nseg + __popcll(nz & lane_mask);
-        seg_w0[slot] = w0;
-        seg_kw[slot] = kx;
-        seg_pos[slot] = i;
-        seg_p[slot] = run + incl - len;
-      }
-      nseg += __popcll(nz);
-      run += __shfl(incl, 63, 64);
-    }
-    if (lane == 0) seg_p[nseg] = run;
+    int32_t nseg, total;
+    tri_setup<SLOTS, 64>(up_ptr, up_col, deg, u0, m, lane, L.htab, L.seg, L.segp, nullptr, nseg,
+                         total);
     wave_sync();
-    const int32_t total = run;
     Acc accu = Acc();
     int64_t cntu = 0;
-    for (int32_t base = 0; base < total; base += 64 * U) {
-      int32_t xs[U], sg[U];
-#pragma unroll
-      for (int q = 0; q < U; ++q) {
-        const int32_t idx = base + q * 64 + lane;
-        xs[q] = -2;
-        sg[q] = 0;
-        if (idx < total) {
-          int32_t lo = 0, hi = nseg;  // largest s with seg_p[s] <= idx
-          while (hi - lo > 1) {
-            const int32_t mid = (lo + hi) >> 1;
-            if (seg_p[mid] <= idx) lo = mid; else hi = mid;
-          }
-          sg[q] = lo;
-          xs[q] = up_col[seg_w0[lo] + (idx - seg_p[lo])];
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < U; ++q) {
-        const int32_t x = xs[q];
-        if (x < 0) continue;
-        uint32_t h = hash32((uint32_t)x) >> kShift;
-        int32_t key;
-        while ((key = hkey[h]) != x && key != -1) h = (h + 1) & (SLOTS - 1);
-        if (key == x) {
-          const int2 pv = hval[h];
-          const T dl = tri_delta<T>(ku + seg_kw[sg[q]] + pv.y);
-          const unsigned long long f = (unsigned long long)to_fix(dl);
-          S::add_term(accu, dl);
-          ++cntu;
-          atomicAdd(&acc[pv.x], f);
-          atomicAdd(&accT[pv.x], 1);
-          atomicAdd(&acc[seg_pos[sg[q]]], f);
-          atomicAdd(&accT[seg_pos[sg[q]]], 1);
-        }
-      }
-    }
-    wave_sync();
+    tri_walk<T, SLOTS, MAXM>(up_col, L, flg, nseg, 0, total, ku, accu, cntu);
     accu = wave_sum(accu);
     cntu = wave_sum_i64(cntu);
     if (lane == 0) {
       S::store(accu, Z, u);
       ZT[u] = cntu;
     }
-    for (int i = lane; i < m; i += 64) {
-      Y[u0 + i] = (long long)acc[i];
-      YT[u0 + i] = accT[i];
-    }
+    tri_store(L, u0, m, lane, 64, Y, YT);
     wave_sync();
+  }
+}
+
+// One node u per workgroup of WPB wavefronts sharing one LDS state; each
+// wavefront walks a contiguous share of the sequence.
+template <typename T, int SLOTS, int MAXM, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_tri_block(
+    const int32_t *__restrict__ up_ptr, const int32_t *__restrict__ up_col,
+    const int32_t *__restrict__ deg, const int32_t *__restrict__ nodes, int64_t count,
+    long long *__restrict__ Y, int32_t *__restrict__ YT, void *__restrict__ Z,
+    int64_t *__restrict__ ZT) {
+  using S = SumT<T>;
+  using Acc = typename S::type;
+  constexpr int NT = 64 * WPB;
+  __shared__ TriLds<T, SLOTS, MAXM> L;
+  __shared__ int32_t flg_s[WPB][64];
+  __shared__ int32_t part[2 * WPB];
+  __shared__ Acc sh_acc[WPB];
+  __shared__ int64_t sh_cnt[WPB];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  int32_t *flg = flg_s[wv];
+  flg[lane] = 0;
+  for (int64_t it = blockIdx.x; it < count; it += gridDim.x) {
+    const int32_t u = nodes[it];
+    const int32_t u0 = up_ptr[u], m = up_ptr[u + 1] - u0, ku = deg[u];
+    tri_clear(L, m, tid, NT);
+    __syncthreads();
+    int32_t nseg, total;
+    tri_setup<SLOTS, NT>(up_ptr, up_col, deg, u0, m, tid, L.htab, L.seg, L.segp, part, nseg,
+                         total);
+    __syncthreads();
+    // contiguous shares, multiples of 64 entries
+    const int32_t steps = (total + 63) >> 6;
+    const int32_t beg = (int32_t)(((int64_t)steps * wv / WPB) << 6);
+    const int32_t fin = (int32_t)(((int64_t)steps * (wv + 1) / WPB) << 6);
+    Acc accu = Acc();
+    int64_t cntu = 0;
+    tri_walk<T, SLOTS, MAXM>(up_col, L, flg, nseg, beg, fin < total ? fin : total, ku, accu,
+                             cntu);
+    accu = wave_sum(accu);
+    cntu = wave_sum_i64(cntu);
+    if (lane == 0) {
+      sh_acc[wv] = accu;
+      sh_cnt[wv] = cntu;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      Acc a = sh_acc[0];
+      int64_t cs = sh_cnt[0];
+      for (int w = 1; w < WPB; ++w) {
+        acc_merge(a, sh_acc[w]);
+        cs += sh_cnt[w];
+      }
+      S::store(a, Z, u);
+      ZT[u] = cs;
+    }
+    tri_store(L, u0, m, tid, NT, Y, YT);
+    __syncthreads();
   }
 }
 
@@ -269,16 +438,16 @@ static hipError_t tri_impl(const Graph &g, const int32_t *const *lists, const in
   hipLaunchKernelGGL(k_tri_zero<T>, dim3(cap_blocks((g.n + 255) / 256, 1 << 16)), dim3(256), 0,
                      st, g.up_ptr, g.n, Y, YT, Z, ZT, kTriLongMin);
   if (counts[0] > 0)
-    hipLaunchKernelGGL((k_tri_hash<T, 128, 64, 4>), dim3(cap_blocks((counts[0] + 3) / 4, 1 << 20)),
+    hipLaunchKernelGGL((k_tri_wave<T, 128, 64, 4>), dim3(cap_blocks((counts[0] + 3) / 4, 1 << 20)),
                        dim3(256), 0, st, g.up_ptr, g.up_col, g.deg, lists[0], counts[0], Y, YT,
                        Z, ZT);
   if (counts[1] > 0)
-    hipLaunchKernelGGL((k_tri_hash<T, 1024, 512, 2>), dim3(cap_blocks((counts[1] + 1) / 2, 1 << 20)),
-                       dim3(128), 0, st, g.up_ptr, g.up_col, g.deg, lists[1], counts[1], Y, YT,
+    hipLaunchKernelGGL((k_tri_block<T, 1024, 512, 8>), dim3(cap_blocks(counts[1], 1 << 20)),
+                       dim3(512), 0, st, g.up_ptr, g.up_col, g.deg, lists[1], counts[1], Y, YT,
                        Z, ZT);
   if (counts[2] > 0)
-    hipLaunchKernelGGL((k_tri_hash<T, 4096, 2048, 1>), dim3(cap_blocks(counts[2], 1 << 20)),
-                       dim3(64), 0, st, g.up_ptr, g.up_col, g.deg, lists[2], counts[2], Y, YT,
+    hipLaunchKernelGGL((k_tri_block<T, 4096, 2048, 16>), dim3(cap_blocks(counts[2], 1 << 20)),
+                       dim3(1024), 0, st, g.up_ptr, g.up_col, g.deg, lists[2], counts[2], Y, YT,
                        Z, ZT);
   if (counts[3] > 0)
     hipLaunchKernelGGL(k_tri_long<T>, dim3(cap_blocks(counts[3], 1 << 20)), dim3(64), 0, st,

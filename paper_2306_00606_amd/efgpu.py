@@ -35,8 +35,14 @@ EXPORTS = [
     "ef_last_error", "ef_version", "ef_device_count", "ef_validate_csr", "ef_graph_load_csr",
     "ef_graph_from_edges", "ef_graph_free", "ef_graph_info_get", "ef_compute", "ef_topk",
     "ef_stats", "ef_batch_create", "ef_batch_autotune", "ef_batch_compute",
-    "ef_batch_stats_get", "ef_batch_free",
+    "ef_batch_stats_get", "ef_batch_free", "ef_surrogate_create", "ef_surrogate_free",
+    "ef_surrogate_get_params", "ef_surrogate_set_params", "ef_surrogate_save",
+    "ef_surrogate_load", "ef_features", "ef_surrogate_gradients", "ef_surrogate_train",
+    "ef_surrogate_predict", "ef_topk_surrogate",
 ]
+
+N_FEATURES = 16
+N_PARAMS = 5313
 
 
 class EFError(RuntimeError):
@@ -77,6 +83,31 @@ class BatchStats(ctypes.Structure):
         d = {f: getattr(self, f) for f, _ in self._fields_}
         d["tune_ms"] = list(self.tune_ms)
         return d
+
+
+class TrainCfg(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("epochs", ctypes.c_int32), ("batch", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("weight_decay", ctypes.c_float),
+                ("val_fraction", ctypes.c_float), ("patience", ctypes.c_int32)]
+
+
+class TrainReport(ctypes.Structure):
+    _fields_ = [("epochs_run", ctypes.c_int32), ("train_loss", ctypes.c_float),
+                ("val_loss", ctypes.c_float), ("train_ms", ctypes.c_float),
+                ("rows", ctypes.c_int64), ("val_rows", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class JudgeReport(ctypes.Structure):
+    _fields_ = [("candidates", ctypes.c_int32), ("sample", ctypes.c_int32),
+                ("spearman", ctypes.c_float), ("fallback", ctypes.c_int32),
+                ("t_predict_ms", ctypes.c_float), ("t_rescore_ms", ctypes.c_float),
+                ("t_judge_ms", ctypes.c_float)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 _lib = None
@@ -123,6 +154,19 @@ def lib():
     L.ef_batch_compute.argtypes = [vp, ctypes.c_int, vp, vp, vp, u32, vp]
     L.ef_batch_stats_get.argtypes = [vp, ctypes.POINTER(BatchStats)]
     L.ef_batch_free.argtypes = [vp]
+    L.ef_surrogate_create.argtypes = [ctypes.c_uint64, ctypes.POINTER(vp)]
+    L.ef_surrogate_free.argtypes = [vp]
+    L.ef_surrogate_get_params.argtypes = [vp, vp, vp, vp]
+    L.ef_surrogate_set_params.argtypes = [vp, vp, vp, vp]
+    L.ef_surrogate_save.argtypes = [vp, ctypes.c_char_p]
+    L.ef_surrogate_load.argtypes = [vp, ctypes.c_char_p]
+    L.ef_features.argtypes = [vp, vp, vp, u32, vp]
+    L.ef_surrogate_gradients.argtypes = [vp, vp, vp, i64, vp, vp, vp]
+    L.ef_surrogate_train.argtypes = [vp, vp, vp, i64, ctypes.POINTER(TrainCfg),
+                                     ctypes.POINTER(TrainReport), vp]
+    L.ef_surrogate_predict.argtypes = [vp, vp, vp, u32, vp]
+    L.ef_topk_surrogate.argtypes = [vp, vp, i32, i32, i32, ctypes.c_float, ctypes.c_uint64, vp,
+                                    vp, ctypes.POINTER(JudgeReport), vp]
     for name in EXPORTS[2:]:
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -264,6 +308,13 @@ class Graph:
                              _stream_ptr(stream)))
         return nodes, ef
 
+    def features(self):
+        """Raw per-node features (n x 16, float32) and ln N (float32)."""
+        X = np.zeros((max(self.n, 1), N_FEATURES), np.float32)
+        L = np.zeros(max(self.n, 1), np.float32)
+        _check(lib().ef_features(self._h, X.ctypes.data, L.ctypes.data, 0, _stream_ptr(None)))
+        return X[:self.n], L[:self.n]
+
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
             lib().ef_graph_free(self._h)
@@ -357,3 +408,80 @@ class Batch:
 
     def __exit__(self, *a):
         self.close()
+
+
+class Surrogate:
+    """The learned EF surrogate (handle ``ef_surrogate``)."""
+
+    def __init__(self, seed: int = 0):
+        self._h = ctypes.c_void_p()
+        _check(lib().ef_surrogate_create(int(seed), ctypes.byref(self._h)))
+
+    def params(self):
+        P = np.zeros(N_PARAMS, np.float32)
+        m = np.zeros(N_FEATURES, np.float32)
+        s = np.zeros(N_FEATURES, np.float32)
+        _check(lib().ef_surrogate_get_params(self._h, P.ctypes.data, m.ctypes.data, s.ctypes.data))
+        return P, m, s
+
+    def set_params(self, P=None, mean=None, inv_std=None):
+        arrs = [None if a is None else np.ascontiguousarray(a, np.float32) for a in (P, mean, inv_std)]
+        _check(lib().ef_surrogate_set_params(self._h, *[None if a is None else a.ctypes.data
+                                                         for a in arrs]))
+
+    def save(self, path):
+        _check(lib().ef_surrogate_save(self._h, str(path).encode()))
+
+    def load(self, path):
+        _check(lib().ef_surrogate_load(self._h, str(path).encode()))
+
+    def gradients(self, X, y):
+        X = np.ascontiguousarray(X, np.float32)
+        y = np.ascontiguousarray(y, np.float32)
+        g = np.zeros(N_PARAMS, np.float32)
+        loss = ctypes.c_float()
+        _check(lib().ef_surrogate_gradients(self._h, X.ctypes.data, y.ctypes.data, len(y),
+                                            g.ctypes.data, ctypes.byref(loss), _stream_ptr(None)))
+        return g, float(loss.value)
+
+    def train(self, X, y, lr=3e-3, epochs=30, batch=4096, seed=0, weight_decay=0.0,
+              val_fraction=0.05, patience=4):
+        X = np.ascontiguousarray(X, np.float32)
+        y = np.ascontiguousarray(y, np.float32)
+        cfg = TrainCfg(lr, epochs, batch, seed, weight_decay, val_fraction, patience)
+        rep = TrainReport()
+        _check(lib().ef_surrogate_train(self._h, X.ctypes.data, y.ctypes.data, len(y),
+                                        ctypes.byref(cfg), ctypes.byref(rep), _stream_ptr(None)))
+        return rep.as_dict()
+
+    def predict(self, graph: Graph, out=None, stream=None):
+        if out is None:
+            ef = np.zeros(max(graph.n, 1), np.float64)
+            _check(lib().ef_surrogate_predict(self._h, graph._h, ef.ctypes.data, 0,
+                                              _stream_ptr(stream)))
+            return ef[:graph.n]
+        _check(lib().ef_surrogate_predict(self._h, graph._h, out.data_ptr(), EF_OUT_DEVICE,
+                                          _stream_ptr(stream)))
+        return out
+
+    def topk(self, graph: Graph, k: int, rerank_factor: int = 4, judge_sample: int = 4096,
+             min_spearman: float = 0.98, seed: int = 0):
+        nodes = np.zeros(max(k, 1), np.int32)
+        ef = np.zeros(max(k, 1), np.float64)
+        rep = JudgeReport()
+        _check(lib().ef_topk_surrogate(graph._h, self._h, int(k), int(rerank_factor),
+                                       int(judge_sample), float(min_spearman), int(seed),
+                                       nodes.ctypes.data, ef.ctypes.data, ctypes.byref(rep),
+                                       _stream_ptr(None)))
+        return nodes[:k], ef[:k], rep.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().ef_surrogate_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -312,3 +312,57 @@ def test_planted_mistakes_are_caught(name):
         subprocess.run(["gcc", "-O1", "-std=c11", "-fPIC", "-shared", "-fopenmp", c, "-lm",
                         "-o", so], check=True)
         assert not _quick_pin_suite(so), f"mutant {name} survived the pins"
+
+
+# --------------------------------------------------------------------------
+# The surrogate MLP oracle: hand-written gradients pinned by finite differences
+# --------------------------------------------------------------------------
+
+def test_mlp_oracle_gradients_match_finite_differences():
+    from oracle import mlp_ref
+    rs = np.random.default_rng(3)
+    p = mlp_ref.init_params(1)
+    p["b1"] = rs.normal(0, 0.1, 64)
+    p["b2"] = rs.normal(0, 0.1, 64)
+    p["b3"] = np.array([0.3])
+    X = rs.normal(0, 1, (7, 16))
+    t = rs.normal(0, 1, 7)
+    loss, g = mlp_ref.loss_and_grads(p, X, t)
+    h = 1e-6
+    for name in ("W1", "b1", "W2", "b2", "w3", "b3"):
+        flat = p[name].reshape(-1)
+        for idx in rs.choice(flat.size, min(6, flat.size), replace=False):
+            old = flat[idx]
+            flat[idx] = old + h
+            lp, _ = mlp_ref.loss_and_grads(p, X, t)
+            flat[idx] = old - h
+            lm, _ = mlp_ref.loss_and_grads(p, X, t)
+            flat[idx] = old
+            fd = (lp - lm) / (2 * h)
+            an = g[name].reshape(-1)[idx]
+            assert abs(fd - an) <= 1e-6 * max(1.0, abs(fd)), (name, idx, fd, an)
+
+
+def test_mlp_oracle_gelu_and_bf16_rounding():
+    from oracle import mlp_ref
+    import math
+    # gelu(0) = 0, gelu(x) -> x for large x, gelu(-x) -> 0; derivative at 0 is 1/2
+    assert mlp_ref.gelu(np.array([0.0]))[0] == 0.0
+    assert abs(mlp_ref.gelu(np.array([10.0]))[0] - 10.0) < 1e-12
+    assert abs(mlp_ref.gelu(np.array([-10.0]))[0]) < 1e-12
+    assert abs(mlp_ref.gelu_grad(np.array([0.0]))[0] - 0.5) < 1e-15
+    assert abs(mlp_ref.gelu(np.array([1.0]))[0] - 0.5 * (1 + math.erf(1 / math.sqrt(2)))) < 1e-15
+    # bfloat16 keeps 8 significant bits, ties to even
+    assert mlp_ref.bf16_round(np.array([1.0]))[0] == 1.0
+    assert mlp_ref.bf16_round(np.array([1.0 + 2 ** -8]))[0] == 1.0          # tie -> even
+    assert mlp_ref.bf16_round(np.array([1.0 + 3 * 2 ** -8]))[0] == 1.0 + 2 ** -6
+    assert mlp_ref.bf16_round(np.array([-3.0]))[0] == -3.0
+
+
+def test_spearman_reference():
+    from oracle import mlp_ref
+    from scipy.stats import spearmanr
+    rs = np.random.default_rng(0)
+    a = rs.integers(0, 20, 300).astype(float)   # with ties
+    b = a + rs.normal(0, 3, 300)
+    assert abs(mlp_ref.spearman(a, b) - spearmanr(a, b).correlation) < 1e-12
