@@ -96,4 +96,79 @@ template <typename T> __device__ __forceinline__ T tri_delta(int32_t sigma) {
 
 __device__ __forceinline__ uint32_t hash32(uint32_t x) { return x * 2654435761u; }
 
+// ---------------------------------------------------------------------------
+// Walking a concatenation of variable-length lists ("segments") with one
+// wavefront, 64 consecutive entries per step. segp[s] is the first
+// concatenated index of segment s (strictly increasing: no empty segments),
+// segp[nseg] = total.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// segment holding entry idx (largest s < nseg with segp[s] <= idx), idx < total
+__device__ __forceinline__ int32_t seg_find(const int32_t *segp, int32_t nseg, int32_t idx) {
+  int32_t lo = 0, hi = nseg;
+  while (hi - lo > 1) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (segp[mid] <= idx) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// One step at entries c .. c+63 with s0 the segment holding entry c: returns
+// the segment of this lane's entry c + lane (meaningful for c + lane < total)
+// and advances s0 to the segment holding entry c + 64. flg is this
+// wavefront's 64-word LDS scratch, all zero on entry and on return. The
+// starts of segments s0+1 .. s0+64 inside the step are flagged in LDS and
+// read back as a ballot; p == 64 marks a start at the next step, lanes past
+// nseg take p = 65 (no segment).
+__device__ __forceinline__ int32_t seg_step(const int32_t *segp, int32_t nseg, int32_t c,
+                                            int32_t &s0, int32_t *flg) {
+  const int lane = threadIdx.x & 63;
+  const unsigned long long le_mask = ~0ull >> (63 - lane);
+  const int32_t s = s0 + 1 + lane;
+  const int32_t p = (s <= nseg) ? segp[s] - c : 65;
+  if (p < 64) flg[p] = 1;
+  wave_sync();
+  const int32_t f = flg[lane];
+  flg[lane] = 0;
+  const unsigned long long starts = __ballot(f != 0);
+  const int32_t sg = s0 + __popcll(starts & le_mask);
+  s0 += __popcll(starts) + (int32_t)(__ballot(p == 64) != 0ull);
+  return sg;
+}
+
+// Exclusive scan of one int32 per thread over NT threads (one wavefront, or
+// a workgroup of NT/64 wavefronts with `part` = NT/64 ints of LDS); returns
+// the exclusive prefix and the group total. Workgroup form: every thread
+// must call it (it synchronises twice).
+template <int NT>
+__device__ __forceinline__ int32_t group_excl_scan(int32_t x, int32_t *part, int32_t &total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int32_t incl = x;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int32_t y = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += y;
+  }
+  if constexpr (NT == 64) {
+    total = __shfl(incl, 63, 64);
+    return incl - x;
+  } else {
+    if (lane == 63) part[wv] = incl;
+    __syncthreads();
+    int32_t pre = 0, tot = 0;
+    for (int w = 0; w < NT / 64; ++w) {
+      const int32_t a = part[w];
+      if (w < wv) pre += a;
+      tot += a;
+    }
+    __syncthreads();
+    total = tot;
+    return pre + incl - x;
+  }
+}
+
 }  // namespace efi

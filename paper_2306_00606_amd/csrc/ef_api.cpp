@@ -214,7 +214,8 @@ ef_status ef_graph_free(ef_graph *h) {
     (void)hipFree(g.col_idx);
   }
   void *arrays[] = {g.deg, g.src, g.rev, g.adj2, g.asum, g.up_ptr, g.up_col, g.tslot,
-                    g.tri_list[0], g.tri_list[1], g.tri_list[2], g.tri_list[3], g.d_counters};
+                    g.tri_list[0], g.tri_list[1], g.tri_list[2], g.tri_list[3], g.fin_list,
+                    g.ps_list[0], g.ps_list[1], g.ps_list[2], g.ps_list[3], g.d_counters};
   for (void *p : arrays)
     if (p) (void)hipFree(p);
   for (auto &b : g.ws)
@@ -355,7 +356,7 @@ ef_status ef_graph_load_csr(int32_t n, int64_t nnz, const int32_t *row_ptr,
   inf.nnz = nnz;
   inf.max_degree = kmax;
   inf.up_arcs = nnz / 2;
-  std::vector<int32_t> tri[4];
+  std::vector<int32_t> tri[4], fin;
   for (int32_t v = 0; v < n; ++v) {
     const int64_t k = g.h_deg[v];
     const int32_t up = h_up_ptr[v + 1] - h_up_ptr[v];
@@ -381,6 +382,7 @@ ef_status ef_graph_load_csr(int32_t n, int64_t nnz, const int32_t *row_ptr,
       const int bin = up <= kTriBin0 ? 0 : up <= kTriBin1 ? 1 : up <= kTriBin2 ? 2 : 3;
       tri[bin].push_back(v);
     }
+    if (k > kFinGroupMax) fin.push_back(v);
   }
   // longest lists first
   auto by_up = [&](int32_t a, int32_t b) {
@@ -391,15 +393,22 @@ ef_status ef_graph_load_csr(int32_t n, int64_t nnz, const int32_t *row_ptr,
     g.n_tri[bin] = (int64_t)tri[bin].size();
     ALLOC(g.tri_list[bin], sizeof(int32_t) * std::max<size_t>(tri[bin].size(), 1), "triangle list");
   }
+  std::sort(fin.begin(), fin.end(), [&](int32_t a, int32_t b) {
+    return g.h_deg[a] != g.h_deg[b] ? g.h_deg[a] > g.h_deg[b] : a < b;
+  });
+  g.n_fin = (int64_t)fin.size();
+  ALLOC(g.fin_list, sizeof(int32_t) * std::max<size_t>(fin.size(), 1), "finalize list");
 #undef ALLOC
   hipError_t e = hipSuccess;
   for (int bin = 0; bin < 4 && e == hipSuccess; ++bin)
     if (!tri[bin].empty())
       e = hipMemcpy(g.tri_list[bin], tri[bin].data(), sizeof(int32_t) * tri[bin].size(),
                     hipMemcpyHostToDevice);
+  if (e == hipSuccess && !fin.empty())
+    e = hipMemcpy(g.fin_list, fin.data(), sizeof(int32_t) * fin.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     ef_graph_free(h);
-    return hip_status(e, "upload triangle lists");
+    return hip_status(e, "upload node lists");
   }
   *out = h;
   return EF_OK;
@@ -639,7 +648,7 @@ extern "C" ef_status ef_compute(ef_graph *h, ef_algo algo, ef_prec prec, const i
   if ((s = ws_ensure(g, WS_REC, tsz * (size_t)kRecEntries * (size_t)std::max<int64_t>(b.n_tiles, 1),
                      "super-tile records")) != EF_OK)
     return s;
-  if ((s = ws_ensure(g, WS_FLAG, sizeof(int32_t) * (size_t)std::max<int32_t>(n_work, 1),
+  if ((s = ws_ensure(g, WS_FLAG, (sizeof(int32_t) + 1) * (size_t)std::max<int32_t>(n_work, 1),
                      "flag list")) != EF_OK)
     return s;
   // outputs of the unique work list: straight into the caller's device arrays
@@ -663,51 +672,73 @@ extern "C" ef_status ef_compute(ef_graph *h, ef_algo algo, ef_prec prec, const i
   hipError_t e = launch_zero_i32(cnt, 4, st);
   if (e != hipSuccess) return hip_status(e, "clear counters");
   int32_t *flagged = (int32_t *)g.ws[WS_FLAG].p;
+  uint8_t *flag_bytes = (uint8_t *)(flagged + std::max<int32_t>(n_work, 1));
 
-  // device seed arrays
-  int32_t *d_useeds = nullptr, *d_inv = nullptr, *d_bigseeds = nullptr, *d_bigslot = nullptr;
-  std::vector<int32_t> bigseeds, bigslot;
-  if (per_seed) {
-    const std::vector<int32_t> *work = &useeds;
-    std::vector<int32_t> iota;
-    if (all) {
-      iota.resize((size_t)g.n);
-      std::iota(iota.begin(), iota.end(), 0);
-      work = &iota;
-    }
-    bigslot.assign(work->size(), -1);
-    for (size_t i = 0; i < work->size(); ++i)
-      if (g.h_deg[(*work)[i]] > kSeedHashMax) {
-        bigslot[i] = (int32_t)bigseeds.size();
-        bigseeds.push_back((*work)[i]);
+  // device seed arrays: the unique work list (all nodes: none, position =
+  // node id), the inverse map, and output positions by seed degree bin
+  int32_t *d_useeds = nullptr, *d_inv = nullptr;
+  const int32_t *ps_lists[4] = {nullptr, nullptr, nullptr, nullptr};
+  int64_t ps_counts[4] = {0, 0, 0, 0};
+  auto seed_bin = [](int32_t k) {
+    return k <= kSeedBin0 ? 0 : k <= kSeedBin1 ? 1 : k <= kSeedHashMax ? 2 : 3;
+  };
+  if (per_seed && all) {
+    if (!g.ps_ready) {
+      std::vector<int32_t> lst[4];
+      for (int32_t v = 0; v < g.n; ++v) lst[seed_bin(g.h_deg[v])].push_back(v);
+      for (int bin = 0; bin < 4; ++bin) {
+        // largest seeds first
+        std::stable_sort(lst[bin].begin(), lst[bin].end(),
+                         [&](int32_t a, int32_t c) { return g.h_deg[a] > g.h_deg[c]; });
+        g.n_ps[bin] = (int64_t)lst[bin].size();
+        if ((s = dev_alloc(g, (void **)&g.ps_list[bin],
+                           sizeof(int32_t) * std::max<size_t>(lst[bin].size(), 1),
+                           "seed lists")) != EF_OK)
+          return s;
+        if (!lst[bin].empty()) {
+          e = hipMemcpy(g.ps_list[bin], lst[bin].data(), sizeof(int32_t) * lst[bin].size(),
+                        hipMemcpyHostToDevice);
+          if (e != hipSuccess) return hip_status(e, "upload seed lists");
+        }
       }
-    const size_t cnt_all = work->size() * 2 + bigseeds.size() + inv.size() + 4;
+      g.ps_ready = true;
+    }
+    for (int bin = 0; bin < 4; ++bin) {
+      ps_lists[bin] = g.ps_list[bin];
+      ps_counts[bin] = g.n_ps[bin];
+    }
+  } else if (per_seed) {
+    std::vector<int32_t> lst[4];
+    for (size_t i = 0; i < useeds.size(); ++i) lst[seed_bin(g.h_deg[useeds[i]])].push_back((int32_t)i);
+    const size_t cnt_all = useeds.size() * 2 + inv.size() + 4;
     if ((s = ws_ensure(g, WS_SEEDS, sizeof(int32_t) * cnt_all, "seed lists")) != EF_OK) return s;
     d_useeds = (int32_t *)g.ws[WS_SEEDS].p;
-    d_bigslot = d_useeds + work->size();
-    d_bigseeds = d_bigslot + work->size();
-    d_inv = d_bigseeds + bigseeds.size();
-    e = hipMemcpyAsync(d_useeds, work->data(), sizeof(int32_t) * work->size(),
+    int32_t *p = d_useeds + useeds.size();
+    e = hipMemcpyAsync(d_useeds, useeds.data(), sizeof(int32_t) * useeds.size(),
                        hipMemcpyHostToDevice, st);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(d_bigslot, bigslot.data(), sizeof(int32_t) * bigslot.size(),
-                         hipMemcpyHostToDevice, st);
-    if (e == hipSuccess && !bigseeds.empty())
-      e = hipMemcpyAsync(d_bigseeds, bigseeds.data(), sizeof(int32_t) * bigseeds.size(),
-                         hipMemcpyHostToDevice, st);
+    for (int bin = 0; bin < 4; ++bin) {
+      ps_lists[bin] = p;
+      ps_counts[bin] = (int64_t)lst[bin].size();
+      if (e == hipSuccess && !lst[bin].empty())
+        e = hipMemcpyAsync(p, lst[bin].data(), sizeof(int32_t) * lst[bin].size(),
+                           hipMemcpyHostToDevice, st);
+      p += lst[bin].size();
+    }
+    d_inv = p;
     if (e == hipSuccess && !inv.empty())
       e = hipMemcpyAsync(d_inv, inv.data(), sizeof(int32_t) * inv.size(), hipMemcpyHostToDevice,
                          st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);  // host vectors go out of scope
     if (e != hipSuccess) return hip_status(e, "upload seeds");
-    if (!bigseeds.empty()) {
-      const size_t words = ((size_t)g.n + 31) / 32;
-      const size_t need = sizeof(uint32_t) * words * bigseeds.size();
-      const bool fresh = g.ws[WS_BITMAP].bytes < need;
-      if ((s = ws_ensure(g, WS_BITMAP, need, "membership bitmaps")) != EF_OK) return s;
-      if (fresh) {
-        e = hipMemsetAsync(g.ws[WS_BITMAP].p, 0, g.ws[WS_BITMAP].bytes, st);
-        if (e != hipSuccess) return hip_status(e, "clear bitmaps");
-      }
+  }
+  if (per_seed && ps_counts[3] > 0) {
+    const size_t words = ((size_t)g.n + 31) / 32;
+    const size_t need = sizeof(uint32_t) * words * (size_t)ps_counts[3];
+    const bool fresh = g.ws[WS_BITMAP].bytes < need;
+    if ((s = ws_ensure(g, WS_BITMAP, need, "membership bitmaps")) != EF_OK) return s;
+    if (fresh) {
+      e = hipMemsetAsync(g.ws[WS_BITMAP].p, 0, g.ws[WS_BITMAP].bytes, st);
+      if (e != hipSuccess) return hip_status(e, "clear bitmaps");
     }
   }
 
@@ -730,15 +761,16 @@ extern "C" ef_status ef_compute(ef_graph *h, ef_algo algo, ef_prec prec, const i
     if (e != hipSuccess) return hip_status(e, "triangle pass");
     prof.mark(6);
     e = launch_finalize_cluster(g, prec, g.ws[WS_R].p, (const long long *)g.ws[WS_Y].p,
-                                (int32_t *)g.ws[WS_YT].p,
-                                g.ws[WS_Z].p, (int64_t *)g.ws[WS_ZT].p, ef_w, D_w, N_w, flagged,
-                                cnt, cnt + 1, st);
+                                (int32_t *)g.ws[WS_YT].p, g.ws[WS_Z].p, (int64_t *)g.ws[WS_ZT].p,
+                                ef_w, D_w, N_w, flag_bytes, st);
+    if (e == hipSuccess) e = launch_flag_compact(flag_bytes, n_work, flagged, cnt, st);
     if (e != hipSuccess) return hip_status(e, "finalize");
     prof.mark(7);
   } else {
-    e = launch_per_seed(g, prec, d_useeds, n_work, g.ws[WS_R].p, (uint32_t *)g.ws[WS_BITMAP].p,
-                        d_bigseeds, d_bigslot, (int32_t)bigseeds.size(), ef_w, D_w, N_w, flagged,
-                        cnt, cnt + 1, st, prof.ev(6));
+    e = launch_per_seed(g, prec, d_useeds, ps_lists, ps_counts, g.ws[WS_R].p,
+                        (uint32_t *)g.ws[WS_BITMAP].p, ef_w, D_w, N_w, flag_bytes, st,
+                        prof.ev(6));
+    if (e == hipSuccess) e = launch_flag_compact(flag_bytes, n_work, flagged, cnt, st);
     if (e != hipSuccess) return hip_status(e, "per-seed stream");
     prof.mark(7);
   }

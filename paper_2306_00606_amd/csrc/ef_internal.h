@@ -36,10 +36,13 @@ constexpr int kRecEntries = 2 * kSuper;  // row part + column part per super-til
 // (degree, position) words of the triangle pass.
 constexpr int32_t kMaxDegree = 1000000;
 constexpr int kTriBin0 = 64, kTriBin1 = 512, kTriBin2 = 2048;
+// Finalize: nodes of degree <= kFinGroupMax share wavefronts, 8 lanes each.
+constexpr int32_t kFinGroupMax = 32;
 constexpr int kTriLongMin = kTriBin2 + 1;
 
 // Per-seed stream: seeds with k <= kSeedHashMax use an LDS hash of N(s);
 // larger seeds a bitmap over all node ids in device memory.
+constexpr int kSeedBin0 = 64, kSeedBin1 = 512;
 constexpr int kSeedHashMax = 2048;
 constexpr int kSeedHashSlots = 4096;
 
@@ -95,6 +98,13 @@ struct Graph {
   std::vector<int32_t> h_up_len;
   // triangle-pass node lists (device) by |up(u)|: 2..64, 65..512, 513..4096, >4096
   int32_t *tri_list[4] = {nullptr, nullptr, nullptr, nullptr};
+  // nodes of degree > kFinGroupMax (finalized one wavefront each), by degree descending
+  int32_t *fin_list = nullptr;
+  int64_t n_fin = 0;
+  // per-seed formulation over all nodes: node ids by seed bin (built on first use)
+  int32_t *ps_list[4] = {nullptr, nullptr, nullptr, nullptr};
+  int64_t n_ps[4] = {0, 0, 0, 0};
+  bool ps_ready = false;
   int64_t n_tri[4] = {0, 0, 0, 0};
   // bin counts for the all-nodes centre set
   int64_t all_small = 0, all_mid = 0, all_big = 0, all_tiles = 0;
@@ -170,22 +180,27 @@ hipError_t launch_pairs(const Graph &g, ef_prec prec, const Bins &b, void *R, vo
 hipError_t launch_triangles(const Graph &g, ef_prec prec, long long *Y, int32_t *YT, void *Z,
                             int64_t *ZT, hipStream_t st);
 
-// per-node sums + Eq. 1 (cluster-centric). Appends cancellation-prone seeds to
-// `flagged` (count in *flag_count).
+// per-node sums + Eq. 1 (cluster-centric); per-node flag bytes in fl.
 hipError_t launch_finalize_cluster(const Graph &g, ef_prec prec, const void *R,
-                                   const long long *Y, const int32_t *YT, const void *Z, const int64_t *ZT,
-                                   double *ef, int64_t *D, int64_t *N, int32_t *flagged,
-                                   int32_t *flag_count, int32_t *fp64_count, hipStream_t st);
+                                   const long long *Y, const int32_t *YT, const void *Z,
+                                   const int64_t *ZT, double *ef, int64_t *D, int64_t *N,
+                                   uint8_t *fl, hipStream_t st);
 
-// per-seed formulation: star sums from R of the seed's own arcs, 2-hop stream,
-// then Eq. 1. seeds[i] (unique) are processed; outputs at position i.
-// Seeds with k > kSeedHashMax use the bitmaps; big_seeds lists them and
-// big_slot[i] gives seed i's bitmap (or -1).
-hipError_t launch_per_seed(const Graph &g, ef_prec prec, const int32_t *seeds, int32_t n_seeds,
-                           const void *R, uint32_t *bitmaps, const int32_t *big_seeds,
-                           const int32_t *big_slot, int32_t n_big_seeds, double *ef, int64_t *D,
-                           int64_t *N, int32_t *flagged, int32_t *flag_count,
-                           int32_t *fp64_count, hipStream_t st, hipEvent_t ev_stream_done);
+// flag bytes of positions 0..n-1 (written by the finalize and per-seed
+// kernels: bit 0 pass 2, bit 1 FP64-finalised) -> flagged list and
+// counts[0] (its length), counts[1] (FP64 count); counts are added to.
+hipError_t launch_flag_compact(const uint8_t *fl, int64_t n, int32_t *flagged, int32_t *counts,
+                               hipStream_t st);
+
+// per-seed formulation: star sums from R of the seed's own arcs, 2-hop walk,
+// then Eq. 1. seeds: the unique work list (NULL: position = node id);
+// lists[b] / counts[b]: output positions by seed degree, b = 0: k <=
+// kSeedBin0, 1: k <= kSeedBin1, 2: k <= kSeedHashMax, 3: larger (membership
+// from bitmaps: counts[3] of n bits each, in list order).
+hipError_t launch_per_seed(const Graph &g, ef_prec prec, const int32_t *seeds,
+                           const int32_t *const *lists, const int64_t *counts, const void *R,
+                           uint32_t *bitmaps, double *ef, int64_t *D, int64_t *N, uint8_t *fl,
+                           hipStream_t st, hipEvent_t ev_stream_done);
 
 // FP32C pass 2: recompute EF of flagged positions from non-negative terms.
 // seeds[pos] gives the node of output position pos (NULL: pos is the node).

@@ -380,50 +380,95 @@ __global__ __launch_bounds__(256) void k_arc_reduce(const int32_t *__restrict__ 
 // A small centre of degree k goes to the first segment size S with
 // k <= thr[S] (thr[64] = 64), so the thresholds pick the segment size.
 // ---------------------------------------------------------------------------
-// append to a global list with one atomic per wavefront (ballot + rank)
-__device__ __forceinline__ int32_t wave_append(int32_t *counter, bool pred) {
-  const unsigned long long mask = __ballot(pred);
-  if (!mask) return -1;
-  const int lane = threadIdx.x & 63;
-  const int leader = __ffsll((long long)mask) - 1;
-  int32_t base = 0;
-  if (lane == leader) base = atomicAdd(counter, __popcll(mask));
-  base = __shfl(base, leader, 64);
-  const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  return pred ? base + __popcll(mask & below) : -1;
-}
+// binning: each workgroup classifies 256 * kBinPer centres per round; ranks
+// within a bin come from wavefront ballots (and, for the big bin, a scan of
+// super-tile counts), per-wavefront counts meet in LDS, and each bin takes one
+// global atomic per workgroup and round: device-scope atomics on one address
+// serialise across the XCDs.
+constexpr int kBinPer = 8;
 
-__global__ void k_bin(const int32_t *__restrict__ deg, const int32_t *__restrict__ centres,
-                      int32_t n_centres, SmallThr thr, int32_t *__restrict__ small0,
-                      int32_t *__restrict__ small1, int32_t *__restrict__ small2,
-                      int32_t *__restrict__ small3, int32_t *__restrict__ mid,
-                      BigCentre *__restrict__ big, int32_t *__restrict__ counters) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  // every lane of a wavefront runs the same number of iterations (ballots)
-  const int64_t rounds = (n_centres + stride - 1) / stride;
-  for (int64_t r = 0; r < rounds; ++r) {
-    const int64_t i = r * stride + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    int32_t v = 0, k = 0;
-    if (i < n_centres) {
-      v = centres ? centres[i] : (int32_t)i;
-      k = deg[v];
-    }
-    const int b = (k < 2) ? -1 : k <= kSmallMax ? small_bin(k, thr) : k <= kSuper ? 4 : 5;
-    int32_t *lists[4] = {small0, small1, small2, small3};
-    for (int q = 0; q < 5; ++q) {
-      const int32_t pos = wave_append(&counters[q], b == q);
-      if (pos >= 0) {
-        if (q < 4) lists[q][pos] = v;
-        else mid[pos] = v;
+__global__ __launch_bounds__(256) void k_bin(const int32_t *__restrict__ deg,
+                                             const int32_t *__restrict__ centres,
+                                             int32_t n_centres, SmallThr thr,
+                                             int32_t *__restrict__ small0,
+                                             int32_t *__restrict__ small1,
+                                             int32_t *__restrict__ small2,
+                                             int32_t *__restrict__ small3,
+                                             int32_t *__restrict__ mid,
+                                             BigCentre *__restrict__ big,
+                                             int32_t *__restrict__ counters) {
+  // bins 0..3 small, 4 mid, 5 big (centres), 6 big (super-tiles)
+  __shared__ int32_t wcnt[4][7];
+  __shared__ int32_t gbase[7];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  constexpr int64_t kRound = 256 * kBinPer;
+  for (int64_t r0 = blockIdx.x * kRound; r0 < n_centres; r0 += (int64_t)gridDim.x * kRound) {
+    int32_t vv[kBinPer], rank[kBinPer], tpre[kBinPer], nsb[kBinPer];
+    int bb[kBinPer];
+    int32_t run[7] = {0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < kBinPer; ++j) {
+      const int64_t i = r0 + (int64_t)(j * 4 + wv) * 64 + lane;
+      int32_t v = 0, k = 0;
+      if (i < n_centres) {
+        v = centres ? centres[i] : (int32_t)i;
+        k = deg[v];
       }
-    }
-    if (b == 5) {
-      const int32_t ns = (k + kSuper - 1) / kSuper;
+      const int b = (k < 2) ? -1 : k <= kSmallMax ? small_bin(k, thr) : k <= kSuper ? 4 : 5;
+      vv[j] = v;
+      bb[j] = b;
+      rank[j] = 0;
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        const unsigned long long m = __ballot(b == q);
+        if (b == q) rank[j] = run[q] + __popcll(m & below);
+        run[q] += __popcll(m);
+      }
+      // super-tiles of big centres: exclusive scan within the wavefront
+      const int32_t ns = b == 5 ? (k + kSuper - 1) / kSuper : 0;
       const int32_t nt = ns * (ns + 1) / 2;
-      const int32_t slot = atomicAdd(&counters[5], 1);
-      const int32_t rb = atomicAdd(&counters[6], nt);
-      big[slot] = BigCentre{v, ns, (int64_t)rb};
+      int32_t incl = nt;
+      for (int off = 1; off < 64; off <<= 1) {
+        const int32_t y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
+      }
+      nsb[j] = ns;
+      tpre[j] = run[6] + incl - nt;
+      run[6] += __shfl(incl, 63, 64);
     }
+    if (lane == 0) {
+#pragma unroll
+      for (int q = 0; q < 7; ++q) wcnt[wv][q] = run[q];
+    }
+    __syncthreads();
+    if (tid < 7) {
+      const int32_t tot = wcnt[0][tid] + wcnt[1][tid] + wcnt[2][tid] + wcnt[3][tid];
+      gbase[tid] = tot ? atomicAdd(&counters[tid], tot) : 0;
+    }
+    __syncthreads();
+    int32_t off[7];
+#pragma unroll
+    for (int q = 0; q < 7; ++q) {
+      int32_t o = gbase[q];
+      for (int w = 0; w < wv; ++w) o += wcnt[w][q];
+      off[q] = o;
+    }
+#pragma unroll
+    for (int j = 0; j < kBinPer; ++j) {
+      const int b = bb[j];
+      if (b < 0) continue;
+      if (b == 5) {
+        big[off[5] + rank[j]] = BigCentre{vv[j], nsb[j], (int64_t)(off[6] + tpre[j])};
+        continue;
+      }
+      const int32_t pos = (b == 0 ? off[0] : b == 1 ? off[1] : b == 2 ? off[2] : b == 3 ? off[3]
+                                                                                      : off[4]) +
+                          rank[j];
+      int32_t *list = b == 0 ? small0 : b == 1 ? small1 : b == 2 ? small2 : b == 3 ? small3 : mid;
+      list[pos] = vv[j];
+    }
+    __syncthreads();
   }
 }
 
@@ -466,7 +511,8 @@ hipError_t launch_bin_centres(const Graph &g, const int32_t *centres, int32_t n_
                               Bins &b, hipStream_t st) {
   hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, b.counters, 8);
   if (n_centres <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_bin, dim3(capped((n_centres + 255) / 256, 65536)), dim3(256), 0, st,
+  hipLaunchKernelGGL(k_bin, dim3(capped((n_centres + 256 * kBinPer - 1) / (256 * kBinPer), 4096)),
+                     dim3(256), 0, st,
                      g.deg, centres, n_centres, b.thr, b.small[0], b.small[1], b.small[2],
                      b.small[3], b.mid, b.big, b.counters);
   if (b.n_big > 0)

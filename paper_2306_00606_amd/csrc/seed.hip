@@ -17,15 +17,18 @@ namespace efi {
 
 constexpr double kLn2 = 0.69314718055994530942;
 
-// Eq. 1 from the sums; appends cancellation-prone FP32 results to `flagged`.
+// Eq. 1 from the sums. fl[pos] receives the position's flags: bit 0 the
+// FP32 result is cancellation-prone (recomputed by pass 2), bit 1 it was
+// finalised in FP64 (more than 2^24 clusters). Flags are bytes, compacted
+// afterwards by k_flag_compact: no contended atomics here.
 template <typename T>
 __device__ __forceinline__ double finish_ef(int64_t Nn, int64_t Dd, double S, int32_t pos,
-                                           int32_t *flagged, int32_t *flag_count,
-                                           int32_t *fp64_count);
+                                           uint8_t *fl);
 
 template <>
-__device__ __forceinline__ double finish_ef<double>(int64_t Nn, int64_t Dd, double S, int32_t,
-                                                   int32_t *, int32_t *, int32_t *) {
+__device__ __forceinline__ double finish_ef<double>(int64_t Nn, int64_t Dd, double S, int32_t pos,
+                                                   uint8_t *fl) {
+  fl[pos] = 0;
   if (Dd <= 0 || Nn <= 1) return 0.0;
   const double ef = log((double)Dd) - S / (double)Dd;
   return ef > 0.0 ? ef : 0.0;
@@ -34,11 +37,14 @@ __device__ __forceinline__ double finish_ef<double>(int64_t Nn, int64_t Dd, doub
 // FP32 path: S in log2 units (double-float, passed as its double value).
 template <>
 __device__ __forceinline__ double finish_ef<float>(int64_t Nn, int64_t Dd, double S2, int32_t pos,
-                                                  int32_t *flagged, int32_t *flag_count,
-                                                  int32_t *fp64_count) {
-  if (Dd <= 0 || Nn <= 1) return 0.0;
+                                                  uint8_t *fl) {
+  if (Dd <= 0 || Nn <= 1) {
+    fl[pos] = 0;
+    return 0.0;
+  }
   double ef;
   float mu, e32;
+  uint8_t f = 0;
   if (Nn > (1LL << 24)) {
     // more than 2^24 clusters: final combination in double precision
     const double mu_d = S2 / (double)Dd;
@@ -46,44 +52,138 @@ __device__ __forceinline__ double finish_ef<float>(int64_t Nn, int64_t Dd, doubl
     ef = kLn2 * e2;
     mu = (float)mu_d;
     e32 = (float)e2;
-    atomicAdd(fp64_count, 1);
+    f |= 2;
   } else {
     const float Df = (float)Dd;
     mu = (float)S2 / Df;
     e32 = log2f(Df) - mu;
     ef = kLn2 * (double)e32;
   }
-  if (!(e32 > 0.0f) || mu > kKappaMax * e32) {
-    flagged[atomicAdd(flag_count, 1)] = pos;
-  }
+  if (!(e32 > 0.0f) || mu > kKappaMax * e32) f |= 1;
+  fl[pos] = f;
   return ef > 0.0 ? ef : 0.0;
 }
 
+// Compact the flag bytes of positions 0..n-1: positions with bit 0 go to
+// `flagged` (counts[0] of them), bit 1 is counted in counts[1]. Each
+// workgroup owns a contiguous range and takes one atomic per counter.
+__global__ __launch_bounds__(1024) void k_flag_compact(const uint8_t *__restrict__ fl, int64_t n,
+                                                       int32_t *__restrict__ flagged,
+                                                       int32_t *__restrict__ counts) {
+  __shared__ int32_t wa[16], wb[16];
+  __shared__ int32_t base_s;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = (int64_t)blockIdx.x * per;
+  const int64_t hi = lo + per < n ? lo + per : n;
+  int32_t c = 0, f = 0;
+  for (int64_t i = lo + tid; i < hi; i += 1024) {
+    const uint8_t x = fl[i];
+    c += x & 1;
+    f += (x >> 1) & 1;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    c += __shfl_xor(c, off, 64);
+    f += __shfl_xor(f, off, 64);
+  }
+  if (lane == 0) {
+    wa[wv] = c;
+    wb[wv] = f;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int32_t ct = 0, ft = 0;
+    for (int w = 0; w < 16; ++w) {
+      ct += wa[w];
+      ft += wb[w];
+    }
+    base_s = ct ? atomicAdd(&counts[0], ct) : 0;
+    if (ft) atomicAdd(&counts[1], ft);
+  }
+  __syncthreads();
+  int32_t run = base_s;
+  for (int64_t i0 = lo; i0 < hi; i0 += 1024) {
+    const int64_t i = i0 + tid;
+    const bool p = i < hi && (fl[i] & 1);
+    const unsigned long long m = __ballot(p);
+    if (lane == 0) wa[wv] = __popcll(m);
+    __syncthreads();
+    int32_t pre = 0, tot = 0;
+    for (int w = 0; w < 16; ++w) {
+      if (w < wv) pre += wa[w];
+      tot += wa[w];
+    }
+    if (p) flagged[run + pre + __popcll(m & below)] = (int32_t)i;
+    run += tot;
+    __syncthreads();
+  }
+}
+
+hipError_t launch_flag_compact(const uint8_t *fl, int64_t n, int32_t *flagged, int32_t *counts,
+                               hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 4095) / 4096;
+  if (blocks > 256) blocks = 256;
+  hipLaunchKernelGGL(k_flag_compact, dim3((unsigned)blocks), dim3(1024), 0, st, fl, n, flagged,
+                     counts);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
-// cluster-centric: one wavefront per node
+// cluster-centric finalize: G lanes per node. nodes == nullptr: nodes
+// 0..count-1 of degree <= kmax; otherwise the listed nodes.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <int G> __device__ __forceinline__ int64_t group_sum(int64_t x) {
+  for (int off = G / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, G);
+  return x;
+}
+template <int G> __device__ __forceinline__ double group_sum(double x) {
+  for (int off = G / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, G);
+  return x;
+}
+template <int G> __device__ __forceinline__ DFv group_sum(DFv x) {
+  for (int off = G / 2; off > 0; off >>= 1) {
+    DFv o;
+    o.hi = __shfl_xor(x.hi, off, G);
+    o.lo = __shfl_xor(x.lo, off, G);
+    x.add(o);
+  }
+  return x;
+}
+
+template <typename T, int G>
 __global__ __launch_bounds__(256) void k_finalize_cluster(
     const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ deg,
     const int2 *__restrict__ adj2, const int32_t *__restrict__ rev,
     const int32_t *__restrict__ tslot, const int64_t *__restrict__ asum,
     const void *__restrict__ R, const long long *__restrict__ Y, const int32_t *__restrict__ YT,
-    const void *__restrict__ Z, const int64_t *__restrict__ ZT, int32_t n,
+    const void *__restrict__ Z, const int64_t *__restrict__ ZT,
+    const int32_t *__restrict__ nodes, int64_t count, int32_t kmax,
     double *__restrict__ ef, int64_t *__restrict__ Dout, int64_t *__restrict__ Nout,
-    int32_t *__restrict__ flagged, int32_t *__restrict__ flag_count,
-    int32_t *__restrict__ fp64_count) {
+    uint8_t *__restrict__ fl) {
   using S = SumT<T>;
   using Acc = typename S::type;
-  const int lane = threadIdx.x & 63;
-  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  for (int64_t v = wave; v < n; v += nwaves) {
-    const int32_t k = deg[v], base = row_ptr[v];
-    const int64_t As = asum[v];
+  const int sub = threadIdx.x & (G - 1);
+  const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+  const int64_t ngrp = ((int64_t)gridDim.x * blockDim.x) / G;
+  // every lane of a wavefront runs the same number of rounds (group shuffles)
+  const int64_t rounds = (count + ngrp - 1) / ngrp;
+  for (int64_t r = 0; r < rounds; ++r) {
+    const int64_t it = r * ngrp + grp;
+    int32_t v = -1, k = 0;
+    if (it < count) {
+      v = nodes ? nodes[it] : (int32_t)it;
+      k = deg[v];
+      if (!nodes && k > kmax) v = -1;
+    }
+    if (v < 0) k = 0;
+    const int32_t base = v >= 0 ? row_ptr[v] : 0;
+    const int64_t As = v >= 0 ? asum[v] : 0;
     Acc sacc = Acc();
     double tfix = 0.0;  // triangle credits, 2^-40 fixed-point units
     int64_t Nn = 0, Dd = 0, Tc = 0;
-    for (int32_t e = base + lane; e < base + k; e += 64) {
+    for (int32_t e = base + sub; e < base + k; e += G) {
       const int2 ad = adj2[e];
       const int32_t a = ad.x, ka = ad.y;
       // a centre of degree 1 has no pairs: its row sums were never written
@@ -92,25 +192,25 @@ __global__ __launch_bounds__(256) void k_finalize_cluster(
       Nn += (int64_t)(k - 1) + (ka - 1);
       Dd += (int64_t)(k - 1) * (k + ka - 4) + (As - ka) + (int64_t)(ka - 1) * (ka + k - 4) +
             (asum[a] - k);
-      if (rank_less_d(a, ka, (int32_t)v, k)) {
+      if (rank_less_d(a, ka, v, k)) {
         const int32_t sl = tslot[e];
         tfix += (double)Y[sl];
         Tc += YT[sl];
       }
     }
-    sacc = wave_sum(sacc);
-    tfix = wave_sum_f64(tfix);
-    Nn = wave_sum_i64(Nn);
-    Dd = wave_sum_i64(Dd);
-    Tc = wave_sum_i64(Tc);
-    if (lane == 0) {
+    sacc = group_sum<G>(sacc);
+    tfix = group_sum<G>(tfix);
+    Nn = group_sum<G>(Nn);
+    Dd = group_sum<G>(Dd);
+    Tc = group_sum<G>(Tc);
+    if (v >= 0 && sub == 0) {
       Acc z = Acc();
       S::add_stored(z, Z, v);
       Tc += ZT[v];
       const double tri = tfix * (1.0 / 1099511627776.0) + S::value(z);
       const double Stot = S::value(sacc) + 4.0 * tri;
       Dd -= 8 * Tc;
-      ef[v] = finish_ef<T>(Nn, Dd, Stot, (int32_t)v, flagged, flag_count, fp64_count);
+      ef[v] = finish_ef<T>(Nn, Dd, Stot, v, fl);
       Dout[v] = Dd;
       Nout[v] = Nn;
     }
@@ -123,18 +223,29 @@ static unsigned cap_blocks(int64_t b, int64_t cap) {
 }
 
 hipError_t launch_finalize_cluster(const Graph &g, ef_prec prec, const void *R,
-                                   const long long *Y, const int32_t *YT, const void *Z, const int64_t *ZT,
-                                   double *ef, int64_t *D, int64_t *N, int32_t *flagged,
-                                   int32_t *flag_count, int32_t *fp64_count, hipStream_t st) {
-  const unsigned blocks = cap_blocks(((int64_t)g.n * 64 + 255) / 256, 1 << 20);
-  if (prec == EF_PREC_FP64)
-    hipLaunchKernelGGL(k_finalize_cluster<double>, dim3(blocks), dim3(256), 0, st, g.row_ptr,
-                       g.deg, g.adj2, g.rev, g.tslot, g.asum, R, Y, YT, Z, ZT, g.n, ef, D, N,
-                       flagged, flag_count, fp64_count);
-  else
-    hipLaunchKernelGGL(k_finalize_cluster<float>, dim3(blocks), dim3(256), 0, st, g.row_ptr,
-                       g.deg, g.adj2, g.rev, g.tslot, g.asum, R, Y, YT, Z, ZT, g.n, ef, D, N,
-                       flagged, flag_count, fp64_count);
+                                   const long long *Y, const int32_t *YT, const void *Z,
+                                   const int64_t *ZT, double *ef, int64_t *D, int64_t *N,
+                                   uint8_t *fl, hipStream_t st) {
+  // nodes of degree <= kFinGroupMax: 8 lanes each; the rest: one wavefront each
+  const unsigned blocks_s = cap_blocks(((int64_t)g.n * 8 + 255) / 256, 1 << 20);
+  const unsigned blocks_l = cap_blocks((g.n_fin * 64 + 255) / 256, 1 << 20);
+  if (prec == EF_PREC_FP64) {
+    hipLaunchKernelGGL((k_finalize_cluster<double, 8>), dim3(blocks_s), dim3(256), 0, st,
+                       g.row_ptr, g.deg, g.adj2, g.rev, g.tslot, g.asum, R, Y, YT, Z, ZT,
+                       nullptr, (int64_t)g.n, kFinGroupMax, ef, D, N, fl);
+    if (g.n_fin > 0)
+      hipLaunchKernelGGL((k_finalize_cluster<double, 64>), dim3(blocks_l), dim3(256), 0, st,
+                         g.row_ptr, g.deg, g.adj2, g.rev, g.tslot, g.asum, R, Y, YT, Z, ZT,
+                         g.fin_list, g.n_fin, 0, ef, D, N, fl);
+  } else {
+    hipLaunchKernelGGL((k_finalize_cluster<float, 8>), dim3(blocks_s), dim3(256), 0, st,
+                       g.row_ptr, g.deg, g.adj2, g.rev, g.tslot, g.asum, R, Y, YT, Z, ZT,
+                       nullptr, (int64_t)g.n, kFinGroupMax, ef, D, N, fl);
+    if (g.n_fin > 0)
+      hipLaunchKernelGGL((k_finalize_cluster<float, 64>), dim3(blocks_l), dim3(256), 0, st,
+                         g.row_ptr, g.deg, g.adj2, g.rev, g.tslot, g.asum, R, Y, YT, Z, ZT,
+                         g.fin_list, g.n_fin, 0, ef, D, N, fl);
+  }
   return hipGetLastError();
 }
 
@@ -165,16 +276,22 @@ __device__ int64_t block_sum_i64(int64_t x, int64_t *sh) {
 }
 
 // ---------------------------------------------------------------------------
-// per-seed formulation: star sums from R over the seed's own arcs, paths and
-// the star triangle adjustment from the 2-hop stream, membership in N(s) from
-// an LDS hash (k <= 2048) or a device bitmap.
+// per-seed formulation (the original visit of each seed's own clusters):
+//   stars a-s-b: the pair loop's row sums R over the seed's own arcs, plus the
+//     triangle adjustment for adjacent a, b (found in the 2-hop walk);
+//   paths s-a-b: the walk over the rows of every neighbour a, each entry
+//     (b, k_b) one cluster of degree k_s + k_a + k_b - 4, less 2 if b ~ s.
+// The rows of N(s) form one concatenated sequence ("segments"), walked 64
+// entries per wavefront step; membership b in N(s) comes from an LDS hash
+// (k <= kSeedHashMax) or a device bitmap. N and D are exact integers.
 // ---------------------------------------------------------------------------
 __global__ void k_bitmap_set(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
-                             const int32_t *__restrict__ big_seeds, int32_t n_big,
-                             uint32_t *__restrict__ bm, int64_t words, int set) {
-  for (int32_t bi = blockIdx.x; bi < n_big; bi += gridDim.x) {
-    const int32_t s = big_seeds[bi];
-    uint32_t *b = bm + (int64_t)bi * words;
+                             const int32_t *__restrict__ seeds, const int32_t *__restrict__ list,
+                             int64_t n_big, uint32_t *__restrict__ bm, int64_t words, int set) {
+  for (int64_t bi = blockIdx.x; bi < n_big; bi += gridDim.x) {
+    const int32_t pos = list[bi];
+    const int32_t s = seeds ? seeds[pos] : pos;
+    uint32_t *b = bm + bi * words;
     for (int32_t e = row_ptr[s] + threadIdx.x; e < row_ptr[s + 1]; e += blockDim.x) {
       const int32_t x = col[e];
       if (set) atomicOr(&b[x >> 5], 1u << (x & 31));
@@ -183,95 +300,73 @@ __global__ void k_bitmap_set(const int32_t *__restrict__ row_ptr, const int32_t 
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_seed_stream(
-    const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ deg,
-    const int2 *__restrict__ adj2, const int64_t *__restrict__ asum,
-    const int32_t *__restrict__ seeds, int32_t n_seeds, const void *__restrict__ R,
-    const uint32_t *__restrict__ bm, const int32_t *__restrict__ big_slot, int64_t words,
-    double *__restrict__ ef, int64_t *__restrict__ Dout, int64_t *__restrict__ Nout,
-    int32_t *__restrict__ flagged, int32_t *__restrict__ flag_count,
-    int32_t *__restrict__ fp64_count) {
-  using S = SumT<T>;
-  using Acc = typename S::type;
-  __shared__ int32_t hkey[kSeedHashSlots];
-  __shared__ int32_t pref[257];
-  __shared__ int32_t arow[256], aid[256], ak[256];
-  __shared__ Acc shA[4];
-  __shared__ int64_t shI[4];
-  constexpr int kShift = 32 - __builtin_ctz(kSeedHashSlots);
-  const int tid = threadIdx.x;
-  for (int32_t it = blockIdx.x; it < n_seeds; it += gridDim.x) {
-    const int32_t s = seeds[it];
-    const int32_t k = deg[s], base = row_ptr[s];
-    const int32_t bslot = big_slot ? big_slot[it] : -1;
-    const uint32_t *mybm = bslot >= 0 ? bm + (int64_t)bslot * words : nullptr;
-    if (!mybm) {
-      for (int i = tid; i < kSeedHashSlots; i += 256) hkey[i] = -1;
-      __syncthreads();
-      for (int e = base + tid; e < base + k; e += 256) {
-        const int32_t x = adj2[e].x;
-        uint32_t h = hash32((uint32_t)x) >> kShift;
-        while (atomicCAS(&hkey[h], -1, x) != -1) h = (h + 1) & (kSeedHashSlots - 1);
-      }
-      __syncthreads();
+// segment table of neighbours c0 .. c0+cnt-1 of a seed (row base `base`):
+// seg[j] = {row start of a_j minus its first concatenated index, k_{a_j}},
+// segp[j] = first concatenated index, segp[cnt] = total. NT threads.
+template <int NT>
+__device__ __forceinline__ int32_t seed_chunk_setup(const int32_t *__restrict__ row_ptr,
+                                                    const int2 *__restrict__ adj2, int32_t base,
+                                                    int32_t c0, int32_t cnt, int tid, int2 *seg,
+                                                    int32_t *segp, int32_t *part) {
+  int32_t run = 0;
+  for (int32_t j0 = 0; j0 < cnt; j0 += NT) {
+    const int32_t j = j0 + tid;
+    int32_t a = 0, ka = 0;
+    if (j < cnt) {
+      const int2 ad = adj2[base + c0 + j];
+      a = ad.x;
+      ka = ad.y;
     }
-    Acc sacc = Acc();
-    int64_t Dd = 0, Nn = 0;
-    if (k >= 2)
-      for (int e = base + tid; e < base + k; e += 256) S::add_stored(sacc, R, e);
-    for (int32_t c0 = 0; c0 < k; c0 += 256) {
-      const int32_t cnt = min(256, k - c0);
-      int32_t len = 0;
-      if (tid < cnt) {
-        const int2 ad = adj2[base + c0 + tid];
-        aid[tid] = ad.x;
-        ak[tid] = ad.y;
-        arow[tid] = row_ptr[ad.x];
-        len = ad.y;
-      }
-      // block exclusive scan of len into pref
-      {
-        const int lane = tid & 63, w = tid >> 6;
-        int32_t incl = len;
-        for (int off = 1; off < 64; off <<= 1) {
-          int32_t y = __shfl_up(incl, off, 64);
-          if (lane >= off) incl += y;
-        }
-        __shared__ int32_t wsum[4];
-        if (lane == 63) wsum[w] = incl;
-        __syncthreads();
-        int32_t woff = 0;
-        for (int i = 0; i < w; ++i) woff += wsum[i];
-        pref[tid] = woff + incl - len;
-        if (tid == 255) pref[256] = woff + incl;
-        __syncthreads();
-      }
-      const int32_t total = pref[256];
-      for (int32_t idx = tid; idx < total; idx += 256) {
-        int32_t lo = 0, hi = cnt;  // largest j with pref[j] <= idx
-        while (hi - lo > 1) {
-          int32_t mid = (lo + hi) >> 1;
-          if (pref[mid] <= idx) lo = mid; else hi = mid;
-        }
-        const int32_t ka = ak[lo];
-        const int2 bd = adj2[arow[lo] + (idx - pref[lo])];
-        const int32_t b = bd.x, kb = bd.y;
-        if (b == s) continue;
+    int32_t tot;
+    const int32_t excl = group_excl_scan<NT>(ka, part, tot);
+    if (j < cnt) {
+      seg[j] = make_int2(row_ptr[a] - (run + excl), ka);
+      segp[j] = run + excl;
+    }
+    run += tot;
+  }
+  if (tid == 0) segp[cnt] = run;
+  return run;
+}
+
+template <int SLOTS>
+__device__ __forceinline__ void hash_insert(int32_t *hkey, int32_t x) {
+  constexpr int kShift = 32 - __builtin_ctz(SLOTS);
+  uint32_t h = hash32((uint32_t)x) >> kShift;
+  while (atomicCAS(&hkey[h], -1, x) != -1) h = (h + 1) & (SLOTS - 1);
+}
+
+// one wavefront walks entries [beg, end) of the current chunk
+template <typename T, int SLOTS, bool BITMAP>
+__device__ __forceinline__ void seed_walk(const int2 *__restrict__ adj2, const int2 *seg,
+                                          const int32_t *segp, int32_t nseg, int32_t beg,
+                                          int32_t end, int32_t s, int32_t k, const int32_t *hkey,
+                                          const uint32_t *__restrict__ bm, int32_t *flg,
+                                          typename SumT<T>::type &sacc, int64_t &Dd,
+                                          int64_t &Nn) {
+  using S = SumT<T>;
+  constexpr int kShift = 32 - __builtin_ctz(SLOTS);
+  if (beg >= end) return;
+  const int lane = threadIdx.x & 63;
+  int32_t s0 = seg_find(segp, nseg, beg);
+  for (int32_t c = beg; c < end; c += 64) {
+    const int32_t sg = seg_step(segp, nseg, c, s0, flg);
+    const int32_t idx = c + lane;
+    if (idx < end) {
+      const int2 sv = seg[sg];
+      const int2 bd = adj2[sv.x + idx];
+      const int32_t b = bd.x;
+      if (b != s) {
         bool m;
-        if (mybm) {
-          m = (mybm[b >> 5] >> (b & 31)) & 1u;
+        if constexpr (BITMAP) {
+          m = (bm[b >> 5] >> (b & 31)) & 1u;
         } else {
           uint32_t h = hash32((uint32_t)b) >> kShift;
-          m = false;
-          while (true) {
-            const int32_t key = hkey[h];
-            if (key == b) { m = true; break; }
-            if (key == -1) break;
-            h = (h + 1) & (kSeedHashSlots - 1);
-          }
+          int32_t key;
+          while ((key = hkey[h]) != b && key != -1) h = (h + 1) & (SLOTS - 1);
+          m = key == b;
         }
-        const int32_t sigma = k + ka + kb;
+        const int32_t sigma = k + sv.y + bd.y;
         const int32_t d = sigma - 4 - (m ? 2 : 0);
         S::add_term(sacc, score_t<T>(d));
         Dd += d;
@@ -282,48 +377,187 @@ __global__ __launch_bounds__(256) void k_seed_stream(
           Dd -= 2;
         }
       }
+    }
+    wave_sync();
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void seed_finish(int32_t pos, int32_t k, int64_t As,
+                                            typename SumT<T>::type sacc, int64_t Nn, int64_t Dd,
+                                            double *ef, int64_t *Dout, int64_t *Nout,
+                                            uint8_t *fl) {
+  using S = SumT<T>;
+  const int64_t kk = k;
+  Nn += kk * (kk - 1);
+  Dd += kk * (kk - 1) * (kk - 4) + 2 * (kk - 1) * As;
+  ef[pos] = finish_ef<T>(Nn, Dd, S::value(sacc), pos, fl);
+  Dout[pos] = Dd;
+  Nout[pos] = Nn;
+}
+
+// seeds of degree <= MAXK: one wavefront per seed, WPB independent
+// wavefronts per workgroup, each with its own LDS hash and segment table
+template <typename T, int SLOTS, int MAXK, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_seed_wave(
+    const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ deg,
+    const int2 *__restrict__ adj2, const int64_t *__restrict__ asum,
+    const int32_t *__restrict__ seeds, const int32_t *__restrict__ list, int64_t count,
+    const void *__restrict__ R, double *__restrict__ ef, int64_t *__restrict__ Dout,
+    int64_t *__restrict__ Nout, uint8_t *__restrict__ fl) {
+  using S = SumT<T>;
+  using Acc = typename S::type;
+  __shared__ int32_t hkey_s[WPB][SLOTS];
+  __shared__ int2 seg_s[WPB][MAXK];
+  __shared__ int32_t segp_s[WPB][MAXK + 1];
+  __shared__ int32_t flg_s[WPB][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int32_t *hkey = hkey_s[wv];
+  int32_t *flg = flg_s[wv];
+  flg[lane] = 0;
+  const int64_t nwaves = (int64_t)gridDim.x * WPB;
+  for (int64_t it = (int64_t)blockIdx.x * WPB + wv; it < count; it += nwaves) {
+    const int32_t pos = list[it];
+    const int32_t s = seeds ? seeds[pos] : pos;
+    const int32_t k = deg[s], base = row_ptr[s];
+    for (int i = lane; i < SLOTS; i += 64) hkey[i] = -1;
+    wave_sync();
+    Acc sacc = Acc();
+    int64_t Dd = 0, Nn = 0;
+    for (int32_t j = lane; j < k; j += 64) {
+      hash_insert<SLOTS>(hkey, adj2[base + j].x);
+      if (k >= 2) S::add_stored(sacc, R, base + j);
+    }
+    const int32_t total =
+        seed_chunk_setup<64>(row_ptr, adj2, base, 0, k, lane, seg_s[wv], segp_s[wv], nullptr);
+    wave_sync();
+    seed_walk<T, SLOTS, false>(adj2, seg_s[wv], segp_s[wv], k, 0, total, s, k, hkey, nullptr, flg,
+                               sacc, Dd, Nn);
+    sacc = wave_sum(sacc);
+    Dd = wave_sum_i64(Dd);
+    Nn = wave_sum_i64(Nn);
+    if (lane == 0)
+      seed_finish<T>(pos, k, asum[s], sacc, Nn, Dd, ef, Dout, Nout, fl);
+    wave_sync();
+  }
+}
+
+// one workgroup of WPB wavefronts per seed; neighbours in chunks of MAXK,
+// each wavefront walking a contiguous share of a chunk's sequence. BITMAP:
+// membership from bm + slot * words, slot = index in the list.
+template <typename T, int SLOTS, int MAXK, int WPB, bool BITMAP>
+__global__ __launch_bounds__(64 * WPB) void k_seed_block(
+    const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ deg,
+    const int2 *__restrict__ adj2, const int64_t *__restrict__ asum,
+    const int32_t *__restrict__ seeds, const int32_t *__restrict__ list, int64_t count,
+    const void *__restrict__ R, const uint32_t *__restrict__ bm, int64_t words,
+    double *__restrict__ ef, int64_t *__restrict__ Dout, int64_t *__restrict__ Nout,
+    uint8_t *__restrict__ fl) {
+  using S = SumT<T>;
+  using Acc = typename S::type;
+  constexpr int NT = 64 * WPB;
+  __shared__ int32_t hkey[BITMAP ? 1 : SLOTS];
+  __shared__ int2 seg[MAXK];
+  __shared__ int32_t segp[MAXK + 1];
+  __shared__ int32_t flg_s[WPB][64];
+  __shared__ int32_t part[WPB];
+  __shared__ Acc shA[WPB];
+  __shared__ int64_t shD[WPB], shN[WPB];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  int32_t *flg = flg_s[wv];
+  flg[lane] = 0;
+  for (int64_t it = blockIdx.x; it < count; it += gridDim.x) {
+    const int32_t pos = list[it];
+    const int32_t s = seeds ? seeds[pos] : pos;
+    const int32_t k = deg[s], base = row_ptr[s];
+    const uint32_t *mybm = BITMAP ? bm + it * words : nullptr;
+    if constexpr (!BITMAP) {
+      for (int i = tid; i < SLOTS; i += NT) hkey[i] = -1;
       __syncthreads();
     }
-    sacc = block_sum_acc(sacc, shA);
-    Dd = block_sum_i64(Dd, shI);
-    Nn = block_sum_i64(Nn, shI);
+    Acc sacc = Acc();
+    int64_t Dd = 0, Nn = 0;
+    for (int32_t j = tid; j < k; j += NT) {
+      if constexpr (!BITMAP) hash_insert<SLOTS>(hkey, adj2[base + j].x);
+      if (k >= 2) S::add_stored(sacc, R, base + j);
+    }
+    for (int32_t c0 = 0; c0 < k; c0 += MAXK) {
+      const int32_t cnt = min(MAXK, k - c0);
+      const int32_t total = seed_chunk_setup<NT>(row_ptr, adj2, base, c0, cnt, tid, seg, segp, part);
+      __syncthreads();
+      const int32_t steps = (total + 63) >> 6;
+      const int32_t beg = (int32_t)(((int64_t)steps * wv / WPB) << 6);
+      const int32_t fin = (int32_t)(((int64_t)steps * (wv + 1) / WPB) << 6);
+      seed_walk<T, SLOTS, BITMAP>(adj2, seg, segp, cnt, beg, fin < total ? fin : total, s, k, hkey,
+                                  mybm, flg, sacc, Dd, Nn);
+      __syncthreads();
+    }
+    sacc = wave_sum(sacc);
+    Dd = wave_sum_i64(Dd);
+    Nn = wave_sum_i64(Nn);
+    if (lane == 0) {
+      shA[wv] = sacc;
+      shD[wv] = Dd;
+      shN[wv] = Nn;
+    }
+    __syncthreads();
     if (tid == 0) {
-      const int64_t kk = k;
-      const int64_t As = asum[s];
-      Nn += kk * (kk - 1);
-      Dd += kk * (kk - 1) * (kk - 4) + 2 * (kk - 1) * As;
-      ef[it] = finish_ef<T>(Nn, Dd, S::value(sacc), it, flagged, flag_count, fp64_count);
-      Dout[it] = Dd;
-      Nout[it] = Nn;
+      Acc a = shA[0];
+      int64_t dsum = shD[0], nsum = shN[0];
+      for (int w = 1; w < WPB; ++w) {
+        acc_merge(a, shA[w]);
+        dsum += shD[w];
+        nsum += shN[w];
+      }
+      seed_finish<T>(pos, k, asum[s], a, nsum, dsum, ef, Dout, Nout, fl);
     }
     __syncthreads();
   }
 }
 
-hipError_t launch_per_seed(const Graph &g, ef_prec prec, const int32_t *seeds, int32_t n_seeds,
-                           const void *R, uint32_t *bitmaps, const int32_t *big_seeds,
-                           const int32_t *big_slot, int32_t n_big_seeds, double *ef, int64_t *D,
-                           int64_t *N, int32_t *flagged, int32_t *flag_count,
-                           int32_t *fp64_count, hipStream_t st, hipEvent_t ev_stream_done) {
+template <typename T>
+static void per_seed_impl(const Graph &g, const int32_t *seeds, const int32_t *const *lists,
+                          const int64_t *counts, const void *R, const uint32_t *bitmaps,
+                          int64_t words, double *ef, int64_t *D, int64_t *N, uint8_t *fl,
+                          hipStream_t st) {
+  if (counts[0] > 0)
+    hipLaunchKernelGGL((k_seed_wave<T, 2 * kSeedBin0, kSeedBin0, 4>),
+                       dim3(cap_blocks((counts[0] + 3) / 4, 1 << 20)), dim3(256), 0, st,
+                       g.row_ptr, g.deg, g.adj2, g.asum, seeds, lists[0], counts[0], R, ef, D, N,
+                       fl);
+  if (counts[1] > 0)
+    hipLaunchKernelGGL((k_seed_block<T, 2 * kSeedBin1, kSeedBin1, 8, false>),
+                       dim3(cap_blocks(counts[1], 1 << 20)), dim3(512), 0, st, g.row_ptr, g.deg,
+                       g.adj2, g.asum, seeds, lists[1], counts[1], R, nullptr, words, ef, D, N,
+                       fl);
+  if (counts[2] > 0)
+    hipLaunchKernelGGL((k_seed_block<T, kSeedHashSlots, kSeedHashMax, 16, false>),
+                       dim3(cap_blocks(counts[2], 1 << 20)), dim3(1024), 0, st, g.row_ptr,
+                       g.deg, g.adj2, g.asum, seeds, lists[2], counts[2], R, nullptr, words, ef,
+                       D, N, fl);
+  if (counts[3] > 0)
+    hipLaunchKernelGGL((k_seed_block<T, 1, kSeedHashMax, 16, true>),
+                       dim3(cap_blocks(counts[3], 1 << 20)), dim3(1024), 0, st, g.row_ptr,
+                       g.deg, g.adj2, g.asum, seeds, lists[3], counts[3], R, bitmaps, words, ef,
+                       D, N, fl);
+}
+
+hipError_t launch_per_seed(const Graph &g, ef_prec prec, const int32_t *seeds,
+                           const int32_t *const *lists, const int64_t *counts, const void *R,
+                           uint32_t *bitmaps, double *ef, int64_t *D, int64_t *N, uint8_t *fl,
+                           hipStream_t st, hipEvent_t ev_stream_done) {
   const int64_t words = ((int64_t)g.n + 31) / 32;
-  if (n_big_seeds > 0)
-    hipLaunchKernelGGL(k_bitmap_set, dim3(cap_blocks(n_big_seeds, 65536)), dim3(256), 0, st,
-                       g.row_ptr, g.col_idx, big_seeds, n_big_seeds, bitmaps, words, 1);
-  const unsigned blocks = cap_blocks(n_seeds, 1 << 20);
+  if (counts[3] > 0)
+    hipLaunchKernelGGL(k_bitmap_set, dim3(cap_blocks(counts[3], 65536)), dim3(256), 0, st,
+                       g.row_ptr, g.col_idx, seeds, lists[3], counts[3], bitmaps, words, 1);
   if (prec == EF_PREC_FP64)
-    hipLaunchKernelGGL(k_seed_stream<double>, dim3(blocks), dim3(256), 0, st, g.row_ptr, g.deg,
-                       g.adj2, g.asum, seeds, n_seeds, R, bitmaps,
-                       n_big_seeds > 0 ? big_slot : nullptr, words, ef, D, N, flagged,
-                       flag_count, fp64_count);
+    per_seed_impl<double>(g, seeds, lists, counts, R, bitmaps, words, ef, D, N, fl, st);
   else
-    hipLaunchKernelGGL(k_seed_stream<float>, dim3(blocks), dim3(256), 0, st, g.row_ptr, g.deg,
-                       g.adj2, g.asum, seeds, n_seeds, R, bitmaps,
-                       n_big_seeds > 0 ? big_slot : nullptr, words, ef, D, N, flagged,
-                       flag_count, fp64_count);
+    per_seed_impl<float>(g, seeds, lists, counts, R, bitmaps, words, ef, D, N, fl, st);
   if (ev_stream_done) (void)hipEventRecord(ev_stream_done, st);
-  if (n_big_seeds > 0)
-    hipLaunchKernelGGL(k_bitmap_set, dim3(cap_blocks(n_big_seeds, 65536)), dim3(256), 0, st,
-                       g.row_ptr, g.col_idx, big_seeds, n_big_seeds, bitmaps, words, 0);
+  if (counts[3] > 0)
+    hipLaunchKernelGGL(k_bitmap_set, dim3(cap_blocks(counts[3], 65536)), dim3(256), 0, st,
+                       g.row_ptr, g.col_idx, seeds, lists[3], counts[3], bitmaps, words, 0);
   return hipGetLastError();
 }
 

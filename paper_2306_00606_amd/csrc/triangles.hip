@@ -40,12 +40,6 @@ template <typename T> __device__ __forceinline__ long long to_fix(T v) {
   return __double2ll_rn((double)v * kFix);
 }
 
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
 // Integer credit slots, 2^-40 units on output.
 // FP32: delta < 0 is a float with 2 <= |delta| < 2^7 (log2 units, degrees
 //   below kMaxDegree), so its ulp is >= 2^-22 and |delta| * 2^24 is an exact
@@ -178,29 +172,9 @@ __device__ __forceinline__ void tri_walk(const int32_t *__restrict__ up_col,
   constexpr int32_t kPosMask = (1 << kPosBits) - 1;
   if (beg >= end) return;
   const int lane = threadIdx.x & 63;
-  const unsigned long long le_mask = ~0ull >> (63 - lane);
-  // s0: segment holding entry beg (largest s with segp[s] <= beg)
-  int32_t s0 = 0;
-  {
-    int32_t hi = nseg;
-    while (hi - s0 > 1) {
-      const int32_t mid = (s0 + hi) >> 1;
-      if (L.segp[mid] <= beg) s0 = mid; else hi = mid;
-    }
-  }
+  int32_t s0 = seg_find(L.segp, nseg, beg);
   for (int32_t c = beg; c < end; c += 64) {
-    // flag the starts of segments s0+1 .. s0+64 that fall inside this step;
-    // segp[nseg] = total closes the last segment. p == 64 means a segment
-    // starts at the next step; lanes past nseg take p = 65 (no segment).
-    const int32_t s = s0 + 1 + lane;
-    const int32_t p = (s <= nseg) ? L.segp[s] - c : 65;
-    if (p < 64) flg[p] = 1;
-    wave_sync();
-    const int32_t f = flg[lane];
-    flg[lane] = 0;
-    const unsigned long long starts = __ballot(f != 0);
-    const int32_t sg = s0 + __popcll(starts & le_mask);
-    s0 += __popcll(starts) + (int32_t)(__ballot(p == 64) != 0ull);
+    const int32_t sg = seg_step(L.segp, nseg, c, s0, flg);
     const int32_t idx = c + lane;
     if (idx < end) {
       const int2 sv = L.seg[sg];
