@@ -128,6 +128,7 @@ __device__ __forceinline__ int32_t seg_find(const int32_t *segp, int32_t nseg, i
 __device__ __forceinline__ int32_t seg_step(const int32_t *segp, int32_t nseg, int32_t c,
                                             int32_t &s0, int32_t *flg) {
   const int lane = threadIdx.x & 63;
+  wave_sync();  // the previous step's clearing of flg is complete
   const unsigned long long le_mask = ~0ull >> (63 - lane);
   const int32_t s = s0 + 1 + lane;
   const int32_t p = (s <= nseg) ? segp[s] - c : 65;
@@ -139,6 +140,36 @@ __device__ __forceinline__ int32_t seg_step(const int32_t *segp, int32_t nseg, i
   const int32_t sg = s0 + __popcll(starts & le_mask);
   s0 += __popcll(starts) + (int32_t)(__ballot(p == 64) != 0ull);
   return sg;
+}
+
+// Walk entries [beg, end) with one wavefront, U steps of 64 per round: the
+// segments of all U steps are found first, then every step's load is issued
+// (U loads in flight per lane), then the entries are used.
+//   load(seg, idx) -> V   reads what entry idx of segment seg needs
+//   use(seg, idx, V)      consumes it
+template <int U, typename Load, typename Use>
+__device__ __forceinline__ void seg_walk(const int32_t *segp, int32_t nseg, int32_t beg,
+                                         int32_t end, int32_t *flg, Load load, Use use) {
+  if (beg >= end) return;
+  const int lane = threadIdx.x & 63;
+  int32_t s0 = seg_find(segp, nseg, beg);
+  for (int32_t c = beg; c < end; c += 64 * U) {
+    int32_t sg[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) sg[q] = (c + 64 * q < end) ? seg_step(segp, nseg, c + 64 * q, s0, flg) : 0;
+    decltype(load(0, 0)) v[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int32_t idx = c + 64 * q + lane;
+      if (idx < end) v[q] = load(sg[q], idx);
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int32_t idx = c + 64 * q + lane;
+      if (idx < end) use(sg[q], idx, v[q]);
+    }
+  }
+  wave_sync();
 }
 
 // Exclusive scan of one int32 per thread over NT threads (one wavefront, or

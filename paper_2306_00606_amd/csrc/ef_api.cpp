@@ -215,7 +215,8 @@ ef_status ef_graph_free(ef_graph *h) {
   }
   void *arrays[] = {g.deg, g.src, g.rev, g.adj2, g.asum, g.up_ptr, g.up_col, g.tslot,
                     g.tri_list[0], g.tri_list[1], g.tri_list[2], g.tri_list[3], g.fin_list,
-                    g.ps_list[0], g.ps_list[1], g.ps_list[2], g.ps_list[3], g.d_counters};
+                    g.ps_list[0], g.ps_list[1], g.ps_list[2], g.ps_list[3], g.ps_list[4],
+                    g.d_counters};
   for (void *p : arrays)
     if (p) (void)hipFree(p);
   for (auto &b : g.ws)
@@ -397,6 +398,8 @@ ef_status ef_graph_load_csr(int32_t n, int64_t nnz, const int32_t *row_ptr,
     return g.h_deg[a] != g.h_deg[b] ? g.h_deg[a] > g.h_deg[b] : a < b;
   });
   g.n_fin = (int64_t)fin.size();
+  for (int32_t v : fin)
+    if (g.h_deg[v] > kFinBlockMin) g.n_fin_hub++;
   ALLOC(g.fin_list, sizeof(int32_t) * std::max<size_t>(fin.size(), 1), "finalize list");
 #undef ALLOC
   hipError_t e = hipSuccess;
@@ -677,19 +680,32 @@ extern "C" ef_status ef_compute(ef_graph *h, ef_algo algo, ef_prec prec, const i
   // device seed arrays: the unique work list (all nodes: none, position =
   // node id), the inverse map, and output positions by seed degree bin
   int32_t *d_useeds = nullptr, *d_inv = nullptr;
-  const int32_t *ps_lists[4] = {nullptr, nullptr, nullptr, nullptr};
-  int64_t ps_counts[4] = {0, 0, 0, 0};
-  auto seed_bin = [](int32_t k) {
-    return k <= kSeedBin0 ? 0 : k <= kSeedBin1 ? 1 : k <= kSeedHashMax ? 2 : 3;
+  const int32_t *ps_lists[kSeedBins] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  int64_t ps_counts[kSeedBins] = {0, 0, 0, 0, 0};
+  if (per_seed && g.h_asum.empty() && g.n > 0) {
+    g.h_asum.resize((size_t)g.n);
+    e = hipMemcpy(g.h_asum.data(), g.asum, sizeof(int64_t) * (size_t)g.n, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      g.h_asum.clear();
+      return hip_status(e, "copy neighbour-degree sums");
+    }
+  }
+  auto seed_bin = [&](int32_t v) {
+    const int32_t k = g.h_deg[v];
+    if (k <= kSeedBin0 && g.h_asum[v] <= kSeedWaveWork) return 0;
+    return k <= kSeedBin1 ? 1 : k <= kSeedBin2 ? 2 : k <= kSeedBin3 ? 3 : 4;
+  };
+  // largest 2-hop work first
+  auto by_work = [&](int32_t a, int32_t c) {
+    const int64_t wa = g.h_asum[a], wc = g.h_asum[c];
+    return wa != wc ? wa > wc : a < c;
   };
   if (per_seed && all) {
     if (!g.ps_ready) {
-      std::vector<int32_t> lst[4];
-      for (int32_t v = 0; v < g.n; ++v) lst[seed_bin(g.h_deg[v])].push_back(v);
-      for (int bin = 0; bin < 4; ++bin) {
-        // largest seeds first
-        std::stable_sort(lst[bin].begin(), lst[bin].end(),
-                         [&](int32_t a, int32_t c) { return g.h_deg[a] > g.h_deg[c]; });
+      std::vector<int32_t> lst[kSeedBins];
+      for (int32_t v = 0; v < g.n; ++v) lst[seed_bin(v)].push_back(v);
+      for (int bin = 0; bin < kSeedBins; ++bin) {
+        std::sort(lst[bin].begin(), lst[bin].end(), by_work);
         g.n_ps[bin] = (int64_t)lst[bin].size();
         if ((s = dev_alloc(g, (void **)&g.ps_list[bin],
                            sizeof(int32_t) * std::max<size_t>(lst[bin].size(), 1),
@@ -703,20 +719,24 @@ extern "C" ef_status ef_compute(ef_graph *h, ef_algo algo, ef_prec prec, const i
       }
       g.ps_ready = true;
     }
-    for (int bin = 0; bin < 4; ++bin) {
+    for (int bin = 0; bin < kSeedBins; ++bin) {
       ps_lists[bin] = g.ps_list[bin];
       ps_counts[bin] = g.n_ps[bin];
     }
   } else if (per_seed) {
-    std::vector<int32_t> lst[4];
-    for (size_t i = 0; i < useeds.size(); ++i) lst[seed_bin(g.h_deg[useeds[i]])].push_back((int32_t)i);
+    std::vector<int32_t> lst[kSeedBins];
+    std::vector<int32_t> order(useeds.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::sort(order.begin(), order.end(),
+              [&](int32_t a, int32_t c) { return by_work(useeds[a], useeds[c]); });
+    for (int32_t i : order) lst[seed_bin(useeds[i])].push_back(i);
     const size_t cnt_all = useeds.size() * 2 + inv.size() + 4;
     if ((s = ws_ensure(g, WS_SEEDS, sizeof(int32_t) * cnt_all, "seed lists")) != EF_OK) return s;
     d_useeds = (int32_t *)g.ws[WS_SEEDS].p;
     int32_t *p = d_useeds + useeds.size();
     e = hipMemcpyAsync(d_useeds, useeds.data(), sizeof(int32_t) * useeds.size(),
                        hipMemcpyHostToDevice, st);
-    for (int bin = 0; bin < 4; ++bin) {
+    for (int bin = 0; bin < kSeedBins; ++bin) {
       ps_lists[bin] = p;
       ps_counts[bin] = (int64_t)lst[bin].size();
       if (e == hipSuccess && !lst[bin].empty())
@@ -731,9 +751,9 @@ extern "C" ef_status ef_compute(ef_graph *h, ef_algo algo, ef_prec prec, const i
     if (e == hipSuccess) e = hipStreamSynchronize(st);  // host vectors go out of scope
     if (e != hipSuccess) return hip_status(e, "upload seeds");
   }
-  if (per_seed && ps_counts[3] > 0) {
+  if (per_seed && ps_counts[kSeedBins - 1] > 0) {
     const size_t words = ((size_t)g.n + 31) / 32;
-    const size_t need = sizeof(uint32_t) * words * (size_t)ps_counts[3];
+    const size_t need = sizeof(uint32_t) * words * (size_t)ps_counts[kSeedBins - 1];
     const bool fresh = g.ws[WS_BITMAP].bytes < need;
     if ((s = ws_ensure(g, WS_BITMAP, need, "membership bitmaps")) != EF_OK) return s;
     if (fresh) {

@@ -36,15 +36,25 @@ constexpr int kRecEntries = 2 * kSuper;  // row part + column part per super-til
 // (degree, position) words of the triangle pass.
 constexpr int32_t kMaxDegree = 1000000;
 constexpr int kTriBin0 = 64, kTriBin1 = 512, kTriBin2 = 2048;
-// Finalize: nodes of degree <= kFinGroupMax share wavefronts, 8 lanes each.
+// Finalize: nodes of degree <= kFinGroupMax share wavefronts, 8 lanes each;
+// hubs of degree > kFinBlockMin take a workgroup each.
 constexpr int32_t kFinGroupMax = 32;
+constexpr int32_t kFinBlockMin = 4096;
 constexpr int kTriLongMin = kTriBin2 + 1;
 
-// Per-seed stream: seeds with k <= kSeedHashMax use an LDS hash of N(s);
-// larger seeds a bitmap over all node ids in device memory.
-constexpr int kSeedBin0 = 64, kSeedBin1 = 512;
-constexpr int kSeedHashMax = 2048;
-constexpr int kSeedHashSlots = 4096;
+// Per-seed formulation: seeds are binned by degree k and 2-hop work
+// A = sum of neighbour degrees:
+//   0: k <= kSeedBin0 and A <= kSeedWaveWork   one wavefront, LDS hash of N(s)
+//   1: k <= kSeedBin1                          one workgroup (8 wavefronts)
+//   2: k <= kSeedBin2                          one workgroup (16 wavefronts)
+//   3: k <= kSeedBin3                          one workgroup, 64 KB LDS hash
+//   4: larger                                  one workgroup, bitmap of N(s)
+// Hash tables have twice as many slots as keys. Neighbour rows are walked in
+// chunks of at most kSeedChunk neighbours.
+constexpr int kSeedBins = 5;
+constexpr int kSeedBin0 = 64, kSeedBin1 = 512, kSeedBin2 = 2048, kSeedBin3 = 8192;
+constexpr int64_t kSeedWaveWork = 4096;
+constexpr int kSeedChunk = 2048;
 
 // FP32C: seeds whose estimated cancellation factor (S/D)/EF exceeds this are
 // recomputed from non-negative terms.
@@ -101,10 +111,12 @@ struct Graph {
   // nodes of degree > kFinGroupMax (finalized one wavefront each), by degree descending
   int32_t *fin_list = nullptr;
   int64_t n_fin = 0;
+  int64_t n_fin_hub = 0;  // leading entries of fin_list with degree > kFinBlockMin
   // per-seed formulation over all nodes: node ids by seed bin (built on first use)
-  int32_t *ps_list[4] = {nullptr, nullptr, nullptr, nullptr};
-  int64_t n_ps[4] = {0, 0, 0, 0};
+  int32_t *ps_list[kSeedBins] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  int64_t n_ps[kSeedBins] = {0, 0, 0, 0, 0};
   bool ps_ready = false;
+  std::vector<int64_t> h_asum;  // host copy of asum (built on first per-seed use)
   int64_t n_tri[4] = {0, 0, 0, 0};
   // bin counts for the all-nodes centre set
   int64_t all_small = 0, all_mid = 0, all_big = 0, all_tiles = 0;
@@ -179,6 +191,9 @@ hipError_t launch_pairs(const Graph &g, ef_prec prec, const Bins &b, void *R, vo
 // YT per up-arc slot, Z / ZT per node.
 hipError_t launch_triangles(const Graph &g, ef_prec prec, long long *Y, int32_t *YT, void *Z,
                             int64_t *ZT, hipStream_t st);
+// triangle counts only: YT per up-arc slot, ZT per node (Y is zeroed, no Z)
+hipError_t launch_triangles_count(const Graph &g, long long *Y, int32_t *YT, int64_t *ZT,
+                                  hipStream_t st);
 
 // per-node sums + Eq. 1 (cluster-centric); per-node flag bytes in fl.
 hipError_t launch_finalize_cluster(const Graph &g, ef_prec prec, const void *R,
@@ -194,9 +209,9 @@ hipError_t launch_flag_compact(const uint8_t *fl, int64_t n, int32_t *flagged, i
 
 // per-seed formulation: star sums from R of the seed's own arcs, 2-hop walk,
 // then Eq. 1. seeds: the unique work list (NULL: position = node id);
-// lists[b] / counts[b]: output positions by seed degree, b = 0: k <=
-// kSeedBin0, 1: k <= kSeedBin1, 2: k <= kSeedHashMax, 3: larger (membership
-// from bitmaps: counts[3] of n bits each, in list order).
+// lists[b] / counts[b]: output positions by seed bin (kSeedBins bins, see
+// above); the last bin's membership comes from bitmaps, counts[last] of n
+// bits each, in list order.
 hipError_t launch_per_seed(const Graph &g, ef_prec prec, const int32_t *seeds,
                            const int32_t *const *lists, const int64_t *counts, const void *R,
                            uint32_t *bitmaps, double *ef, int64_t *D, int64_t *N, uint8_t *fl,

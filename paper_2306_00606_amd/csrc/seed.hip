@@ -222,29 +222,114 @@ static unsigned cap_blocks(int64_t b, int64_t cap) {
   return (unsigned)(b < cap ? b : cap);
 }
 
+// hubs (degree > kFinBlockMin): one workgroup of 16 wavefronts per node, the
+// wavefront partials combined in a fixed order
+template <typename T>
+__global__ __launch_bounds__(1024) void k_finalize_hub(
+    const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ deg,
+    const int2 *__restrict__ adj2, const int32_t *__restrict__ rev,
+    const int32_t *__restrict__ tslot, const int64_t *__restrict__ asum,
+    const void *__restrict__ R, const long long *__restrict__ Y, const int32_t *__restrict__ YT,
+    const void *__restrict__ Z, const int64_t *__restrict__ ZT,
+    const int32_t *__restrict__ nodes, int64_t count, double *__restrict__ ef,
+    int64_t *__restrict__ Dout, int64_t *__restrict__ Nout, uint8_t *__restrict__ fl) {
+  using S = SumT<T>;
+  using Acc = typename S::type;
+  __shared__ Acc shS[16];
+  __shared__ double shT[16];
+  __shared__ int64_t shN[16], shD[16], shC[16];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int64_t it = blockIdx.x; it < count; it += gridDim.x) {
+    const int32_t v = nodes[it];
+    const int32_t k = deg[v], base = row_ptr[v];
+    const int64_t As = asum[v];
+    Acc sacc = Acc();
+    double tfix = 0.0;
+    int64_t Nn = 0, Dd = 0, Tc = 0;
+    for (int32_t e = base + tid; e < base + k; e += 1024) {
+      const int2 ad = adj2[e];
+      const int32_t a = ad.x, ka = ad.y;
+      S::add_stored(sacc, R, e);
+      if (ka >= 2) S::add_stored(sacc, R, rev[e]);
+      Nn += (int64_t)(k - 1) + (ka - 1);
+      Dd += (int64_t)(k - 1) * (k + ka - 4) + (As - ka) + (int64_t)(ka - 1) * (ka + k - 4) +
+            (asum[a] - k);
+      if (rank_less_d(a, ka, v, k)) {
+        const int32_t sl = tslot[e];
+        tfix += (double)Y[sl];
+        Tc += YT[sl];
+      }
+    }
+    sacc = wave_sum(sacc);
+    tfix = wave_sum_f64(tfix);
+    Nn = wave_sum_i64(Nn);
+    Dd = wave_sum_i64(Dd);
+    Tc = wave_sum_i64(Tc);
+    if (lane == 0) {
+      shS[wv] = sacc;
+      shT[wv] = tfix;
+      shN[wv] = Nn;
+      shD[wv] = Dd;
+      shC[wv] = Tc;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      for (int w = 1; w < 16; ++w) {
+        acc_merge(sacc, shS[w]);
+        tfix += shT[w];
+        Nn += shN[w];
+        Dd += shD[w];
+        Tc += shC[w];
+      }
+      Acc z = Acc();
+      S::add_stored(z, Z, v);
+      Tc += ZT[v];
+      const double tri = tfix * (1.0 / 1099511627776.0) + S::value(z);
+      const double Stot = S::value(sacc) + 4.0 * tri;
+      Dd -= 8 * Tc;
+      ef[v] = finish_ef<T>(Nn, Dd, Stot, v, fl);
+      Dout[v] = Dd;
+      Nout[v] = Nn;
+    }
+    __syncthreads();
+  }
+}
+
 hipError_t launch_finalize_cluster(const Graph &g, ef_prec prec, const void *R,
                                    const long long *Y, const int32_t *YT, const void *Z,
                                    const int64_t *ZT, double *ef, int64_t *D, int64_t *N,
                                    uint8_t *fl, hipStream_t st) {
-  // nodes of degree <= kFinGroupMax: 8 lanes each; the rest: one wavefront each
+  // nodes of degree <= kFinGroupMax: 8 lanes each; hubs (the first n_fin_hub
+  // entries of fin_list, degree > kFinBlockMin): one workgroup each; the rest
+  // of fin_list: one wavefront each
+  const int64_t n_wave = g.n_fin - g.n_fin_hub;
   const unsigned blocks_s = cap_blocks(((int64_t)g.n * 8 + 255) / 256, 1 << 20);
-  const unsigned blocks_l = cap_blocks((g.n_fin * 64 + 255) / 256, 1 << 20);
+  const unsigned blocks_l = cap_blocks((n_wave * 64 + 255) / 256, 1 << 20);
+  const unsigned blocks_h = cap_blocks(g.n_fin_hub, 1 << 16);
   if (prec == EF_PREC_FP64) {
+    if (g.n_fin_hub > 0)
+      hipLaunchKernelGGL(k_finalize_hub<double>, dim3(blocks_h), dim3(1024), 0, st, g.row_ptr,
+                         g.deg, g.adj2, g.rev, g.tslot, g.asum, R, Y, YT, Z, ZT, g.fin_list,
+                         g.n_fin_hub, ef, D, N, fl);
     hipLaunchKernelGGL((k_finalize_cluster<double, 8>), dim3(blocks_s), dim3(256), 0, st,
                        g.row_ptr, g.deg, g.adj2, g.rev, g.tslot, g.asum, R, Y, YT, Z, ZT,
                        nullptr, (int64_t)g.n, kFinGroupMax, ef, D, N, fl);
-    if (g.n_fin > 0)
+    if (n_wave > 0)
       hipLaunchKernelGGL((k_finalize_cluster<double, 64>), dim3(blocks_l), dim3(256), 0, st,
                          g.row_ptr, g.deg, g.adj2, g.rev, g.tslot, g.asum, R, Y, YT, Z, ZT,
-                         g.fin_list, g.n_fin, 0, ef, D, N, fl);
+                         g.fin_list + g.n_fin_hub, n_wave, 0, ef, D, N, fl);
   } else {
+    if (g.n_fin_hub > 0)
+      hipLaunchKernelGGL(k_finalize_hub<float>, dim3(blocks_h), dim3(1024), 0, st, g.row_ptr,
+                         g.deg, g.adj2, g.rev, g.tslot, g.asum, R, Y, YT, Z, ZT, g.fin_list,
+                         g.n_fin_hub, ef, D, N, fl);
     hipLaunchKernelGGL((k_finalize_cluster<float, 8>), dim3(blocks_s), dim3(256), 0, st,
                        g.row_ptr, g.deg, g.adj2, g.rev, g.tslot, g.asum, R, Y, YT, Z, ZT,
                        nullptr, (int64_t)g.n, kFinGroupMax, ef, D, N, fl);
-    if (g.n_fin > 0)
+    if (n_wave > 0)
       hipLaunchKernelGGL((k_finalize_cluster<float, 64>), dim3(blocks_l), dim3(256), 0, st,
                          g.row_ptr, g.deg, g.adj2, g.rev, g.tslot, g.asum, R, Y, YT, Z, ZT,
-                         g.fin_list, g.n_fin, 0, ef, D, N, fl);
+                         g.fin_list + g.n_fin_hub, n_wave, 0, ef, D, N, fl);
   }
   return hipGetLastError();
 }
@@ -283,7 +368,7 @@ __device__ int64_t block_sum_i64(int64_t x, int64_t *sh) {
 //     (b, k_b) one cluster of degree k_s + k_a + k_b - 4, less 2 if b ~ s.
 // The rows of N(s) form one concatenated sequence ("segments"), walked 64
 // entries per wavefront step; membership b in N(s) comes from an LDS hash
-// (k <= kSeedHashMax) or a device bitmap. N and D are exact integers.
+// (all but the largest seeds) or a device bitmap. N and D are exact integers.
 // ---------------------------------------------------------------------------
 __global__ void k_bitmap_set(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
                              const int32_t *__restrict__ seeds, const int32_t *__restrict__ list,
@@ -346,17 +431,16 @@ __device__ __forceinline__ void seed_walk(const int2 *__restrict__ adj2, const i
                                           int64_t &Nn) {
   using S = SumT<T>;
   constexpr int kShift = 32 - __builtin_ctz(SLOTS);
-  if (beg >= end) return;
-  const int lane = threadIdx.x & 63;
-  int32_t s0 = seg_find(segp, nseg, beg);
-  for (int32_t c = beg; c < end; c += 64) {
-    const int32_t sg = seg_step(segp, nseg, c, s0, flg);
-    const int32_t idx = c + lane;
-    if (idx < end) {
-      const int2 sv = seg[sg];
-      const int2 bd = adj2[sv.x + idx];
-      const int32_t b = bd.x;
-      if (b != s) {
+  seg_walk<4>(
+      segp, nseg, beg, end, flg,
+      [&](int32_t sg, int32_t idx) {
+        const int2 sv = seg[sg];
+        const int2 bd = adj2[sv.x + idx];
+        return make_int3(bd.x, bd.y, sv.y);
+      },
+      [&](int32_t, int32_t, int3 e) {
+        const int32_t b = e.x;
+        if (b == s) return;
         bool m;
         if constexpr (BITMAP) {
           m = (bm[b >> 5] >> (b & 31)) & 1u;
@@ -366,7 +450,7 @@ __device__ __forceinline__ void seed_walk(const int2 *__restrict__ adj2, const i
           while ((key = hkey[h]) != b && key != -1) h = (h + 1) & (SLOTS - 1);
           m = key == b;
         }
-        const int32_t sigma = k + sv.y + bd.y;
+        const int32_t sigma = k + e.z + e.y;
         const int32_t d = sigma - 4 - (m ? 2 : 0);
         S::add_term(sacc, score_t<T>(d));
         Dd += d;
@@ -376,10 +460,7 @@ __device__ __forceinline__ void seed_walk(const int2 *__restrict__ adj2, const i
           S::add_term(sacc, tri_delta<T>(sigma));
           Dd -= 2;
         }
-      }
-    }
-    wave_sync();
-  }
+      });
 }
 
 template <typename T>
@@ -531,14 +612,19 @@ static void per_seed_impl(const Graph &g, const int32_t *seeds, const int32_t *c
                        g.adj2, g.asum, seeds, lists[1], counts[1], R, nullptr, words, ef, D, N,
                        fl);
   if (counts[2] > 0)
-    hipLaunchKernelGGL((k_seed_block<T, kSeedHashSlots, kSeedHashMax, 16, false>),
+    hipLaunchKernelGGL((k_seed_block<T, 2 * kSeedBin2, kSeedChunk, 16, false>),
                        dim3(cap_blocks(counts[2], 1 << 20)), dim3(1024), 0, st, g.row_ptr,
                        g.deg, g.adj2, g.asum, seeds, lists[2], counts[2], R, nullptr, words, ef,
                        D, N, fl);
   if (counts[3] > 0)
-    hipLaunchKernelGGL((k_seed_block<T, 1, kSeedHashMax, 16, true>),
+    hipLaunchKernelGGL((k_seed_block<T, 2 * kSeedBin3, kSeedChunk, 16, false>),
                        dim3(cap_blocks(counts[3], 1 << 20)), dim3(1024), 0, st, g.row_ptr,
-                       g.deg, g.adj2, g.asum, seeds, lists[3], counts[3], R, bitmaps, words, ef,
+                       g.deg, g.adj2, g.asum, seeds, lists[3], counts[3], R, nullptr, words, ef,
+                       D, N, fl);
+  if (counts[4] > 0)
+    hipLaunchKernelGGL((k_seed_block<T, 1, kSeedChunk, 16, true>),
+                       dim3(cap_blocks(counts[4], 1 << 20)), dim3(1024), 0, st, g.row_ptr,
+                       g.deg, g.adj2, g.asum, seeds, lists[4], counts[4], R, bitmaps, words, ef,
                        D, N, fl);
 }
 
@@ -547,17 +633,18 @@ hipError_t launch_per_seed(const Graph &g, ef_prec prec, const int32_t *seeds,
                            uint32_t *bitmaps, double *ef, int64_t *D, int64_t *N, uint8_t *fl,
                            hipStream_t st, hipEvent_t ev_stream_done) {
   const int64_t words = ((int64_t)g.n + 31) / 32;
-  if (counts[3] > 0)
-    hipLaunchKernelGGL(k_bitmap_set, dim3(cap_blocks(counts[3], 65536)), dim3(256), 0, st,
-                       g.row_ptr, g.col_idx, seeds, lists[3], counts[3], bitmaps, words, 1);
+  constexpr int L = kSeedBins - 1;
+  if (counts[L] > 0)
+    hipLaunchKernelGGL(k_bitmap_set, dim3(cap_blocks(counts[L], 65536)), dim3(256), 0, st,
+                       g.row_ptr, g.col_idx, seeds, lists[L], counts[L], bitmaps, words, 1);
   if (prec == EF_PREC_FP64)
     per_seed_impl<double>(g, seeds, lists, counts, R, bitmaps, words, ef, D, N, fl, st);
   else
     per_seed_impl<float>(g, seeds, lists, counts, R, bitmaps, words, ef, D, N, fl, st);
   if (ev_stream_done) (void)hipEventRecord(ev_stream_done, st);
-  if (counts[3] > 0)
-    hipLaunchKernelGGL(k_bitmap_set, dim3(cap_blocks(counts[3], 65536)), dim3(256), 0, st,
-                       g.row_ptr, g.col_idx, seeds, lists[3], counts[3], bitmaps, words, 0);
+  if (counts[L] > 0)
+    hipLaunchKernelGGL(k_bitmap_set, dim3(cap_blocks(counts[L], 65536)), dim3(256), 0, st,
+                       g.row_ptr, g.col_idx, seeds, lists[L], counts[L], bitmaps, words, 0);
   return hipGetLastError();
 }
 

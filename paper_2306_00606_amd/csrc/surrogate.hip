@@ -47,89 +47,181 @@ __device__ __forceinline__ float gelu_grad(float z) {
 __device__ __forceinline__ float bf(float x) { return (float)(__bf16)x; }
 
 // ---------------------------------------------------------------------------
-// features: one wavefront per node
+// features: G lanes per node (8 for degree <= kFinGroupMax, 64 for the rest
+// of the finalize list), one workgroup per hub (degree > kFinBlockMin)
 // ---------------------------------------------------------------------------
+struct FeatAcc {  // POD (lives in LDS); start from feat_zero()
+  int64_t B, Q, T, c1, smax;
+  float mx, mn;
+  double s1, s2;
+  __device__ void add(int2 ad, int64_t sa) {
+    const int64_t ka = ad.y;
+    B += ka * ka;
+    Q += sa;
+    smax = sa > smax ? sa : smax;
+    c1 += ka == 1;
+    const float lk = logf((float)ka);
+    mx = fmaxf(mx, lk);
+    mn = fminf(mn, lk);
+    s1 += lk;
+    s2 += (double)lk * lk;
+  }
+  __device__ void merge(const FeatAcc &o) {
+    B += o.B;
+    Q += o.Q;
+    T += o.T;
+    c1 += o.c1;
+    smax = o.smax > smax ? o.smax : smax;
+    mx = fmaxf(mx, o.mx);
+    mn = fminf(mn, o.mn);
+    s1 += o.s1;
+    s2 += o.s2;
+  }
+};
+
+__device__ __forceinline__ FeatAcc feat_zero() {
+  FeatAcc a;
+  a.B = a.Q = a.T = a.c1 = a.smax = 0;
+  a.mx = -1e30f;
+  a.mn = 1e30f;
+  a.s1 = a.s2 = 0.0;
+  return a;
+}
+
+template <int G> __device__ __forceinline__ FeatAcc feat_reduce(FeatAcc a) {
+  for (int off = G / 2; off > 0; off >>= 1) {
+    FeatAcc o = feat_zero();
+    o.B = __shfl_xor(a.B, off, G);
+    o.Q = __shfl_xor(a.Q, off, G);
+    o.T = __shfl_xor(a.T, off, G);
+    o.c1 = __shfl_xor(a.c1, off, G);
+    o.smax = __shfl_xor(a.smax, off, G);
+    o.mx = __shfl_xor(a.mx, off, G);
+    o.mn = __shfl_xor(a.mn, off, G);
+    o.s1 = __shfl_xor(a.s1, off, G);
+    o.s2 = __shfl_xor(a.s2, off, G);
+    a.merge(o);
+  }
+  return a;
+}
+
+__device__ __forceinline__ void feat_arcs(const int2 *__restrict__ adj2,
+                                          const int64_t *__restrict__ asum,
+                                          const int32_t *__restrict__ tslot,
+                                          const int32_t *__restrict__ YT, int32_t v, int32_t k,
+                                          int32_t base, int32_t first, int32_t stride,
+                                          FeatAcc &f) {
+  for (int32_t e = base + first; e < base + k; e += stride) {
+    const int2 ad = adj2[e];
+    f.add(ad, asum[ad.x]);
+    if (rank_less_d(ad.x, ad.y, v, k)) f.T += YT[tslot[e]];
+  }
+}
+
+__device__ void feat_store(int32_t v, int32_t k, int64_t A, FeatAcc a,
+                           const int64_t *__restrict__ ZT, const float *__restrict__ mean,
+                           const float *__restrict__ inv_std, float *__restrict__ X,
+                           float *__restrict__ lnN) {
+  const int64_t T = a.T + ZT[v];
+  const int64_t kk = k, B = a.B, Q = a.Q;
+  const int64_t Ns = kk * kk - 2 * kk + A;
+  const int64_t Ds = kk * (kk - 1) * (kk - 4) + 2 * (kk - 1) * A + (kk - 4) * (A - kk) +
+                     (B - A) + (Q - kk * kk) - 8 * T;
+  float f[kF];
+  f[0] = logf(1.0f + (float)kk);
+  f[1] = logf(1.0f + (float)A);
+  f[2] = logf(1.0f + (float)B);
+  f[3] = logf(1.0f + (float)T);
+  f[4] = kk >= 2 ? (float)(2.0 * (double)T / (double)(kk * (kk - 1))) : 0.0f;
+  f[5] = logf(1.0f + (float)(A - kk));
+  f[6] = logf(1.0f + (float)Ns);
+  f[7] = logf(1.0f + (float)Ds);
+  f[8] = (Ns > 0 && Ds > 0) ? (float)log((double)Ds / (double)Ns) : 0.0f;
+  const double mean_lk = k > 0 ? a.s1 / k : 0.0;
+  f[9] = k > 0 ? a.mx : 0.0f;
+  f[10] = k > 0 ? a.mn : 0.0f;
+  f[11] = (float)mean_lk;
+  f[12] = k > 0 ? (float)sqrt(fmax(a.s2 / k - mean_lk * mean_lk, 0.0)) : 0.0f;
+  f[13] = logf(1.0f + (float)Q);
+  f[14] = k > 0 ? (float)a.c1 / (float)k : 0.0f;
+  f[15] = logf(1.0f + (float)a.smax);
+  float *dst = X + (int64_t)v * kF;
+#pragma unroll
+  for (int i = 0; i < kF; ++i) dst[i] = mean ? (f[i] - mean[i]) * inv_std[i] : f[i];
+  lnN[v] = Ns > 0 ? logf((float)Ns) : 0.0f;
+}
+
+// nodes == nullptr: nodes 0..count-1 of degree <= kmax; else the listed nodes
+template <int G>
 __global__ __launch_bounds__(256) void k_features(
     const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ deg,
     const int2 *__restrict__ adj2, const int64_t *__restrict__ asum,
     const int32_t *__restrict__ tslot, const int32_t *__restrict__ YT,
-    const int64_t *__restrict__ ZT, int32_t n, const float *__restrict__ mean,
-    const float *__restrict__ inv_std, float *__restrict__ X, float *__restrict__ lnN) {
-  const int lane = threadIdx.x & 63;
-  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  for (int64_t v = wave; v < n; v += nwaves) {
-    const int32_t k = deg[v], base = row_ptr[v];
-    int64_t B = 0, Q = 0, T = 0, c1 = 0, smax = 0;
-    float mx = -1e30f, mn = 1e30f;
-    double s1 = 0.0, s2 = 0.0;
-    for (int32_t e = base + lane; e < base + k; e += 64) {
-      const int2 ad = adj2[e];
-      const int64_t ka = ad.y, sa = asum[ad.x];
-      B += ka * ka;
-      Q += sa;
-      smax = sa > smax ? sa : smax;
-      c1 += ka == 1;
-      const float lk = logf((float)ka);
-      mx = fmaxf(mx, lk);
-      mn = fminf(mn, lk);
-      s1 += lk;
-      s2 += (double)lk * lk;
-      if (rank_less_d(ad.x, ad.y, (int32_t)v, k)) T += YT[tslot[e]];
+    const int64_t *__restrict__ ZT, const int32_t *__restrict__ nodes, int64_t count,
+    int32_t kmax, const float *__restrict__ mean, const float *__restrict__ inv_std,
+    float *__restrict__ X, float *__restrict__ lnN) {
+  const int sub = threadIdx.x & (G - 1);
+  const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+  const int64_t ngrp = ((int64_t)gridDim.x * blockDim.x) / G;
+  const int64_t rounds = (count + ngrp - 1) / ngrp;
+  for (int64_t r = 0; r < rounds; ++r) {
+    const int64_t it = r * ngrp + grp;
+    int32_t v = -1, k = 0;
+    if (it < count) {
+      v = nodes ? nodes[it] : (int32_t)it;
+      k = deg[v];
+      if (!nodes && k > kmax) v = -1;
     }
-    B = wave_sum_i64(B);
-    Q = wave_sum_i64(Q);
-    T = wave_sum_i64(T);
-    c1 = wave_sum_i64(c1);
-    s1 = wave_sum_f64(s1);
-    s2 = wave_sum_f64(s2);
-    for (int off = 32; off > 0; off >>= 1) {
-      mx = fmaxf(mx, __shfl_xor(mx, off, 64));
-      mn = fminf(mn, __shfl_xor(mn, off, 64));
-      const int64_t o = __shfl_xor(smax, off, 64);
-      smax = o > smax ? o : smax;
+    if (v < 0) k = 0;
+    FeatAcc f = feat_zero();
+    if (v >= 0) feat_arcs(adj2, asum, tslot, YT, v, k, row_ptr[v], sub, G, f);
+    f = feat_reduce<G>(f);
+    if (v >= 0 && sub == 0) feat_store(v, k, asum[v], f, ZT, mean, inv_std, X, lnN);
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_features_hub(
+    const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ deg,
+    const int2 *__restrict__ adj2, const int64_t *__restrict__ asum,
+    const int32_t *__restrict__ tslot, const int32_t *__restrict__ YT,
+    const int64_t *__restrict__ ZT, const int32_t *__restrict__ nodes, int64_t count,
+    const float *__restrict__ mean, const float *__restrict__ inv_std, float *__restrict__ X,
+    float *__restrict__ lnN) {
+  __shared__ FeatAcc sh[16];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int64_t it = blockIdx.x; it < count; it += gridDim.x) {
+    const int32_t v = nodes[it];
+    const int32_t k = deg[v];
+    FeatAcc f = feat_zero();
+    feat_arcs(adj2, asum, tslot, YT, v, k, row_ptr[v], tid, 1024, f);
+    f = feat_reduce<64>(f);
+    if (lane == 0) sh[wv] = f;
+    __syncthreads();
+    if (tid == 0) {
+      FeatAcc a = sh[0];
+      for (int w = 1; w < 16; ++w) a.merge(sh[w]);
+      feat_store(v, k, asum[v], a, ZT, mean, inv_std, X, lnN);
     }
-    if (lane == 0) {
-      T += ZT[v];
-      const int64_t kk = k, A = asum[v];
-      const int64_t Ns = kk * kk - 2 * kk + A;
-      const int64_t Ds = kk * (kk - 1) * (kk - 4) + 2 * (kk - 1) * A + (kk - 4) * (A - kk) +
-                         (B - A) + (Q - kk * kk) - 8 * T;
-      float f[kF];
-      f[0] = logf(1.0f + (float)kk);
-      f[1] = logf(1.0f + (float)A);
-      f[2] = logf(1.0f + (float)B);
-      f[3] = logf(1.0f + (float)T);
-      f[4] = kk >= 2 ? (float)(2.0 * (double)T / (double)(kk * (kk - 1))) : 0.0f;
-      f[5] = logf(1.0f + (float)(A - kk));
-      f[6] = logf(1.0f + (float)Ns);
-      f[7] = logf(1.0f + (float)Ds);
-      f[8] = (Ns > 0 && Ds > 0) ? (float)log((double)Ds / (double)Ns) : 0.0f;
-      const double mean_lk = k > 0 ? s1 / k : 0.0;
-      f[9] = k > 0 ? mx : 0.0f;
-      f[10] = k > 0 ? mn : 0.0f;
-      f[11] = (float)mean_lk;
-      f[12] = k > 0 ? (float)sqrt(fmax(s2 / k - mean_lk * mean_lk, 0.0)) : 0.0f;
-      f[13] = logf(1.0f + (float)Q);
-      f[14] = k > 0 ? (float)c1 / (float)k : 0.0f;
-      f[15] = logf(1.0f + (float)smax);
-      for (int i = 0; i < kF; ++i) {
-        float x = f[i];
-        if (mean) x = (x - mean[i]) * inv_std[i];
-        X[v * kF + i] = x;
-      }
-      lnN[v] = Ns > 0 ? logf((float)Ns) : 0.0f;
-    }
+    __syncthreads();
   }
 }
 
 hipError_t launch_features(const Graph &g, const int32_t *YT, const int64_t *ZT,
                            const float *mean, const float *inv_std, float *X, float *lnN,
                            hipStream_t st) {
-  const int64_t blocks = std::min<int64_t>(((int64_t)g.n * 64 + 255) / 256, 1 << 20);
-  hipLaunchKernelGGL(k_features, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st,
-                     g.row_ptr, g.deg, g.adj2, g.asum, g.tslot, YT, ZT, g.n, mean, inv_std, X,
-                     lnN);
+  auto cap = [](int64_t b, int64_t c) { return (unsigned)std::max<int64_t>(1, std::min(b, c)); };
+  const int64_t n_wave = g.n_fin - g.n_fin_hub;
+  if (g.n_fin_hub > 0)
+    hipLaunchKernelGGL(k_features_hub, dim3(cap(g.n_fin_hub, 1 << 16)), dim3(1024), 0, st,
+                       g.row_ptr, g.deg, g.adj2, g.asum, g.tslot, YT, ZT, g.fin_list,
+                       g.n_fin_hub, mean, inv_std, X, lnN);
+  hipLaunchKernelGGL(k_features<8>, dim3(cap(((int64_t)g.n * 8 + 255) / 256, 1 << 20)), dim3(256),
+                     0, st, g.row_ptr, g.deg, g.adj2, g.asum, g.tslot, YT, ZT, nullptr,
+                     (int64_t)g.n, kFinGroupMax, mean, inv_std, X, lnN);
+  if (n_wave > 0)
+    hipLaunchKernelGGL(k_features<64>, dim3(cap((n_wave * 64 + 255) / 256, 1 << 20)), dim3(256),
+                       0, st, g.row_ptr, g.deg, g.adj2, g.asum, g.tslot, YT, ZT,
+                       g.fin_list + g.n_fin_hub, n_wave, 0, mean, inv_std, X, lnN);
   return hipGetLastError();
 }
 

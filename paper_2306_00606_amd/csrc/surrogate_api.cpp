@@ -270,7 +270,7 @@ ef_status ef_features(ef_graph *h, float *X, float *lnN, uint32_t flags, void *h
   const bool dev = (flags & EF_OUT_DEVICE) != 0;
   float *Xd = dev ? X : (float *)take(sizeof(float) * kNF * n);
   float *Ld = (dev && lnN) ? lnN : (float *)take(sizeof(float) * n);
-  e = launch_triangles(g, EF_PREC_FP32C, Y, YT, Z, ZT, st);
+  e = launch_triangles_count(g, Y, YT, ZT, st);
   if (e == hipSuccess) e = launch_features(g, YT, ZT, nullptr, nullptr, Xd, Ld, st);
   if (e == hipSuccess && !dev) {
     e = hipMemcpyAsync(X, Xd, sizeof(float) * kNF * n, hipMemcpyDeviceToHost, st);
@@ -490,7 +490,7 @@ ef_status ef_surrogate_predict(ef_surrogate *s, ef_graph *h, double *ef_pred, ui
   float *Ld = (float *)take(sizeof(float) * n);
   const bool dev = (flags & EF_OUT_DEVICE) != 0;
   double *Ed = dev ? ef_pred : (double *)take(sizeof(double) * n);
-  e = launch_triangles(g, EF_PREC_FP32C, Y, YT, Z, ZT, st);
+  e = launch_triangles_count(g, Y, YT, ZT, st);
   if (e == hipSuccess) e = launch_features(g, YT, ZT, s->dmean, s->dinv, Xd, Ld, st);
   if (e == hipSuccess) e = launch_mlp_forward(Xd, (int64_t)n, s->dP, s->dpack, Ld, nullptr, Ed, st);
   if (e == hipSuccess && !dev)

@@ -74,6 +74,31 @@ template <> struct Credit<double> {
   }
 };
 
+// Count-only pass (triangle counts per node and up-arc, no score terms): a
+// tag type whose sums, deltas and credits reduce to counting.
+struct TriCount {};
+struct NoSum {};
+__device__ __forceinline__ NoSum wave_sum(NoSum x) { return x; }
+__device__ __forceinline__ void acc_merge(NoSum &, NoSum) {}
+template <> struct SumT<TriCount> {
+  using type = NoSum;
+  __device__ static void add_term(NoSum &, TriCount) {}
+  __device__ static void store(const NoSum &, void *, int64_t) {}
+};
+template <> __device__ __forceinline__ TriCount tri_delta<TriCount>(int32_t) { return TriCount{}; }
+__device__ __forceinline__ long long to_fix(TriCount) { return 0; }
+template <> struct Credit<TriCount> {
+  static constexpr bool kPacked = true;
+  __device__ static void add(unsigned long long *acc, int32_t *, int32_t slot, TriCount) {
+    atomicAdd(&acc[slot], 1ull << 44);
+  }
+  __device__ static void load(const unsigned long long *acc, const int32_t *, int32_t slot,
+                              long long &y, int32_t &yt) {
+    y = 0;
+    yt = (int32_t)(acc[slot] >> 44);
+  }
+};
+
 // LDS state of one u:
 //   htab[SLOTS]   {x, k_x << kPosBits | position of x in up(u)}, x = -1 empty
 //   seg[MAXM]     per non-empty up(w): {first index of up(w) in up_col minus
@@ -170,28 +195,27 @@ __device__ __forceinline__ void tri_walk(const int32_t *__restrict__ up_col,
   using S = SumT<T>;
   constexpr int kShift = 32 - __builtin_ctz(SLOTS);
   constexpr int32_t kPosMask = (1 << kPosBits) - 1;
-  if (beg >= end) return;
-  const int lane = threadIdx.x & 63;
-  int32_t s0 = seg_find(L.segp, nseg, beg);
-  for (int32_t c = beg; c < end; c += 64) {
-    const int32_t sg = seg_step(L.segp, nseg, c, s0, flg);
-    const int32_t idx = c + lane;
-    if (idx < end) {
-      const int2 sv = L.seg[sg];
-      const int32_t x = up_col[sv.x + idx];
-      uint32_t h = hash32((uint32_t)x) >> kShift;
-      int2 e;
-      while ((e = L.htab[h]).x != x && e.x != -1) h = (h + 1) & (SLOTS - 1);
-      if (e.x == x) {
-        const T dl = tri_delta<T>(ku + unpack_k(sv.y) + unpack_k(e.y));
-        S::add_term(accu, dl);
-        ++cntu;
-        Credit<T>::add(L.acc, L.cnt, e.y & kPosMask, dl);
-        Credit<T>::add(L.acc, L.cnt, sv.y & kPosMask, dl);
-      }
-    }
-    wave_sync();
-  }
+  const int2 *seg = L.seg;
+  const int2 *htab = L.htab;
+  seg_walk<4>(
+      L.segp, nseg, beg, end, flg,
+      [&](int32_t sg, int32_t idx) {
+        const int2 sv = seg[sg];
+        return make_int2(up_col[sv.x + idx], sv.y);
+      },
+      [&](int32_t, int32_t, int2 xv) {
+        const int32_t x = xv.x;
+        uint32_t h = hash32((uint32_t)x) >> kShift;
+        int2 e;
+        while ((e = htab[h]).x != x && e.x != -1) h = (h + 1) & (SLOTS - 1);
+        if (e.x == x) {
+          const T dl = tri_delta<T>(ku + unpack_k(xv.y) + unpack_k(e.y));
+          S::add_term(accu, dl);
+          ++cntu;
+          Credit<T>::add(L.acc, L.cnt, e.y & kPosMask, dl);
+          Credit<T>::add(L.acc, L.cnt, xv.y & kPosMask, dl);
+        }
+      });
 }
 
 template <typename T, int SLOTS, int MAXM>
@@ -427,6 +451,12 @@ static hipError_t tri_impl(const Graph &g, const int32_t *const *lists, const in
     hipLaunchKernelGGL(k_tri_long<T>, dim3(cap_blocks(counts[3], 1 << 20)), dim3(64), 0, st,
                        g.up_ptr, g.up_col, g.deg, lists[3], counts[3], Y, YT, Z, ZT);
   return hipGetLastError();
+}
+
+hipError_t launch_triangles_count(const Graph &g, long long *Y, int32_t *YT, int64_t *ZT,
+                                  hipStream_t st) {
+  const int32_t *lists[4] = {g.tri_list[0], g.tri_list[1], g.tri_list[2], g.tri_list[3]};
+  return tri_impl<TriCount>(g, lists, g.n_tri, Y, YT, nullptr, ZT, st);
 }
 
 hipError_t launch_triangles(const Graph &g, ef_prec prec, long long *Y, int32_t *YT, void *Z,
