@@ -90,6 +90,13 @@ template <> __device__ __forceinline__ float score_t<float>(int32_t d) {
 template <> __device__ __forceinline__ double score_t<double>(int32_t d) {
   return d > 0 ? score_d((double)d) : 0.0;
 }
+// g(d) for d >= 0 given as a float/double, without a branch: the log of
+// max(d, 1) makes g(0) = 0 (and any negative d, whose result is unused, 0).
+__device__ __forceinline__ float score_nn(float d) {
+  return d * __builtin_amdgcn_logf(fmaxf(d, 1.0f));
+}
+__device__ __forceinline__ double score_nn(double d) { return d * log(fmax(d, 1.0)); }
+
 template <typename T> __device__ __forceinline__ T tri_delta(int32_t sigma) {
   return score_t<T>(sigma - 6) - score_t<T>(sigma - 4);
 }
@@ -118,41 +125,61 @@ __device__ __forceinline__ int32_t seg_find(const int32_t *segp, int32_t nseg, i
   return lo;
 }
 
-// One step at entries c .. c+63 with s0 the segment holding entry c: returns
-// the segment of this lane's entry c + lane (meaningful for c + lane < total)
-// and advances s0 to the segment holding entry c + 64. flg is this
-// wavefront's 64-word LDS scratch, all zero on entry and on return. The
-// starts of segments s0+1 .. s0+64 inside the step are flagged in LDS and
-// read back as a ballot; p == 64 marks a start at the next step, lanes past
-// nseg take p = 65 (no segment).
+// Per-wavefront LDS scratch of seg_step: 64 flags plus a dummy slot.
+constexpr int kFlg = 72;
+
+// One step at entries c .. c+63 with s0 the segment holding entry c (c, s0
+// and nseg uniform): returns the segment of this lane's entry c + lane
+// (meaningful for c + lane < total) and advances s0 to the segment holding
+// entry c + 64. flg is this wavefront's kFlg-word LDS scratch; flags 0..63
+// are zero on entry and on return. The starts of segments s0+1 .. s0+64
+// inside the step are flagged in LDS and read back as a ballot; p == 64
+// marks a start at the next step, lanes past nseg take p = 65 (no segment).
+// Branch-free: out-of-step flags land in the dummy slot 64.
 __device__ __forceinline__ int32_t seg_step(const int32_t *segp, int32_t nseg, int32_t c,
                                             int32_t &s0, int32_t *flg) {
   const int lane = threadIdx.x & 63;
   wave_sync();  // the previous step's clearing of flg is complete
-  const unsigned long long le_mask = ~0ull >> (63 - lane);
   const int32_t s = s0 + 1 + lane;
-  const int32_t p = (s <= nseg) ? segp[s] - c : 65;
-  if (p < 64) flg[p] = 1;
+  const int32_t sp = segp[s < nseg ? s : nseg];
+  const int32_t p = s <= nseg ? sp - c : 65;
+  flg[p < 64 ? p : 64] = 1;
   wave_sync();
   const int32_t f = flg[lane];
   flg[lane] = 0;
   const unsigned long long starts = __ballot(f != 0);
-  const int32_t sg = s0 + __popcll(starts & le_mask);
-  s0 += __popcll(starts) + (int32_t)(__ballot(p == 64) != 0ull);
+  const int32_t sg = s0 + (int32_t)__builtin_amdgcn_mbcnt_hi(
+                              (uint32_t)(starts >> 32),
+                              __builtin_amdgcn_mbcnt_lo((uint32_t)starts, 0u)) +
+                     (f != 0);
+  s0 = __builtin_amdgcn_readfirstlane(s0 + __popcll(starts) +
+                                      (int32_t)(__ballot(p == 64) != 0ull));
   return sg;
 }
 
 // Walk entries [beg, end) with one wavefront, U steps of 64 per round: the
 // segments of all U steps are found first, then every step's load is issued
 // (U loads in flight per lane), then the entries are used.
-//   load(seg, idx) -> V   reads what entry idx of segment seg needs
-//   use(seg, idx, V)      consumes it
-template <int U, typename Load, typename Use>
+//   load(seg, idx) -> V   reads what entry idx of segment seg needs (lanes
+//                         with idx < end only)
+//   use(seg, idx, V, ok)  consumes it; called on every lane of the wavefront,
+//                         ok = (idx < end), V undefined when !ok (so use may
+//                         run wavefront-wide operations such as ballots)
+//   flush()               after each round (e.g. folds per-round partial sums)
+struct NoFlush {
+  __device__ void operator()() const {}
+};
+template <int U, typename Load, typename Use, typename Flush = NoFlush>
 __device__ __forceinline__ void seg_walk(const int32_t *segp, int32_t nseg, int32_t beg,
-                                         int32_t end, int32_t *flg, Load load, Use use) {
+                                         int32_t end, int32_t *flg, Load load, Use use,
+                                         Flush flush = Flush()) {
+  // uniform bounds in scalar registers: the step conditions become scalar branches
+  beg = __builtin_amdgcn_readfirstlane(beg);
+  end = __builtin_amdgcn_readfirstlane(end);
+  nseg = __builtin_amdgcn_readfirstlane(nseg);
   if (beg >= end) return;
   const int lane = threadIdx.x & 63;
-  int32_t s0 = seg_find(segp, nseg, beg);
+  int32_t s0 = __builtin_amdgcn_readfirstlane(seg_find(segp, nseg, beg));
   for (int32_t c = beg; c < end; c += 64 * U) {
     int32_t sg[U];
 #pragma unroll
@@ -166,8 +193,9 @@ __device__ __forceinline__ void seg_walk(const int32_t *segp, int32_t nseg, int3
 #pragma unroll
     for (int q = 0; q < U; ++q) {
       const int32_t idx = c + 64 * q + lane;
-      if (idx < end) use(sg[q], idx, v[q]);
+      use(sg[q], idx, v[q], idx < end);
     }
+    flush();
   }
   wave_sync();
 }

@@ -49,7 +49,8 @@ constexpr int kTriLongMin = kTriBin2 + 1;
 //   2: k <= kSeedBin2                          one workgroup (16 wavefronts)
 //   3: k <= kSeedBin3                          one workgroup, 64 KB LDS hash
 //   4: larger                                  one workgroup, bitmap of N(s)
-// Hash tables have twice as many slots as keys. Neighbour rows are walked in
+// Hash tables have four times as many slots as keys (twice in bin 3), so a
+// miss rarely probes more than a few slots. Neighbour rows are walked in
 // chunks of at most kSeedChunk neighbours.
 constexpr int kSeedBins = 5;
 constexpr int kSeedBin0 = 64, kSeedBin1 = 512, kSeedBin2 = 2048, kSeedBin3 = 8192;

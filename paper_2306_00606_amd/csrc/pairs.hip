@@ -32,7 +32,7 @@ constexpr float kNegF = -1.0e9f;
 // wave rotate: lane l receives the value of lane (l + 1) mod 64
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int rot1i(int x) {
-  return __builtin_amdgcn_update_dpp(0, x, 0x134, 0xf, 0xf, false);
+  return __builtin_amdgcn_mov_dpp(x, 0x134, 0xf, 0xf, false);
 }
 __device__ __forceinline__ float rot1(float x) { return __int_as_float(rot1i(__float_as_int(x))); }
 __device__ __forceinline__ double rot1(double x) {
@@ -137,9 +137,9 @@ __device__ __forceinline__ void tile(T cp, T kq, T &Rt, T &C) {
 template <int S>
 __device__ __forceinline__ int rot_seg_i(int x) {
   if constexpr (S == 64) {
-    return __builtin_amdgcn_update_dpp(0, x, 0x134, 0xf, 0xf, false);  // wave_rol:1
+    return __builtin_amdgcn_mov_dpp(x, 0x134, 0xf, 0xf, false);  // wave_rol:1
   } else if constexpr (S == 16) {
-    return __builtin_amdgcn_update_dpp(0, x, 0x12F, 0xf, 0xf, false);  // row_ror:15
+    return __builtin_amdgcn_mov_dpp(x, 0x12F, 0xf, 0xf, false);  // row_ror:15
   } else {
     const int lane = threadIdx.x & 63;
     const int src = (lane & ~(S - 1)) | ((lane + 1) & (S - 1));

@@ -431,6 +431,11 @@ __device__ __forceinline__ void seed_walk(const int2 *__restrict__ adj2, const i
                                           int64_t &Nn) {
   using S = SumT<T>;
   constexpr int kShift = 32 - __builtin_ctz(SLOTS);
+  // per-round partials: at most 4 terms per lane, folded into the compensated
+  // and 64-bit sums after each round (d < 3 * kMaxDegree, so 4 fit in int32)
+  static_assert(4LL * 3 * kMaxDegree < (1LL << 31), "per-round degree sum overflows");
+  T rs = T(0);
+  int32_t rd = 0, rn = 0;
   seg_walk<4>(
       segp, nseg, beg, end, flg,
       [&](int32_t sg, int32_t idx) {
@@ -438,9 +443,9 @@ __device__ __forceinline__ void seed_walk(const int2 *__restrict__ adj2, const i
         const int2 bd = adj2[sv.x + idx];
         return make_int3(bd.x, bd.y, sv.y);
       },
-      [&](int32_t, int32_t, int3 e) {
+      [&](int32_t, int32_t, int3 e, bool ok) {
         const int32_t b = e.x;
-        if (b == s) return;
+        if (!ok || b == s) return;
         bool m;
         if constexpr (BITMAP) {
           m = (bm[b >> 5] >> (b & 31)) & 1u;
@@ -450,16 +455,25 @@ __device__ __forceinline__ void seed_walk(const int2 *__restrict__ adj2, const i
           while ((key = hkey[h]) != b && key != -1) h = (h + 1) & (SLOTS - 1);
           m = key == b;
         }
+        // path s-a-b has degree sigma - 4, less 2 if b ~ s; then the star
+        // (a, b) with a ~ b, which the pair loop scored with degree sigma - 4,
+        // takes delta(sigma) = g(sigma - 6) - g(sigma - 4). Together, for a
+        // member b: 2 g(sigma - 6) - g(sigma - 4); both logs on every lane
+        // (no divergent branch).
         const int32_t sigma = k + e.z + e.y;
-        const int32_t d = sigma - 4 - (m ? 2 : 0);
-        S::add_term(sacc, score_t<T>(d));
-        Dd += d;
-        Nn += 1;
-        if (m) {
-          // star (a, b) with a ~ b: the pair loop scored it with degree sigma - 4
-          S::add_term(sacc, tri_delta<T>(sigma));
-          Dd -= 2;
-        }
+        const T sf = (T)sigma;  // exact: sigma < 2^24
+        const T g4 = score_nn(sf - T(4)), g6 = score_nn(sf - T(6));
+        rs += m ? T(2) * g6 - g4 : g4;
+        rd += sigma - 4 - (m ? 4 : 0);
+        rn += 1;
+      },
+      [&]() {
+        S::add_term(sacc, rs);
+        Dd += rd;
+        Nn += rn;
+        rs = T(0);
+        rd = 0;
+        rn = 0;
       });
 }
 
@@ -491,7 +505,7 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_wave(
   __shared__ int32_t hkey_s[WPB][SLOTS];
   __shared__ int2 seg_s[WPB][MAXK];
   __shared__ int32_t segp_s[WPB][MAXK + 1];
-  __shared__ int32_t flg_s[WPB][64];
+  __shared__ int32_t flg_s[WPB][kFlg];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   int32_t *hkey = hkey_s[wv];
   int32_t *flg = flg_s[wv];
@@ -540,7 +554,7 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_block(
   __shared__ int32_t hkey[BITMAP ? 1 : SLOTS];
   __shared__ int2 seg[MAXK];
   __shared__ int32_t segp[MAXK + 1];
-  __shared__ int32_t flg_s[WPB][64];
+  __shared__ int32_t flg_s[WPB][kFlg];
   __shared__ int32_t part[WPB];
   __shared__ Acc shA[WPB];
   __shared__ int64_t shD[WPB], shN[WPB];
@@ -602,17 +616,17 @@ static void per_seed_impl(const Graph &g, const int32_t *seeds, const int32_t *c
                           int64_t words, double *ef, int64_t *D, int64_t *N, uint8_t *fl,
                           hipStream_t st) {
   if (counts[0] > 0)
-    hipLaunchKernelGGL((k_seed_wave<T, 2 * kSeedBin0, kSeedBin0, 4>),
+    hipLaunchKernelGGL((k_seed_wave<T, 4 * kSeedBin0, kSeedBin0, 4>),
                        dim3(cap_blocks((counts[0] + 3) / 4, 1 << 20)), dim3(256), 0, st,
                        g.row_ptr, g.deg, g.adj2, g.asum, seeds, lists[0], counts[0], R, ef, D, N,
                        fl);
   if (counts[1] > 0)
-    hipLaunchKernelGGL((k_seed_block<T, 2 * kSeedBin1, kSeedBin1, 8, false>),
+    hipLaunchKernelGGL((k_seed_block<T, 4 * kSeedBin1, kSeedBin1, 8, false>),
                        dim3(cap_blocks(counts[1], 1 << 20)), dim3(512), 0, st, g.row_ptr, g.deg,
                        g.adj2, g.asum, seeds, lists[1], counts[1], R, nullptr, words, ef, D, N,
                        fl);
   if (counts[2] > 0)
-    hipLaunchKernelGGL((k_seed_block<T, 2 * kSeedBin2, kSeedChunk, 16, false>),
+    hipLaunchKernelGGL((k_seed_block<T, 4 * kSeedBin2, kSeedChunk, 16, false>),
                        dim3(cap_blocks(counts[2], 1 << 20)), dim3(1024), 0, st, g.row_ptr,
                        g.deg, g.adj2, g.asum, seeds, lists[2], counts[2], R, nullptr, words, ef,
                        D, N, fl);

@@ -106,7 +106,7 @@ template <> struct Credit<TriCount> {
 //                 k_w << kPosBits | position of w in up(u)}
 //   segp[MAXM+1]  first concatenated index of each segment; segp[nseg] = total
 //   acc, cnt      credit slots by position in up(u)
-//   flg[64]       per wavefront: segment-start flags of the current step
+//   flg[kFlg]     per wavefront: segment-start flags of the current step
 template <typename T, int SLOTS, int MAXM> struct TriLds {
   int2 htab[SLOTS];
   int2 seg[MAXM];
@@ -184,38 +184,72 @@ __device__ __forceinline__ void tri_setup(const int32_t *__restrict__ up_ptr,
   total_out = run;
 }
 
-// Walk entries [beg, end) of the concatenated sequence with one wavefront,
-// 64 consecutive entries per step. The segment of each lane comes from the
-// segment starts inside the step, flagged in LDS and read back as a ballot.
+// One wavefront walks entries [beg, end) of u's concatenated up(w) lists,
+// 64 consecutive entries per step (segment of each lane: seg_walk). A hit
+// (x in up(u)) is appended to the wavefront's LDS queue as one word
+// (sigma | pos(w) << 22 | pos(x) << 34); whenever 64 hits are queued they are
+// scored and credited with every lane busy, so the hit path does not run
+// divergently on almost every step (about 6% of the entries are hits).
+constexpr int kQueue = 128;
+static_assert(3LL * kMaxDegree < (1LL << 22), "sigma field too narrow");
+
 template <typename T, int SLOTS, int MAXM>
 __device__ __forceinline__ void tri_walk(const int32_t *__restrict__ up_col,
-                                         TriLds<T, SLOTS, MAXM> &L, int32_t *flg, int32_t nseg,
-                                         int32_t beg, int32_t end, int32_t ku,
+                                         TriLds<T, SLOTS, MAXM> &L, int32_t *flg,
+                                         unsigned long long *hq, int32_t nseg, int32_t beg,
+                                         int32_t end, int32_t ku,
                                          typename SumT<T>::type &accu, int64_t &cntu) {
   using S = SumT<T>;
   constexpr int kShift = 32 - __builtin_ctz(SLOTS);
   constexpr int32_t kPosMask = (1 << kPosBits) - 1;
+  const int lane = threadIdx.x & 63;
+  const unsigned long long lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   const int2 *seg = L.seg;
   const int2 *htab = L.htab;
+  int32_t qn = 0;  // queued hits (uniform)
+  // score and credit hq[qn - cnt .. qn) on lanes 0 .. cnt-1
+  auto drain = [&](int32_t cnt) {
+    wave_sync();
+    if (lane < cnt) {
+      const unsigned long long h = hq[qn - cnt + lane];
+      const int32_t sigma = (int32_t)(h & 0x3FFFFFull);
+      const int32_t pw = (int32_t)((h >> 22) & kPosMask), px = (int32_t)((h >> 34) & kPosMask);
+      const T dl = tri_delta<T>(sigma);
+      S::add_term(accu, dl);
+      ++cntu;
+      Credit<T>::add(L.acc, L.cnt, px, dl);
+      Credit<T>::add(L.acc, L.cnt, pw, dl);
+    }
+    qn -= cnt;
+    wave_sync();
+  };
   seg_walk<4>(
       L.segp, nseg, beg, end, flg,
       [&](int32_t sg, int32_t idx) {
         const int2 sv = seg[sg];
         return make_int2(up_col[sv.x + idx], sv.y);
       },
-      [&](int32_t, int32_t, int2 xv) {
-        const int32_t x = xv.x;
-        uint32_t h = hash32((uint32_t)x) >> kShift;
-        int2 e;
-        while ((e = htab[h]).x != x && e.x != -1) h = (h + 1) & (SLOTS - 1);
-        if (e.x == x) {
-          const T dl = tri_delta<T>(ku + unpack_k(xv.y) + unpack_k(e.y));
-          S::add_term(accu, dl);
-          ++cntu;
-          Credit<T>::add(L.acc, L.cnt, e.y & kPosMask, dl);
-          Credit<T>::add(L.acc, L.cnt, xv.y & kPosMask, dl);
+      [&](int32_t, int32_t, int2 xv, bool ok) {
+        int2 e = make_int2(-1, 0);
+        if (ok) {
+          const int32_t x = xv.x;
+          uint32_t h = hash32((uint32_t)x) >> kShift;
+          while ((e = htab[h]).x != x && e.x != -1) h = (h + 1) & (SLOTS - 1);
+          if (e.x != x) e.x = -1;
         }
+        const bool hit = e.x >= 0;
+        const unsigned long long m = __ballot(hit);
+        if (hit) {
+          const int32_t sigma = ku + unpack_k(xv.y) + unpack_k(e.y);
+          hq[qn + __popcll(m & lt_mask)] =
+              (unsigned long long)sigma |
+              ((unsigned long long)(xv.y & kPosMask) << 22) |
+              ((unsigned long long)(e.y & kPosMask) << 34);
+        }
+        qn += __popcll(m);
+        if (qn >= 64) drain(64);
       });
+  if (qn > 0) drain(qn);
 }
 
 template <typename T, int SLOTS, int MAXM>
@@ -250,7 +284,8 @@ __global__ __launch_bounds__(64 * WPB) void k_tri_wave(
   using S = SumT<T>;
   using Acc = typename S::type;
   __shared__ TriLds<T, SLOTS, MAXM> lds[WPB];
-  __shared__ int32_t flg_s[WPB][64];
+  __shared__ int32_t flg_s[WPB][kFlg];
+  __shared__ unsigned long long hq_s[WPB][kQueue];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   TriLds<T, SLOTS, MAXM> &L = lds[wv];
   int32_t *flg = flg_s[wv];
@@ -267,7 +302,7 @@ __global__ __launch_bounds__(64 * WPB) void k_tri_wave(
     wave_sync();
     Acc accu = Acc();
     int64_t cntu = 0;
-    tri_walk<T, SLOTS, MAXM>(up_col, L, flg, nseg, 0, total, ku, accu, cntu);
+    tri_walk<T, SLOTS, MAXM>(up_col, L, flg, hq_s[wv], nseg, 0, total, ku, accu, cntu);
     accu = wave_sum(accu);
     cntu = wave_sum_i64(cntu);
     if (lane == 0) {
@@ -291,7 +326,8 @@ __global__ __launch_bounds__(64 * WPB) void k_tri_block(
   using Acc = typename S::type;
   constexpr int NT = 64 * WPB;
   __shared__ TriLds<T, SLOTS, MAXM> L;
-  __shared__ int32_t flg_s[WPB][64];
+  __shared__ int32_t flg_s[WPB][kFlg];
+  __shared__ unsigned long long hq_s[WPB][kQueue];
   __shared__ int32_t part[2 * WPB];
   __shared__ Acc sh_acc[WPB];
   __shared__ int64_t sh_cnt[WPB];
@@ -313,8 +349,8 @@ __global__ __launch_bounds__(64 * WPB) void k_tri_block(
     const int32_t fin = (int32_t)(((int64_t)steps * (wv + 1) / WPB) << 6);
     Acc accu = Acc();
     int64_t cntu = 0;
-    tri_walk<T, SLOTS, MAXM>(up_col, L, flg, nseg, beg, fin < total ? fin : total, ku, accu,
-                             cntu);
+    tri_walk<T, SLOTS, MAXM>(up_col, L, flg, hq_s[wv], nseg, beg, fin < total ? fin : total, ku,
+                             accu, cntu);
     accu = wave_sum(accu);
     cntu = wave_sum_i64(cntu);
     if (lane == 0) {
@@ -436,15 +472,15 @@ static hipError_t tri_impl(const Graph &g, const int32_t *const *lists, const in
   hipLaunchKernelGGL(k_tri_zero<T>, dim3(cap_blocks((g.n + 255) / 256, 1 << 16)), dim3(256), 0,
                      st, g.up_ptr, g.n, Y, YT, Z, ZT, kTriLongMin);
   if (counts[0] > 0)
-    hipLaunchKernelGGL((k_tri_wave<T, 128, 64, 4>), dim3(cap_blocks((counts[0] + 3) / 4, 1 << 20)),
+    hipLaunchKernelGGL((k_tri_wave<T, 256, 64, 4>), dim3(cap_blocks((counts[0] + 3) / 4, 1 << 20)),
                        dim3(256), 0, st, g.up_ptr, g.up_col, g.deg, lists[0], counts[0], Y, YT,
                        Z, ZT);
   if (counts[1] > 0)
-    hipLaunchKernelGGL((k_tri_block<T, 1024, 512, 8>), dim3(cap_blocks(counts[1], 1 << 20)),
+    hipLaunchKernelGGL((k_tri_block<T, 2048, 512, 8>), dim3(cap_blocks(counts[1], 1 << 20)),
                        dim3(512), 0, st, g.up_ptr, g.up_col, g.deg, lists[1], counts[1], Y, YT,
                        Z, ZT);
   if (counts[2] > 0)
-    hipLaunchKernelGGL((k_tri_block<T, 4096, 2048, 16>), dim3(cap_blocks(counts[2], 1 << 20)),
+    hipLaunchKernelGGL((k_tri_block<T, 8192, 2048, 16>), dim3(cap_blocks(counts[2], 1 << 20)),
                        dim3(1024), 0, st, g.up_ptr, g.up_col, g.deg, lists[2], counts[2], Y, YT,
                        Z, ZT);
   if (counts[3] > 0)
