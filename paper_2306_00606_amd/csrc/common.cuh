@@ -101,7 +101,37 @@ template <typename T> __device__ __forceinline__ T tri_delta(int32_t sigma) {
   return score_t<T>(sigma - 6) - score_t<T>(sigma - 4);
 }
 
-__device__ __forceinline__ uint32_t hash32(uint32_t x) { return x * 2654435761u; }
+// ---------------------------------------------------------------------------
+// LDS hash set of node ids, open addressing with linear probing (SLOTS a
+// power of two; empty = -1). Callers keep at most SLOTS / 2 keys (the tables
+// here run at 1/4 or 1/2): a lookup ends at the key or at a free slot, so
+// the set must never fill. Hash: multiplicative on the full-rate 24-bit
+// multiplier with the high bits folded in first (a 32-bit v_mul_lo runs at a
+// quarter of the rate). Slots are single words: a wavefront's random probes
+// touch one bank each (4-slot buckets read as 128 bits measured slower).
+// ---------------------------------------------------------------------------
+template <int SLOTS> struct LdsHash {
+  static_assert(SLOTS >= 2 && (SLOTS & (SLOTS - 1)) == 0, "SLOTS must be a power of two");
+  static constexpr int kBits = __builtin_ctz(SLOTS);
+  __device__ static __forceinline__ uint32_t home(int32_t x) {
+    const uint32_t u = (uint32_t)x;
+    const uint32_t a = (u ^ (u >> 16)) & 0xFFFFFFu;  // 24-bit operand: v_mul_u32_u24
+    return ((a * 0x9E3779u) >> (32 - kBits)) & (uint32_t)(SLOTS - 1);
+  }
+  // returns the slot taken by x (x not yet in the set)
+  __device__ static __forceinline__ int32_t insert(int32_t *keys, int32_t x) {
+    uint32_t h = home(x);
+    while (atomicCAS(&keys[h], -1, x) != -1) h = (h + 1) & (SLOTS - 1);
+    return (int32_t)h;
+  }
+  // slot of x, or -1
+  __device__ static __forceinline__ int32_t find(const int32_t *keys, int32_t x) {
+    uint32_t h = home(x);
+    int32_t key;
+    while ((key = keys[h]) != x && key != -1) h = (h + 1) & (SLOTS - 1);
+    return key == x ? (int32_t)h : -1;
+  }
+};
 
 // ---------------------------------------------------------------------------
 // Walking a concatenation of variable-length lists ("segments") with one

@@ -28,6 +28,13 @@ namespace efi {
 
 constexpr float kNegF = -1.0e9f;
 
+// orders this wavefront's LDS accesses (written by one lane, read by another)
+__device__ __forceinline__ void wave_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 // ---------------------------------------------------------------------------
 // wave rotate: lane l receives the value of lane (l + 1) mod 64
 // ---------------------------------------------------------------------------
@@ -128,6 +135,27 @@ __device__ __forceinline__ void tile(T cp, T kq, T &Rt, T &C) {
   }
 }
 
+// Full off-diagonal tile with the column degrees read from LDS instead of
+// rotated through the wavefront: kd points at this lane's entry of a doubled
+// copy of the 64 column degrees (kd[s] = degree of column (lane + s) mod 64),
+// so step s needs no rotation of the degree, only of the column accumulator.
+// Same result layout as tile<T, false, false>.
+template <typename T>
+__device__ __forceinline__ void tile_lds(T cp, const T *kd, T &Rt, T &C) {
+  Rt = T(0);
+  C = T(0);
+  for (int s0 = 0; s0 < 64; s0 += 16) {
+    const T *kp = kd + s0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const T d = cp + kp[j];
+      const T g = score(d);
+      Rt += g;
+      C = rot1(C) + g;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // small centres: segments of S lanes (S = 8, 16, 32, 64), one centre of
 // degree k <= S per segment, 64/S centres per wavefront. The diagonal tile of
@@ -214,7 +242,7 @@ __device__ __forceinline__ T col_degree(const int2 *adj2, int32_t base, int32_t 
 // complete sum for index 64*(blk0+w)+lane over all pairs inside this range.
 template <typename T>
 __device__ void diag_super(const int2 *adj2, int32_t base, int32_t k, T kv4, int blk0, int nb,
-                           T (*parts)[9][64], Acc<T> &out) {
+                           T (*parts)[9][64], T (*kdeg)[128], Acc<T> &out) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (w < nb) {
     const int32_t p = 64 * (blk0 + w) + lane;
@@ -235,8 +263,15 @@ __device__ void diag_super(const int2 *adj2, int32_t base, int32_t k, T kv4, int
         const int32_t q = 64 * (blk0 + c) + lane;
         const T kq = col_degree<T>(adj2, base, k, q);
         const bool masked = ragged && (c == nb - 1 || w == nb - 1) && (blk0 + nb) * 64 > k;
-        if (masked) tile<T, false, true>(cp, kq, Rt, C);
-        else tile<T, false, false>(cp, kq, Rt, C);
+        if (masked) {
+          tile<T, false, true>(cp, kq, Rt, C);
+        } else {
+          kdeg[w][lane] = kq;
+          kdeg[w][64 + lane] = kq;
+          wave_fence();
+          tile_lds<T>(cp, &kdeg[w][lane], Rt, C);
+          wave_fence();
+        }
         parts[c][dl][(lane + 63) & 63] = C;
       }
       out.add(Rt);
@@ -263,6 +298,7 @@ __global__ __launch_bounds__(1024) void k_pairs_mid(const int32_t *__restrict__ 
                                                     const int2 *__restrict__ adj2,
                                                     const int32_t *__restrict__ list,
                                                     int64_t count, void *__restrict__ R) {
+  __shared__ T kdeg[kBlocksPerSuper][128];
   __shared__ T parts[kBlocksPerSuper][9][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int64_t it = blockIdx.x; it < count; it += gridDim.x) {
@@ -273,7 +309,7 @@ __global__ __launch_bounds__(1024) void k_pairs_mid(const int32_t *__restrict__ 
     zero_parts(&parts[0][0][0], nb * 9 * 64);
     __syncthreads();
     Acc<T> out;
-    diag_super<T>(adj2, base, k, (T)(k - 4), 0, nb, parts, out);
+    diag_super<T>(adj2, base, k, (T)(k - 4), 0, nb, parts, kdeg, out);
     const int32_t p = 64 * w + lane;
     if (w < nb && p < k) out.store(R, base + p);
     __syncthreads();
@@ -292,6 +328,7 @@ __global__ __launch_bounds__(1024) void k_pairs_big(const int32_t *__restrict__ 
                                                     const BigCentre *__restrict__ big,
                                                     const TileItem *__restrict__ tiles,
                                                     int64_t count, void *__restrict__ rec) {
+  __shared__ T kdeg[kBlocksPerSuper][128];  // per wavefront: doubled column degrees
   __shared__ T parts[kBlocksPerSuper][kBlocksPerSuper][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int64_t it = blockIdx.x; it < count; it += gridDim.x) {
@@ -308,7 +345,7 @@ __global__ __launch_bounds__(1024) void k_pairs_big(const int32_t *__restrict__ 
       __syncthreads();
       Acc<T> out;
       diag_super<T>(adj2, base, k, kv4, kBlocksPerSuper * P, nbQ,
-                    reinterpret_cast<T(*)[9][64]>(&parts[0][0][0]), out);
+                    reinterpret_cast<T(*)[9][64]>(&parts[0][0][0]), kdeg, out);
       if (w < nbQ) out.store(rec, rbase + 64 * w + lane);
     } else {
       // P < Q: all 16 row blocks of P are full
@@ -321,8 +358,15 @@ __global__ __launch_bounds__(1024) void k_pairs_big(const int32_t *__restrict__ 
         const int32_t q = kSuper * Q + 64 * c + lane;
         const T kq = col_degree<T>(adj2, base, k, q);
         T Rt, C;
-        if (ragged_q && c == nbQ - 1) tile<T, false, true>(cp, kq, Rt, C);
-        else tile<T, false, false>(cp, kq, Rt, C);
+        if (ragged_q && c == nbQ - 1) {
+          tile<T, false, true>(cp, kq, Rt, C);
+        } else {
+          kdeg[w][lane] = kq;
+          kdeg[w][64 + lane] = kq;
+          wave_fence();
+          tile_lds<T>(cp, &kdeg[w][lane], Rt, C);
+          wave_fence();
+        }
         parts[c][w][(lane + 63) & 63] = C;
         out.add(Rt);
       }

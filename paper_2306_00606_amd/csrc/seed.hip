@@ -416,9 +416,7 @@ __device__ __forceinline__ int32_t seed_chunk_setup(const int32_t *__restrict__ 
 
 template <int SLOTS>
 __device__ __forceinline__ void hash_insert(int32_t *hkey, int32_t x) {
-  constexpr int kShift = 32 - __builtin_ctz(SLOTS);
-  uint32_t h = hash32((uint32_t)x) >> kShift;
-  while (atomicCAS(&hkey[h], -1, x) != -1) h = (h + 1) & (SLOTS - 1);
+  (void)LdsHash<SLOTS>::insert(hkey, x);
 }
 
 // one wavefront walks entries [beg, end) of the current chunk
@@ -430,7 +428,6 @@ __device__ __forceinline__ void seed_walk(const int2 *__restrict__ adj2, const i
                                           typename SumT<T>::type &sacc, int64_t &Dd,
                                           int64_t &Nn) {
   using S = SumT<T>;
-  constexpr int kShift = 32 - __builtin_ctz(SLOTS);
   // per-round partials: at most 4 terms per lane, folded into the compensated
   // and 64-bit sums after each round (d < 3 * kMaxDegree, so 4 fit in int32)
   static_assert(4LL * 3 * kMaxDegree < (1LL << 31), "per-round degree sum overflows");
@@ -450,10 +447,7 @@ __device__ __forceinline__ void seed_walk(const int2 *__restrict__ adj2, const i
         if constexpr (BITMAP) {
           m = (bm[b >> 5] >> (b & 31)) & 1u;
         } else {
-          uint32_t h = hash32((uint32_t)b) >> kShift;
-          int32_t key;
-          while ((key = hkey[h]) != b && key != -1) h = (h + 1) & (SLOTS - 1);
-          m = key == b;
+          m = LdsHash<SLOTS>::find(hkey, b) >= 0;
         }
         // path s-a-b has degree sigma - 4, less 2 if b ~ s; then the star
         // (a, b) with a ~ b, which the pair loop scored with degree sigma - 4,
@@ -502,7 +496,7 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_wave(
     int64_t *__restrict__ Nout, uint8_t *__restrict__ fl) {
   using S = SumT<T>;
   using Acc = typename S::type;
-  __shared__ int32_t hkey_s[WPB][SLOTS];
+  __shared__ __align__(16) int32_t hkey_s[WPB][SLOTS];
   __shared__ int2 seg_s[WPB][MAXK];
   __shared__ int32_t segp_s[WPB][MAXK + 1];
   __shared__ int32_t flg_s[WPB][kFlg];
@@ -551,7 +545,7 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_block(
   using S = SumT<T>;
   using Acc = typename S::type;
   constexpr int NT = 64 * WPB;
-  __shared__ int32_t hkey[BITMAP ? 1 : SLOTS];
+  __shared__ __align__(16) int32_t hkey[BITMAP ? 4 : SLOTS];
   __shared__ int2 seg[MAXK];
   __shared__ int32_t segp[MAXK + 1];
   __shared__ int32_t flg_s[WPB][kFlg];
@@ -610,28 +604,35 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_block(
   }
 }
 
+// slots of the LDS hash set of N(s) per bin (bin 4 uses bitmaps); a set
+// holds at most half its slots
+constexpr int kSeedSlots[4] = {4 * kSeedBin0, 4 * kSeedBin1, 4 * kSeedBin2, 2 * kSeedBin3};
+static_assert(kSeedSlots[0] >= 2 * kSeedBin0 && kSeedSlots[1] >= 2 * kSeedBin1 &&
+                  kSeedSlots[2] >= 2 * kSeedBin2 && kSeedSlots[3] >= 2 * kSeedBin3,
+              "per-seed hash sets must stay at most half full");
+
 template <typename T>
 static void per_seed_impl(const Graph &g, const int32_t *seeds, const int32_t *const *lists,
                           const int64_t *counts, const void *R, const uint32_t *bitmaps,
                           int64_t words, double *ef, int64_t *D, int64_t *N, uint8_t *fl,
                           hipStream_t st) {
   if (counts[0] > 0)
-    hipLaunchKernelGGL((k_seed_wave<T, 4 * kSeedBin0, kSeedBin0, 4>),
+    hipLaunchKernelGGL((k_seed_wave<T, kSeedSlots[0], kSeedBin0, 4>),
                        dim3(cap_blocks((counts[0] + 3) / 4, 1 << 20)), dim3(256), 0, st,
                        g.row_ptr, g.deg, g.adj2, g.asum, seeds, lists[0], counts[0], R, ef, D, N,
                        fl);
   if (counts[1] > 0)
-    hipLaunchKernelGGL((k_seed_block<T, 4 * kSeedBin1, kSeedBin1, 8, false>),
+    hipLaunchKernelGGL((k_seed_block<T, kSeedSlots[1], kSeedBin1, 8, false>),
                        dim3(cap_blocks(counts[1], 1 << 20)), dim3(512), 0, st, g.row_ptr, g.deg,
                        g.adj2, g.asum, seeds, lists[1], counts[1], R, nullptr, words, ef, D, N,
                        fl);
   if (counts[2] > 0)
-    hipLaunchKernelGGL((k_seed_block<T, 4 * kSeedBin2, kSeedChunk, 16, false>),
+    hipLaunchKernelGGL((k_seed_block<T, kSeedSlots[2], kSeedChunk, 16, false>),
                        dim3(cap_blocks(counts[2], 1 << 20)), dim3(1024), 0, st, g.row_ptr,
                        g.deg, g.adj2, g.asum, seeds, lists[2], counts[2], R, nullptr, words, ef,
                        D, N, fl);
   if (counts[3] > 0)
-    hipLaunchKernelGGL((k_seed_block<T, 2 * kSeedBin3, kSeedChunk, 16, false>),
+    hipLaunchKernelGGL((k_seed_block<T, kSeedSlots[3], kSeedChunk, 16, false>),
                        dim3(cap_blocks(counts[3], 1 << 20)), dim3(1024), 0, st, g.row_ptr,
                        g.deg, g.adj2, g.asum, seeds, lists[3], counts[3], R, nullptr, words, ef,
                        D, N, fl);

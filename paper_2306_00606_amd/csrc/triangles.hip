@@ -100,7 +100,8 @@ template <> struct Credit<TriCount> {
 };
 
 // LDS state of one u:
-//   htab[SLOTS]   {x, k_x << kPosBits | position of x in up(u)}, x = -1 empty
+//   hkey[SLOTS]   ids x of up(u) (LdsHash), hval[slot] = k_x << kPosBits |
+//                 position of x in up(u)
 //   seg[MAXM]     per non-empty up(w): {first index of up(w) in up_col minus
 //                 its first index in the concatenated sequence,
 //                 k_w << kPosBits | position of w in up(u)}
@@ -108,7 +109,9 @@ template <> struct Credit<TriCount> {
 //   acc, cnt      credit slots by position in up(u)
 //   flg[kFlg]     per wavefront: segment-start flags of the current step
 template <typename T, int SLOTS, int MAXM> struct TriLds {
-  int2 htab[SLOTS];
+  static_assert(SLOTS >= 2 * MAXM, "the hash set of up(u) must stay at most half full");
+  __align__(16) int32_t hkey[SLOTS];
+  int32_t hval[SLOTS];
   int2 seg[MAXM];
   int32_t segp[MAXM + 1];
   unsigned long long acc[MAXM];
@@ -122,9 +125,9 @@ template <int SLOTS, int NT>
 __device__ __forceinline__ void tri_setup(const int32_t *__restrict__ up_ptr,
                                           const int32_t *__restrict__ up_col,
                                           const int32_t *__restrict__ deg, int32_t u0, int32_t m,
-                                          int tid, int2 *htab, int2 *seg, int32_t *segp,
+                                          int tid, int32_t *hkey, int32_t *hval, int2 *seg,
+                                          int32_t *segp,
                                           int32_t *part, int32_t &nseg_out, int32_t &total_out) {
-  constexpr int kShift = 32 - __builtin_ctz(SLOTS);
   constexpr int NW = NT / 64;
   const int lane = tid & 63, wv = tid >> 6;
   const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -137,9 +140,7 @@ __device__ __forceinline__ void tri_setup(const int32_t *__restrict__ up_ptr,
       w0 = up_ptr[x];
       len = up_ptr[x + 1] - w0;
       kx = deg[x];
-      uint32_t h = hash32((uint32_t)x) >> kShift;
-      while (atomicCAS(&htab[h].x, -1, x) != -1) h = (h + 1) & (SLOTS - 1);
-      htab[h].y = pack_kp(kx, i);
+      hval[LdsHash<SLOTS>::insert(hkey, x)] = pack_kp(kx, i);
     }
     const unsigned long long nz = __ballot(len > 0);
     int32_t incl = len;
@@ -200,12 +201,12 @@ __device__ __forceinline__ void tri_walk(const int32_t *__restrict__ up_col,
                                          int32_t end, int32_t ku,
                                          typename SumT<T>::type &accu, int64_t &cntu) {
   using S = SumT<T>;
-  constexpr int kShift = 32 - __builtin_ctz(SLOTS);
   constexpr int32_t kPosMask = (1 << kPosBits) - 1;
   const int lane = threadIdx.x & 63;
   const unsigned long long lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   const int2 *seg = L.seg;
-  const int2 *htab = L.htab;
+  const int32_t *hkey = L.hkey;
+  const int32_t *hval = L.hval;
   int32_t qn = 0;  // queued hits (uniform)
   // score and credit hq[qn - cnt .. qn) on lanes 0 .. cnt-1
   auto drain = [&](int32_t cnt) {
@@ -230,21 +231,16 @@ __device__ __forceinline__ void tri_walk(const int32_t *__restrict__ up_col,
         return make_int2(up_col[sv.x + idx], sv.y);
       },
       [&](int32_t, int32_t, int2 xv, bool ok) {
-        int2 e = make_int2(-1, 0);
-        if (ok) {
-          const int32_t x = xv.x;
-          uint32_t h = hash32((uint32_t)x) >> kShift;
-          while ((e = htab[h]).x != x && e.x != -1) h = (h + 1) & (SLOTS - 1);
-          if (e.x != x) e.x = -1;
-        }
-        const bool hit = e.x >= 0;
+        const int32_t slot = ok ? LdsHash<SLOTS>::find(hkey, xv.x) : -1;
+        const bool hit = slot >= 0;
         const unsigned long long m = __ballot(hit);
         if (hit) {
-          const int32_t sigma = ku + unpack_k(xv.y) + unpack_k(e.y);
+          const int32_t ev = hval[slot];
+          const int32_t sigma = ku + unpack_k(xv.y) + unpack_k(ev);
           hq[qn + __popcll(m & lt_mask)] =
               (unsigned long long)sigma |
               ((unsigned long long)(xv.y & kPosMask) << 22) |
-              ((unsigned long long)(e.y & kPosMask) << 34);
+              ((unsigned long long)(ev & kPosMask) << 34);
         }
         qn += __popcll(m);
         if (qn >= 64) drain(64);
@@ -254,7 +250,7 @@ __device__ __forceinline__ void tri_walk(const int32_t *__restrict__ up_col,
 
 template <typename T, int SLOTS, int MAXM>
 __device__ __forceinline__ void tri_clear(TriLds<T, SLOTS, MAXM> &L, int32_t m, int tid, int nt) {
-  for (int i = tid; i < SLOTS; i += nt) L.htab[i] = make_int2(-1, 0);
+  for (int i = tid; i < SLOTS; i += nt) L.hkey[i] = -1;
   for (int i = tid; i < m; i += nt) {
     L.acc[i] = 0ull;
     if constexpr (!Credit<T>::kPacked) L.cnt[i] = 0;
@@ -297,7 +293,7 @@ __global__ __launch_bounds__(64 * WPB) void k_tri_wave(
     tri_clear(L, m, lane, 64);
     wave_sync();
     int32_t nseg, total;
-    tri_setup<SLOTS, 64>(up_ptr, up_col, deg, u0, m, lane, L.htab, L.seg, L.segp, nullptr, nseg,
+    tri_setup<SLOTS, 64>(up_ptr, up_col, deg, u0, m, lane, L.hkey, L.hval, L.seg, L.segp, nullptr, nseg,
                          total);
     wave_sync();
     Acc accu = Acc();
@@ -340,7 +336,7 @@ __global__ __launch_bounds__(64 * WPB) void k_tri_block(
     tri_clear(L, m, tid, NT);
     __syncthreads();
     int32_t nseg, total;
-    tri_setup<SLOTS, NT>(up_ptr, up_col, deg, u0, m, tid, L.htab, L.seg, L.segp, part, nseg,
+    tri_setup<SLOTS, NT>(up_ptr, up_col, deg, u0, m, tid, L.hkey, L.hval, L.seg, L.segp, part, nseg,
                          total);
     __syncthreads();
     // contiguous shares, multiples of 64 entries
