@@ -41,6 +41,13 @@ VALU_LANE_OPS_PEAK = 256 * 128 * 2.4e9
 # (v_log_f32, a transcendental at a quarter of the FMA rate: 4; multiply: 1),
 # credit to the row sum (1) and to the column sum (1).
 OPS_PER_CLUSTER = 8
+# HBM bytes per launch of k_pairs_big<float> at this workload (R-MAT scale 22,
+# edge factor 10): FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 from two rocprofv3
+# counter runs, each counter scaled by its reading on a 1 GiB copy; mostly the
+# super-tile records the kernel writes. Taken on the current kernel (the
+# counter summaries sit with the other rocprofv3 summaries); set to None
+# whenever the kernel changes.
+PAIRS_BIG_TRAFFIC_BYTES = 2.655e9
 
 
 def log(msg):
@@ -218,7 +225,9 @@ def main():
         achieved = st["pairs_big"] * OPS_PER_CLUSTER / (st["t_pairs_big_ms"] * 1e-3)
         roofline = {"bound": "alu", "kernel": "k_pairs_big<float>",
                     "achieved": achieved / 1e12, "peak": VALU_LANE_OPS_PEAK / 1e12,
-                    "unit": "TOP/s", "frac": achieved / VALU_LANE_OPS_PEAK, "traffic": None,
+                    "unit": "TOP/s", "frac": achieved / VALU_LANE_OPS_PEAK,
+                    "traffic": PAIRS_BIG_TRAFFIC_BYTES
+                    if (args.scale, args.edge_factor) == (22, 10) else None,
                     "ops_per_cluster": OPS_PER_CLUSTER, "clusters_per_launch": st["pairs_big"],
                     "avg_launch_ms": st["t_pairs_big_ms"]}
     else:

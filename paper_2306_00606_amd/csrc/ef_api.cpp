@@ -400,6 +400,7 @@ ef_status ef_graph_load_csr(int32_t n, int64_t nnz, const int32_t *row_ptr,
   g.n_fin = (int64_t)fin.size();
   for (int32_t v : fin)
     if (g.h_deg[v] > kFinBlockMin) g.n_fin_hub++;
+    else if (g.h_deg[v] <= kFinHalfMax) g.n_fin_half++;
   ALLOC(g.fin_list, sizeof(int32_t) * std::max<size_t>(fin.size(), 1), "finalize list");
 #undef ALLOC
   hipError_t e = hipSuccess;

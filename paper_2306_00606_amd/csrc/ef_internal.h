@@ -36,9 +36,11 @@ constexpr int kRecEntries = 2 * kSuper;  // row part + column part per super-til
 // (degree, position) words of the triangle pass.
 constexpr int32_t kMaxDegree = 1000000;
 constexpr int kTriBin0 = 64, kTriBin1 = 512, kTriBin2 = 2048;
-// Finalize: nodes of degree <= kFinGroupMax share wavefronts, 8 lanes each;
-// hubs of degree > kFinBlockMin take a workgroup each.
+// Finalize (and surrogate features): nodes of degree <= kFinGroupMax share
+// wavefronts, 8 lanes each; degree <= kFinHalfMax: 32 lanes; degree <=
+// kFinBlockMin: a wavefront; hubs of degree > kFinBlockMin: a workgroup.
 constexpr int32_t kFinGroupMax = 32;
+constexpr int32_t kFinHalfMax = 512;
 constexpr int32_t kFinBlockMin = 4096;
 constexpr int kTriLongMin = kTriBin2 + 1;
 
@@ -112,7 +114,8 @@ struct Graph {
   // nodes of degree > kFinGroupMax (finalized one wavefront each), by degree descending
   int32_t *fin_list = nullptr;
   int64_t n_fin = 0;
-  int64_t n_fin_hub = 0;  // leading entries of fin_list with degree > kFinBlockMin
+  int64_t n_fin_hub = 0;   // leading entries of fin_list with degree > kFinBlockMin
+  int64_t n_fin_half = 0;  // trailing entries with degree <= kFinHalfMax
   // per-seed formulation over all nodes: node ids by seed bin (built on first use)
   int32_t *ps_list[kSeedBins] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   int64_t n_ps[kSeedBins] = {0, 0, 0, 0, 0};

@@ -152,21 +152,78 @@ template <int G> __device__ __forceinline__ DFv group_sum(DFv x) {
   return x;
 }
 
-template <typename T, int G>
-__global__ __launch_bounds__(256) void k_finalize_cluster(
-    const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ deg,
-    const int2 *__restrict__ adj2, const int32_t *__restrict__ rev,
-    const int32_t *__restrict__ tslot, const int64_t *__restrict__ asum,
-    const void *__restrict__ R, const long long *__restrict__ Y, const int32_t *__restrict__ YT,
-    const void *__restrict__ Z, const int64_t *__restrict__ ZT,
-    const int32_t *__restrict__ nodes, int64_t count, int32_t kmax,
-    double *__restrict__ ef, int64_t *__restrict__ Dout, int64_t *__restrict__ Nout,
-    uint8_t *__restrict__ fl) {
+// arcs first, first + stride, ... of node v: its own row sums R[e], the
+// reverse arcs' R[rev e], exact N and D, and its up-arc triangle slots
+template <typename T>
+__device__ __forceinline__ void fin_arcs(const int2 *__restrict__ adj2,
+                                         const int32_t *__restrict__ rev,
+                                         const int32_t *__restrict__ tslot,
+                                         const int64_t *__restrict__ asum, const void *R,
+                                         const long long *__restrict__ Y,
+                                         const int32_t *__restrict__ YT, int32_t v, int32_t k,
+                                         int32_t base, int64_t As, int32_t first, int32_t stride,
+                                         typename SumT<T>::type &sacc, double &tfix, int64_t &Nn,
+                                         int64_t &Dd, int64_t &Tc) {
   using S = SumT<T>;
-  using Acc = typename S::type;
+  for (int32_t e = base + first; e < base + k; e += stride) {
+    const int2 ad = adj2[e];
+    const int32_t a = ad.x, ka = ad.y;
+    // a centre of degree 1 has no pairs: its row sums were never written
+    if (k >= 2) S::add_stored(sacc, R, e);
+    if (ka >= 2) S::add_stored(sacc, R, rev[e]);
+    Nn += (int64_t)(k - 1) + (ka - 1);
+    Dd += (int64_t)(k - 1) * (k + ka - 4) + (As - ka) + (int64_t)(ka - 1) * (ka + k - 4) +
+          (asum[a] - k);
+    if (rank_less_d(a, ka, v, k)) {
+      const int32_t sl = tslot[e];
+      tfix += (double)Y[sl];  // 2^-40 fixed-point units
+      Tc += YT[sl];
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void fin_store(int32_t v, typename SumT<T>::type sacc, double tfix,
+                                          int64_t Nn, int64_t Dd, int64_t Tc,
+                                          const void *Z, const int64_t *__restrict__ ZT,
+                                          double *ef, int64_t *Dout, int64_t *Nout,
+                                          uint8_t *fl) {
+  using S = SumT<T>;
+  typename S::type z = typename S::type();
+  S::add_stored(z, Z, v);
+  Tc += ZT[v];
+  const double tri = tfix * (1.0 / 1099511627776.0) + S::value(z);
+  const double Stot = S::value(sacc) + 4.0 * tri;
+  Dd -= 8 * Tc;
+  ef[v] = finish_ef<T>(Nn, Dd, Stot, v, fl);
+  Dout[v] = Dd;
+  Nout[v] = Nn;
+}
+
+struct FinArgs {
+  const int32_t *row_ptr, *deg;
+  const int2 *adj2;
+  const int32_t *rev, *tslot;
+  const int64_t *asum;
+  const void *R;
+  const long long *Y;
+  const int32_t *YT;
+  const void *Z;
+  const int64_t *ZT;
+  double *ef;
+  int64_t *D, *N;
+  uint8_t *fl;
+};
+
+// G lanes per node over `nodes` (NULL: node ids 0..count-1 of degree <= kmax),
+// using blocks 0 .. nblk-1 of this role
+template <typename T, int G>
+__device__ __forceinline__ void fin_groups(const FinArgs &A, const int32_t *nodes, int64_t count,
+                                           int32_t kmax, int64_t blk, int64_t nblk) {
+  using Acc = typename SumT<T>::type;
   const int sub = threadIdx.x & (G - 1);
-  const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
-  const int64_t ngrp = ((int64_t)gridDim.x * blockDim.x) / G;
+  const int64_t grp = (blk * blockDim.x + threadIdx.x) / G;
+  const int64_t ngrp = (nblk * blockDim.x) / G;
   // every lane of a wavefront runs the same number of rounds (group shuffles)
   const int64_t rounds = (count + ngrp - 1) / ngrp;
   for (int64_t r = 0; r < rounds; ++r) {
@@ -174,92 +231,42 @@ __global__ __launch_bounds__(256) void k_finalize_cluster(
     int32_t v = -1, k = 0;
     if (it < count) {
       v = nodes ? nodes[it] : (int32_t)it;
-      k = deg[v];
+      k = A.deg[v];
       if (!nodes && k > kmax) v = -1;
     }
     if (v < 0) k = 0;
-    const int32_t base = v >= 0 ? row_ptr[v] : 0;
-    const int64_t As = v >= 0 ? asum[v] : 0;
     Acc sacc = Acc();
-    double tfix = 0.0;  // triangle credits, 2^-40 fixed-point units
+    double tfix = 0.0;
     int64_t Nn = 0, Dd = 0, Tc = 0;
-    for (int32_t e = base + sub; e < base + k; e += G) {
-      const int2 ad = adj2[e];
-      const int32_t a = ad.x, ka = ad.y;
-      // a centre of degree 1 has no pairs: its row sums were never written
-      if (k >= 2) S::add_stored(sacc, R, e);
-      if (ka >= 2) S::add_stored(sacc, R, rev[e]);
-      Nn += (int64_t)(k - 1) + (ka - 1);
-      Dd += (int64_t)(k - 1) * (k + ka - 4) + (As - ka) + (int64_t)(ka - 1) * (ka + k - 4) +
-            (asum[a] - k);
-      if (rank_less_d(a, ka, v, k)) {
-        const int32_t sl = tslot[e];
-        tfix += (double)Y[sl];
-        Tc += YT[sl];
-      }
-    }
+    if (v >= 0)
+      fin_arcs<T>(A.adj2, A.rev, A.tslot, A.asum, A.R, A.Y, A.YT, v, k, A.row_ptr[v], A.asum[v],
+                  sub, G, sacc, tfix, Nn, Dd, Tc);
     sacc = group_sum<G>(sacc);
     tfix = group_sum<G>(tfix);
     Nn = group_sum<G>(Nn);
     Dd = group_sum<G>(Dd);
     Tc = group_sum<G>(Tc);
-    if (v >= 0 && sub == 0) {
-      Acc z = Acc();
-      S::add_stored(z, Z, v);
-      Tc += ZT[v];
-      const double tri = tfix * (1.0 / 1099511627776.0) + S::value(z);
-      const double Stot = S::value(sacc) + 4.0 * tri;
-      Dd -= 8 * Tc;
-      ef[v] = finish_ef<T>(Nn, Dd, Stot, v, fl);
-      Dout[v] = Dd;
-      Nout[v] = Nn;
-    }
+    if (v >= 0 && sub == 0) fin_store<T>(v, sacc, tfix, Nn, Dd, Tc, A.Z, A.ZT, A.ef, A.D, A.N, A.fl);
   }
 }
 
-static unsigned cap_blocks(int64_t b, int64_t cap) {
-  if (b < 1) b = 1;
-  return (unsigned)(b < cap ? b : cap);
-}
-
-// hubs (degree > kFinBlockMin): one workgroup of 16 wavefronts per node, the
-// wavefront partials combined in a fixed order
+// one workgroup (4 wavefronts) per hub; partials combined in a fixed order
 template <typename T>
-__global__ __launch_bounds__(1024) void k_finalize_hub(
-    const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ deg,
-    const int2 *__restrict__ adj2, const int32_t *__restrict__ rev,
-    const int32_t *__restrict__ tslot, const int64_t *__restrict__ asum,
-    const void *__restrict__ R, const long long *__restrict__ Y, const int32_t *__restrict__ YT,
-    const void *__restrict__ Z, const int64_t *__restrict__ ZT,
-    const int32_t *__restrict__ nodes, int64_t count, double *__restrict__ ef,
-    int64_t *__restrict__ Dout, int64_t *__restrict__ Nout, uint8_t *__restrict__ fl) {
-  using S = SumT<T>;
-  using Acc = typename S::type;
-  __shared__ Acc shS[16];
-  __shared__ double shT[16];
-  __shared__ int64_t shN[16], shD[16], shC[16];
+__device__ __forceinline__ void fin_hubs(const FinArgs &A, const int32_t *nodes, int64_t count,
+                                         int64_t blk, int64_t nblk) {
+  using Acc = typename SumT<T>::type;
+  __shared__ Acc shS[4];
+  __shared__ double shT[4];
+  __shared__ int64_t shN[4], shD[4], shC[4];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  for (int64_t it = blockIdx.x; it < count; it += gridDim.x) {
+  for (int64_t it = blk; it < count; it += nblk) {
     const int32_t v = nodes[it];
-    const int32_t k = deg[v], base = row_ptr[v];
-    const int64_t As = asum[v];
+    const int32_t k = A.deg[v];
     Acc sacc = Acc();
     double tfix = 0.0;
     int64_t Nn = 0, Dd = 0, Tc = 0;
-    for (int32_t e = base + tid; e < base + k; e += 1024) {
-      const int2 ad = adj2[e];
-      const int32_t a = ad.x, ka = ad.y;
-      S::add_stored(sacc, R, e);
-      if (ka >= 2) S::add_stored(sacc, R, rev[e]);
-      Nn += (int64_t)(k - 1) + (ka - 1);
-      Dd += (int64_t)(k - 1) * (k + ka - 4) + (As - ka) + (int64_t)(ka - 1) * (ka + k - 4) +
-            (asum[a] - k);
-      if (rank_less_d(a, ka, v, k)) {
-        const int32_t sl = tslot[e];
-        tfix += (double)Y[sl];
-        Tc += YT[sl];
-      }
-    }
+    fin_arcs<T>(A.adj2, A.rev, A.tslot, A.asum, A.R, A.Y, A.YT, v, k, A.row_ptr[v], A.asum[v],
+                tid, 256, sacc, tfix, Nn, Dd, Tc);
     sacc = wave_sum(sacc);
     tfix = wave_sum_f64(tfix);
     Nn = wave_sum_i64(Nn);
@@ -274,63 +281,64 @@ __global__ __launch_bounds__(1024) void k_finalize_hub(
     }
     __syncthreads();
     if (tid == 0) {
-      for (int w = 1; w < 16; ++w) {
+      for (int w = 1; w < 4; ++w) {
         acc_merge(sacc, shS[w]);
         tfix += shT[w];
         Nn += shN[w];
         Dd += shD[w];
         Tc += shC[w];
       }
-      Acc z = Acc();
-      S::add_stored(z, Z, v);
-      Tc += ZT[v];
-      const double tri = tfix * (1.0 / 1099511627776.0) + S::value(z);
-      const double Stot = S::value(sacc) + 4.0 * tri;
-      Dd -= 8 * Tc;
-      ef[v] = finish_ef<T>(Nn, Dd, Stot, v, fl);
-      Dout[v] = Dd;
-      Nout[v] = Nn;
+      fin_store<T>(v, sacc, tfix, Nn, Dd, Tc, A.Z, A.ZT, A.ef, A.D, A.N, A.fl);
     }
     __syncthreads();
   }
+}
+
+// One launch for every node: block ranges select the role, hubs first so
+// their long rows overlap with the rest.
+//   [0, b0)        hubs (degree > kFinBlockMin), a workgroup each
+//   [b0, b1)       degree kFinHalfMax+1 .. kFinBlockMin, a wavefront each
+//   [b1, b2)       degree kFinGroupMax+1 .. kFinHalfMax, 32 lanes each
+//   [b2, grid)     degree <= kFinGroupMax, 8 lanes each (node ids)
+template <typename T>
+__global__ __launch_bounds__(256) void k_finalize_cluster(FinArgs A, const int32_t *l_hub,
+                                                         int64_t n_hub, const int32_t *l_wave,
+                                                         int64_t n_wave, const int32_t *l_half,
+                                                         int64_t n_half, int32_t n, int64_t b0,
+                                                         int64_t b1, int64_t b2) {
+  const int64_t b = blockIdx.x;
+  if (b < b0) fin_hubs<T>(A, l_hub, n_hub, b, b0);
+  else if (b < b1) fin_groups<T, 64>(A, l_wave, n_wave, 0, b - b0, b1 - b0);
+  else if (b < b2) fin_groups<T, 32>(A, l_half, n_half, 0, b - b1, b2 - b1);
+  else fin_groups<T, 8>(A, nullptr, (int64_t)n, kFinGroupMax, b - b2, (int64_t)gridDim.x - b2);
+}
+
+static unsigned cap_blocks(int64_t b, int64_t cap) {
+  if (b < 1) b = 1;
+  return (unsigned)(b < cap ? b : cap);
 }
 
 hipError_t launch_finalize_cluster(const Graph &g, ef_prec prec, const void *R,
                                    const long long *Y, const int32_t *YT, const void *Z,
                                    const int64_t *ZT, double *ef, int64_t *D, int64_t *N,
                                    uint8_t *fl, hipStream_t st) {
-  // nodes of degree <= kFinGroupMax: 8 lanes each; hubs (the first n_fin_hub
-  // entries of fin_list, degree > kFinBlockMin): one workgroup each; the rest
-  // of fin_list: one wavefront each
-  const int64_t n_wave = g.n_fin - g.n_fin_hub;
-  const unsigned blocks_s = cap_blocks(((int64_t)g.n * 8 + 255) / 256, 1 << 20);
-  const unsigned blocks_l = cap_blocks((n_wave * 64 + 255) / 256, 1 << 20);
-  const unsigned blocks_h = cap_blocks(g.n_fin_hub, 1 << 16);
-  if (prec == EF_PREC_FP64) {
-    if (g.n_fin_hub > 0)
-      hipLaunchKernelGGL(k_finalize_hub<double>, dim3(blocks_h), dim3(1024), 0, st, g.row_ptr,
-                         g.deg, g.adj2, g.rev, g.tslot, g.asum, R, Y, YT, Z, ZT, g.fin_list,
-                         g.n_fin_hub, ef, D, N, fl);
-    hipLaunchKernelGGL((k_finalize_cluster<double, 8>), dim3(blocks_s), dim3(256), 0, st,
-                       g.row_ptr, g.deg, g.adj2, g.rev, g.tslot, g.asum, R, Y, YT, Z, ZT,
-                       nullptr, (int64_t)g.n, kFinGroupMax, ef, D, N, fl);
-    if (n_wave > 0)
-      hipLaunchKernelGGL((k_finalize_cluster<double, 64>), dim3(blocks_l), dim3(256), 0, st,
-                         g.row_ptr, g.deg, g.adj2, g.rev, g.tslot, g.asum, R, Y, YT, Z, ZT,
-                         g.fin_list + g.n_fin_hub, n_wave, 0, ef, D, N, fl);
-  } else {
-    if (g.n_fin_hub > 0)
-      hipLaunchKernelGGL(k_finalize_hub<float>, dim3(blocks_h), dim3(1024), 0, st, g.row_ptr,
-                         g.deg, g.adj2, g.rev, g.tslot, g.asum, R, Y, YT, Z, ZT, g.fin_list,
-                         g.n_fin_hub, ef, D, N, fl);
-    hipLaunchKernelGGL((k_finalize_cluster<float, 8>), dim3(blocks_s), dim3(256), 0, st,
-                       g.row_ptr, g.deg, g.adj2, g.rev, g.tslot, g.asum, R, Y, YT, Z, ZT,
-                       nullptr, (int64_t)g.n, kFinGroupMax, ef, D, N, fl);
-    if (n_wave > 0)
-      hipLaunchKernelGGL((k_finalize_cluster<float, 64>), dim3(blocks_l), dim3(256), 0, st,
-                         g.row_ptr, g.deg, g.adj2, g.rev, g.tslot, g.asum, R, Y, YT, Z, ZT,
-                         g.fin_list + g.n_fin_hub, n_wave, 0, ef, D, N, fl);
-  }
+  // fin_list (degree descending) = [hubs][wavefront tier][32-lane tier]
+  const int64_t n_wave = g.n_fin - g.n_fin_hub - g.n_fin_half;
+  const int32_t *l_wave = g.fin_list + g.n_fin_hub, *l_half = l_wave + n_wave;
+  const int64_t bh = g.n_fin_hub > 0 ? cap_blocks(g.n_fin_hub, 1 << 14) : 0;
+  const int64_t bw = n_wave > 0 ? cap_blocks((n_wave * 64 + 255) / 256, 1 << 18) : 0;
+  const int64_t bc = g.n_fin_half > 0 ? cap_blocks((g.n_fin_half * 32 + 255) / 256, 1 << 18) : 0;
+  const int64_t bs = cap_blocks(((int64_t)g.n * 8 + 255) / 256, 1 << 19);
+  const FinArgs A{g.row_ptr, g.deg, g.adj2, g.rev, g.tslot, g.asum, R, Y, YT, Z, ZT, ef, D, N, fl};
+  const unsigned grid = (unsigned)(bh + bw + bc + bs);
+  if (prec == EF_PREC_FP64)
+    hipLaunchKernelGGL(k_finalize_cluster<double>, dim3(grid), dim3(256), 0, st, A, g.fin_list,
+                       g.n_fin_hub, l_wave, n_wave, l_half, g.n_fin_half, g.n, bh, bh + bw,
+                       bh + bw + bc);
+  else
+    hipLaunchKernelGGL(k_finalize_cluster<float>, dim3(grid), dim3(256), 0, st, A, g.fin_list,
+                       g.n_fin_hub, l_wave, n_wave, l_half, g.n_fin_half, g.n, bh, bh + bw,
+                       bh + bw + bc);
   return hipGetLastError();
 }
 
@@ -415,8 +423,8 @@ __device__ __forceinline__ int32_t seed_chunk_setup(const int32_t *__restrict__ 
 }
 
 template <int SLOTS>
-__device__ __forceinline__ void hash_insert(int32_t *hkey, int32_t x) {
-  (void)LdsHash<SLOTS>::insert(hkey, x);
+__device__ __forceinline__ int32_t hash_insert(int32_t *hkey, int32_t x) {
+  return LdsHash<SLOTS>::insert(hkey, x);
 }
 
 // one wavefront walks entries [beg, end) of the current chunk
@@ -496,6 +504,7 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_wave(
     int64_t *__restrict__ Nout, uint8_t *__restrict__ fl) {
   using S = SumT<T>;
   using Acc = typename S::type;
+  static_assert(MAXK <= 64, "one neighbour per lane");
   __shared__ __align__(16) int32_t hkey_s[WPB][SLOTS];
   __shared__ int2 seg_s[WPB][MAXK];
   __shared__ int32_t segp_s[WPB][MAXK + 1];
@@ -505,17 +514,20 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_wave(
   int32_t *flg = flg_s[wv];
   flg[lane] = 0;
   const int64_t nwaves = (int64_t)gridDim.x * WPB;
+  // the hash is cleared once; afterwards each lane empties the one slot it
+  // filled (k <= 64), so a low-degree seed does not pay for the whole table
+  for (int i = lane; i < SLOTS; i += 64) hkey[i] = -1;
   for (int64_t it = (int64_t)blockIdx.x * WPB + wv; it < count; it += nwaves) {
     const int32_t pos = list[it];
     const int32_t s = seeds ? seeds[pos] : pos;
     const int32_t k = deg[s], base = row_ptr[s];
-    for (int i = lane; i < SLOTS; i += 64) hkey[i] = -1;
     wave_sync();
     Acc sacc = Acc();
     int64_t Dd = 0, Nn = 0;
-    for (int32_t j = lane; j < k; j += 64) {
-      hash_insert<SLOTS>(hkey, adj2[base + j].x);
-      if (k >= 2) S::add_stored(sacc, R, base + j);
+    int32_t myslot = -1;
+    if (lane < k) {
+      myslot = hash_insert<SLOTS>(hkey, adj2[base + lane].x);
+      if (k >= 2) S::add_stored(sacc, R, base + lane);
     }
     const int32_t total =
         seed_chunk_setup<64>(row_ptr, adj2, base, 0, k, lane, seg_s[wv], segp_s[wv], nullptr);
@@ -527,6 +539,7 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_wave(
     Nn = wave_sum_i64(Nn);
     if (lane == 0)
       seed_finish<T>(pos, k, asum[s], sacc, Nn, Dd, ef, Dout, Nout, fl);
+    if (myslot >= 0) hkey[myslot] = -1;
     wave_sync();
   }
 }

@@ -47,8 +47,8 @@ __device__ __forceinline__ float gelu_grad(float z) {
 __device__ __forceinline__ float bf(float x) { return (float)(__bf16)x; }
 
 // ---------------------------------------------------------------------------
-// features: G lanes per node (8 for degree <= kFinGroupMax, 64 for the rest
-// of the finalize list), one workgroup per hub (degree > kFinBlockMin)
+// features: G lanes per node (8 for degree <= kFinGroupMax, 32 for degree <=
+// kFinHalfMax, 64 up to kFinBlockMin), one workgroup per hub
 // ---------------------------------------------------------------------------
 struct FeatAcc {  // POD (lives in LDS); start from feat_zero()
   int64_t B, Q, T, c1, smax;
@@ -210,7 +210,8 @@ hipError_t launch_features(const Graph &g, const int32_t *YT, const int64_t *ZT,
                            const float *mean, const float *inv_std, float *X, float *lnN,
                            hipStream_t st) {
   auto cap = [](int64_t b, int64_t c) { return (unsigned)std::max<int64_t>(1, std::min(b, c)); };
-  const int64_t n_wave = g.n_fin - g.n_fin_hub;
+  const int64_t n_wave = g.n_fin - g.n_fin_hub - g.n_fin_half;
+  const int32_t *l_wave = g.fin_list + g.n_fin_hub, *l_half = l_wave + n_wave;
   if (g.n_fin_hub > 0)
     hipLaunchKernelGGL(k_features_hub, dim3(cap(g.n_fin_hub, 1 << 16)), dim3(1024), 0, st,
                        g.row_ptr, g.deg, g.adj2, g.asum, g.tslot, YT, ZT, g.fin_list,
@@ -220,8 +221,12 @@ hipError_t launch_features(const Graph &g, const int32_t *YT, const int64_t *ZT,
                      (int64_t)g.n, kFinGroupMax, mean, inv_std, X, lnN);
   if (n_wave > 0)
     hipLaunchKernelGGL(k_features<64>, dim3(cap((n_wave * 64 + 255) / 256, 1 << 20)), dim3(256),
-                       0, st, g.row_ptr, g.deg, g.adj2, g.asum, g.tslot, YT, ZT,
-                       g.fin_list + g.n_fin_hub, n_wave, 0, mean, inv_std, X, lnN);
+                       0, st, g.row_ptr, g.deg, g.adj2, g.asum, g.tslot, YT, ZT, l_wave, n_wave,
+                       0, mean, inv_std, X, lnN);
+  if (g.n_fin_half > 0)
+    hipLaunchKernelGGL(k_features<32>, dim3(cap((g.n_fin_half * 32 + 255) / 256, 1 << 20)),
+                       dim3(256), 0, st, g.row_ptr, g.deg, g.adj2, g.asum, g.tslot, YT, ZT,
+                       l_half, g.n_fin_half, 0, mean, inv_std, X, lnN);
   return hipGetLastError();
 }
 

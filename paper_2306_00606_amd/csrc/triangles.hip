@@ -127,7 +127,8 @@ __device__ __forceinline__ void tri_setup(const int32_t *__restrict__ up_ptr,
                                           const int32_t *__restrict__ deg, int32_t u0, int32_t m,
                                           int tid, int32_t *hkey, int32_t *hval, int2 *seg,
                                           int32_t *segp,
-                                          int32_t *part, int32_t &nseg_out, int32_t &total_out) {
+                                          int32_t *part, int32_t &nseg_out, int32_t &total_out,
+                                          int32_t &myslot) {
   constexpr int NW = NT / 64;
   const int lane = tid & 63, wv = tid >> 6;
   const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -140,7 +141,8 @@ __device__ __forceinline__ void tri_setup(const int32_t *__restrict__ up_ptr,
       w0 = up_ptr[x];
       len = up_ptr[x + 1] - w0;
       kx = deg[x];
-      hval[LdsHash<SLOTS>::insert(hkey, x)] = pack_kp(kx, i);
+      myslot = LdsHash<SLOTS>::insert(hkey, x);
+      hval[myslot] = pack_kp(kx, i);
     }
     const unsigned long long nz = __ballot(len > 0);
     int32_t incl = len;
@@ -187,23 +189,20 @@ __device__ __forceinline__ void tri_setup(const int32_t *__restrict__ up_ptr,
 
 // One wavefront walks entries [beg, end) of u's concatenated up(w) lists,
 // 64 consecutive entries per step (segment of each lane: seg_walk). A hit
-// (x in up(u)) is appended to the wavefront's LDS queue as one word
-// (sigma | pos(w) << 22 | pos(x) << 34); whenever 64 hits are queued they are
+// (x in up(u)) is appended to the wavefront's LDS queue as two words,
+// {sigma, pos(w) | pos(x) << 16}; whenever 64 hits are queued they are
 // scored and credited with every lane busy, so the hit path does not run
 // divergently on almost every step (about 6% of the entries are hits).
 constexpr int kQueue = 128;
-static_assert(3LL * kMaxDegree < (1LL << 22), "sigma field too narrow");
 
 template <typename T, int SLOTS, int MAXM>
 __device__ __forceinline__ void tri_walk(const int32_t *__restrict__ up_col,
-                                         TriLds<T, SLOTS, MAXM> &L, int32_t *flg,
-                                         unsigned long long *hq, int32_t nseg, int32_t beg,
-                                         int32_t end, int32_t ku,
+                                         TriLds<T, SLOTS, MAXM> &L, int32_t *flg, int2 *hq,
+                                         int32_t nseg, int32_t beg, int32_t end, int32_t ku,
                                          typename SumT<T>::type &accu, int64_t &cntu) {
   using S = SumT<T>;
   constexpr int32_t kPosMask = (1 << kPosBits) - 1;
   const int lane = threadIdx.x & 63;
-  const unsigned long long lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   const int2 *seg = L.seg;
   const int32_t *hkey = L.hkey;
   const int32_t *hval = L.hval;
@@ -212,14 +211,12 @@ __device__ __forceinline__ void tri_walk(const int32_t *__restrict__ up_col,
   auto drain = [&](int32_t cnt) {
     wave_sync();
     if (lane < cnt) {
-      const unsigned long long h = hq[qn - cnt + lane];
-      const int32_t sigma = (int32_t)(h & 0x3FFFFFull);
-      const int32_t pw = (int32_t)((h >> 22) & kPosMask), px = (int32_t)((h >> 34) & kPosMask);
-      const T dl = tri_delta<T>(sigma);
+      const int2 h = hq[qn - cnt + lane];
+      const T dl = tri_delta<T>(h.x);
       S::add_term(accu, dl);
       ++cntu;
-      Credit<T>::add(L.acc, L.cnt, px, dl);
-      Credit<T>::add(L.acc, L.cnt, pw, dl);
+      Credit<T>::add(L.acc, L.cnt, h.y >> 16, dl);
+      Credit<T>::add(L.acc, L.cnt, h.y & 0xFFFF, dl);
     }
     qn -= cnt;
     wave_sync();
@@ -236,16 +233,24 @@ __device__ __forceinline__ void tri_walk(const int32_t *__restrict__ up_col,
         const unsigned long long m = __ballot(hit);
         if (hit) {
           const int32_t ev = hval[slot];
-          const int32_t sigma = ku + unpack_k(xv.y) + unpack_k(ev);
-          hq[qn + __popcll(m & lt_mask)] =
-              (unsigned long long)sigma |
-              ((unsigned long long)(xv.y & kPosMask) << 22) |
-              ((unsigned long long)(ev & kPosMask) << 34);
+          const int32_t rank = (int32_t)__builtin_amdgcn_mbcnt_hi(
+              (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+          hq[qn + rank] = make_int2(ku + unpack_k(xv.y) + unpack_k(ev),
+                                    (xv.y & kPosMask) | ((ev & kPosMask) << 16));
         }
         qn += __popcll(m);
         if (qn >= 64) drain(64);
       });
   if (qn > 0) drain(qn);
+}
+
+template <typename T, int SLOTS, int MAXM>
+__device__ __forceinline__ void tri_clear_acc(TriLds<T, SLOTS, MAXM> &L, int32_t m, int tid,
+                                              int nt) {
+  for (int i = tid; i < m; i += nt) {
+    L.acc[i] = 0ull;
+    if constexpr (!Credit<T>::kPacked) L.cnt[i] = 0;
+  }
 }
 
 template <typename T, int SLOTS, int MAXM>
@@ -281,20 +286,24 @@ __global__ __launch_bounds__(64 * WPB) void k_tri_wave(
   using Acc = typename S::type;
   __shared__ TriLds<T, SLOTS, MAXM> lds[WPB];
   __shared__ int32_t flg_s[WPB][kFlg];
-  __shared__ unsigned long long hq_s[WPB][kQueue];
+  __shared__ int2 hq_s[WPB][kQueue];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   TriLds<T, SLOTS, MAXM> &L = lds[wv];
   int32_t *flg = flg_s[wv];
   flg[lane] = 0;
   const int64_t nwaves = (int64_t)gridDim.x * WPB;
+  // the hash is cleared once; afterwards each lane empties the one slot it
+  // filled (|up(u)| <= 64), so a short list does not pay for the whole table
+  static_assert(MAXM <= 64, "one up(u) entry per lane");
+  for (int i = lane; i < SLOTS; i += 64) L.hkey[i] = -1;
   for (int64_t it = (int64_t)blockIdx.x * WPB + wv; it < count; it += nwaves) {
     const int32_t u = nodes[it];
     const int32_t u0 = up_ptr[u], m = up_ptr[u + 1] - u0, ku = deg[u];
-    tri_clear(L, m, lane, 64);
+    tri_clear_acc(L, m, lane, 64);
     wave_sync();
-    int32_t nseg, total;
-    tri_setup<SLOTS, 64>(up_ptr, up_col, deg, u0, m, lane, L.hkey, L.hval, L.seg, L.segp, nullptr, nseg,
-                         total);
+    int32_t nseg, total, myslot = -1;
+    tri_setup<SLOTS, 64>(up_ptr, up_col, deg, u0, m, lane, L.hkey, L.hval, L.seg, L.segp, nullptr,
+                         nseg, total, myslot);
     wave_sync();
     Acc accu = Acc();
     int64_t cntu = 0;
@@ -306,6 +315,7 @@ __global__ __launch_bounds__(64 * WPB) void k_tri_wave(
       ZT[u] = cntu;
     }
     tri_store(L, u0, m, lane, 64, Y, YT);
+    if (myslot >= 0) L.hkey[myslot] = -1;
     wave_sync();
   }
 }
@@ -323,7 +333,7 @@ __global__ __launch_bounds__(64 * WPB) void k_tri_block(
   constexpr int NT = 64 * WPB;
   __shared__ TriLds<T, SLOTS, MAXM> L;
   __shared__ int32_t flg_s[WPB][kFlg];
-  __shared__ unsigned long long hq_s[WPB][kQueue];
+  __shared__ int2 hq_s[WPB][kQueue];
   __shared__ int32_t part[2 * WPB];
   __shared__ Acc sh_acc[WPB];
   __shared__ int64_t sh_cnt[WPB];
@@ -336,8 +346,9 @@ __global__ __launch_bounds__(64 * WPB) void k_tri_block(
     tri_clear(L, m, tid, NT);
     __syncthreads();
     int32_t nseg, total;
+    int32_t myslot;
     tri_setup<SLOTS, NT>(up_ptr, up_col, deg, u0, m, tid, L.hkey, L.hval, L.seg, L.segp, part, nseg,
-                         total);
+                         total, myslot);
     __syncthreads();
     // contiguous shares, multiples of 64 entries
     const int32_t steps = (total + 63) >> 6;
