@@ -173,6 +173,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--per-seed-steps", type=int, default=2,
                     help="also time the per-seed formulation (0 = skip)")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="only the profiled steps (every phase alone on the stream); for "
+                         "kernel-trace runs whose per-kernel averages the roofline uses")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-graph batch")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate")
     args = ap.parse_args()
@@ -199,18 +202,20 @@ def main():
     N = torch.empty(n, dtype=torch.int64, device=dev)
     out = (ef, D, N)
     log(f"n={n} nnz={info['nnz']} W={W} max_degree={info['max_degree']}; warmup {args.warmup}")
-    for _ in range(args.warmup):
-        g.compute(algo=args.algo, prec=args.prec, out=out)
-    torch.cuda.synchronize()
-    log(f"timing {args.steps} steps")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        g.compute(algo=args.algo, prec=args.prec, out=out)
-    torch.cuda.synchronize()
-    t = time.perf_counter() - t0
-    ms = 1e3 * t / args.steps
-    log(f"{ms:.2f} ms/step")
+    ms = None
+    if not args.profile_only:
+        for _ in range(args.warmup):
+            g.compute(algo=args.algo, prec=args.prec, out=out)
+        torch.cuda.synchronize()
+        log(f"timing {args.steps} steps")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            g.compute(algo=args.algo, prec=args.prec, out=out)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        ms = 1e3 * t / args.steps
+        log(f"{ms:.2f} ms/step")
 
     # per-kernel HIP-event timings on the call's stream (separate profiled steps)
     prof = []
@@ -219,6 +224,8 @@ def main():
         prof.append(g.stats())
     st = {k: float(np.mean([p[k] for p in prof])) for k in prof[0]}
     log("phases (ms): " + ", ".join(f"{k[2:-3]}={st[k]:.2f}" for k in st if k.startswith("t_")))
+    if ms is None:
+        ms = st["t_total_ms"]  # profile-only: phases run one after another
 
     # dominant kernel: the super-tile pair loop (clusters of centres with k > 1024)
     if args.algo == "cluster" and args.prec == "fp32c" and st["t_pairs_big_ms"] > 0:
