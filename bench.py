@@ -176,6 +176,8 @@ def main():
     ap.add_argument("--profile-only", action="store_true",
                     help="only the profiled steps (every phase alone on the stream); for "
                          "kernel-trace runs whose per-kernel averages the roofline uses")
+    ap.add_argument("--agg-steps", type=int, default=5,
+                    help="also time the degree-class aggregated variant (0 = skip)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-graph batch")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate")
     args = ap.parse_args()
@@ -264,6 +266,26 @@ def main():
                     if pst["t_stream_ms"] > 0 else None}
         log(f"per-seed {ps_ms:.1f} ms/step; stream {pst['t_stream_ms']:.1f} ms")
 
+    # degree-class aggregated variant: the same results with the pair sums of
+    # centres of degree > 1024 formed per class of equal neighbour degree;
+    # clusters are accounted, not enumerated, so its rate is "equivalent"
+    agg = None
+    if args.algo == "cluster" and args.agg_steps > 0:
+        log(f"aggregated variant: {args.agg_steps} steps")
+        g.compute(algo="cluster_agg", prec=args.prec, out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.agg_steps):
+            g.compute(algo="cluster_agg", prec=args.prec, out=out)
+        torch.cuda.synchronize()
+        agg_ms = 1e3 * (time.perf_counter() - t0) / args.agg_steps
+        g.compute(algo="cluster_agg", prec=args.prec, out=out, profile=True)
+        ast = g.stats()
+        agg = {"algo": "cluster_agg", "ms_per_step": agg_ms,
+               "equivalent_clusters_per_s": W / (agg_ms * 1e-3),
+               "phases_ms": {k[2:-3]: round(ast[k], 4) for k in ast if k.startswith("t_")}}
+        log(f"aggregated variant {agg_ms:.2f} ms/step")
+
     # whole-step algorithmic HBM bytes: CSR in (row_ptr, col_idx), the triangle
     # pass's walk over up(w) lists (4 B per wedge check), outputs (EF, D, N)
     step_bytes = (4.0 * (n + 1) + 4.0 * info["nnz"] + 4.0 * info["wedge_checks"] + 24.0 * n)
@@ -303,6 +325,7 @@ def main():
         "ef_checksum": float(np.sum(ef_h)),
         "roofline": roofline,
         "per_seed": per_seed,
+        "aggregated": agg,
         "hbm": hbm,
         "batch": batch,
         "surrogate": sur,

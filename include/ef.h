@@ -52,13 +52,23 @@ typedef enum {
   EF_ERR_STATE = 10          /* call not valid for this handle */
 } ef_status;
 
-/* The two exact formulations (both return identical N and D):
- *   EF_ALGO_CLUSTER  - cluster-centric, Algorithm 1: every cluster is scored
- *                      once and credited to its three nodes.
- *   EF_ALGO_PER_SEED - the original per-seed formulation (Sec. 4): each seed
- *                      visits all of its own clusters (stars around it, and
- *                      paths through each neighbour). */
-typedef enum { EF_ALGO_CLUSTER = 0, EF_ALGO_PER_SEED = 1 } ef_algo;
+/* The exact formulations (all return identical N and D):
+ *   EF_ALGO_CLUSTER     - cluster-centric, Algorithm 1: every cluster is
+ *                         scored once and credited to its three nodes.
+ *   EF_ALGO_PER_SEED    - the original per-seed formulation (Sec. 4): each
+ *                         seed visits all of its own clusters (stars around
+ *                         it, and paths through each neighbour).
+ *   EF_ALGO_CLUSTER_AGG - as EF_ALGO_CLUSTER, but the pair sums of centres of
+ *                         degree > 1024 are formed per class of equal
+ *                         neighbour degree (Algorithm 1, Phase 2 regrouped:
+ *                         clusters with the same three degrees have the same
+ *                         score), so such a centre costs M^2 scores for M
+ *                         distinct neighbour degrees instead of k(k-1)/2;
+ *                         centres with more than 4096 distinct neighbour
+ *                         degrees take the EF_ALGO_CLUSTER path. Same results
+ *                         up to rounding order; clusters are accounted, not
+ *                         enumerated one by one. */
+typedef enum { EF_ALGO_CLUSTER = 0, EF_ALGO_PER_SEED = 1, EF_ALGO_CLUSTER_AGG = 2 } ef_algo;
 
 /* Precision of the cluster-degree logarithms and their sums:
  *   EF_PREC_FP64  - every term and sum in double precision.

@@ -523,8 +523,9 @@ static void host_bins(const Graph &g, const int32_t *centres, int64_t count, Bin
 static ef_status alloc_bins(Graph &g, Bins &b) {
   const size_t bytes = sizeof(int32_t) * (size_t)(b.n_small + b.n_mid + 8) + 4 * 256 +
                        sizeof(BigCentre) * (size_t)(b.n_big + 1) +
+                       sizeof(int32_t) * (size_t)(b.n_big + 1) +
                        sizeof(TileItem) * (size_t)(b.n_tiles + 1) +
-                       sizeof(int2) * (size_t)(b.n_sblocks + 1) + 2048;
+                       sizeof(int2) * (size_t)(b.n_sblocks + 1) + 4096;
   ef_status s = ws_ensure(g, WS_BINS, bytes, "work lists");
   if (s != EF_OK) return s;
   char *p = (char *)g.ws[WS_BINS].p;
@@ -538,6 +539,7 @@ static ef_status alloc_bins(Graph &g, Bins &b) {
     b.small[i] = (int32_t *)take(sizeof(int32_t) * (size_t)(b.n_smallb[i] + 1));
   b.mid = (int32_t *)take(sizeof(int32_t) * (size_t)(b.n_mid + 1));
   b.big = (BigCentre *)take(sizeof(BigCentre) * (size_t)(b.n_big + 1));
+  b.agg_done = (int32_t *)take(sizeof(int32_t) * (size_t)(b.n_big + 1));
   b.tiles = (TileItem *)take(sizeof(TileItem) * (size_t)(b.n_tiles + 1));
   b.sblocks = (int2 *)take(sizeof(int2) * (size_t)(b.n_sblocks + 1));
   return EF_OK;
@@ -583,7 +585,7 @@ extern "C" ef_status ef_compute(ef_graph *h, ef_algo algo, ef_prec prec, const i
     set_error("ef_compute: null handle or output");
     return EF_ERR_ARG;
   }
-  if ((algo != EF_ALGO_CLUSTER && algo != EF_ALGO_PER_SEED) ||
+  if ((algo != EF_ALGO_CLUSTER && algo != EF_ALGO_PER_SEED && algo != EF_ALGO_CLUSTER_AGG) ||
       (prec != EF_PREC_FP64 && prec != EF_PREC_FP32C)) {
     set_error("ef_compute: bad algorithm or precision");
     return EF_ERR_ARG;
@@ -768,7 +770,7 @@ extern "C" ef_status ef_compute(ef_graph *h, ef_algo algo, ef_prec prec, const i
   if (e != hipSuccess) return hip_status(e, "binning");
   prof.mark(1);
   e = launch_pairs(g, prec, b, g.ws[WS_R].p, g.ws[WS_REC].p, st, prof.ev(2), prof.ev(3),
-                   prof.ev(4));
+                   prof.ev(4), algo == EF_ALGO_CLUSTER_AGG ? b.agg_done : nullptr);
   if (e != hipSuccess) return hip_status(e, "pair loop");
   prof.mark(5);
   if (!per_seed) {

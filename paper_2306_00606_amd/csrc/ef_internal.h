@@ -175,6 +175,7 @@ struct Bins {
   TileItem *tiles = nullptr;
   int2 *sblocks = nullptr;       // (big-centre index, super-block) reduction items
   int32_t *counters = nullptr;   // [0..3] small, [4] mid, [5] big, [6] tiles, [7] sblocks
+  int32_t *agg_done = nullptr;   // per big centre: 1 = pair sums done by aggregation
   int64_t n_small = 0, n_mid = 0, n_big = 0, n_tiles = 0;  // host-known counts
   int64_t pairs_small = 0, pairs_mid = 0, pairs_big = 0;     // clusters per bin
   int64_t n_sblocks = 0;
@@ -187,9 +188,12 @@ hipError_t launch_bin_centres(const Graph &g, const int32_t *centres, int32_t n_
 // super-tile records and a per-arc reduction.
 // ev_small / ev_mid / ev_big (nullable) are recorded after the small, mid and
 // super-tile kernels.
+// agg_done (nullable, one int per big centre): the degree-class aggregated
+// variant writes R of big centres directly (1), leaving centres with too many
+// distinct neighbour degrees (0) to the super-tile path.
 hipError_t launch_pairs(const Graph &g, ef_prec prec, const Bins &b, void *R, void *records,
                         hipStream_t st, hipEvent_t ev_small, hipEvent_t ev_mid,
-                        hipEvent_t ev_big);
+                        hipEvent_t ev_big, int32_t *agg_done = nullptr);
 
 // triangle pass (cluster-centric): Y (64-bit fixed point, 2^-40 units) and
 // YT per up-arc slot, Z / ZT per node.

@@ -327,12 +327,14 @@ __global__ __launch_bounds__(1024) void k_pairs_big(const int32_t *__restrict__ 
                                                     const int2 *__restrict__ adj2,
                                                     const BigCentre *__restrict__ big,
                                                     const TileItem *__restrict__ tiles,
-                                                    int64_t count, void *__restrict__ rec) {
+                                                    int64_t count, void *__restrict__ rec,
+                                                    const int32_t *__restrict__ agg_done) {
   __shared__ T kdeg[kBlocksPerSuper][128];  // per wavefront: doubled column degrees
   __shared__ T parts[kBlocksPerSuper][kBlocksPerSuper][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int64_t it = blockIdx.x; it < count; it += gridDim.x) {
     const TileItem ti = tiles[it];
+    if (agg_done && agg_done[ti.big]) continue;  // uniform per workgroup
     const BigCentre bc = big[ti.big];
     const int32_t v = bc.v, k = deg[v], base = row_ptr[v], ns = bc.ns;
     const int P = ti.P, Q = ti.Q;
@@ -385,6 +387,145 @@ __global__ __launch_bounds__(1024) void k_pairs_big(const int32_t *__restrict__ 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Degree-class aggregation of the pair loop for big centres (a variant of
+// Algorithm 1, Phase 2 that reaches the same per-arc sums): with c = k_v - 4
+// and m_j neighbours of degree kappa_j,
+//   R[v->a_p] = sum_{q != p} g(c + k_p + k_q)
+//             = T(k_p) - g(c + 2 k_p),   T(kappa) = sum_j m_j g(c + kappa + kappa_j),
+// so a centre costs M^2 score evaluations (M distinct neighbour degrees)
+// instead of k(k-1)/2. One workgroup per big centre:
+//   1. histogram of neighbour degrees in an LDS hash (kAggSlots slots, at
+//      most kAggMax distinct; beyond that the centre is left to the
+//      super-tile path: agg_done[bi] = 0);
+//   2. distinct degrees sorted ascending (bitonic sort in LDS), so every sum
+//      has a fixed order and results are reproducible;
+//   3. T for every distinct degree (row i: sum over j ascending);
+//   4. R for every arc from T.
+// ---------------------------------------------------------------------------
+constexpr int kAggMax = 4096;    // distinct neighbour degrees per centre
+constexpr int kAggSlots = 8192;  // hash slots (load factor <= 1/2)
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_pairs_agg(const int32_t *__restrict__ row_ptr,
+                                                    const int32_t *__restrict__ deg,
+                                                    const int2 *__restrict__ adj2,
+                                                    const BigCentre *__restrict__ big,
+                                                    const int32_t *__restrict__ counters,
+                                                    int32_t *__restrict__ agg_done,
+                                                    void *__restrict__ R) {
+  __shared__ int32_t hkey[kAggSlots];
+  __shared__ int32_t hval[kAggSlots];  // count, then the sorted index
+  __shared__ int32_t skey[kAggMax];
+  __shared__ int32_t scnt[kAggMax];
+  __shared__ T tsum[(sizeof(T) == 4 ? 2 : 1) * kAggMax];  // FP32: (hi, lo) pairs; FP64: one value
+  __shared__ int32_t nd_s, over_s;
+  constexpr uint32_t kMask = kAggSlots - 1;
+  const int tid = threadIdx.x;
+  const int32_t nbig = counters[5];
+  for (int32_t bi = blockIdx.x; bi < nbig; bi += gridDim.x) {
+    const BigCentre bc = big[bi];
+    const int32_t v = bc.v, k = deg[v], base = row_ptr[v];
+    const T c = (T)(k - 4);
+    for (int i = tid; i < kAggSlots; i += 1024) {
+      hkey[i] = -1;
+      hval[i] = 0;
+    }
+    if (tid == 0) {
+      nd_s = 0;
+      over_s = 0;
+    }
+    __syncthreads();
+    // 1. histogram (find-or-insert; a probe gives up after kAggSlots slots)
+    for (int32_t e = base + tid; e < base + k; e += 1024) {
+      const int32_t kap = adj2[e].y;
+      uint32_t h = ((uint32_t)kap * 0x9E3779u) & kMask;
+      for (int t = 0; t < kAggSlots; ++t) {
+        const int32_t cur = atomicCAS(&hkey[h], -1, kap);
+        if (cur == -1) {
+          if (atomicAdd(&nd_s, 1) >= kAggMax) over_s = 1;
+        }
+        if (cur == -1 || cur == kap) {
+          atomicAdd(&hval[h], 1);
+          break;
+        }
+        h = (h + 1) & kMask;
+      }
+    }
+    __syncthreads();
+    if (over_s) {
+      if (tid == 0) agg_done[bi] = 0;
+      __syncthreads();
+      continue;
+    }
+    const int32_t M = nd_s;
+    int32_t P = 1;
+    while (P < M) P <<= 1;
+    // 2. compact (any order), pad to P with +inf keys, bitonic sort ascending
+    for (int i = tid; i < P; i += 1024) {
+      skey[i] = 0x7fffffff;
+      scnt[i] = 0;
+    }
+    __syncthreads();
+    if (tid == 0) nd_s = 0;
+    __syncthreads();
+    for (int i = tid; i < kAggSlots; i += 1024) {
+      if (hkey[i] >= 0) {
+        const int32_t pos = atomicAdd(&nd_s, 1);
+        skey[pos] = hkey[i];
+        scnt[pos] = hval[i];
+      }
+    }
+    __syncthreads();
+    for (int len = 2; len <= P; len <<= 1) {
+      for (int stride = len >> 1; stride > 0; stride >>= 1) {
+        for (int i = tid; i < P; i += 1024) {
+          const int j = i ^ stride;
+          if (j > i) {
+            const bool up = (i & len) == 0;
+            const int32_t a = skey[i], b2 = skey[j];
+            if ((a > b2) == up) {
+              skey[i] = b2;
+              skey[j] = a;
+              const int32_t t2 = scnt[i];
+              scnt[i] = scnt[j];
+              scnt[j] = t2;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    // sorted index of each distinct degree, kept in the hash value slot
+    for (int i = tid; i < M; i += 1024) {
+      const int32_t kap = skey[i];
+      uint32_t h = ((uint32_t)kap * 0x9E3779u) & kMask;
+      while (hkey[h] != kap) h = (h + 1) & kMask;
+      hval[h] = i;
+    }
+    // 3. T(kappa_i) = sum_j m_j g(c + kappa_i + kappa_j), j ascending
+    for (int i = tid; i < M; i += 1024) {
+      const T ci = c + (T)skey[i];
+      Acc<T> a;
+      for (int j = 0; j < M; ++j) a.add((T)scnt[j] * score(ci + (T)skey[j]));
+      a.store(tsum, i);
+    }
+    __syncthreads();
+    // 4. R[e] = T(k_p) - g(c + 2 k_p)
+    for (int32_t e = base + tid; e < base + k; e += 1024) {
+      const int32_t kap = adj2[e].y;
+      uint32_t h = ((uint32_t)kap * 0x9E3779u) & kMask;
+      while (hkey[h] != kap) h = (h + 1) & kMask;
+      Acc<T> a;
+      a.add_stored(tsum, hval[h]);
+      a.add(-score(c + (T)(2 * kap)));
+      a.store(R, e);
+    }
+    if (tid == 0) agg_done[bi] = 1;
+    __syncthreads();
+  }
+}
+
 // Per-arc sum of the super-tile records of big centres, fixed order:
 // R[p] = sum_{Q >= b} row part of (b, Q)  +  sum_{P < b} column part of (P, b)
 // One workgroup per (big centre, super-block b): the 1024 arcs of block b.
@@ -394,9 +535,11 @@ __global__ __launch_bounds__(256) void k_arc_reduce(const int32_t *__restrict__ 
                                                     const BigCentre *__restrict__ big,
                                                     const int2 *__restrict__ items,
                                                     int64_t nitems, const void *__restrict__ rec,
-                                                    void *__restrict__ R) {
+                                                    void *__restrict__ R,
+                                                    const int32_t *__restrict__ agg_done) {
   for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
     const int2 item = items[it];
+    if (agg_done && agg_done[item.x]) continue;
     const BigCentre bc = big[item.x];
     const int b = item.y;
     const int32_t k = deg[bc.v], base = row_ptr[bc.v], ns = bc.ns;
@@ -568,7 +711,7 @@ hipError_t launch_bin_centres(const Graph &g, const int32_t *centres, int32_t n_
 template <typename T>
 static hipError_t pairs_impl(const Graph &g, const Bins &b, void *R, void *records,
                              hipStream_t st, hipEvent_t ev_small, hipEvent_t ev_mid,
-                             hipEvent_t ev_big) {
+                             hipEvent_t ev_big, int32_t *agg_done) {
   if (b.n_smallb[0] > 0)
     hipLaunchKernelGGL((k_pairs_small<T, 8>), dim3(capped((b.n_smallb[0] + 31) / 32, 1 << 20)),
                        dim3(256), 0, st, g.row_ptr, g.deg, g.adj2, b.small[0], b.n_smallb[0], R);
@@ -586,22 +729,25 @@ static hipError_t pairs_impl(const Graph &g, const Bins &b, void *R, void *recor
     hipLaunchKernelGGL(k_pairs_mid<T>, dim3(capped(b.n_mid, 1 << 20)), dim3(1024), 0, st,
                        g.row_ptr, g.deg, g.adj2, b.mid, b.n_mid, R);
   if (ev_mid) (void)hipEventRecord(ev_mid, st);
+  if (agg_done && b.n_big > 0)
+    hipLaunchKernelGGL(k_pairs_agg<T>, dim3(capped(b.n_big, 1 << 16)), dim3(1024), 0, st,
+                       g.row_ptr, g.deg, g.adj2, b.big, b.counters, agg_done, R);
   if (b.n_tiles > 0)
     hipLaunchKernelGGL(k_pairs_big<T>, dim3(capped(b.n_tiles, 1 << 20)), dim3(1024), 0, st,
-                       g.row_ptr, g.deg, g.adj2, b.big, b.tiles, b.n_tiles, records);
+                       g.row_ptr, g.deg, g.adj2, b.big, b.tiles, b.n_tiles, records, agg_done);
   if (ev_big) (void)hipEventRecord(ev_big, st);
   if (b.n_sblocks > 0)
     hipLaunchKernelGGL(k_arc_reduce<T>, dim3(capped(b.n_sblocks, 1 << 20)), dim3(256), 0, st,
-                       g.row_ptr, g.deg, b.big, b.sblocks, b.n_sblocks, records, R);
+                       g.row_ptr, g.deg, b.big, b.sblocks, b.n_sblocks, records, R, agg_done);
   return hipGetLastError();
 }
 
 hipError_t launch_pairs(const Graph &g, ef_prec prec, const Bins &b, void *R, void *records,
                         hipStream_t st, hipEvent_t ev_small, hipEvent_t ev_mid,
-                        hipEvent_t ev_big) {
+                        hipEvent_t ev_big, int32_t *agg_done) {
   if (prec == EF_PREC_FP64)
-    return pairs_impl<double>(g, b, R, records, st, ev_small, ev_mid, ev_big);
-  return pairs_impl<float>(g, b, R, records, st, ev_small, ev_mid, ev_big);
+    return pairs_impl<double>(g, b, R, records, st, ev_small, ev_mid, ev_big, agg_done);
+  return pairs_impl<float>(g, b, R, records, st, ev_small, ev_mid, ev_big, agg_done);
 }
 
 }  // namespace efi

@@ -23,7 +23,7 @@ STATUS_NAMES = {
     4: "EF_ERR_DUPLICATE", 5: "EF_ERR_UNSORTED", 6: "EF_ERR_RANGE", 7: "EF_ERR_OVERFLOW",
     8: "EF_ERR_NOMEM", 9: "EF_ERR_DEVICE", 10: "EF_ERR_STATE",
 }
-ALGO = {"cluster": 0, "per_seed": 1}
+ALGO = {"cluster": 0, "per_seed": 1, "cluster_agg": 2}
 PREC = {"fp64": 0, "fp32c": 1}
 EF_VALIDATE = 0x1
 EF_DEVICE_PTRS = 0x2
