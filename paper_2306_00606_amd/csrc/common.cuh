@@ -190,8 +190,8 @@ __device__ __forceinline__ int32_t seg_step(const int32_t *segp, int32_t nseg, i
 // Walk entries [beg, end) with one wavefront, U steps of 64 per round: the
 // segments of all U steps are found first, then every step's load is issued
 // (U loads in flight per lane), then the entries are used.
-//   load(seg, idx) -> V   reads what entry idx of segment seg needs (lanes
-//                         with idx < end only)
+//   load(seg, idx) -> V   reads what entry idx of segment seg needs; lanes
+//                         past end call it on entry c of the round (valid)
 //   use(seg, idx, V, ok)  consumes it; called on every lane of the wavefront,
 //                         ok = (idx < end), V undefined when !ok (so use may
 //                         run wavefront-wide operations such as ballots)
@@ -211,14 +211,18 @@ __device__ __forceinline__ void seg_walk(const int32_t *segp, int32_t nseg, int3
   const int lane = threadIdx.x & 63;
   int32_t s0 = __builtin_amdgcn_readfirstlane(seg_find(segp, nseg, beg));
   for (int32_t c = beg; c < end; c += 64 * U) {
+    const int32_t s_c = s0;  // segment of entry c (< end): a valid fallback
     int32_t sg[U];
 #pragma unroll
-    for (int q = 0; q < U; ++q) sg[q] = (c + 64 * q < end) ? seg_step(segp, nseg, c + 64 * q, s0, flg) : 0;
+    for (int q = 0; q < U; ++q) sg[q] = (c + 64 * q < end) ? seg_step(segp, nseg, c + 64 * q, s0, flg) : s_c;
+    // every lane loads (lanes past end load entry c and ignore it): no
+    // branches around the loads, so all U are in flight together
     decltype(load(0, 0)) v[U];
 #pragma unroll
     for (int q = 0; q < U; ++q) {
       const int32_t idx = c + 64 * q + lane;
-      if (idx < end) v[q] = load(sg[q], idx);
+      const bool ok = idx < end;
+      v[q] = load(ok ? sg[q] : s_c, ok ? idx : c);
     }
 #pragma unroll
     for (int q = 0; q < U; ++q) {
