@@ -214,6 +214,7 @@ ef_status ef_graph_free(ef_graph *h) {
     (void)hipFree(g.col_idx);
   }
   void *arrays[] = {g.deg, g.src, g.rev, g.adj2, g.asum, g.up_ptr, g.up_col, g.tslot,
+                    g.up_deg, g.dn_ptr, g.dn, g.tri_zero,
                     g.tri_list[0], g.tri_list[1], g.tri_list[2], g.tri_list[3], g.fin_list,
                     g.ps_list[0], g.ps_list[1], g.ps_list[2], g.ps_list[3], g.ps_list[4],
                     g.d_counters};
@@ -325,18 +326,65 @@ ef_status ef_graph_load_csr(int32_t n, int64_t nnz, const int32_t *row_ptr,
   ALLOC(g.asum, sizeof(int64_t) * std::max<size_t>(n, 1), "asum");
   ALLOC(g.up_ptr, sizeof(int32_t) * N1, "up_ptr");
   ALLOC(g.up_col, sizeof(int32_t) * NUP, "up_col");
+  ALLOC(g.up_deg, sizeof(int32_t) * NUP, "up_deg");
   ALLOC(g.tslot, sizeof(int32_t) * NNZ, "tslot");
+  ALLOC(g.dn_ptr, sizeof(int32_t) * N1, "dn_ptr");
+  ALLOC(g.dn, sizeof(int4) * NUP, "triangle segments");
   ALLOC(g.d_counters, sizeof(int32_t) * 64, "counters");
+  // tail entries walked at each node by the triangle pass (binning)
+  std::vector<int64_t> h_work((size_t)n);
   {
     int32_t *tmp = nullptr;
-    const size_t tmp_bytes = sizeof(int32_t) * (2 * NNZ + (size_t)scan_tmp_len((int64_t)NNZ));
+    int64_t *work = nullptr;
+    const size_t tmp_bytes = sizeof(int32_t) * (size_t)graph_prep_tmp_len((int64_t)NNZ);
+    const size_t work_bytes = sizeof(int64_t) * std::max<size_t>(n, 1);
     ALLOC(tmp, tmp_bytes, "preprocessing scratch");
-    hipError_t e = launch_graph_prep(g, tmp, stream);
+    st = dev_alloc(g, (void **)&work, work_bytes, "preprocessing scratch");
+    if (st != EF_OK) {
+      dev_free(g, tmp, tmp_bytes);
+      ef_graph_free(h);
+      return st;
+    }
+    bool not_symmetric = false;
+    hipError_t e = launch_graph_prep(g, tmp, work, not_symmetric, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e == hipSuccess && not_symmetric) {
+      dev_free(g, work, work_bytes);
+      dev_free(g, tmp, tmp_bytes);
+      ef_graph_free(h);
+      set_error("the CSR is not simple and symmetric (load with EF_VALIDATE for details)");
+      return EF_ERR_NOT_SYMMETRIC;
+    }
+    if (e == hipSuccess) e = graph_zero_count(g, tmp, g.n_tri_zero);
+    if (e == hipSuccess) {
+      st = dev_alloc(g, (void **)&g.tri_zero,
+                     sizeof(int32_t) * (size_t)std::max<int64_t>(g.n_tri_zero, 1), "zero slots");
+      if (st == EF_OK) {
+        e = launch_zero_list(g, tmp, stream);
+        if (e == hipSuccess && n > 0)
+          e = hipMemcpyAsync(h_work.data(), work, sizeof(int64_t) * (size_t)n,
+                             hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+      }
+    }
+    dev_free(g, work, work_bytes);
     dev_free(g, tmp, tmp_bytes);
+    if (st != EF_OK) {
+      ef_graph_free(h);
+      return st;
+    }
     if (e != hipSuccess) {
       ef_graph_free(h);
       return hip_status(e, "graph preprocessing");
+    }
+  }
+  std::vector<int32_t> h_dn_ptr(N1);
+  {
+    hipError_t e = hipMemcpy(h_dn_ptr.data(), g.dn_ptr, sizeof(int32_t) * N1,
+                             hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      ef_graph_free(h);
+      return hip_status(e, "copy dn_ptr to host");
     }
   }
   // host copies: degrees and |up(u)|
@@ -364,7 +412,7 @@ ef_status ef_graph_load_csr(int32_t n, int64_t nnz, const int32_t *row_ptr,
     g.h_up_len[v] = up;
     inf.clusters += k * (k - 1) / 2;
     inf.sum_sq_degree += k * k;
-    inf.wedge_checks += (int64_t)up * (k - up);
+    inf.wedge_checks += h_work[v];
     if (k >= 2 && k <= kSmallMax) {
       g.all_small++;
       g.all_small_deg[k]++;
@@ -379,18 +427,22 @@ ef_status ef_graph_load_csr(int32_t n, int64_t nnz, const int32_t *row_ptr,
       g.all_pairs_big += k * (k - 1) / 2;
       g.all_sblocks += ns;
     }
-    if (up >= 2) {
-      const int bin = up <= kTriBin0 ? 0 : up <= kTriBin1 ? 1 : up <= kTriBin2 ? 2 : 3;
+    const int32_t nd = h_dn_ptr[v + 1] - h_dn_ptr[v];
+    if (nd > 0) {
+      const int bin = (up <= kTriBin0 && h_work[v] <= kTriWaveWork && nd <= kTriWaveSegs) ? 0
+                      : up <= kTriBin1                                                  ? 1
+                      : up <= kTriBin2                                                  ? 2
+                                                                                        : 3;
       tri[bin].push_back(v);
     }
     if (k > kFinGroupMax) fin.push_back(v);
   }
-  // longest lists first
-  auto by_up = [&](int32_t a, int32_t b) {
-    return g.h_up_len[a] != g.h_up_len[b] ? g.h_up_len[a] > g.h_up_len[b] : a < b;
+  // longest walks first
+  auto by_work = [&](int32_t a, int32_t b) {
+    return h_work[a] != h_work[b] ? h_work[a] > h_work[b] : a < b;
   };
   for (int bin = 0; bin < 4; ++bin) {
-    std::sort(tri[bin].begin(), tri[bin].end(), by_up);
+    std::sort(tri[bin].begin(), tri[bin].end(), by_work);
     g.n_tri[bin] = (int64_t)tri[bin].size();
     ALLOC(g.tri_list[bin], sizeof(int32_t) * std::max<size_t>(tri[bin].size(), 1), "triangle list");
   }
@@ -774,8 +826,10 @@ extern "C" ef_status ef_compute(ef_graph *h, ef_algo algo, ef_prec prec, const i
   if (e != hipSuccess) return hip_status(e, "pair loop");
   prof.mark(5);
   if (!per_seed) {
-    if ((s = ws_ensure(g, WS_Y, sizeof(long long) * (size_t)nup, "triangle slots")) != EF_OK) return s;
-    if ((s = ws_ensure(g, WS_YT, sizeof(int32_t) * (size_t)nup, "triangle counts")) != EF_OK) return s;
+    if ((s = ws_ensure(g, WS_Y, sizeof(long long) * 2 * (size_t)nup, "triangle slots")) != EF_OK)
+      return s;
+    if ((s = ws_ensure(g, WS_YT, sizeof(int32_t) * 2 * (size_t)nup, "triangle counts")) != EF_OK)
+      return s;
     if ((s = ws_ensure(g, WS_Z, tsz * (size_t)std::max(g.n, 1), "triangle node sums")) != EF_OK) return s;
     if ((s = ws_ensure(g, WS_ZT, sizeof(int64_t) * (size_t)std::max(g.n, 1), "triangle node counts")) != EF_OK)
       return s;

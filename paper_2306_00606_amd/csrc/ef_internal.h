@@ -28,9 +28,14 @@ constexpr int kSuper = 1024;          // neighbours per super-block
 constexpr int kBlocksPerSuper = 16;   // 64-wide blocks per super-block
 constexpr int kRecEntries = 2 * kSuper;  // row part + column part per super-tile record
 
-// Triangle pass: nodes are binned by the length of their degree-oriented
-// out-list up(u): 2..64, 65..512, 513..2048 use an LDS hash of up(u) sized
-// for the bin; longer lists search global memory.
+// Triangle pass: a triangle is listed at its middle node w (by rank), with
+// an LDS hash of w's degree-oriented out-list up(w). Nodes w with segments
+// are binned by |up(w)| and by their walk (tail entries, segments):
+//   0: |up| <= kTriBin0, walk <= kTriWaveWork, segments <= kTriWaveSegs
+//      one wavefront
+//   1: |up| <= kTriBin1     one workgroup (8 wavefronts)
+//   2: |up| <= kTriBin2     one workgroup (16 wavefronts)
+//   3: longer               binary search of up(w) in global memory
 // Largest node degree accepted by the loader: cluster degrees (< 3 * kMaxDegree)
 // stay exact in int32, and a degree fits the 20-bit field of the packed
 // (degree, position) words of the triangle pass.
@@ -43,6 +48,8 @@ constexpr int32_t kFinGroupMax = 32;
 constexpr int32_t kFinHalfMax = 512;
 constexpr int32_t kFinBlockMin = 4096;
 constexpr int kTriLongMin = kTriBin2 + 1;
+constexpr int64_t kTriWaveWork = 4096;
+constexpr int32_t kTriWaveSegs = 256;
 
 // Per-seed formulation: seeds are binned by degree k and 2-hop work
 // A = sum of neighbour degrees:
@@ -104,12 +111,21 @@ struct Graph {
   int2 *adj2 = nullptr;        // (neighbour id, neighbour degree) per arc
   int64_t *asum = nullptr;     // sum of neighbour degrees per node
   int32_t *up_ptr = nullptr;   // degree-oriented half adjacency: u -> {w : rank(w) > rank(u)}
-  int32_t *up_col = nullptr;
+  int32_t *up_col = nullptr;   // each up(u) in rank order
+  int32_t *up_deg = nullptr;   // degree of every up_col entry
   int32_t *tslot = nullptr;    // for every arc: slot of its undirected edge in up_col
+  // triangle-pass segments of every node w (rows dn_ptr[w] .. dn_ptr[w+1]):
+  // {slot of {u, w} in up(u), length of the tail of up(u) above w, k_u, u}
+  // for the lower neighbours u of w with a non-empty tail
+  int32_t *dn_ptr = nullptr;
+  int4 *dn = nullptr;
+  // triangle slots (of 2 * up arcs) that no walk writes, cleared on each pass
+  int32_t *tri_zero = nullptr;
+  int64_t n_tri_zero = 0;
   // host copies used for sizing work lists
   std::vector<int32_t> h_deg;
   std::vector<int32_t> h_up_len;
-  // triangle-pass node lists (device) by |up(u)|: 2..64, 65..512, 513..4096, >4096
+  // triangle-pass node lists (device): see kTriBin*
   int32_t *tri_list[4] = {nullptr, nullptr, nullptr, nullptr};
   // nodes of degree > kFinGroupMax (finalized one wavefront each), by degree descending
   int32_t *fin_list = nullptr;
@@ -157,7 +173,11 @@ ef_status hip_status(hipError_t e, const char *what);
 // ---------------------------------------------------------------------------
 
 // graph preprocessing
-hipError_t launch_graph_prep(Graph &g, int32_t *flags_scan_tmp, hipStream_t st);
+int64_t graph_prep_tmp_len(int64_t nnz);
+hipError_t launch_graph_prep(Graph &g, int32_t *tmp, int64_t *work, bool &not_symmetric,
+                             hipStream_t st);
+hipError_t graph_zero_count(const Graph &g, const int32_t *tmp, int64_t &count);
+hipError_t launch_zero_list(Graph &g, const int32_t *tmp, hipStream_t st);
 hipError_t launch_exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t count,
                                      int32_t *block_tmp, int64_t block_tmp_len, hipStream_t st);
 int64_t scan_tmp_len(int64_t count);

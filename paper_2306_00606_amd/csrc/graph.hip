@@ -6,6 +6,11 @@
 // k_a < k_b, or k_a == k_b and a < b. up(u) = {w in N(u) : rank(w) > rank(u)}
 // keeps every undirected edge exactly once and bounds |up(u)| by
 // sqrt(2 * edges), which keeps the triangle pass short on skewed graphs.
+// Each up(u) is stored in rank order, so the part of up(u) ranked above one
+// of its members w is the contiguous tail after w. The triangle pass lists a
+// triangle u < w < x at its middle node w, walking for every lower neighbour
+// u of w that tail of up(u) against up(w); the per-node lists of those tails
+// ("segments": slot of {u, w} in up(u), tail length, k_u) are built here.
 #include "ef_internal.h"
 
 namespace efi {
@@ -73,6 +78,122 @@ __global__ void k_up_fill(const int32_t *__restrict__ row_ptr, const int32_t *__
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v <= n; v += stride) {
     if (v < n) up_ptr[v] = (row_ptr[v] < nnz) ? upidx[row_ptr[v]] : (int32_t)(nnz / 2);
     else up_ptr[v] = (int32_t)(nnz / 2);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Rank order inside every up(u) (rows are in id order after k_up_fill).
+// ---------------------------------------------------------------------------
+__global__ void k_up_keys(const int32_t *__restrict__ up_col, const int32_t *__restrict__ deg,
+                          int64_t nup, int32_t *__restrict__ upk) {
+  for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < nup;
+       s += (int64_t)gridDim.x * blockDim.x)
+    upk[s] = deg[up_col[s]];
+}
+
+// For every up-arc u -> x: its rank position r inside up(u) (number of
+// members ranked below x); newcol[up_ptr[u] + r] = x, newdeg[...] = k_x,
+// perm[old slot] = new slot. Quadratic in |up(u)|, which is at most sqrt(2 * edges).
+__global__ void k_up_sort(const int32_t *__restrict__ src, const int2 *__restrict__ adj2,
+                          const int32_t *__restrict__ upflag, const int32_t *__restrict__ upidx,
+                          int64_t nnz, const int32_t *__restrict__ up_ptr,
+                          const int32_t *__restrict__ up_col, const int32_t *__restrict__ upk,
+                          int32_t *__restrict__ newcol, int32_t *__restrict__ newdeg,
+                          int32_t *__restrict__ perm) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    if (!upflag[e]) continue;
+    const int32_t u = src[e];
+    const int2 xk = adj2[e];
+    const int32_t b0 = up_ptr[u], b1 = up_ptr[u + 1];
+    int32_t r = 0;
+    for (int32_t j = b0; j < b1; ++j) r += rank_less(up_col[j], upk[j], xk.x, xk.y) ? 1 : 0;
+    newcol[b0 + r] = xk.x;
+    newdeg[b0 + r] = xk.y;
+    perm[upidx[e]] = b0 + r;
+  }
+}
+
+__global__ void k_tslot_remap(int32_t *__restrict__ tslot, const int32_t *__restrict__ perm,
+                              int64_t nnz) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
+       e += (int64_t)gridDim.x * blockDim.x)
+    tslot[e] = perm[tslot[e]];
+}
+
+// Segments: a down-arc w -> u (rank(u) < rank(w)) with a non-empty tail of
+// up(u) above w, at a node w with up(w) non-empty (otherwise no triangle
+// has w in the middle).
+__global__ void k_dn_flag(const int32_t *__restrict__ src, const int32_t *__restrict__ col,
+                          const int32_t *__restrict__ upflag, const int32_t *__restrict__ tslot,
+                          const int32_t *__restrict__ up_ptr, int64_t nnz,
+                          int32_t *__restrict__ dnflag) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int32_t f = 0;
+    if (!upflag[e]) {
+      const int32_t w = src[e], u = col[e];
+      const int32_t tail = up_ptr[u + 1] - tslot[e] - 1;
+      f = (tail > 0 && up_ptr[w + 1] > up_ptr[w]) ? 1 : 0;
+    }
+    dnflag[e] = f;
+  }
+}
+
+__global__ void k_dn_fill(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                          const int32_t *__restrict__ deg, const int32_t *__restrict__ tslot,
+                          const int32_t *__restrict__ up_ptr, const int32_t *__restrict__ dnflag,
+                          const int32_t *__restrict__ dnidx, int32_t n, int64_t nnz,
+                          int4 *__restrict__ dn, int32_t *__restrict__ dn_ptr) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int32_t ndn = nnz > 0 ? dnidx[nnz - 1] + dnflag[nnz - 1] : 0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz; e += stride) {
+    if (dnflag[e]) {
+      const int32_t u = col[e], s = tslot[e];
+      dn[dnidx[e]] = make_int4(s, up_ptr[u + 1] - s - 1, deg[u], u);
+    }
+  }
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v <= n; v += stride)
+    dn_ptr[v] = (v < n && row_ptr[v] < nnz) ? dnidx[row_ptr[v]] : ndn;
+}
+
+// Triangle slots that no kernel writes on a pass (cleared before it):
+//   upper-end slot s of {a, b} (a < b): written by a's walk unless a has no
+//     segments, or is a long-list node (those add with atomics);
+//   lower-end slot nup + s: written by b's walk when {a, b} is a segment.
+__global__ void k_zero_flag(const int32_t *__restrict__ src, const int32_t *__restrict__ rev,
+                            const int32_t *__restrict__ upflag, const int32_t *__restrict__ tslot,
+                            const int32_t *__restrict__ up_ptr, const int32_t *__restrict__ dn_ptr,
+                            const int32_t *__restrict__ dnflag, int64_t nnz, int64_t nup,
+                            int32_t *__restrict__ zf) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    if (!upflag[e]) continue;
+    const int32_t a = src[e], s = tslot[e];
+    const int32_t nd = dn_ptr[a + 1] - dn_ptr[a], m = up_ptr[a + 1] - up_ptr[a];
+    zf[s] = (nd == 0 || m > kTriBin2) ? 1 : 0;
+    zf[nup + s] = dnflag[rev[e]] ? 0 : 1;
+  }
+}
+
+__global__ void k_zero_fill(const int32_t *__restrict__ zf, const int32_t *__restrict__ zidx,
+                            int64_t count, int32_t *__restrict__ list) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    if (zf[i]) list[zidx[i]] = (int32_t)i;
+}
+
+// One wavefront per node: tail entries walked at w (sum of its segment lengths).
+__global__ void k_dn_work(const int32_t *__restrict__ dn_ptr, const int4 *__restrict__ dn,
+                          int32_t n, int64_t *__restrict__ work) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t v = wave; v < n; v += nwaves) {
+    int64_t acc = 0;
+    for (int32_t i = dn_ptr[v] + lane; i < dn_ptr[v + 1]; i += 64) acc += dn[i].y;
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) work[v] = acc;
   }
 }
 
@@ -189,30 +310,110 @@ static unsigned grid_for(int64_t work, int threads) {
   return (unsigned)b;
 }
 
-// flags_scan_tmp: 2 * nnz + scan_tmp_len(nnz) ints of scratch.
-hipError_t launch_graph_prep(Graph &g, int32_t *tmp, hipStream_t st) {
+// Scratch of launch_graph_prep, in ints:
+//   [0, nnz)          up flags          [nnz, 2 nnz)   up indices, then zero-slot indices
+//   [2 nnz, 3 nnz)    rank keys | rank-sorted up_col, then segment indices, then zero flags
+//   [3 nnz, 4 nnz)    segment flags     [4 nnz, 4 nnz + nup)   slot permutation
+//   then the scan's block totals
+int64_t graph_prep_tmp_len(int64_t nnz) {
+  return 4 * nnz + nnz / 2 + scan_tmp_len(nnz);
+}
+
+// Everything but the zero-slot list, whose length the caller reads back
+// (graph_zero_count) to size it; work[v] = tail entries walked at v.
+// A simple symmetric graph has exactly nnz / 2 up-arcs; anything else is
+// reported through not_symmetric before any array is filled by them.
+hipError_t launch_graph_prep(Graph &g, int32_t *tmp, int64_t *work, bool &not_symmetric,
+                             hipStream_t st) {
+  not_symmetric = false;
   const int T = 256;
   hipLaunchKernelGGL(k_degree, dim3(grid_for(g.n, T)), dim3(T), 0, st, g.row_ptr, g.n, g.deg);
   if (g.nnz > 0) {
-    int32_t *upflag = tmp, *upidx = tmp + g.nnz, *scan_tmp = tmp + 2 * g.nnz;
-    hipLaunchKernelGGL(k_arc_src, dim3(grid_for(g.nnz, T)), dim3(T), 0, st, g.row_ptr, g.n,
-                       g.nnz, g.src);
-    hipLaunchKernelGGL(k_arc_rev, dim3(grid_for(g.nnz, T)), dim3(T), 0, st, g.row_ptr,
-                       g.col_idx, g.src, g.deg, g.nnz, g.rev, g.adj2, upflag);
-    hipError_t e = launch_exclusive_scan_i32(upflag, upidx, g.nnz, scan_tmp,
-                                             scan_tmp_len(g.nnz), st);
+    const int64_t nnz = g.nnz, nup = nnz / 2;
+    int32_t *upflag = tmp, *upidx = tmp + nnz, *G = tmp + 2 * nnz, *dnflag = tmp + 3 * nnz,
+            *perm = tmp + 4 * nnz, *scan_tmp = tmp + 4 * nnz + nup;
+    const int64_t sl = scan_tmp_len(nnz);
+    hipLaunchKernelGGL(k_arc_src, dim3(grid_for(nnz, T)), dim3(T), 0, st, g.row_ptr, g.n, nnz,
+                       g.src);
+    hipLaunchKernelGGL(k_arc_rev, dim3(grid_for(nnz, T)), dim3(T), 0, st, g.row_ptr,
+                       g.col_idx, g.src, g.deg, nnz, g.rev, g.adj2, upflag);
+    hipError_t e = launch_exclusive_scan_i32(upflag, upidx, nnz, scan_tmp, sl, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    int32_t last_idx = 0, last_flag = 0;
+    if (e == hipSuccess)
+      e = hipMemcpy(&last_idx, upidx + nnz - 1, sizeof(int32_t), hipMemcpyDeviceToHost);
+    if (e == hipSuccess)
+      e = hipMemcpy(&last_flag, upflag + nnz - 1, sizeof(int32_t), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_up_fill, dim3(grid_for(g.nnz, T)), dim3(T), 0, st, g.row_ptr,
-                       g.col_idx, g.rev, upflag, upidx, g.n, g.nnz, g.up_ptr, g.up_col,
+    if ((int64_t)last_idx + last_flag != nup || 2 * nup != nnz) {
+      not_symmetric = true;
+      return hipSuccess;
+    }
+    hipLaunchKernelGGL(k_up_fill, dim3(grid_for(nnz, T)), dim3(T), 0, st, g.row_ptr,
+                       g.col_idx, g.rev, upflag, upidx, g.n, nnz, g.up_ptr, g.up_col,
                        g.tslot);
+    // rank order inside each up(u)
+    int32_t *upk = G, *newcol = G + nup;
+    hipLaunchKernelGGL(k_up_keys, dim3(grid_for(nup, T)), dim3(T), 0, st, g.up_col, g.deg, nup,
+                       upk);
+    hipLaunchKernelGGL(k_up_sort, dim3(grid_for(nnz, T)), dim3(T), 0, st, g.src, g.adj2,
+                       upflag, upidx, nnz, g.up_ptr, g.up_col, upk, newcol, g.up_deg, perm);
+    e = hipMemcpyAsync(g.up_col, newcol, sizeof(int32_t) * (size_t)nup, hipMemcpyDeviceToDevice,
+                       st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_tslot_remap, dim3(grid_for(nnz, T)), dim3(T), 0, st, g.tslot, perm,
+                       nnz);
+    // segments of the triangle pass
+    int32_t *dnidx = G;
+    hipLaunchKernelGGL(k_dn_flag, dim3(grid_for(nnz, T)), dim3(T), 0, st, g.src, g.col_idx,
+                       upflag, g.tslot, g.up_ptr, nnz, dnflag);
+    e = launch_exclusive_scan_i32(dnflag, dnidx, nnz, scan_tmp, sl, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_dn_fill, dim3(grid_for(nnz, T)), dim3(T), 0, st, g.row_ptr, g.col_idx,
+                       g.deg, g.tslot, g.up_ptr, dnflag, dnidx, g.n, nnz, g.dn, g.dn_ptr);
+    hipLaunchKernelGGL(k_dn_work, dim3(grid_for((int64_t)g.n * 64, T)), dim3(T), 0, st,
+                       g.dn_ptr, g.dn, g.n, work);
+    // slots no walk writes: flags over both halves, then their scan
+    int32_t *zf = G, *zidx = upidx;
+    hipLaunchKernelGGL(k_zero_flag, dim3(grid_for(nnz, T)), dim3(T), 0, st, g.src, g.rev,
+                       upflag, g.tslot, g.up_ptr, g.dn_ptr, dnflag, nnz, nup, zf);
+    e = launch_exclusive_scan_i32(zf, zidx, 2 * nup, scan_tmp, sl, st);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_asum, dim3(grid_for((int64_t)g.n * 64, T)), dim3(T), 0, st,
                        g.row_ptr, g.adj2, g.n, g.asum);
   } else {
     hipLaunchKernelGGL(k_up_fill, dim3(grid_for(g.n + 1, T)), dim3(T), 0, st, g.row_ptr,
                        g.col_idx, g.rev, tmp, tmp, g.n, (int64_t)0, g.up_ptr, g.up_col,
                        g.tslot);
+    hipLaunchKernelGGL(k_dn_fill, dim3(grid_for(g.n + 1, T)), dim3(T), 0, st, g.row_ptr,
+                       g.col_idx, g.deg, g.tslot, g.up_ptr, tmp, tmp, g.n, (int64_t)0, g.dn,
+                       g.dn_ptr);
     (void)hipMemsetAsync(g.asum, 0, sizeof(int64_t) * (size_t)g.n, st);
+    (void)hipMemsetAsync(work, 0, sizeof(int64_t) * (size_t)g.n, st);
   }
+  return hipGetLastError();
+}
+
+// Length of the zero-slot list (after launch_graph_prep has completed).
+hipError_t graph_zero_count(const Graph &g, const int32_t *tmp, int64_t &count) {
+  count = 0;
+  const int64_t nnz = g.nnz, nup = nnz / 2;
+  if (nup <= 0) return hipSuccess;
+  int32_t last_idx = 0, last_flag = 0;
+  hipError_t e = hipMemcpy(&last_idx, tmp + nnz + 2 * nup - 1, sizeof(int32_t),
+                           hipMemcpyDeviceToHost);
+  if (e == hipSuccess)
+    e = hipMemcpy(&last_flag, tmp + 2 * nnz + 2 * nup - 1, sizeof(int32_t),
+                  hipMemcpyDeviceToHost);
+  count = (int64_t)last_idx + last_flag;
+  return e;
+}
+
+hipError_t launch_zero_list(Graph &g, const int32_t *tmp, hipStream_t st) {
+  const int64_t nnz = g.nnz, nup = nnz / 2;
+  if (nup <= 0 || g.n_tri_zero <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_fill, dim3(grid_for(2 * nup, 256)), dim3(256), 0, st,
+                     tmp + 2 * nnz, tmp + nnz, 2 * nup, g.tri_zero);
   return hipGetLastError();
 }
 

@@ -153,14 +153,17 @@ template <int G> __device__ __forceinline__ DFv group_sum(DFv x) {
 }
 
 // arcs first, first + stride, ... of node v: its own row sums R[e], the
-// reverse arcs' R[rev e], exact N and D, and its up-arc triangle slots
+// reverse arcs' R[rev e], exact N and D, and the triangle credits to v kept
+// with each of its edges (the upper-end slot of an edge to a lower-ranked
+// neighbour, the lower-end slot nup + slot otherwise)
 template <typename T>
 __device__ __forceinline__ void fin_arcs(const int2 *__restrict__ adj2,
                                          const int32_t *__restrict__ rev,
                                          const int32_t *__restrict__ tslot,
                                          const int64_t *__restrict__ asum, const void *R,
                                          const long long *__restrict__ Y,
-                                         const int32_t *__restrict__ YT, int32_t v, int32_t k,
+                                         const int32_t *__restrict__ YT, int64_t nup, int32_t v,
+                                         int32_t k,
                                          int32_t base, int64_t As, int32_t first, int32_t stride,
                                          typename SumT<T>::type &sacc, double &tfix, int64_t &Nn,
                                          int64_t &Dd, int64_t &Tc) {
@@ -174,11 +177,9 @@ __device__ __forceinline__ void fin_arcs(const int2 *__restrict__ adj2,
     Nn += (int64_t)(k - 1) + (ka - 1);
     Dd += (int64_t)(k - 1) * (k + ka - 4) + (As - ka) + (int64_t)(ka - 1) * (ka + k - 4) +
           (asum[a] - k);
-    if (rank_less_d(a, ka, v, k)) {
-      const int32_t sl = tslot[e];
-      tfix += (double)Y[sl];  // 2^-40 fixed-point units
-      Tc += YT[sl];
-    }
+    const int64_t sl = tslot[e] + (rank_less_d(a, ka, v, k) ? 0 : nup);
+    tfix += (double)Y[sl];  // 2^-40 fixed-point units
+    Tc += YT[sl];
   }
 }
 
@@ -208,6 +209,7 @@ struct FinArgs {
   const void *R;
   const long long *Y;
   const int32_t *YT;
+  int64_t nup;
   const void *Z;
   const int64_t *ZT;
   double *ef;
@@ -239,7 +241,7 @@ __device__ __forceinline__ void fin_groups(const FinArgs &A, const int32_t *node
     double tfix = 0.0;
     int64_t Nn = 0, Dd = 0, Tc = 0;
     if (v >= 0)
-      fin_arcs<T>(A.adj2, A.rev, A.tslot, A.asum, A.R, A.Y, A.YT, v, k, A.row_ptr[v], A.asum[v],
+      fin_arcs<T>(A.adj2, A.rev, A.tslot, A.asum, A.R, A.Y, A.YT, A.nup, v, k, A.row_ptr[v], A.asum[v],
                   sub, G, sacc, tfix, Nn, Dd, Tc);
     sacc = group_sum<G>(sacc);
     tfix = group_sum<G>(tfix);
@@ -265,7 +267,7 @@ __device__ __forceinline__ void fin_hubs(const FinArgs &A, const int32_t *nodes,
     Acc sacc = Acc();
     double tfix = 0.0;
     int64_t Nn = 0, Dd = 0, Tc = 0;
-    fin_arcs<T>(A.adj2, A.rev, A.tslot, A.asum, A.R, A.Y, A.YT, v, k, A.row_ptr[v], A.asum[v],
+    fin_arcs<T>(A.adj2, A.rev, A.tslot, A.asum, A.R, A.Y, A.YT, A.nup, v, k, A.row_ptr[v], A.asum[v],
                 tid, 256, sacc, tfix, Nn, Dd, Tc);
     sacc = wave_sum(sacc);
     tfix = wave_sum_f64(tfix);
@@ -329,7 +331,8 @@ hipError_t launch_finalize_cluster(const Graph &g, ef_prec prec, const void *R,
   const int64_t bw = n_wave > 0 ? cap_blocks((n_wave * 64 + 255) / 256, 1 << 18) : 0;
   const int64_t bc = g.n_fin_half > 0 ? cap_blocks((g.n_fin_half * 32 + 255) / 256, 1 << 18) : 0;
   const int64_t bs = cap_blocks(((int64_t)g.n * 8 + 255) / 256, 1 << 19);
-  const FinArgs A{g.row_ptr, g.deg, g.adj2, g.rev, g.tslot, g.asum, R, Y, YT, Z, ZT, ef, D, N, fl};
+  const FinArgs A{g.row_ptr, g.deg, g.adj2, g.rev, g.tslot, g.asum, R,  Y,  YT,
+                  g.nnz / 2,  Z,       ZT,     ef,     D,      N,      fl};
   const unsigned grid = (unsigned)(bh + bw + bc + bs);
   if (prec == EF_PREC_FP64)
     hipLaunchKernelGGL(k_finalize_cluster<double>, dim3(grid), dim3(256), 0, st, A, g.fin_list,

@@ -249,10 +249,12 @@ ef_status ef_features(ef_graph *h, float *X, float *lnN, uint32_t flags, void *h
   Graph &g = h->g;
   if (g.n == 0) return EF_OK;
   hipStream_t st = (hipStream_t)hip_stream;
-  const size_t n = (size_t)g.n, nup = (size_t)std::max<int64_t>(g.nnz / 2, 1);
+  const size_t n = (size_t)g.n;
+  // triangle slots: an upper-end and a lower-end slot per up arc
+  const size_t nts = 2 * (size_t)std::max<int64_t>(g.nnz / 2, 1);
   // triangle counts per node come from the triangle pass (FP32 deltas unused)
   char *p = nullptr;
-  const size_t need = sizeof(long long) * nup + sizeof(int32_t) * nup + sizeof(float2) * n +
+  const size_t need = sizeof(long long) * nts + sizeof(int32_t) * nts + sizeof(float2) * n +
                       sizeof(int64_t) * n + (sizeof(float) * kNF + sizeof(float)) * n + 4096;
   ef_status rs = graph_scratch(g, need, (void **)&p);
   if (rs != EF_OK) return rs;
@@ -263,8 +265,8 @@ ef_status ef_features(ef_graph *h, float *X, float *lnN, uint32_t flags, void *h
     return r;
   };
   char *base = p;
-  long long *Y = (long long *)take(sizeof(long long) * nup);
-  int32_t *YT = (int32_t *)take(sizeof(int32_t) * nup);
+  long long *Y = (long long *)take(sizeof(long long) * nts);
+  int32_t *YT = (int32_t *)take(sizeof(int32_t) * nts);
   void *Z = take(sizeof(float2) * n);
   int64_t *ZT = (int64_t *)take(sizeof(int64_t) * n);
   const bool dev = (flags & EF_OUT_DEVICE) != 0;
@@ -468,9 +470,11 @@ ef_status ef_surrogate_predict(ef_surrogate *s, ef_graph *h, double *ef_pred, ui
   hipStream_t st = (hipStream_t)hip_stream;
   ef_status r = s->device_ready ? EF_OK : sg_upload(s, st);
   if (r != EF_OK) return r;
-  const size_t n = (size_t)g.n, nup = (size_t)std::max<int64_t>(g.nnz / 2, 1);
+  const size_t n = (size_t)g.n;
+  // triangle slots: an upper-end and a lower-end slot per up arc
+  const size_t nts = 2 * (size_t)std::max<int64_t>(g.nnz / 2, 1);
   char *p = nullptr;
-  const size_t need = sizeof(long long) * nup + sizeof(int32_t) * nup + sizeof(float2) * n +
+  const size_t need = sizeof(long long) * nts + sizeof(int32_t) * nts + sizeof(float2) * n +
                       sizeof(int64_t) * n + (sizeof(float) * kNF + sizeof(float)) * n +
                       sizeof(double) * n + 4096;
   ef_status rs = graph_scratch(g, need, (void **)&p);
@@ -482,8 +486,8 @@ ef_status ef_surrogate_predict(ef_surrogate *s, ef_graph *h, double *ef_pred, ui
     p += (b + 255) & ~(size_t)255;
     return rr;
   };
-  long long *Y = (long long *)take(sizeof(long long) * nup);
-  int32_t *YT = (int32_t *)take(sizeof(int32_t) * nup);
+  long long *Y = (long long *)take(sizeof(long long) * nts);
+  int32_t *YT = (int32_t *)take(sizeof(int32_t) * nts);
   void *Z = take(sizeof(float2) * n);
   int64_t *ZT = (int64_t *)take(sizeof(int64_t) * n);
   float *Xd = (float *)take(sizeof(float) * kNF * n);

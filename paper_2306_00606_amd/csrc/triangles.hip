@@ -9,19 +9,23 @@
 //   4 * delta(sigma), delta(sigma) = g(sigma - 6) - g(sigma - 4), and the
 //   degree sum D by -8.
 //
-// Listing: nodes are ranked by (degree, id); a triangle u < w < x (by rank) is
-// found once, at u, as x in up(u) and up(w), where up(.) is the rank-oriented
-// out-list. up(u) is hashed in LDS (id -> degree, position) and the lists
-// up(w), w in up(u), are walked as one concatenated sequence ("segments"),
-// 64 consecutive entries per wavefront step. Short up(u): one wavefront per u.
-// Longer up(u): one workgroup per u, each wavefront walking a contiguous
-// share of the sequence. Credits:
-//   u  - lane registers (floating point), reduced at the end  -> Z[u], ZT[u]
-//   w  - LDS add at w's position in up(u)
-//   x  - LDS add at x's position in up(u)
+// Listing: nodes are ranked by (degree, id) and every up(.) list (members of
+// higher rank) is stored in rank order. A triangle u < w < x (by rank) is
+// found once, at its middle node w: x lies in up(w) and in the tail of up(u)
+// above w. up(w) is hashed in LDS (id -> degree, position), and the tails of
+// up(u) for the lower neighbours u of w ("segments", built with the graph)
+// are walked as one concatenated sequence, 64 consecutive entries per
+// wavefront step. Each membership test is one pair (w, x) inside some up(u),
+// so the pass makes sum_u C(|up(u)|, 2) tests, against
+// sum_w |up(w)| * |down(w)| for a listing at the lowest node.
+// Credits, per triangle:
+//   w  - lane registers (floating point), reduced at the end  -> Z[w], ZT[w]
+//   x  - LDS add at x's position in up(w)  -> upper-end slot Y[slot of {w, x}]
+//   u  - LDS add at the segment's index    -> lower-end slot Y[nup + slot of {u, w}]
 // The LDS credit slots are integers (see Credit), so concurrent adds are exact
-// and order-independent: results are bitwise reproducible. The slots are
-// written to Y[slot], YT[slot] for the up-arc slots of u.
+// and order-independent: results are bitwise reproducible. Segments are taken
+// in chunks of at most MAXS; the credits to x are added to their slots after
+// every chunk, which bounds the credits an LDS slot holds by 2^11.
 #include "common.cuh"
 
 namespace efi {
@@ -44,7 +48,9 @@ template <typename T> __device__ __forceinline__ long long to_fix(T v) {
 // FP32: delta < 0 is a float with 2 <= |delta| < 2^7 (log2 units, degrees
 //   below kMaxDegree), so its ulp is >= 2^-22 and |delta| * 2^24 is an exact
 //   integer below 2^31. A slot holds one word, count << 44 plus the sum of
-//   those integers; at most kTriBin2 = 2^11 credits land in a slot, so the
+//   those integers; at most 2^11 credits land in a slot before it is flushed
+//   (a segment's hits are members of up(w), |up(w)| <= kTriBin2 = 2^11; x
+//   gets at most one credit per segment of a chunk, MAXS <= 2^11), so the
 //   sum stays below 2^42 and one 64-bit add records credit and count.
 // FP64: the credit rounded to 2^-40 in one 64-bit slot, the count in a
 //   separate 32-bit slot.
@@ -99,107 +105,76 @@ template <> struct Credit<TriCount> {
   }
 };
 
-// LDS state of one u:
-//   hkey[SLOTS]   ids x of up(u) (LdsHash), hval[slot] = k_x << kPosBits |
-//                 position of x in up(u)
-//   seg[MAXM]     per non-empty up(w): {first index of up(w) in up_col minus
-//                 its first index in the concatenated sequence,
-//                 k_w << kPosBits | position of w in up(u)}
-//   segp[MAXM+1]  first concatenated index of each segment; segp[nseg] = total
-//   acc, cnt      credit slots by position in up(u)
-//   flg[kFlg]     per wavefront: segment-start flags of the current step
-template <typename T, int SLOTS, int MAXM> struct TriLds {
-  static_assert(SLOTS >= 2 * MAXM, "the hash set of up(u) must stay at most half full");
+// LDS state of one w:
+//   hkey[SLOTS]   ids x of up(w) (LdsHash), hval[slot] = k_x << kPosBits |
+//                 position of x in up(w)
+//   seg[MAXS]     per segment of the chunk: {first index of the tail in up_col
+//                 minus its first index in the concatenated sequence, k_u}
+//   segp[MAXS+1]  first concatenated index of each segment; segp[nseg] = total
+//   sslot[MAXS]   slot of {u, w} in up(u): the segment's lower-end slot
+//   acc, cnt      credits to x by position in up(w)
+//   sacc, scnt    credits to u by segment
+template <typename T, int SLOTS, int MAXM, int MAXS> struct TriLds {
+  static_assert(SLOTS >= 2 * MAXM, "the hash set of up(w) must stay at most half full");
+  static_assert(MAXM <= (1 << 11) && MAXS <= (1 << 11), "credit slots hold at most 2^11 credits");
   __align__(16) int32_t hkey[SLOTS];
   int32_t hval[SLOTS];
-  int2 seg[MAXM];
-  int32_t segp[MAXM + 1];
+  int2 seg[MAXS];
+  int32_t segp[MAXS + 1];
+  int32_t sslot[MAXS];
   unsigned long long acc[MAXM];
+  unsigned long long sacc[MAXS];
   int32_t cnt[Credit<T>::kPacked ? 1 : MAXM];
+  int32_t scnt[Credit<T>::kPacked ? 1 : MAXS];
 };
 
-// Build the hash of up(u) and the segment table with NT threads (one
-// wavefront, or the workgroup); `part` holds 2 * NT/64 ints of scratch.
-// Returns the segment count and the sequence length.
+// Hash up(w) (m entries from w0) with NT threads; returns the slot this
+// thread filled last (-1 if none).
 template <int SLOTS, int NT>
-__device__ __forceinline__ void tri_setup(const int32_t *__restrict__ up_ptr,
-                                          const int32_t *__restrict__ up_col,
-                                          const int32_t *__restrict__ deg, int32_t u0, int32_t m,
-                                          int tid, int32_t *hkey, int32_t *hval, int2 *seg,
-                                          int32_t *segp,
-                                          int32_t *part, int32_t &nseg_out, int32_t &total_out,
-                                          int32_t &myslot) {
-  constexpr int NW = NT / 64;
-  const int lane = tid & 63, wv = tid >> 6;
-  const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  int32_t nseg = 0, run = 0;
-  for (int c = 0; c < m; c += NT) {
-    const int i = c + tid;
-    int32_t x = 0, w0 = 0, len = 0, kx = 0;
-    if (i < m) {
-      x = up_col[u0 + i];
-      w0 = up_ptr[x];
-      len = up_ptr[x + 1] - w0;
-      kx = deg[x];
-      myslot = LdsHash<SLOTS>::insert(hkey, x);
-      hval[myslot] = pack_kp(kx, i);
-    }
-    const unsigned long long nz = __ballot(len > 0);
-    int32_t incl = len;
-    for (int off = 1; off < 64; off <<= 1) {
-      const int32_t y = __shfl_up(incl, off, 64);
-      if (lane >= off) incl += y;
-    }
-    int32_t pre_n = 0, pre_l = 0, tot_n, tot_l;
-    if constexpr (NW == 1) {
-      tot_n = __popcll(nz);
-      tot_l = __shfl(incl, 63, 64);
-    } else {
-      if (lane == 63) {
-        part[2 * wv] = __popcll(nz);
-        part[2 * wv + 1] = incl;
-      }
-      __syncthreads();
-      tot_n = 0;
-      tot_l = 0;
-      for (int w = 0; w < NW; ++w) {
-        const int32_t a = part[2 * w], b = part[2 * w + 1];
-        if (w < wv) {
-          pre_n += a;
-          pre_l += b;
-        }
-        tot_n += a;
-        tot_l += b;
-      }
-    }
-    if (len > 0) {
-      const int32_t slot = nseg + pre_n + __popcll(nz & lt_mask);
-      const int32_t start = run + pre_l + incl - len;
-      seg[slot] = make_int2(w0 - start, pack_kp(kx, i));
-      segp[slot] = start;
-    }
-    nseg += tot_n;
-    run += tot_l;
-    if constexpr (NW > 1) __syncthreads();
+__device__ __forceinline__ int32_t tri_hash(const int32_t *__restrict__ up_col,
+                                            const int32_t *__restrict__ up_deg, int32_t w0,
+                                            int32_t m, int tid, int32_t *hkey, int32_t *hval) {
+  int32_t myslot = -1;
+  for (int32_t i = tid; i < m; i += NT) {
+    const int32_t x = up_col[w0 + i];
+    myslot = LdsHash<SLOTS>::insert(hkey, x);
+    hval[myslot] = pack_kp(up_deg[w0 + i], i);
   }
-  if (tid == 0) segp[nseg] = run;
-  nseg_out = nseg;
-  total_out = run;
+  return myslot;
 }
 
-// One wavefront walks entries [beg, end) of u's concatenated up(w) lists,
+// Segment table of one chunk: cnt <= NT segments from dn[d0]; every segment
+// is non-empty. Returns the concatenated length (workgroup form: every
+// thread calls it; `part` holds NT/64 ints).
+template <int NT, typename L>
+__device__ __forceinline__ int32_t tri_segs(const int4 *__restrict__ dn, int32_t d0, int32_t cnt,
+                                            int tid, L &lds, int32_t *part) {
+  int4 e = make_int4(0, 0, 0, 0);
+  if (tid < cnt) e = dn[d0 + tid];
+  int32_t total;
+  const int32_t start = group_excl_scan<NT>(e.y, part, total);
+  if (tid < cnt) {
+    lds.seg[tid] = make_int2(e.x + 1 - start, e.z);
+    lds.segp[tid] = start;
+    lds.sslot[tid] = e.x;
+  }
+  if (tid == 0) lds.segp[cnt] = total;
+  return total;
+}
+
+// One wavefront walks entries [beg, end) of the chunk's concatenated tails,
 // 64 consecutive entries per step (segment of each lane: seg_walk). A hit
-// (x in up(u)) is appended to the wavefront's LDS queue as two words,
-// {sigma, pos(w) | pos(x) << 16}; whenever 64 hits are queued they are
+// (x in up(w)) is appended to the wavefront's LDS queue as two words,
+// {sigma, segment | pos(x) << 16}; whenever 64 hits are queued they are
 // scored and credited with every lane busy, so the hit path does not run
-// divergently on almost every step (about 6% of the entries are hits).
+// divergently on almost every step.
 constexpr int kQueue = 128;
 
-template <typename T, int SLOTS, int MAXM>
+template <typename T, int SLOTS, int MAXM, int MAXS>
 __device__ __forceinline__ void tri_walk(const int32_t *__restrict__ up_col,
-                                         TriLds<T, SLOTS, MAXM> &L, int32_t *flg, int2 *hq,
-                                         int32_t nseg, int32_t beg, int32_t end, int32_t ku,
-                                         typename SumT<T>::type &accu, int64_t &cntu) {
+                                         TriLds<T, SLOTS, MAXM, MAXS> &L, int32_t *flg, int2 *hq,
+                                         int32_t nseg, int32_t beg, int32_t end, int32_t kw,
+                                         typename SumT<T>::type &accw, int64_t &cntw) {
   using S = SumT<T>;
   constexpr int32_t kPosMask = (1 << kPosBits) - 1;
   const int lane = threadIdx.x & 63;
@@ -213,10 +188,10 @@ __device__ __forceinline__ void tri_walk(const int32_t *__restrict__ up_col,
     if (lane < cnt) {
       const int2 h = hq[qn - cnt + lane];
       const T dl = tri_delta<T>(h.x);
-      S::add_term(accu, dl);
-      ++cntu;
+      S::add_term(accw, dl);
+      ++cntw;
       Credit<T>::add(L.acc, L.cnt, h.y >> 16, dl);
-      Credit<T>::add(L.acc, L.cnt, h.y & 0xFFFF, dl);
+      Credit<T>::add(L.sacc, L.scnt, h.y & 0xFFFF, dl);
     }
     qn -= cnt;
     wave_sync();
@@ -227,7 +202,7 @@ __device__ __forceinline__ void tri_walk(const int32_t *__restrict__ up_col,
         const int2 sv = seg[sg];
         return make_int2(up_col[sv.x + idx], sv.y);
       },
-      [&](int32_t, int32_t, int2 xv, bool ok) {
+      [&](int32_t sg, int32_t, int2 xv, bool ok) {
         const int32_t slot = ok ? LdsHash<SLOTS>::find(hkey, xv.x) : -1;
         const bool hit = slot >= 0;
         const unsigned long long m = __ballot(hit);
@@ -235,8 +210,7 @@ __device__ __forceinline__ void tri_walk(const int32_t *__restrict__ up_col,
           const int32_t ev = hval[slot];
           const int32_t rank = (int32_t)__builtin_amdgcn_mbcnt_hi(
               (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-          hq[qn + rank] = make_int2(ku + unpack_k(xv.y) + unpack_k(ev),
-                                    (xv.y & kPosMask) | ((ev & kPosMask) << 16));
+          hq[qn + rank] = make_int2(kw + xv.y + unpack_k(ev), sg | ((ev & kPosMask) << 16));
         }
         qn += __popcll(m);
         if (qn >= 64) drain(64);
@@ -244,225 +218,241 @@ __device__ __forceinline__ void tri_walk(const int32_t *__restrict__ up_col,
   if (qn > 0) drain(qn);
 }
 
-template <typename T, int SLOTS, int MAXM>
-__device__ __forceinline__ void tri_clear_acc(TriLds<T, SLOTS, MAXM> &L, int32_t m, int tid,
-                                              int nt) {
-  for (int i = tid; i < m; i += nt) {
-    L.acc[i] = 0ull;
-    if constexpr (!Credit<T>::kPacked) L.cnt[i] = 0;
+// After a chunk: the credits to u go to the segments' lower-end slots, the
+// credits to x are stored (first chunk) or added to w's upper-end slots.
+// Clears both for the next chunk.
+template <typename T, int SLOTS, int MAXM, int MAXS>
+__device__ __forceinline__ void tri_flush(TriLds<T, SLOTS, MAXM, MAXS> &L, int32_t cnt, int32_t w0,
+                                          int32_t m, bool first, int tid, int nt, int64_t nup,
+                                          long long *Y, int32_t *YT) {
+  for (int32_t i = tid; i < cnt; i += nt) {
+    long long y;
+    int32_t yt;
+    Credit<T>::load(L.sacc, L.scnt, i, y, yt);
+    const int64_t sl = nup + L.sslot[i];
+    Y[sl] = y;
+    YT[sl] = yt;
+    L.sacc[i] = 0ull;
+    if constexpr (!Credit<T>::kPacked) L.scnt[i] = 0;
   }
-}
-
-template <typename T, int SLOTS, int MAXM>
-__device__ __forceinline__ void tri_clear(TriLds<T, SLOTS, MAXM> &L, int32_t m, int tid, int nt) {
-  for (int i = tid; i < SLOTS; i += nt) L.hkey[i] = -1;
-  for (int i = tid; i < m; i += nt) {
-    L.acc[i] = 0ull;
-    if constexpr (!Credit<T>::kPacked) L.cnt[i] = 0;
-  }
-}
-
-template <typename T, int SLOTS, int MAXM>
-__device__ __forceinline__ void tri_store(const TriLds<T, SLOTS, MAXM> &L, int32_t u0, int32_t m,
-                                          int tid, int nt, long long *Y, int32_t *YT) {
-  for (int i = tid; i < m; i += nt) {
+  for (int32_t i = tid; i < m; i += nt) {
     long long y;
     int32_t yt;
     Credit<T>::load(L.acc, L.cnt, i, y, yt);
-    Y[u0 + i] = y;
-    YT[u0 + i] = yt;
+    if (first) {
+      Y[w0 + i] = y;
+      YT[w0 + i] = yt;
+    } else {
+      Y[w0 + i] += y;
+      YT[w0 + i] += yt;
+    }
+    L.acc[i] = 0ull;
+    if constexpr (!Credit<T>::kPacked) L.cnt[i] = 0;
   }
 }
 
-// One node u per wavefront (short up(u)); WPB wavefronts per workgroup, each
-// with its own LDS state.
+template <typename T, int SLOTS, int MAXM, int MAXS>
+__device__ __forceinline__ void tri_clear_credits(TriLds<T, SLOTS, MAXM, MAXS> &L, int tid,
+                                                  int nt) {
+  for (int i = tid; i < MAXM; i += nt) {
+    L.acc[i] = 0ull;
+    if constexpr (!Credit<T>::kPacked) L.cnt[i] = 0;
+  }
+  for (int i = tid; i < MAXS; i += nt) {
+    L.sacc[i] = 0ull;
+    if constexpr (!Credit<T>::kPacked) L.scnt[i] = 0;
+  }
+}
+
+struct TriArgs {
+  const int32_t *up_ptr, *up_col, *up_deg, *deg, *dn_ptr;
+  const int4 *dn;
+  int64_t nup;
+  long long *Y;
+  int32_t *YT;
+  void *Z;
+  int64_t *ZT;
+};
+
+// One node w per wavefront (|up(w)| <= 64, short walk); WPB wavefronts per
+// workgroup, each with its own LDS state; chunks of 64 segments.
 template <typename T, int SLOTS, int MAXM, int WPB>
-__global__ __launch_bounds__(64 * WPB) void k_tri_wave(
-    const int32_t *__restrict__ up_ptr, const int32_t *__restrict__ up_col,
-    const int32_t *__restrict__ deg, const int32_t *__restrict__ nodes, int64_t count,
-    long long *__restrict__ Y, int32_t *__restrict__ YT, void *__restrict__ Z,
-    int64_t *__restrict__ ZT) {
+__global__ __launch_bounds__(64 * WPB) void k_tri_wave(TriArgs A, const int32_t *__restrict__ nodes,
+                                                        int64_t count) {
   using S = SumT<T>;
   using Acc = typename S::type;
-  __shared__ TriLds<T, SLOTS, MAXM> lds[WPB];
+  constexpr int MAXS = 64;
+  __shared__ TriLds<T, SLOTS, MAXM, MAXS> lds[WPB];
   __shared__ int32_t flg_s[WPB][kFlg];
   __shared__ int2 hq_s[WPB][kQueue];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  TriLds<T, SLOTS, MAXM> &L = lds[wv];
+  TriLds<T, SLOTS, MAXM, MAXS> &L = lds[wv];
   int32_t *flg = flg_s[wv];
   flg[lane] = 0;
   const int64_t nwaves = (int64_t)gridDim.x * WPB;
   // the hash is cleared once; afterwards each lane empties the one slot it
-  // filled (|up(u)| <= 64), so a short list does not pay for the whole table
-  static_assert(MAXM <= 64, "one up(u) entry per lane");
+  // filled (|up(w)| <= 64), so a short list does not pay for the whole table
+  static_assert(MAXM <= 64, "one up(w) entry per lane");
   for (int i = lane; i < SLOTS; i += 64) L.hkey[i] = -1;
+  tri_clear_credits(L, lane, 64);
   for (int64_t it = (int64_t)blockIdx.x * WPB + wv; it < count; it += nwaves) {
-    const int32_t u = nodes[it];
-    const int32_t u0 = up_ptr[u], m = up_ptr[u + 1] - u0, ku = deg[u];
-    tri_clear_acc(L, m, lane, 64);
+    const int32_t w = nodes[it];
+    const int32_t w0 = A.up_ptr[w], m = A.up_ptr[w + 1] - w0, kw = A.deg[w];
+    const int32_t d0 = A.dn_ptr[w], nd = A.dn_ptr[w + 1] - d0;
     wave_sync();
-    int32_t nseg, total, myslot = -1;
-    tri_setup<SLOTS, 64>(up_ptr, up_col, deg, u0, m, lane, L.hkey, L.hval, L.seg, L.segp, nullptr,
-                         nseg, total, myslot);
-    wave_sync();
-    Acc accu = Acc();
-    int64_t cntu = 0;
-    tri_walk<T, SLOTS, MAXM>(up_col, L, flg, hq_s[wv], nseg, 0, total, ku, accu, cntu);
-    accu = wave_sum(accu);
-    cntu = wave_sum_i64(cntu);
-    if (lane == 0) {
-      S::store(accu, Z, u);
-      ZT[u] = cntu;
+    const int32_t myslot = tri_hash<SLOTS, 64>(A.up_col, A.up_deg, w0, m, lane, L.hkey, L.hval);
+    Acc accw = Acc();
+    int64_t cntw = 0;
+    for (int32_t c0 = 0; c0 < nd; c0 += MAXS) {
+      const int32_t cnt = nd - c0 < MAXS ? nd - c0 : MAXS;
+      const int32_t total = tri_segs<64>(A.dn, d0 + c0, cnt, lane, L, nullptr);
+      wave_sync();
+      tri_walk<T, SLOTS, MAXM, MAXS>(A.up_col, L, flg, hq_s[wv], cnt, 0, total, kw, accw, cntw);
+      tri_flush(L, cnt, w0, m, c0 == 0, lane, 64, A.nup, A.Y, A.YT);
     }
-    tri_store(L, u0, m, lane, 64, Y, YT);
+    accw = wave_sum(accw);
+    cntw = wave_sum_i64(cntw);
+    if (lane == 0) {
+      S::store(accw, A.Z, w);
+      A.ZT[w] = cntw;
+    }
     if (myslot >= 0) L.hkey[myslot] = -1;
-    wave_sync();
   }
 }
 
-// One node u per workgroup of WPB wavefronts sharing one LDS state; each
-// wavefront walks a contiguous share of the sequence.
+// One node w per workgroup of WPB wavefronts sharing one LDS state; chunks
+// of NT segments, each wavefront walking a contiguous share of a chunk.
 template <typename T, int SLOTS, int MAXM, int WPB>
-__global__ __launch_bounds__(64 * WPB) void k_tri_block(
-    const int32_t *__restrict__ up_ptr, const int32_t *__restrict__ up_col,
-    const int32_t *__restrict__ deg, const int32_t *__restrict__ nodes, int64_t count,
-    long long *__restrict__ Y, int32_t *__restrict__ YT, void *__restrict__ Z,
-    int64_t *__restrict__ ZT) {
+__global__ __launch_bounds__(64 * WPB) void k_tri_block(TriArgs A,
+                                                         const int32_t *__restrict__ nodes,
+                                                         int64_t count) {
   using S = SumT<T>;
   using Acc = typename S::type;
   constexpr int NT = 64 * WPB;
-  __shared__ TriLds<T, SLOTS, MAXM> L;
+  constexpr int MAXS = NT;
+  __shared__ TriLds<T, SLOTS, MAXM, MAXS> L;
   __shared__ int32_t flg_s[WPB][kFlg];
   __shared__ int2 hq_s[WPB][kQueue];
-  __shared__ int32_t part[2 * WPB];
+  __shared__ int32_t part[WPB];
   __shared__ Acc sh_acc[WPB];
   __shared__ int64_t sh_cnt[WPB];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   int32_t *flg = flg_s[wv];
   flg[lane] = 0;
+  tri_clear_credits(L, tid, NT);
   for (int64_t it = blockIdx.x; it < count; it += gridDim.x) {
-    const int32_t u = nodes[it];
-    const int32_t u0 = up_ptr[u], m = up_ptr[u + 1] - u0, ku = deg[u];
-    tri_clear(L, m, tid, NT);
+    const int32_t w = nodes[it];
+    const int32_t w0 = A.up_ptr[w], m = A.up_ptr[w + 1] - w0, kw = A.deg[w];
+    const int32_t d0 = A.dn_ptr[w], nd = A.dn_ptr[w + 1] - d0;
+    for (int i = tid; i < SLOTS; i += NT) L.hkey[i] = -1;
     __syncthreads();
-    int32_t nseg, total;
-    int32_t myslot;
-    tri_setup<SLOTS, NT>(up_ptr, up_col, deg, u0, m, tid, L.hkey, L.hval, L.seg, L.segp, part, nseg,
-                         total, myslot);
-    __syncthreads();
-    // contiguous shares, multiples of 64 entries
-    const int32_t steps = (total + 63) >> 6;
-    const int32_t beg = (int32_t)(((int64_t)steps * wv / WPB) << 6);
-    const int32_t fin = (int32_t)(((int64_t)steps * (wv + 1) / WPB) << 6);
-    Acc accu = Acc();
-    int64_t cntu = 0;
-    tri_walk<T, SLOTS, MAXM>(up_col, L, flg, hq_s[wv], nseg, beg, fin < total ? fin : total, ku,
-                             accu, cntu);
-    accu = wave_sum(accu);
-    cntu = wave_sum_i64(cntu);
+    tri_hash<SLOTS, NT>(A.up_col, A.up_deg, w0, m, tid, L.hkey, L.hval);
+    Acc accw = Acc();
+    int64_t cntw = 0;
+    for (int32_t c0 = 0; c0 < nd; c0 += MAXS) {
+      const int32_t cnt = nd - c0 < MAXS ? nd - c0 : MAXS;
+      const int32_t total = tri_segs<NT>(A.dn, d0 + c0, cnt, tid, L, part);
+      __syncthreads();
+      // contiguous shares, multiples of 64 entries
+      const int32_t steps = (total + 63) >> 6;
+      const int32_t beg = (int32_t)(((int64_t)steps * wv / WPB) << 6);
+      const int32_t fin = (int32_t)(((int64_t)steps * (wv + 1) / WPB) << 6);
+      tri_walk<T, SLOTS, MAXM, MAXS>(A.up_col, L, flg, hq_s[wv], cnt, beg,
+                                     fin < total ? fin : total, kw, accw, cntw);
+      __syncthreads();
+      tri_flush(L, cnt, w0, m, c0 == 0, tid, NT, A.nup, A.Y, A.YT);
+      __syncthreads();
+    }
+    accw = wave_sum(accw);
+    cntw = wave_sum_i64(cntw);
     if (lane == 0) {
-      sh_acc[wv] = accu;
-      sh_cnt[wv] = cntu;
+      sh_acc[wv] = accw;
+      sh_cnt[wv] = cntw;
     }
     __syncthreads();
     if (tid == 0) {
       Acc a = sh_acc[0];
       int64_t cs = sh_cnt[0];
-      for (int w = 1; w < WPB; ++w) {
-        acc_merge(a, sh_acc[w]);
-        cs += sh_cnt[w];
+      for (int i = 1; i < WPB; ++i) {
+        acc_merge(a, sh_acc[i]);
+        cs += sh_cnt[i];
       }
-      S::store(a, Z, u);
-      ZT[u] = cs;
+      S::store(a, A.Z, w);
+      A.ZT[w] = cs;
     }
-    tri_store(L, u0, m, tid, NT, Y, YT);
-    __syncthreads();
   }
 }
 
-// |up(u)| too long for LDS: membership by binary search in global memory;
-// credits go straight to the up-arc slots of u with integer atomics
-// (exact, so still order-independent).
+// |up(w)| too long for LDS: one wavefront per w, one segment per lane, and
+// membership by binary search of up(w) (rank order) in global memory.
+// Credits to x go to w's upper-end slots with integer atomics (exact, so
+// still order-independent; the slots are cleared first), credits to u to the
+// lane's own lower-end slot.
 template <typename T>
-__global__ __launch_bounds__(64) void k_tri_long(const int32_t *__restrict__ up_ptr,
-                                                 const int32_t *__restrict__ up_col,
-                                                 const int32_t *__restrict__ deg,
-                                                 const int32_t *__restrict__ nodes,
-                                                 int64_t count, long long *__restrict__ Y,
-                                                 int32_t *__restrict__ YT,
-                                                 void *__restrict__ Z,
-                                                 int64_t *__restrict__ ZT) {
+__global__ __launch_bounds__(64) void k_tri_long(TriArgs A, const int32_t *__restrict__ nodes,
+                                                 int64_t count) {
   using S = SumT<T>;
   using Acc = typename S::type;
   const int lane = threadIdx.x;
   for (int64_t it = blockIdx.x; it < count; it += gridDim.x) {
-    const int32_t u = nodes[it];
-    const int32_t u0 = up_ptr[u], m = up_ptr[u + 1] - u0, ku = deg[u];
-    Acc accu = Acc();
-    int64_t cntu = 0;
-    for (int base = 0; base < m; base += 64) {
-      const int i = base + lane;
-      int32_t kw = 0, w0 = 0, wl = 0;
-      if (i < m) {
-        const int32_t w = up_col[u0 + i];
-        kw = deg[w];
-        w0 = up_ptr[w];
-        wl = up_ptr[w + 1] - w0;
-      }
-      long long accw = 0;
-      int32_t cntw = 0;
-      for (int32_t j = 0; j < wl; ++j) {
-        const int32_t x = up_col[w0 + j];
-        int32_t lo = 0, hi = m;
+    const int32_t w = nodes[it];
+    const int32_t w0 = A.up_ptr[w], m = A.up_ptr[w + 1] - w0, kw = A.deg[w];
+    const int32_t d0 = A.dn_ptr[w], nd = A.dn_ptr[w + 1] - d0;
+    Acc accw = Acc();
+    int64_t cntw = 0;
+    for (int32_t base = 0; base < nd; base += 64) {
+      const int32_t i = base + lane;
+      if (i >= nd) continue;
+      const int4 sgm = A.dn[d0 + i];  // {slot of {u, w}, tail length, k_u, u}
+      long long accu = 0;
+      int32_t cntu = 0;
+      for (int32_t j = sgm.x + 1; j <= sgm.x + sgm.y; ++j) {
+        const int32_t x = A.up_col[j], kx = A.up_deg[j];
+        int32_t lo = 0, hi = m;  // first member of up(w) not ranked below x
         while (lo < hi) {
           const int32_t mid = (lo + hi) >> 1;
-          if (up_col[u0 + mid] < x) lo = mid + 1; else hi = mid;
+          const int32_t y = A.up_col[w0 + mid], ky = A.up_deg[w0 + mid];
+          if (ky < kx || (ky == kx && y < x)) lo = mid + 1; else hi = mid;
         }
-        if (lo < m && up_col[u0 + lo] == x) {
-          const T dl = tri_delta<T>(ku + kw + deg[x]);
+        if (lo < m && A.up_col[w0 + lo] == x) {
+          const T dl = tri_delta<T>(kw + sgm.z + kx);
           const long long f = to_fix(dl);
-          S::add_term(accu, dl);
-          ++cntu;
-          accw += f;
+          S::add_term(accw, dl);
           ++cntw;
-          atomicAdd((unsigned long long *)&Y[u0 + lo], (unsigned long long)f);
-          atomicAdd(&YT[u0 + lo], 1);
+          accu += f;
+          ++cntu;
+          atomicAdd((unsigned long long *)&A.Y[w0 + lo], (unsigned long long)f);
+          atomicAdd(&A.YT[w0 + lo], 1);
         }
       }
-      if (cntw) {
-        atomicAdd((unsigned long long *)&Y[u0 + i], (unsigned long long)accw);
-        atomicAdd(&YT[u0 + i], cntw);
-      }
+      A.Y[A.nup + sgm.x] = accu;
+      A.YT[A.nup + sgm.x] = cntu;
     }
-    accu = wave_sum(accu);
-    cntu = wave_sum_i64(cntu);
+    accw = wave_sum(accw);
+    cntw = wave_sum_i64(cntw);
     if (lane == 0) {
-      S::store(accu, Z, u);
-      ZT[u] = cntu;
+      S::store(accw, A.Z, w);
+      A.ZT[w] = cntw;
     }
   }
 }
 
-// zero the outputs of nodes that list no triangle (|up(u)| <= 1) and the
-// slots of the long-list nodes (they accumulate with atomics)
+// Clear what no walk writes: Z and ZT of nodes without segments, and the
+// listed slots (upper-end slots of nodes without segments or with long
+// lists, lower-end slots of edges that are no segment).
 template <typename T>
-__global__ void k_tri_zero(const int32_t *__restrict__ up_ptr, int32_t n, long long *__restrict__ Y,
-                           int32_t *__restrict__ YT, void *__restrict__ Z,
-                           int64_t *__restrict__ ZT, int32_t long_min) {
+__global__ void k_tri_zero(TriArgs A, int32_t n, const int32_t *__restrict__ zl, int64_t nz) {
   using S = SumT<T>;
-  for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n;
-       u += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t m = up_ptr[u + 1] - up_ptr[u];
-    if (m <= 1) {
-      S::store(typename S::type(), Z, u);
-      ZT[u] = 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += stride)
+    if (A.dn_ptr[v + 1] == A.dn_ptr[v]) {
+      S::store(typename S::type(), A.Z, v);
+      A.ZT[v] = 0;
     }
-    if (m == 1 || m >= long_min) {
-      for (int32_t s = up_ptr[u]; s < up_ptr[u + 1]; ++s) {
-        Y[s] = 0;
-        YT[s] = 0;
-      }
-    }
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nz; i += stride) {
+    const int32_t sl = zl[i];
+    A.Y[sl] = 0;
+    A.YT[sl] = 0;
   }
 }
 
@@ -471,42 +461,40 @@ static unsigned cap_blocks(int64_t b, int64_t cap) {
   return (unsigned)(b < cap ? b : cap);
 }
 
-// node lists by |up(u)|: small (2..64), mid (65..512), large (513..2048),
-// long (> 2048).
+// node lists: see kTriBin* (wavefront, 8-wavefront and 16-wavefront
+// workgroups, long lists)
 template <typename T>
-static hipError_t tri_impl(const Graph &g, const int32_t *const *lists, const int64_t *counts,
-                           long long *Y, int32_t *YT, void *Z, int64_t *ZT, hipStream_t st) {
-  hipLaunchKernelGGL(k_tri_zero<T>, dim3(cap_blocks((g.n + 255) / 256, 1 << 16)), dim3(256), 0,
-                     st, g.up_ptr, g.n, Y, YT, Z, ZT, kTriLongMin);
+static hipError_t tri_impl(const Graph &g, long long *Y, int32_t *YT, void *Z, int64_t *ZT,
+                           hipStream_t st) {
+  const TriArgs A{g.up_ptr, g.up_col, g.up_deg, g.deg, g.dn_ptr, g.dn, g.nnz / 2, Y, YT, Z, ZT};
+  const int64_t zw = std::max<int64_t>(g.n, g.n_tri_zero);
+  hipLaunchKernelGGL(k_tri_zero<T>, dim3(cap_blocks((zw + 255) / 256, 1 << 16)), dim3(256), 0, st,
+                     A, g.n, g.tri_zero, g.n_tri_zero);
+  const int64_t *counts = g.n_tri;
   if (counts[0] > 0)
     hipLaunchKernelGGL((k_tri_wave<T, 256, 64, 4>), dim3(cap_blocks((counts[0] + 3) / 4, 1 << 20)),
-                       dim3(256), 0, st, g.up_ptr, g.up_col, g.deg, lists[0], counts[0], Y, YT,
-                       Z, ZT);
+                       dim3(256), 0, st, A, g.tri_list[0], counts[0]);
   if (counts[1] > 0)
     hipLaunchKernelGGL((k_tri_block<T, 2048, 512, 8>), dim3(cap_blocks(counts[1], 1 << 20)),
-                       dim3(512), 0, st, g.up_ptr, g.up_col, g.deg, lists[1], counts[1], Y, YT,
-                       Z, ZT);
+                       dim3(512), 0, st, A, g.tri_list[1], counts[1]);
   if (counts[2] > 0)
     hipLaunchKernelGGL((k_tri_block<T, 8192, 2048, 16>), dim3(cap_blocks(counts[2], 1 << 20)),
-                       dim3(1024), 0, st, g.up_ptr, g.up_col, g.deg, lists[2], counts[2], Y, YT,
-                       Z, ZT);
+                       dim3(1024), 0, st, A, g.tri_list[2], counts[2]);
   if (counts[3] > 0)
-    hipLaunchKernelGGL(k_tri_long<T>, dim3(cap_blocks(counts[3], 1 << 20)), dim3(64), 0, st,
-                       g.up_ptr, g.up_col, g.deg, lists[3], counts[3], Y, YT, Z, ZT);
+    hipLaunchKernelGGL(k_tri_long<T>, dim3(cap_blocks(counts[3], 1 << 20)), dim3(64), 0, st, A,
+                       g.tri_list[3], counts[3]);
   return hipGetLastError();
 }
 
 hipError_t launch_triangles_count(const Graph &g, long long *Y, int32_t *YT, int64_t *ZT,
                                   hipStream_t st) {
-  const int32_t *lists[4] = {g.tri_list[0], g.tri_list[1], g.tri_list[2], g.tri_list[3]};
-  return tri_impl<TriCount>(g, lists, g.n_tri, Y, YT, nullptr, ZT, st);
+  return tri_impl<TriCount>(g, Y, YT, nullptr, ZT, st);
 }
 
 hipError_t launch_triangles(const Graph &g, ef_prec prec, long long *Y, int32_t *YT, void *Z,
                             int64_t *ZT, hipStream_t st) {
-  const int32_t *lists[4] = {g.tri_list[0], g.tri_list[1], g.tri_list[2], g.tri_list[3]};
-  if (prec == EF_PREC_FP64) return tri_impl<double>(g, lists, g.n_tri, Y, YT, Z, ZT, st);
-  return tri_impl<float>(g, lists, g.n_tri, Y, YT, Z, ZT, st);
+  if (prec == EF_PREC_FP64) return tri_impl<double>(g, Y, YT, Z, ZT, st);
+  return tri_impl<float>(g, Y, YT, Z, ZT, st);
 }
 
 }  // namespace efi

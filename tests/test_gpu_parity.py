@@ -204,10 +204,51 @@ def test_edge_cases():
         with pytest.raises(efgpu.EFError) as ei:
             g.compute(seeds=[0, 1000])
         assert ei.value.name == "EF_ERR_RANGE"
-    # malformed input is rejected on load
+    # malformed input is rejected on load, also without the host validation
+    # (the up-arc count of an asymmetric CSR is checked before it is used)
+    for validate in (True, False):
+        with pytest.raises(efgpu.EFError) as ei:
+            efgpu.Graph(np.array([0, 1, 1], np.int32), np.array([1], np.int32), validate=validate)
+        assert ei.value.name == "EF_ERR_NOT_SYMMETRIC"
     with pytest.raises(efgpu.EFError) as ei:
-        efgpu.Graph(np.array([0, 1, 1], np.int32), np.array([1], np.int32))
+        efgpu.Graph(np.array([0, 2, 2, 2], np.int32), np.array([1, 2], np.int32), validate=False)
     assert ei.value.name == "EF_ERR_NOT_SYMMETRIC"
+
+
+def dense_core_graph():
+    """A core of 2300 nodes with edge probability 0.97 on a sparse periphery of
+    3000 nodes: the lowest-ranked core nodes have more than 2048 members of
+    higher rank (triangles listed from global memory), the rest of the core
+    513..2048 (16-wavefront workgroups, several segment chunks)."""
+    rs = np.random.default_rng(5)
+    nc, n = 2300, 5300
+    iu = np.triu_indices(nc, 1)
+    keep = rs.random(iu[0].size) < 0.97
+    src = [iu[0][keep].astype(np.int32)]
+    dst = [iu[1][keep].astype(np.int32)]
+    e = rs.integers(0, n, size=(12000, 2)).astype(np.int32)
+    src.append(e[:, 0])
+    dst.append(e[:, 1])
+    return gen.from_edges(n, np.concatenate(src), np.concatenate(dst))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_dense_core_long_lists(prec):
+    rp, ci = dense_core_graph()
+    n = rp.size - 1
+    deg = np.diff(rp).astype(np.int64)
+    ef, D, N = run_all(rp, ci, "cluster", prec)
+    src = np.repeat(np.arange(n), deg)
+    A = np.bincount(src, weights=deg[ci], minlength=n).astype(np.int64)
+    assert np.array_equal(N, deg * deg - 2 * deg + A)
+    rng = np.random.default_rng(3)
+    core = np.argsort(deg)[::-1][:2300]
+    seeds = np.unique(np.concatenate([np.sort(core)[:12], rng.choice(core, 12, replace=False),
+                                      rng.choice(np.arange(2300, n), 12, replace=False)]))
+    seeds = seeds.astype(np.int32)
+    oN, oD, oE = oracle.ef(rp, ci, seeds=seeds, threads=16)
+    worst = assert_parity(ef[seeds], D[seeds], N[seeds], oN, oD, oE, prec, "dense core")
+    sys.stderr.write(f"[parity] dense core {prec} {seeds.size} seeds max rel err {worst:.3e}\n")
 
 
 @pytest.mark.parametrize("algo,prec", [("cluster", "fp32c"), ("cluster", "fp64"),
