@@ -213,7 +213,7 @@ ef_status ef_graph_free(ef_graph *h) {
     (void)hipFree(g.row_ptr);
     (void)hipFree(g.col_idx);
   }
-  void *arrays[] = {g.deg, g.src, g.rev, g.adj2, g.asum, g.up_ptr, g.up_col, g.tslot,
+  void *arrays[] = {g.deg, g.src, g.rev, g.adj2, g.asum, g.qa, g.up_ptr, g.up_col, g.tslot,
                     g.up_deg, g.dn_ptr, g.dn, g.tri_zero,
                     g.tri_list[0], g.tri_list[1], g.tri_list[2], g.tri_list[3], g.fin_list,
                     g.ps_list[0], g.ps_list[1], g.ps_list[2], g.ps_list[3], g.ps_list[4],
@@ -324,6 +324,7 @@ ef_status ef_graph_load_csr(int32_t n, int64_t nnz, const int32_t *row_ptr,
   ALLOC(g.rev, sizeof(int32_t) * NNZ, "rev");
   ALLOC(g.adj2, sizeof(int2) * NNZ, "adj2");
   ALLOC(g.asum, sizeof(int64_t) * std::max<size_t>(n, 1), "asum");
+  ALLOC(g.qa, sizeof(longlong2) * std::max<size_t>(n, 1), "qa");
   ALLOC(g.up_ptr, sizeof(int32_t) * N1, "up_ptr");
   ALLOC(g.up_col, sizeof(int32_t) * NUP, "up_col");
   ALLOC(g.up_deg, sizeof(int32_t) * NUP, "up_deg");
@@ -536,7 +537,7 @@ namespace efi {
 
 // workspace slots
 enum {
-  WS_R = 0, WS_REC, WS_Y, WS_YT, WS_Z, WS_ZT, WS_YACC, WS_FLAG, WS_BINS, WS_OUT, WS_BITMAP,
+  WS_R = 0, WS_REC, WS_Y, WS_Z, WS_ZT, WS_FLAG, WS_BINS, WS_OUT, WS_BITMAP,
   WS_SEEDS, WS_UOUT, WS_TOPK, WS_SURR
 };
 
@@ -826,20 +827,18 @@ extern "C" ef_status ef_compute(ef_graph *h, ef_algo algo, ef_prec prec, const i
   if (e != hipSuccess) return hip_status(e, "pair loop");
   prof.mark(5);
   if (!per_seed) {
-    if ((s = ws_ensure(g, WS_Y, sizeof(long long) * 2 * (size_t)nup, "triangle slots")) != EF_OK)
-      return s;
-    if ((s = ws_ensure(g, WS_YT, sizeof(int32_t) * 2 * (size_t)nup, "triangle counts")) != EF_OK)
+    if ((s = ws_ensure(g, WS_Y, sizeof(TriSlot) * 2 * (size_t)nup, "triangle slots")) != EF_OK)
       return s;
     if ((s = ws_ensure(g, WS_Z, tsz * (size_t)std::max(g.n, 1), "triangle node sums")) != EF_OK) return s;
     if ((s = ws_ensure(g, WS_ZT, sizeof(int64_t) * (size_t)std::max(g.n, 1), "triangle node counts")) != EF_OK)
       return s;
-    e = launch_triangles(g, prec, (long long *)g.ws[WS_Y].p, (int32_t *)g.ws[WS_YT].p,
-                         g.ws[WS_Z].p, (int64_t *)g.ws[WS_ZT].p, st);
+    e = launch_triangles(g, prec, (TriSlot *)g.ws[WS_Y].p, g.ws[WS_Z].p,
+                         (int64_t *)g.ws[WS_ZT].p, st);
     if (e != hipSuccess) return hip_status(e, "triangle pass");
     prof.mark(6);
-    e = launch_finalize_cluster(g, prec, g.ws[WS_R].p, (const long long *)g.ws[WS_Y].p,
-                                (int32_t *)g.ws[WS_YT].p, g.ws[WS_Z].p, (int64_t *)g.ws[WS_ZT].p,
-                                ef_w, D_w, N_w, flag_bytes, st);
+    e = launch_finalize_cluster(g, prec, g.ws[WS_R].p, (const TriSlot *)g.ws[WS_Y].p,
+                                g.ws[WS_Z].p, (int64_t *)g.ws[WS_ZT].p, ef_w, D_w, N_w,
+                                flag_bytes, st);
     if (e == hipSuccess) e = launch_flag_compact(flag_bytes, n_work, flagged, cnt, st);
     if (e != hipSuccess) return hip_status(e, "finalize");
     prof.mark(7);

@@ -97,6 +97,16 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
+// Triangle credits kept with one end of an edge: their sum (64-bit fixed
+// point, 2^-36 units: at most 2^20 credits below 2^6 in magnitude each) and
+// their count, in one 16-byte record.
+struct alignas(16) TriSlot {
+  long long y;
+  int32_t t;
+  int32_t pad;
+};
+constexpr double kTriFix = 68719476736.0;  // 2^36
+
 struct Graph {
   int dev = 0;
   int32_t n = 0;
@@ -110,6 +120,7 @@ struct Graph {
   int32_t *rev = nullptr;      // index of the reverse arc
   int2 *adj2 = nullptr;        // (neighbour id, neighbour degree) per arc
   int64_t *asum = nullptr;     // sum of neighbour degrees per node
+  longlong2 *qa = nullptr;     // per node: {sum of squared neighbour degrees, sum of neighbours' asum}
   int32_t *up_ptr = nullptr;   // degree-oriented half adjacency: u -> {w : rank(w) > rank(u)}
   int32_t *up_col = nullptr;   // each up(u) in rank order
   int32_t *up_deg = nullptr;   // degree of every up_col entry
@@ -215,19 +226,17 @@ hipError_t launch_pairs(const Graph &g, ef_prec prec, const Bins &b, void *R, vo
                         hipStream_t st, hipEvent_t ev_small, hipEvent_t ev_mid,
                         hipEvent_t ev_big, int32_t *agg_done = nullptr);
 
-// triangle pass (cluster-centric): Y (64-bit fixed point, 2^-40 units) and
-// YT per up-arc slot, Z / ZT per node.
-hipError_t launch_triangles(const Graph &g, ef_prec prec, long long *Y, int32_t *YT, void *Z,
-                            int64_t *ZT, hipStream_t st);
-// triangle counts only: YT per up-arc slot, ZT per node (Y is zeroed, no Z)
-hipError_t launch_triangles_count(const Graph &g, long long *Y, int32_t *YT, int64_t *ZT,
-                                  hipStream_t st);
+// triangle pass (cluster-centric): Y, two TriSlots per up arc (upper end at
+// the up-arc slot, lower end at nup + slot), Z / ZT per node.
+hipError_t launch_triangles(const Graph &g, ef_prec prec, TriSlot *Y, void *Z, int64_t *ZT,
+                            hipStream_t st);
+// triangle counts only: the counts of Y (sums zero) and ZT, no Z
+hipError_t launch_triangles_count(const Graph &g, TriSlot *Y, int64_t *ZT, hipStream_t st);
 
 // per-node sums + Eq. 1 (cluster-centric); per-node flag bytes in fl.
-hipError_t launch_finalize_cluster(const Graph &g, ef_prec prec, const void *R,
-                                   const long long *Y, const int32_t *YT, const void *Z,
-                                   const int64_t *ZT, double *ef, int64_t *D, int64_t *N,
-                                   uint8_t *fl, hipStream_t st);
+hipError_t launch_finalize_cluster(const Graph &g, ef_prec prec, const void *R, const TriSlot *Y,
+                                   const void *Z, const int64_t *ZT, double *ef, int64_t *D,
+                                   int64_t *N, uint8_t *fl, hipStream_t st);
 
 // flag bytes of positions 0..n-1 (written by the finalize and per-seed
 // kernels: bit 0 pass 2, bit 1 FP64-finalised) -> flagged list and

@@ -153,20 +153,17 @@ template <int G> __device__ __forceinline__ DFv group_sum(DFv x) {
 }
 
 // arcs first, first + stride, ... of node v: its own row sums R[e], the
-// reverse arcs' R[rev e], exact N and D, and the triangle credits to v kept
-// with each of its edges (the upper-end slot of an edge to a lower-ranked
-// neighbour, the lower-end slot nup + slot otherwise)
+// reverse arcs' R[rev e], and the triangle credits to v kept with each of its
+// edges (the upper-end record of an edge to a lower-ranked neighbour, the
+// lower-end record nup + slot otherwise)
 template <typename T>
 __device__ __forceinline__ void fin_arcs(const int2 *__restrict__ adj2,
                                          const int32_t *__restrict__ rev,
-                                         const int32_t *__restrict__ tslot,
-                                         const int64_t *__restrict__ asum, const void *R,
-                                         const long long *__restrict__ Y,
-                                         const int32_t *__restrict__ YT, int64_t nup, int32_t v,
-                                         int32_t k,
-                                         int32_t base, int64_t As, int32_t first, int32_t stride,
-                                         typename SumT<T>::type &sacc, double &tfix, int64_t &Nn,
-                                         int64_t &Dd, int64_t &Tc) {
+                                         const int32_t *__restrict__ tslot, const void *R,
+                                         const TriSlot *__restrict__ Y, int64_t nup, int32_t v,
+                                         int32_t k, int32_t base, int32_t first, int32_t stride,
+                                         typename SumT<T>::type &sacc, double &tfix,
+                                         int64_t &Tc) {
   using S = SumT<T>;
   for (int32_t e = base + first; e < base + k; e += stride) {
     const int2 ad = adj2[e];
@@ -174,18 +171,20 @@ __device__ __forceinline__ void fin_arcs(const int2 *__restrict__ adj2,
     // a centre of degree 1 has no pairs: its row sums were never written
     if (k >= 2) S::add_stored(sacc, R, e);
     if (ka >= 2) S::add_stored(sacc, R, rev[e]);
-    Nn += (int64_t)(k - 1) + (ka - 1);
-    Dd += (int64_t)(k - 1) * (k + ka - 4) + (As - ka) + (int64_t)(ka - 1) * (ka + k - 4) +
-          (asum[a] - k);
-    const int64_t sl = tslot[e] + (rank_less_d(a, ka, v, k) ? 0 : nup);
-    tfix += (double)Y[sl];  // 2^-40 fixed-point units
-    Tc += YT[sl];
+    const TriSlot r = Y[tslot[e] + (rank_less_d(a, ka, v, k) ? 0 : nup)];
+    tfix += (double)r.y;  // 2^-36 fixed-point units
+    Tc += r.t;
   }
 }
 
+// N and D of v in closed form from k, As = sum k_a, Q = sum k_a^2 and
+// A2 = sum asum[a] over the neighbours a (summing the per-arc identities
+// N_e = (k-1) + (k_a-1) and
+// D_e = (k-1)(k+k_a-4) + (As-k_a) + (k_a-1)(k_a+k-4) + (asum[a]-k)),
+// less 8 per triangle.
 template <typename T>
-__device__ __forceinline__ void fin_store(int32_t v, typename SumT<T>::type sacc, double tfix,
-                                          int64_t Nn, int64_t Dd, int64_t Tc,
+__device__ __forceinline__ void fin_store(int32_t v, int32_t k, int64_t As, longlong2 qa,
+                                          typename SumT<T>::type sacc, double tfix, int64_t Tc,
                                           const void *Z, const int64_t *__restrict__ ZT,
                                           double *ef, int64_t *Dout, int64_t *Nout,
                                           uint8_t *fl) {
@@ -193,9 +192,11 @@ __device__ __forceinline__ void fin_store(int32_t v, typename SumT<T>::type sacc
   typename S::type z = typename S::type();
   S::add_stored(z, Z, v);
   Tc += ZT[v];
-  const double tri = tfix * (1.0 / 1099511627776.0) + S::value(z);
+  const double tri = tfix * (1.0 / kTriFix) + S::value(z);
   const double Stot = S::value(sacc) + 4.0 * tri;
-  Dd -= 8 * Tc;
+  const int64_t kk = k;
+  const int64_t Nn = kk * kk - 2 * kk + As;
+  const int64_t Dd = kk * (kk - 4) * (kk - 2) + (3 * kk - 7) * As + qa.x + qa.y - kk * kk - 8 * Tc;
   ef[v] = finish_ef<T>(Nn, Dd, Stot, v, fl);
   Dout[v] = Dd;
   Nout[v] = Nn;
@@ -206,9 +207,9 @@ struct FinArgs {
   const int2 *adj2;
   const int32_t *rev, *tslot;
   const int64_t *asum;
+  const longlong2 *qa;
   const void *R;
-  const long long *Y;
-  const int32_t *YT;
+  const TriSlot *Y;
   int64_t nup;
   const void *Z;
   const int64_t *ZT;
@@ -239,16 +240,15 @@ __device__ __forceinline__ void fin_groups(const FinArgs &A, const int32_t *node
     if (v < 0) k = 0;
     Acc sacc = Acc();
     double tfix = 0.0;
-    int64_t Nn = 0, Dd = 0, Tc = 0;
+    int64_t Tc = 0;
     if (v >= 0)
-      fin_arcs<T>(A.adj2, A.rev, A.tslot, A.asum, A.R, A.Y, A.YT, A.nup, v, k, A.row_ptr[v], A.asum[v],
-                  sub, G, sacc, tfix, Nn, Dd, Tc);
+      fin_arcs<T>(A.adj2, A.rev, A.tslot, A.R, A.Y, A.nup, v, k, A.row_ptr[v], sub, G, sacc, tfix,
+                  Tc);
     sacc = group_sum<G>(sacc);
     tfix = group_sum<G>(tfix);
-    Nn = group_sum<G>(Nn);
-    Dd = group_sum<G>(Dd);
     Tc = group_sum<G>(Tc);
-    if (v >= 0 && sub == 0) fin_store<T>(v, sacc, tfix, Nn, Dd, Tc, A.Z, A.ZT, A.ef, A.D, A.N, A.fl);
+    if (v >= 0 && sub == 0)
+      fin_store<T>(v, k, A.asum[v], A.qa[v], sacc, tfix, Tc, A.Z, A.ZT, A.ef, A.D, A.N, A.fl);
   }
 }
 
@@ -259,26 +259,22 @@ __device__ __forceinline__ void fin_hubs(const FinArgs &A, const int32_t *nodes,
   using Acc = typename SumT<T>::type;
   __shared__ Acc shS[4];
   __shared__ double shT[4];
-  __shared__ int64_t shN[4], shD[4], shC[4];
+  __shared__ int64_t shC[4];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   for (int64_t it = blk; it < count; it += nblk) {
     const int32_t v = nodes[it];
     const int32_t k = A.deg[v];
     Acc sacc = Acc();
     double tfix = 0.0;
-    int64_t Nn = 0, Dd = 0, Tc = 0;
-    fin_arcs<T>(A.adj2, A.rev, A.tslot, A.asum, A.R, A.Y, A.YT, A.nup, v, k, A.row_ptr[v], A.asum[v],
-                tid, 256, sacc, tfix, Nn, Dd, Tc);
+    int64_t Tc = 0;
+    fin_arcs<T>(A.adj2, A.rev, A.tslot, A.R, A.Y, A.nup, v, k, A.row_ptr[v], tid, 256, sacc, tfix,
+                Tc);
     sacc = wave_sum(sacc);
     tfix = wave_sum_f64(tfix);
-    Nn = wave_sum_i64(Nn);
-    Dd = wave_sum_i64(Dd);
     Tc = wave_sum_i64(Tc);
     if (lane == 0) {
       shS[wv] = sacc;
       shT[wv] = tfix;
-      shN[wv] = Nn;
-      shD[wv] = Dd;
       shC[wv] = Tc;
     }
     __syncthreads();
@@ -286,11 +282,9 @@ __device__ __forceinline__ void fin_hubs(const FinArgs &A, const int32_t *nodes,
       for (int w = 1; w < 4; ++w) {
         acc_merge(sacc, shS[w]);
         tfix += shT[w];
-        Nn += shN[w];
-        Dd += shD[w];
         Tc += shC[w];
       }
-      fin_store<T>(v, sacc, tfix, Nn, Dd, Tc, A.Z, A.ZT, A.ef, A.D, A.N, A.fl);
+      fin_store<T>(v, k, A.asum[v], A.qa[v], sacc, tfix, Tc, A.Z, A.ZT, A.ef, A.D, A.N, A.fl);
     }
     __syncthreads();
   }
@@ -320,10 +314,9 @@ static unsigned cap_blocks(int64_t b, int64_t cap) {
   return (unsigned)(b < cap ? b : cap);
 }
 
-hipError_t launch_finalize_cluster(const Graph &g, ef_prec prec, const void *R,
-                                   const long long *Y, const int32_t *YT, const void *Z,
-                                   const int64_t *ZT, double *ef, int64_t *D, int64_t *N,
-                                   uint8_t *fl, hipStream_t st) {
+hipError_t launch_finalize_cluster(const Graph &g, ef_prec prec, const void *R, const TriSlot *Y,
+                                   const void *Z, const int64_t *ZT, double *ef, int64_t *D,
+                                   int64_t *N, uint8_t *fl, hipStream_t st) {
   // fin_list (degree descending) = [hubs][wavefront tier][32-lane tier]
   const int64_t n_wave = g.n_fin - g.n_fin_hub - g.n_fin_half;
   const int32_t *l_wave = g.fin_list + g.n_fin_hub, *l_half = l_wave + n_wave;
@@ -331,8 +324,8 @@ hipError_t launch_finalize_cluster(const Graph &g, ef_prec prec, const void *R,
   const int64_t bw = n_wave > 0 ? cap_blocks((n_wave * 64 + 255) / 256, 1 << 18) : 0;
   const int64_t bc = g.n_fin_half > 0 ? cap_blocks((g.n_fin_half * 32 + 255) / 256, 1 << 18) : 0;
   const int64_t bs = cap_blocks(((int64_t)g.n * 8 + 255) / 256, 1 << 19);
-  const FinArgs A{g.row_ptr, g.deg, g.adj2, g.rev, g.tslot, g.asum, R,  Y,  YT,
-                  g.nnz / 2,  Z,       ZT,     ef,     D,      N,      fl};
+  const FinArgs A{g.row_ptr, g.deg, g.adj2, g.rev, g.tslot, g.asum, g.qa, R,
+                  Y,         g.nnz / 2, Z, ZT,  ef,      D,      N,      fl};
   const unsigned grid = (unsigned)(bh + bw + bc + bs);
   if (prec == EF_PREC_FP64)
     hipLaunchKernelGGL(k_finalize_cluster<double>, dim3(grid), dim3(256), 0, st, A, g.fin_list,

@@ -13,7 +13,7 @@
 #include "ef_internal.h"
 
 namespace efi {
-hipError_t launch_features(const Graph &g, const int32_t *YT, const int64_t *ZT,
+hipError_t launch_features(const Graph &g, const TriSlot *Y, const int64_t *ZT,
                            const float *mean, const float *inv_std, float *X, float *lnN,
                            hipStream_t st);
 hipError_t launch_mlp_pack(const float *P, __bf16 *pack, hipStream_t st);
@@ -254,7 +254,7 @@ ef_status ef_features(ef_graph *h, float *X, float *lnN, uint32_t flags, void *h
   const size_t nts = 2 * (size_t)std::max<int64_t>(g.nnz / 2, 1);
   // triangle counts per node come from the triangle pass (FP32 deltas unused)
   char *p = nullptr;
-  const size_t need = sizeof(long long) * nts + sizeof(int32_t) * nts + sizeof(float2) * n +
+  const size_t need = sizeof(TriSlot) * nts + sizeof(float2) * n +
                       sizeof(int64_t) * n + (sizeof(float) * kNF + sizeof(float)) * n + 4096;
   ef_status rs = graph_scratch(g, need, (void **)&p);
   if (rs != EF_OK) return rs;
@@ -265,15 +265,14 @@ ef_status ef_features(ef_graph *h, float *X, float *lnN, uint32_t flags, void *h
     return r;
   };
   char *base = p;
-  long long *Y = (long long *)take(sizeof(long long) * nts);
-  int32_t *YT = (int32_t *)take(sizeof(int32_t) * nts);
+  TriSlot *Y = (TriSlot *)take(sizeof(TriSlot) * nts);
   void *Z = take(sizeof(float2) * n);
   int64_t *ZT = (int64_t *)take(sizeof(int64_t) * n);
   const bool dev = (flags & EF_OUT_DEVICE) != 0;
   float *Xd = dev ? X : (float *)take(sizeof(float) * kNF * n);
   float *Ld = (dev && lnN) ? lnN : (float *)take(sizeof(float) * n);
-  e = launch_triangles_count(g, Y, YT, ZT, st);
-  if (e == hipSuccess) e = launch_features(g, YT, ZT, nullptr, nullptr, Xd, Ld, st);
+  e = launch_triangles_count(g, Y, ZT, st);
+  if (e == hipSuccess) e = launch_features(g, Y, ZT, nullptr, nullptr, Xd, Ld, st);
   if (e == hipSuccess && !dev) {
     e = hipMemcpyAsync(X, Xd, sizeof(float) * kNF * n, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess && lnN) e = hipMemcpyAsync(lnN, Ld, sizeof(float) * n, hipMemcpyDeviceToHost, st);
@@ -474,7 +473,7 @@ ef_status ef_surrogate_predict(ef_surrogate *s, ef_graph *h, double *ef_pred, ui
   // triangle slots: an upper-end and a lower-end slot per up arc
   const size_t nts = 2 * (size_t)std::max<int64_t>(g.nnz / 2, 1);
   char *p = nullptr;
-  const size_t need = sizeof(long long) * nts + sizeof(int32_t) * nts + sizeof(float2) * n +
+  const size_t need = sizeof(TriSlot) * nts + sizeof(float2) * n +
                       sizeof(int64_t) * n + (sizeof(float) * kNF + sizeof(float)) * n +
                       sizeof(double) * n + 4096;
   ef_status rs = graph_scratch(g, need, (void **)&p);
@@ -486,16 +485,15 @@ ef_status ef_surrogate_predict(ef_surrogate *s, ef_graph *h, double *ef_pred, ui
     p += (b + 255) & ~(size_t)255;
     return rr;
   };
-  long long *Y = (long long *)take(sizeof(long long) * nts);
-  int32_t *YT = (int32_t *)take(sizeof(int32_t) * nts);
+  TriSlot *Y = (TriSlot *)take(sizeof(TriSlot) * nts);
   void *Z = take(sizeof(float2) * n);
   int64_t *ZT = (int64_t *)take(sizeof(int64_t) * n);
   float *Xd = (float *)take(sizeof(float) * kNF * n);
   float *Ld = (float *)take(sizeof(float) * n);
   const bool dev = (flags & EF_OUT_DEVICE) != 0;
   double *Ed = dev ? ef_pred : (double *)take(sizeof(double) * n);
-  e = launch_triangles_count(g, Y, YT, ZT, st);
-  if (e == hipSuccess) e = launch_features(g, YT, ZT, s->dmean, s->dinv, Xd, Ld, st);
+  e = launch_triangles_count(g, Y, ZT, st);
+  if (e == hipSuccess) e = launch_features(g, Y, ZT, s->dmean, s->dinv, Xd, Ld, st);
   if (e == hipSuccess) e = launch_mlp_forward(Xd, (int64_t)n, s->dP, s->dpack, Ld, nullptr, Ed, st);
   if (e == hipSuccess && !dev)
     e = hipMemcpyAsync(ef_pred, Ed, sizeof(double) * n, hipMemcpyDeviceToHost, st);

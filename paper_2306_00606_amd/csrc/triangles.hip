@@ -20,8 +20,8 @@
 // sum_w |up(w)| * |down(w)| for a listing at the lowest node.
 // Credits, per triangle:
 //   w  - lane registers (floating point), reduced at the end  -> Z[w], ZT[w]
-//   x  - LDS add at x's position in up(w)  -> upper-end slot Y[slot of {w, x}]
-//   u  - LDS add at the segment's index    -> lower-end slot Y[nup + slot of {u, w}]
+//   x  - LDS add at x's position in up(w)  -> upper-end record Y[slot of {w, x}]
+//   u  - LDS add at the segment's index    -> lower-end record Y[nup + slot of {u, w}]
 // The LDS credit slots are integers (see Credit), so concurrent adds are exact
 // and order-independent: results are bitwise reproducible. Segments are taken
 // in chunks of at most MAXS; the credits to x are added to their slots after
@@ -30,7 +30,6 @@
 
 namespace efi {
 
-constexpr double kFix = 1099511627776.0;  // 2^40
 constexpr int kPosBits = 12;              // position in up(u) < 4096
 static_assert(kTriBin2 <= (1 << kPosBits), "position field too narrow");
 static_assert(kMaxDegree < (1u << (32 - kPosBits)), "degree field too narrow");
@@ -41,10 +40,10 @@ __device__ __forceinline__ int32_t pack_kp(int32_t k, int32_t pos) {
 __device__ __forceinline__ int32_t unpack_k(int32_t v) { return (int32_t)((uint32_t)v >> kPosBits); }
 
 template <typename T> __device__ __forceinline__ long long to_fix(T v) {
-  return __double2ll_rn((double)v * kFix);
+  return __double2ll_rn((double)v * kTriFix);
 }
 
-// Integer credit slots, 2^-40 units on output.
+// Integer credit slots in LDS, 2^-36 units on output (TriSlot).
 // FP32: delta < 0 is a float with 2 <= |delta| < 2^7 (log2 units, degrees
 //   below kMaxDegree), so its ulp is >= 2^-22 and |delta| * 2^24 is an exact
 //   integer below 2^31. A slot holds one word, count << 44 plus the sum of
@@ -52,7 +51,7 @@ template <typename T> __device__ __forceinline__ long long to_fix(T v) {
 //   (a segment's hits are members of up(w), |up(w)| <= kTriBin2 = 2^11; x
 //   gets at most one credit per segment of a chunk, MAXS <= 2^11), so the
 //   sum stays below 2^42 and one 64-bit add records credit and count.
-// FP64: the credit rounded to 2^-40 in one 64-bit slot, the count in a
+// FP64: the credit rounded to 2^-36 in one 64-bit slot, the count in a
 //   separate 32-bit slot.
 template <typename T> struct Credit;
 template <> struct Credit<float> {
@@ -63,7 +62,7 @@ template <> struct Credit<float> {
   __device__ static void load(const unsigned long long *acc, const int32_t *, int32_t slot,
                               long long &y, int32_t &yt) {
     const unsigned long long w = acc[slot];
-    y = -(long long)((w & ((1ull << 44) - 1)) << 16);
+    y = -(long long)((w & ((1ull << 44) - 1)) << 12);
     yt = (int32_t)(w >> 44);
   }
 };
@@ -224,28 +223,23 @@ __device__ __forceinline__ void tri_walk(const int32_t *__restrict__ up_col,
 template <typename T, int SLOTS, int MAXM, int MAXS>
 __device__ __forceinline__ void tri_flush(TriLds<T, SLOTS, MAXM, MAXS> &L, int32_t cnt, int32_t w0,
                                           int32_t m, bool first, int tid, int nt, int64_t nup,
-                                          long long *Y, int32_t *YT) {
+                                          TriSlot *Y) {
   for (int32_t i = tid; i < cnt; i += nt) {
-    long long y;
-    int32_t yt;
-    Credit<T>::load(L.sacc, L.scnt, i, y, yt);
-    const int64_t sl = nup + L.sslot[i];
-    Y[sl] = y;
-    YT[sl] = yt;
+    TriSlot r{0, 0, 0};
+    Credit<T>::load(L.sacc, L.scnt, i, r.y, r.t);
+    Y[nup + L.sslot[i]] = r;
     L.sacc[i] = 0ull;
     if constexpr (!Credit<T>::kPacked) L.scnt[i] = 0;
   }
   for (int32_t i = tid; i < m; i += nt) {
-    long long y;
-    int32_t yt;
-    Credit<T>::load(L.acc, L.cnt, i, y, yt);
-    if (first) {
-      Y[w0 + i] = y;
-      YT[w0 + i] = yt;
-    } else {
-      Y[w0 + i] += y;
-      YT[w0 + i] += yt;
+    TriSlot r{0, 0, 0};
+    Credit<T>::load(L.acc, L.cnt, i, r.y, r.t);
+    if (!first) {
+      const TriSlot o = Y[w0 + i];
+      r.y += o.y;
+      r.t += o.t;
     }
+    Y[w0 + i] = r;
     L.acc[i] = 0ull;
     if constexpr (!Credit<T>::kPacked) L.cnt[i] = 0;
   }
@@ -268,8 +262,7 @@ struct TriArgs {
   const int32_t *up_ptr, *up_col, *up_deg, *deg, *dn_ptr;
   const int4 *dn;
   int64_t nup;
-  long long *Y;
-  int32_t *YT;
+  TriSlot *Y;
   void *Z;
   int64_t *ZT;
 };
@@ -308,7 +301,7 @@ __global__ __launch_bounds__(64 * WPB) void k_tri_wave(TriArgs A, const int32_t 
       const int32_t total = tri_segs<64>(A.dn, d0 + c0, cnt, lane, L, nullptr);
       wave_sync();
       tri_walk<T, SLOTS, MAXM, MAXS>(A.up_col, L, flg, hq_s[wv], cnt, 0, total, kw, accw, cntw);
-      tri_flush(L, cnt, w0, m, c0 == 0, lane, 64, A.nup, A.Y, A.YT);
+      tri_flush(L, cnt, w0, m, c0 == 0, lane, 64, A.nup, A.Y);
     }
     accw = wave_sum(accw);
     cntw = wave_sum_i64(cntw);
@@ -360,7 +353,7 @@ __global__ __launch_bounds__(64 * WPB) void k_tri_block(TriArgs A,
       tri_walk<T, SLOTS, MAXM, MAXS>(A.up_col, L, flg, hq_s[wv], cnt, beg,
                                      fin < total ? fin : total, kw, accw, cntw);
       __syncthreads();
-      tri_flush(L, cnt, w0, m, c0 == 0, tid, NT, A.nup, A.Y, A.YT);
+      tri_flush(L, cnt, w0, m, c0 == 0, tid, NT, A.nup, A.Y);
       __syncthreads();
     }
     accw = wave_sum(accw);
@@ -421,12 +414,11 @@ __global__ __launch_bounds__(64) void k_tri_long(TriArgs A, const int32_t *__res
           ++cntw;
           accu += f;
           ++cntu;
-          atomicAdd((unsigned long long *)&A.Y[w0 + lo], (unsigned long long)f);
-          atomicAdd(&A.YT[w0 + lo], 1);
+          atomicAdd((unsigned long long *)&A.Y[w0 + lo].y, (unsigned long long)f);
+          atomicAdd(&A.Y[w0 + lo].t, 1);
         }
       }
-      A.Y[A.nup + sgm.x] = accu;
-      A.YT[A.nup + sgm.x] = cntu;
+      A.Y[A.nup + sgm.x] = TriSlot{accu, cntu, 0};
     }
     accw = wave_sum(accw);
     cntw = wave_sum_i64(cntw);
@@ -450,9 +442,7 @@ __global__ void k_tri_zero(TriArgs A, int32_t n, const int32_t *__restrict__ zl,
       A.ZT[v] = 0;
     }
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nz; i += stride) {
-    const int32_t sl = zl[i];
-    A.Y[sl] = 0;
-    A.YT[sl] = 0;
+    A.Y[zl[i]] = TriSlot{0, 0, 0};
   }
 }
 
@@ -464,9 +454,8 @@ static unsigned cap_blocks(int64_t b, int64_t cap) {
 // node lists: see kTriBin* (wavefront, 8-wavefront and 16-wavefront
 // workgroups, long lists)
 template <typename T>
-static hipError_t tri_impl(const Graph &g, long long *Y, int32_t *YT, void *Z, int64_t *ZT,
-                           hipStream_t st) {
-  const TriArgs A{g.up_ptr, g.up_col, g.up_deg, g.deg, g.dn_ptr, g.dn, g.nnz / 2, Y, YT, Z, ZT};
+static hipError_t tri_impl(const Graph &g, TriSlot *Y, void *Z, int64_t *ZT, hipStream_t st) {
+  const TriArgs A{g.up_ptr, g.up_col, g.up_deg, g.deg, g.dn_ptr, g.dn, g.nnz / 2, Y, Z, ZT};
   const int64_t zw = std::max<int64_t>(g.n, g.n_tri_zero);
   hipLaunchKernelGGL(k_tri_zero<T>, dim3(cap_blocks((zw + 255) / 256, 1 << 16)), dim3(256), 0, st,
                      A, g.n, g.tri_zero, g.n_tri_zero);
@@ -486,15 +475,14 @@ static hipError_t tri_impl(const Graph &g, long long *Y, int32_t *YT, void *Z, i
   return hipGetLastError();
 }
 
-hipError_t launch_triangles_count(const Graph &g, long long *Y, int32_t *YT, int64_t *ZT,
-                                  hipStream_t st) {
-  return tri_impl<TriCount>(g, Y, YT, nullptr, ZT, st);
+hipError_t launch_triangles_count(const Graph &g, TriSlot *Y, int64_t *ZT, hipStream_t st) {
+  return tri_impl<TriCount>(g, Y, nullptr, ZT, st);
 }
 
-hipError_t launch_triangles(const Graph &g, ef_prec prec, long long *Y, int32_t *YT, void *Z,
-                            int64_t *ZT, hipStream_t st) {
-  if (prec == EF_PREC_FP64) return tri_impl<double>(g, Y, YT, Z, ZT, st);
-  return tri_impl<float>(g, Y, YT, Z, ZT, st);
+hipError_t launch_triangles(const Graph &g, ef_prec prec, TriSlot *Y, void *Z, int64_t *ZT,
+                            hipStream_t st) {
+  if (prec == EF_PREC_FP64) return tri_impl<double>(g, Y, Z, ZT, st);
+  return tri_impl<float>(g, Y, Z, ZT, st);
 }
 
 }  // namespace efi
