@@ -314,15 +314,16 @@ __global__ __launch_bounds__(64 * WPB) void k_tri_wave(TriArgs A, const int32_t 
 }
 
 // One node w per workgroup of WPB wavefronts sharing one LDS state; chunks
-// of NT segments, each wavefront walking a contiguous share of a chunk.
-template <typename T, int SLOTS, int MAXM, int WPB>
+// of MAXS <= NT segments, each wavefront walking a contiguous share of a
+// chunk.
+template <typename T, int SLOTS, int MAXM, int WPB, int MAXS>
 __global__ __launch_bounds__(64 * WPB) void k_tri_block(TriArgs A,
                                                          const int32_t *__restrict__ nodes,
                                                          int64_t count) {
   using S = SumT<T>;
   using Acc = typename S::type;
   constexpr int NT = 64 * WPB;
-  constexpr int MAXS = NT;
+  static_assert(MAXS <= NT, "one segment per thread in the chunk setup");
   __shared__ TriLds<T, SLOTS, MAXM, MAXS> L;
   __shared__ int32_t flg_s[WPB][kFlg];
   __shared__ int2 hq_s[WPB][kQueue];
@@ -464,11 +465,12 @@ static hipError_t tri_impl(const Graph &g, TriSlot *Y, void *Z, int64_t *ZT, hip
     hipLaunchKernelGGL((k_tri_wave<T, 256, 64, 4>), dim3(cap_blocks((counts[0] + 3) / 4, 1 << 20)),
                        dim3(256), 0, st, A, g.tri_list[0], counts[0]);
   if (counts[1] > 0)
-    hipLaunchKernelGGL((k_tri_block<T, 2048, 512, 8>), dim3(cap_blocks(counts[1], 1 << 20)),
+    hipLaunchKernelGGL((k_tri_block<T, 2048, 512, 8, 512>), dim3(cap_blocks(counts[1], 1 << 20)),
                        dim3(512), 0, st, A, g.tri_list[1], counts[1]);
   if (counts[2] > 0)
-    hipLaunchKernelGGL((k_tri_block<T, 8192, 2048, 16>), dim3(cap_blocks(counts[2], 1 << 20)),
-                       dim3(1024), 0, st, A, g.tri_list[2], counts[2]);
+    hipLaunchKernelGGL((k_tri_block<T, 8192, 2048, 16, 1024>),
+                       dim3(cap_blocks(counts[2], 1 << 20)), dim3(1024), 0, st, A, g.tri_list[2],
+                       counts[2]);
   if (counts[3] > 0)
     hipLaunchKernelGGL(k_tri_long<T>, dim3(cap_blocks(counts[3], 1 << 20)), dim3(64), 0, st, A,
                        g.tri_list[3], counts[3]);
