@@ -213,9 +213,10 @@ ef_status ef_graph_free(ef_graph *h) {
     (void)hipFree(g.row_ptr);
     (void)hipFree(g.col_idx);
   }
-  void *arrays[] = {g.deg, g.src, g.rev, g.adj2, g.asum, g.qa, g.up_ptr, g.up_col, g.tslot,
+  void *arrays[] = {g.deg, g.src, g.rev, g.adj2, g.asum, g.qa, g.up_ptr, g.up_col, g.trec,
                     g.up_deg, g.dn_ptr, g.dn, g.tri_zero,
-                    g.tri_list[0], g.tri_list[1], g.tri_list[2], g.tri_list[3], g.fin_list,
+                    g.tri_rec0, g.tri_list[0], g.tri_list[1], g.tri_list[2], g.tri_list[3],
+                    g.fin_list,
                     g.ps_list[0], g.ps_list[1], g.ps_list[2], g.ps_list[3], g.ps_list[4],
                     g.d_counters};
   for (void *p : arrays)
@@ -328,7 +329,7 @@ ef_status ef_graph_load_csr(int32_t n, int64_t nnz, const int32_t *row_ptr,
   ALLOC(g.up_ptr, sizeof(int32_t) * N1, "up_ptr");
   ALLOC(g.up_col, sizeof(int32_t) * NUP, "up_col");
   ALLOC(g.up_deg, sizeof(int32_t) * NUP, "up_deg");
-  ALLOC(g.tslot, sizeof(int32_t) * NNZ, "tslot");
+  ALLOC(g.trec, sizeof(int32_t) * NNZ, "triangle record index");
   ALLOC(g.dn_ptr, sizeof(int32_t) * N1, "dn_ptr");
   ALLOC(g.dn, sizeof(int4) * NUP, "triangle segments");
   ALLOC(g.d_counters, sizeof(int32_t) * 64, "counters");
@@ -445,8 +446,17 @@ ef_status ef_graph_load_csr(int32_t n, int64_t nnz, const int32_t *row_ptr,
   for (int bin = 0; bin < 4; ++bin) {
     std::sort(tri[bin].begin(), tri[bin].end(), by_work);
     g.n_tri[bin] = (int64_t)tri[bin].size();
-    ALLOC(g.tri_list[bin], sizeof(int32_t) * std::max<size_t>(tri[bin].size(), 1), "triangle list");
+    if (bin > 0)
+      ALLOC(g.tri_list[bin], sizeof(int32_t) * std::max<size_t>(tri[bin].size(), 1),
+            "triangle list");
   }
+  std::vector<int4> rec0(tri[0].size());
+  for (size_t i = 0; i < tri[0].size(); ++i) {
+    const int32_t v = tri[0][i];
+    const int32_t m = h_up_ptr[v + 1] - h_up_ptr[v], nd = h_dn_ptr[v + 1] - h_dn_ptr[v];
+    rec0[i] = make_int4(v, h_up_ptr[v], h_dn_ptr[v], m | (nd << 16));
+  }
+  ALLOC(g.tri_rec0, sizeof(int4) * std::max<size_t>(rec0.size(), 1), "triangle records");
   std::sort(fin.begin(), fin.end(), [&](int32_t a, int32_t b) {
     return g.h_deg[a] != g.h_deg[b] ? g.h_deg[a] > g.h_deg[b] : a < b;
   });
@@ -457,10 +467,12 @@ ef_status ef_graph_load_csr(int32_t n, int64_t nnz, const int32_t *row_ptr,
   ALLOC(g.fin_list, sizeof(int32_t) * std::max<size_t>(fin.size(), 1), "finalize list");
 #undef ALLOC
   hipError_t e = hipSuccess;
-  for (int bin = 0; bin < 4 && e == hipSuccess; ++bin)
+  for (int bin = 1; bin < 4 && e == hipSuccess; ++bin)
     if (!tri[bin].empty())
       e = hipMemcpy(g.tri_list[bin], tri[bin].data(), sizeof(int32_t) * tri[bin].size(),
                     hipMemcpyHostToDevice);
+  if (e == hipSuccess && !rec0.empty())
+    e = hipMemcpy(g.tri_rec0, rec0.data(), sizeof(int4) * rec0.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess && !fin.empty())
     e = hipMemcpy(g.fin_list, fin.data(), sizeof(int32_t) * fin.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) {

@@ -50,6 +50,7 @@ constexpr int32_t kFinBlockMin = 4096;
 constexpr int kTriLongMin = kTriBin2 + 1;
 constexpr int64_t kTriWaveWork = 4096;
 constexpr int32_t kTriWaveSegs = 256;
+static_assert(kTriBin0 < (1 << 16) && kTriWaveSegs < (1 << 15), "wave-bin record packing");
 
 // Per-seed formulation: seeds are binned by degree k and 2-hop work
 // A = sum of neighbour degrees:
@@ -124,7 +125,7 @@ struct Graph {
   int32_t *up_ptr = nullptr;   // degree-oriented half adjacency: u -> {w : rank(w) > rank(u)}
   int32_t *up_col = nullptr;   // each up(u) in rank order
   int32_t *up_deg = nullptr;   // degree of every up_col entry
-  int32_t *tslot = nullptr;    // for every arc: slot of its undirected edge in up_col
+  int32_t *trec = nullptr;     // for every arc v -> a: the triangle record of credits to v, or -1
   // triangle-pass segments of every node w (rows dn_ptr[w] .. dn_ptr[w+1]):
   // {slot of {u, w} in up(u), length of the tail of up(u) above w, k_u, u}
   // for the lower neighbours u of w with a non-empty tail
@@ -136,7 +137,9 @@ struct Graph {
   // host copies used for sizing work lists
   std::vector<int32_t> h_deg;
   std::vector<int32_t> h_up_len;
-  // triangle-pass node lists (device): see kTriBin*
+  // triangle-pass node lists (device): see kTriBin*. Bin 0 as records
+  // {w, up_ptr[w], dn_ptr[w], |up(w)| | segments << 16}, bins 1-3 as ids.
+  int4 *tri_rec0 = nullptr;
   int32_t *tri_list[4] = {nullptr, nullptr, nullptr, nullptr};
   // nodes of degree > kFinGroupMax (finalized one wavefront each), by degree descending
   int32_t *fin_list = nullptr;

@@ -10,7 +10,9 @@
 // of its members w is the contiguous tail after w. The triangle pass lists a
 // triangle u < w < x at its middle node w, walking for every lower neighbour
 // u of w that tail of up(u) against up(w); the per-node lists of those tails
-// ("segments": slot of {u, w} in up(u), tail length, k_u) are built here.
+// ("segments": slot of {u, w} in up(u), tail length, k_u + k_w) are built
+// here, and every arc gets the index of the triangle record that holds the
+// credits to its source node (-1 when no walk writes one).
 #include "ef_internal.h"
 
 namespace efi {
@@ -140,7 +142,8 @@ __global__ void k_dn_flag(const int32_t *__restrict__ src, const int32_t *__rest
   }
 }
 
-__global__ void k_dn_fill(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+__global__ void k_dn_fill(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ src,
+                          const int32_t *__restrict__ col,
                           const int32_t *__restrict__ deg, const int32_t *__restrict__ tslot,
                           const int32_t *__restrict__ up_ptr, const int32_t *__restrict__ dnflag,
                           const int32_t *__restrict__ dnidx, int32_t n, int64_t nnz,
@@ -150,29 +153,48 @@ __global__ void k_dn_fill(const int32_t *__restrict__ row_ptr, const int32_t *__
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz; e += stride) {
     if (dnflag[e]) {
       const int32_t u = col[e], s = tslot[e];
-      dn[dnidx[e]] = make_int4(s, up_ptr[u + 1] - s - 1, deg[u], u);
+      dn[dnidx[e]] = make_int4(s, up_ptr[u + 1] - s - 1, deg[u] + deg[src[e]], u);
     }
   }
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v <= n; v += stride)
     dn_ptr[v] = (v < n && row_ptr[v] < nnz) ? dnidx[row_ptr[v]] : ndn;
 }
 
-// Triangle slots that no kernel writes on a pass (cleared before it):
-//   upper-end slot s of {a, b} (a < b): written by a's walk unless a has no
-//     segments, or is a long-list node (those add with atomics);
-//   lower-end slot nup + s: written by b's walk when {a, b} is a segment.
-__global__ void k_zero_flag(const int32_t *__restrict__ src, const int32_t *__restrict__ rev,
-                            const int32_t *__restrict__ upflag, const int32_t *__restrict__ tslot,
-                            const int32_t *__restrict__ up_ptr, const int32_t *__restrict__ dn_ptr,
-                            const int32_t *__restrict__ dnflag, int64_t nnz, int64_t nup,
+// Upper-end slots of long-list nodes with segments: their walk adds with
+// atomics, so they are cleared before each pass.
+__global__ void k_zero_flag(const int32_t *__restrict__ src, const int32_t *__restrict__ upflag,
+                            const int32_t *__restrict__ tslot, const int32_t *__restrict__ up_ptr,
+                            const int32_t *__restrict__ dn_ptr, int64_t nnz,
                             int32_t *__restrict__ zf) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
        e += (int64_t)gridDim.x * blockDim.x) {
     if (!upflag[e]) continue;
-    const int32_t a = src[e], s = tslot[e];
+    const int32_t a = src[e];
     const int32_t nd = dn_ptr[a + 1] - dn_ptr[a], m = up_ptr[a + 1] - up_ptr[a];
-    zf[s] = (nd == 0 || m > kTriBin2) ? 1 : 0;
-    zf[nup + s] = dnflag[rev[e]] ? 0 : 1;
+    zf[tslot[e]] = (nd > 0 && m > kTriBin2) ? 1 : 0;
+  }
+}
+
+// Per arc v -> a: the triangle record that holds the credits to v, in place
+// of tslot. An edge to a lower-ranked a: a's upper-end slot of {a, v},
+// written by a's walk when a has segments. An edge to a higher-ranked a: the
+// lower-end slot nup + slot of {v, a}, written by a's walk when {v, a} is a
+// segment of a. Otherwise -1: no walk writes the record and readers skip it.
+__global__ void k_trec(const int32_t *__restrict__ col, const int32_t *__restrict__ rev,
+                       const int32_t *__restrict__ upflag, const int32_t *__restrict__ dn_ptr,
+                       const int32_t *__restrict__ dnflag, int64_t nnz, int64_t nup,
+                       int32_t *__restrict__ tslot) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t s = tslot[e];
+    int32_t r;
+    if (upflag[e]) {
+      r = dnflag[rev[e]] ? (int32_t)(nup + s) : -1;
+    } else {
+      const int32_t a = col[e];
+      r = dn_ptr[a + 1] > dn_ptr[a] ? s : -1;
+    }
+    tslot[e] = r;
   }
 }
 
@@ -334,8 +356,8 @@ static unsigned grid_for(int64_t work, int threads) {
 }
 
 // Scratch of launch_graph_prep, in ints:
-//   [0, nnz)          up flags          [nnz, 2 nnz)   up indices, then zero-slot indices
-//   [2 nnz, 3 nnz)    rank keys | rank-sorted up_col, then segment indices, then zero flags
+//   [0, nnz)          up flags          [nnz, 2 nnz)   up indices, then cleared-slot indices
+//   [2 nnz, 3 nnz)    rank keys | rank-sorted up_col, then segment indices, then cleared-slot flags
 //   [3 nnz, 4 nnz)    segment flags     [4 nnz, 4 nnz + nup)   slot permutation
 //   then the scan's block totals
 int64_t graph_prep_tmp_len(int64_t nnz) {
@@ -374,7 +396,7 @@ hipError_t launch_graph_prep(Graph &g, int32_t *tmp, int64_t *work, bool &not_sy
     }
     hipLaunchKernelGGL(k_up_fill, dim3(grid_for(nnz, T)), dim3(T), 0, st, g.row_ptr,
                        g.col_idx, g.rev, upflag, upidx, g.n, nnz, g.up_ptr, g.up_col,
-                       g.tslot);
+                       g.trec);
     // rank order inside each up(u)
     int32_t *upk = G, *newcol = G + nup;
     hipLaunchKernelGGL(k_up_keys, dim3(grid_for(nup, T)), dim3(T), 0, st, g.up_col, g.deg, nup,
@@ -384,24 +406,28 @@ hipError_t launch_graph_prep(Graph &g, int32_t *tmp, int64_t *work, bool &not_sy
     e = hipMemcpyAsync(g.up_col, newcol, sizeof(int32_t) * (size_t)nup, hipMemcpyDeviceToDevice,
                        st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_tslot_remap, dim3(grid_for(nnz, T)), dim3(T), 0, st, g.tslot, perm,
+    hipLaunchKernelGGL(k_tslot_remap, dim3(grid_for(nnz, T)), dim3(T), 0, st, g.trec, perm,
                        nnz);
     // segments of the triangle pass
     int32_t *dnidx = G;
     hipLaunchKernelGGL(k_dn_flag, dim3(grid_for(nnz, T)), dim3(T), 0, st, g.src, g.col_idx,
-                       upflag, g.tslot, g.up_ptr, nnz, dnflag);
+                       upflag, g.trec, g.up_ptr, nnz, dnflag);
     e = launch_exclusive_scan_i32(dnflag, dnidx, nnz, scan_tmp, sl, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_dn_fill, dim3(grid_for(nnz, T)), dim3(T), 0, st, g.row_ptr, g.col_idx,
-                       g.deg, g.tslot, g.up_ptr, dnflag, dnidx, g.n, nnz, g.dn, g.dn_ptr);
+    hipLaunchKernelGGL(k_dn_fill, dim3(grid_for(nnz, T)), dim3(T), 0, st, g.row_ptr, g.src,
+                       g.col_idx, g.deg, g.trec, g.up_ptr, dnflag, dnidx, g.n, nnz, g.dn,
+                       g.dn_ptr);
     hipLaunchKernelGGL(k_dn_work, dim3(grid_for((int64_t)g.n * 64, T)), dim3(T), 0, st,
                        g.dn_ptr, g.dn, g.n, work);
-    // slots no walk writes: flags over both halves, then their scan
+    // slots cleared before each pass (long lists), then their scan
     int32_t *zf = G, *zidx = upidx;
-    hipLaunchKernelGGL(k_zero_flag, dim3(grid_for(nnz, T)), dim3(T), 0, st, g.src, g.rev,
-                       upflag, g.tslot, g.up_ptr, g.dn_ptr, dnflag, nnz, nup, zf);
-    e = launch_exclusive_scan_i32(zf, zidx, 2 * nup, scan_tmp, sl, st);
+    hipLaunchKernelGGL(k_zero_flag, dim3(grid_for(nnz, T)), dim3(T), 0, st, g.src, upflag,
+                       g.trec, g.up_ptr, g.dn_ptr, nnz, zf);
+    e = launch_exclusive_scan_i32(zf, zidx, nup, scan_tmp, sl, st);
     if (e != hipSuccess) return e;
+    // tslot becomes the per-arc triangle record index
+    hipLaunchKernelGGL(k_trec, dim3(grid_for(nnz, T)), dim3(T), 0, st, g.col_idx, g.rev, upflag,
+                       g.dn_ptr, dnflag, nnz, nup, g.trec);
     hipLaunchKernelGGL(k_asum, dim3(grid_for((int64_t)g.n * 64, T)), dim3(T), 0, st,
                        g.row_ptr, g.adj2, g.n, g.asum);
     hipLaunchKernelGGL(k_qa, dim3(grid_for((int64_t)g.n * 64, T)), dim3(T), 0, st, g.row_ptr,
@@ -409,9 +435,9 @@ hipError_t launch_graph_prep(Graph &g, int32_t *tmp, int64_t *work, bool &not_sy
   } else {
     hipLaunchKernelGGL(k_up_fill, dim3(grid_for(g.n + 1, T)), dim3(T), 0, st, g.row_ptr,
                        g.col_idx, g.rev, tmp, tmp, g.n, (int64_t)0, g.up_ptr, g.up_col,
-                       g.tslot);
-    hipLaunchKernelGGL(k_dn_fill, dim3(grid_for(g.n + 1, T)), dim3(T), 0, st, g.row_ptr,
-                       g.col_idx, g.deg, g.tslot, g.up_ptr, tmp, tmp, g.n, (int64_t)0, g.dn,
+                       g.trec);
+    hipLaunchKernelGGL(k_dn_fill, dim3(grid_for(g.n + 1, T)), dim3(T), 0, st, g.row_ptr, g.src,
+                       g.col_idx, g.deg, g.trec, g.up_ptr, tmp, tmp, g.n, (int64_t)0, g.dn,
                        g.dn_ptr);
     (void)hipMemsetAsync(g.asum, 0, sizeof(int64_t) * (size_t)g.n, st);
     (void)hipMemsetAsync(g.qa, 0, sizeof(longlong2) * (size_t)g.n, st);
@@ -426,11 +452,10 @@ hipError_t graph_zero_count(const Graph &g, const int32_t *tmp, int64_t &count) 
   const int64_t nnz = g.nnz, nup = nnz / 2;
   if (nup <= 0) return hipSuccess;
   int32_t last_idx = 0, last_flag = 0;
-  hipError_t e = hipMemcpy(&last_idx, tmp + nnz + 2 * nup - 1, sizeof(int32_t),
+  hipError_t e = hipMemcpy(&last_idx, tmp + nnz + nup - 1, sizeof(int32_t),
                            hipMemcpyDeviceToHost);
   if (e == hipSuccess)
-    e = hipMemcpy(&last_flag, tmp + 2 * nnz + 2 * nup - 1, sizeof(int32_t),
-                  hipMemcpyDeviceToHost);
+    e = hipMemcpy(&last_flag, tmp + 2 * nnz + nup - 1, sizeof(int32_t), hipMemcpyDeviceToHost);
   count = (int64_t)last_idx + last_flag;
   return e;
 }
@@ -438,8 +463,8 @@ hipError_t graph_zero_count(const Graph &g, const int32_t *tmp, int64_t &count) 
 hipError_t launch_zero_list(Graph &g, const int32_t *tmp, hipStream_t st) {
   const int64_t nnz = g.nnz, nup = nnz / 2;
   if (nup <= 0 || g.n_tri_zero <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_zero_fill, dim3(grid_for(2 * nup, 256)), dim3(256), 0, st,
-                     tmp + 2 * nnz, tmp + nnz, 2 * nup, g.tri_zero);
+  hipLaunchKernelGGL(k_zero_fill, dim3(grid_for(nup, 256)), dim3(256), 0, st, tmp + 2 * nnz,
+                     tmp + nnz, nup, g.tri_zero);
   return hipGetLastError();
 }
 

@@ -154,26 +154,26 @@ template <int G> __device__ __forceinline__ DFv group_sum(DFv x) {
 
 // arcs first, first + stride, ... of node v: its own row sums R[e], the
 // reverse arcs' R[rev e], and the triangle credits to v kept with each of its
-// edges (the upper-end record of an edge to a lower-ranked neighbour, the
-// lower-end record nup + slot otherwise)
+// edges (record trec[e]; -1: no walk wrote one, nothing to add)
 template <typename T>
 __device__ __forceinline__ void fin_arcs(const int2 *__restrict__ adj2,
                                          const int32_t *__restrict__ rev,
-                                         const int32_t *__restrict__ tslot, const void *R,
-                                         const TriSlot *__restrict__ Y, int64_t nup, int32_t v,
-                                         int32_t k, int32_t base, int32_t first, int32_t stride,
+                                         const int32_t *__restrict__ trec, const void *R,
+                                         const TriSlot *__restrict__ Y, int32_t k, int32_t base,
+                                         int32_t first, int32_t stride,
                                          typename SumT<T>::type &sacc, double &tfix,
                                          int64_t &Tc) {
   using S = SumT<T>;
   for (int32_t e = base + first; e < base + k; e += stride) {
-    const int2 ad = adj2[e];
-    const int32_t a = ad.x, ka = ad.y;
     // a centre of degree 1 has no pairs: its row sums were never written
     if (k >= 2) S::add_stored(sacc, R, e);
-    if (ka >= 2) S::add_stored(sacc, R, rev[e]);
-    const TriSlot r = Y[tslot[e] + (rank_less_d(a, ka, v, k) ? 0 : nup)];
-    tfix += (double)r.y;  // 2^-36 fixed-point units
-    Tc += r.t;
+    if (adj2[e].y >= 2) S::add_stored(sacc, R, rev[e]);
+    const int32_t r = trec[e];
+    if (r >= 0) {
+      const TriSlot t = Y[r];
+      tfix += (double)t.y;  // 2^-36 fixed-point units
+      Tc += t.t;
+    }
   }
 }
 
@@ -184,14 +184,17 @@ __device__ __forceinline__ void fin_arcs(const int2 *__restrict__ adj2,
 // less 8 per triangle.
 template <typename T>
 __device__ __forceinline__ void fin_store(int32_t v, int32_t k, int64_t As, longlong2 qa,
-                                          typename SumT<T>::type sacc, double tfix, int64_t Tc,
-                                          const void *Z, const int64_t *__restrict__ ZT,
-                                          double *ef, int64_t *Dout, int64_t *Nout,
-                                          uint8_t *fl) {
+                                          bool has_z, typename SumT<T>::type sacc, double tfix,
+                                          int64_t Tc, const void *Z,
+                                          const int64_t *__restrict__ ZT, double *ef,
+                                          int64_t *Dout, int64_t *Nout, uint8_t *fl) {
   using S = SumT<T>;
   typename S::type z = typename S::type();
-  S::add_stored(z, Z, v);
-  Tc += ZT[v];
+  // Z, ZT: written by the triangle walk of nodes that have segments
+  if (has_z) {
+    S::add_stored(z, Z, v);
+    Tc += ZT[v];
+  }
   const double tri = tfix * (1.0 / kTriFix) + S::value(z);
   const double Stot = S::value(sacc) + 4.0 * tri;
   const int64_t kk = k;
@@ -205,12 +208,11 @@ __device__ __forceinline__ void fin_store(int32_t v, int32_t k, int64_t As, long
 struct FinArgs {
   const int32_t *row_ptr, *deg;
   const int2 *adj2;
-  const int32_t *rev, *tslot;
+  const int32_t *rev, *trec, *dn_ptr;
   const int64_t *asum;
   const longlong2 *qa;
   const void *R;
   const TriSlot *Y;
-  int64_t nup;
   const void *Z;
   const int64_t *ZT;
   double *ef;
@@ -242,13 +244,13 @@ __device__ __forceinline__ void fin_groups(const FinArgs &A, const int32_t *node
     double tfix = 0.0;
     int64_t Tc = 0;
     if (v >= 0)
-      fin_arcs<T>(A.adj2, A.rev, A.tslot, A.R, A.Y, A.nup, v, k, A.row_ptr[v], sub, G, sacc, tfix,
-                  Tc);
+      fin_arcs<T>(A.adj2, A.rev, A.trec, A.R, A.Y, k, A.row_ptr[v], sub, G, sacc, tfix, Tc);
     sacc = group_sum<G>(sacc);
     tfix = group_sum<G>(tfix);
     Tc = group_sum<G>(Tc);
     if (v >= 0 && sub == 0)
-      fin_store<T>(v, k, A.asum[v], A.qa[v], sacc, tfix, Tc, A.Z, A.ZT, A.ef, A.D, A.N, A.fl);
+      fin_store<T>(v, k, A.asum[v], A.qa[v], A.dn_ptr[v + 1] > A.dn_ptr[v], sacc, tfix, Tc, A.Z,
+                   A.ZT, A.ef, A.D, A.N, A.fl);
   }
 }
 
@@ -267,8 +269,7 @@ __device__ __forceinline__ void fin_hubs(const FinArgs &A, const int32_t *nodes,
     Acc sacc = Acc();
     double tfix = 0.0;
     int64_t Tc = 0;
-    fin_arcs<T>(A.adj2, A.rev, A.tslot, A.R, A.Y, A.nup, v, k, A.row_ptr[v], tid, 256, sacc, tfix,
-                Tc);
+    fin_arcs<T>(A.adj2, A.rev, A.trec, A.R, A.Y, k, A.row_ptr[v], tid, 256, sacc, tfix, Tc);
     sacc = wave_sum(sacc);
     tfix = wave_sum_f64(tfix);
     Tc = wave_sum_i64(Tc);
@@ -284,7 +285,8 @@ __device__ __forceinline__ void fin_hubs(const FinArgs &A, const int32_t *nodes,
         tfix += shT[w];
         Tc += shC[w];
       }
-      fin_store<T>(v, k, A.asum[v], A.qa[v], sacc, tfix, Tc, A.Z, A.ZT, A.ef, A.D, A.N, A.fl);
+      fin_store<T>(v, k, A.asum[v], A.qa[v], A.dn_ptr[v + 1] > A.dn_ptr[v], sacc, tfix, Tc, A.Z,
+                   A.ZT, A.ef, A.D, A.N, A.fl);
     }
     __syncthreads();
   }
@@ -324,8 +326,8 @@ hipError_t launch_finalize_cluster(const Graph &g, ef_prec prec, const void *R, 
   const int64_t bw = n_wave > 0 ? cap_blocks((n_wave * 64 + 255) / 256, 1 << 18) : 0;
   const int64_t bc = g.n_fin_half > 0 ? cap_blocks((g.n_fin_half * 32 + 255) / 256, 1 << 18) : 0;
   const int64_t bs = cap_blocks(((int64_t)g.n * 8 + 255) / 256, 1 << 19);
-  const FinArgs A{g.row_ptr, g.deg, g.adj2, g.rev, g.tslot, g.asum, g.qa, R,
-                  Y,         g.nnz / 2, Z, ZT,  ef,      D,      N,      fl};
+  const FinArgs A{g.row_ptr, g.deg, g.adj2, g.rev, g.trec, g.dn_ptr, g.asum, g.qa,
+                  R,         Y,     Z,      ZT,    ef,     D,      N,        fl};
   const unsigned grid = (unsigned)(bh + bw + bc + bs);
   if (prec == EF_PREC_FP64)
     hipLaunchKernelGGL(k_finalize_cluster<double>, dim3(grid), dim3(256), 0, st, A, g.fin_list,

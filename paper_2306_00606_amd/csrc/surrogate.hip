@@ -107,23 +107,24 @@ template <int G> __device__ __forceinline__ FeatAcc feat_reduce(FeatAcc a) {
 
 __device__ __forceinline__ void feat_arcs(const int2 *__restrict__ adj2,
                                           const int64_t *__restrict__ asum,
-                                          const int32_t *__restrict__ tslot,
-                                          const TriSlot *__restrict__ Y, int64_t nup, int32_t v,
-                                          int32_t k, int32_t base, int32_t first, int32_t stride,
-                                          FeatAcc &f) {
+                                          const int32_t *__restrict__ trec,
+                                          const TriSlot *__restrict__ Y, int32_t k, int32_t base,
+                                          int32_t first, int32_t stride, FeatAcc &f) {
   for (int32_t e = base + first; e < base + k; e += stride) {
     const int2 ad = adj2[e];
     f.add(ad, asum[ad.x]);
-    // triangles credited to v through this edge (upper-end or lower-end record)
-    f.T += Y[tslot[e] + (rank_less_d(ad.x, ad.y, v, k) ? 0 : nup)].t;
+    // triangles credited to the node through this edge
+    const int32_t r = trec[e];
+    if (r >= 0) f.T += Y[r].t;
   }
 }
 
-__device__ void feat_store(int32_t v, int32_t k, int64_t A, FeatAcc a,
+// ZT[v] is written by the triangle walk of nodes with segments (has_z)
+__device__ void feat_store(int32_t v, int32_t k, int64_t A, FeatAcc a, bool has_z,
                            const int64_t *__restrict__ ZT, const float *__restrict__ mean,
                            const float *__restrict__ inv_std, float *__restrict__ X,
                            float *__restrict__ lnN) {
-  const int64_t T = a.T + ZT[v];
+  const int64_t T = a.T + (has_z ? ZT[v] : 0);
   const int64_t kk = k, B = a.B, Q = a.Q;
   const int64_t Ns = kk * kk - 2 * kk + A;
   const int64_t Ds = kk * (kk - 1) * (kk - 4) + 2 * (kk - 1) * A + (kk - 4) * (A - kk) +
@@ -157,7 +158,8 @@ template <int G>
 __global__ __launch_bounds__(256) void k_features(
     const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ deg,
     const int2 *__restrict__ adj2, const int64_t *__restrict__ asum,
-    const int32_t *__restrict__ tslot, const TriSlot *__restrict__ Y, int64_t nup,
+    const int32_t *__restrict__ trec, const TriSlot *__restrict__ Y,
+    const int32_t *__restrict__ dn_ptr,
     const int64_t *__restrict__ ZT, const int32_t *__restrict__ nodes, int64_t count,
     int32_t kmax, const float *__restrict__ mean, const float *__restrict__ inv_std,
     float *__restrict__ X, float *__restrict__ lnN) {
@@ -175,16 +177,18 @@ __global__ __launch_bounds__(256) void k_features(
     }
     if (v < 0) k = 0;
     FeatAcc f = feat_zero();
-    if (v >= 0) feat_arcs(adj2, asum, tslot, Y, nup, v, k, row_ptr[v], sub, G, f);
+    if (v >= 0) feat_arcs(adj2, asum, trec, Y, k, row_ptr[v], sub, G, f);
     f = feat_reduce<G>(f);
-    if (v >= 0 && sub == 0) feat_store(v, k, asum[v], f, ZT, mean, inv_std, X, lnN);
+    if (v >= 0 && sub == 0)
+      feat_store(v, k, asum[v], f, dn_ptr[v + 1] > dn_ptr[v], ZT, mean, inv_std, X, lnN);
   }
 }
 
 __global__ __launch_bounds__(1024) void k_features_hub(
     const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ deg,
     const int2 *__restrict__ adj2, const int64_t *__restrict__ asum,
-    const int32_t *__restrict__ tslot, const TriSlot *__restrict__ Y, int64_t nup,
+    const int32_t *__restrict__ trec, const TriSlot *__restrict__ Y,
+    const int32_t *__restrict__ dn_ptr,
     const int64_t *__restrict__ ZT, const int32_t *__restrict__ nodes, int64_t count,
     const float *__restrict__ mean, const float *__restrict__ inv_std, float *__restrict__ X,
     float *__restrict__ lnN) {
@@ -194,14 +198,14 @@ __global__ __launch_bounds__(1024) void k_features_hub(
     const int32_t v = nodes[it];
     const int32_t k = deg[v];
     FeatAcc f = feat_zero();
-    feat_arcs(adj2, asum, tslot, Y, nup, v, k, row_ptr[v], tid, 1024, f);
+    feat_arcs(adj2, asum, trec, Y, k, row_ptr[v], tid, 1024, f);
     f = feat_reduce<64>(f);
     if (lane == 0) sh[wv] = f;
     __syncthreads();
     if (tid == 0) {
       FeatAcc a = sh[0];
       for (int w = 1; w < 16; ++w) a.merge(sh[w]);
-      feat_store(v, k, asum[v], a, ZT, mean, inv_std, X, lnN);
+      feat_store(v, k, asum[v], a, dn_ptr[v + 1] > dn_ptr[v], ZT, mean, inv_std, X, lnN);
     }
     __syncthreads();
   }
@@ -215,18 +219,18 @@ hipError_t launch_features(const Graph &g, const TriSlot *Y, const int64_t *ZT,
   const int32_t *l_wave = g.fin_list + g.n_fin_hub, *l_half = l_wave + n_wave;
   if (g.n_fin_hub > 0)
     hipLaunchKernelGGL(k_features_hub, dim3(cap(g.n_fin_hub, 1 << 16)), dim3(1024), 0, st,
-                       g.row_ptr, g.deg, g.adj2, g.asum, g.tslot, Y, g.nnz / 2, ZT, g.fin_list,
+                       g.row_ptr, g.deg, g.adj2, g.asum, g.trec, Y, g.dn_ptr, ZT, g.fin_list,
                        g.n_fin_hub, mean, inv_std, X, lnN);
   hipLaunchKernelGGL(k_features<8>, dim3(cap(((int64_t)g.n * 8 + 255) / 256, 1 << 20)), dim3(256),
-                     0, st, g.row_ptr, g.deg, g.adj2, g.asum, g.tslot, Y, g.nnz / 2, ZT, nullptr,
+                     0, st, g.row_ptr, g.deg, g.adj2, g.asum, g.trec, Y, g.dn_ptr, ZT, nullptr,
                      (int64_t)g.n, kFinGroupMax, mean, inv_std, X, lnN);
   if (n_wave > 0)
     hipLaunchKernelGGL(k_features<64>, dim3(cap((n_wave * 64 + 255) / 256, 1 << 20)), dim3(256),
-                       0, st, g.row_ptr, g.deg, g.adj2, g.asum, g.tslot, Y, g.nnz / 2, ZT, l_wave, n_wave,
+                       0, st, g.row_ptr, g.deg, g.adj2, g.asum, g.trec, Y, g.dn_ptr, ZT, l_wave, n_wave,
                        0, mean, inv_std, X, lnN);
   if (g.n_fin_half > 0)
     hipLaunchKernelGGL(k_features<32>, dim3(cap((g.n_fin_half * 32 + 255) / 256, 1 << 20)),
-                       dim3(256), 0, st, g.row_ptr, g.deg, g.adj2, g.asum, g.tslot, Y, g.nnz / 2, ZT,
+                       dim3(256), 0, st, g.row_ptr, g.deg, g.adj2, g.asum, g.trec, Y, g.dn_ptr, ZT,
                        l_half, g.n_fin_half, 0, mean, inv_std, X, lnN);
   return hipGetLastError();
 }

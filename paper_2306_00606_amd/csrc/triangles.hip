@@ -108,7 +108,7 @@ template <> struct Credit<TriCount> {
 //   hkey[SLOTS]   ids x of up(w) (LdsHash), hval[slot] = k_x << kPosBits |
 //                 position of x in up(w)
 //   seg[MAXS]     per segment of the chunk: {first index of the tail in up_col
-//                 minus its first index in the concatenated sequence, k_u}
+//                 minus its first index in the concatenated sequence, k_u + k_w}
 //   segp[MAXS+1]  first concatenated index of each segment; segp[nseg] = total
 //   sslot[MAXS]   slot of {u, w} in up(u): the segment's lower-end slot
 //   acc, cnt      credits to x by position in up(w)
@@ -142,16 +142,13 @@ __device__ __forceinline__ int32_t tri_hash(const int32_t *__restrict__ up_col,
   return myslot;
 }
 
-// Segment table of one chunk: cnt <= NT segments from dn[d0]; every segment
-// is non-empty. Returns the concatenated length (workgroup form: every
-// thread calls it; `part` holds NT/64 ints).
+// Segment table of one chunk: entry e (a dn record, meaningful for
+// tid < cnt <= NT; every segment is non-empty). Returns the concatenated
+// length (workgroup form: every thread calls it; `part` holds NT/64 ints).
 template <int NT, typename L>
-__device__ __forceinline__ int32_t tri_segs(const int4 *__restrict__ dn, int32_t d0, int32_t cnt,
-                                            int tid, L &lds, int32_t *part) {
-  int4 e = make_int4(0, 0, 0, 0);
-  if (tid < cnt) e = dn[d0 + tid];
+__device__ __forceinline__ int32_t tri_segs(int4 e, int32_t cnt, int tid, L &lds, int32_t *part) {
   int32_t total;
-  const int32_t start = group_excl_scan<NT>(e.y, part, total);
+  const int32_t start = group_excl_scan<NT>(tid < cnt ? e.y : 0, part, total);
   if (tid < cnt) {
     lds.seg[tid] = make_int2(e.x + 1 - start, e.z);
     lds.segp[tid] = start;
@@ -172,7 +169,7 @@ constexpr int kQueue = 128;
 template <typename T, int SLOTS, int MAXM, int MAXS>
 __device__ __forceinline__ void tri_walk(const int32_t *__restrict__ up_col,
                                          TriLds<T, SLOTS, MAXM, MAXS> &L, int32_t *flg, int2 *hq,
-                                         int32_t nseg, int32_t beg, int32_t end, int32_t kw,
+                                         int32_t nseg, int32_t beg, int32_t end,
                                          typename SumT<T>::type &accw, int64_t &cntw) {
   using S = SumT<T>;
   constexpr int32_t kPosMask = (1 << kPosBits) - 1;
@@ -209,7 +206,7 @@ __device__ __forceinline__ void tri_walk(const int32_t *__restrict__ up_col,
           const int32_t ev = hval[slot];
           const int32_t rank = (int32_t)__builtin_amdgcn_mbcnt_hi(
               (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-          hq[qn + rank] = make_int2(kw + xv.y + unpack_k(ev), sg | ((ev & kPosMask) << 16));
+          hq[qn + rank] = make_int2(xv.y + unpack_k(ev), sg | ((ev & kPosMask) << 16));
         }
         qn += __popcll(m);
         if (qn >= 64) drain(64);
@@ -259,7 +256,7 @@ __device__ __forceinline__ void tri_clear_credits(TriLds<T, SLOTS, MAXM, MAXS> &
 }
 
 struct TriArgs {
-  const int32_t *up_ptr, *up_col, *up_deg, *deg, *dn_ptr;
+  const int32_t *up_ptr, *up_col, *up_deg, *dn_ptr;
   const int4 *dn;
   int64_t nup;
   TriSlot *Y;
@@ -268,9 +265,13 @@ struct TriArgs {
 };
 
 // One node w per wavefront (|up(w)| <= 64, short walk); WPB wavefronts per
-// workgroup, each with its own LDS state; chunks of 64 segments.
+// workgroup, each with its own LDS state; chunks of 64 segments. The list
+// holds {w, first up slot, first segment, |up(w)| | segments << 16} per node:
+// the next node's record is loaded while this one runs, and this node's
+// up(w) and first segments are loaded together, so a short node waits on
+// one global round trip before its walk.
 template <typename T, int SLOTS, int MAXM, int WPB>
-__global__ __launch_bounds__(64 * WPB) void k_tri_wave(TriArgs A, const int32_t *__restrict__ nodes,
+__global__ __launch_bounds__(64 * WPB) void k_tri_wave(TriArgs A, const int4 *__restrict__ recs,
                                                         int64_t count) {
   using S = SumT<T>;
   using Acc = typename S::type;
@@ -288,19 +289,31 @@ __global__ __launch_bounds__(64 * WPB) void k_tri_wave(TriArgs A, const int32_t 
   static_assert(MAXM <= 64, "one up(w) entry per lane");
   for (int i = lane; i < SLOTS; i += 64) L.hkey[i] = -1;
   tri_clear_credits(L, lane, 64);
-  for (int64_t it = (int64_t)blockIdx.x * WPB + wv; it < count; it += nwaves) {
-    const int32_t w = nodes[it];
-    const int32_t w0 = A.up_ptr[w], m = A.up_ptr[w + 1] - w0, kw = A.deg[w];
-    const int32_t d0 = A.dn_ptr[w], nd = A.dn_ptr[w + 1] - d0;
+  int64_t it = (int64_t)blockIdx.x * WPB + wv;
+  int4 nxt = it < count ? recs[it] : make_int4(0, 0, 0, 0);
+  for (; it < count; it += nwaves) {
+    const int4 rc = nxt;
+    if (it + nwaves < count) nxt = recs[it + nwaves];
+    const int32_t w = rc.x, w0 = rc.y, d0 = rc.z, m = rc.w & 0xFFFF, nd = rc.w >> 16;
+    // m >= 1 and nd >= 1 for every listed node: clamped indices stay in
+    // w's rows, and every lane loads without a branch
+    const int32_t ui = w0 + (lane < m ? lane : m - 1);
+    const int32_t x = A.up_col[ui], kx = A.up_deg[ui];
+    int4 sg = A.dn[d0 + (lane < nd ? lane : nd - 1)];
     wave_sync();
-    const int32_t myslot = tri_hash<SLOTS, 64>(A.up_col, A.up_deg, w0, m, lane, L.hkey, L.hval);
+    int32_t myslot = -1;
+    if (lane < m) {
+      myslot = LdsHash<SLOTS>::insert(L.hkey, x);
+      L.hval[myslot] = pack_kp(kx, lane);
+    }
     Acc accw = Acc();
     int64_t cntw = 0;
     for (int32_t c0 = 0; c0 < nd; c0 += MAXS) {
       const int32_t cnt = nd - c0 < MAXS ? nd - c0 : MAXS;
-      const int32_t total = tri_segs<64>(A.dn, d0 + c0, cnt, lane, L, nullptr);
+      if (c0 > 0) sg = A.dn[d0 + c0 + (lane < cnt ? lane : cnt - 1)];
+      const int32_t total = tri_segs<64>(sg, cnt, lane, L, nullptr);
       wave_sync();
-      tri_walk<T, SLOTS, MAXM, MAXS>(A.up_col, L, flg, hq_s[wv], cnt, 0, total, kw, accw, cntw);
+      tri_walk<T, SLOTS, MAXM, MAXS>(A.up_col, L, flg, hq_s[wv], cnt, 0, total, accw, cntw);
       tri_flush(L, cnt, w0, m, c0 == 0, lane, 64, A.nup, A.Y);
     }
     accw = wave_sum(accw);
@@ -336,7 +349,7 @@ __global__ __launch_bounds__(64 * WPB) void k_tri_block(TriArgs A,
   tri_clear_credits(L, tid, NT);
   for (int64_t it = blockIdx.x; it < count; it += gridDim.x) {
     const int32_t w = nodes[it];
-    const int32_t w0 = A.up_ptr[w], m = A.up_ptr[w + 1] - w0, kw = A.deg[w];
+    const int32_t w0 = A.up_ptr[w], m = A.up_ptr[w + 1] - w0;
     const int32_t d0 = A.dn_ptr[w], nd = A.dn_ptr[w + 1] - d0;
     for (int i = tid; i < SLOTS; i += NT) L.hkey[i] = -1;
     __syncthreads();
@@ -345,14 +358,15 @@ __global__ __launch_bounds__(64 * WPB) void k_tri_block(TriArgs A,
     int64_t cntw = 0;
     for (int32_t c0 = 0; c0 < nd; c0 += MAXS) {
       const int32_t cnt = nd - c0 < MAXS ? nd - c0 : MAXS;
-      const int32_t total = tri_segs<NT>(A.dn, d0 + c0, cnt, tid, L, part);
+      const int4 sg = tid < cnt ? A.dn[d0 + c0 + tid] : make_int4(0, 0, 0, 0);
+      const int32_t total = tri_segs<NT>(sg, cnt, tid, L, part);
       __syncthreads();
       // contiguous shares, multiples of 64 entries
       const int32_t steps = (total + 63) >> 6;
       const int32_t beg = (int32_t)(((int64_t)steps * wv / WPB) << 6);
       const int32_t fin = (int32_t)(((int64_t)steps * (wv + 1) / WPB) << 6);
       tri_walk<T, SLOTS, MAXM, MAXS>(A.up_col, L, flg, hq_s[wv], cnt, beg,
-                                     fin < total ? fin : total, kw, accw, cntw);
+                                     fin < total ? fin : total, accw, cntw);
       __syncthreads();
       tri_flush(L, cnt, w0, m, c0 == 0, tid, NT, A.nup, A.Y);
       __syncthreads();
@@ -390,14 +404,14 @@ __global__ __launch_bounds__(64) void k_tri_long(TriArgs A, const int32_t *__res
   const int lane = threadIdx.x;
   for (int64_t it = blockIdx.x; it < count; it += gridDim.x) {
     const int32_t w = nodes[it];
-    const int32_t w0 = A.up_ptr[w], m = A.up_ptr[w + 1] - w0, kw = A.deg[w];
+    const int32_t w0 = A.up_ptr[w], m = A.up_ptr[w + 1] - w0;
     const int32_t d0 = A.dn_ptr[w], nd = A.dn_ptr[w + 1] - d0;
     Acc accw = Acc();
     int64_t cntw = 0;
     for (int32_t base = 0; base < nd; base += 64) {
       const int32_t i = base + lane;
       if (i >= nd) continue;
-      const int4 sgm = A.dn[d0 + i];  // {slot of {u, w}, tail length, k_u, u}
+      const int4 sgm = A.dn[d0 + i];  // {slot of {u, w}, tail length, k_u + k_w, u}
       long long accu = 0;
       int32_t cntu = 0;
       for (int32_t j = sgm.x + 1; j <= sgm.x + sgm.y; ++j) {
@@ -409,7 +423,7 @@ __global__ __launch_bounds__(64) void k_tri_long(TriArgs A, const int32_t *__res
           if (ky < kx || (ky == kx && y < x)) lo = mid + 1; else hi = mid;
         }
         if (lo < m && A.up_col[w0 + lo] == x) {
-          const T dl = tri_delta<T>(kw + sgm.z + kx);
+          const T dl = tri_delta<T>(sgm.z + kx);
           const long long f = to_fix(dl);
           S::add_term(accw, dl);
           ++cntw;
@@ -430,21 +444,13 @@ __global__ __launch_bounds__(64) void k_tri_long(TriArgs A, const int32_t *__res
   }
 }
 
-// Clear what no walk writes: Z and ZT of nodes without segments, and the
-// listed slots (upper-end slots of nodes without segments or with long
-// lists, lower-end slots of edges that are no segment).
-template <typename T>
-__global__ void k_tri_zero(TriArgs A, int32_t n, const int32_t *__restrict__ zl, int64_t nz) {
-  using S = SumT<T>;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += stride)
-    if (A.dn_ptr[v + 1] == A.dn_ptr[v]) {
-      S::store(typename S::type(), A.Z, v);
-      A.ZT[v] = 0;
-    }
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nz; i += stride) {
-    A.Y[zl[i]] = TriSlot{0, 0, 0};
-  }
+// Clear the listed records (upper-end records of long-list nodes, which
+// their walk adds to with atomics). Records no walk writes are never read:
+// readers skip trec = -1, and read Z / ZT only of nodes with segments.
+__global__ void k_tri_zero(TriSlot *__restrict__ Y, const int32_t *__restrict__ zl, int64_t nz) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nz;
+       i += (int64_t)gridDim.x * blockDim.x)
+    Y[zl[i]] = TriSlot{0, 0, 0};
 }
 
 static unsigned cap_blocks(int64_t b, int64_t cap) {
@@ -456,14 +462,14 @@ static unsigned cap_blocks(int64_t b, int64_t cap) {
 // workgroups, long lists)
 template <typename T>
 static hipError_t tri_impl(const Graph &g, TriSlot *Y, void *Z, int64_t *ZT, hipStream_t st) {
-  const TriArgs A{g.up_ptr, g.up_col, g.up_deg, g.deg, g.dn_ptr, g.dn, g.nnz / 2, Y, Z, ZT};
-  const int64_t zw = std::max<int64_t>(g.n, g.n_tri_zero);
-  hipLaunchKernelGGL(k_tri_zero<T>, dim3(cap_blocks((zw + 255) / 256, 1 << 16)), dim3(256), 0, st,
-                     A, g.n, g.tri_zero, g.n_tri_zero);
+  const TriArgs A{g.up_ptr, g.up_col, g.up_deg, g.dn_ptr, g.dn, g.nnz / 2, Y, Z, ZT};
+  if (g.n_tri_zero > 0)
+    hipLaunchKernelGGL(k_tri_zero, dim3(cap_blocks((g.n_tri_zero + 255) / 256, 1 << 16)),
+                       dim3(256), 0, st, Y, g.tri_zero, g.n_tri_zero);
   const int64_t *counts = g.n_tri;
   if (counts[0] > 0)
     hipLaunchKernelGGL((k_tri_wave<T, 256, 64, 4>), dim3(cap_blocks((counts[0] + 3) / 4, 1 << 20)),
-                       dim3(256), 0, st, A, g.tri_list[0], counts[0]);
+                       dim3(256), 0, st, A, g.tri_rec0, counts[0]);
   if (counts[1] > 0)
     hipLaunchKernelGGL((k_tri_block<T, 2048, 512, 8, 512>), dim3(cap_blocks(counts[1], 1 << 20)),
                        dim3(512), 0, st, A, g.tri_list[1], counts[1]);
