@@ -10,7 +10,9 @@ What it computes is the plain definition: per seed, every ordered pair of
 transmission events, the degree of the resulting three-node cluster (edges
 leaving it), the histogram of those degrees and the entropy of Eq. 1 of
 "Scaling Expected Force" (Sec. 3.3), in double precision, with the
-multiplicities of Algorithm 1. See ``ef_oracle.c`` for the exact statement.
+multiplicities of Algorithm 1; and the same with three events (four-node
+clusters, the parameter j = 3 of Sec. 3.3). See ``ef_oracle.c`` for the exact
+statement.
 """
 from __future__ import annotations
 
@@ -48,6 +50,10 @@ def _load():
     lib.oracle_histogram.argtypes = [ctypes.c_int32, vp, vp, ctypes.c_int32, vp, vp,
                                      ctypes.c_int64]
     lib.oracle_histogram.restype = ctypes.c_int64
+    lib.oracle_ef3.argtypes = lib.oracle_ef.argtypes
+    lib.oracle_ef3.restype = ctypes.c_int
+    lib.oracle_histogram3.argtypes = lib.oracle_histogram.argtypes
+    lib.oracle_histogram3.restype = ctypes.c_int64
     _lib = lib
     return lib
 
@@ -60,9 +66,11 @@ def _csr(row_ptr, col_idx):
     return rp, ci
 
 
-def ef(row_ptr, col_idx, seeds=None, threads: int = 1):
+def ef(row_ptr, col_idx, seeds=None, threads: int = 1, j: int = 2):
     """Returns (N, D, EF) as int64, int64, float64 arrays aligned with `seeds`
-    (all nodes when seeds is None)."""
+    (all nodes when seeds is None), for j = 2 or j = 3 transmission events."""
+    if j not in (2, 3):
+        raise ValueError("j must be 2 or 3")
     rp, ci = _csr(row_ptr, col_idx)
     n = rp.size - 1
     if seeds is None:
@@ -76,24 +84,27 @@ def ef(row_ptr, col_idx, seeds=None, threads: int = 1):
     D = np.zeros(max(cnt, 1), np.int64)
     E = np.zeros(max(cnt, 1), np.float64)
     if cnt:
-        st = _load().oracle_ef(n, rp.ctypes.data, ci.ctypes.data, sp, cnt, N.ctypes.data,
-                               D.ctypes.data, E.ctypes.data, int(threads))
+        fn = _load().oracle_ef if j == 2 else _load().oracle_ef3
+        st = fn(n, rp.ctypes.data, ci.ctypes.data, sp, cnt, N.ctypes.data, D.ctypes.data,
+                E.ctypes.data, int(threads))
         if st != 0:
             raise RuntimeError(f"oracle_ef failed with status {st}")
     return N[:cnt], D[:cnt], E[:cnt]
 
 
-def histogram(row_ptr, col_idx, s: int):
-    """H_s as a dict {cluster degree: number of event sequences}."""
+def histogram(row_ptr, col_idx, s: int, j: int = 2):
+    """H_s as a dict {cluster degree: number of event sequences} (j = 2 or 3)."""
+    if j not in (2, 3):
+        raise ValueError("j must be 2 or 3")
     rp, ci = _csr(row_ptr, col_idx)
     n = rp.size - 1
     lib = _load()
+    fn = lib.oracle_histogram if j == 2 else lib.oracle_histogram3
     cap = 64
     while True:
         d = np.zeros(cap, np.int64)
         c = np.zeros(cap, np.int64)
-        m = lib.oracle_histogram(n, rp.ctypes.data, ci.ctypes.data, int(s), d.ctypes.data,
-                                 c.ctypes.data, cap)
+        m = fn(n, rp.ctypes.data, ci.ctypes.data, int(s), d.ctypes.data, c.ctypes.data, cap)
         if m < 0:
             raise RuntimeError("oracle_histogram failed")
         if m <= cap:

@@ -159,6 +159,126 @@ static int32_t max_degree(int32_t n, const int32_t *row_ptr) {
 }
 
 /*
+ * Expected Force with j = 3 transmission events (Sec. 3.3 defines EF for a
+ * number j of events and uses j = 2; the sequences are counted the same way
+ * as for j = 2, one per ordered list of events):
+ *     event 1:  s infects a neighbour y of s;
+ *     event 2:  x2 in {s, y} infects a susceptible neighbour z of x2;
+ *     event 3:  x3 in {s, y, z} infects a susceptible neighbour w of x3.
+ * The cluster is J = {s, y, z, w}; its degree is the number of edges with
+ * exactly one endpoint in J, (sum of the four degrees) - 2 * (edges inside J),
+ * the internal edges found by the membership tests below. H_s, N_s, D_s and
+ * EF_s then follow exactly as for j = 2 (seed_finish).
+ */
+static void seed_histogram3(int32_t s, const int32_t *row_ptr, const int32_t *col_idx,
+                            scratch_t *w, int64_t *mark_z, int64_t *stamp2, int64_t *stamp3) {
+  const int32_t s0 = row_ptr[s], s1 = row_ptr[s + 1];
+  const int64_t ks = s1 - s0;
+  for (int32_t e = s0; e < s1; ++e) w->mark_s[col_idx[e]] = s;
+  for (int32_t e1 = s0; e1 < s1; ++e1) {
+    const int32_t y = col_idx[e1]; /* event 1: s -> y */
+    const int32_t y0 = row_ptr[y], y1 = row_ptr[y + 1];
+    const int64_t ky = y1 - y0;
+    const int64_t st = (*stamp2)++;
+    for (int32_t e = y0; e < y1; ++e) w->mark_y[col_idx[e]] = st;
+    /* event 2: x2 -> z, from s (pass 0) or from y (pass 1) */
+    for (int pass = 0; pass < 2; ++pass) {
+      const int32_t x2 = pass == 0 ? s : y;
+      for (int32_t e2 = row_ptr[x2]; e2 < row_ptr[x2 + 1]; ++e2) {
+        const int32_t z = col_idx[e2];
+        if (z == s || z == y) continue;
+        const int32_t z0 = row_ptr[z], z1 = row_ptr[z + 1];
+        const int64_t kz = z1 - z0;
+        const int64_t st3 = (*stamp3)++;
+        for (int32_t e = z0; e < z1; ++e) mark_z[col_idx[e]] = st3;
+        /* edges inside {s, y, z}: s~y, and z's edges to s and to y */
+        const int64_t in3 = 1 + (w->mark_s[z] == s ? 1 : 0) + (w->mark_y[z] == st ? 1 : 0);
+        /* event 3: x3 -> v, x3 in {s, y, z}, v not in {s, y, z} */
+        const int32_t tri[3] = {s, y, z};
+        for (int t = 0; t < 3; ++t) {
+          const int32_t x3 = tri[t];
+          for (int32_t e3 = row_ptr[x3]; e3 < row_ptr[x3 + 1]; ++e3) {
+            const int32_t v = col_idx[e3];
+            if (v == s || v == y || v == z) continue;
+            const int64_t kv = row_ptr[v + 1] - row_ptr[v];
+            const int64_t cv = (w->mark_s[v] == s ? 1 : 0) + (w->mark_y[v] == st ? 1 : 0) +
+                               (mark_z[v] == st3 ? 1 : 0);
+            hist_add(w, ks + ky + kz + kv - 2 * (in3 + cv));
+          }
+        }
+      }
+    }
+  }
+}
+
+/* EF with j = 3 events for `seeds` (all nodes when NULL); as oracle_ef. */
+int oracle_ef3(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+               const int32_t *seeds, int32_t n_seeds, int64_t *N_out, int64_t *D_out,
+               double *EF_out, int32_t n_threads) {
+  if (n < 0 || !row_ptr || (n > 0 && row_ptr[n] > 0 && !col_idx)) return ORACLE_ERR_ARG;
+  const int32_t count = seeds ? n_seeds : n;
+  if (count < 0) return ORACLE_ERR_ARG;
+  if (count == 0) return ORACLE_OK;
+  for (int32_t t = 0; seeds && t < count; ++t)
+    if (seeds[t] < 0 || seeds[t] >= n) return ORACLE_ERR_ARG;
+  const int64_t max_d = 4 * (int64_t)max_degree(n, row_ptr);
+  int status = ORACLE_OK;
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#else
+  (void)n_threads;
+#endif
+#pragma omp parallel
+  {
+    scratch_t w;
+    int64_t *mark_z = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n + 1));
+    int ok = scratch_init(&w, n, max_d) == ORACLE_OK && mark_z;
+    if (!ok) {
+#pragma omp atomic write
+      status = ORACLE_ERR_NOMEM;
+    } else {
+      for (int32_t i = 0; i <= n; ++i) mark_z[i] = -1;
+    }
+    int64_t stamp2 = 0, stamp3 = 0;
+#pragma omp for schedule(dynamic, 2)
+    for (int32_t t = 0; t < count; ++t) {
+      if (!ok) continue;
+      const int32_t s = seeds ? seeds[t] : t;
+      seed_histogram3(s, row_ptr, col_idx, &w, mark_z, &stamp2, &stamp3);
+      seed_finish(&w, &N_out[t], &D_out[t], &EF_out[t]);
+    }
+    scratch_free(&w);
+    free(mark_z);
+  }
+  return status;
+}
+
+/* H_s for j = 3 events, as oracle_histogram. */
+int64_t oracle_histogram3(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                          int32_t s, int64_t *deg_out, int64_t *count_out, int64_t cap) {
+  if (n <= 0 || s < 0 || s >= n || !row_ptr) return -1;
+  scratch_t w;
+  int64_t *mark_z = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n + 1));
+  if (!mark_z || scratch_init(&w, n, 4 * (int64_t)max_degree(n, row_ptr)) != ORACLE_OK) {
+    scratch_free(&w);
+    free(mark_z);
+    return -1;
+  }
+  for (int32_t i = 0; i <= n; ++i) mark_z[i] = -1;
+  int64_t stamp2 = 0, stamp3 = 0;
+  seed_histogram3(s, row_ptr, col_idx, &w, mark_z, &stamp2, &stamp3);
+  qsort(w.touched, (size_t)w.n_touched, sizeof(int32_t), cmp_i32);
+  const int64_t m = w.n_touched;
+  for (int64_t t = 0; t < m && t < cap; ++t) {
+    deg_out[t] = w.touched[t];
+    count_out[t] = w.hist[w.touched[t]];
+  }
+  scratch_free(&w);
+  free(mark_z);
+  return m;
+}
+
+/*
  * EF of the seeds `seeds[0..n_seeds)` (all nodes 0..n-1 when seeds == NULL,
  * then n_seeds is ignored). Outputs are position-aligned with the seed list.
  * The CSR must describe a simple undirected graph with sorted rows; it is not
