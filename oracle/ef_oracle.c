@@ -186,7 +186,8 @@ static void seed_histogram3(int32_t s, const int32_t *row_ptr, const int32_t *co
       const int32_t x2 = pass == 0 ? s : y;
       for (int32_t e2 = row_ptr[x2]; e2 < row_ptr[x2 + 1]; ++e2) {
         const int32_t z = col_idx[e2];
-        if (z == s || z == y) continue;
+        const int z_infected = z == s || z == y; /* z must be susceptible */
+        if (z_infected) continue;
         const int32_t z0 = row_ptr[z], z1 = row_ptr[z + 1];
         const int64_t kz = z1 - z0;
         const int64_t st3 = (*stamp3)++;

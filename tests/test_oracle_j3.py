@@ -13,6 +13,10 @@ The oracle enumerates event sequences one by one. It is checked against
 """
 import itertools
 import math
+import os
+import shutil
+import subprocess
+import tempfile
 
 import numpy as np
 import pytest
@@ -106,3 +110,81 @@ def test_brute_force_node_orderings(seed):
     adj = [set(ci[rp[v]:rp[v + 1]].tolist()) for v in range(n)]
     for s in range(n):
         assert oracle.histogram(rp, ci, s, j=3) == brute_histogram3(n, adj, s), (seed, s)
+
+
+# Plausible mistakes in the j = 3 enumeration, each of which the pins above
+# must catch (run on a rebuilt copy of the oracle).
+MUTANTS = {
+    "no_third_node_adjacency": ("(mark_z[v] == st3 ? 1 : 0)", "0"),
+    "no_second_node_edge_to_y": (
+        "const int64_t in3 = 1 + (w->mark_s[z] == s ? 1 : 0) + (w->mark_y[z] == st ? 1 : 0);",
+        "const int64_t in3 = 1 + (w->mark_s[z] == s ? 1 : 0);"),
+    "third_event_may_reinfect_z": ("if (v == s || v == y || v == z) continue;",
+                                   "if (v == s || v == y) continue;"),
+    "no_third_event_from_z": ("for (int t = 0; t < 3; ++t) {", "for (int t = 0; t < 2; ++t) {"),
+}
+
+
+def _quick_suite3(lib_path):
+    import ctypes
+    lib = ctypes.CDLL(lib_path)
+    vp = ctypes.c_void_p
+    lib.oracle_ef3.argtypes = [ctypes.c_int32, vp, vp, vp, ctypes.c_int32, vp, vp, vp,
+                               ctypes.c_int32]
+    lib.oracle_histogram3.argtypes = [ctypes.c_int32, vp, vp, ctypes.c_int32, vp, vp,
+                                      ctypes.c_int64]
+    lib.oracle_histogram3.restype = ctypes.c_int64
+    for pin in PINS:
+        src, dst = efref.pin_graph(pin)
+        rp, ci = gen.from_edges(pin["n"], src, dst)
+        n = rp.size - 1
+        N = np.zeros(n, np.int64)
+        D = np.zeros(n, np.int64)
+        E = np.zeros(n, np.float64)
+        lib.oracle_ef3(n, rp.ctypes.data, ci.ctypes.data, None, n, N.ctypes.data, D.ctypes.data,
+                       E.ctypes.data, 1)
+        s = pin["node"]
+        if (int(N[s]), int(D[s])) != (pin["N"], pin["D"]):
+            return False
+        if abs(E[s] - efref.eval_pin_expr(pin["expr"])) > 1e-12 * max(1.0, abs(E[s])):
+            return False
+    for seed in range(2):
+        rng = np.random.default_rng(seed)
+        n = 8
+        pairs = [(a, b) for a, b in itertools.combinations(range(n), 2) if rng.random() < 0.45]
+        src, dst = (np.array(x, np.int32) for x in zip(*pairs))
+        rp, ci = gen.from_edges(n, src, dst)
+        adj = [set(ci[rp[v]:rp[v + 1]].tolist()) for v in range(n)]
+        for s in range(n):
+            d = np.zeros(256, np.int64)
+            c = np.zeros(256, np.int64)
+            m = lib.oracle_histogram3(n, rp.ctypes.data, ci.ctypes.data, s, d.ctypes.data,
+                                      c.ctypes.data, 256)
+            got = {int(a): int(b) for a, b in zip(d[:m], c[:m])}
+            if got != brute_histogram3(n, adj, s):
+                return False
+    return True
+
+
+def test_unmutated_oracle_passes_quick_suite3():
+    oracle._load()
+    assert _quick_suite3(oracle.LIB_PATH)
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_planted_mistakes_are_caught3(name):
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    old, new = MUTANTS[name]
+    with open(oracle.SRC_PATH) as f:
+        src = f.read()
+    assert src.count(old) == 1, f"mutation site for {name} not found exactly once"
+    src = src.replace(old, new)
+    with tempfile.TemporaryDirectory() as td:
+        c = os.path.join(td, "m.c")
+        so = os.path.join(td, "m.so")
+        with open(c, "w") as f:
+            f.write(src)
+        subprocess.run(["gcc", "-O1", "-std=c11", "-fPIC", "-shared", "-fopenmp", c, "-lm",
+                        "-o", so], check=True)
+        assert not _quick_suite3(so), f"mutant {name} survived the pins"
