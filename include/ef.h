@@ -167,6 +167,26 @@ ef_status ef_compute(ef_graph *g, ef_algo algo, ef_prec prec, const int32_t *see
                      int32_t n_seeds, double *ef, int64_t *D, int64_t *N, uint32_t flags,
                      void *hip_stream);
 
+/* Expected Force with three transmission events: Sec. 3.3 defines EF for a
+ * number j of events and evaluates j = 2 (ef_compute); this is j = 3. Every
+ * ordered sequence of three events from the seed counts once, as Algorithm 1
+ * counts the two-event sequences: event 1 s -> y, event 2 from s or y, event
+ * 3 from s, y or the second node, each to a susceptible neighbour of its
+ * infector. The cluster degree is the number of edges leaving the four
+ * infected nodes; N, D and EF then follow Eq. 1 as for j = 2 (EF = +0.0 when
+ * D = 0 or N <= 1). N(s) equals the two-event D(s).
+ * Arguments, outputs, seeds, duplicates and flags (EF_OUT_DEVICE,
+ * EF_PROFILE) as ef_compute; ef_stats reports the item, finalize and FP64
+ * recompute times (t_stream_ms, t_finalize_ms, t_pass2_ms) and the number of
+ * recomputed seeds (promoted). FP32C scores in FP32 and sums in double; a
+ * seed whose EF cancels (kappa = (S/D)/EF > 16 or EF <= 0) is recomputed in
+ * FP64. The work is the number of sequences, about k_s^3 for a seed of
+ * degree k_s: intended for graphs of moderate degree. EF_ERR_OVERFLOW when a
+ * requested seed's sums could exceed int64. Synchronises the stream in FP32C
+ * mode (the recompute list is built on the host). */
+ef_status ef_compute_j3(ef_graph *g, ef_prec prec, const int32_t *seeds, int32_t n_seeds,
+                        double *ef, int64_t *D, int64_t *N, uint32_t flags, void *hip_stream);
+
 /* The k nodes of largest EF ("key nodes", the paper's title and Sec. 1):
  * computes EF of all nodes with `algo` / `prec`, then writes nodes[0..k) and
  * (nullable) ef[0..k) in EF-descending order, ties by node id ascending.

@@ -214,7 +214,7 @@ ef_status ef_graph_free(ef_graph *h) {
     (void)hipFree(g.col_idx);
   }
   void *arrays[] = {g.deg, g.src, g.rev, g.adj2, g.asum, g.qa, g.up_ptr, g.up_col, g.trec,
-                    g.up_deg, g.dn_ptr, g.dn, g.tri_zero,
+                    g.up_deg, g.dn_ptr, g.dn, g.tri_zero, g.j3_seeds, g.j3_off,
                     g.tri_rec0, g.tri_list[0], g.tri_list[1], g.tri_list[2], g.tri_list[3],
                     g.fin_list,
                     g.ps_list[0], g.ps_list[1], g.ps_list[2], g.ps_list[3], g.ps_list[4],
@@ -550,7 +550,7 @@ namespace efi {
 // workspace slots
 enum {
   WS_R = 0, WS_REC, WS_Y, WS_Z, WS_ZT, WS_FLAG, WS_BINS, WS_OUT, WS_BITMAP,
-  WS_SEEDS, WS_UOUT, WS_TOPK, WS_SURR
+  WS_SEEDS, WS_UOUT, WS_TOPK, WS_SURR, WS_J3, WS_J3P
 };
 
 // scratch for other translation units (kept in the handle, grow-only)
@@ -926,6 +926,259 @@ extern "C" ef_status ef_compute(ef_graph *h, ef_algo algo, ef_prec prec, const i
     }
     g.stats.t_pass2_ms = prof.ms(7, 8);
     g.stats.t_total_ms = prof.ms(0, 8);
+  }
+  return EF_OK;
+}
+
+extern "C" ef_status ef_compute_j3(ef_graph *h, ef_prec prec, const int32_t *seeds,
+                                   int32_t n_seeds, double *ef, int64_t *D, int64_t *N,
+                                   uint32_t flags, void *hip_stream) {
+  if (!h || !ef) {
+    set_error("ef_compute_j3: null handle or output");
+    return EF_ERR_ARG;
+  }
+  if (prec != EF_PREC_FP64 && prec != EF_PREC_FP32C) {
+    set_error("ef_compute_j3: bad precision");
+    return EF_ERR_ARG;
+  }
+  if (flags & ~(EF_OUT_DEVICE | EF_PROFILE)) {
+    set_error("ef_compute_j3: unknown flags 0x%x", flags);
+    return EF_ERR_ARG;
+  }
+  Graph &g = h->g;
+  if (seeds && n_seeds < 0) {
+    set_error("ef_compute_j3: negative n_seeds");
+    return EF_ERR_ARG;
+  }
+  if (seeds && n_seeds == 0) return EF_OK;
+  if (seeds)
+    for (int32_t i = 0; i < n_seeds; ++i)
+      if (seeds[i] < 0 || seeds[i] >= g.n) {
+        set_error("ef_compute_j3: seed %d at position %d out of range [0, %d)", seeds[i], i,
+                  g.n);
+        return EF_ERR_RANGE;
+      }
+  if (!seeds && g.n == 0) return EF_OK;
+  hipStream_t st = (hipStream_t)hip_stream;
+  const bool out_dev = (flags & EF_OUT_DEVICE) != 0;
+  Prof prof(g, (flags & EF_PROFILE) != 0, st);
+  ef_status s = prof.init();
+  if (s != EF_OK) return s;
+  g.stats = ef_run_stats{};
+  hipError_t e = hipSuccess;
+
+  // host copies of the per-node sums (work estimates and the int64 bound)
+  if (g.h_asum.empty() && g.n > 0) {
+    g.h_asum.resize((size_t)g.n);
+    e = hipMemcpy(g.h_asum.data(), g.asum, sizeof(int64_t) * (size_t)g.n, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      g.h_asum.clear();
+      return hip_status(e, "copy neighbour-degree sums");
+    }
+  }
+  if (g.h_qa.empty() && g.n > 0) {
+    g.h_qa.resize((size_t)g.n);
+    e = hipMemcpy(g.h_qa.data(), g.qa, sizeof(longlong2) * (size_t)g.n, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      g.h_qa.clear();
+      return hip_status(e, "copy neighbour-degree moments");
+    }
+  }
+  // N_3(s) is the two-event degree sum D_2(s), at most its triangle-free
+  // closed form; every cluster degree is below k_s + 3 k_max
+  auto n3_bound = [&](int32_t v) {
+    const double k = g.h_deg[v], A = (double)g.h_asum[v];
+    const double Q = (double)g.h_qa[v].x, A2 = (double)g.h_qa[v].y;
+    return std::max(0.0, k * (k - 4) * (k - 2) + (3 * k - 7) * A + Q + A2 - k * k);
+  };
+  const bool all = seeds == nullptr;
+  std::vector<int32_t> useeds, inv;
+  if (!all) {
+    useeds.assign(seeds, seeds + n_seeds);
+    std::sort(useeds.begin(), useeds.end());
+    useeds.erase(std::unique(useeds.begin(), useeds.end()), useeds.end());
+    inv.resize((size_t)n_seeds);
+    for (int32_t i = 0; i < n_seeds; ++i)
+      inv[i] = (int32_t)(std::lower_bound(useeds.begin(), useeds.end(), seeds[i]) - useeds.begin());
+  }
+  const int32_t n_work = all ? g.n : (int32_t)useeds.size();
+  const double dmax = (double)g.info.max_degree;
+  for (int32_t i = 0; i < n_work; ++i) {
+    const int32_t v = all ? i : useeds[i];
+    if (n3_bound(v) * ((double)g.h_deg[v] + 3 * dmax) > 4.0e18) {
+      set_error("ef_compute_j3: the sums of seed %d (degree %d) could exceed int64", v,
+                g.h_deg[v]);
+      return EF_ERR_OVERFLOW;
+    }
+  }
+  // items: the arcs of the seeds, largest seeds first
+  auto order_of = [&](std::vector<int32_t> &ord, std::vector<int64_t> &off) {
+    std::sort(ord.begin(), ord.end(), [&](int32_t a, int32_t c) {
+      const double wa = n3_bound(a), wc = n3_bound(c);
+      return wa != wc ? wa > wc : a < c;
+    });
+    off.assign(ord.size() + 1, 0);
+    for (size_t i = 0; i < ord.size(); ++i) off[i + 1] = off[i] + g.h_deg[ord[i]];
+  };
+  const int64_t nnz = std::max<int64_t>(g.nnz, 1);
+  if ((s = ws_ensure(g, WS_J3P, (2 * sizeof(long long) + sizeof(double)) * (size_t)nnz,
+                     "per-arc partial sums")) != EF_OK)
+    return s;
+  long long *PN = (long long *)g.ws[WS_J3P].p, *PD = PN + nnz;
+  double *PS = (double *)(PD + nnz);
+  const int32_t *d_ord = nullptr;
+  const int64_t *d_off = nullptr;
+  int64_t n_items = 0;
+  int32_t *d_useeds = nullptr;
+  if (all) {
+    if (!g.j3_seeds) {
+      std::vector<int32_t> ord((size_t)g.n);
+      std::iota(ord.begin(), ord.end(), 0);
+      std::vector<int64_t> off;
+      order_of(ord, off);
+      if ((s = dev_alloc(g, (void **)&g.j3_seeds, sizeof(int32_t) * ord.size(), "j3 order")) !=
+          EF_OK)
+        return s;
+      if ((s = dev_alloc(g, (void **)&g.j3_off, sizeof(int64_t) * off.size(), "j3 offsets")) !=
+          EF_OK)
+        return s;
+      e = hipMemcpy(g.j3_seeds, ord.data(), sizeof(int32_t) * ord.size(), hipMemcpyHostToDevice);
+      if (e == hipSuccess)
+        e = hipMemcpy(g.j3_off, off.data(), sizeof(int64_t) * off.size(), hipMemcpyHostToDevice);
+      if (e != hipSuccess) return hip_status(e, "upload j3 order");
+    }
+    d_ord = g.j3_seeds;
+    d_off = g.j3_off;
+    n_items = g.nnz;
+  } else {
+    std::vector<int32_t> ord(useeds);
+    std::vector<int64_t> off;
+    order_of(ord, off);
+    n_items = off.back();
+    const size_t bytes = sizeof(int64_t) * off.size() + sizeof(int32_t) * (2 * useeds.size()) + 64;
+    if ((s = ws_ensure(g, WS_J3, bytes, "j3 seed lists")) != EF_OK) return s;
+    int64_t *po = (int64_t *)g.ws[WS_J3].p;
+    int32_t *pord = (int32_t *)(po + off.size());
+    d_useeds = pord + ord.size();
+    e = hipMemcpyAsync(po, off.data(), sizeof(int64_t) * off.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(pord, ord.data(), sizeof(int32_t) * ord.size(), hipMemcpyHostToDevice,
+                         st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(d_useeds, useeds.data(), sizeof(int32_t) * useeds.size(),
+                         hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_status(e, "upload seeds");
+    d_ord = pord;
+    d_off = po;
+  }
+  // outputs of the unique work list (staging unless they can go straight to
+  // the caller's device arrays) and flag bytes
+  const size_t out_bytes = (sizeof(double) + 2 * sizeof(int64_t)) * (size_t)std::max(n_work, 1);
+  if ((s = ws_ensure(g, WS_UOUT, out_bytes, "output staging")) != EF_OK) return s;
+  if ((s = ws_ensure(g, WS_FLAG, (sizeof(int32_t) + 1) * (size_t)std::max(n_work, 1),
+                     "flag list")) != EF_OK)
+    return s;
+  double *ef_w = (double *)g.ws[WS_UOUT].p;
+  int64_t *D_w = (int64_t *)(ef_w + std::max(n_work, 1)), *N_w = D_w + std::max(n_work, 1);
+  if (all && out_dev) {
+    ef_w = ef;
+    if (D) D_w = D;
+    if (N) N_w = N;
+  }
+  int32_t *fpos = (int32_t *)g.ws[WS_FLAG].p;
+  uint8_t *fl = (uint8_t *)(fpos + std::max(n_work, 1));
+  const bool fp64 = prec == EF_PREC_FP64;
+  prof.mark(0);
+  e = launch_j3_items(g, fp64, d_ord, d_off, n_work, n_items, PN, PD, PS, st);
+  if (e != hipSuccess) return hip_status(e, "three-event items");
+  prof.mark(1);
+  e = launch_j3_finish(g, fp64, PN, PD, PS, d_useeds, nullptr, n_work, ef_w, D_w, N_w,
+                       fp64 ? nullptr : fl, st);
+  if (e != hipSuccess) return hip_status(e, "three-event finalize");
+  prof.mark(2);
+  int32_t n_flag = 0;
+  if (!fp64) {
+    // seeds whose FP32 EF cancels: their items again in FP64
+    std::vector<uint8_t> hf((size_t)n_work);
+    e = hipMemcpyAsync(hf.data(), fl, (size_t)n_work, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_status(e, "read flags");
+    std::vector<int32_t> fpos_h, ford;
+    for (int32_t i = 0; i < n_work; ++i)
+      if (hf[i]) {
+        fpos_h.push_back(i);
+        ford.push_back(all ? i : useeds[i]);
+      }
+    n_flag = (int32_t)fpos_h.size();
+    if (n_flag > 0) {
+      std::vector<int64_t> foff;
+      order_of(ford, foff);
+      const size_t bytes = sizeof(int64_t) * foff.size() + sizeof(int32_t) * ford.size() + 64;
+      if ((s = ws_ensure(g, WS_SEEDS, bytes, "promoted seeds")) != EF_OK) return s;
+      int64_t *po = (int64_t *)g.ws[WS_SEEDS].p;
+      int32_t *pord = (int32_t *)(po + foff.size());
+      e = hipMemcpyAsync(po, foff.data(), sizeof(int64_t) * foff.size(), hipMemcpyHostToDevice,
+                         st);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(pord, ford.data(), sizeof(int32_t) * ford.size(),
+                           hipMemcpyHostToDevice, st);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(fpos, fpos_h.data(), sizeof(int32_t) * fpos_h.size(),
+                           hipMemcpyHostToDevice, st);
+      if (e == hipSuccess)
+        e = launch_j3_items(g, true, pord, po, n_flag, foff.back(), PN, PD, PS, st);
+      if (e == hipSuccess)
+        e = launch_j3_finish(g, true, PN, PD, PS, d_useeds, fpos, n_flag, ef_w, D_w, N_w,
+                             nullptr, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) return hip_status(e, "three-event FP64 recompute");
+    }
+  }
+  prof.mark(3);
+  // deliver outputs
+  if (!all) {
+    if (out_dev) {
+      if ((s = ws_ensure(g, WS_SEEDS, sizeof(int32_t) * inv.size() + 64, "inverse map")) != EF_OK)
+        return s;
+      int32_t *d_inv = (int32_t *)g.ws[WS_SEEDS].p;
+      e = hipMemcpyAsync(d_inv, inv.data(), sizeof(int32_t) * inv.size(), hipMemcpyHostToDevice,
+                         st);
+      if (e == hipSuccess) e = launch_gather_outputs(d_inv, n_seeds, ef_w, D_w, N_w, ef, D, N, st);
+      if (e != hipSuccess) return hip_status(e, "scatter outputs");
+    } else {
+      std::vector<double> hef((size_t)n_work);
+      std::vector<int64_t> hD((size_t)n_work), hN((size_t)n_work);
+      e = hipMemcpyAsync(hef.data(), ef_w, sizeof(double) * n_work, hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(hD.data(), D_w, sizeof(int64_t) * n_work, hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(hN.data(), N_w, sizeof(int64_t) * n_work, hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) return hip_status(e, "copy outputs");
+      for (int32_t i = 0; i < n_seeds; ++i) {
+        ef[i] = hef[inv[i]];
+        if (D) D[i] = hD[inv[i]];
+        if (N) N[i] = hN[inv[i]];
+      }
+    }
+  } else if (!out_dev) {
+    e = hipMemcpyAsync(ef, ef_w, sizeof(double) * (size_t)g.n, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && D)
+      e = hipMemcpyAsync(D, D_w, sizeof(int64_t) * (size_t)g.n, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && N)
+      e = hipMemcpyAsync(N, N_w, sizeof(int64_t) * (size_t)g.n, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_status(e, "copy outputs");
+  }
+  g.stats.seeds = n_work;
+  g.stats.promoted = n_flag;
+  if (prof.on) {
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_status(e, "profile");
+    g.stats.t_stream_ms = prof.ms(0, 1);
+    g.stats.t_finalize_ms = prof.ms(1, 2);
+    g.stats.t_pass2_ms = prof.ms(2, 3);
+    g.stats.t_total_ms = prof.ms(0, 3);
   }
   return EF_OK;
 }

@@ -151,6 +151,11 @@ struct Graph {
   int64_t n_ps[kSeedBins] = {0, 0, 0, 0, 0};
   bool ps_ready = false;
   std::vector<int64_t> h_asum;  // host copy of asum (built on first per-seed use)
+  std::vector<longlong2> h_qa;  // host copy of qa (built on first three-event use)
+  // three-event EF over all nodes: seeds by work, descending, and their item
+  // offsets (device, built on first use)
+  int32_t *j3_seeds = nullptr;
+  int64_t *j3_off = nullptr;
   int64_t n_tri[4] = {0, 0, 0, 0};
   // bin counts for the all-nodes centre set
   int64_t all_small = 0, all_mid = 0, all_big = 0, all_tiles = 0;
@@ -256,6 +261,19 @@ hipError_t launch_per_seed(const Graph &g, ef_prec prec, const int32_t *seeds,
                            const int32_t *const *lists, const int64_t *counts, const void *R,
                            uint32_t *bitmaps, double *ef, int64_t *D, int64_t *N, uint8_t *fl,
                            hipStream_t st, hipEvent_t ev_stream_done);
+
+// Expected Force with three transmission events (j3.hip): items are the arcs
+// of seeds[0 .. nseeds), seed i owning items off[i] .. off[i+1]; per-arc
+// partial sums in PN / PD / PS.
+hipError_t launch_j3_items(const Graph &g, bool fp64, const int32_t *seeds, const int64_t *off,
+                           int32_t nseeds, int64_t n_items, long long *PN, long long *PD,
+                           double *PS, hipStream_t st);
+// N, D, EF of output positions (all of 0 .. count-1, or the count listed in
+// pos), node nodes[i] (i when null); FP32C sets fl[i] = 1 where EF cancels.
+hipError_t launch_j3_finish(const Graph &g, bool fp64, const long long *PN, const long long *PD,
+                            const double *PS, const int32_t *nodes, const int32_t *pos,
+                            int32_t count, double *ef, int64_t *D, int64_t *N, uint8_t *fl,
+                            hipStream_t st);
 
 // FP32C pass 2: recompute EF of flagged positions from non-negative terms.
 // seeds[pos] gives the node of output position pos (NULL: pos is the node).

@@ -33,7 +33,8 @@ EF_PROFILE = 0x8
 # every entry point declared in include/ef.h
 EXPORTS = [
     "ef_last_error", "ef_version", "ef_device_count", "ef_validate_csr", "ef_graph_load_csr",
-    "ef_graph_from_edges", "ef_graph_free", "ef_graph_info_get", "ef_compute", "ef_topk",
+    "ef_graph_from_edges", "ef_graph_free", "ef_graph_info_get", "ef_compute", "ef_compute_j3",
+    "ef_topk",
     "ef_stats", "ef_batch_create", "ef_batch_autotune", "ef_batch_compute",
     "ef_batch_stats_get", "ef_batch_free", "ef_surrogate_create", "ef_surrogate_free",
     "ef_surrogate_get_params", "ef_surrogate_set_params", "ef_surrogate_save",
@@ -147,6 +148,7 @@ def lib():
     L.ef_graph_free.argtypes = [vp]
     L.ef_graph_info_get.argtypes = [vp, ctypes.POINTER(GraphInfo)]
     L.ef_compute.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, i32, vp, vp, vp, u32, vp]
+    L.ef_compute_j3.argtypes = [vp, ctypes.c_int, vp, i32, vp, vp, vp, u32, vp]
     L.ef_stats.argtypes = [vp, ctypes.POINTER(RunStats)]
     L.ef_topk.argtypes = [vp, ctypes.c_int, ctypes.c_int, i32, vp, vp, u32, vp]
     L.ef_batch_create.argtypes = [i32, vp, i64, vp, vp, u32, vp, ctypes.POINTER(vp)]
@@ -260,14 +262,25 @@ class Graph:
         return st.as_dict()
 
     def compute(self, algo: str = "cluster", prec: str = "fp32c", seeds=None,
-                out=None, profile: bool = False, stream=None):
-        """EF (and exact D, N) of all nodes or of `seeds`.
+                out=None, profile: bool = False, stream=None, j: int = 2):
+        """EF (and exact D, N) of all nodes or of `seeds`, for j = 2 (the
+        paper's setting; `algo` picks the formulation) or j = 3 transmission
+        events (ef_compute_j3; `algo` is not used).
 
         Host mode (out=None): returns numpy (ef float64, D int64, N int64).
         Device mode: `out` = (ef, D, N) torch CUDA tensors (D, N may be None);
         the call is asynchronous on `stream` (default: torch's current stream).
         """
+        if j not in (2, 3):
+            raise ValueError("j must be 2 or 3")
         flags = EF_PROFILE if profile else 0
+
+        def call(p_ef, p_D, p_N, fl):
+            if j == 3:
+                return lib().ef_compute_j3(self._h, PREC[prec], sp, ns, p_ef, p_D, p_N, fl,
+                                           _stream_ptr(stream))
+            return lib().ef_compute(self._h, ALGO[algo], PREC[prec], sp, ns, p_ef, p_D, p_N, fl,
+                                    _stream_ptr(stream))
         if seeds is not None:
             sd = np.ascontiguousarray(seeds, dtype=np.int32)
             ns = sd.size
@@ -279,15 +292,11 @@ class Graph:
             ef = np.zeros(max(count, 1), np.float64)
             D = np.zeros(max(count, 1), np.int64)
             N = np.zeros(max(count, 1), np.int64)
-            _check(lib().ef_compute(self._h, ALGO[algo], PREC[prec], sp, ns, ef.ctypes.data,
-                                    D.ctypes.data, N.ctypes.data, flags, _stream_ptr(stream)))
+            _check(call(ef.ctypes.data, D.ctypes.data, N.ctypes.data, flags))
             return ef[:count], D[:count], N[:count]
         ef, D, N = out
-        flags |= EF_OUT_DEVICE
-        _check(lib().ef_compute(self._h, ALGO[algo], PREC[prec], sp, ns, ef.data_ptr(),
-                                D.data_ptr() if D is not None else None,
-                                N.data_ptr() if N is not None else None, flags,
-                                _stream_ptr(stream)))
+        _check(call(ef.data_ptr(), D.data_ptr() if D is not None else None,
+                    N.data_ptr() if N is not None else None, flags | EF_OUT_DEVICE))
         return ef, D, N
 
     def topk(self, k: int, algo: str = "cluster", prec: str = "fp32c", out=None,
