@@ -87,6 +87,72 @@ def cpu_baseline(rp, ci, budget_s=15.0):
                       f"clusters/s = sequences/s / 4"}
 
 
+def bench_j3(steps, with_cpu):
+    """Expected Force with three transmission events (ef_compute_j3) on the
+    Barabasi-Albert graph n = 10^6, m = 5, all nodes, FP32C. The unit of work
+    is one event sequence (a cluster instance of Sec. 3.3 with j = 3); the
+    GPU reports their count as sum N."""
+    import numpy as np
+    import torch
+
+    from paper_2306_00606_amd import efgpu, gen
+
+    dev = torch.device("cuda:0")
+    log("three events: generating BA n = 1e6, m = 5")
+    rp, ci = gen.ba_1m()
+    n = rp.size - 1
+    g = efgpu.Graph(rp, ci, validate=False)
+    out = (torch.empty(n, dtype=torch.float64, device=dev),
+           torch.empty(n, dtype=torch.int64, device=dev),
+           torch.empty(n, dtype=torch.int64, device=dev))
+    g.compute(prec="fp32c", out=out, j=3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.compute(prec="fp32c", out=out, j=3)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    g.compute(prec="fp32c", out=out, j=3, profile=True)
+    st = g.stats()
+    seqs = float(out[2].sum().item())
+    log(f"three events: {ms:.1f} ms/step, {seqs:.3e} sequences")
+    achieved = seqs * OPS_PER_CLUSTER / (st["t_stream_ms"] * 1e-3)
+    rec = {"workload": "ba_1m_m5", "nodes": n, "arcs": int(ci.size), "precision": "fp32c",
+           "steps": steps, "ms_per_step": ms, "sequences": seqs,
+           "sequences_per_s": seqs / (ms * 1e-3),
+           "phases_ms": {"items": st["t_stream_ms"], "finalize": st["t_finalize_ms"],
+                         "fp64_recompute": st["t_pass2_ms"]},
+           "fp64_recomputed_seeds": int(st["promoted"]),
+           "roofline": {"bound": "alu", "kernel": "k_j3_items<float>",
+                        "achieved": achieved / 1e12, "peak": VALU_LANE_OPS_PEAK / 1e12,
+                        "unit": "TOP/s", "frac": achieved / VALU_LANE_OPS_PEAK,
+                        "ops_per_sequence": OPS_PER_CLUSTER,
+                        "avg_launch_ms": st["t_stream_ms"]}}
+    g.close()
+    if with_cpu:
+        import oracle
+        threads = max(1, min(os.cpu_count() or 1, 16))
+        N3 = out[2].cpu().numpy()
+        order = np.random.default_rng(7).permutation(np.flatnonzero(N3 > 0)).astype(np.int32)
+        done, total, t_used, chunk = 0, 0.0, 0.0, 64
+        while t_used < 10.0 and done < order.size:
+            seeds = order[done:done + chunk]
+            t1 = time.perf_counter()
+            oracle.ef(rp, ci, seeds=seeds, threads=threads, j=3)
+            dt = time.perf_counter() - t1
+            t_used += dt
+            total += float(N3[seeds].sum())
+            done += seeds.size
+            # grow the chunk only while a chunk stays well inside the budget
+            if dt < 1.0:
+                chunk = min(chunk * 2, 4096)
+        rec["cpu_baseline"] = {
+            "value": total / t_used, "unit": "sequences/s", "cores": threads, "kind": "oracle",
+            "sample": f"{done} seeds drawn uniformly from the nodes with sequences, "
+                      f"{total:.3e} sequences in {t_used:.1f} s on {threads} threads"}
+    return rec
+
+
 def bench_batch(steps):
     """Config of 512 uneven graphs in one replayed HIP graph vs separate calls."""
     import numpy as np
@@ -180,6 +246,8 @@ def main():
                     help="also time the degree-class aggregated variant (0 = skip)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-graph batch")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate")
+    ap.add_argument("--j3-steps", type=int, default=2,
+                    help="also time EF with three transmission events (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -295,6 +363,7 @@ def main():
 
     batch = None if args.no_batch else bench_batch(max(3, args.steps))
     sur = None if args.no_surrogate else bench_surrogate()
+    j3 = None if args.j3_steps <= 0 else bench_j3(args.j3_steps, not args.no_cpu_baseline)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -329,6 +398,7 @@ def main():
         "hbm": hbm,
         "batch": batch,
         "surrogate": sur,
+        "three_events": j3,
         "cpu_baseline": cpu,
     }
     g.close()
