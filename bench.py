@@ -143,9 +143,9 @@ def bench_j3(steps, with_cpu):
             t_used += dt
             total += float(N3[seeds].sum())
             done += seeds.size
-            # grow the chunk only while a chunk stays well inside the budget
-            if dt < 1.0:
-                chunk = min(chunk * 2, 4096)
+            # size the next chunk to about half of the budget left
+            rate = seeds.size / max(dt, 1e-3)
+            chunk = int(max(16, min(4096, 0.5 * rate * max(10.0 - t_used, 0.0))))
         rec["cpu_baseline"] = {
             "value": total / t_used, "unit": "sequences/s", "cores": threads, "kind": "oracle",
             "sample": f"{done} seeds drawn uniformly from the nodes with sequences, "
