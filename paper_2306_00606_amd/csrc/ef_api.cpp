@@ -550,7 +550,7 @@ namespace efi {
 // workspace slots
 enum {
   WS_R = 0, WS_REC, WS_Y, WS_Z, WS_ZT, WS_FLAG, WS_BINS, WS_OUT, WS_BITMAP,
-  WS_SEEDS, WS_UOUT, WS_TOPK, WS_SURR, WS_J3, WS_J3P
+  WS_SEEDS, WS_UOUT, WS_TOPK, WS_SURR, WS_J3, WS_J3P, WS_J3L
 };
 
 // scratch for other translation units (kept in the handle, grow-only)
@@ -1087,9 +1087,16 @@ extern "C" ef_status ef_compute_j3(ef_graph *h, ef_prec prec, const int32_t *see
   }
   int32_t *fpos = (int32_t *)g.ws[WS_FLAG].p;
   uint8_t *fl = (uint8_t *)(fpos + std::max(n_work, 1));
+  // per-bin item lists and their counts
+  if ((s = ws_ensure(g, WS_J3L, sizeof(int32_t) * (5 * (size_t)std::max<int64_t>(n_items, 1) + 8),
+                     "item lists")) != EF_OK)
+    return s;
+  int32_t *j3_lists = (int32_t *)g.ws[WS_J3L].p;
+  int32_t *j3_counts = j3_lists + 5 * std::max<int64_t>(n_items, 1);
   const bool fp64 = prec == EF_PREC_FP64;
   prof.mark(0);
-  e = launch_j3_items(g, fp64, d_ord, d_off, n_work, n_items, PN, PD, PS, st);
+  e = launch_j3_items(g, fp64, d_ord, d_off, n_work, n_items, j3_lists, j3_counts, PN, PD, PS,
+                      st);
   if (e != hipSuccess) return hip_status(e, "three-event items");
   prof.mark(1);
   e = launch_j3_finish(g, fp64, PN, PD, PS, d_useeds, nullptr, n_work, ef_w, D_w, N_w,
@@ -1126,7 +1133,8 @@ extern "C" ef_status ef_compute_j3(ef_graph *h, ef_prec prec, const int32_t *see
         e = hipMemcpyAsync(fpos, fpos_h.data(), sizeof(int32_t) * fpos_h.size(),
                            hipMemcpyHostToDevice, st);
       if (e == hipSuccess)
-        e = launch_j3_items(g, true, pord, po, n_flag, foff.back(), PN, PD, PS, st);
+        e = launch_j3_items(g, true, pord, po, n_flag, foff.back(), j3_lists, j3_counts, PN, PD,
+                            PS, st);
       if (e == hipSuccess)
         e = launch_j3_finish(g, true, PN, PD, PS, d_useeds, fpos, n_flag, ef_w, D_w, N_w,
                              nullptr, st);

@@ -264,10 +264,10 @@ hipError_t launch_per_seed(const Graph &g, ef_prec prec, const int32_t *seeds,
 
 // Expected Force with three transmission events (j3.hip): items are the arcs
 // of seeds[0 .. nseeds), seed i owning items off[i] .. off[i+1]; per-arc
-// partial sums in PN / PD / PS.
+// partial sums in PN / PD / PS. lists: 5 * n_items ints of scratch, counts: 5.
 hipError_t launch_j3_items(const Graph &g, bool fp64, const int32_t *seeds, const int64_t *off,
-                           int32_t nseeds, int64_t n_items, long long *PN, long long *PD,
-                           double *PS, hipStream_t st);
+                           int32_t nseeds, int64_t n_items, int32_t *lists, int32_t *counts,
+                           long long *PN, long long *PD, double *PS, hipStream_t st);
 // N, D, EF of output positions (all of 0 .. count-1, or the count listed in
 // pos), node nodes[i] (i when null); FP32C sets fl[i] = 1 where EF cancels.
 hipError_t launch_j3_finish(const Graph &g, bool fp64, const long long *PN, const long long *PD,

@@ -167,3 +167,32 @@ def test_edge_cases_j3():
         with pytest.raises(efgpu.EFError) as ei:
             g.compute(j=3)
         assert ei.value.name == "EF_ERR_OVERFLOW"
+
+
+def two_hub_graph():
+    """Hubs 0 and 1 (adjacent, 4200 leaves each, some leaves of 1 also joined
+    to 0, and 100 leaf-leaf edges across): the first events 0 -> 1 and
+    1 -> 0 have lists longer than 8192 (merge path), the leaves' first events
+    lists of about 4200 (the largest union bin)."""
+    L = 4200
+    src = [0] + [0] * L + [1] * L + [0] * 50
+    dst = [1] + list(range(2, 2 + L)) + list(range(2 + L, 2 + 2 * L)) + list(range(2 + L, 52 + L))
+    src += list(range(2, 102))
+    dst += list(range(2 + L, 102 + L))
+    return gen.from_edges(2 + 2 * L, np.array(src, np.int32), np.array(dst, np.int32))
+
+
+def test_two_hubs_merge_path_j3():
+    rp, ci = two_hub_graph()
+    with efgpu.Graph(rp, ci) as g:
+        e32, D32, N32 = g.compute(prec="fp32c", j=3)
+        e64, D64, N64 = g.compute(prec="fp64", j=3)
+        _, D2, _ = g.compute(algo="cluster", prec="fp64")
+    assert np.array_equal(N32, D2) and np.array_equal(N64, D2)
+    assert np.array_equal(D32, D64)
+    ok = e64 > 0
+    assert np.all(np.abs(e32[ok] - e64[ok]) <= 1e-5 * e64[ok]) and np.all(e32[~ok] == 0)
+    seeds = np.array([2, 3, 60, 150, 2 + 4200, 2 + 4200 + 10, 2 + 4200 + 120, 8401], np.int32)
+    oN, oD, oE = oracle.ef(rp, ci, seeds=seeds, threads=16, j=3)
+    assert_parity(e64[seeds], D64[seeds], N64[seeds], oN, oD, oE, "fp64", "two hubs")
+    assert_parity(e32[seeds], D32[seeds], N32[seeds], oN, oD, oE, "fp32c", "two hubs")
