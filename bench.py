@@ -90,8 +90,8 @@ def cpu_baseline(rp, ci, budget_s=15.0):
 def bench_j3(steps, with_cpu):
     """Expected Force with three transmission events (ef_compute_j3) on the
     Barabasi-Albert graph n = 10^6, m = 5, all nodes, FP32C. The unit of work
-    is one event sequence (a cluster instance of Sec. 3.3 with j = 3); the
-    GPU reports their count as sum N."""
+    is one event sequence (a cluster instance of Sec. 3.3 with j = 3); their
+    count is sum N."""
     import numpy as np
     import torch
 
@@ -116,18 +116,14 @@ def bench_j3(steps, with_cpu):
     st = g.stats()
     seqs = float(out[2].sum().item())
     log(f"three events: {ms:.1f} ms/step, {seqs:.3e} sequences")
-    achieved = seqs * OPS_PER_CLUSTER / (st["t_stream_ms"] * 1e-3)
+    # sequences are accounted for, not scored one by one (the M part of a
+    # first event is scored once per distinct d_T): an equivalent rate
     rec = {"workload": "ba_1m_m5", "nodes": n, "arcs": int(ci.size), "precision": "fp32c",
            "steps": steps, "ms_per_step": ms, "sequences": seqs,
-           "sequences_per_s": seqs / (ms * 1e-3),
+           "equivalent_sequences_per_s": seqs / (ms * 1e-3),
            "phases_ms": {"items": st["t_stream_ms"], "finalize": st["t_finalize_ms"],
                          "fp64_recompute": st["t_pass2_ms"]},
-           "fp64_recomputed_seeds": int(st["promoted"]),
-           "roofline": {"bound": "alu", "kernel": "k_j3_items<float>",
-                        "achieved": achieved / 1e12, "peak": VALU_LANE_OPS_PEAK / 1e12,
-                        "unit": "TOP/s", "frac": achieved / VALU_LANE_OPS_PEAK,
-                        "ops_per_sequence": OPS_PER_CLUSTER,
-                        "avg_launch_ms": st["t_stream_ms"]}}
+           "fp64_recomputed_seeds": int(st["promoted"])}
     g.close()
     if with_cpu:
         import oracle
