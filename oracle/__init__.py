@@ -12,7 +12,8 @@ leaving it), the histogram of those degrees and the entropy of Eq. 1 of
 "Scaling Expected Force" (Sec. 3.3), in double precision, with the
 multiplicities of Algorithm 1; and the same with three events (four-node
 clusters, the parameter j = 3 of Sec. 3.3). See ``ef_oracle.c`` for the exact
-statement.
+statement. ``sir_oracle.c`` simulates the SIR model of Sec. 3.1 and sums the
+empirical spreading power of Sec. 3.3.
 """
 from __future__ import annotations
 
@@ -29,10 +30,13 @@ SRC_PATH = os.path.join(_HERE, "ef_oracle.c")
 _lib = None
 
 
+SIR_SRC_PATH = os.path.join(_HERE, "sir_oracle.c")
+
+
 def build():
     tmp = LIB_PATH + ".tmp"
     subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", SRC_PATH,
-                    "-lm", "-o", tmp], check=True)
+                    SIR_SRC_PATH, "-lm", "-o", tmp], check=True)
     os.replace(tmp, LIB_PATH)
 
 
@@ -54,6 +58,12 @@ def _load():
     lib.oracle_ef3.restype = ctypes.c_int
     lib.oracle_histogram3.argtypes = lib.oracle_histogram.argtypes
     lib.oracle_histogram3.restype = ctypes.c_int64
+    lib.oracle_splitmix64.argtypes = [ctypes.c_uint64]
+    lib.oracle_splitmix64.restype = ctypes.c_uint64
+    lib.oracle_sir.argtypes = [ctypes.c_int32, vp, vp, ctypes.c_double, ctypes.c_double,
+                               ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp,
+                               vp, vp]
+    lib.oracle_sir.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -110,3 +120,32 @@ def histogram(row_ptr, col_idx, s: int, j: int = 2):
         if m <= cap:
             return {int(a): int(b) for a, b in zip(d[:m], c[:m])}
         cap = int(m)
+
+
+def splitmix64(z: int) -> int:
+    """SplitMix64's output function of a 64-bit counter (the oracle's copy)."""
+    return int(_load().oracle_splitmix64(ctypes.c_uint64(z & (2**64 - 1))))
+
+
+def sir(row_ptr, col_idx, beta: float, mu: float, seed: int, n_sims: int, t_max: int = 100000):
+    """SIR simulations (Sec. 3.1) and the spreading-power sums over the global
+    ones (Sec. 3.3); see sir_oracle.c. Returns a dict of numpy arrays."""
+    rp, ci = _csr(row_ptr, col_idx)
+    n = rp.size - 1
+    out = {"index": np.zeros(max(n_sims, 1), np.int32), "size": np.zeros(max(n_sims, 1), np.int32),
+           "t_end": np.zeros(max(n_sims, 1), np.int32),
+           "t_peak": np.zeros(max(n_sims, 1), np.int32),
+           "sp_sum": np.zeros((4, max(n, 1)), np.int64),
+           "inf_count": np.zeros(max(n, 1), np.int64)}
+    st = _load().oracle_sir(n, rp.ctypes.data, ci.ctypes.data, float(beta), float(mu),
+                            ctypes.c_uint64(seed & (2**64 - 1)), int(n_sims), int(t_max),
+                            out["index"].ctypes.data, out["size"].ctypes.data,
+                            out["t_end"].ctypes.data, out["t_peak"].ctypes.data,
+                            out["sp_sum"].ctypes.data, out["inf_count"].ctypes.data)
+    if st != 0:
+        raise RuntimeError(f"oracle_sir failed with status {st}")
+    for k in ("index", "size", "t_end", "t_peak"):
+        out[k] = out[k][:n_sims]
+    out["sp_sum"] = out["sp_sum"][:, :n]
+    out["inf_count"] = out["inf_count"][:n]
+    return out
