@@ -187,6 +187,26 @@ ef_status ef_compute(ef_graph *g, ef_algo algo, ef_prec prec, const int32_t *see
 ef_status ef_compute_j3(ef_graph *g, ef_prec prec, const int32_t *seeds, int32_t n_seeds,
                         double *ef, int64_t *D, int64_t *N, uint32_t flags, void *hip_stream);
 
+/* SIR outbreaks on the graph (Sec. 3.1) and the empirical spreading power of
+ * every node (Sec. 3.3), to check EF against simulated spreading. Discrete
+ * steps: every node infected at the start of a step infects each susceptible
+ * neighbour with probability beta (the smallest successful infector is the
+ * node's infector), then recovers with probability mu; an outbreak ends when
+ * no node is infected or after t_max steps. The paper's calibration is
+ * mu = 1/3, beta = 1.3 / (3 <k>). Every decision is a SplitMix64 draw on a
+ * counter of (seed, simulation, step, arc or node), so results are
+ * reproducible and independent of scheduling.
+ * Outputs (host memory): per simulation r < n_sims the index case, size
+ * (nodes ever infected), t_end (steps run) and t_peak (first step with the
+ * most infected nodes); over the global simulations (size >= n/4, rounded
+ * up): inf_count[v] = those in which v was infected, and sp_sum[(d-1) n + v]
+ * = the sum over them of v's descendants within d generations of the
+ * infection tree, d = 1..4 (divide by inf_count for the empirical spreading
+ * power of order d). Synchronises the stream after every step. */
+ef_status ef_sir(ef_graph *g, double beta, double mu, uint64_t seed, int32_t n_sims,
+                 int32_t t_max, int32_t *index, int32_t *size, int32_t *t_end, int32_t *t_peak,
+                 int64_t *sp_sum, int64_t *inf_count, void *hip_stream);
+
 /* The k nodes of largest EF ("key nodes", the paper's title and Sec. 1):
  * computes EF of all nodes with `algo` / `prec`, then writes nodes[0..k) and
  * (nullable) ef[0..k) in EF-descending order, ties by node id ascending.

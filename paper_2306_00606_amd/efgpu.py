@@ -39,7 +39,7 @@ EXPORTS = [
     "ef_batch_stats_get", "ef_batch_free", "ef_surrogate_create", "ef_surrogate_free",
     "ef_surrogate_get_params", "ef_surrogate_set_params", "ef_surrogate_save",
     "ef_surrogate_load", "ef_features", "ef_surrogate_gradients", "ef_surrogate_train",
-    "ef_surrogate_predict", "ef_topk_surrogate",
+    "ef_surrogate_predict", "ef_topk_surrogate", "ef_sir",
 ]
 
 N_FEATURES = 16
@@ -149,6 +149,8 @@ def lib():
     L.ef_graph_info_get.argtypes = [vp, ctypes.POINTER(GraphInfo)]
     L.ef_compute.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, i32, vp, vp, vp, u32, vp]
     L.ef_compute_j3.argtypes = [vp, ctypes.c_int, vp, i32, vp, vp, vp, u32, vp]
+    L.ef_sir.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_uint64, i32, i32, vp, vp,
+                         vp, vp, vp, vp, vp]
     L.ef_stats.argtypes = [vp, ctypes.POINTER(RunStats)]
     L.ef_topk.argtypes = [vp, ctypes.c_int, ctypes.c_int, i32, vp, vp, u32, vp]
     L.ef_batch_create.argtypes = [i32, vp, i64, vp, vp, u32, vp, ctypes.POINTER(vp)]
@@ -316,6 +318,28 @@ class Graph:
                              ef.data_ptr() if ef is not None else None, flags | EF_OUT_DEVICE,
                              _stream_ptr(stream)))
         return nodes, ef
+
+    def sir(self, beta: float, mu: float, seed: int, n_sims: int, t_max: int = 100000,
+            stream=None) -> dict:
+        """SIR outbreaks (ef_sir): per-simulation index, size, t_end, t_peak and,
+        over the global outbreaks, inf_count[v] and sp_sum[d-1, v] (d = 1..4)."""
+        n = self.n
+        out = {"index": np.zeros(max(n_sims, 1), np.int32),
+               "size": np.zeros(max(n_sims, 1), np.int32),
+               "t_end": np.zeros(max(n_sims, 1), np.int32),
+               "t_peak": np.zeros(max(n_sims, 1), np.int32),
+               "sp_sum": np.zeros((4, max(n, 1)), np.int64),
+               "inf_count": np.zeros(max(n, 1), np.int64)}
+        _check(lib().ef_sir(self._h, float(beta), float(mu), ctypes.c_uint64(seed & (2**64 - 1)),
+                            int(n_sims), int(t_max), out["index"].ctypes.data,
+                            out["size"].ctypes.data, out["t_end"].ctypes.data,
+                            out["t_peak"].ctypes.data, out["sp_sum"].ctypes.data,
+                            out["inf_count"].ctypes.data, _stream_ptr(stream)))
+        for k in ("index", "size", "t_end", "t_peak"):
+            out[k] = out[k][:n_sims]
+        out["sp_sum"] = out["sp_sum"][:, :n]
+        out["inf_count"] = out["inf_count"][:n]
+        return out
 
     def features(self):
         """Raw per-node features (n x 16, float32) and ln N (float32)."""
