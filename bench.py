@@ -19,7 +19,11 @@ beside it in the same line (they are not the headline value):
               disjoint union by a replayed HIP graph, against 512 separate calls;
   surrogate - the MLP surrogate trained on exact EF of generator graphs and
               evaluated on a held-out Barabasi-Albert graph (n = 4M, m = 8):
-              rank agreement with exact EF, and its speed against the exact path.
+              rank agreement with exact EF, and its speed against the exact path;
+  three_events - EF with three transmission events on Barabasi-Albert n = 1e6;
+  sir       - 100 SIR outbreaks on the same Barabasi-Albert graph at the paper's
+              calibration, and the correlation of exp(EF) with the measured
+              spreading power of orders 1-4.
 """
 import argparse
 import json
@@ -149,6 +153,73 @@ def bench_j3(steps, with_cpu):
     return rec
 
 
+def bench_sir(runs, with_cpu):
+    """SIR outbreaks (ef_sir) on the Barabasi-Albert graph n = 10^6, m = 5 at
+    the paper's calibration (beta = 1.3 / (3 <k>), mu = 1/3), 100 outbreaks from
+    uniform index cases, as in the spreading-power comparison of Sec. 3.3. The
+    empirical spreading power of order d of a node is its mean number of
+    descendants within d generations of the infection tree over the global
+    outbreaks (size >= n / 4) that infected it; reported with its Pearson
+    correlation with exp(EF) and with degree over the nodes that have one.
+    Throughput is counted in node-steps: every step of a simulation visits all
+    n nodes."""
+    import numpy as np
+    import torch
+
+    from paper_2306_00606_amd import efgpu, gen
+
+    sims, seed = 100, 2306
+    log("SIR: generating BA n = 1e6, m = 5")
+    rp, ci = gen.ba_1m()
+    n = rp.size - 1
+    kbar = ci.size / n
+    beta, mu = 1.3 / (3.0 * kbar), 1.0 / 3.0
+    g = efgpu.Graph(rp, ci, validate=False)
+    ef, _, _ = g.compute(prec="fp32c")
+    g.sir(beta, mu, seed, sims)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(runs):
+        o = g.sir(beta, mu, seed, sims)
+    ms = 1e3 * (time.perf_counter() - t0) / runs
+    g.close()
+    glob = o["size"] >= (n + 3) // 4
+    node_steps = float(n) * float(o["t_end"].sum())
+    have = o["inf_count"] > 0
+    deg = np.diff(rp).astype(np.float64)
+    x = np.exp(ef[have])
+    pe, pd = [], []
+    for d in range(4):
+        sp = o["sp_sum"][d][have] / o["inf_count"][have]
+        pe.append(float(np.corrcoef(x, sp)[0, 1]))
+        pd.append(float(np.corrcoef(deg[have], sp)[0, 1]))
+    idx_ef = ef[o["index"]]
+    rec = {"workload": "ba_1m_m5", "nodes": n, "arcs": int(ci.size), "beta": beta, "mu": mu,
+           "outbreaks": sims, "runs": runs, "ms_per_run": ms,
+           "outbreaks_per_s": sims / (ms * 1e-3), "node_steps_per_s": node_steps / (ms * 1e-3),
+           "global_outbreaks": int(glob.sum()), "mean_global_size": float(o["size"][glob].mean())
+           if glob.any() else None, "nodes_with_spreading_power": int(have.sum()),
+           "pearson_expEF_vs_sp_d1_4": pe, "pearson_degree_vs_sp_d1_4": pd,
+           "index_case_ef_mean_global": float(idx_ef[glob].mean()) if glob.any() else None,
+           "index_case_ef_mean_local": float(idx_ef[~glob].mean()) if (~glob).any() else None}
+    log(f"SIR: {ms:.1f} ms per {sims} outbreaks, {int(glob.sum())} global; "
+        f"Pearson exp(EF) {[round(v, 3) for v in pe]}, degree {[round(v, 3) for v in pd]}")
+    if with_cpu:
+        import oracle
+        done, steps_done, t_used = 0, 0.0, 0.0
+        while t_used < 10.0 and done < sims:
+            k = min(sims, max(done + 4, 2 * done))
+            t1 = time.perf_counter()
+            oc = oracle.sir(rp, ci, beta, mu, seed, k)
+            t_used = time.perf_counter() - t1
+            done, steps_done = k, float(n) * float(oc["t_end"].sum())
+        rec["cpu_baseline"] = {
+            "value": steps_done / t_used, "unit": "node-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"the first {done} of the same outbreaks ({int((oc['size'] >= (n + 3) // 4).sum())} "
+                      f"global) in {t_used:.1f} s on one thread"}
+    return rec
+
+
 def bench_batch(steps):
     """Config of 512 uneven graphs in one replayed HIP graph vs separate calls."""
     import numpy as np
@@ -244,6 +315,8 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate")
     ap.add_argument("--j3-steps", type=int, default=2,
                     help="also time EF with three transmission events (0 = skip)")
+    ap.add_argument("--sir-runs", type=int, default=2,
+                    help="also time 100 SIR outbreaks with spreading power (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -360,6 +433,7 @@ def main():
     batch = None if args.no_batch else bench_batch(max(3, args.steps))
     sur = None if args.no_surrogate else bench_surrogate()
     j3 = None if args.j3_steps <= 0 else bench_j3(args.j3_steps, not args.no_cpu_baseline)
+    sir = None if args.sir_runs <= 0 else bench_sir(args.sir_runs, not args.no_cpu_baseline)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -395,6 +469,7 @@ def main():
         "batch": batch,
         "surrogate": sur,
         "three_events": j3,
+        "sir": sir,
         "cpu_baseline": cpu,
     }
     g.close()

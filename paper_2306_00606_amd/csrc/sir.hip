@@ -19,11 +19,19 @@
 // (value >> 11) < floor(p 2^53). Every outcome is an integer function of
 // these draws, so results do not depend on scheduling.
 //
-// Layout: a batch of R simulations runs together, each with a byte of state,
-// a candidate infector and an infector per node ([R][n] arrays). One step is
-// two launches over the batch (attempts with atomicMin on the candidate,
-// then infections and recoveries with one count per workgroup and
-// simulation); the host reads the per-simulation counts after each step.
+// Layout: a batch of R simulations runs together. Per (simulation, node): a
+// state byte and a candidate word, which holds the smallest successful
+// attempter while the node is susceptible and keeps it as the infector once
+// the node is infected; per simulation two frontier lists of length n (the
+// infected nodes at the start of a step, and the next step's list). One step
+// is four launches: a one-workgroup prefix over the simulations' frontier
+// lengths, the attempts (one flat index space over all frontiers, each
+// wavefront expanding the arcs of 64 frontier nodes with a wave-wide prefix of
+// their degrees), a prefix over frontier + new infections, and the update
+// (new infections become infected, frontier nodes recover or stay). Lists
+// grow with wave-aggregated atomic appends; the order of entries varies from
+// run to run but no outcome depends on it. Per-simulation counters stay on
+// the device; the host checks every few steps whether any outbreak is alive.
 // After the batch, the descendants within d = 1..4 generations of the
 // infection tree are summed per node over the global simulations
 // (size >= n / 4, rounded up).
@@ -46,116 +54,369 @@ __device__ __host__ __forceinline__ uint64_t sir_mix(uint64_t z) {
 
 enum : uint8_t { kSus = 0, kInf = 1, kRec = 2 };
 
-// state S, no candidate, no infector; then the index case of each simulation
+constexpr int32_t kSirMaxBatch = 1024;  // simulations per batch: one prefix workgroup
+constexpr int32_t kSirCheck = 8;        // steps between the host's checks for live outbreaks
+constexpr unsigned kSirGrid = 2048;     // workgroups of the frontier kernels (grid-stride)
+
+constexpr int32_t kSirPad = 32;  // int32 stride of the append counters: one 128-byte line each
+constexpr int32_t kSirTab = kSirMaxBatch + 1;  // stride of the per-batch tables below
+
+// per simulation of a batch
+struct SirSim {
+  int32_t F;      // frontier length: infected nodes at the start of the step
+  int32_t fresh;  // new infections of the step (set between attempts and update)
+  int32_t size, peak, t_peak, t_end, index, pad;
+};
+
+// exclusive prefix over one value per thread of a 1024-thread workgroup
+__device__ int32_t sir_scan1024(int32_t v, int32_t *sh, int32_t *total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int32_t incl = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int32_t y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  if (lane == 63) sh[wv] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t run = 0;
+    for (int w = 0; w < 16; ++w) {
+      const int32_t x = sh[w];
+      sh[w] = run;
+      run += x;
+    }
+    sh[16] = run;
+  }
+  __syncthreads();
+  *total = sh[16];
+  return sh[wv] + incl - v;
+}
+
+// state S and no candidate everywhere
 __global__ void k_sir_init(int32_t n, int32_t R, uint8_t *__restrict__ state,
-                           int32_t *__restrict__ cand, int32_t *__restrict__ infector) {
+                           int32_t *__restrict__ cand) {
   const int64_t total = (int64_t)n * R;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
        i += (int64_t)gridDim.x * blockDim.x) {
     state[i] = kSus;
     cand[i] = kSirNone;
-    infector[i] = -1;
   }
 }
 
+// index case of each simulation: infected, alone in the frontier
 __global__ void k_sir_seed(int32_t n, int32_t R, uint64_t seed, int64_t r0,
-                           uint8_t *__restrict__ state, int32_t *__restrict__ index_out,
-                           int32_t *__restrict__ active) {
+                           uint8_t *__restrict__ state, int32_t *__restrict__ cur,
+                           SirSim *__restrict__ sims, int32_t *__restrict__ nxc) {
   const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= R) return;
   const uint64_t base = sir_mix(seed ^ (uint64_t)(r0 + r));
   const int32_t idx = (int32_t)__umul64hi(sir_mix(base ^ ~0ull), (uint64_t)n);
   state[(int64_t)r * n + idx] = kInf;
-  index_out[r] = idx;
-  active[r] = 1;
+  cur[(int64_t)r * n] = idx;
+  SirSim s;
+  s.F = 1;
+  s.fresh = 0;
+  s.size = 1;
+  s.peak = 1;
+  s.t_peak = 0;
+  s.t_end = 0;
+  s.index = idx;
+  s.pad = 0;
+  sims[r] = s;
+  nxc[(int64_t)r * kSirPad] = 0;
 }
 
-// attempts of step t: grid (node blocks, simulation)
-__global__ __launch_bounds__(256) void k_sir_attempt(const int32_t *__restrict__ row_ptr,
-                                                     const int32_t *__restrict__ col,
-                                                     int32_t n, uint64_t seed, int64_t r0,
-                                                     int32_t t, uint64_t tb,
-                                                     const int32_t *__restrict__ active,
-                                                     const uint8_t *__restrict__ state,
-                                                     int32_t *__restrict__ cand) {
-  const int32_t r = blockIdx.y;
-  if (active[r] == 0) return;
-  const int64_t off = (int64_t)r * n;
-  const uint64_t st = sir_mix(sir_mix(seed ^ (uint64_t)(r0 + r)) ^ (uint64_t)(t + 1));
-  for (int32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
-    if (state[off + u] != kInf) continue;
-    for (int32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
-      const int32_t w = col[e];
-      if (state[off + w] != kSus) continue;
-      const uint64_t x = sir_mix(st ^ ((uint64_t)(2 * (int64_t)e) * kSirK));
-      if ((x >> 11) < tb) atomicMin(&cand[off + w], u);
-    }
-  }
-}
-
-// recoveries and infections of step t; next[r] / fresh[r] count the infected
-// nodes after the step and the new infections (cleared before)
-__global__ __launch_bounds__(256) void k_sir_update(int32_t n, uint64_t seed, int64_t r0,
-                                                    int32_t t, uint64_t tm,
-                                                    const int32_t *__restrict__ active,
-                                                    uint8_t *__restrict__ state,
-                                                    int32_t *__restrict__ cand,
-                                                    int32_t *__restrict__ infector,
-                                                    int32_t *__restrict__ next,
-                                                    int32_t *__restrict__ fresh) {
-  __shared__ int32_t sh[2][4];
-  const int32_t r = blockIdx.y;
-  if (active[r] == 0) return;
-  const int64_t off = (int64_t)r * n;
-  const uint64_t st = sir_mix(sir_mix(seed ^ (uint64_t)(r0 + r)) ^ (uint64_t)(t + 1));
-  int32_t c_next = 0, c_new = 0;
-  for (int32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
-    const uint8_t s = state[off + u];
-    if (s == kInf) {
-      const uint64_t x = sir_mix(st ^ ((uint64_t)(2 * (int64_t)u + 1) * kSirK));
-      if ((x >> 11) < tm) state[off + u] = kRec;
-      else ++c_next;
-    } else if (s == kSus) {
-      const int32_t c = cand[off + u];
-      if (c != kSirNone) {
-        state[off + u] = kInf;
-        infector[off + u] = c;
-        cand[off + u] = kSirNone;
-        ++c_next;
-        ++c_new;
+// Start of step t: fold step t - 1 into each simulation's outcome (the next
+// frontier becomes the frontier), then the attempts' table: prefix over the
+// frontier lengths in units of 64 nodes (tab[0..R]) and the lengths
+// (tab[kSirTab + a]); and the number of live simulations.
+__global__ __launch_bounds__(1024) void k_sir_prep(int32_t R, int32_t t, SirSim *__restrict__ sims,
+                                                   int32_t *__restrict__ nxc,
+                                                   int32_t *__restrict__ tab,
+                                                   int32_t *__restrict__ alive) {
+  __shared__ int32_t sh[17];
+  const int32_t a = threadIdx.x;
+  int32_t len = 0, act = 0;
+  if (a < R) {
+    SirSim s = sims[a];
+    if (t > 0 && s.F > 0) {
+      const int32_t nx = nxc[(int64_t)a * kSirPad];
+      s.size += s.fresh;
+      s.t_end = t;
+      if (nx > s.peak) {
+        s.peak = nx;
+        s.t_peak = t;
       }
+      s.F = nx;
+    }
+    s.fresh = 0;
+    sims[a] = s;
+    nxc[(int64_t)a * kSirPad] = 0;
+    tab[kSirTab + a] = s.F;
+    len = (s.F + 63) >> 6;
+    act = s.F > 0 ? 1 : 0;
+  }
+  int32_t tot;
+  const int32_t ex = sir_scan1024(len, sh, &tot);
+  if (a < R) tab[a] = ex;
+  if (a == 0) tab[R] = tot;
+  __syncthreads();
+  int32_t na;
+  sir_scan1024(act, sh, &na);
+  if (a == 0) *alive = na;
+}
+
+// Between attempts and update: the entries appended so far are the step's
+// new infections. The update's table: prefix over frontier + new lengths in
+// units of 256 entries (tab[0..R]), the frontier lengths (tab[kSirTab + a])
+// and the new counts (tab[2 kSirTab + a]).
+__global__ __launch_bounds__(1024) void k_sir_prep_u(int32_t R, SirSim *__restrict__ sims,
+                                                     const int32_t *__restrict__ nxc,
+                                                     int32_t *__restrict__ tab) {
+  __shared__ int32_t sh[17];
+  const int32_t a = threadIdx.x;
+  int32_t len = 0;
+  if (a < R) {
+    const int32_t F = sims[a].F, fr = nxc[(int64_t)a * kSirPad];
+    sims[a].fresh = fr;
+    tab[kSirTab + a] = F;
+    tab[2 * kSirTab + a] = fr;
+    len = F > 0 ? (F + fr + 255) >> 8 : 0;
+  }
+  int32_t tot;
+  const int32_t ex = sir_scan1024(len, sh, &tot);
+  if (a < R) tab[a] = ex;
+  if (a == 0) tab[R] = tot;
+}
+
+// the simulation whose range of work units holds unit c: the largest a with
+// p[a] <= c (p[0] = 0 <= c < p[R])
+__device__ __forceinline__ int32_t sir_owner(const int32_t *p, int32_t R, int32_t c) {
+  int32_t lo = 0, hi = R;
+  while (hi - lo > 1) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (p[mid] <= c) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// orders this wavefront's LDS accesses (written by one lane, read by another)
+__device__ __forceinline__ void sir_wave_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Appends to a simulation's next frontier, gathered per wavefront in LDS and
+// written with one atomic reservation per flush (not one per 64 entries:
+// every wavefront of a simulation reserves on the same counter).
+constexpr int32_t kSirBuf = 256;
+
+struct SirBuf {
+  int32_t *lds;  // this wavefront's kSirBuf entries
+  int32_t cnt;   // entries held (the same in every lane)
+  int32_t sim;   // simulation slot they belong to (-1: none)
+};
+
+__device__ __forceinline__ void sir_flush(SirBuf &b, int32_t *__restrict__ nxc,
+                                          int32_t *__restrict__ lists, int32_t n) {
+  if (b.cnt > 0) {
+    const int lane = threadIdx.x & 63;
+    sir_wave_fence();
+    int32_t base = 0;
+    if (lane == 0) base = atomicAdd(&nxc[(int64_t)b.sim * kSirPad], b.cnt);
+    base = __shfl(base, 0, 64);
+    int32_t *dst = lists + (int64_t)b.sim * n + base;
+    for (int32_t i = lane; i < b.cnt; i += 64) dst[i] = b.lds[i];
+    sir_wave_fence();
+  }
+  b.cnt = 0;
+}
+
+// the wavefront moves on to simulation a: flush what belongs to another one
+__device__ __forceinline__ void sir_switch(SirBuf &b, int32_t a, int32_t *__restrict__ nxc,
+                                           int32_t *__restrict__ lists, int32_t n) {
+  if (b.sim != a) {
+    sir_flush(b, nxc, lists, n);
+    b.sim = a;
+  }
+}
+
+__device__ __forceinline__ void sir_push(SirBuf &b, bool take, int32_t v,
+                                         int32_t *__restrict__ nxc, int32_t *__restrict__ lists,
+                                         int32_t n) {
+  const unsigned long long m = __ballot(take);
+  if (m == 0) return;
+  const int32_t k = __popcll(m);
+  if (b.cnt + k > kSirBuf) sir_flush(b, nxc, lists, n);
+  const int lane = threadIdx.x & 63;
+  if (take) b.lds[b.cnt + __popcll(m & ((1ull << lane) - 1))] = v;
+  b.cnt += k;
+}
+
+// Attempts of step t along every arc of every frontier node. A wavefront
+// takes 64 frontier nodes of one simulation and walks their arcs 256 at a
+// time (four per lane, so that the loads and atomics of the four overlap),
+// the owner of each arc found by a search over the wave-wide degree prefix.
+__global__ __launch_bounds__(256) void k_sir_attempt(
+    const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col, int32_t n, uint64_t seed,
+    int64_t r0, int32_t t, uint64_t tb, int32_t R, const int32_t *__restrict__ tab,
+    int32_t *__restrict__ nxc, const int32_t *__restrict__ cur, const uint8_t *__restrict__ state,
+    int32_t *__restrict__ cand, int32_t *__restrict__ nxt) {
+  __shared__ int32_t sp[kSirTab], sF[kSirMaxBatch];
+  __shared__ int32_t sbuf[4][kSirBuf];
+  __shared__ int32_t shw[4][256], shu[4][256];  // successful attempts: target, attempter
+  for (int32_t x = threadIdx.x; x <= R; x += blockDim.x) sp[x] = tab[x];
+  for (int32_t x = threadIdx.x; x < R; x += blockDim.x) sF[x] = tab[kSirTab + x];
+  __syncthreads();
+  const int32_t chunks = sp[R];
+  const int lane = threadIdx.x & 63;
+  const unsigned long long below = (1ull << lane) - 1;
+  const int32_t nw = (int32_t)gridDim.x * 4;
+  SirBuf buf{sbuf[threadIdx.x >> 6], 0, -1};
+  int32_t *hw = shw[threadIdx.x >> 6], *hu = shu[threadIdx.x >> 6];
+  for (int32_t c = (int32_t)blockIdx.x * 4 + (threadIdx.x >> 6); c < chunks; c += nw) {
+    const int32_t a = sir_owner(sp, R, c);
+    sir_switch(buf, a, nxc, nxt, n);
+    const int64_t off = (int64_t)a * n;
+    const int32_t i = (c - sp[a]) * 64 + lane;
+    int32_t u = 0, beg = 0, deg = 0;
+    if (i < sF[a]) {
+      u = cur[off + i];
+      beg = row_ptr[u];
+      deg = row_ptr[u + 1] - beg;
+    }
+    int32_t incl = deg;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int32_t y = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += y;
+    }
+    const int32_t tot = __shfl(incl, 63, 64), excl = incl - deg;
+    const uint64_t st = sir_mix(sir_mix(seed ^ (uint64_t)(r0 + a)) ^ (uint64_t)(t + 1));
+    for (int32_t jb = 0; jb < tot; jb += 256) {
+      int32_t e[4], ou[4], w[4];
+      bool hit[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int32_t j = jb + 64 * q + lane;
+        // owner lane of arc j: the largest k with excl[k] <= j
+        int32_t k = 0;
+        for (int32_t sstep = 32; sstep > 0; sstep >>= 1) {
+          const int32_t ex = __shfl(excl, k + sstep, 64);
+          if (ex <= j) k += sstep;
+        }
+        const int32_t ob = __shfl(beg, k, 64), oe = __shfl(excl, k, 64);
+        ou[q] = __shfl(u, k, 64);
+        e[q] = ob + (j - oe);
+        // the draw depends on the arc alone: only a successful one needs the
+        // target and its state
+        const uint64_t x = sir_mix(st ^ ((uint64_t)(2 * (int64_t)e[q]) * kSirK));
+        hit[q] = j < tot && (x >> 11) < tb;
+      }
+      // lanes without a success read arc 0 and its target (valid: tot > 0)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) w[q] = col[hit[q] ? e[q] : 0];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) hit[q] = hit[q] & (state[off + w[q]] == kSus);
+      // gather the successes, so that their atomics go out together
+      int32_t nh = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const unsigned long long m = __ballot(hit[q]);
+        if (hit[q]) {
+          const int32_t r = nh + __popcll(m & below);
+          hw[r] = w[q];
+          hu[r] = ou[q];
+        }
+        nh += __popcll(m);
+      }
+      sir_wave_fence();
+      for (int32_t r = 0; r < nh; r += 64) {
+        bool fresh = false;
+        int32_t x = 0;
+        if (r + lane < nh) {
+          x = hw[r + lane];
+          fresh = atomicMin(&cand[off + x], hu[r + lane]) == kSirNone;
+        }
+        sir_push(buf, fresh, x, nxc, nxt, n);
+      }
+      sir_wave_fence();
     }
   }
-  for (int o = 32; o > 0; o >>= 1) {
-    c_next += __shfl_xor(c_next, o, 64);
-    c_new += __shfl_xor(c_new, o, 64);
-  }
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (lane == 0) {
-    sh[0][wv] = c_next;
-    sh[1][wv] = c_new;
+  sir_flush(buf, nxc, nxt, n);
+}
+
+// Update of step t, 256 entries per wavefront (four per lane): the step's new
+// infections become infected; frontier nodes recover with probability mu or
+// stay in the next frontier.
+__global__ __launch_bounds__(256) void k_sir_update(int32_t n, uint64_t seed, int64_t r0,
+                                                    int32_t t, uint64_t tm, int32_t R,
+                                                    const int32_t *__restrict__ tab,
+                                                    int32_t *__restrict__ nxc,
+                                                    const int32_t *__restrict__ cur,
+                                                    uint8_t *__restrict__ state,
+                                                    int32_t *__restrict__ nxt) {
+  __shared__ int32_t sp[kSirTab], sF[kSirMaxBatch], sfr[kSirMaxBatch];
+  __shared__ int32_t sbuf[4][kSirBuf];
+  for (int32_t x = threadIdx.x; x <= R; x += blockDim.x) sp[x] = tab[x];
+  for (int32_t x = threadIdx.x; x < R; x += blockDim.x) {
+    sF[x] = tab[kSirTab + x];
+    sfr[x] = tab[2 * kSirTab + x];
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    const int32_t a = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
-    const int32_t b = sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3];
-    if (a) atomicAdd(&next[r], a);
-    if (b) atomicAdd(&fresh[r], b);
+  const int32_t units = sp[R];
+  const int lane = threadIdx.x & 63;
+  const int32_t nw = (int32_t)gridDim.x * 4;
+  SirBuf buf{sbuf[threadIdx.x >> 6], 0, -1};
+  for (int32_t c = (int32_t)blockIdx.x * 4 + (threadIdx.x >> 6); c < units; c += nw) {
+    const int32_t a = sir_owner(sp, R, c);
+    sir_switch(buf, a, nxc, nxt, n);
+    const int32_t F = sF[a], fr = sfr[a];
+    const int64_t off = (int64_t)a * n;
+    const int32_t i0 = (c - sp[a]) * 256 + lane;
+    const uint64_t st = sir_mix(sir_mix(seed ^ (uint64_t)(r0 + a)) ^ (uint64_t)(t + 1));
+    int32_t v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int32_t i = i0 + 64 * q;
+      // entries [0, fr) of the next list are the new infections; then the
+      // frontier (lanes past the end read frontier entry 0)
+      const int32_t *src = i < fr ? nxt + off + i : cur + off + (i < fr + F ? i - fr : 0);
+      v[q] = *src;
+    }
+    bool keep[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int32_t i = i0 + 64 * q;
+      keep[q] = false;
+      if (i < fr) {
+        state[off + v[q]] = kInf;
+      } else if (i < fr + F) {
+        const uint64_t x = sir_mix(st ^ ((uint64_t)(2 * (int64_t)v[q] + 1) * kSirK));
+        if ((x >> 11) < tm) state[off + v[q]] = kRec;
+        else keep[q] = true;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sir_push(buf, keep[q], v[q], nxc, nxt, n);
   }
+  sir_flush(buf, nxc, nxt, n);
 }
 
 // one level of descendant counts: cur[p] += 1 + prev[c] for every infected c
-// with infector p (prev null: level 1)
-__global__ void k_sir_level(int32_t n, int32_t R, const int32_t *__restrict__ glob,
-                            const int32_t *__restrict__ infector,
+// with infector p (prev null: level 1); grid (node blocks, simulation)
+__global__ void k_sir_level(int32_t n, const int32_t *__restrict__ glob,
+                            const uint8_t *__restrict__ state, const int32_t *__restrict__ cand,
                             const int32_t *__restrict__ prev, int32_t *__restrict__ cur) {
-  const int64_t total = (int64_t)n * R;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t r = (int32_t)(i / n);
-    const int32_t p = infector[i];
-    if (!glob[r] || p < 0) continue;
-    atomicAdd(&cur[(int64_t)r * n + p], 1 + (prev ? prev[i] : 0));
+  const int32_t r = blockIdx.y;
+  if (!glob[r]) return;
+  const int64_t off = (int64_t)r * n;
+  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+    if (state[off + v] == kSus) continue;
+    const int32_t p = cand[off + v];
+    if (p == kSirNone) continue;  // the index case
+    atomicAdd(&cur[off + p], 1 + (prev ? prev[off + v] : 0));
   }
 }
 
@@ -225,14 +486,16 @@ extern "C" ef_status ef_sir(ef_graph *h, double beta, double mu, uint64_t seed, 
     return EF_OK;
   }
   hipStream_t st = (hipStream_t)hip_stream;
-  // batch of simulations: about 1.5 GB of per-(simulation, node) state
-  const int64_t per_sim = (int64_t)n * (1 + 4 + 4 + 4 + 4);
-  // (and at most 32768 simulations: the simulation is the grid's y index)
+  // batch: about 3 GB of per-(simulation, node) state (13 bytes), at most
+  // one prefix workgroup of simulations
+  const int64_t per_sim = (int64_t)n * (1 + 4 + 4 + 4);
   const int32_t RB = (int32_t)std::max<int64_t>(
-      1, std::min<int64_t>({(int64_t)std::max(n_sims, 1), 32768,
-                            (1536LL << 20) / std::max<int64_t>(per_sim, 1)}));
-  const size_t bytes = (size_t)RB * (size_t)n * (1 + 4 * 4) + sizeof(int32_t) * 6 * (size_t)RB +
-                       sizeof(int64_t) * 5 * (size_t)n + 4096;
+      1, std::min<int64_t>({(int64_t)std::max(n_sims, 1), (int64_t)kSirMaxBatch,
+                            (3LL << 30) / std::max<int64_t>(per_sim, 1)}));
+  const size_t cells = (size_t)RB * (size_t)n;
+  const size_t bytes = cells * 13 + sizeof(SirSim) * RB + sizeof(int32_t) * kSirPad * RB +
+                       sizeof(int32_t) * (5 * (size_t)kSirTab + RB + 1) +
+                       sizeof(int64_t) * 5 * (size_t)n + 16 * 256;
   char *p = nullptr;
   ef_status s = graph_scratch(g, bytes, (void **)&p);
   if (s != EF_OK) return s;
@@ -241,16 +504,16 @@ extern "C" ef_status ef_sir(ef_graph *h, double beta, double mu, uint64_t seed, 
     p += (b + 255) & ~(size_t)255;
     return q;
   };
-  const int64_t cells = (int64_t)RB * n;
-  uint8_t *state = (uint8_t *)take((size_t)cells);
-  int32_t *cand = (int32_t *)take(sizeof(int32_t) * (size_t)cells);
-  int32_t *infector = (int32_t *)take(sizeof(int32_t) * (size_t)cells);
-  int32_t *lvl[2] = {(int32_t *)take(sizeof(int32_t) * (size_t)cells),
-                     (int32_t *)take(sizeof(int32_t) * (size_t)cells)};
-  int32_t *d_index = (int32_t *)take(sizeof(int32_t) * RB);
-  int32_t *d_active = (int32_t *)take(sizeof(int32_t) * RB);
-  int32_t *d_cnt = (int32_t *)take(sizeof(int32_t) * 2 * RB);  // next, fresh
-  int32_t *d_glob = (int32_t *)take(sizeof(int32_t) * RB);
+  uint8_t *state = (uint8_t *)take(cells);
+  int32_t *cand = (int32_t *)take(sizeof(int32_t) * cells);
+  int32_t *list[2] = {(int32_t *)take(sizeof(int32_t) * cells),
+                      (int32_t *)take(sizeof(int32_t) * cells)};
+  SirSim *d_sims = (SirSim *)take(sizeof(SirSim) * RB);
+  int32_t *d_nxc = (int32_t *)take(sizeof(int32_t) * kSirPad * RB);
+  int32_t *d_tabA = (int32_t *)take(sizeof(int32_t) * 2 * kSirTab);
+  int32_t *d_tabU = (int32_t *)take(sizeof(int32_t) * 3 * kSirTab);
+  int32_t *d_glob = (int32_t *)take(sizeof(int32_t) * RB + sizeof(int32_t));
+  int32_t *d_alive = d_glob + RB;
   int64_t *d_sp = (int64_t *)take(sizeof(int64_t) * 5 * (size_t)n);  // 4 orders, then counts
   int64_t *d_ic = d_sp + 4 * (int64_t)n;
   const uint64_t tb = sir_threshold(beta), tm = sir_threshold(mu);
@@ -258,67 +521,62 @@ extern "C" ef_status ef_sir(ef_graph *h, double beta, double mu, uint64_t seed, 
   hipError_t e = hipSuccess;
   hipLaunchKernelGGL(k_sir_zero64, dim3(sir_blocks(5 * (int64_t)n)), dim3(256), 0, st,
                      5 * (int64_t)n, d_sp);
-  std::vector<int32_t> h_cnt(2 * (size_t)RB), h_active((size_t)RB), h_glob((size_t)RB);
+  std::vector<SirSim> h_sims((size_t)RB);
+  std::vector<int32_t> h_glob((size_t)RB);
   const unsigned gx = sir_blocks(n);
   for (int32_t r0 = 0; r0 < n_sims && e == hipSuccess; r0 += RB) {
     const int32_t R = std::min(RB, n_sims - r0);
     hipLaunchKernelGGL(k_sir_init, dim3(sir_blocks((int64_t)R * n)), dim3(256), 0, st, n, R,
-                       state, cand, infector);
+                       state, cand);
     hipLaunchKernelGGL(k_sir_seed, dim3((R + 255) / 256), dim3(256), 0, st, n, R, seed,
-                       (int64_t)r0, state, d_index, d_active);
-    std::vector<int64_t> sz((size_t)R, 1), peak((size_t)R, 1);
-    std::vector<int32_t> tpk((size_t)R, 0), tend((size_t)R, 0);
-    std::fill(h_active.begin(), h_active.begin() + R, 1);
-    int32_t alive = R;
-    for (int32_t t = 0; t < t_max && alive > 0; ++t) {
-      hipLaunchKernelGGL(k_sir_zero, dim3(1), dim3(256), 0, st, (int64_t)2 * R, d_cnt);
-      hipLaunchKernelGGL(k_sir_attempt, dim3(gx, R), dim3(256), 0, st, g.row_ptr, g.col_idx, n,
-                         seed, (int64_t)r0, t, tb, d_active, state, cand);
-      hipLaunchKernelGGL(k_sir_update, dim3(gx, R), dim3(256), 0, st, n, seed, (int64_t)r0, t, tm,
-                         d_active, state, cand, infector, d_cnt, d_cnt + R);
-      e = hipMemcpyAsync(h_cnt.data(), d_cnt, sizeof(int32_t) * 2 * R, hipMemcpyDeviceToHost, st);
-      if (e == hipSuccess) e = hipStreamSynchronize(st);
-      if (e != hipSuccess) break;
-      alive = 0;
-      for (int32_t r = 0; r < R; ++r) {
-        if (!h_active[r]) continue;
-        const int32_t nx = h_cnt[r];
-        sz[r] += h_cnt[R + r];
-        tend[r] = t + 1;
-        if (nx > peak[r]) {
-          peak[r] = nx;
-          tpk[r] = t + 1;
-        }
-        if (nx == 0) h_active[r] = 0;
-        else ++alive;
+                       (int64_t)r0, state, list[0], d_sims, d_nxc);
+    int32_t t = 0;
+    while (t < t_max) {
+      int32_t *cur = list[t & 1], *nxt = list[(t + 1) & 1];
+      hipLaunchKernelGGL(k_sir_prep, dim3(1), dim3(1024), 0, st, R, t, d_sims, d_nxc, d_tabA,
+                         d_alive);
+      hipLaunchKernelGGL(k_sir_attempt, dim3(kSirGrid), dim3(256), 0, st, g.row_ptr, g.col_idx, n,
+                         seed, (int64_t)r0, t, tb, R, d_tabA, d_nxc, cur, state, cand, nxt);
+      hipLaunchKernelGGL(k_sir_prep_u, dim3(1), dim3(1024), 0, st, R, d_sims, d_nxc, d_tabU);
+      hipLaunchKernelGGL(k_sir_update, dim3(kSirGrid), dim3(256), 0, st, n, seed, (int64_t)r0, t,
+                         tm, R, d_tabU, d_nxc, cur, state, nxt);
+      ++t;
+      if (t % kSirCheck == 0 || t == t_max) {
+        // live simulations in the step just run (from its prefix workgroup)
+        int32_t alive = 0;
+        e = hipMemcpyAsync(&alive, d_alive, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess || alive == 0) break;
       }
-      e = hipMemcpyAsync(d_active, h_active.data(), sizeof(int32_t) * R, hipMemcpyHostToDevice, st);
-      if (e != hipSuccess) break;
     }
     if (e != hipSuccess) break;
-    // outputs of the batch, and the spreading power of its global simulations
-    for (int32_t r = 0; r < R; ++r) {
-      size[r0 + r] = (int32_t)sz[r];
-      t_end[r0 + r] = tend[r];
-      t_peak[r0 + r] = tpk[r];
-      h_glob[r] = sz[r] >= global_min ? 1 : 0;
-    }
-    e = hipMemcpyAsync(index + r0, d_index, sizeof(int32_t) * R, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(d_glob, h_glob.data(), sizeof(int32_t) * R, hipMemcpyHostToDevice, st);
+    // fold the last step, then the outcomes of the batch
+    hipLaunchKernelGGL(k_sir_prep, dim3(1), dim3(1024), 0, st, R, t, d_sims, d_nxc, d_tabA,
+                       d_alive);
+    e = hipMemcpyAsync(h_sims.data(), d_sims, sizeof(SirSim) * R, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) break;
     bool any = false;
-    for (int32_t r = 0; r < R; ++r) any = any || h_glob[r];
-    if (any) {
-      const unsigned gb = sir_blocks((int64_t)R * n);
-      for (int d = 1; d <= 4; ++d) {
-        int32_t *cur = lvl[d & 1], *prev = d == 1 ? nullptr : lvl[(d - 1) & 1];
-        hipLaunchKernelGGL(k_sir_zero, dim3(gb), dim3(256), 0, st, (int64_t)R * n, cur);
-        hipLaunchKernelGGL(k_sir_level, dim3(gb), dim3(256), 0, st, n, R, d_glob, infector, prev,
-                           cur);
-        hipLaunchKernelGGL(k_sir_accum, dim3(gx), dim3(256), 0, st, n, R, d_glob, state, cur,
-                           d_sp + (int64_t)(d - 1) * n, d == 1 ? d_ic : nullptr);
-      }
+    for (int32_t r = 0; r < R; ++r) {
+      index[r0 + r] = h_sims[r].index;
+      size[r0 + r] = h_sims[r].size;
+      t_end[r0 + r] = h_sims[r].t_end;
+      t_peak[r0 + r] = h_sims[r].t_peak;
+      h_glob[r] = h_sims[r].size >= global_min ? 1 : 0;
+      any = any || h_glob[r];
+    }
+    if (!any) continue;
+    e = hipMemcpyAsync(d_glob, h_glob.data(), sizeof(int32_t) * R, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) break;
+    // the frontier lists are free now: levels d - 1 and d of the descendant counts
+    const unsigned gb = sir_blocks((int64_t)R * n);
+    for (int d = 1; d <= 4; ++d) {
+      int32_t *lc = list[d & 1], *lp = d == 1 ? nullptr : list[(d - 1) & 1];
+      hipLaunchKernelGGL(k_sir_zero, dim3(gb), dim3(256), 0, st, (int64_t)R * n, lc);
+      hipLaunchKernelGGL(k_sir_level, dim3(gx, R), dim3(256), 0, st, n, d_glob, state, cand, lp,
+                         lc);
+      hipLaunchKernelGGL(k_sir_accum, dim3(gx), dim3(256), 0, st, n, R, d_glob, state, lc,
+                         d_sp + (int64_t)(d - 1) * n, d == 1 ? d_ic : nullptr);
     }
     e = hipStreamSynchronize(st);
   }

@@ -58,10 +58,9 @@ def test_sir_matches_oracle(name):
     assert got["sp_sum"][0].sum() == int((got["size"][glob] - 1).sum())
 
 
-def test_sir_two_batches_ba_1m():
-    """BA n = 10^6, m = 5 at the paper's calibration: a batch holds 94
-    simulations of this size, so 100 simulations run in two batches and the
-    spreading-power sums add up across them."""
+def test_sir_ba_1m_paper_calibration():
+    """BA n = 10^6, m = 5 at the paper's calibration, 100 outbreaks: the size
+    the benchmark runs, every output against the oracle."""
     rp, ci = gen.ba_1m(seed=8)
     beta = paper_beta(rp)
     with efgpu.Graph(rp, ci, validate=False) as g:
@@ -73,6 +72,18 @@ def test_sir_two_batches_ba_1m():
     sys.stderr.write(f"[sir] BA 1e6: {int(glob.sum())} global of 100\n")
     assert glob.sum() > 0
     assert np.all(got["sp_sum"][1:] >= got["sp_sum"][:-1])  # deeper subtrees are larger
+
+
+def test_sir_two_batches():
+    """More simulations than one batch holds (1024): the outcomes and the
+    spreading-power sums continue across the batch boundary."""
+    rp, ci = gen.erdos_renyi(600, 0.01, 21)
+    with efgpu.Graph(rp, ci) as g:
+        got = g.sir(0.3, 0.3, seed=99, n_sims=1500)
+    compare(got, oracle.sir(rp, ci, 0.3, 0.3, seed=99, n_sims=1500), "1500 simulations")
+    glob = got["size"] >= 150
+    sys.stderr.write(f"[sir] ER 600: {int(glob.sum())} global of 1500\n")
+    assert 0 < glob[:1024].sum() and 0 < glob[1024:].sum()
 
 
 def test_sir_t_max_and_edge_cases():
