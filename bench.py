@@ -21,9 +21,9 @@ beside it in the same line (they are not the headline value):
               evaluated on a held-out Barabasi-Albert graph (n = 4M, m = 8):
               rank agreement with exact EF, and its speed against the exact path;
   three_events - EF with three transmission events on Barabasi-Albert n = 1e6;
-  sir       - 100 SIR outbreaks on the same Barabasi-Albert graph at the paper's
-              calibration, and the correlation of exp(EF) with the measured
-              spreading power of orders 1-4.
+  sir       - 300 SIR outbreaks (about 100 global) on the same Barabasi-Albert
+              graph at the paper's calibration, and the correlation of exp(EF)
+              with the measured spreading power of orders 1-4.
 """
 import argparse
 import json
@@ -52,6 +52,12 @@ OPS_PER_CLUSTER = 8
 # counter summaries sit with the other rocprofv3 summaries); set to None
 # whenever the kernel changes.
 PAIRS_BIG_TRAFFIC_BYTES = 2.655e9
+# VALU cost of one SIR attempt along an arc, in FP32-FMA-equivalent lane slots:
+# the counter (2e) K and SplitMix64's two multiplications are three 64-bit
+# products of three 32-bit multiplies each, at a quarter of the FMA rate
+# (36); three 64-bit xor-shifts (9), the 64-bit additions and xors of the
+# counter (4), the threshold compare (2) and the arc's index (3).
+SIR_OPS_PER_ARC = 54
 
 
 def log(msg):
@@ -155,20 +161,20 @@ def bench_j3(steps, with_cpu):
 
 def bench_sir(runs, with_cpu):
     """SIR outbreaks (ef_sir) on the Barabasi-Albert graph n = 10^6, m = 5 at
-    the paper's calibration (beta = 1.3 / (3 <k>), mu = 1/3), 100 outbreaks from
-    uniform index cases, as in the spreading-power comparison of Sec. 3.3. The
+    the paper's calibration (beta = 1.3 / (3 <k>), mu = 1/3): 300 outbreaks from
+    uniform index cases, of which about 100 are global, the number the paper's
+    spreading-power comparison rests on (Sec. 5.4). The
     empirical spreading power of order d of a node is its mean number of
     descendants within d generations of the infection tree over the global
     outbreaks (size >= n / 4) that infected it; reported with its Pearson
     correlation with exp(EF) and with degree over the nodes that have one.
-    Throughput is counted in node-steps: every step of a simulation visits all
-    n nodes."""
+    Roofline of the attempt kernel: VALU slots of the per-arc draws."""
     import numpy as np
     import torch
 
     from paper_2306_00606_amd import efgpu, gen
 
-    sims, seed = 100, 2306
+    sims, seed = 300, 2306
     log("SIR: generating BA n = 1e6, m = 5")
     rp, ci = gen.ba_1m()
     n = rp.size - 1
@@ -182,9 +188,11 @@ def bench_sir(runs, with_cpu):
     for _ in range(runs):
         o = g.sir(beta, mu, seed, sims)
     ms = 1e3 * (time.perf_counter() - t0) / runs
+    prof = g.sir(beta, mu, seed, sims, profile=True)
     g.close()
+    ph = prof["phase_ms"]
+    arcs, fsteps = int(o["work"][0]), int(o["work"][1])
     glob = o["size"] >= (n + 3) // 4
-    node_steps = float(n) * float(o["t_end"].sum())
     have = o["inf_count"] > 0
     deg = np.diff(rp).astype(np.float64)
     x = np.exp(ef[have])
@@ -194,29 +202,39 @@ def bench_sir(runs, with_cpu):
         pe.append(float(np.corrcoef(x, sp)[0, 1]))
         pd.append(float(np.corrcoef(deg[have], sp)[0, 1]))
     idx_ef = ef[o["index"]]
+    achieved = arcs * SIR_OPS_PER_ARC / (ph["attempts"] * 1e-3)
     rec = {"workload": "ba_1m_m5", "nodes": n, "arcs": int(ci.size), "beta": beta, "mu": mu,
            "outbreaks": sims, "runs": runs, "ms_per_run": ms,
-           "outbreaks_per_s": sims / (ms * 1e-3), "node_steps_per_s": node_steps / (ms * 1e-3),
+           "outbreaks_per_s": sims / (ms * 1e-3), "arc_visits": arcs,
+           "frontier_node_steps": fsteps, "arc_visits_per_s": arcs / (ms * 1e-3),
+           "phases_ms": {k: round(v, 4) for k, v in ph.items()},
+           "roofline": {"bound": "alu", "kernel": "k_sir_attempt",
+                        "achieved": achieved / 1e12, "peak": VALU_LANE_OPS_PEAK / 1e12,
+                        "unit": "TOP/s", "frac": achieved / VALU_LANE_OPS_PEAK, "traffic": None,
+                        "ops_per_arc": SIR_OPS_PER_ARC, "arcs_per_run": arcs,
+                        "kernel_ms_per_run": ph["attempts"]},
            "global_outbreaks": int(glob.sum()), "mean_global_size": float(o["size"][glob].mean())
            if glob.any() else None, "nodes_with_spreading_power": int(have.sum()),
            "pearson_expEF_vs_sp_d1_4": pe, "pearson_degree_vs_sp_d1_4": pd,
            "index_case_ef_mean_global": float(idx_ef[glob].mean()) if glob.any() else None,
            "index_case_ef_mean_local": float(idx_ef[~glob].mean()) if (~glob).any() else None}
-    log(f"SIR: {ms:.1f} ms per {sims} outbreaks, {int(glob.sum())} global; "
-        f"Pearson exp(EF) {[round(v, 3) for v in pe]}, degree {[round(v, 3) for v in pd]}")
+    log(f"SIR: {ms:.1f} ms per {sims} outbreaks, {int(glob.sum())} global, {arcs:.3e} arcs; "
+        f"phases {ph}; Pearson exp(EF) {[round(v, 3) for v in pe]}, "
+        f"degree {[round(v, 3) for v in pd]}")
     if with_cpu:
         import oracle
-        done, steps_done, t_used = 0, 0.0, 0.0
+        done, t_used, oc = 0, 0.0, None
         while t_used < 10.0 and done < sims:
             k = min(sims, max(done + 4, 2 * done))
             t1 = time.perf_counter()
             oc = oracle.sir(rp, ci, beta, mu, seed, k)
             t_used = time.perf_counter() - t1
-            done, steps_done = k, float(n) * float(oc["t_end"].sum())
+            done = k
         rec["cpu_baseline"] = {
-            "value": steps_done / t_used, "unit": "node-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"the first {done} of the same outbreaks ({int((oc['size'] >= (n + 3) // 4).sum())} "
-                      f"global) in {t_used:.1f} s on one thread"}
+            "value": done / t_used, "unit": "outbreaks/s", "cores": 1, "kind": "oracle",
+            "sample": f"the first {done} of the same outbreaks "
+                      f"({int((oc['size'] >= (n + 3) // 4).sum())} global) in {t_used:.1f} s "
+                      f"on one thread"}
     return rec
 
 
@@ -316,7 +334,7 @@ def main():
     ap.add_argument("--j3-steps", type=int, default=2,
                     help="also time EF with three transmission events (0 = skip)")
     ap.add_argument("--sir-runs", type=int, default=2,
-                    help="also time 100 SIR outbreaks with spreading power (0 = skip)")
+                    help="also time 300 SIR outbreaks with spreading power (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "

@@ -195,17 +195,31 @@ ef_status ef_compute_j3(ef_graph *g, ef_prec prec, const int32_t *seeds, int32_t
  * no node is infected or after t_max steps. The paper's calibration is
  * mu = 1/3, beta = 1.3 / (3 <k>). Every decision is a SplitMix64 draw on a
  * counter of (seed, simulation, step, arc or node), so results are
- * reproducible and independent of scheduling.
+ * reproducible and independent of scheduling:
+ *   stream(r, t) = mix(mix(seed ^ r) ^ (t + 1)) for simulation r, step t;
+ *   the attempt along arc e draws mix(stream ^ (2e) K), the recovery of node
+ *   u draws mix(stream ^ (2u + 1) K), K = 0xD1B54A32D192ED03; the index case
+ *   is the high 64 bits of mix(mix(seed ^ r) ^ ~0) * n; a decision of
+ *   probability p succeeds when (draw >> 11) < floor(p 2^53).
  * Outputs (host memory): per simulation r < n_sims the index case, size
  * (nodes ever infected), t_end (steps run) and t_peak (first step with the
  * most infected nodes); over the global simulations (size >= n/4, rounded
  * up): inf_count[v] = those in which v was infected, and sp_sum[(d-1) n + v]
  * = the sum over them of v's descendants within d generations of the
  * infection tree, d = 1..4 (divide by inf_count for the empirical spreading
- * power of order d). Synchronises the stream after every step. */
+ * power of order d). Nullable: work[0] = arcs walked by the attempts (one draw
+ * each), work[1] = frontier node-steps (infected nodes summed over the steps
+ * run); phase_ms[0..2] = kernel time of the attempts, of the updates with
+ * their prefix kernels, and of the descendant counts, from HIP events on the
+ * stream. Simulations run in batches of up to 1024 sharing about 3 GB of the
+ * graph's scratch memory (13 bytes per node and simulation). The stream is
+ * synchronised every 8 steps and at the end. EF_ERR_ARG for beta or mu
+ * outside [0, 1], negative n_sims or t_max, null outputs, or simulations on
+ * a graph without nodes. */
 ef_status ef_sir(ef_graph *g, double beta, double mu, uint64_t seed, int32_t n_sims,
                  int32_t t_max, int32_t *index, int32_t *size, int32_t *t_end, int32_t *t_peak,
-                 int64_t *sp_sum, int64_t *inf_count, void *hip_stream);
+                 int64_t *sp_sum, int64_t *inf_count, int64_t *work, double *phase_ms,
+                 void *hip_stream);
 
 /* The k nodes of largest EF ("key nodes", the paper's title and Sec. 1):
  * computes EF of all nodes with `algo` / `prec`, then writes nodes[0..k) and

@@ -66,6 +66,7 @@ struct SirSim {
   int32_t F;      // frontier length: infected nodes at the start of the step
   int32_t fresh;  // new infections of the step (set between attempts and update)
   int32_t size, peak, t_peak, t_end, index, pad;
+  int64_t fsteps;  // frontier nodes summed over the steps run
 };
 
 // exclusive prefix over one value per thread of a 1024-thread workgroup
@@ -122,6 +123,7 @@ __global__ void k_sir_seed(int32_t n, int32_t R, uint64_t seed, int64_t r0,
   s.t_end = 0;
   s.index = idx;
   s.pad = 0;
+  s.fsteps = 0;
   sims[r] = s;
   nxc[(int64_t)r * kSirPad] = 0;
 }
@@ -141,6 +143,7 @@ __global__ __launch_bounds__(1024) void k_sir_prep(int32_t R, int32_t t, SirSim 
     SirSim s = sims[a];
     if (t > 0 && s.F > 0) {
       const int32_t nx = nxc[(int64_t)a * kSirPad];
+      s.fsteps += s.F;
       s.size += s.fresh;
       s.t_end = t;
       if (nx > s.peak) {
@@ -263,7 +266,7 @@ __global__ __launch_bounds__(256) void k_sir_attempt(
     const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col, int32_t n, uint64_t seed,
     int64_t r0, int32_t t, uint64_t tb, int32_t R, const int32_t *__restrict__ tab,
     int32_t *__restrict__ nxc, const int32_t *__restrict__ cur, const uint8_t *__restrict__ state,
-    int32_t *__restrict__ cand, int32_t *__restrict__ nxt) {
+    int32_t *__restrict__ cand, int32_t *__restrict__ nxt, int64_t *__restrict__ wk) {
   __shared__ int32_t sp[kSirTab], sF[kSirMaxBatch];
   __shared__ int32_t sbuf[4][kSirBuf];
   __shared__ int32_t shw[4][256], shu[4][256];  // successful attempts: target, attempter
@@ -276,6 +279,7 @@ __global__ __launch_bounds__(256) void k_sir_attempt(
   const int32_t nw = (int32_t)gridDim.x * 4;
   SirBuf buf{sbuf[threadIdx.x >> 6], 0, -1};
   int32_t *hw = shw[threadIdx.x >> 6], *hu = shu[threadIdx.x >> 6];
+  int64_t arcs = 0;  // arcs walked by this wavefront (work count)
   for (int32_t c = (int32_t)blockIdx.x * 4 + (threadIdx.x >> 6); c < chunks; c += nw) {
     const int32_t a = sir_owner(sp, R, c);
     sir_switch(buf, a, nxc, nxt, n);
@@ -293,6 +297,7 @@ __global__ __launch_bounds__(256) void k_sir_attempt(
       if (lane >= o) incl += y;
     }
     const int32_t tot = __shfl(incl, 63, 64), excl = incl - deg;
+    arcs += tot;
     const uint64_t st = sir_mix(sir_mix(seed ^ (uint64_t)(r0 + a)) ^ (uint64_t)(t + 1));
     for (int32_t jb = 0; jb < tot; jb += 256) {
       int32_t e[4], ou[4], w[4];
@@ -345,6 +350,8 @@ __global__ __launch_bounds__(256) void k_sir_attempt(
     }
   }
   sir_flush(buf, nxc, nxt, n);
+  // each wavefront owns one slot of the arc counts: no atomic needed
+  if (lane == 0) wk[blockIdx.x * 4 + (threadIdx.x >> 6)] += arcs;
 }
 
 // Update of step t, 256 entries per wavefront (four per lane): the step's new
@@ -404,14 +411,13 @@ __global__ __launch_bounds__(256) void k_sir_update(int32_t n, uint64_t seed, in
   sir_flush(buf, nxc, nxt, n);
 }
 
-// one level of descendant counts: cur[p] += 1 + prev[c] for every infected c
-// with infector p (prev null: level 1); grid (node blocks, simulation)
-__global__ void k_sir_level(int32_t n, const int32_t *__restrict__ glob,
+// one level of descendant counts over the global simulations (slots gl[]):
+// cur[p] += 1 + prev[c] for every infected c with infector p (prev null:
+// level 1); grid (node blocks, global simulation)
+__global__ void k_sir_level(int32_t n, const int32_t *__restrict__ gl,
                             const uint8_t *__restrict__ state, const int32_t *__restrict__ cand,
                             const int32_t *__restrict__ prev, int32_t *__restrict__ cur) {
-  const int32_t r = blockIdx.y;
-  if (!glob[r]) return;
-  const int64_t off = (int64_t)r * n;
+  const int64_t off = (int64_t)gl[blockIdx.y] * n;
   for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
     if (state[off + v] == kSus) continue;
     const int32_t p = cand[off + v];
@@ -420,16 +426,16 @@ __global__ void k_sir_level(int32_t n, const int32_t *__restrict__ glob,
   }
 }
 
-// per node: add the level-d counts of the global simulations in which it was
+// per node: add the level-d counts of the G global simulations in which it was
 // infected (and, at d = 1, count those simulations)
-__global__ void k_sir_accum(int32_t n, int32_t R, const int32_t *__restrict__ glob,
+__global__ void k_sir_accum(int32_t n, int32_t G, const int32_t *__restrict__ gl,
                             const uint8_t *__restrict__ state, const int32_t *__restrict__ cur,
                             int64_t *__restrict__ sp, int64_t *__restrict__ cnt) {
   for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
     int64_t a = 0, c = 0;
-    for (int32_t r = 0; r < R; ++r) {
-      const int64_t i = (int64_t)r * n + v;
-      if (glob[r] && state[i] != kSus) {
+    for (int32_t j = 0; j < G; ++j) {
+      const int64_t i = (int64_t)gl[j] * n + v;
+      if (state[i] != kSus) {
         a += cur[i];
         ++c;
       }
@@ -439,10 +445,12 @@ __global__ void k_sir_accum(int32_t n, int32_t R, const int32_t *__restrict__ gl
   }
 }
 
-__global__ void k_sir_zero(int64_t count, int32_t *__restrict__ p) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
-       i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = 0;
+// zero the rows of the global simulations; grid (node blocks, global simulation)
+__global__ void k_sir_zero_rows(int32_t n, const int32_t *__restrict__ gl,
+                                int32_t *__restrict__ p) {
+  const int64_t off = (int64_t)gl[blockIdx.y] * n;
+  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+    p[off + v] = 0;
 }
 
 __global__ void k_sir_zero64(int64_t count, int64_t *__restrict__ p) {
@@ -469,13 +477,15 @@ using namespace efi;
 extern "C" ef_status ef_sir(ef_graph *h, double beta, double mu, uint64_t seed, int32_t n_sims,
                             int32_t t_max, int32_t *index, int32_t *size, int32_t *t_end,
                             int32_t *t_peak, int64_t *sp_sum, int64_t *inf_count,
-                            void *hip_stream) {
+                            int64_t *work, double *phase_ms, void *hip_stream) {
   if (!h || n_sims < 0 || t_max < 0 || !(beta >= 0.0 && beta <= 1.0) ||
       !(mu >= 0.0 && mu <= 1.0) || (n_sims > 0 && (!index || !size || !t_end || !t_peak)) ||
       !sp_sum || !inf_count) {
     set_error("ef_sir: bad arguments");
     return EF_ERR_ARG;
   }
+  if (work) work[0] = work[1] = 0;
+  if (phase_ms) phase_ms[0] = phase_ms[1] = phase_ms[2] = 0.0;
   Graph &g = h->g;
   const int32_t n = g.n;
   if (n == 0) {
@@ -495,7 +505,7 @@ extern "C" ef_status ef_sir(ef_graph *h, double beta, double mu, uint64_t seed, 
   const size_t cells = (size_t)RB * (size_t)n;
   const size_t bytes = cells * 13 + sizeof(SirSim) * RB + sizeof(int32_t) * kSirPad * RB +
                        sizeof(int32_t) * (5 * (size_t)kSirTab + RB + 1) +
-                       sizeof(int64_t) * 5 * (size_t)n + 16 * 256;
+                       sizeof(int64_t) * (5 * (size_t)n + kSirGrid * 4) + 16 * 256;
   char *p = nullptr;
   ef_status s = graph_scratch(g, bytes, (void **)&p);
   if (s != EF_OK) return s;
@@ -516,11 +526,23 @@ extern "C" ef_status ef_sir(ef_graph *h, double beta, double mu, uint64_t seed, 
   int32_t *d_alive = d_glob + RB;
   int64_t *d_sp = (int64_t *)take(sizeof(int64_t) * 5 * (size_t)n);  // 4 orders, then counts
   int64_t *d_ic = d_sp + 4 * (int64_t)n;
+  int64_t *d_wk = (int64_t *)take(sizeof(int64_t) * kSirGrid * 4);  // arcs per attempt wavefront
   const uint64_t tb = sir_threshold(beta), tm = sir_threshold(mu);
   const int64_t global_min = ((int64_t)n + 3) / 4;
   hipError_t e = hipSuccess;
   hipLaunchKernelGGL(k_sir_zero64, dim3(sir_blocks(5 * (int64_t)n)), dim3(256), 0, st,
                      5 * (int64_t)n, d_sp);
+  hipLaunchKernelGGL(k_sir_zero64, dim3(kSirGrid * 4 / 256), dim3(256), 0, st,
+                     (int64_t)kSirGrid * 4, d_wk);
+  // kernel timing: for each step between two checks, events before the
+  // prefix, after it, after the attempts and after the update
+  std::vector<hipEvent_t> ev(phase_ms ? 4 * kSirCheck : 0, nullptr);
+  for (size_t i = 0; i < ev.size() && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
+  auto elapsed = [&](int i, int j) {
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[i], ev[j]);
+    return (double)ms;
+  };
   std::vector<SirSim> h_sims((size_t)RB);
   std::vector<int32_t> h_glob((size_t)RB);
   const unsigned gx = sir_blocks(n);
@@ -530,22 +552,33 @@ extern "C" ef_status ef_sir(ef_graph *h, double beta, double mu, uint64_t seed, 
                        state, cand);
     hipLaunchKernelGGL(k_sir_seed, dim3((R + 255) / 256), dim3(256), 0, st, n, R, seed,
                        (int64_t)r0, state, list[0], d_sims, d_nxc);
-    int32_t t = 0;
+    int32_t t = 0, pending = 0;  // steps whose events are not read yet
     while (t < t_max) {
       int32_t *cur = list[t & 1], *nxt = list[(t + 1) & 1];
+      hipEvent_t *se = phase_ms ? &ev[4 * pending] : nullptr;
+      if (se) (void)hipEventRecord(se[0], st);
       hipLaunchKernelGGL(k_sir_prep, dim3(1), dim3(1024), 0, st, R, t, d_sims, d_nxc, d_tabA,
                          d_alive);
+      if (se) (void)hipEventRecord(se[1], st);
       hipLaunchKernelGGL(k_sir_attempt, dim3(kSirGrid), dim3(256), 0, st, g.row_ptr, g.col_idx, n,
-                         seed, (int64_t)r0, t, tb, R, d_tabA, d_nxc, cur, state, cand, nxt);
+                         seed, (int64_t)r0, t, tb, R, d_tabA, d_nxc, cur, state, cand, nxt, d_wk);
+      if (se) (void)hipEventRecord(se[2], st);
       hipLaunchKernelGGL(k_sir_prep_u, dim3(1), dim3(1024), 0, st, R, d_sims, d_nxc, d_tabU);
       hipLaunchKernelGGL(k_sir_update, dim3(kSirGrid), dim3(256), 0, st, n, seed, (int64_t)r0, t,
                          tm, R, d_tabU, d_nxc, cur, state, nxt);
+      if (se) (void)hipEventRecord(se[3], st);
       ++t;
+      ++pending;
       if (t % kSirCheck == 0 || t == t_max) {
         // live simulations in the step just run (from its prefix workgroup)
         int32_t alive = 0;
         e = hipMemcpyAsync(&alive, d_alive, sizeof(int32_t), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
+        for (int32_t k = 0; phase_ms && k < pending; ++k) {
+          phase_ms[0] += elapsed(4 * k + 1, 4 * k + 2);
+          phase_ms[1] += elapsed(4 * k, 4 * k + 1) + elapsed(4 * k + 2, 4 * k + 3);
+        }
+        pending = 0;
         if (e != hipSuccess || alive == 0) break;
       }
     }
@@ -556,27 +589,33 @@ extern "C" ef_status ef_sir(ef_graph *h, double beta, double mu, uint64_t seed, 
     e = hipMemcpyAsync(h_sims.data(), d_sims, sizeof(SirSim) * R, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) break;
-    bool any = false;
+    int32_t G = 0;
     for (int32_t r = 0; r < R; ++r) {
+      if (work) work[1] += h_sims[r].fsteps;
       index[r0 + r] = h_sims[r].index;
       size[r0 + r] = h_sims[r].size;
       t_end[r0 + r] = h_sims[r].t_end;
       t_peak[r0 + r] = h_sims[r].t_peak;
-      h_glob[r] = h_sims[r].size >= global_min ? 1 : 0;
-      any = any || h_glob[r];
+      if (h_sims[r].size >= global_min) h_glob[G++] = r;
     }
-    if (!any) continue;
-    e = hipMemcpyAsync(d_glob, h_glob.data(), sizeof(int32_t) * R, hipMemcpyHostToDevice, st);
+    if (G == 0) continue;
+    e = hipMemcpyAsync(d_glob, h_glob.data(), sizeof(int32_t) * G, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) break;
     // the frontier lists are free now: levels d - 1 and d of the descendant counts
-    const unsigned gb = sir_blocks((int64_t)R * n);
+    if (phase_ms) (void)hipEventRecord(ev[0], st);
     for (int d = 1; d <= 4; ++d) {
       int32_t *lc = list[d & 1], *lp = d == 1 ? nullptr : list[(d - 1) & 1];
-      hipLaunchKernelGGL(k_sir_zero, dim3(gb), dim3(256), 0, st, (int64_t)R * n, lc);
-      hipLaunchKernelGGL(k_sir_level, dim3(gx, R), dim3(256), 0, st, n, d_glob, state, cand, lp,
+      hipLaunchKernelGGL(k_sir_zero_rows, dim3(gx, G), dim3(256), 0, st, n, d_glob, lc);
+      hipLaunchKernelGGL(k_sir_level, dim3(gx, G), dim3(256), 0, st, n, d_glob, state, cand, lp,
                          lc);
-      hipLaunchKernelGGL(k_sir_accum, dim3(gx), dim3(256), 0, st, n, R, d_glob, state, lc,
+      hipLaunchKernelGGL(k_sir_accum, dim3(gx), dim3(256), 0, st, n, G, d_glob, state, lc,
                          d_sp + (int64_t)(d - 1) * n, d == 1 ? d_ic : nullptr);
+    }
+    if (phase_ms) {
+      e = hipEventRecord(ev[3], st);
+      if (e == hipSuccess) e = hipEventSynchronize(ev[3]);
+      phase_ms[2] += elapsed(0, 3);
+      if (e != hipSuccess) break;
     }
     e = hipStreamSynchronize(st);
   }
@@ -584,7 +623,13 @@ extern "C" ef_status ef_sir(ef_graph *h, double beta, double mu, uint64_t seed, 
     e = hipMemcpyAsync(sp_sum, d_sp, sizeof(int64_t) * 4 * (size_t)n, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess)
     e = hipMemcpyAsync(inf_count, d_ic, sizeof(int64_t) * (size_t)n, hipMemcpyDeviceToHost, st);
+  std::vector<int64_t> h_wk(work ? (size_t)kSirGrid * 4 : 0);
+  if (e == hipSuccess && work)
+    e = hipMemcpyAsync(h_wk.data(), d_wk, sizeof(int64_t) * h_wk.size(), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
+  for (int64_t x : h_wk) work[0] += x;
+  for (hipEvent_t x : ev)
+    if (x) (void)hipEventDestroy(x);
   if (e != hipSuccess) return hip_status(e, "SIR simulations");
   return EF_OK;
 }

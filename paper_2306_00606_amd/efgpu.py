@@ -150,7 +150,7 @@ def lib():
     L.ef_compute.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, i32, vp, vp, vp, u32, vp]
     L.ef_compute_j3.argtypes = [vp, ctypes.c_int, vp, i32, vp, vp, vp, u32, vp]
     L.ef_sir.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_uint64, i32, i32, vp, vp,
-                         vp, vp, vp, vp, vp]
+                         vp, vp, vp, vp, vp, vp, vp]
     L.ef_stats.argtypes = [vp, ctypes.POINTER(RunStats)]
     L.ef_topk.argtypes = [vp, ctypes.c_int, ctypes.c_int, i32, vp, vp, u32, vp]
     L.ef_batch_create.argtypes = [i32, vp, i64, vp, vp, u32, vp, ctypes.POINTER(vp)]
@@ -320,25 +320,32 @@ class Graph:
         return nodes, ef
 
     def sir(self, beta: float, mu: float, seed: int, n_sims: int, t_max: int = 100000,
-            stream=None) -> dict:
+            profile: bool = False, stream=None) -> dict:
         """SIR outbreaks (ef_sir): per-simulation index, size, t_end, t_peak and,
-        over the global outbreaks, inf_count[v] and sp_sum[d-1, v] (d = 1..4)."""
+        over the global outbreaks, inf_count[v] and sp_sum[d-1, v] (d = 1..4);
+        work = (arcs walked by the attempts, frontier node-steps); with profile,
+        phase_ms = kernel time of attempts, updates and descendant counts."""
         n = self.n
         out = {"index": np.zeros(max(n_sims, 1), np.int32),
                "size": np.zeros(max(n_sims, 1), np.int32),
                "t_end": np.zeros(max(n_sims, 1), np.int32),
                "t_peak": np.zeros(max(n_sims, 1), np.int32),
                "sp_sum": np.zeros((4, max(n, 1)), np.int64),
-               "inf_count": np.zeros(max(n, 1), np.int64)}
+               "inf_count": np.zeros(max(n, 1), np.int64),
+               "work": np.zeros(2, np.int64)}
+        ph = np.zeros(3, np.float64)
         _check(lib().ef_sir(self._h, float(beta), float(mu), ctypes.c_uint64(seed & (2**64 - 1)),
                             int(n_sims), int(t_max), out["index"].ctypes.data,
                             out["size"].ctypes.data, out["t_end"].ctypes.data,
                             out["t_peak"].ctypes.data, out["sp_sum"].ctypes.data,
-                            out["inf_count"].ctypes.data, _stream_ptr(stream)))
+                            out["inf_count"].ctypes.data, out["work"].ctypes.data,
+                            ph.ctypes.data if profile else None, _stream_ptr(stream)))
         for k in ("index", "size", "t_end", "t_peak"):
             out[k] = out[k][:n_sims]
         out["sp_sum"] = out["sp_sum"][:, :n]
         out["inf_count"] = out["inf_count"][:n]
+        if profile:
+            out["phase_ms"] = {"attempts": ph[0], "updates": ph[1], "descendants": ph[2]}
         return out
 
     def features(self):

@@ -56,6 +56,9 @@ def test_sir_matches_oracle(name):
     # every infected node but the index case has an infector: order-1 sums
     # over a global outbreak add up to its size - 1
     assert got["sp_sum"][0].sum() == int((got["size"][glob] - 1).sum())
+    # work counters: every infected node is in the frontier for at least one
+    # step, and each step walks all of its arcs
+    assert got["work"][1] >= got["size"].sum() and got["work"][0] >= 0
 
 
 def test_sir_ba_1m_paper_calibration():
@@ -72,6 +75,30 @@ def test_sir_ba_1m_paper_calibration():
     sys.stderr.write(f"[sir] BA 1e6: {int(glob.sum())} global of 100\n")
     assert glob.sum() > 0
     assert np.all(got["sp_sum"][1:] >= got["sp_sum"][:-1])  # deeper subtrees are larger
+
+
+def test_sir_work_counts_bfs():
+    """beta = mu = 1: each infected node is in the frontier for exactly one
+    step, so the frontier node-steps are the outbreak sizes and the arcs walked
+    are the degrees of the infected nodes."""
+    rp, ci = gen.config_model(3000, 2.4, 5)
+    deg = np.diff(rp)
+    with efgpu.Graph(rp, ci) as g:
+        got = g.sir(1.0, 1.0, seed=12, n_sims=20, profile=True)
+    want = oracle.sir(rp, ci, 1.0, 1.0, seed=12, n_sims=20)
+    compare(got, want, "BFS")
+    # the infected set of one outbreak is the index case's component
+    import scipy.sparse as sps
+    from scipy.sparse.csgraph import connected_components
+    n = rp.size - 1
+    A = sps.csr_matrix((np.ones(ci.size), ci, rp), shape=(n, n))
+    _, lab = connected_components(A, directed=False)
+    comp_deg = np.bincount(lab, weights=deg)
+    comp_size = np.bincount(lab)
+    assert np.array_equal(got["size"], comp_size[lab[got["index"]]])
+    assert got["work"][1] == int(got["size"].sum())
+    assert got["work"][0] == int(comp_deg[lab[got["index"]]].sum())
+    assert all(v >= 0 for v in got["phase_ms"].values()) and got["phase_ms"]["attempts"] > 0
 
 
 def test_sir_two_batches():
