@@ -45,19 +45,46 @@ VALU_LANE_OPS_PEAK = 256 * 128 * 2.4e9
 # (v_log_f32, a transcendental at a quarter of the FMA rate: 4; multiply: 1),
 # credit to the row sum (1) and to the column sum (1).
 OPS_PER_CLUSTER = 8
+# The same with the score read from the centre's LDS table (tiles of big
+# centres whose degrees fit it): the table index k_p + k_q - 2 (1), row sum
+# (1), column sum (1); the read itself goes to the LDS pipe.
+OPS_PER_TABLE_CLUSTER = 3
+# the kernel's rule: a full off-diagonal 64 x 64 tile of a big centre (rows in
+# an earlier super-block of 1024 than its columns) whose largest degrees
+# satisfy k_p + k_q - 2 < TABLE_ENTRIES reads the table
+TABLE_ENTRIES = 4096
 # HBM bytes per launch of k_pairs_big<float> at this workload (R-MAT scale 22,
 # edge factor 10): FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 from two rocprofv3
 # counter runs, each counter scaled by its reading on a 1 GiB copy; mostly the
 # super-tile records the kernel writes. Taken on the current kernel (the
 # counter summaries sit with the other rocprofv3 summaries); set to None
 # whenever the kernel changes.
-PAIRS_BIG_TRAFFIC_BYTES = 2.655e9
+PAIRS_BIG_TRAFFIC_BYTES = None
 # VALU cost of one SIR attempt along an arc, in FP32-FMA-equivalent lane slots:
 # the counter (2e) K and SplitMix64's two multiplications are three 64-bit
 # products of three 32-bit multiplies each, at a quarter of the FMA rate
 # (36); three 64-bit xor-shifts (9), the 64-bit additions and xors of the
 # counter (4), the threshold compare (2) and the arc's index (3).
 SIR_OPS_PER_ARC = 54
+
+
+def table_clusters(rp, ci):
+    """Clusters of big centres (degree > 1024) that the FP32 super-tile loop
+    scores from its LDS table, by the kernel's rule on the degree-sorted rows."""
+    import numpy as np
+
+    deg = np.diff(rp).astype(np.int64)
+    total = 0
+    for v in np.flatnonzero(deg > 1024):
+        k = int(deg[v])
+        nbr = np.sort(deg[ci[rp[v]:rp[v + 1]]])
+        nb = (k + 63) // 64
+        m = nbr[np.minimum(np.arange(nb) * 64 + 63, k - 1)]  # largest degree per block
+        full = (np.arange(nb) + 1) * 64 <= k
+        rows_before = 16 * (np.arange(nb) // 16)  # row blocks of earlier super-blocks
+        fit = np.minimum(np.searchsorted(m, TABLE_ENTRIES + 2 - m, side="left"), rows_before)
+        total += int(fit[full].sum()) * 64 * 64
+    return total
 
 
 def log(msg):
@@ -386,13 +413,17 @@ def main():
 
     # dominant kernel: the super-tile pair loop (clusters of centres with k > 1024)
     if args.algo == "cluster" and args.prec == "fp32c" and st["t_pairs_big_ms"] > 0:
-        achieved = st["pairs_big"] * OPS_PER_CLUSTER / (st["t_pairs_big_ms"] * 1e-3)
+        n_tab = table_clusters(rp, ci)
+        ops = n_tab * OPS_PER_TABLE_CLUSTER + (st["pairs_big"] - n_tab) * OPS_PER_CLUSTER
+        achieved = ops / (st["t_pairs_big_ms"] * 1e-3)
         roofline = {"bound": "alu", "kernel": "k_pairs_big<float>",
                     "achieved": achieved / 1e12, "peak": VALU_LANE_OPS_PEAK / 1e12,
                     "unit": "TOP/s", "frac": achieved / VALU_LANE_OPS_PEAK,
                     "traffic": PAIRS_BIG_TRAFFIC_BYTES
                     if (args.scale, args.edge_factor) == (22, 10) else None,
-                    "ops_per_cluster": OPS_PER_CLUSTER, "clusters_per_launch": st["pairs_big"],
+                    "ops_per_cluster": OPS_PER_CLUSTER,
+                    "ops_per_table_cluster": OPS_PER_TABLE_CLUSTER,
+                    "clusters_per_launch": st["pairs_big"], "table_clusters": n_tab,
                     "avg_launch_ms": st["t_pairs_big_ms"]}
     else:
         roofline = None

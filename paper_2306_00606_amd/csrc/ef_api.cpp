@@ -213,7 +213,7 @@ ef_status ef_graph_free(ef_graph *h) {
     (void)hipFree(g.row_ptr);
     (void)hipFree(g.col_idx);
   }
-  void *arrays[] = {g.deg, g.src, g.rev, g.adj2, g.asum, g.qa, g.up_ptr, g.up_col, g.trec,
+  void *arrays[] = {g.deg, g.src, g.rev, g.adj2, g.adjs, g.asum, g.qa, g.up_ptr, g.up_col, g.trec,
                     g.up_deg, g.dn_ptr, g.dn, g.tri_zero, g.j3_seeds, g.j3_off,
                     g.tri_rec0, g.tri_list[0], g.tri_list[1], g.tri_list[2], g.tri_list[3],
                     g.fin_list,
@@ -407,6 +407,43 @@ ef_status ef_graph_load_csr(int32_t n, int64_t nnz, const int32_t *row_ptr,
   inf.nnz = nnz;
   inf.max_degree = kmax;
   inf.up_arcs = nnz / 2;
+  // degree-ordered rows of the big centres (the super-tile pair loop)
+  {
+    std::vector<int32_t> hb;
+    for (int32_t v = 0; v < n; ++v)
+      if (g.h_deg[v] > kSuper) hb.push_back(v);
+    if (!hb.empty()) {
+      ALLOC(g.adjs, sizeof(int2) * NNZ, "degree-ordered rows");
+      const int32_t nbig = (int32_t)hb.size();
+      const size_t sb = sizeof(int32_t) * 4 * NNZ, gb = sizeof(int32_t) * 2 * (size_t)nbig,
+                   bb = sizeof(int32_t) * (size_t)nbig;
+      int32_t *scratch = nullptr, *seg = nullptr, *d_big = nullptr;
+      void *temp = nullptr;
+      size_t temp_bytes = 0;
+      st = dev_alloc(g, (void **)&scratch, sb, "sort scratch");
+      if (st == EF_OK) st = dev_alloc(g, (void **)&seg, gb, "sort segments");
+      if (st == EF_OK) st = dev_alloc(g, (void **)&d_big, bb, "big centres");
+      hipError_t e = hipSuccess;
+      if (st == EF_OK) {
+        e = hipMemcpyAsync(d_big, hb.data(), bb, hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess)
+          e = launch_big_sort(g, d_big, nbig, scratch, seg, nullptr, temp_bytes, stream);
+        if (e == hipSuccess) st = dev_alloc(g, &temp, temp_bytes, "sort scratch");
+        if (e == hipSuccess && st == EF_OK)
+          e = launch_big_sort(g, d_big, nbig, scratch, seg, temp, temp_bytes, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+      }
+      dev_free(g, temp, temp_bytes);
+      dev_free(g, d_big, bb);
+      dev_free(g, seg, gb);
+      dev_free(g, scratch, sb);
+      if (st == EF_OK && e != hipSuccess) st = hip_status(e, "degree-ordered rows");
+      if (st != EF_OK) {
+        ef_graph_free(h);
+        return st;
+      }
+    }
+  }
   std::vector<int32_t> tri[4], fin;
   for (int32_t v = 0; v < n; ++v) {
     const int64_t k = g.h_deg[v];

@@ -120,6 +120,9 @@ struct Graph {
   int32_t *src = nullptr;      // source node of every arc
   int32_t *rev = nullptr;      // index of the reverse arc
   int2 *adj2 = nullptr;        // (neighbour id, neighbour degree) per arc
+  int2 *adjs = nullptr;        // rows of big centres ordered by neighbour degree (stable):
+                               // (offset of the arc in its row, neighbour degree); null
+                               // when no centre has more than kSuper neighbours
   int64_t *asum = nullptr;     // sum of neighbour degrees per node
   longlong2 *qa = nullptr;     // per node: {sum of squared neighbour degrees, sum of neighbours' asum}
   int32_t *up_ptr = nullptr;   // degree-oriented half adjacency: u -> {w : rank(w) > rank(u)}
@@ -195,6 +198,13 @@ ef_status hip_status(hipError_t e, const char *what);
 int64_t graph_prep_tmp_len(int64_t nnz);
 hipError_t launch_graph_prep(Graph &g, int32_t *tmp, int64_t *work, bool &not_symmetric,
                              hipStream_t st);
+// Degree-ordered view of the rows of the big centres big[0..nbig) (device
+// list): fills g.adjs with a stable segmented sort by neighbour degree.
+// scratch: 4 nnz int32 (keys and values, in and out); seg: 2 nbig int32
+// (segment ends); temp: the sort's scratch (temp == nullptr: only sets
+// temp_bytes).
+hipError_t launch_big_sort(Graph &g, const int32_t *big, int32_t nbig, int32_t *scratch,
+                           int32_t *seg, void *temp, size_t &temp_bytes, hipStream_t st);
 hipError_t graph_zero_count(const Graph &g, const int32_t *tmp, int64_t &count);
 hipError_t launch_zero_list(Graph &g, const int32_t *tmp, hipStream_t st);
 hipError_t launch_exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t count,

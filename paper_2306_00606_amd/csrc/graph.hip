@@ -13,6 +13,8 @@
 // ("segments": slot of {u, w} in up(u), tail length, k_u + k_w) are built
 // here, and every arc gets the index of the triangle record that holds the
 // credits to its source node (-1 when no walk writes one).
+#include <hipcub/hipcub.hpp>
+
 #include "ef_internal.h"
 
 namespace efi {
@@ -465,6 +467,61 @@ hipError_t launch_zero_list(Graph &g, const int32_t *tmp, hipStream_t st) {
   if (nup <= 0 || g.n_tri_zero <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_zero_fill, dim3(grid_for(nup, 256)), dim3(256), 0, st, tmp + 2 * nnz,
                      tmp + nnz, nup, g.tri_zero);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// degree-ordered rows of the big centres, for the super-tile pair loop: with
+// the neighbours in ascending degree, the degrees inside a 64 x 64 tile are
+// close, so most tiles can read their scores from a small table
+// ---------------------------------------------------------------------------
+__global__ void k_big_keys(const int32_t *__restrict__ row_ptr, const int2 *__restrict__ adj2,
+                           const int32_t *__restrict__ big, int32_t nbig,
+                           int32_t *__restrict__ kin, int32_t *__restrict__ vin,
+                           int32_t *__restrict__ seg_beg, int32_t *__restrict__ seg_end) {
+  for (int32_t i = blockIdx.x; i < nbig; i += gridDim.x) {
+    const int32_t v = big[i], b = row_ptr[v], e = row_ptr[v + 1];
+    if (threadIdx.x == 0) {
+      seg_beg[i] = b;
+      seg_end[i] = e;
+    }
+    for (int32_t x = b + threadIdx.x; x < e; x += blockDim.x) {
+      kin[x] = adj2[x].y;
+      vin[x] = x - b;
+    }
+  }
+}
+
+__global__ void k_big_pack(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ big,
+                           int32_t nbig, const int32_t *__restrict__ kout,
+                           const int32_t *__restrict__ vout, int2 *__restrict__ adjs) {
+  for (int32_t i = blockIdx.x; i < nbig; i += gridDim.x) {
+    const int32_t v = big[i], b = row_ptr[v], e = row_ptr[v + 1];
+    for (int32_t x = b + threadIdx.x; x < e; x += blockDim.x) adjs[x] = make_int2(vout[x], kout[x]);
+  }
+}
+
+hipError_t launch_big_sort(Graph &g, const int32_t *big, int32_t nbig, int32_t *scratch,
+                           int32_t *seg, void *temp, size_t &temp_bytes, hipStream_t st) {
+  const int64_t nnz = g.nnz;
+  int32_t *kin = scratch, *kout = scratch + nnz, *vin = scratch + 2 * nnz,
+          *vout = scratch + 3 * nnz;
+  int end_bit = 1;
+  while (end_bit < 31 && (int64_t(1) << end_bit) <= (int64_t)g.info.max_degree) ++end_bit;
+  if (temp == nullptr) {
+    return hipcub::DeviceSegmentedRadixSort::SortPairs(
+        nullptr, temp_bytes, kin, kout, vin, vout, (int)nnz, (int)nbig, seg, seg + nbig, 0,
+        end_bit, st);
+  }
+  const unsigned grid = (unsigned)std::min<int64_t>(std::max<int32_t>(nbig, 1), 65536);
+  hipLaunchKernelGGL(k_big_keys, dim3(grid), dim3(256), 0, st, g.row_ptr, g.adj2, big, nbig, kin,
+                     vin, seg, seg + nbig);
+  hipError_t e = hipcub::DeviceSegmentedRadixSort::SortPairs(
+      temp, temp_bytes, kin, kout, vin, vout, (int)nnz, (int)nbig, seg, seg + nbig, 0, end_bit,
+      st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_big_pack, dim3(grid), dim3(256), 0, st, g.row_ptr, big, nbig, kout, vout,
+                     g.adjs);
   return hipGetLastError();
 }
 

@@ -22,24 +22,21 @@
 //                     records and summed per arc in a fixed order afterwards.
 // Column partials cross wavefronts through LDS; every sum has a fixed order,
 // so results are bitwise reproducible.
+#include <type_traits>
+
 #include "ef_internal.h"
 
 namespace efi {
 
 constexpr float kNegF = -1.0e9f;
 
-// orders this wavefront's LDS accesses (written by one lane, read by another)
-__device__ __forceinline__ void wave_fence() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
 // ---------------------------------------------------------------------------
 // wave rotate: lane l receives the value of lane (l + 1) mod 64
 // ---------------------------------------------------------------------------
+// bound_ctrl is set: a full rotation has no lane without a source, and with it
+// the compiler folds the rotation into the consuming add (v_add_f32_dpp)
 __device__ __forceinline__ int rot1i(int x) {
-  return __builtin_amdgcn_mov_dpp(x, 0x134, 0xf, 0xf, false);
+  return __builtin_amdgcn_mov_dpp(x, 0x134, 0xf, 0xf, true);
 }
 __device__ __forceinline__ float rot1(float x) { return __int_as_float(rot1i(__float_as_int(x))); }
 __device__ __forceinline__ double rot1(double x) {
@@ -123,36 +120,50 @@ __device__ __forceinline__ void tile(T cp, T kq, T &Rt, T &C) {
       Rt += g;
       C = rot1(C) + g;
     }
-  } else {
+  } else if (MASKED) {
 #pragma unroll 8
     for (int s = 0; s < 64; ++s) {
       T d = cp + kq;
-      T g = MASKED ? score_masked(d) : score(d);
+      T g = score_masked(d);
       Rt += g;
       C = rot1(C) + g;
       kq = rot1(kq);
     }
+  } else {
+    // d_s(l) = cp(l) + kq(l + s). The lane that holds column q at step s
+    // holds column q + 1 at step s + 1, so d_{s+1} = rot(d_s) + cp - rot(cp):
+    // one add with the rotation folded in. All values are integers below
+    // 2^24, exact in either precision.
+    T d = cp + kq;
+    const T D = cp - rot1(cp);
+#pragma unroll 8
+    for (int s = 0; s < 64; ++s) {
+      T g = score(d);
+      Rt += g;
+      C = rot1(C) + g;
+      d = rot1(d) + D;
+    }
   }
 }
 
-// Full off-diagonal tile with the column degrees read from LDS instead of
-// rotated through the wavefront: kd points at this lane's entry of a doubled
-// copy of the 64 column degrees (kd[s] = degree of column (lane + s) mod 64),
-// so step s needs no rotation of the degree, only of the column accumulator.
-// Same result layout as tile<T, false, false>.
+// Full off-diagonal tile of a big centre with the scores read from the
+// centre's table: gt[i] = score(k_v - 2 + i), the same FP32 expression the
+// other tiles evaluate, so every cluster gets the same score bits. roff =
+// k_p - 2 for this lane's row, kq = degree of its column at step 0; every
+// index roff + kq of the tile must lie in the table (checked by the caller).
+// Same result layout as tile<T, false, false>; used by the FP32 path.
 template <typename T>
-__device__ __forceinline__ void tile_lds(T cp, const T *kd, T &Rt, T &C) {
+__device__ __forceinline__ void tile_tab(int32_t roff, int32_t kq, const float *gt, T &Rt, T &C) {
   Rt = T(0);
   C = T(0);
-  for (int s0 = 0; s0 < 64; s0 += 16) {
-    const T *kp = kd + s0;
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const T d = cp + kp[j];
-      const T g = score(d);
-      Rt += g;
-      C = rot1(C) + g;
-    }
+  // The column degree rotates on its own (an index recurrence in the style of
+  // tile() computed wrong table addresses on the device, so it is not used).
+#pragma unroll 8
+  for (int s = 0; s < 64; ++s) {
+    const T g = gt[roff + kq];
+    Rt += g;
+    C = rot1(C) + g;
+    kq = rot1i(kq);
   }
 }
 
@@ -165,9 +176,9 @@ __device__ __forceinline__ void tile_lds(T cp, const T *kd, T &Rt, T &C) {
 template <int S>
 __device__ __forceinline__ int rot_seg_i(int x) {
   if constexpr (S == 64) {
-    return __builtin_amdgcn_mov_dpp(x, 0x134, 0xf, 0xf, false);  // wave_rol:1
+    return __builtin_amdgcn_mov_dpp(x, 0x134, 0xf, 0xf, true);  // wave_rol:1
   } else if constexpr (S == 16) {
-    return __builtin_amdgcn_mov_dpp(x, 0x12F, 0xf, 0xf, false);  // row_ror:15
+    return __builtin_amdgcn_mov_dpp(x, 0x12F, 0xf, 0xf, true);  // row_ror:15
   } else {
     const int lane = threadIdx.x & 63;
     const int src = (lane & ~(S - 1)) | ((lane + 1) & (S - 1));
@@ -242,7 +253,7 @@ __device__ __forceinline__ T col_degree(const int2 *adj2, int32_t base, int32_t 
 // complete sum for index 64*(blk0+w)+lane over all pairs inside this range.
 template <typename T>
 __device__ void diag_super(const int2 *adj2, int32_t base, int32_t k, T kv4, int blk0, int nb,
-                           T (*parts)[9][64], T (*kdeg)[128], Acc<T> &out) {
+                           T (*parts)[9][64], Acc<T> &out) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (w < nb) {
     const int32_t p = 64 * (blk0 + w) + lane;
@@ -266,11 +277,7 @@ __device__ void diag_super(const int2 *adj2, int32_t base, int32_t k, T kv4, int
         if (masked) {
           tile<T, false, true>(cp, kq, Rt, C);
         } else {
-          kdeg[w][lane] = kq;
-          kdeg[w][64 + lane] = kq;
-          wave_fence();
-          tile_lds<T>(cp, &kdeg[w][lane], Rt, C);
-          wave_fence();
+          tile<T, false, false>(cp, kq, Rt, C);
         }
         parts[c][dl][(lane + 63) & 63] = C;
       }
@@ -298,7 +305,6 @@ __global__ __launch_bounds__(1024) void k_pairs_mid(const int32_t *__restrict__ 
                                                     const int2 *__restrict__ adj2,
                                                     const int32_t *__restrict__ list,
                                                     int64_t count, void *__restrict__ R) {
-  __shared__ T kdeg[kBlocksPerSuper][128];
   __shared__ T parts[kBlocksPerSuper][9][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int64_t it = blockIdx.x; it < count; it += gridDim.x) {
@@ -309,7 +315,7 @@ __global__ __launch_bounds__(1024) void k_pairs_mid(const int32_t *__restrict__ 
     zero_parts(&parts[0][0][0], nb * 9 * 64);
     __syncthreads();
     Acc<T> out;
-    diag_super<T>(adj2, base, k, (T)(k - 4), 0, nb, parts, kdeg, out);
+    diag_super<T>(adj2, base, k, (T)(k - 4), 0, nb, parts, out);
     const int32_t p = 64 * w + lane;
     if (w < nb && p < k) out.store(R, base + p);
     __syncthreads();
@@ -317,21 +323,40 @@ __global__ __launch_bounds__(1024) void k_pairs_mid(const int32_t *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// big centres: one workgroup per 1024x1024 super-tile (P, Q), P <= Q.
-// record layout: [0, 1024) row part (for P == Q: complete in-range sums),
+// big centres: one workgroup per 1024x1024 super-tile (P, Q), P <= Q, over
+// the centre's neighbours in ascending degree (adjs: (offset in the row,
+// degree)). record layout, by sorted position:
+//                [0, 1024) row part (for P == Q: complete in-range sums),
 //                [1024, 2048) column part (P < Q only).
+// In the FP32 path a full off-diagonal 64 x 64 tile whose largest row and
+// column degrees satisfy k_p + k_q - 2 < kGTab reads its scores from an LDS
+// table of score(k_v - 2 + i), i < kGTab, built once per centre and
+// workgroup: one LDS read in place of a v_log_f32 and a multiply. In
+// degree order that holds for most tiles; the others take the log.
+// LDS: the column partials (64 KB) and the table keep to 80 KB, so that two
+// workgroups fit on a compute unit (measured: one workgroup per CU with a
+// larger table is slower).
 // ---------------------------------------------------------------------------
+constexpr int kGTab = 4096;
 template <typename T>
 __global__ __launch_bounds__(1024) void k_pairs_big(const int32_t *__restrict__ row_ptr,
                                                     const int32_t *__restrict__ deg,
-                                                    const int2 *__restrict__ adj2,
+                                                    const int2 *__restrict__ adjs,
                                                     const BigCentre *__restrict__ big,
                                                     const TileItem *__restrict__ tiles,
                                                     int64_t count, void *__restrict__ rec,
                                                     const int32_t *__restrict__ agg_done) {
-  __shared__ T kdeg[kBlocksPerSuper][128];  // per wavefront: doubled column degrees
-  __shared__ T parts[kBlocksPerSuper][kBlocksPerSuper][64];
+  constexpr bool kTab = std::is_same<T, float>::value;
+  constexpr int kTabBytes = kTab ? kGTab * 4 : 0;
+  constexpr int kPartBytes = kBlocksPerSuper * kBlocksPerSuper * 64 * (int)sizeof(T);
+  // one LDS buffer: the scores of the current centre (FP32 path) first, at
+  // address 0, so that a table read needs no base added; then the partials
+  __shared__ __align__(16) unsigned char lds[kTabBytes + kPartBytes];
+  float *gtab = reinterpret_cast<float *>(lds);
+  T(*parts)[kBlocksPerSuper][64] = reinterpret_cast<T(*)[kBlocksPerSuper][64]>(lds + kTabBytes);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int32_t tab_v = -1;                       // centre whose scores gtab holds
+  const int2 *adj2 = adjs;
   for (int64_t it = blockIdx.x; it < count; it += gridDim.x) {
     const TileItem ti = tiles[it];
     if (agg_done && agg_done[ti.big]) continue;  // uniform per workgroup
@@ -347,13 +372,23 @@ __global__ __launch_bounds__(1024) void k_pairs_big(const int32_t *__restrict__ 
       __syncthreads();
       Acc<T> out;
       diag_super<T>(adj2, base, k, kv4, kBlocksPerSuper * P, nbQ,
-                    reinterpret_cast<T(*)[9][64]>(&parts[0][0][0]), kdeg, out);
+                    reinterpret_cast<T(*)[9][64]>(&parts[0][0][0]), out);
       if (w < nbQ) out.store(rec, rbase + 64 * w + lane);
     } else {
       // P < Q: all 16 row blocks of P are full
       const int32_t p = kSuper * P + 64 * w + lane;
-      const T cp = kv4 + (T)adj2[base + p].y;
+      const int32_t kp = adj2[base + p].y;
+      const T cp = kv4 + (T)kp;
       const bool ragged_q = (kSuper * Q + 64 * nbQ) > k;
+      // the largest row degree of this wavefront's block (rows ascend)
+      const int32_t kp_max = __shfl(kp, 63, 64);
+      if (kTab && v != tab_v) {  // uniform: one centre per work item
+        const float d0 = (float)(k - 2);
+        for (int i = threadIdx.x; i < kGTab; i += blockDim.x)
+          gtab[i] = score(d0 + (float)i);
+        __syncthreads();
+        tab_v = v;
+      }
       Acc<T> out;
       for (int dl = 0; dl < nbQ; ++dl) {
         const int c = (w + dl) % nbQ;
@@ -362,12 +397,10 @@ __global__ __launch_bounds__(1024) void k_pairs_big(const int32_t *__restrict__ 
         T Rt, C;
         if (ragged_q && c == nbQ - 1) {
           tile<T, false, true>(cp, kq, Rt, C);
+        } else if (kTab && kp_max + __shfl((int32_t)kq, 63, 64) - 2 < kGTab) {
+          tile_tab<T>(kp - 2, (int32_t)kq, gtab, Rt, C);
         } else {
-          kdeg[w][lane] = kq;
-          kdeg[w][64 + lane] = kq;
-          wave_fence();
-          tile_lds<T>(cp, &kdeg[w][lane], Rt, C);
-          wave_fence();
+          tile<T, false, false>(cp, kq, Rt, C);
         }
         parts[c][w][(lane + 63) & 63] = C;
         out.add(Rt);
@@ -526,12 +559,14 @@ __global__ __launch_bounds__(1024) void k_pairs_agg(const int32_t *__restrict__ 
   }
 }
 
-// Per-arc sum of the super-tile records of big centres, fixed order:
-// R[p] = sum_{Q >= b} row part of (b, Q)  +  sum_{P < b} column part of (P, b)
+// Per-arc sum of the super-tile records of big centres, fixed order, for the
+// neighbour at sorted position p (stored at its arc, offset adjs[base + p].x):
+// R = sum_{Q >= b} row part of (b, Q)  +  sum_{P < b} column part of (P, b)
 // One workgroup per (big centre, super-block b): the 1024 arcs of block b.
 template <typename T>
 __global__ __launch_bounds__(256) void k_arc_reduce(const int32_t *__restrict__ row_ptr,
                                                     const int32_t *__restrict__ deg,
+                                                    const int2 *__restrict__ adjs,
                                                     const BigCentre *__restrict__ big,
                                                     const int2 *__restrict__ items,
                                                     int64_t nitems, const void *__restrict__ rec,
@@ -555,7 +590,7 @@ __global__ __launch_bounds__(256) void k_arc_reduce(const int32_t *__restrict__ 
         const int64_t t = bc.rec_base + (int64_t)P * ns - (int64_t)P * (P - 1) / 2 + (b - P);
         a.add_stored(rec, t * kRecEntries + kSuper + j);
       }
-      a.store(R, base + p);
+      a.store(R, base + adjs[base + p].x);  // sorted position -> arc of the row
     }
   }
 }
@@ -734,11 +769,12 @@ static hipError_t pairs_impl(const Graph &g, const Bins &b, void *R, void *recor
                        g.row_ptr, g.deg, g.adj2, b.big, b.counters, agg_done, R);
   if (b.n_tiles > 0)
     hipLaunchKernelGGL(k_pairs_big<T>, dim3(capped(b.n_tiles, 1 << 20)), dim3(1024), 0, st,
-                       g.row_ptr, g.deg, g.adj2, b.big, b.tiles, b.n_tiles, records, agg_done);
+                       g.row_ptr, g.deg, g.adjs, b.big, b.tiles, b.n_tiles, records, agg_done);
   if (ev_big) (void)hipEventRecord(ev_big, st);
   if (b.n_sblocks > 0)
     hipLaunchKernelGGL(k_arc_reduce<T>, dim3(capped(b.n_sblocks, 1 << 20)), dim3(256), 0, st,
-                       g.row_ptr, g.deg, b.big, b.sblocks, b.n_sblocks, records, R, agg_done);
+                       g.row_ptr, g.deg, g.adjs, b.big, b.sblocks, b.n_sblocks, records, R,
+                       agg_done);
   return hipGetLastError();
 }
 

@@ -142,6 +142,34 @@ def test_hub_graph(algo, prec):
     assert_parity(ef, D, N, oN, oD, oE, prec, "hub graph")
 
 
+def table_edge_graph():
+    """Hub H = 0 of degree 9000 and centre C = 1 of degree exactly 2048: C's
+    neighbours in degree order end with H, so C's last 64-column block is full
+    and holds a degree above the score table's reach (those tiles take the
+    log), while its other tiles and all of H's read the table; some of C's
+    neighbours are linked in pairs (triangles through C and H)."""
+    rs = np.random.default_rng(7)
+    n = 9100
+    hub = np.arange(2, 9002, dtype=np.int32)                      # H's 9000 neighbours, with C
+    hub[-1] = 1
+    cn = rs.choice(np.arange(2, 9002), 2047, replace=False).astype(np.int32)
+    pairs = cn[:600].reshape(-1, 2)
+    e = rs.integers(9002, n, size=(300, 2)).astype(np.int32)
+    src = np.concatenate([np.zeros(9000, np.int32), np.ones(2047, np.int32), pairs[:, 0], e[:, 0]])
+    dst = np.concatenate([hub, cn, pairs[:, 1], e[:, 1]])
+    return gen.from_edges(n, src, dst)
+
+
+@pytest.mark.parametrize("prec", ["fp32c", "fp64"])
+def test_score_table_and_log_tiles(prec):
+    rp, ci = table_edge_graph()
+    deg = np.diff(rp)
+    assert deg[0] == 9000 and deg[1] == 2048
+    ef, D, N = run_all(rp, ci, "cluster", prec)
+    oN, oD, oE = oracle.ef(rp, ci, threads=8)
+    assert_parity(ef, D, N, oN, oD, oE, prec, "score table edge")
+
+
 def test_selected_seeds_with_duplicates():
     rp, ci = hub_graph()
     seeds = np.array([0, 1, 5, 0, 5999, 17, 1, 2, 3001], np.int32)
