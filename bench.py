@@ -59,7 +59,7 @@ TABLE_ENTRIES = 4096
 # super-tile records the kernel writes. Taken on the current kernel (the
 # counter summaries sit with the other rocprofv3 summaries); set to None
 # whenever the kernel changes.
-PAIRS_BIG_TRAFFIC_BYTES = None
+PAIRS_BIG_TRAFFIC_BYTES = 2.655e9
 # VALU cost of one SIR attempt along an arc, in FP32-FMA-equivalent lane slots:
 # the counter (2e) K and SplitMix64's two multiplications are three 64-bit
 # products of three 32-bit multiplies each, at a quarter of the FMA rate
