@@ -165,6 +165,9 @@ __device__ __forceinline__ int32_t tri_segs(int4 e, int32_t cnt, int tid, L &lds
 // scored and credited with every lane busy, so the hit path does not run
 // divergently on almost every step.
 constexpr int kQueue = 128;
+// tri_walk drains once the queue holds 64 hits, so up to 63 wait while a
+// wavefront appends up to 64 more: indices reach 126
+static_assert(kQueue >= 127, "the hit queue must hold 63 waiting + 64 new hits");
 
 template <typename T, int SLOTS, int MAXM, int MAXS>
 __device__ __forceinline__ void tri_walk(const int32_t *__restrict__ up_col,
