@@ -44,9 +44,11 @@ def build_gen():
 
 
 def build_oracle():
-    src = os.path.join(ROOT, "oracle", "ef_oracle.c")
-    out = os.path.join(ROOT, "oracle", "liboracle.so")
-    _run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", src, "-lm",
+    """The CPU oracle (test infrastructure): every C source under oracle/."""
+    d = os.path.join(ROOT, "oracle")
+    srcs = sorted(os.path.join(d, f) for f in os.listdir(d) if f.endswith(".c"))
+    out = os.path.join(d, "liboracle.so")
+    _run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp"] + srcs + ["-lm",
           "-o", out + ".tmp"])
     os.replace(out + ".tmp", out)
     return out
