@@ -114,3 +114,16 @@ def test_union_and_batch_validation_on_host():
                                      efgpu.EF_VALIDATE, None, ctypes.byref(h))
     assert st == 6  # EF_ERR_RANGE
     assert "leaves graph" in efgpu.last_error()
+
+
+def test_package_build_compiles_the_whole_oracle():
+    """The package build (run by the entry point's build()) compiles every C
+    source of the oracle, so the library it leaves exports the Expected Force
+    and the SIR functions that the tests load."""
+    from paper_2306_00606_amd import build as b
+
+    path = b.build_oracle()
+    lib = ctypes.CDLL(path)
+    for name in ("oracle_ef", "oracle_ef3", "oracle_histogram", "oracle_histogram3",
+                 "oracle_splitmix64", "oracle_sir"):
+        assert hasattr(lib, name), name
