@@ -458,6 +458,7 @@ ef_status ef_graph_load_csr(int32_t n, int64_t nnz, const int32_t *row_ptr,
       g.all_pairs_small += k * (k - 1) / 2;
     } else if (k > kSmallMax && k <= kSuper) {
       g.all_mid++;
+      g.all_midc[mid_class((int32_t)k)]++;
       g.all_pairs_mid += k * (k - 1) / 2;
     } else if (k > kSuper) {
       const int64_t ns = (k + kSuper - 1) / kSuper;
@@ -602,6 +603,7 @@ static void host_bins(const Graph &g, const int32_t *centres, int64_t count, Bin
   b.pairs_small = b.pairs_mid = b.pairs_big = 0;
   b.n_sblocks = 0;
   for (auto &c : b.n_smallb) c = 0;
+  for (auto &c : b.n_midc) c = 0;
   for (int64_t i = 0; i < count; ++i) {
     const int64_t k = g.h_deg[centres ? centres[i] : i];
     if (k < 2) continue;
@@ -611,6 +613,7 @@ static void host_bins(const Graph &g, const int32_t *centres, int64_t count, Bin
       b.pairs_small += k * (k - 1) / 2;
     } else if (k <= kSuper) {
       b.n_mid++;
+      b.n_midc[mid_class((int32_t)k)]++;
       b.pairs_mid += k * (k - 1) / 2;
     } else {
       const int64_t ns = (k + kSuper - 1) / kSuper;
@@ -623,7 +626,7 @@ static void host_bins(const Graph &g, const int32_t *centres, int64_t count, Bin
 }
 
 static ef_status alloc_bins(Graph &g, Bins &b) {
-  const size_t bytes = sizeof(int32_t) * (size_t)(b.n_small + b.n_mid + 8) + 4 * 256 +
+  const size_t bytes = sizeof(int32_t) * (size_t)(b.n_small + 2 * b.n_mid + 16) + 8 * 256 +
                        sizeof(BigCentre) * (size_t)(b.n_big + 1) +
                        sizeof(int32_t) * (size_t)(b.n_big + 1) +
                        sizeof(TileItem) * (size_t)(b.n_tiles + 1) +
@@ -636,10 +639,12 @@ static ef_status alloc_bins(Graph &g, Bins &b) {
     p += (n + 255) & ~(size_t)255;
     return r;
   };
-  b.counters = (int32_t *)take(sizeof(int32_t) * 8);
+  b.counters = (int32_t *)take(sizeof(int32_t) * 16);
   for (int i = 0; i < 4; ++i)
     b.small[i] = (int32_t *)take(sizeof(int32_t) * (size_t)(b.n_smallb[i] + 1));
   b.mid = (int32_t *)take(sizeof(int32_t) * (size_t)(b.n_mid + 1));
+  for (int c = 0; c < 3; ++c)
+    b.midc[c] = (int32_t *)take(sizeof(int32_t) * (size_t)(b.n_midc[c] + 1));
   b.big = (BigCentre *)take(sizeof(BigCentre) * (size_t)(b.n_big + 1));
   b.agg_done = (int32_t *)take(sizeof(int32_t) * (size_t)(b.n_big + 1));
   b.tiles = (TileItem *)take(sizeof(TileItem) * (size_t)(b.n_tiles + 1));
@@ -741,6 +746,7 @@ extern "C" ef_status ef_compute(ef_graph *h, ef_algo algo, ef_prec prec, const i
     b.n_small = g.all_small;
     for (int k = 2; k <= kSmallMax; ++k) b.n_smallb[small_bin(k, b.thr)] += g.all_small_deg[k];
     b.n_mid = g.all_mid;
+    for (int c = 0; c < 3; ++c) b.n_midc[c] = g.all_midc[c];
     b.n_big = g.all_big;
     b.n_tiles = g.all_tiles;
     b.pairs_small = g.all_pairs_small;

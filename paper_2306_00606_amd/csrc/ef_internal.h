@@ -162,6 +162,7 @@ struct Graph {
   int64_t n_tri[4] = {0, 0, 0, 0};
   // bin counts for the all-nodes centre set
   int64_t all_small = 0, all_mid = 0, all_big = 0, all_tiles = 0;
+  int64_t all_midc[3] = {0, 0, 0};
   int64_t all_small_deg[kSmallMax + 1] = {};  // centres of each degree <= 64
   SmallThr thr;                               // current small-bin thresholds
   int64_t all_pairs_small = 0, all_pairs_mid = 0, all_pairs_big = 0;
@@ -215,15 +216,25 @@ int64_t scan_tmp_len(int64_t count);
 hipError_t launch_zero_i32(int32_t *p, int32_t count, hipStream_t st);
 
 // work lists
+// Mid centres are packed by their number of 64-neighbour blocks: up to 4
+// blocks, 4 centres per 16-wavefront workgroup; 5-8 blocks, 2; 9-16, 1.
+__host__ __device__ inline int mid_class(int32_t k) {
+  const int nb = (k + 63) >> 6;
+  return nb <= 4 ? 0 : nb <= 8 ? 1 : 2;
+}
+
 struct Bins {
   SmallThr thr;
   int32_t *small[4] = {nullptr, nullptr, nullptr, nullptr};  // centre ids per segment size
   int64_t n_smallb[4] = {0, 0, 0, 0};
   int32_t *mid = nullptr;
+  int32_t *midc[3] = {nullptr, nullptr, nullptr};  // mid centres per class (mid_class)
+  int64_t n_midc[3] = {0, 0, 0};
   BigCentre *big = nullptr;
   TileItem *tiles = nullptr;
   int2 *sblocks = nullptr;       // (big-centre index, super-block) reduction items
-  int32_t *counters = nullptr;   // [0..3] small, [4] mid, [5] big, [6] tiles, [7] sblocks
+  int32_t *counters = nullptr;   // [0..3] small, [4] mid, [5] big, [6] tiles, [7] sblocks,
+                                 // [8..10] mid classes
   int32_t *agg_done = nullptr;   // per big centre: 1 = pair sums done by aggregation
   int64_t n_small = 0, n_mid = 0, n_big = 0, n_tiles = 0;  // host-known counts
   int64_t pairs_small = 0, pairs_mid = 0, pairs_big = 0;     // clusters per bin

@@ -247,14 +247,16 @@ __device__ __forceinline__ T col_degree(const int2 *adj2, int32_t base, int32_t 
 
 // Diagonal block of blocks (a centre's whole pair triangle for mid centres,
 // or a diagonal super-tile for big centres). Blocks blk0 .. blk0+nb-1 of the
-// centre's neighbour list; wavefront w owns row block blk0 + w.
+// centre's neighbour list; wavefront w (of the group working on this centre)
+// owns row block blk0 + w. Every thread of the workgroup calls it the same
+// number of times (it holds one workgroup barrier).
 // parts[c][delta][64]: column partials, zeroed by the caller.
 // On return (after the final barrier), wavefront w's lanes hold in `out` the
 // complete sum for index 64*(blk0+w)+lane over all pairs inside this range.
 template <typename T>
 __device__ void diag_super(const int2 *adj2, int32_t base, int32_t k, T kv4, int blk0, int nb,
-                           T (*parts)[9][64], Acc<T> &out) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+                           T (*parts)[9][64], int w, Acc<T> &out) {
+  const int lane = threadIdx.x & 63;
   if (w < nb) {
     const int32_t p = 64 * (blk0 + w) + lane;
     const bool rvalid = p < k;
@@ -297,28 +299,63 @@ __device__ __forceinline__ void zero_parts(T *p, int count) {
 }
 
 // ---------------------------------------------------------------------------
-// mid centres: one 16-wavefront workgroup per centre (64 < k <= 1024)
+// mid centres (64 < k <= 1024): G centres per 16-wavefront workgroup, 16/G
+// wavefronts each (G = 4, 2, 1 for up to 4, 8, 16 blocks of 64 neighbours)
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int G>
 __global__ __launch_bounds__(1024) void k_pairs_mid(const int32_t *__restrict__ row_ptr,
                                                     const int32_t *__restrict__ deg,
                                                     const int2 *__restrict__ adj2,
                                                     const int32_t *__restrict__ list,
                                                     int64_t count, void *__restrict__ R) {
-  __shared__ T parts[kBlocksPerSuper][9][64];
+  constexpr int WPG = kBlocksPerSuper / G;  // wavefronts per centre
+  __shared__ T parts[G][WPG][9][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int64_t it = blockIdx.x; it < count; it += gridDim.x) {
-    const int32_t v = list[it];
-    const int32_t k = deg[v];
-    const int32_t base = row_ptr[v];
+  const int grp = w / WPG, wl = w % WPG;
+  const int64_t ngroups = (count + G - 1) / G;
+  for (int64_t gi = blockIdx.x; gi < ngroups; gi += gridDim.x) {
+    const int64_t it = gi * G + grp;
+    const bool have = it < count;  // a group without a centre still meets the barriers
+    const int32_t v = have ? list[it] : 0;
+    const int32_t k = have ? deg[v] : 0;
+    const int32_t base = have ? row_ptr[v] : 0;
     const int nb = (k + 63) >> 6;
-    zero_parts(&parts[0][0][0], nb * 9 * 64);
+    zero_parts(&parts[0][0][0][0], G * WPG * 9 * 64);
     __syncthreads();
     Acc<T> out;
-    diag_super<T>(adj2, base, k, (T)(k - 4), 0, nb, parts, out);
-    const int32_t p = 64 * w + lane;
-    if (w < nb && p < k) out.store(R, base + p);
+    diag_super<T>(adj2, base, k, (T)(k - 4), 0, nb, parts[grp], wl, out);
+    const int32_t p = 64 * wl + lane;
+    if (wl < nb && p < k) out.store(R, base + p);
     __syncthreads();
+  }
+}
+
+// mid centres into their classes (order within a class is not fixed; every
+// centre's sums are independent of it)
+__global__ __launch_bounds__(256) void k_mid_split(const int32_t *__restrict__ deg,
+                                                   const int32_t *__restrict__ mid, int64_t n_mid,
+                                                   int32_t *__restrict__ c0,
+                                                   int32_t *__restrict__ c1,
+                                                   int32_t *__restrict__ c2,
+                                                   int32_t *__restrict__ counters) {
+  const int lane = threadIdx.x & 63;
+  const unsigned long long below = (1ull << lane) - 1;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < n_mid;
+       base += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = base + lane;
+    const int32_t v = i < n_mid ? mid[i] : 0;
+    const int c = i < n_mid ? mid_class(deg[v]) : -1;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const unsigned long long m = __ballot(c == q);
+      if (m == 0) continue;
+      const int lead = __ffsll((unsigned long long)m) - 1;
+      int32_t at = 0;
+      if (lane == lead) at = atomicAdd(&counters[8 + q], __popcll(m));
+      at = __shfl(at, lead, 64);
+      int32_t *dst = q == 0 ? c0 : q == 1 ? c1 : c2;
+      if (c == q) dst[at + __popcll(m & below)] = v;
+    }
   }
 }
 
@@ -372,7 +409,7 @@ __global__ __launch_bounds__(1024) void k_pairs_big(const int32_t *__restrict__ 
       __syncthreads();
       Acc<T> out;
       diag_super<T>(adj2, base, k, kv4, kBlocksPerSuper * P, nbQ,
-                    reinterpret_cast<T(*)[9][64]>(&parts[0][0][0]), out);
+                    reinterpret_cast<T(*)[9][64]>(&parts[0][0][0]), w, out);
       if (w < nbQ) out.store(rec, rbase + 64 * w + lane);
     } else {
       // P < Q: all 16 row blocks of P are full
@@ -731,7 +768,7 @@ static unsigned capped(int64_t blocks, int64_t cap) {
 
 hipError_t launch_bin_centres(const Graph &g, const int32_t *centres, int32_t n_centres,
                               Bins &b, hipStream_t st) {
-  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, b.counters, 8);
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, b.counters, 16);
   if (n_centres <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_bin, dim3(capped((n_centres + 256 * kBinPer - 1) / (256 * kBinPer), 4096)),
                      dim3(256), 0, st,
@@ -740,6 +777,9 @@ hipError_t launch_bin_centres(const Graph &g, const int32_t *centres, int32_t n_
   if (b.n_big > 0)
     hipLaunchKernelGGL(k_expand_tiles, dim3(capped(b.n_big, 65536)), dim3(256), 0, st, b.big,
                        b.counters, b.tiles, b.sblocks);
+  if (b.n_mid > 0)
+    hipLaunchKernelGGL(k_mid_split, dim3(capped((b.n_mid + 255) / 256, 4096)), dim3(256), 0, st,
+                       g.deg, b.mid, b.n_mid, b.midc[0], b.midc[1], b.midc[2], b.counters);
   return hipGetLastError();
 }
 
@@ -760,9 +800,15 @@ static hipError_t pairs_impl(const Graph &g, const Bins &b, void *R, void *recor
     hipLaunchKernelGGL((k_pairs_small<T, 64>), dim3(capped((b.n_smallb[3] + 3) / 4, 1 << 20)),
                        dim3(256), 0, st, g.row_ptr, g.deg, g.adj2, b.small[3], b.n_smallb[3], R);
   if (ev_small) (void)hipEventRecord(ev_small, st);
-  if (b.n_mid > 0)
-    hipLaunchKernelGGL(k_pairs_mid<T>, dim3(capped(b.n_mid, 1 << 20)), dim3(1024), 0, st,
-                       g.row_ptr, g.deg, g.adj2, b.mid, b.n_mid, R);
+  if (b.n_midc[0] > 0)
+    hipLaunchKernelGGL((k_pairs_mid<T, 4>), dim3(capped((b.n_midc[0] + 3) / 4, 1 << 20)),
+                       dim3(1024), 0, st, g.row_ptr, g.deg, g.adj2, b.midc[0], b.n_midc[0], R);
+  if (b.n_midc[1] > 0)
+    hipLaunchKernelGGL((k_pairs_mid<T, 2>), dim3(capped((b.n_midc[1] + 1) / 2, 1 << 20)),
+                       dim3(1024), 0, st, g.row_ptr, g.deg, g.adj2, b.midc[1], b.n_midc[1], R);
+  if (b.n_midc[2] > 0)
+    hipLaunchKernelGGL((k_pairs_mid<T, 1>), dim3(capped(b.n_midc[2], 1 << 20)), dim3(1024), 0,
+                       st, g.row_ptr, g.deg, g.adj2, b.midc[2], b.n_midc[2], R);
   if (ev_mid) (void)hipEventRecord(ev_mid, st);
   if (agg_done && b.n_big > 0)
     hipLaunchKernelGGL(k_pairs_agg<T>, dim3(capped(b.n_big, 1 << 16)), dim3(1024), 0, st,
