@@ -546,11 +546,13 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_wave(
 // each wavefront walking a contiguous share of a chunk's sequence. BITMAP:
 // membership from bm + slot * words, slot = index in the list.
 // Minimum wavefronts per SIMD asked of the compiler for a per-seed bin: 8
-// (64 VGPRs, a few spilled) where the LDS allows two workgroups of 16 or four
-// of 8 on a compute unit. The 2-hop stream waits on memory, and the doubled
-// occupancy outweighs the spills: 499 -> 408 ms per step at R-MAT scale 22.
-// The 16384-slot bin is held to one workgroup per CU by its LDS.
-constexpr int seed_block_min_waves(int slots) { return slots == 16384 ? 1 : 8; }
+// (64 VGPRs, a few spilled) for the 2048- and 8192-slot hashes, which then
+// fit four 8-wavefront or two 16-wavefront workgroups on a compute unit. The
+// 2-hop stream waits on memory, and the doubled occupancy outweighs the
+// spills (at R-MAT scale 22: 174.6 -> 151.6 and 181.9 -> 114.6 ms). The
+// bitmap bin gained nothing that way; the 16384-slot bin is held to one
+// workgroup per CU by its LDS.
+constexpr int seed_block_min_waves(int slots) { return slots == 2048 || slots == 8192 ? 8 : 1; }
 
 template <typename T, int SLOTS, int MAXK, int WPB, bool BITMAP>
 __global__ __launch_bounds__(64 * WPB, seed_block_min_waves(SLOTS)) void k_seed_block(
