@@ -1,4 +1,4 @@
-"""Training driver and evaluation of the learned EF surrogate.
+"""Training loop and evaluation of the learned EF surrogate.
 
 Labelled sets come from the exact kernel of this library (cluster-centric,
 FP32C) on graphs drawn from the three exact-path generators at training
