@@ -66,6 +66,13 @@ PAIRS_BIG_TRAFFIC_BYTES = 2.655e9
 # (36); three 64-bit xor-shifts (9), the 64-bit additions and xors of the
 # counter (4), the threshold compare (2) and the arc's index (3).
 SIR_OPS_PER_ARC = 54
+# HBM bytes of the attempt kernels per call on the SIR workload below (BA
+# n = 1e6, m = 5, 300 outbreaks, seed 2306): FETCH_SIZE x 2.0 + WRITE_SIZE x
+# 1.0 summed over the call's launches, from two rocprofv3 counter runs (the
+# counter summaries sit with the other rocprofv3 summaries); None whenever
+# the kernel changes. Mostly whole lines fetched for the row bounds of each
+# frontier node and the column entry of each successful draw.
+SIR_ATTEMPT_TRAFFIC_BYTES = 25.1e9
 
 
 def table_clusters(rp, ci):
@@ -237,7 +244,8 @@ def bench_sir(runs, with_cpu):
            "phases_ms": {k: round(v, 4) for k, v in ph.items()},
            "roofline": {"bound": "alu", "kernel": "k_sir_attempt",
                         "achieved": achieved / 1e12, "peak": VALU_LANE_OPS_PEAK / 1e12,
-                        "unit": "TOP/s", "frac": achieved / VALU_LANE_OPS_PEAK, "traffic": None,
+                        "unit": "TOP/s", "frac": achieved / VALU_LANE_OPS_PEAK,
+                        "traffic": SIR_ATTEMPT_TRAFFIC_BYTES,
                         "ops_per_arc": SIR_OPS_PER_ARC, "arcs_per_run": arcs,
                         "kernel_ms_per_run": ph["attempts"]},
            "global_outbreaks": int(glob.sum()), "mean_global_size": float(o["size"][glob].mean())
