@@ -11,6 +11,7 @@
 #include <string>
 #include <vector>
 
+#include "csr_check.h"
 #include "ef_internal.h"
 
 
@@ -142,65 +143,10 @@ ef_status ef_device_count(int32_t *count) {
 }
 
 ef_status ef_validate_csr(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx) {
-  if (n < 0 || nnz < 0) {
-    set_error("ef_validate_csr: negative size (n=%d, nnz=%lld)", n, (long long)nnz);
-    return EF_ERR_ARG;
-  }
-  if (nnz >= (int64_t)INT32_MAX) {
-    set_error("ef_validate_csr: nnz=%lld does not fit int32 offsets", (long long)nnz);
-    return EF_ERR_OVERFLOW;
-  }
-  if (!row_ptr || (nnz > 0 && !col_idx)) {
-    set_error("ef_validate_csr: null array");
-    return EF_ERR_ARG;
-  }
-  if (row_ptr[0] != 0) {
-    set_error("row_ptr[0] = %d, expected 0", row_ptr[0]);
-    return EF_ERR_RANGE;
-  }
-  for (int32_t v = 0; v < n; ++v) {
-    if (row_ptr[v + 1] < row_ptr[v]) {
-      set_error("row_ptr decreases at row %d", v);
-      return EF_ERR_UNSORTED;
-    }
-  }
-  if ((int64_t)row_ptr[n] != nnz) {
-    set_error("row_ptr[n] = %d but nnz = %lld", row_ptr[n], (long long)nnz);
-    return EF_ERR_RANGE;
-  }
-  for (int32_t v = 0; v < n; ++v) {
-    for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
-      const int32_t x = col_idx[e];
-      if (x < 0 || x >= n) {
-        set_error("row %d: neighbour %d out of range [0, %d)", v, x, n);
-        return EF_ERR_RANGE;
-      }
-      if (x == v) {
-        set_error("row %d: self-loop", v);
-        return EF_ERR_SELF_LOOP;
-      }
-      if (e > row_ptr[v]) {
-        if (col_idx[e - 1] == x) {
-          set_error("row %d: neighbour %d listed twice", v, x);
-          return EF_ERR_DUPLICATE;
-        }
-        if (col_idx[e - 1] > x) {
-          set_error("row %d: neighbours not ascending at position %d", v, e - row_ptr[v]);
-          return EF_ERR_UNSORTED;
-        }
-      }
-    }
-  }
-  for (int32_t v = 0; v < n; ++v) {
-    for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
-      const int32_t x = col_idx[e];
-      if (!std::binary_search(col_idx + row_ptr[x], col_idx + row_ptr[x + 1], v)) {
-        set_error("arc %d->%d has no reverse arc %d->%d", v, x, x, v);
-        return EF_ERR_NOT_SYMMETRIC;
-      }
-    }
-  }
-  return EF_OK;
+  char msg[256] = "";
+  const ef_status s = csr_validate(n, nnz, row_ptr, col_idx, msg, sizeof(msg));
+  if (s != EF_OK) set_error("ef_validate_csr: %s", msg);
+  return s;
 }
 
 ef_status ef_graph_free(ef_graph *h) {
@@ -249,16 +195,16 @@ ef_status ef_graph_load_csr(int32_t n, int64_t nnz, const int32_t *row_ptr,
     set_error("ef_graph_load_csr: nnz=%lld does not fit int32 offsets", (long long)nnz);
     return EF_ERR_OVERFLOW;
   }
-  int dev = 0;
-  ef_status st = check_device(&dev);
-  if (st != EF_OK) return st;
   hipStream_t stream = (hipStream_t)hip_stream;
   const bool devptr = (flags & EF_DEVICE_PTRS) != 0;
+  int dev = 0;
+  ef_status st = EF_OK;
 
   // host view of the CSR (needed for validation and for sizing work lists)
   std::vector<int32_t> h_rp, h_ci;
   const int32_t *hrp = row_ptr, *hci = col_idx;
   if (devptr) {
+    if ((st = check_device(&dev)) != EF_OK) return st;
     h_rp.resize((size_t)n + 1);
     hipError_t e = hipMemcpy(h_rp.data(), row_ptr, sizeof(int32_t) * ((size_t)n + 1),
                              hipMemcpyDeviceToHost);
@@ -276,9 +222,16 @@ ef_status ef_graph_load_csr(int32_t n, int64_t nnz, const int32_t *row_ptr,
   if (flags & EF_VALIDATE) {
     st = ef_validate_csr(n, nnz, hrp, hci);
     if (st != EF_OK) return st;
-  } else if (hrp[0] != 0 || (int64_t)hrp[n] != nnz) {
-    set_error("row_ptr[0] must be 0 and row_ptr[n] must equal nnz");
-    return EF_ERR_RANGE;
+  } else {
+    // Without the full validation the arrays must still be safe to index
+    // before any kernel reads them: offsets are checked here, neighbour ids
+    // here for host input and by a device pass for device input.
+    char msg[256] = "";
+    st = csr_check_bounds(n, nnz, hrp, devptr ? nullptr : hci, msg, sizeof(msg));
+    if (st != EF_OK) {
+      set_error("ef_graph_load_csr: %s", msg);
+      return st;
+    }
   }
   int32_t kmax = 0;
   for (int32_t v = 0; v < n; ++v) kmax = std::max(kmax, hrp[v + 1] - hrp[v]);
@@ -286,6 +239,20 @@ ef_status ef_graph_load_csr(int32_t n, int64_t nnz, const int32_t *row_ptr,
     set_error("max degree %d exceeds %d (exact cluster degrees / int64 sums)", kmax, kMaxDegree);
     return EF_ERR_OVERFLOW;
   }
+  // the arrays every graph holds, against EF_MAX_DEVICE_BYTES, before the
+  // device is touched (graph-dependent arrays are accounted as allocated)
+  {
+    const int64_t n1 = (int64_t)n + 1, m = std::max<int64_t>(nnz, 1),
+                  mu = std::max<int64_t>(nnz / 2, 1), nn = std::max<int64_t>(n, 1);
+    const int64_t need = (devptr ? 0 : 4 * n1 + 4 * m) + 4 * nn + (4 + 4 + 8 + 4) * m +
+                         (8 + 16) * nn + 2 * 4 * n1 + (4 + 4 + 16) * mu + 256;
+    if (need > max_device_bytes()) {
+      set_error("ef_graph_load_csr: the graph's %lld device bytes would exceed "
+                "EF_MAX_DEVICE_BYTES", (long long)need);
+      return EF_ERR_NOMEM;
+    }
+  }
+  if (!devptr && (st = check_device(&dev)) != EF_OK) return st;
 
   ef_graph *h = new (std::nothrow) ef_graph();
   if (!h) {
@@ -333,6 +300,24 @@ ef_status ef_graph_load_csr(int32_t n, int64_t nnz, const int32_t *row_ptr,
   ALLOC(g.dn_ptr, sizeof(int32_t) * N1, "dn_ptr");
   ALLOC(g.dn, sizeof(int4) * NUP, "triangle segments");
   ALLOC(g.d_counters, sizeof(int32_t) * 64, "counters");
+  if (devptr && !(flags & EF_VALIDATE) && nnz > 0) {
+    // neighbour ids of borrowed device arrays: in range before any kernel
+    // indexes with them
+    int32_t bad = 0;
+    hipError_t e = launch_check_cols(g.col_idx, nnz, n, g.d_counters, stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(&bad, g.d_counters, sizeof(int32_t), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+      ef_graph_free(h);
+      return hip_status(e, "check neighbour ids");
+    }
+    if (bad) {
+      ef_graph_free(h);
+      set_error("ef_graph_load_csr: a neighbour id is outside [0, %d)", n);
+      return EF_ERR_RANGE;
+    }
+  }
   // tail entries walked at each node by the triangle pass (binning)
   std::vector<int64_t> h_work((size_t)n);
   {

@@ -212,6 +212,11 @@ hipError_t launch_exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t co
                                      int32_t *block_tmp, int64_t block_tmp_len, hipStream_t st);
 int64_t scan_tmp_len(int64_t count);
 
+// flag[0] = 1 if some col[0 .. nnz) lies outside [0, n), else 0 (clears it
+// first)
+hipError_t launch_check_cols(const int32_t *col, int64_t nnz, int32_t n, int32_t *flag,
+                             hipStream_t st);
+
 // zero a small int32 array with a kernel (usable under stream capture)
 hipError_t launch_zero_i32(int32_t *p, int32_t count, hipStream_t st);
 

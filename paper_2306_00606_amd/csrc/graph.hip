@@ -23,6 +23,33 @@ __device__ __forceinline__ bool rank_less(int32_t a, int32_t ka, int32_t b, int3
   return ka < kb || (ka == kb && a < b);
 }
 
+// flag[0] = 1 when a neighbour id lies outside [0, n); launch_check_cols
+// clears the flag first
+__global__ void k_check_clear(int32_t *__restrict__ flag) {
+  if (threadIdx.x == 0) flag[0] = 0;
+}
+
+__global__ void k_check_cols(const int32_t *__restrict__ col, int64_t nnz, int32_t n,
+                             int32_t *__restrict__ flag) {
+  bool bad = false;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
+       e += (int64_t)gridDim.x * blockDim.x)
+    bad |= (uint32_t)col[e] >= (uint32_t)n;
+  // one store per wavefront that saw a bad id
+  if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+
+hipError_t launch_check_cols(const int32_t *col, int64_t nnz, int32_t n, int32_t *flag,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_check_clear, dim3(1), dim3(64), 0, st, flag);
+  if (nnz > 0) {
+    int64_t blocks = (nnz + 1023) / 1024;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_check_cols, dim3((unsigned)blocks), dim3(256), 0, st, col, nnz, n, flag);
+  }
+  return hipGetLastError();
+}
+
 __global__ void k_degree(const int32_t *__restrict__ row_ptr, int32_t n,
                          int32_t *__restrict__ deg) {
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;

@@ -127,3 +127,41 @@ def test_package_build_compiles_the_whole_oracle():
     for name in ("oracle_ef", "oracle_ef3", "oracle_histogram", "oracle_histogram3",
                  "oracle_splitmix64", "oracle_sir"):
         assert hasattr(lib, name), name
+
+
+def _load_status(rp, ci, flags=0):
+    h = ctypes.c_void_p()
+    rp = np.ascontiguousarray(rp, np.int32)
+    ci = np.ascontiguousarray(ci, np.int32)
+    st = efgpu.lib().ef_graph_load_csr(rp.size - 1, ci.size, rp.ctypes.data,
+                                       ci.ctypes.data if ci.size else None, flags, None,
+                                       ctypes.byref(h))
+    if st == 0:
+        efgpu.lib().ef_graph_free(h)
+    return st
+
+
+@pytest.mark.parametrize("name,rp,ci,code", [
+    ("row_ptr_decreasing", [0, 2, 1, 2], [1, 2], 5),     # EF_ERR_UNSORTED
+    ("offset_past_end", [0, 9, 1, 2], [1, 2], 5),
+    ("out_of_range", [0, 1, 2], [1, 5], 6),              # EF_ERR_RANGE
+    ("negative_id", [0, 1, 2], [1, -1], 6),
+    ("row_ptr_end", [0, 1, 1], [1, 0], 6),
+])
+def test_load_without_validation_still_checks_bounds(name, rp, ci, code):
+    """Without EF_VALIDATE the loader still rejects offsets and ids that a
+    kernel could not index safely, on the host, before any device work."""
+    assert _load_status(rp, ci, flags=0) == code
+    assert "ef_graph_load_csr" in efgpu.last_error()
+
+
+def test_device_byte_cap_reports_nomem(monkeypatch):
+    """EF_MAX_DEVICE_BYTES caps the library's device memory; a graph whose
+    fixed arrays exceed it is refused with EF_ERR_NOMEM before the device is
+    used (so this holds with or without a GPU)."""
+    rp, ci = _valid()
+    monkeypatch.setenv("EF_MAX_DEVICE_BYTES", "100")
+    assert _load_status(rp, ci) == 8  # EF_ERR_NOMEM
+    assert "EF_MAX_DEVICE_BYTES" in efgpu.last_error()
+    monkeypatch.setenv("EF_MAX_DEVICE_BYTES", str(1 << 40))
+    assert _load_status(rp, ci) in (0, 9)  # loads, or EF_ERR_DEVICE without a GPU
