@@ -121,7 +121,7 @@ def test_config1_er1000_seeds_1_to_20():
 
 
 def hub_graph():
-    """A hub of degree 3000 (two super-blocks, ragged; per-seed bitmap path),
+    """A hub of degree 3000 (two super-blocks, ragged; per-seed 16-wavefront bin),
     a second hub of degree 1500 sharing neighbours with it, on an ER
     background: many triangles through the hubs."""
     rs = np.random.default_rng(11)
