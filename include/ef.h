@@ -229,6 +229,17 @@ ef_status ef_sir(ef_graph *g, double beta, double mu, uint64_t seed, int32_t n_s
 ef_status ef_topk(ef_graph *g, ef_algo algo, ef_prec prec, int32_t k, int32_t *nodes,
                   double *ef, uint32_t flags, void *hip_stream);
 
+/* Top-k selection alone (the ranking step of ef_topk, for EF a caller already
+ * holds, e.g. from ef_compute with EF_OUT_DEVICE): ef_in is a device array of
+ * the graph's n values, non-negative (a value that is not positive counts as
+ * 0); writes nodes[0..k) and (nullable) ef[0..k) in descending order, ties by
+ * node id ascending. The selection runs on the device with scratch memory
+ * held by the handle. 0 <= k <= n, else EF_ERR_ARG. Flags: EF_OUT_DEVICE
+ * (nodes / ef are device pointers, asynchronous on hip_stream); without it
+ * they are host memory and the call synchronises the stream. */
+ef_status ef_topk_values(ef_graph *g, const double *ef_in, int32_t k, int32_t *nodes,
+                         double *ef, uint32_t flags, void *hip_stream);
+
 /* ---------------------------------------------------------------------------
  * Batches: many graphs computed together. The caller concatenates the graphs
  * into one disjoint union: graph i owns nodes node_off[i] .. node_off[i+1]-1,

@@ -75,16 +75,30 @@ def hip_runtime_dir():
     return os.path.join(ROCM, "lib")
 
 
-def build_lib():
+def build_lib(jobs=None):
+    """Compiles every source of the library to an object (in parallel, in
+    _build/), then links libef.so."""
+    from concurrent.futures import ThreadPoolExecutor
+
     out = os.path.join(PKG, "libef.so")
     srcs = lib_sources()
     if not srcs:
         return None
     inc = ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(PKG, "csrc")]
+    obj_dir = os.path.join(ROOT, "_build")
+    os.makedirs(obj_dir, exist_ok=True)
+    cflags = [f for f in HIP_FLAGS if f != "-shared"]
+    objs = [os.path.join(obj_dir, os.path.basename(s) + ".o") for s in srcs]
+    jobs = jobs or min(8, os.cpu_count() or 1)
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        for f in [ex.submit(_run, [HIPCC] + cflags + inc + ["-c", s, "-o", o])
+                  for s, o in zip(srcs, objs)]:
+            f.result()
     rt = hip_runtime_dir()
     link = ["-no-hip-rt", "-L", rt, "-l:libamdhip64.so", f"-Wl,-rpath,{rt}",
             f"-Wl,-rpath,{os.path.join(ROCM, 'lib')}"]
-    _run([HIPCC] + HIP_FLAGS + inc + srcs + link + ["-o", out + ".tmp"])
+    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC"] + objs + link
+         + ["-o", out + ".tmp"])
     os.replace(out + ".tmp", out)
     return out
 

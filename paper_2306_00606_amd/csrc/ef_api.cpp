@@ -1219,6 +1219,34 @@ extern "C" ef_status ef_compute_j3(ef_graph *h, ef_prec prec, const int32_t *see
   return EF_OK;
 }
 
+// Top-k over device EF values of the graph's nodes, in the handle's workspace;
+// host outputs go through a device staging area after the top-k scratch.
+static ef_status topk_device_values(Graph &g, const double *ef_all, int32_t k, int32_t *nodes,
+                                    double *ef, bool out_dev, hipStream_t st) {
+  const size_t sort_bytes = (topk_scratch_bytes(g.n, k) + 255) & ~(size_t)255;
+  const size_t node_bytes = (sizeof(int32_t) * (size_t)k + 255) & ~(size_t)255;
+  const size_t stage = out_dev ? 0 : node_bytes + sizeof(double) * (size_t)k;
+  ef_status s = ws_ensure(g, WS_TOPK, sort_bytes + stage, "top-k scratch");
+  if (s != EF_OK) return s;
+  char *base = (char *)g.ws[WS_TOPK].p;
+  int32_t *nodes_d = nodes;
+  double *ef_d = ef;
+  if (!out_dev) {
+    nodes_d = (int32_t *)(base + sort_bytes);
+    ef_d = (double *)(base + sort_bytes + node_bytes);
+  }
+  hipError_t e = launch_topk(ef_all, g.n, k, base, sort_bytes, nodes_d, ef ? ef_d : nullptr, st);
+  if (e != hipSuccess) return hip_status(e, "top-k");
+  if (!out_dev) {
+    e = hipMemcpyAsync(nodes, nodes_d, sizeof(int32_t) * (size_t)k, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && ef)
+      e = hipMemcpyAsync(ef, ef_d, sizeof(double) * (size_t)k, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_status(e, "copy top-k");
+  }
+  return EF_OK;
+}
+
 extern "C" ef_status ef_topk(ef_graph *h, ef_algo algo, ef_prec prec, int32_t k, int32_t *nodes,
                              double *ef, uint32_t flags, void *hip_stream) {
   if (!h || !nodes) {
@@ -1235,7 +1263,6 @@ extern "C" ef_status ef_topk(ef_graph *h, ef_algo algo, ef_prec prec, int32_t k,
     return EF_ERR_ARG;
   }
   if (k == 0) return EF_OK;
-  hipStream_t st = (hipStream_t)hip_stream;
   const size_t n = (size_t)g.n;
   ef_status s = ws_ensure(g, WS_OUT, sizeof(double) * n + 2 * sizeof(int64_t) * n + 2048,
                           "all-node outputs");
@@ -1246,26 +1273,26 @@ extern "C" ef_status ef_topk(ef_graph *h, ef_algo algo, ef_prec prec, int32_t k,
   s = ef_compute(h, algo, prec, nullptr, 0, ef_all, D_all, N_all,
                  EF_OUT_DEVICE | (flags & EF_PROFILE), hip_stream);
   if (s != EF_OK) return s;
-  const size_t scratch = topk_scratch_bytes(g.n) + sizeof(int32_t) * (size_t)k +
-                         sizeof(double) * (size_t)k + 1024;
-  if ((s = ws_ensure(g, WS_TOPK, scratch, "top-k scratch")) != EF_OK) return s;
-  const bool out_dev = (flags & EF_OUT_DEVICE) != 0;
-  int32_t *nodes_d = nodes;
-  double *ef_d = ef;
-  char *base = (char *)g.ws[WS_TOPK].p;
-  const size_t sort_bytes = topk_scratch_bytes(g.n);
-  if (!out_dev) {
-    nodes_d = (int32_t *)(base + sort_bytes);
-    ef_d = (double *)(base + sort_bytes + ((sizeof(int32_t) * (size_t)k + 255) & ~(size_t)255));
+  return topk_device_values(g, ef_all, k, nodes, ef, (flags & EF_OUT_DEVICE) != 0,
+                            (hipStream_t)hip_stream);
+}
+
+extern "C" ef_status ef_topk_values(ef_graph *h, const double *ef_in, int32_t k, int32_t *nodes,
+                                    double *ef, uint32_t flags, void *hip_stream) {
+  if (!h || !nodes || (!ef_in && k > 0)) {
+    set_error("ef_topk_values: null handle, values or output");
+    return EF_ERR_ARG;
   }
-  hipError_t e = launch_topk(ef_all, g.n, k, base, sort_bytes, nodes_d, ef ? ef_d : nullptr, st);
-  if (e != hipSuccess) return hip_status(e, "top-k");
-  if (!out_dev) {
-    e = hipMemcpyAsync(nodes, nodes_d, sizeof(int32_t) * (size_t)k, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess && ef)
-      e = hipMemcpyAsync(ef, ef_d, sizeof(double) * (size_t)k, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return hip_status(e, "copy top-k");
+  Graph &g = h->g;
+  if (k < 0 || k > g.n) {
+    set_error("ef_topk_values: k=%d outside [0, n=%d]", k, g.n);
+    return EF_ERR_ARG;
   }
-  return EF_OK;
+  if (flags & ~EF_OUT_DEVICE) {
+    set_error("ef_topk_values: unknown flags 0x%x", flags);
+    return EF_ERR_ARG;
+  }
+  if (k == 0) return EF_OK;
+  return topk_device_values(g, ef_in, k, nodes, ef, (flags & EF_OUT_DEVICE) != 0,
+                            (hipStream_t)hip_stream);
 }

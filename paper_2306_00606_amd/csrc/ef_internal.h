@@ -307,10 +307,17 @@ hipError_t launch_pass2(const Graph &g, const int32_t *seeds, const int32_t *fla
                         const int32_t *flag_count, int32_t max_flagged, double *ef,
                         const int64_t *D, hipStream_t st);
 
-// top-k by EF (descending, ties by id ascending) over ef[0..n)
-size_t topk_scratch_bytes(int32_t n);
+// top-k by EF (descending, ties by id ascending) over ef[0..n): device
+// values in, device nodes[0..k) and (nullable) ef_out[0..k) out; scratch of
+// topk_scratch_bytes(n, k) device bytes, none of it needing prior clearing.
+// hipErrorInvalidValue when k > n or the scratch is too small.
+size_t topk_scratch_bytes(int32_t n, int32_t k);
 hipError_t launch_topk(const double *ef, int32_t n, int32_t k, void *scratch,
                        size_t scratch_bytes, int32_t *nodes, double *ef_out, hipStream_t st);
+// the same over non-negative float scores (surrogate predictions)
+hipError_t launch_topk_f32(const float *score, int32_t n, int32_t k, void *scratch,
+                           size_t scratch_bytes, int32_t *nodes, double *score_out,
+                           hipStream_t st);
 
 // scatter outputs of unique seeds back to the caller's positions
 hipError_t launch_gather_outputs(const int32_t *inv, int32_t count, const double *ef_u,

@@ -254,7 +254,7 @@ ef_status ef_features(ef_graph *h, float *X, float *lnN, uint32_t flags, void *h
   const size_t nts = 2 * (size_t)std::max<int64_t>(g.nnz / 2, 1);
   // triangle counts per node come from the triangle pass (FP32 deltas unused)
   char *p = nullptr;
-  const size_t need = sizeof(TriSlot) * nts + sizeof(float2) * n +
+  const size_t need = sizeof(TriSlot) * nts +
                       sizeof(int64_t) * n + (sizeof(float) * kNF + sizeof(float)) * n + 4096;
   ef_status rs = graph_scratch(g, need, (void **)&p);
   if (rs != EF_OK) return rs;
@@ -266,7 +266,6 @@ ef_status ef_features(ef_graph *h, float *X, float *lnN, uint32_t flags, void *h
   };
   char *base = p;
   TriSlot *Y = (TriSlot *)take(sizeof(TriSlot) * nts);
-  void *Z = take(sizeof(float2) * n);
   int64_t *ZT = (int64_t *)take(sizeof(int64_t) * n);
   const bool dev = (flags & EF_OUT_DEVICE) != 0;
   float *Xd = dev ? X : (float *)take(sizeof(float) * kNF * n);
@@ -473,7 +472,7 @@ ef_status ef_surrogate_predict(ef_surrogate *s, ef_graph *h, double *ef_pred, ui
   // triangle slots: an upper-end and a lower-end slot per up arc
   const size_t nts = 2 * (size_t)std::max<int64_t>(g.nnz / 2, 1);
   char *p = nullptr;
-  const size_t need = sizeof(TriSlot) * nts + sizeof(float2) * n +
+  const size_t need = sizeof(TriSlot) * nts +
                       sizeof(int64_t) * n + (sizeof(float) * kNF + sizeof(float)) * n +
                       sizeof(double) * n + 4096;
   ef_status rs = graph_scratch(g, need, (void **)&p);
@@ -486,7 +485,6 @@ ef_status ef_surrogate_predict(ef_surrogate *s, ef_graph *h, double *ef_pred, ui
     return rr;
   };
   TriSlot *Y = (TriSlot *)take(sizeof(TriSlot) * nts);
-  void *Z = take(sizeof(float2) * n);
   int64_t *ZT = (int64_t *)take(sizeof(int64_t) * n);
   float *Xd = (float *)take(sizeof(float) * kNF * n);
   float *Ld = (float *)take(sizeof(float) * n);

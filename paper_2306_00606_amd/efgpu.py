@@ -34,7 +34,7 @@ EF_PROFILE = 0x8
 EXPORTS = [
     "ef_last_error", "ef_version", "ef_device_count", "ef_validate_csr", "ef_graph_load_csr",
     "ef_graph_from_edges", "ef_graph_free", "ef_graph_info_get", "ef_compute", "ef_compute_j3",
-    "ef_topk",
+    "ef_topk", "ef_topk_values",
     "ef_stats", "ef_batch_create", "ef_batch_autotune", "ef_batch_compute",
     "ef_batch_stats_get", "ef_batch_free", "ef_surrogate_create", "ef_surrogate_free",
     "ef_surrogate_get_params", "ef_surrogate_set_params", "ef_surrogate_save",
@@ -153,6 +153,7 @@ def lib():
                          vp, vp, vp, vp, vp, vp, vp]
     L.ef_stats.argtypes = [vp, ctypes.POINTER(RunStats)]
     L.ef_topk.argtypes = [vp, ctypes.c_int, ctypes.c_int, i32, vp, vp, u32, vp]
+    L.ef_topk_values.argtypes = [vp, vp, i32, vp, vp, u32, vp]
     L.ef_batch_create.argtypes = [i32, vp, i64, vp, vp, u32, vp, ctypes.POINTER(vp)]
     L.ef_batch_autotune.argtypes = [vp, ctypes.c_int]
     L.ef_batch_compute.argtypes = [vp, ctypes.c_int, vp, vp, vp, u32, vp]
@@ -318,6 +319,22 @@ class Graph:
                              ef.data_ptr() if ef is not None else None, flags | EF_OUT_DEVICE,
                              _stream_ptr(stream)))
         return nodes, ef
+
+    def topk_values(self, ef, k: int, out=None, stream=None):
+        """Top-k selection over EF values already on the device (`ef`: a torch
+        CUDA float64 tensor of n values). Host mode returns numpy (nodes, ef);
+        device mode writes `out` = (nodes, ef) torch CUDA tensors."""
+        if out is None:
+            nodes = np.zeros(max(k, 1), np.int32)
+            val = np.zeros(max(k, 1), np.float64)
+            _check(lib().ef_topk_values(self._h, ef.data_ptr(), int(k), nodes.ctypes.data,
+                                        val.ctypes.data, 0, _stream_ptr(stream)))
+            return nodes[:k], val[:k]
+        nodes, val = out
+        _check(lib().ef_topk_values(self._h, ef.data_ptr(), int(k), nodes.data_ptr(),
+                                    val.data_ptr() if val is not None else None, EF_OUT_DEVICE,
+                                    _stream_ptr(stream)))
+        return nodes, val
 
     def sir(self, beta: float, mu: float, seed: int, n_sims: int, t_max: int = 100000,
             profile: bool = False, stream=None) -> dict:
