@@ -240,6 +240,24 @@ ef_status ef_topk(ef_graph *g, ef_algo algo, ef_prec prec, int32_t k, int32_t *n
 ef_status ef_topk_values(ef_graph *g, const double *ef_in, int32_t k, int32_t *nodes,
                          double *ef, uint32_t flags, void *hip_stream);
 
+/* ef_topk_values without any allocation, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc. Same selection and order (descending, ties by id
+ * ascending) over the n device values ef_in, written to the device arrays
+ * nodes[0..k) and (nullable) ef[0..k); no graph handle. Its scratch is a fixed
+ * 3 MiB array in device memory that each GPU holds from the library's load to
+ * process end; it is resolved on the calling thread's current device (which
+ * must own ef_in, nodes, ef and hip_stream) on the first call there. The call
+ * makes no hipMalloc / hipFree and no other allocating call, and no memset
+ * (every scratch word it reads is written by the same call first), so it can
+ * be captured. Calls that overlap on one GPU (two streams, two threads) share
+ * that array and race: serialise them. Asynchronous on hip_stream.
+ * EF_ERR_ARG unless 0 <= k <= n and k <= 65536, flags == EF_OUT_DEVICE, and
+ * ef_in / nodes are non-null when k > 0; EF_ERR_DEVICE if the array's address
+ * cannot be obtained or a launch fails. */
+ef_status ef_topk_values_noalloc(const double *ef_in, int32_t n, int32_t k, int32_t *nodes,
+                                 double *ef, uint32_t flags, void *hip_stream);
+
 /* ---------------------------------------------------------------------------
  * Batches: many graphs computed together. The caller concatenates the graphs
  * into one disjoint union: graph i owns nodes node_off[i] .. node_off[i+1]-1,

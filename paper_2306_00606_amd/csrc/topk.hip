@@ -19,6 +19,8 @@
 //      bitonic sort in LDS for k <= 4096; above that a stable LSD radix sort
 //      (8-bit digits, ballot-ranked stable scatter), which keeps the id order
 //      of equal keys that the compaction produced.
+#include <mutex>
+
 #include "ef_internal.h"
 
 namespace efi {
@@ -488,4 +490,77 @@ hipError_t launch_topk_f32(const float *score, int32_t n, int32_t k, void *scrat
   return topk_impl<float>(score, n, k, scratch, scratch_bytes, nodes, score_out, st);
 }
 
+// ---------------------------------------------------------------------------
+// Top-k for callers that cannot allocate (code under HIP graph capture,
+// serving loops): the same kernels on a fixed scratch array instead of
+// workspace from a graph handle. Each device holds its own copy of the array
+// from module load to process end; host code reaches it only through the
+// address hipGetSymbolAddress returns on that device.
+// ---------------------------------------------------------------------------
+constexpr size_t kNoAllocScratchBytes = (size_t)3 << 20;
+constexpr int32_t kNoAllocMaxK = 65536;
+constexpr int kNoAllocMaxDevices = 64;
+static_assert(kNoAllocMaxK >= kTkSmall, "the no-allocation bound covers the LDS sort");
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kNoAllocMaxDevices] = {};
+
+// device address of `scratch` on the current device, resolved once per device
+hipError_t noalloc_scratch(void **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kNoAllocMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+}  // namespace
+
 }  // namespace efi
+
+extern "C" ef_status ef_topk_values_noalloc(const double *ef_in, int32_t n, int32_t k,
+                                            int32_t *nodes, double *ef, uint32_t flags,
+                                            void *hip_stream) {
+  using namespace efi;
+  if (n < 0 || k < 0 || k > n) {
+    set_error("ef_topk_values_noalloc: need 0 <= k <= n (k=%d, n=%d)", k, n);
+    return EF_ERR_ARG;
+  }
+  if (k > kNoAllocMaxK) {
+    set_error("ef_topk_values_noalloc: k=%d above the fixed-scratch limit %d", k, kNoAllocMaxK);
+    return EF_ERR_ARG;
+  }
+  if (flags != EF_OUT_DEVICE) {
+    set_error("ef_topk_values_noalloc: flags must be EF_OUT_DEVICE (device outputs), got 0x%x",
+              flags);
+    return EF_ERR_ARG;
+  }
+  if (k == 0) return EF_OK;
+  if (!ef_in || !nodes) {
+    set_error("ef_topk_values_noalloc: null values or output");
+    return EF_ERR_ARG;
+  }
+  const size_t need = topk_scratch_bytes(n, k);
+  if (need > kNoAllocScratchBytes) {
+    set_error("ef_topk_values_noalloc: n=%d, k=%d need %zu scratch bytes, above %zu", n, k, need,
+              kNoAllocScratchBytes);
+    return EF_ERR_ARG;
+  }
+  void *ptr = nullptr;
+  hipError_t e = noalloc_scratch(&ptr);
+  if (e != hipSuccess) return hip_status(e, "fixed scratch address");
+  e = launch_topk(ef_in, n, k, ptr, kNoAllocScratchBytes, nodes, ef, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_status(e, "top-k");
+  return EF_OK;
+}

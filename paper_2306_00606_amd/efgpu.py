@@ -34,7 +34,7 @@ EF_PROFILE = 0x8
 EXPORTS = [
     "ef_last_error", "ef_version", "ef_device_count", "ef_validate_csr", "ef_graph_load_csr",
     "ef_graph_from_edges", "ef_graph_free", "ef_graph_info_get", "ef_compute", "ef_compute_j3",
-    "ef_topk", "ef_topk_values",
+    "ef_topk", "ef_topk_values", "ef_topk_values_noalloc",
     "ef_stats", "ef_batch_create", "ef_batch_autotune", "ef_batch_compute",
     "ef_batch_stats_get", "ef_batch_free", "ef_surrogate_create", "ef_surrogate_free",
     "ef_surrogate_get_params", "ef_surrogate_set_params", "ef_surrogate_save",
@@ -154,6 +154,7 @@ def lib():
     L.ef_stats.argtypes = [vp, ctypes.POINTER(RunStats)]
     L.ef_topk.argtypes = [vp, ctypes.c_int, ctypes.c_int, i32, vp, vp, u32, vp]
     L.ef_topk_values.argtypes = [vp, vp, i32, vp, vp, u32, vp]
+    L.ef_topk_values_noalloc.argtypes = [vp, i32, i32, vp, vp, u32, vp]
     L.ef_batch_create.argtypes = [i32, vp, i64, vp, vp, u32, vp, ctypes.POINTER(vp)]
     L.ef_batch_autotune.argtypes = [vp, ctypes.c_int]
     L.ef_batch_compute.argtypes = [vp, ctypes.c_int, vp, vp, vp, u32, vp]
@@ -185,6 +186,16 @@ def last_error() -> str:
 def _check(status: int):
     if status != EF_OK:
         raise EFError(status, last_error())
+
+
+def topk_values_noalloc(ef, k: int, nodes, values=None, stream=None):
+    """ef_topk_values_noalloc: top-k of the device tensor `ef` (float64) into
+    the caller's device tensors `nodes` (int32, >= k) and `values` (float64 or
+    None), without any allocation; asynchronous on the stream."""
+    _check(lib().ef_topk_values_noalloc(ef.data_ptr(), int(ef.numel()), int(k), nodes.data_ptr(),
+                                        values.data_ptr() if values is not None else None,
+                                        EF_OUT_DEVICE, _stream_ptr(stream)))
+    return nodes, values
 
 
 def device_count() -> int:
