@@ -36,19 +36,18 @@ sys.path.insert(0, ROOT)
 
 METRIC = "clusters/s & EF nodes/s (R-MAT 42M edges), % HBM peak; surrogate vs exact"
 
-# MI355X FP32 vector peak 157.3 TFLOP/s counts an FMA as two flops: 78.6e12
-# FP32 lane operations per second (256 CUs x 128 lanes x 2.4 GHz). On the box,
-# non-packed FMA chains reach 5.8e13/s and a v_log_f32 costs about 4 FMA slots.
+# MI355X published FP32 vector peak: 157.3 TFLOP/s = 256 CUs x 2.4 GHz x 256
+# flops per CU and clock (128 FP32 lanes, an FMA counted as two flops).
+FP32_VECTOR_PEAK_FLOPS = 157.3e12
+# VALU issue model of a CU: FP32 instructions issue over 128 lanes per clock,
+# two wave64 instructions per CU and clock, 78.6e12 FP32 lane-instructions per
+# second (256 x 2.4 GHz x 128); transcendentals at a quarter of that. On the
+# box, chains of non-packed FMAs reach 5.8e13 lane-instructions/s (74%).
 VALU_LANE_OPS_PEAK = 256 * 128 * 2.4e9
-# Algorithmic VALU cost of scoring one cluster in the FP32 pair loop, in
-# FP32 lane-operation slots: the degree d = c_p + k_q (1), g = d log2 d
-# (v_log_f32, a transcendental at a quarter of the FMA rate: 4; multiply: 1),
-# credit to the row sum (1) and to the column sum (1).
-OPS_PER_CLUSTER = 8
-# The same with the score read from the centre's LDS table (tiles of big
-# centres whose degrees fit it): the table index k_p + k_q - 2 (1), row sum
-# (1), column sum (1); the read itself goes to the LDS pipe.
-OPS_PER_TABLE_CLUSTER = 3
+# Algorithmic cost of one cluster, the scope table's figure: about 16 FP32
+# VALU operations (the degree, d log d, the two credits, the triangle test's
+# share), counted as flops against the FP32 vector peak.
+OPS_PER_CLUSTER = 16
 # the kernel's rule: a full off-diagonal 64 x 64 tile of a big centre (rows in
 # an earlier super-block of 1024 than its columns) whose largest degrees
 # satisfy k_p + k_q - 2 < TABLE_ENTRIES reads the table
@@ -60,6 +59,12 @@ TABLE_ENTRIES = 4096
 # counter summaries sit with the other rocprofv3 summaries); set to None
 # whenever the kernel changes.
 PAIRS_BIG_TRAFFIC_BYTES = 2.655e9
+# Hardware counters of k_pairs_big<float> at the same workload, per launch
+# (rocprofv3 --pmc, the counter summaries sit with the other rocprofv3
+# summaries): SQ_INSTS_VALU (wave64 VALU instructions) and VALUBusy (percent
+# of the kernel's time the VALUs were busy); None whenever the kernel changes.
+PAIRS_BIG_VALU_INSTS = None
+PAIRS_BIG_VALU_BUSY = None
 # VALU cost of one SIR attempt along an arc, in FP32-FMA-equivalent lane slots:
 # the counter (2e) K and SplitMix64's two multiplications are three 64-bit
 # products of three 32-bit multiplies each, at a quarter of the FMA rate
@@ -99,15 +104,59 @@ def log(msg):
     sys.stderr.flush()
 
 
-def cpu_baseline(rp, ci, budget_s=15.0):
-    """The CPU oracle (single pass, as it stands) on a bounded random sample of
-    seeds of the same graph, on this host's cores. Returns Algorithm-1
-    clusters per second (each cluster is 4 event sequences across its seeds)."""
+def host_cpu():
+    """CPU model name and the number of host cores this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return model, os.cpu_count() or 1, usable
+
+
+def oracle_sample(rp, ci, order, Ns, threads, budget_s, start_chunk=256):
+    """Runs the oracle on seeds order[0..m) in growing chunks until budget_s of
+    oracle time is spent; returns (m, event sequences, seconds, N, D, EF)."""
     import numpy as np
 
     import oracle
 
-    threads = max(1, min(os.cpu_count() or 1, 16))
+    done, seqs, t_used, chunk = 0, 0, 0.0, start_chunk
+    outs = []
+    while t_used < budget_s and done < order.size:
+        seeds = order[done:done + chunk]
+        t0 = time.perf_counter()
+        outs.append(oracle.ef(rp, ci, seeds=seeds, threads=threads))
+        t_used += time.perf_counter() - t0
+        seqs += int(Ns[seeds].sum())
+        done += seeds.size
+        chunk = min(chunk * 2, 65536)
+    N, D, E = (np.concatenate([o[i] for o in outs]) for i in range(3))
+    return done, seqs, t_used, N, D, E
+
+
+def cpu_baseline(rp, ci, gpu_out, prec, budget_s=15.0, budget_1t_s=8.0):
+    """The CPU oracle (single pass, as it stands) on a bounded random sample of
+    seeds of the same graph, on this host's cores (up to 16 threads, OpenMP
+    dynamic schedule with chunk 2) and on one thread. Returns Algorithm-1
+    clusters per second (each cluster is 4 event sequences across its seeds).
+    The oracle's N, D and EF of the sampled seeds are compared with the timed
+    GPU step's outputs gpu_out = (EF, D, N): integers bit-exact, EF within the
+    precision's relative tolerance."""
+    import numpy as np
+
+    import oracle
+
+    model, nproc, usable = host_cpu()
+    threads = max(1, min(usable, 16))
     n = rp.size - 1
     deg = np.diff(rp).astype(np.int64)
     src = np.repeat(np.arange(n), deg)
@@ -115,20 +164,30 @@ def cpu_baseline(rp, ci, budget_s=15.0):
     Ns = deg * deg - 2 * deg + A
     order = np.random.default_rng(123).permutation(np.flatnonzero(deg > 0)).astype(np.int32)
     oracle.ef(rp, ci, seeds=order[:64], threads=threads)  # warm caches
-    done, seqs, t_used, chunk = 0, 0, 0.0, 256
-    while t_used < budget_s and done < order.size:
-        seeds = order[done:done + chunk]
-        t0 = time.perf_counter()
-        oracle.ef(rp, ci, seeds=seeds, threads=threads)
-        t_used += time.perf_counter() - t0
-        seqs += int(Ns[seeds].sum())
-        done += seeds.size
-        chunk = min(chunk * 2, 65536)
+    done, seqs, t_used, oN, oD, oE = oracle_sample(rp, ci, order, Ns, threads, budget_s)
     rate = seqs / t_used
+    # single thread, on a prefix of the same sample
+    d1, s1, t1, _, _, _ = oracle_sample(rp, ci, order, Ns, 1, budget_1t_s, start_chunk=64)
+    # parity of the benched step on the sampled seeds
+    ef, D, N = gpu_out
+    seeds = order[:done]
+    tol = 1e-5 if prec == "fp32c" else 1e-9
+    int_ok = bool(np.array_equal(N[seeds], oN) and np.array_equal(D[seeds], oD))
+    pos = oE > 0
+    rel = np.abs(ef[seeds] - oE)
+    max_rel = float((rel[pos] / oE[pos]).max()) if pos.any() else 0.0
+    ef_ok = bool(np.all(rel <= tol * np.abs(oE)))
     return {"value": rate / 4.0, "unit": "clusters/s", "cores": threads, "kind": "oracle",
             "sample": f"{done} seeds drawn uniformly from the non-isolated nodes of the same "
                       f"graph, {seqs} event sequences in {t_used:.1f} s on {threads} threads; "
-                      f"clusters/s = sequences/s / 4"}
+                      f"clusters/s = sequences/s / 4",
+            "single_thread": {"value": s1 / t1 / 4.0, "unit": "clusters/s", "cores": 1,
+                              "sample": f"the first {d1} of the same seeds, {s1} event "
+                                        f"sequences in {t1:.1f} s on one thread"},
+            "cpu_model": model, "nproc": nproc, "usable_cores": usable,
+            "parity": {"seeds": int(done), "integers_bit_exact": int_ok,
+                       "ef_max_rel_err": max_rel, "ef_tolerance": tol,
+                       "ok": bool(int_ok and ef_ok)}}
 
 
 def bench_j3(steps, with_cpu):
@@ -368,6 +427,8 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate")
     ap.add_argument("--j3-steps", type=int, default=2,
                     help="also time EF with three transmission events (0 = skip)")
+    ap.add_argument("--only", choices=["batch", "surrogate", "three_events", "sir"],
+                    help="run only this section and print its record (profiling runs)")
     ap.add_argument("--sir-runs", type=int, default=2,
                     help="also time 300 SIR outbreaks with spreading power (0 = skip)")
     args = ap.parse_args()
@@ -375,6 +436,13 @@ def main():
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the exact path runs on a single MI355X)", file=sys.stderr)
         sys.exit(2)
+
+    if args.only:
+        run = {"batch": lambda: bench_batch(max(3, args.steps)), "surrogate": bench_surrogate,
+               "three_events": lambda: bench_j3(max(1, args.j3_steps), False),
+               "sir": lambda: bench_sir(max(1, args.sir_runs), False)}[args.only]
+        print(json.dumps({"section": args.only, "record": run()}))
+        return
 
     import numpy as np
     import torch
@@ -420,22 +488,34 @@ def main():
         ms = st["t_total_ms"]  # profile-only: phases run one after another
 
     # dominant kernel: the super-tile pair loop (clusters of centres with k > 1024)
+    headline = (args.scale, args.edge_factor) == (22, 10)
     if args.algo == "cluster" and args.prec == "fp32c" and st["t_pairs_big_ms"] > 0:
-        n_tab = table_clusters(rp, ci)
-        ops = n_tab * OPS_PER_TABLE_CLUSTER + (st["pairs_big"] - n_tab) * OPS_PER_CLUSTER
-        achieved = ops / (st["t_pairs_big_ms"] * 1e-3)
+        t_launch = st["t_pairs_big_ms"] * 1e-3
+        achieved = st["pairs_big"] * OPS_PER_CLUSTER / t_launch
+        counters = None
+        if headline and PAIRS_BIG_VALU_INSTS:
+            lane_insts = PAIRS_BIG_VALU_INSTS * 64 / t_launch
+            counters = {"valu_insts_per_launch": PAIRS_BIG_VALU_INSTS,
+                        "valu_insts_per_cluster": PAIRS_BIG_VALU_INSTS * 64 / st["pairs_big"],
+                        "valu_lane_insts_per_s": lane_insts,
+                        "issue_peak_lane_insts_per_s": VALU_LANE_OPS_PEAK,
+                        "frac_of_issue_peak": lane_insts / VALU_LANE_OPS_PEAK,
+                        "valu_busy_pct": PAIRS_BIG_VALU_BUSY}
         roofline = {"bound": "alu", "kernel": "k_pairs_big<float>",
-                    "achieved": achieved / 1e12, "peak": VALU_LANE_OPS_PEAK / 1e12,
-                    "unit": "TOP/s", "frac": achieved / VALU_LANE_OPS_PEAK,
-                    "traffic": PAIRS_BIG_TRAFFIC_BYTES
-                    if (args.scale, args.edge_factor) == (22, 10) else None,
+                    "achieved": achieved / 1e12, "peak": FP32_VECTOR_PEAK_FLOPS / 1e12,
+                    "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_FLOPS,
+                    "traffic": PAIRS_BIG_TRAFFIC_BYTES if headline else None,
                     "ops_per_cluster": OPS_PER_CLUSTER,
-                    "ops_per_table_cluster": OPS_PER_TABLE_CLUSTER,
-                    "clusters_per_launch": st["pairs_big"], "table_clusters": n_tab,
-                    "avg_launch_ms": st["t_pairs_big_ms"]}
+                    "clusters_per_launch": st["pairs_big"],
+                    "table_clusters": table_clusters(rp, ci),
+                    "avg_launch_ms": st["t_pairs_big_ms"], "counters": counters}
     else:
         roofline = None
+    # the headline step's outputs, before any other section reuses the device
+    ef_h, D_h, N_h = ef.cpu().numpy(), D.cpu().numpy(), N.cpu().numpy()
 
+    # the other formulations write their own buffers
+    out = tuple(torch.empty_like(x) for x in out)
     per_seed = None
     if args.algo == "cluster" and args.per_seed_steps > 0:
         log(f"per-seed formulation: {args.per_seed_steps} steps")
@@ -495,9 +575,9 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample")
-        cpu = cpu_baseline(rp, ci)
+        cpu = cpu_baseline(rp, ci, (ef_h, D_h, N_h), args.prec)
+        log(f"oracle parity of the benched step on the sample: {cpu['parity']}")
 
-    ef_h = ef.cpu().numpy()
     rec = {
         "metric": METRIC,
         "value": W / (ms * 1e-3),
@@ -531,6 +611,9 @@ def main():
     }
     g.close()
     print(json.dumps(rec))
+    if cpu is not None and not cpu["parity"]["ok"]:
+        log("the benched step disagrees with the oracle on the sampled seeds")
+        sys.exit(1)
 
 
 if __name__ == "__main__":

@@ -161,7 +161,7 @@ ef_status ef_graph_free(ef_graph *h) {
   }
   void *arrays[] = {g.deg, g.src, g.rev, g.adj2, g.adjs, g.asum, g.qa, g.up_ptr, g.up_col, g.trec,
                     g.up_deg, g.dn_ptr, g.dn, g.tri_zero, g.j3_seeds, g.j3_off,
-                    g.tri_rec0, g.tri_list[0], g.tri_list[1], g.tri_list[2], g.tri_list[3],
+                    g.tri_rec0, g.tri_recL, g.tri_list[0], g.tri_list[1], g.tri_list[2], g.tri_list[3],
                     g.fin_list,
                     g.ps_list[0], g.ps_list[1], g.ps_list[2], g.ps_list[3], g.ps_list[4],
                     g.d_counters};
@@ -430,6 +430,7 @@ ef_status ef_graph_load_csr(int32_t n, int64_t nnz, const int32_t *row_ptr,
     }
   }
   std::vector<int32_t> tri[4], fin;
+  std::vector<int4> recL;
   for (int32_t v = 0; v < n; ++v) {
     const int64_t k = g.h_deg[v];
     const int32_t up = h_up_ptr[v + 1] - h_up_ptr[v];
@@ -453,7 +454,10 @@ ef_status ef_graph_load_csr(int32_t n, int64_t nnz, const int32_t *row_ptr,
       g.all_sblocks += ns;
     }
     const int32_t nd = h_dn_ptr[v + 1] - h_dn_ptr[v];
-    if (nd > 0) {
+    if (nd > 0 && up <= kTriLaneM && h_work[v] <= kTriLaneWork && nd <= kTriLaneSegs) {
+      recL.push_back(make_int4(v, h_up_ptr[v], h_dn_ptr[v],
+                               up | (nd << 8) | ((int32_t)h_work[v] << 16)));
+    } else if (nd > 0) {
       const int bin = (up <= kTriBin0 && h_work[v] <= kTriWaveWork && nd <= kTriWaveSegs) ? 0
                       : up <= kTriBin1                                                  ? 1
                       : up <= kTriBin2                                                  ? 2
@@ -480,6 +484,8 @@ ef_status ef_graph_load_csr(int32_t n, int64_t nnz, const int32_t *row_ptr,
     rec0[i] = make_int4(v, h_up_ptr[v], h_dn_ptr[v], m | (nd << 16));
   }
   ALLOC(g.tri_rec0, sizeof(int4) * std::max<size_t>(rec0.size(), 1), "triangle records");
+  g.n_tri_lane = (int64_t)recL.size();
+  ALLOC(g.tri_recL, sizeof(int4) * std::max<size_t>(recL.size(), 1), "triangle lane records");
   std::sort(fin.begin(), fin.end(), [&](int32_t a, int32_t b) {
     return g.h_deg[a] != g.h_deg[b] ? g.h_deg[a] > g.h_deg[b] : a < b;
   });
@@ -496,6 +502,8 @@ ef_status ef_graph_load_csr(int32_t n, int64_t nnz, const int32_t *row_ptr,
                     hipMemcpyHostToDevice);
   if (e == hipSuccess && !rec0.empty())
     e = hipMemcpy(g.tri_rec0, rec0.data(), sizeof(int4) * rec0.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !recL.empty())
+    e = hipMemcpy(g.tri_recL, recL.data(), sizeof(int4) * recL.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess && !fin.empty())
     e = hipMemcpy(g.fin_list, fin.data(), sizeof(int32_t) * fin.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) {

@@ -31,6 +31,8 @@ constexpr int kRecEntries = 2 * kSuper;  // row part + column part per super-til
 // Triangle pass: a triangle is listed at its middle node w (by rank), with
 // an LDS hash of w's degree-oriented out-list up(w). Nodes w with segments
 // are binned by |up(w)| and by their walk (tail entries, segments):
+//   L: |up| <= kTriLaneM, walk <= kTriLaneWork, segments <= kTriLaneSegs
+//      one lane (up(w) and the credits in registers)
 //   0: |up| <= kTriBin0, walk <= kTriWaveWork, segments <= kTriWaveSegs
 //      one wavefront
 //   1: |up| <= kTriBin1     one workgroup (8 wavefronts)
@@ -49,6 +51,11 @@ constexpr int32_t kFinHalfMax = 512;
 constexpr int32_t kFinBlockMin = 4096;
 constexpr int kTriLongMin = kTriBin2 + 1;
 constexpr int64_t kTriWaveWork = 4096;
+constexpr int kTriLaneM = 16;
+constexpr int64_t kTriLaneWork = 64;
+constexpr int32_t kTriLaneSegs = 64;
+static_assert(kTriLaneM < 256 && kTriLaneSegs < 256 && kTriLaneWork < 65536,
+              "lane-bin record packing");
 constexpr int32_t kTriWaveSegs = 256;
 static_assert(kTriBin0 < (1 << 16) && kTriWaveSegs < (1 << 15), "wave-bin record packing");
 
@@ -143,6 +150,9 @@ struct Graph {
   // triangle-pass node lists (device): see kTriBin*. Bin 0 as records
   // {w, up_ptr[w], dn_ptr[w], |up(w)| | segments << 16}, bins 1-3 as ids.
   int4 *tri_rec0 = nullptr;
+  // lane bin: {w, up_ptr[w], dn_ptr[w], |up(w)| | segments << 8 | walk << 16}, by id
+  int4 *tri_recL = nullptr;
+  int64_t n_tri_lane = 0;
   int32_t *tri_list[4] = {nullptr, nullptr, nullptr, nullptr};
   // nodes of degree > kFinGroupMax (finalized one wavefront each), by degree descending
   int32_t *fin_list = nullptr;

@@ -447,6 +447,91 @@ __global__ __launch_bounds__(64) void k_tri_long(TriArgs A, const int32_t *__res
   }
 }
 
+// One node w per lane (|up(w)| <= M, a walk of at most kTriLaneWork entries),
+// for the many nodes whose whole triangle work is a few membership tests: a
+// wavefront per node would spend its time on setup. up(w) sits in registers
+// (a test compares against all M entries), the credits to x by position and
+// to u by segment in per-lane integer slots (the LDS slots' representation,
+// so the records are the same bits as the other bins would write). Nodes are
+// listed by id, so neighbouring lanes read neighbouring rows.
+template <typename T> struct LaneSlot;
+template <> struct LaneSlot<float> {
+  unsigned long long w = 0;
+  __device__ void add(float dl) {
+    w += (1ull << 44) + (unsigned long long)(uint32_t)(-dl * 16777216.0f);
+  }
+  __device__ TriSlot slot() const {
+    return TriSlot{-(long long)((w & ((1ull << 44) - 1)) << 12), (int32_t)(w >> 44), 0};
+  }
+};
+template <> struct LaneSlot<double> {
+  long long y = 0;
+  int32_t t = 0;
+  __device__ void add(double dl) {
+    y += to_fix(dl);
+    ++t;
+  }
+  __device__ TriSlot slot() const { return TriSlot{y, t, 0}; }
+};
+template <> struct LaneSlot<TriCount> {
+  int32_t t = 0;
+  __device__ void add(TriCount) { ++t; }
+  __device__ TriSlot slot() const { return TriSlot{0, t, 0}; }
+};
+
+template <typename T, int M>
+__global__ __launch_bounds__(256) void k_tri_lane(TriArgs A, const int4 *__restrict__ recs,
+                                                  int64_t count) {
+  using S = SumT<T>;
+  using Acc = typename S::type;
+  for (int64_t it = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; it < count;
+       it += (int64_t)gridDim.x * blockDim.x) {
+    const int4 rc = recs[it];
+    const int32_t w = rc.x, w0 = rc.y, d0 = rc.z;
+    const int32_t m = rc.w & 0xFF, nd = (rc.w >> 8) & 0xFF, walk = rc.w >> 16;
+    int32_t up[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) up[q] = q < m ? A.up_col[w0 + q] : -1;
+    LaneSlot<T> acc[M];
+    LaneSlot<T> su;
+    Acc accw = Acc();
+    int64_t cntw = 0;
+    // every listed node has nd >= 1 segments, each non-empty; walk = their total
+    int32_t s = 0;
+    int4 sg = A.dn[d0];
+    int32_t j = sg.x + 1, jend = sg.x + sg.y;
+    for (int32_t t = 0; t < walk; ++t) {
+      const int32_t x = A.up_col[j], kx = A.up_deg[j];
+      int32_t p = -1;
+#pragma unroll
+      for (int q = 0; q < M; ++q) p = up[q] == x ? q : p;
+      if (p >= 0) {
+        const T dl = tri_delta<T>(sg.z + kx);
+        S::add_term(accw, dl);
+        ++cntw;
+        su.add(dl);
+#pragma unroll
+        for (int q = 0; q < M; ++q)
+          if (q == p) acc[q].add(dl);
+      }
+      if (++j > jend) {
+        A.Y[A.nup + sg.x] = su.slot();
+        su = LaneSlot<T>();
+        if (++s < nd) {
+          sg = A.dn[d0 + s];
+          j = sg.x + 1;
+          jend = sg.x + sg.y;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < M; ++q)
+      if (q < m) A.Y[w0 + q] = acc[q].slot();
+    S::store(accw, A.Z, w);
+    A.ZT[w] = cntw;
+  }
+}
+
 // Clear the listed records (upper-end records of long-list nodes, which
 // their walk adds to with atomics). Records no walk writes are never read:
 // readers skip trec = -1, and read Z / ZT only of nodes with segments.
@@ -470,6 +555,10 @@ static hipError_t tri_impl(const Graph &g, TriSlot *Y, void *Z, int64_t *ZT, hip
     hipLaunchKernelGGL(k_tri_zero, dim3(cap_blocks((g.n_tri_zero + 255) / 256, 1 << 16)),
                        dim3(256), 0, st, Y, g.tri_zero, g.n_tri_zero);
   const int64_t *counts = g.n_tri;
+  if (g.n_tri_lane > 0)
+    hipLaunchKernelGGL((k_tri_lane<T, kTriLaneM>),
+                       dim3(cap_blocks((g.n_tri_lane + 255) / 256, 1 << 16)), dim3(256), 0, st,
+                       A, g.tri_recL, g.n_tri_lane);
   if (counts[0] > 0)
     hipLaunchKernelGGL((k_tri_wave<T, 256, 64, 4>), dim3(cap_blocks((counts[0] + 3) / 4, 1 << 20)),
                        dim3(256), 0, st, A, g.tri_rec0, counts[0]);
