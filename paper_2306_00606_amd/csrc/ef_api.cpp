@@ -429,7 +429,7 @@ ef_status ef_graph_load_csr(int32_t n, int64_t nnz, const int32_t *row_ptr,
       }
     }
   }
-  std::vector<int32_t> tri[4], fin;
+  std::vector<int32_t> tri[4], fin, fin_group;
   std::vector<int4> recL;
   for (int32_t v = 0; v < n; ++v) {
     const int64_t k = g.h_deg[v];
@@ -465,6 +465,7 @@ ef_status ef_graph_load_csr(int32_t n, int64_t nnz, const int32_t *row_ptr,
       tri[bin].push_back(v);
     }
     if (k > kFinGroupMax) fin.push_back(v);
+    else if (k > kFinLaneMax) fin_group.push_back(v);
   }
   // longest walks first
   auto by_work = [&](int32_t a, int32_t b) {
@@ -493,6 +494,8 @@ ef_status ef_graph_load_csr(int32_t n, int64_t nnz, const int32_t *row_ptr,
   for (int32_t v : fin)
     if (g.h_deg[v] > kFinBlockMin) g.n_fin_hub++;
     else if (g.h_deg[v] <= kFinHalfMax) g.n_fin_half++;
+  g.n_fin_group = (int64_t)fin_group.size();
+  fin.insert(fin.end(), fin_group.begin(), fin_group.end());
   ALLOC(g.fin_list, sizeof(int32_t) * std::max<size_t>(fin.size(), 1), "finalize list");
 #undef ALLOC
   hipError_t e = hipSuccess;

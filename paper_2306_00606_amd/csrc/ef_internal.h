@@ -47,6 +47,7 @@ constexpr int kTriBin0 = 64, kTriBin1 = 512, kTriBin2 = 2048;
 // wavefronts, 8 lanes each; degree <= kFinHalfMax: 32 lanes; degree <=
 // kFinBlockMin: a wavefront; hubs of degree > kFinBlockMin: a workgroup.
 constexpr int32_t kFinGroupMax = 32;
+constexpr int32_t kFinLaneMax = 8;  // the cluster finalize: one lane per node up to this degree
 constexpr int32_t kFinHalfMax = 512;
 constexpr int32_t kFinBlockMin = 4096;
 constexpr int kTriLongMin = kTriBin2 + 1;
@@ -81,6 +82,10 @@ constexpr float kKappaMax = 16.0f;
 // Segment-size thresholds of the small bin: a centre of degree k <= 64 is
 // scored on segments of 8, 16, 32 or 64 lanes: the first S with k <= t[S]
 // (t8 <= 8, t16 <= 16, t32 <= 32; 0 disables a segment size).
+// Small centres go to the first bin whose threshold holds their degree:
+// bin 0 (k <= t8, at most kSmallLaneMax) one lane per centre; bins 1-3
+// (k <= t16, t32, 64) segments of 16, 32, 64 lanes.
+constexpr int32_t kSmallLaneMax = 8;
 struct SmallThr {
   int32_t t8 = 8, t16 = 16, t32 = 32;
 };
@@ -159,6 +164,9 @@ struct Graph {
   int64_t n_fin = 0;
   int64_t n_fin_hub = 0;   // leading entries of fin_list with degree > kFinBlockMin
   int64_t n_fin_half = 0;  // trailing entries with degree <= kFinHalfMax
+  // after those n_fin entries: the n_fin_group nodes of degree kFinLaneMax+1 ..
+  // kFinGroupMax in id order (the cluster finalize takes them 8 lanes each)
+  int64_t n_fin_group = 0;
   // per-seed formulation over all nodes: node ids by seed bin (built on first use)
   int32_t *ps_list[kSeedBins] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   int64_t n_ps[kSeedBins] = {0, 0, 0, 0, 0};

@@ -15,7 +15,8 @@
 // diagonal of the pair triangle take 32 steps (each unordered pair once).
 //
 // Work bins:
-//   small (k <= 64)   one wavefront per centre: one diagonal tile
+//   tiny  (k <= 8)    one lane per centre, its pairs in registers
+//   small (k <= 64)   segments of 16, 32 or 64 lanes: one diagonal tile
 //   mid   (k <= 1024) one 16-wavefront workgroup per centre: block pairs are
 //                     dealt round-robin so every wavefront gets the same load
 //   big   (k > 1024)  1024x1024 super-tiles, one workgroup each, written as
@@ -233,6 +234,50 @@ __global__ __launch_bounds__(256) void k_pairs_small(const int32_t *__restrict__
       a.add(Rt);
       a.add(Cl);
       a.store(R, base + j);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// tiny centres (k <= 8): one lane per centre, all C(k, 2) pairs in registers.
+// With a few pairs per centre, a segment per centre would spend its time on
+// the dependent loads of every centre; a lane keeps 64 centres in flight per
+// wavefront. Rows past k are clamped to valid neighbours and masked.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_pairs_lane(const int32_t *__restrict__ row_ptr,
+                                                    const int32_t *__restrict__ deg,
+                                                    const int2 *__restrict__ adj2,
+                                                    const int32_t *__restrict__ list,
+                                                    int64_t count, void *__restrict__ R) {
+  constexpr int K = 8;
+  for (int64_t it = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; it < count;
+       it += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = list[it];
+    const int32_t k = deg[v], base = row_ptr[v];  // 2 <= k <= K
+    T kp[K];
+#pragma unroll
+    for (int p = 0; p < K; ++p) kp[p] = (T)adj2[base + (p < k ? p : k - 1)].y;
+    const T c = (T)(k - 4);
+    T r[K];
+#pragma unroll
+    for (int p = 0; p < K; ++p) r[p] = T(0);
+#pragma unroll
+    for (int p = 0; p < K; ++p) {
+#pragma unroll
+      for (int q = p + 1; q < K; ++q) {
+        const T g = q < k ? score_masked(c + kp[p] + kp[q]) : T(0);
+        r[p] += g;
+        r[q] += g;
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < K; ++p) {
+      if (p < k) {
+        Acc<T> a;
+        a.add(r[p]);
+        a.store(R, base + p);
+      }
     }
   }
 }
@@ -787,8 +832,9 @@ template <typename T>
 static hipError_t pairs_impl(const Graph &g, const Bins &b, void *R, void *records,
                              hipStream_t st, hipEvent_t ev_small, hipEvent_t ev_mid,
                              hipEvent_t ev_big, int32_t *agg_done) {
+  static_assert(kSmallLaneMax == 8, "bin 0 holds centres of degree <= 8, one lane each");
   if (b.n_smallb[0] > 0)
-    hipLaunchKernelGGL((k_pairs_small<T, 8>), dim3(capped((b.n_smallb[0] + 31) / 32, 1 << 20)),
+    hipLaunchKernelGGL(k_pairs_lane<T>, dim3(capped((b.n_smallb[0] + 255) / 256, 1 << 16)),
                        dim3(256), 0, st, g.row_ptr, g.deg, g.adj2, b.small[0], b.n_smallb[0], R);
   if (b.n_smallb[1] > 0)
     hipLaunchKernelGGL((k_pairs_small<T, 16>), dim3(capped((b.n_smallb[1] + 15) / 16, 1 << 20)),

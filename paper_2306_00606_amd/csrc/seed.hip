@@ -254,6 +254,71 @@ __device__ __forceinline__ void fin_groups(const FinArgs &A, const int32_t *node
   }
 }
 
+// one lane per node of degree <= kFinLaneMax over node ids 0..n-1: the loads
+// of all of a node's arcs are issued together (indices clamped to its row,
+// contributions past k masked), so a node costs two dependent round trips
+template <typename T> struct RVal;
+template <> struct RVal<float> {
+  __device__ static float2 load(const void *R, int64_t i) {
+    return reinterpret_cast<const float2 *>(R)[i];
+  }
+  __device__ static void add(DFv &a, float2 x, bool on) {
+    a.add(on ? x.x : 0.0f);
+    a.add(on ? x.y : 0.0f);
+  }
+};
+template <> struct RVal<double> {
+  __device__ static double load(const void *R, int64_t i) {
+    return reinterpret_cast<const double *>(R)[i];
+  }
+  __device__ static void add(double &a, double x, bool on) { a += on ? x : 0.0; }
+};
+
+template <typename T>
+__device__ __forceinline__ void fin_lanes(const FinArgs &A, int32_t n, int64_t blk, int64_t nblk) {
+  using Acc = typename SumT<T>::type;
+  constexpr int K = kFinLaneMax;
+  const int64_t stride = nblk * (int64_t)blockDim.x;
+  for (int64_t v = blk * (int64_t)blockDim.x + threadIdx.x; v < n; v += stride) {
+    const int32_t k = A.deg[v];
+    if (k > K) continue;
+    Acc sacc = Acc();
+    double tfix = 0.0;
+    int64_t Tc = 0;
+    if (k > 0) {
+      const int32_t base = A.row_ptr[v];
+      int32_t ka[K], rv[K], tr[K];
+#pragma unroll
+      for (int i = 0; i < K; ++i) {
+        const int32_t e = base + (i < k ? i : k - 1);
+        ka[i] = A.adj2[e].y;
+        rv[i] = A.rev[e];
+        tr[i] = A.trec[e];
+      }
+      decltype(RVal<T>::load(A.R, 0)) own[K], back[K];
+      TriSlot ts[K];
+#pragma unroll
+      for (int i = 0; i < K; ++i) {
+        own[i] = RVal<T>::load(A.R, base + (i < k ? i : k - 1));
+        back[i] = RVal<T>::load(A.R, rv[i]);
+        ts[i] = A.Y[tr[i] >= 0 ? tr[i] : 0];
+      }
+#pragma unroll
+      for (int i = 0; i < K; ++i) {
+        const bool in = i < k;
+        // a centre of degree 1 has no pairs: its row sums were never written
+        RVal<T>::add(sacc, own[i], in && k >= 2);
+        RVal<T>::add(sacc, back[i], in && ka[i] >= 2);
+        const bool hit = in && tr[i] >= 0;
+        tfix += hit ? (double)ts[i].y : 0.0;
+        Tc += hit ? ts[i].t : 0;
+      }
+    }
+    fin_store<T>((int32_t)v, k, A.asum[v], A.qa[v], A.dn_ptr[v + 1] > A.dn_ptr[v], sacc, tfix,
+                 Tc, A.Z, A.ZT, A.ef, A.D, A.N, A.fl);
+  }
+}
+
 // one workgroup (4 wavefronts) per hub; partials combined in a fixed order
 template <typename T>
 __device__ __forceinline__ void fin_hubs(const FinArgs &A, const int32_t *nodes, int64_t count,
@@ -297,18 +362,19 @@ __device__ __forceinline__ void fin_hubs(const FinArgs &A, const int32_t *nodes,
 //   [0, b0)        hubs (degree > kFinBlockMin), a workgroup each
 //   [b0, b1)       degree kFinHalfMax+1 .. kFinBlockMin, a wavefront each
 //   [b1, b2)       degree kFinGroupMax+1 .. kFinHalfMax, 32 lanes each
-//   [b2, grid)     degree <= kFinGroupMax, 8 lanes each (node ids)
+//   [b2, b3)       degree kFinLaneMax+1 .. kFinGroupMax, 8 lanes each (list by id)
+//   [b3, grid)     degree <= kFinLaneMax, one lane each (node ids)
 template <typename T>
-__global__ __launch_bounds__(256) void k_finalize_cluster(FinArgs A, const int32_t *l_hub,
-                                                         int64_t n_hub, const int32_t *l_wave,
-                                                         int64_t n_wave, const int32_t *l_half,
-                                                         int64_t n_half, int32_t n, int64_t b0,
-                                                         int64_t b1, int64_t b2) {
+__global__ __launch_bounds__(256) void k_finalize_cluster(
+    FinArgs A, const int32_t *l_hub, int64_t n_hub, const int32_t *l_wave, int64_t n_wave,
+    const int32_t *l_half, int64_t n_half, const int32_t *l_group, int64_t n_group, int32_t n,
+    int64_t b0, int64_t b1, int64_t b2, int64_t b3) {
   const int64_t b = blockIdx.x;
   if (b < b0) fin_hubs<T>(A, l_hub, n_hub, b, b0);
   else if (b < b1) fin_groups<T, 64>(A, l_wave, n_wave, 0, b - b0, b1 - b0);
   else if (b < b2) fin_groups<T, 32>(A, l_half, n_half, 0, b - b1, b2 - b1);
-  else fin_groups<T, 8>(A, nullptr, (int64_t)n, kFinGroupMax, b - b2, (int64_t)gridDim.x - b2);
+  else if (b < b3) fin_groups<T, 8>(A, l_group, n_group, 0, b - b2, b3 - b2);
+  else fin_lanes<T>(A, n, b - b3, (int64_t)gridDim.x - b3);
 }
 
 static unsigned cap_blocks(int64_t b, int64_t cap) {
@@ -319,24 +385,27 @@ static unsigned cap_blocks(int64_t b, int64_t cap) {
 hipError_t launch_finalize_cluster(const Graph &g, ef_prec prec, const void *R, const TriSlot *Y,
                                    const void *Z, const int64_t *ZT, double *ef, int64_t *D,
                                    int64_t *N, uint8_t *fl, hipStream_t st) {
-  // fin_list (degree descending) = [hubs][wavefront tier][32-lane tier]
+  // fin_list = [hubs][wavefront tier][32-lane tier] (degree descending), then
+  // the 8-lane tier (id order)
   const int64_t n_wave = g.n_fin - g.n_fin_hub - g.n_fin_half;
   const int32_t *l_wave = g.fin_list + g.n_fin_hub, *l_half = l_wave + n_wave;
+  const int32_t *l_group = g.fin_list + g.n_fin;
   const int64_t bh = g.n_fin_hub > 0 ? cap_blocks(g.n_fin_hub, 1 << 14) : 0;
   const int64_t bw = n_wave > 0 ? cap_blocks((n_wave * 64 + 255) / 256, 1 << 18) : 0;
   const int64_t bc = g.n_fin_half > 0 ? cap_blocks((g.n_fin_half * 32 + 255) / 256, 1 << 18) : 0;
-  const int64_t bs = cap_blocks(((int64_t)g.n * 8 + 255) / 256, 1 << 19);
+  const int64_t bg = g.n_fin_group > 0 ? cap_blocks((g.n_fin_group * 8 + 255) / 256, 1 << 18) : 0;
+  const int64_t bl = cap_blocks(((int64_t)g.n + 255) / 256, 1 << 17);
   const FinArgs A{g.row_ptr, g.deg, g.adj2, g.rev, g.trec, g.dn_ptr, g.asum, g.qa,
                   R,         Y,     Z,      ZT,    ef,     D,      N,        fl};
-  const unsigned grid = (unsigned)(bh + bw + bc + bs);
+  const unsigned grid = (unsigned)(bh + bw + bc + bg + bl);
   if (prec == EF_PREC_FP64)
     hipLaunchKernelGGL(k_finalize_cluster<double>, dim3(grid), dim3(256), 0, st, A, g.fin_list,
-                       g.n_fin_hub, l_wave, n_wave, l_half, g.n_fin_half, g.n, bh, bh + bw,
-                       bh + bw + bc);
+                       g.n_fin_hub, l_wave, n_wave, l_half, g.n_fin_half, l_group, g.n_fin_group,
+                       g.n, bh, bh + bw, bh + bw + bc, bh + bw + bc + bg);
   else
     hipLaunchKernelGGL(k_finalize_cluster<float>, dim3(grid), dim3(256), 0, st, A, g.fin_list,
-                       g.n_fin_hub, l_wave, n_wave, l_half, g.n_fin_half, g.n, bh, bh + bw,
-                       bh + bw + bc);
+                       g.n_fin_hub, l_wave, n_wave, l_half, g.n_fin_half, l_group, g.n_fin_group,
+                       g.n, bh, bh + bw, bh + bw + bc, bh + bw + bc + bg);
   return hipGetLastError();
 }
 
