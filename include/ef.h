@@ -365,6 +365,14 @@ ef_status ef_features(ef_graph *g, float *X, float *lnN, uint32_t flags, void *h
 ef_status ef_surrogate_gradients(ef_surrogate *s, const float *X, const float *y, int64_t rows,
                                  float *grad, float *loss, void *hip_stream);
 
+/* The network's output y[i] (the predicted ln N - EF) for rows of 16 inputs
+ * X (row-major, used as given: standardise raw features first), on the same
+ * BF16-operand MFMA kernel that ef_surrogate_predict runs. Host X and y
+ * (copied; the call synchronises), or device pointers with EF_OUT_DEVICE
+ * (asynchronous on hip_stream). rows >= 0, else EF_ERR_ARG. */
+ef_status ef_surrogate_forward(ef_surrogate *s, const float *X, int64_t rows, float *y,
+                               uint32_t flags, void *hip_stream);
+
 /* Train on host rows: X raw features (rows x 16), y targets (ln N - exact EF).
  * Standardises the features (stored with the surrogate), then runs Adam on the
  * GPU with early stopping on a held-out share. */

@@ -318,6 +318,36 @@ ef_status ef_surrogate_gradients(ef_surrogate *s, const float *X, const float *y
   return hip_status(e, "surrogate gradients");
 }
 
+ef_status ef_surrogate_forward(ef_surrogate *s, const float *X, int64_t rows, float *y,
+                               uint32_t flags, void *hip_stream) {
+  if (!s || rows < 0 || (rows > 0 && (!X || !y))) {
+    set_error("ef_surrogate_forward: bad arguments");
+    return EF_ERR_ARG;
+  }
+  if (flags & ~EF_OUT_DEVICE) {
+    set_error("ef_surrogate_forward: unknown flags 0x%x", flags);
+    return EF_ERR_ARG;
+  }
+  if (rows == 0) return EF_OK;
+  hipStream_t st = (hipStream_t)hip_stream;
+  ef_status r = s->device_ready ? EF_OK : sg_upload(s, st);
+  if (r != EF_OK) return r;
+  if (flags & EF_OUT_DEVICE)
+    return hip_status(launch_mlp_forward(X, rows, s->dP, s->dpack, nullptr, y, nullptr, st),
+                      "surrogate forward");
+  float *dX = nullptr, *dy = nullptr;
+  hipError_t e = hipMalloc(&dX, sizeof(float) * kNF * rows);
+  if (e == hipSuccess) e = hipMalloc(&dy, sizeof(float) * rows);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dX, X, sizeof(float) * kNF * rows, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = launch_mlp_forward(dX, rows, s->dP, s->dpack, nullptr, dy, nullptr, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(y, dy, sizeof(float) * rows, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(dX);
+  (void)hipFree(dy);
+  return hip_status(e, "surrogate forward");
+}
+
 ef_status ef_surrogate_train(ef_surrogate *s, const float *X, const float *y, int64_t rows,
                              const ef_train_cfg *cfg, ef_train_report *rep, void *hip_stream) {
   if (!s || !X || !y || rows < 64 || !cfg || cfg->epochs < 0 || cfg->batch < 32 ||

@@ -38,7 +38,8 @@ EXPORTS = [
     "ef_stats", "ef_batch_create", "ef_batch_autotune", "ef_batch_compute",
     "ef_batch_stats_get", "ef_batch_free", "ef_surrogate_create", "ef_surrogate_free",
     "ef_surrogate_get_params", "ef_surrogate_set_params", "ef_surrogate_save",
-    "ef_surrogate_load", "ef_features", "ef_surrogate_gradients", "ef_surrogate_train",
+    "ef_surrogate_load", "ef_features", "ef_surrogate_gradients", "ef_surrogate_forward",
+    "ef_surrogate_train",
     "ef_surrogate_predict", "ef_topk_surrogate", "ef_sir",
 ]
 
@@ -168,6 +169,7 @@ def lib():
     L.ef_surrogate_load.argtypes = [vp, ctypes.c_char_p]
     L.ef_features.argtypes = [vp, vp, vp, u32, vp]
     L.ef_surrogate_gradients.argtypes = [vp, vp, vp, i64, vp, vp, vp]
+    L.ef_surrogate_forward.argtypes = [vp, vp, i64, vp, u32, vp]
     L.ef_surrogate_train.argtypes = [vp, vp, vp, i64, ctypes.POINTER(TrainCfg),
                                      ctypes.POINTER(TrainReport), vp]
     L.ef_surrogate_predict.argtypes = [vp, vp, vp, u32, vp]
@@ -511,6 +513,14 @@ class Surrogate:
         _check(lib().ef_surrogate_gradients(self._h, X.ctypes.data, y.ctypes.data, len(y),
                                             g.ctypes.data, ctypes.byref(loss), _stream_ptr(None)))
         return g, float(loss.value)
+
+    def forward(self, X):
+        """The network's output for rows of 16 (standardised) inputs."""
+        X = np.ascontiguousarray(X, np.float32)
+        y = np.zeros(max(X.shape[0], 1), np.float32)
+        _check(lib().ef_surrogate_forward(self._h, X.ctypes.data, X.shape[0], y.ctypes.data, 0,
+                                          _stream_ptr(None)))
+        return y[:X.shape[0]]
 
     def train(self, X, y, lr=3e-3, epochs=30, batch=4096, seed=0, weight_decay=0.0,
               val_fraction=0.05, patience=4):

@@ -71,3 +71,43 @@ def test_graph_replays_match_eager():
         assert st["replay_ms"] > 0
         assert 0 <= st["tuned_choice"] < 8
         assert all(t > 0 for t in st["tune_ms"])
+
+
+@pytest.mark.parametrize("prec", ["fp32c", "fp64"])
+def test_config4_batch512_full_size_sampled(prec):
+    """The full 512-graph batch (half Watts-Strogatz, half erased configuration
+    model with power-law degrees, n ~ U[1e3, 1e5]; 25.5M nodes). On every
+    node: N against its closed form, the sum rule sum N = 4 W, and the
+    entropy bounds 0 <= EF <= ln N. Against the oracle: 16 random nodes and
+    the three largest-degree nodes of every graph, and every node with more
+    than 2^24 event sequences (the FP64-finalised seeds)."""
+    graphs = gen.batch_512()
+    node_off, rp, ci = efgpu.union_csr(graphs)
+    n = rp.size - 1
+    deg = np.diff(rp).astype(np.int64)
+    with efgpu.Batch(graphs) as b:
+        ef, D, N = b.compute(prec=prec)
+    src = np.repeat(np.arange(n), deg)
+    A = np.bincount(src, weights=deg[ci], minlength=n).astype(np.int64)
+    Nc = deg * deg - 2 * deg + A
+    assert np.array_equal(N, Nc)
+    assert int(N.sum()) == 4 * int((deg * (deg - 1) // 2).sum())
+    ok = N > 1
+    assert np.all(ef >= 0) and np.all(ef[~ok] == 0) and not np.any(np.signbit(ef))
+    assert np.all(ef[ok] <= np.log(N[ok].astype(np.float64)) * (1 + 1e-6))
+    rng = np.random.default_rng(512)
+    pick = [np.flatnonzero(N > (1 << 24))]
+    for i in range(len(graphs)):
+        lo, hi = int(node_off[i]), int(node_off[i + 1])
+        pick.append(lo + rng.choice(hi - lo, 16, replace=False))
+        pick.append(lo + np.argsort(deg[lo:hi], kind="stable")[-3:])
+    seeds = np.unique(np.concatenate(pick)).astype(np.int32)
+    assert np.count_nonzero(N[seeds] > (1 << 24)) >= 10
+    oN, oD, oE = oracle.ef(rp, ci, seeds=seeds, threads=16)
+    assert np.array_equal(N[seeds], oN) and np.array_equal(D[seeds], oD)
+    err = np.abs(ef[seeds] - oE)
+    bad = np.flatnonzero(err > REL[prec] * np.abs(oE))
+    assert bad.size == 0, (prec, seeds[bad[:5]], ef[seeds[bad[:5]]], oE[bad[:5]])
+    pos = oE > 0
+    sys.stderr.write(f"[batch512] {prec}: {seeds.size} oracle seeds, max rel err "
+                     f"{float((err[pos] / oE[pos]).max()):.3e}\n")
