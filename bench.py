@@ -348,14 +348,20 @@ def bench_batch(steps):
            torch.empty(n, dtype=torch.int64, device=dev),
            torch.empty(n, dtype=torch.int64, device=dev))
     b.autotune("fp32c")
-    b.compute(out=out)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        b.compute(out=out)
-    torch.cuda.synchronize()
-    replay_ms = 1e3 * (time.perf_counter() - t0) / steps
+    designs = {}
+    for design in ("phased", "persistent"):
+        b.compute(out=out, design=design)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            b.compute(out=out, design=design)
+        torch.cuda.synchronize()
+        designs[design] = 1e3 * (time.perf_counter() - t0) / steps
+        b.compute(out=out, design=design, profile=True)
+        designs[design + "_kernel_ms"] = b.stats()["replay_ms"]
     bst = b.stats()
+    tuned = "persistent" if bst["design"] == 1 else "phased"
+    replay_ms = designs[tuned]
     b.close()
     # the same work as 512 separate calls (graphs loaded beforehand, device outputs)
     gs = [efgpu.Graph(rp, ci, validate=False) for rp, ci in graphs]
@@ -373,13 +379,18 @@ def bench_batch(steps):
     for g in gs:
         g.close()
     W = int(bst["clusters"])
-    log(f"batch: replay {replay_ms:.2f} ms, separate calls {sep_ms:.1f} ms")
+    log(f"batch: replay {replay_ms:.2f} ms ({tuned}; phased {designs['phased']:.2f}, "
+        f"persistent {designs['persistent']:.2f}), separate calls {sep_ms:.1f} ms")
     return {"workload": "batch512_ws_cm", "graphs": len(graphs), "nodes": n,
             "arcs": int(bst["nnz"]), "clusters": W, "ms_per_batch": replay_ms,
-            "graphs_per_s": len(graphs) / (replay_ms * 1e-3),
+            "tuned_design": tuned, "graphs_per_s": len(graphs) / (replay_ms * 1e-3),
             "clusters_per_s": W / (replay_ms * 1e-3),
+            "designs_ms": {k: round(v, 4) for k, v in designs.items()},
+            "persistent_items": int(bst["items"]),
             "separate_calls_ms": sep_ms, "speedup_vs_separate": sep_ms / replay_ms,
-            "tuned_thresholds": [int(bst["thr8"]), int(bst["thr16"]), int(bst["thr32"])]}
+            "tuned_thresholds": [int(bst["thr8"]), int(bst["thr16"]), int(bst["thr32"])],
+            "tune_ms": {"phased": [round(x, 3) for x in bst["tune_ms"]],
+                        "persistent": [round(x, 3) for x in bst["persist_tune_ms"]]}}
 
 
 def bench_surrogate():

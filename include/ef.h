@@ -263,13 +263,27 @@ ef_status ef_topk_values_noalloc(const double *ef_in, int32_t n, int32_t k, int3
  * into one disjoint union: graph i owns nodes node_off[i] .. node_off[i+1]-1,
  * row_ptr / col_idx are the union's CSR (global ids, host memory, copied).
  * EF of a node of the union equals its EF in its own graph, since a cluster
- * never spans two components (Sec. 3.3). One call computes every graph: each
- * phase of the exact path runs once over the whole batch, the launch sequence
- * is captured into a HIP graph on the first call and replayed afterwards, and
- * the small-degree bin thresholds are tuned on the batch on first use.
- * Outputs are per node of the union, in union order (cluster-centric).
+ * never spans two components (Sec. 3.3). One call computes every graph, in
+ * one of two designs:
+ *   phased      each phase of the exact path runs once over the whole batch
+ *               (one launch per phase and degree bin);
+ *   persistent  a single launch of a persistent kernel whose workgroups take
+ *               (graph, bin, chunk) work items from an atomic cursor; each
+ *               graph moves to its next phase as soon as its own items of
+ *               the previous one are done.
+ * The launch sequence of a design is captured into a HIP graph on its first
+ * use and replayed afterwards. On first use the batch is tuned: both designs
+ * are timed with several settings (small-degree bin thresholds; chunk sizes
+ * of the persistent items) and the fastest is kept; the choice is cached for
+ * the process per size class (graphs, nodes, arcs, largest degree, each
+ * rounded up to a power of two) and precision, so a later batch of the same
+ * class is not timed again. Outputs are per node of the union, in union
+ * order (cluster-centric).
  * ------------------------------------------------------------------------- */
 typedef struct ef_batch ef_batch;
+
+#define EF_BATCH_PHASED     0x10u  /* batch compute: use the phased design */
+#define EF_BATCH_PERSISTENT 0x20u  /* batch compute: use the persistent design */
 
 typedef struct {
   int32_t n_graphs;
@@ -277,9 +291,18 @@ typedef struct {
   int64_t nnz;            /* arcs of the union */
   int64_t clusters;       /* W of the union */
   double replay_ms;       /* last graph replay (set when called with EF_PROFILE) */
-  float tune_ms[8];       /* eager pass time of each threshold candidate */
-  int32_t tuned_choice;   /* index of the chosen candidate */
-  int32_t thr8, thr16, thr32; /* chosen small-bin thresholds */
+  float tune_ms[8];       /* phased design: eager pass time of each threshold candidate */
+  int32_t tuned_choice;   /* phased design: index of the chosen candidate */
+  int32_t thr8, thr16, thr32; /* phased design: chosen small-bin thresholds */
+  float persist_tune_ms[8];   /* persistent design: time of each candidate (thresholds x
+                                 chunk sizes) */
+  int32_t persist_choice;     /* persistent design: index of the chosen candidate */
+  int32_t design;             /* design used without a flag: 0 phased, 1 persistent */
+  int32_t items;              /* work items of the persistent schedule */
+  int32_t from_cache;         /* 1: the tuning came from the size-class cache */
+  int32_t size_class;         /* the batch's size class */
+  int32_t persist_pass2;      /* last synchronised persistent launch: pass-2 seeds */
+  int32_t persist_fp64;       /*   and FP64-finalised seeds */
 } ef_batch_stats;
 
 /* EF_VALIDATE also checks that no arc leaves its graph (EF_ERR_RANGE). */
@@ -287,13 +310,18 @@ ef_status ef_batch_create(int32_t n_graphs, const int32_t *node_off, int64_t nnz
                           const int32_t *row_ptr, const int32_t *col_idx, uint32_t flags,
                           void *hip_stream, ef_batch **out);
 
-/* Time each candidate set of small-bin thresholds on this batch (eager
- * passes) and keep the fastest; drops any captured graph. */
+/* Tune the batch (see above): time every candidate of both designs on this
+ * batch (eager passes) and keep the fastest, or take the size class's cached
+ * choice; drops any captured graph. */
 ef_status ef_batch_autotune(ef_batch *b, ef_prec prec);
 
 /* EF, D, N (D, N nullable) of every node of the union. Host outputs: returns
  * after the copy. EF_OUT_DEVICE: asynchronous on hip_stream. EF_PROFILE:
- * records the replay time (ef_batch_stats_get). */
+ * records the replay time (ef_batch_stats_get). EF_BATCH_PHASED or
+ * EF_BATCH_PERSISTENT runs that design (untuned settings if the batch was
+ * never tuned); without either, the tuned design (tuning on first use).
+ * EF_ERR_DEVICE if, in a synchronised call, the persistent kernel reports a
+ * wait that exceeded its bound (no result is then complete). */
 ef_status ef_batch_compute(ef_batch *b, ef_prec prec, double *ef, int64_t *D, int64_t *N,
                            uint32_t flags, void *hip_stream);
 

@@ -178,6 +178,16 @@ ef_status ef_graph_free(ef_graph *h) {
 ef_status ef_graph_load_csr(int32_t n, int64_t nnz, const int32_t *row_ptr,
                             const int32_t *col_idx, uint32_t flags, void *hip_stream,
                             ef_graph **out) {
+  return efi::graph_load(n, nnz, row_ptr, col_idx, flags, hip_stream, nullptr, 0, out);
+}
+
+}  // extern "C"
+
+namespace efi {
+
+ef_status graph_load(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                     uint32_t flags, void *hip_stream, const int64_t *part_off, int32_t n_parts,
+                     ef_graph **out) {
   if (!out) {
     set_error("ef_graph_load_csr: null output handle");
     return EF_ERR_ARG;
@@ -467,8 +477,17 @@ ef_status ef_graph_load_csr(int32_t n, int64_t nnz, const int32_t *row_ptr,
     if (k > kFinGroupMax) fin.push_back(v);
     else if (k > kFinLaneMax) fin_group.push_back(v);
   }
+  // graph by graph when the nodes are a union of parts (a batch), then
   // longest walks first
+  std::vector<int32_t> part;
+  if (part_off && n_parts > 0) {
+    part.resize((size_t)n);
+    for (int32_t q = 0; q < n_parts; ++q)
+      for (int64_t v = part_off[q]; v < part_off[q + 1]; ++v) part[(size_t)v] = q;
+  }
+  auto part_of = [&](int32_t v) { return part.empty() ? 0 : part[(size_t)v]; };
   auto by_work = [&](int32_t a, int32_t b) {
+    if (part_of(a) != part_of(b)) return part_of(a) < part_of(b);
     return h_work[a] != h_work[b] ? h_work[a] > h_work[b] : a < b;
   };
   for (int bin = 0; bin < 4; ++bin) {
@@ -487,7 +506,13 @@ ef_status ef_graph_load_csr(int32_t n, int64_t nnz, const int32_t *row_ptr,
   ALLOC(g.tri_rec0, sizeof(int4) * std::max<size_t>(rec0.size(), 1), "triangle records");
   g.n_tri_lane = (int64_t)recL.size();
   ALLOC(g.tri_recL, sizeof(int4) * std::max<size_t>(recL.size(), 1), "triangle lane records");
+  // tiers by degree (descending), each graph by graph
+  auto fin_tier = [&](int32_t v) {
+    return g.h_deg[v] > kFinBlockMin ? 0 : g.h_deg[v] > kFinHalfMax ? 1 : 2;
+  };
   std::sort(fin.begin(), fin.end(), [&](int32_t a, int32_t b) {
+    if (fin_tier(a) != fin_tier(b)) return fin_tier(a) < fin_tier(b);
+    if (part_of(a) != part_of(b)) return part_of(a) < part_of(b);
     return g.h_deg[a] != g.h_deg[b] ? g.h_deg[a] > g.h_deg[b] : a < b;
   });
   g.n_fin = (int64_t)fin.size();
@@ -496,6 +521,13 @@ ef_status ef_graph_load_csr(int32_t n, int64_t nnz, const int32_t *row_ptr,
     else if (g.h_deg[v] <= kFinHalfMax) g.n_fin_half++;
   g.n_fin_group = (int64_t)fin_group.size();
   fin.insert(fin.end(), fin_group.begin(), fin_group.end());
+  if (!part.empty()) {
+    // node ids of the lists, for schedules that split them by graph
+    g.h_fin = fin;
+    for (int bin = 0; bin < 4; ++bin) g.h_tri[bin] = tri[bin];
+    g.h_tri_lane.resize(recL.size());
+    for (size_t i = 0; i < recL.size(); ++i) g.h_tri_lane[i] = recL[i].x;
+  }
   ALLOC(g.fin_list, sizeof(int32_t) * std::max<size_t>(fin.size(), 1), "finalize list");
 #undef ALLOC
   hipError_t e = hipSuccess;
@@ -516,6 +548,10 @@ ef_status ef_graph_load_csr(int32_t n, int64_t nnz, const int32_t *row_ptr,
   *out = h;
   return EF_OK;
 }
+
+}  // namespace efi
+
+extern "C" {
 
 ef_status ef_graph_from_edges(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
                               void *hip_stream, ef_graph **out) {

@@ -172,6 +172,9 @@ struct Graph {
   int64_t n_ps[kSeedBins] = {0, 0, 0, 0, 0};
   bool ps_ready = false;
   std::vector<int64_t> h_asum;  // host copy of asum (built on first per-seed use)
+  // graphs loaded as a union of parts (batches): node ids of the triangle
+  // lane bin, of triangle bins 0-3 and of fin_list, in list order
+  std::vector<int32_t> h_tri_lane, h_tri[4], h_fin;
   std::vector<longlong2> h_qa;  // host copy of qa (built on first three-event use)
   // three-event EF over all nodes: seeds by work, descending, and their item
   // offsets (device, built on first use)
@@ -199,6 +202,13 @@ struct Graph {
 // ef_compute flag reserved for the library: launch only, no host read-back
 // (the call is being captured into a HIP graph)
 constexpr uint32_t kInternalNoReadback = 0x80000000u;
+
+// ef_graph_load_csr with the nodes split into n_parts consecutive ranges
+// (part_off[n_parts + 1]; null: one part): the node lists are then ordered
+// part by part, and their node ids kept on the host
+ef_status graph_load(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                     uint32_t flags, void *hip_stream, const int64_t *part_off, int32_t n_parts,
+                     ef_graph **out);
 
 // grow-only device scratch held by the graph handle (one slot shared by the
 // surrogate entry points)
@@ -336,6 +346,47 @@ hipError_t launch_topk(const double *ef, int32_t n, int32_t k, void *scratch,
 hipError_t launch_topk_f32(const float *score, int32_t n, int32_t k, void *scratch,
                            size_t scratch_bytes, int32_t *nodes, double *score_out,
                            hipStream_t st);
+
+// Schedule of the persistent batch kernel (one launch for the whole exact
+// path of a disjoint union of graphs), all device arrays. Work lists per bin,
+// each ordered by graph: pair centres (tiny, 16-, 32-, 64-lane segments, mid
+// classes of 4, 2, 1 centres per workgroup), big centres with their
+// super-tiles and reduction items, triangle nodes of the wavefront bin
+// (records as tri_rec0), of the workgroup bin and of the long bin (ids), and
+// finalize nodes of the 8-, 32-, 64-lane and workgroup tiers (the lane tier
+// takes node id ranges). items: {type, graph, first, end} into those lists
+// (or node ids), in phase order; pend0: items of phases 0, 1, 2 per graph;
+// ctl and pend: counters the kernel resets after every launch. The triangle
+// lane bin is the graph's own tri_recL.
+enum PItemType : int32_t {
+  PI_PAIR_LANE = 0, PI_PAIR_S16, PI_PAIR_S32, PI_PAIR_S64, PI_PAIR_M4, PI_PAIR_M2, PI_PAIR_M1,
+  PI_PAIR_BIG, PI_TRI_LANE, PI_TRI_WAVE, PI_TRI_BLOCK, PI_TRI_LONG,   // phase 0
+  PI_REDUCE,                                                          // phase 1
+  PI_FIN_LANE, PI_FIN_G8, PI_FIN_G32, PI_FIN_G64, PI_FIN_HUB,         // phase 2
+  PI_PASS2,                                                           // phase 3
+  PI_TYPES
+};
+__host__ __device__ constexpr int pitem_phase(int32_t type) {
+  return type <= PI_TRI_LONG ? 0 : type == PI_REDUCE ? 1 : type <= PI_FIN_HUB ? 2 : 3;
+}
+
+struct PersistPlan {
+  int32_t *pair[7] = {};
+  BigCentre *big = nullptr;
+  TileItem *tiles = nullptr;
+  int2 *reduce = nullptr;
+  int4 *tri_wave = nullptr;
+  int32_t *tri_block = nullptr, *tri_long = nullptr;
+  int32_t *fin_list[4] = {};
+  int4 *items = nullptr;
+  int32_t n_items = 0, n_graphs = 0;
+  int32_t *ctl = nullptr, *pend = nullptr, *pend0 = nullptr;
+};
+// a persistent-kernel wait longer than this many polls raises the error flag
+constexpr int32_t kPersistSpinLimit = 1 << 22;
+hipError_t launch_batch_persist(const Graph &g, ef_prec prec, const PersistPlan &pl, void *R,
+                                void *rec, TriSlot *Y, void *Z, int64_t *ZT, double *ef,
+                                int64_t *D, int64_t *N, uint8_t *fl, hipStream_t st);
 
 // scatter outputs of unique seeds back to the caller's positions
 hipError_t launch_gather_outputs(const int32_t *inv, int32_t count, const double *ef_u,

@@ -196,6 +196,44 @@ template <int S> __device__ __forceinline__ double rot_seg(double x) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// one group of 64/S centres (list positions gi*PER ..) on a wavefront
+template <typename T, int S>
+__device__ __forceinline__ void pairs_seg_group(const int32_t *__restrict__ row_ptr,
+                                                const int32_t *__restrict__ deg,
+                                                const int2 *__restrict__ adj2,
+                                                const int32_t *__restrict__ list, int64_t count,
+                                                int64_t gi, void *__restrict__ R) {
+  constexpr int PER = 64 / S;
+  const int lane = threadIdx.x & 63;
+  const int seg = lane / S, j = lane & (S - 1);
+  const int64_t it = gi * PER + seg;
+  const bool have = it < count;
+  const int32_t v = have ? list[it] : 0;
+  const int32_t k = have ? deg[v] : 0;
+  const int32_t base = have ? row_ptr[v] : 0;
+  const bool valid = j < k;
+  const T kp = valid ? (T)adj2[base + j].y : T(0);
+  const T cp = valid ? (T)(k - 4) + kp : (T)kNegF;
+  T kq = valid ? kp : (T)kNegF;
+  T Rt = T(0), C = T(0);
+#pragma unroll 4
+  for (int s = 1; s <= S / 2; ++s) {
+    kq = rot_seg<S>(kq);
+    T g = score_masked(cp + kq);
+    if (s == S / 2) g = j < S / 2 ? g : T(0);
+    Rt += g;
+    C = rot_seg<S>(C) + g;
+  }
+  // column (j + S/2) mod S is in C of this lane; bring column j home
+  const T Cl = __shfl_xor(C, S / 2, 64);
+  if (valid) {
+    Acc<T> a;
+    a.add(Rt);
+    a.add(Cl);
+    a.store(R, base + j);
+  }
+}
+
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_pairs_small(const int32_t *__restrict__ row_ptr,
                                                      const int32_t *__restrict__ deg,
@@ -203,39 +241,11 @@ __global__ __launch_bounds__(256) void k_pairs_small(const int32_t *__restrict__
                                                      const int32_t *__restrict__ list,
                                                      int64_t count, void *__restrict__ R) {
   constexpr int PER = 64 / S;
-  const int lane = threadIdx.x & 63;
-  const int seg = lane / S, j = lane & (S - 1);
   const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   const int64_t groups = (count + PER - 1) / PER;
-  for (int64_t gi = wave; gi < groups; gi += nwaves) {
-    const int64_t it = gi * PER + seg;
-    const bool have = it < count;
-    const int32_t v = have ? list[it] : 0;
-    const int32_t k = have ? deg[v] : 0;
-    const int32_t base = have ? row_ptr[v] : 0;
-    const bool valid = j < k;
-    const T kp = valid ? (T)adj2[base + j].y : T(0);
-    const T cp = valid ? (T)(k - 4) + kp : (T)kNegF;
-    T kq = valid ? kp : (T)kNegF;
-    T Rt = T(0), C = T(0);
-#pragma unroll 4
-    for (int s = 1; s <= S / 2; ++s) {
-      kq = rot_seg<S>(kq);
-      T g = score_masked(cp + kq);
-      if (s == S / 2) g = j < S / 2 ? g : T(0);
-      Rt += g;
-      C = rot_seg<S>(C) + g;
-    }
-    // column (j + S/2) mod S is in C of this lane; bring column j home
-    const T Cl = __shfl_xor(C, S / 2, 64);
-    if (valid) {
-      Acc<T> a;
-      a.add(Rt);
-      a.add(Cl);
-      a.store(R, base + j);
-    }
-  }
+  for (int64_t gi = wave; gi < groups; gi += nwaves)
+    pairs_seg_group<T, S>(row_ptr, deg, adj2, list, count, gi, R);
 }
 
 // ---------------------------------------------------------------------------
@@ -245,41 +255,47 @@ __global__ __launch_bounds__(256) void k_pairs_small(const int32_t *__restrict__
 // wavefront. Rows past k are clamped to valid neighbours and masked.
 // ---------------------------------------------------------------------------
 template <typename T>
+__device__ __forceinline__ void pairs_lane_one(const int32_t *__restrict__ row_ptr,
+                                               const int32_t *__restrict__ deg,
+                                               const int2 *__restrict__ adj2, int32_t v,
+                                               void *__restrict__ R) {
+  constexpr int K = kSmallLaneMax;
+  const int32_t k = deg[v], base = row_ptr[v];  // 2 <= k <= K
+  T kp[K];
+#pragma unroll
+  for (int p = 0; p < K; ++p) kp[p] = (T)adj2[base + (p < k ? p : k - 1)].y;
+  const T c = (T)(k - 4);
+  T r[K];
+#pragma unroll
+  for (int p = 0; p < K; ++p) r[p] = T(0);
+#pragma unroll
+  for (int p = 0; p < K; ++p) {
+#pragma unroll
+    for (int q = p + 1; q < K; ++q) {
+      const T g = q < k ? score_masked(c + kp[p] + kp[q]) : T(0);
+      r[p] += g;
+      r[q] += g;
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < K; ++p) {
+    if (p < k) {
+      Acc<T> a;
+      a.add(r[p]);
+      a.store(R, base + p);
+    }
+  }
+}
+
+template <typename T>
 __global__ __launch_bounds__(256) void k_pairs_lane(const int32_t *__restrict__ row_ptr,
                                                     const int32_t *__restrict__ deg,
                                                     const int2 *__restrict__ adj2,
                                                     const int32_t *__restrict__ list,
                                                     int64_t count, void *__restrict__ R) {
-  constexpr int K = 8;
   for (int64_t it = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; it < count;
-       it += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t v = list[it];
-    const int32_t k = deg[v], base = row_ptr[v];  // 2 <= k <= K
-    T kp[K];
-#pragma unroll
-    for (int p = 0; p < K; ++p) kp[p] = (T)adj2[base + (p < k ? p : k - 1)].y;
-    const T c = (T)(k - 4);
-    T r[K];
-#pragma unroll
-    for (int p = 0; p < K; ++p) r[p] = T(0);
-#pragma unroll
-    for (int p = 0; p < K; ++p) {
-#pragma unroll
-      for (int q = p + 1; q < K; ++q) {
-        const T g = q < k ? score_masked(c + kp[p] + kp[q]) : T(0);
-        r[p] += g;
-        r[q] += g;
-      }
-    }
-#pragma unroll
-    for (int p = 0; p < K; ++p) {
-      if (p < k) {
-        Acc<T> a;
-        a.add(r[p]);
-        a.store(R, base + p);
-      }
-    }
-  }
+       it += (int64_t)gridDim.x * blockDim.x)
+    pairs_lane_one<T>(row_ptr, deg, adj2, list[it], R);
 }
 
 // ---------------------------------------------------------------------------
@@ -348,31 +364,45 @@ __device__ __forceinline__ void zero_parts(T *p, int count) {
 // wavefronts each (G = 4, 2, 1 for up to 4, 8, 16 blocks of 64 neighbours)
 // ---------------------------------------------------------------------------
 template <typename T, int G>
+using MidParts = T[G][kBlocksPerSuper / G][9][64];
+
+// centres gi*G .. gi*G+G-1 of the list on a 16-wavefront workgroup (every
+// thread calls it: it holds workgroup barriers)
+template <typename T, int G>
+__device__ __forceinline__ void pairs_mid_group(const int32_t *__restrict__ row_ptr,
+                                                const int32_t *__restrict__ deg,
+                                                const int2 *__restrict__ adj2,
+                                                const int32_t *__restrict__ list, int64_t count,
+                                                int64_t gi, void *__restrict__ R,
+                                                MidParts<T, G> &parts) {
+  constexpr int WPG = kBlocksPerSuper / G;  // wavefronts per centre
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int grp = w / WPG, wl = w % WPG;
+  const int64_t it = gi * G + grp;
+  const bool have = it < count;  // a group without a centre still meets the barriers
+  const int32_t v = have ? list[it] : 0;
+  const int32_t k = have ? deg[v] : 0;
+  const int32_t base = have ? row_ptr[v] : 0;
+  const int nb = (k + 63) >> 6;
+  zero_parts(&parts[0][0][0][0], G * WPG * 9 * 64);
+  __syncthreads();
+  Acc<T> out;
+  diag_super<T>(adj2, base, k, (T)(k - 4), 0, nb, parts[grp], wl, out);
+  const int32_t p = 64 * wl + lane;
+  if (wl < nb && p < k) out.store(R, base + p);
+  __syncthreads();
+}
+
+template <typename T, int G>
 __global__ __launch_bounds__(1024) void k_pairs_mid(const int32_t *__restrict__ row_ptr,
                                                     const int32_t *__restrict__ deg,
                                                     const int2 *__restrict__ adj2,
                                                     const int32_t *__restrict__ list,
                                                     int64_t count, void *__restrict__ R) {
-  constexpr int WPG = kBlocksPerSuper / G;  // wavefronts per centre
-  __shared__ T parts[G][WPG][9][64];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int grp = w / WPG, wl = w % WPG;
+  __shared__ MidParts<T, G> parts;
   const int64_t ngroups = (count + G - 1) / G;
-  for (int64_t gi = blockIdx.x; gi < ngroups; gi += gridDim.x) {
-    const int64_t it = gi * G + grp;
-    const bool have = it < count;  // a group without a centre still meets the barriers
-    const int32_t v = have ? list[it] : 0;
-    const int32_t k = have ? deg[v] : 0;
-    const int32_t base = have ? row_ptr[v] : 0;
-    const int nb = (k + 63) >> 6;
-    zero_parts(&parts[0][0][0][0], G * WPG * 9 * 64);
-    __syncthreads();
-    Acc<T> out;
-    diag_super<T>(adj2, base, k, (T)(k - 4), 0, nb, parts[grp], wl, out);
-    const int32_t p = 64 * wl + lane;
-    if (wl < nb && p < k) out.store(R, base + p);
-    __syncthreads();
-  }
+  for (int64_t gi = blockIdx.x; gi < ngroups; gi += gridDim.x)
+    pairs_mid_group<T, G>(row_ptr, deg, adj2, list, count, gi, R, parts);
 }
 
 // mid centres into their classes (order within a class is not fixed; every
@@ -420,6 +450,89 @@ __global__ __launch_bounds__(256) void k_mid_split(const int32_t *__restrict__ d
 // larger table is slower).
 // ---------------------------------------------------------------------------
 constexpr int kGTab = 4096;
+template <typename T> struct BigLds {
+  static constexpr bool kTab = std::is_same<T, float>::value;
+  static constexpr int kTabBytes = kTab ? kGTab * 4 : 0;
+  static constexpr int kPartBytes = kBlocksPerSuper * kBlocksPerSuper * 64 * (int)sizeof(T);
+  static constexpr int kBytes = kTabBytes + kPartBytes;
+};
+
+// One super-tile on a 16-wavefront workgroup (every thread calls it: it holds
+// workgroup barriers). lds: BigLds<T>::kBytes, the scores of the current
+// centre (FP32 path) first, at address 0, so that a table read needs no base
+// added; then the partials. tab_v: the centre whose scores lds holds (-1:
+// none), kept by the caller across calls.
+template <typename T>
+__device__ __forceinline__ void pairs_big_tile(const int32_t *__restrict__ row_ptr,
+                                               const int32_t *__restrict__ deg,
+                                               const int2 *__restrict__ adjs,
+                                               const BigCentre *__restrict__ big,
+                                               const TileItem ti, void *__restrict__ rec,
+                                               unsigned char *lds, int32_t &tab_v) {
+  constexpr bool kTab = BigLds<T>::kTab;
+  float *gtab = reinterpret_cast<float *>(lds);
+  T(*parts)[kBlocksPerSuper][64] =
+      reinterpret_cast<T(*)[kBlocksPerSuper][64]>(lds + BigLds<T>::kTabBytes);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int2 *adj2 = adjs;
+  const BigCentre bc = big[ti.big];
+  const int32_t v = bc.v, k = deg[v], base = row_ptr[v], ns = bc.ns;
+  const int P = ti.P, Q = ti.Q;
+  const int64_t tile_idx = bc.rec_base + (int64_t)P * ns - (int64_t)P * (P - 1) / 2 + (Q - P);
+  const int64_t rbase = tile_idx * kRecEntries;
+  const int nbQ = min(kBlocksPerSuper, (k - kSuper * Q + 63) >> 6);
+  const T kv4 = (T)(k - 4);
+  if (P == Q) {
+    zero_parts(&parts[0][0][0], kBlocksPerSuper * 9 * 64);
+    __syncthreads();
+    Acc<T> out;
+    diag_super<T>(adj2, base, k, kv4, kBlocksPerSuper * P, nbQ,
+                  reinterpret_cast<T(*)[9][64]>(&parts[0][0][0]), w, out);
+    if (w < nbQ) out.store(rec, rbase + 64 * w + lane);
+  } else {
+    // P < Q: all 16 row blocks of P are full
+    const int32_t p = kSuper * P + 64 * w + lane;
+    const int32_t kp = adj2[base + p].y;
+    const T cp = kv4 + (T)kp;
+    const bool ragged_q = (kSuper * Q + 64 * nbQ) > k;
+    // the largest row degree of this wavefront's block (rows ascend)
+    const int32_t kp_max = __shfl(kp, 63, 64);
+    if (kTab && v != tab_v) {  // uniform: one centre per work item
+      const float d0 = (float)(k - 2);
+      for (int i = threadIdx.x; i < kGTab; i += blockDim.x) gtab[i] = score(d0 + (float)i);
+      __syncthreads();
+      tab_v = v;
+    }
+    Acc<T> out;
+    for (int dl = 0; dl < nbQ; ++dl) {
+      const int c = (w + dl) % nbQ;
+      const int32_t q = kSuper * Q + 64 * c + lane;
+      const T kq = col_degree<T>(adj2, base, k, q);
+      T Rt, C;
+      if (ragged_q && c == nbQ - 1) {
+        tile<T, false, true>(cp, kq, Rt, C);
+      } else if (kTab && kp_max + __shfl((int32_t)kq, 63, 64) - 2 < kGTab) {
+        tile_tab<T>(kp - 2, (int32_t)kq, gtab, Rt, C);
+      } else {
+        tile<T, false, false>(cp, kq, Rt, C);
+      }
+      parts[c][w][(lane + 63) & 63] = C;
+      out.add(Rt);
+    }
+    out.store(rec, rbase + 64 * w + lane);
+    __syncthreads();
+    {
+      const int c = threadIdx.x >> 6, j = threadIdx.x & 63;
+      if (c < nbQ) {
+        Acc<T> col;
+        for (int ww = 0; ww < kBlocksPerSuper; ++ww) col.add(parts[c][ww][j]);
+        col.store(rec, rbase + kSuper + 64 * c + j);
+      }
+    }
+  }
+  __syncthreads();
+}
+
 template <typename T>
 __global__ __launch_bounds__(1024) void k_pairs_big(const int32_t *__restrict__ row_ptr,
                                                     const int32_t *__restrict__ deg,
@@ -428,77 +541,12 @@ __global__ __launch_bounds__(1024) void k_pairs_big(const int32_t *__restrict__ 
                                                     const TileItem *__restrict__ tiles,
                                                     int64_t count, void *__restrict__ rec,
                                                     const int32_t *__restrict__ agg_done) {
-  constexpr bool kTab = std::is_same<T, float>::value;
-  constexpr int kTabBytes = kTab ? kGTab * 4 : 0;
-  constexpr int kPartBytes = kBlocksPerSuper * kBlocksPerSuper * 64 * (int)sizeof(T);
-  // one LDS buffer: the scores of the current centre (FP32 path) first, at
-  // address 0, so that a table read needs no base added; then the partials
-  __shared__ __align__(16) unsigned char lds[kTabBytes + kPartBytes];
-  float *gtab = reinterpret_cast<float *>(lds);
-  T(*parts)[kBlocksPerSuper][64] = reinterpret_cast<T(*)[kBlocksPerSuper][64]>(lds + kTabBytes);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  int32_t tab_v = -1;                       // centre whose scores gtab holds
-  const int2 *adj2 = adjs;
+  __shared__ __align__(16) unsigned char lds[BigLds<T>::kBytes];
+  int32_t tab_v = -1;  // centre whose scores the table holds
   for (int64_t it = blockIdx.x; it < count; it += gridDim.x) {
     const TileItem ti = tiles[it];
     if (agg_done && agg_done[ti.big]) continue;  // uniform per workgroup
-    const BigCentre bc = big[ti.big];
-    const int32_t v = bc.v, k = deg[v], base = row_ptr[v], ns = bc.ns;
-    const int P = ti.P, Q = ti.Q;
-    const int64_t tile_idx = bc.rec_base + (int64_t)P * ns - (int64_t)P * (P - 1) / 2 + (Q - P);
-    const int64_t rbase = tile_idx * kRecEntries;
-    const int nbQ = min(kBlocksPerSuper, (k - kSuper * Q + 63) >> 6);
-    const T kv4 = (T)(k - 4);
-    if (P == Q) {
-      zero_parts(&parts[0][0][0], kBlocksPerSuper * 9 * 64);
-      __syncthreads();
-      Acc<T> out;
-      diag_super<T>(adj2, base, k, kv4, kBlocksPerSuper * P, nbQ,
-                    reinterpret_cast<T(*)[9][64]>(&parts[0][0][0]), w, out);
-      if (w < nbQ) out.store(rec, rbase + 64 * w + lane);
-    } else {
-      // P < Q: all 16 row blocks of P are full
-      const int32_t p = kSuper * P + 64 * w + lane;
-      const int32_t kp = adj2[base + p].y;
-      const T cp = kv4 + (T)kp;
-      const bool ragged_q = (kSuper * Q + 64 * nbQ) > k;
-      // the largest row degree of this wavefront's block (rows ascend)
-      const int32_t kp_max = __shfl(kp, 63, 64);
-      if (kTab && v != tab_v) {  // uniform: one centre per work item
-        const float d0 = (float)(k - 2);
-        for (int i = threadIdx.x; i < kGTab; i += blockDim.x)
-          gtab[i] = score(d0 + (float)i);
-        __syncthreads();
-        tab_v = v;
-      }
-      Acc<T> out;
-      for (int dl = 0; dl < nbQ; ++dl) {
-        const int c = (w + dl) % nbQ;
-        const int32_t q = kSuper * Q + 64 * c + lane;
-        const T kq = col_degree<T>(adj2, base, k, q);
-        T Rt, C;
-        if (ragged_q && c == nbQ - 1) {
-          tile<T, false, true>(cp, kq, Rt, C);
-        } else if (kTab && kp_max + __shfl((int32_t)kq, 63, 64) - 2 < kGTab) {
-          tile_tab<T>(kp - 2, (int32_t)kq, gtab, Rt, C);
-        } else {
-          tile<T, false, false>(cp, kq, Rt, C);
-        }
-        parts[c][w][(lane + 63) & 63] = C;
-        out.add(Rt);
-      }
-      out.store(rec, rbase + 64 * w + lane);
-      __syncthreads();
-      {
-        const int c = threadIdx.x >> 6, j = threadIdx.x & 63;
-        if (c < nbQ) {
-          Acc<T> col;
-          for (int ww = 0; ww < kBlocksPerSuper; ++ww) col.add(parts[c][ww][j]);
-          col.store(rec, rbase + kSuper + 64 * c + j);
-        }
-      }
-    }
-    __syncthreads();
+    pairs_big_tile<T>(row_ptr, deg, adjs, big, ti, rec, lds, tab_v);
   }
 }
 
@@ -646,6 +694,32 @@ __global__ __launch_bounds__(1024) void k_pairs_agg(const int32_t *__restrict__ 
 // R = sum_{Q >= b} row part of (b, Q)  +  sum_{P < b} column part of (P, b)
 // One workgroup per (big centre, super-block b): the 1024 arcs of block b.
 template <typename T>
+__device__ __forceinline__ void arc_reduce_item(const int32_t *__restrict__ row_ptr,
+                                                const int32_t *__restrict__ deg,
+                                                const int2 *__restrict__ adjs,
+                                                const BigCentre *__restrict__ big,
+                                                const int2 item, const void *__restrict__ rec,
+                                                void *__restrict__ R) {
+  const BigCentre bc = big[item.x];
+  const int b = item.y;
+  const int32_t k = deg[bc.v], base = row_ptr[bc.v], ns = bc.ns;
+  for (int j = threadIdx.x; j < kSuper; j += blockDim.x) {
+    const int32_t p = kSuper * b + j;
+    if (p >= k) break;
+    Acc<T> a;
+    for (int Q = b; Q < ns; ++Q) {
+      const int64_t t = bc.rec_base + (int64_t)b * ns - (int64_t)b * (b - 1) / 2 + (Q - b);
+      a.add_stored(rec, t * kRecEntries + j);
+    }
+    for (int P = 0; P < b; ++P) {
+      const int64_t t = bc.rec_base + (int64_t)P * ns - (int64_t)P * (P - 1) / 2 + (b - P);
+      a.add_stored(rec, t * kRecEntries + kSuper + j);
+    }
+    a.store(R, base + adjs[base + p].x);  // sorted position -> arc of the row
+  }
+}
+
+template <typename T>
 __global__ __launch_bounds__(256) void k_arc_reduce(const int32_t *__restrict__ row_ptr,
                                                     const int32_t *__restrict__ deg,
                                                     const int2 *__restrict__ adjs,
@@ -657,23 +731,7 @@ __global__ __launch_bounds__(256) void k_arc_reduce(const int32_t *__restrict__ 
   for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
     const int2 item = items[it];
     if (agg_done && agg_done[item.x]) continue;
-    const BigCentre bc = big[item.x];
-    const int b = item.y;
-    const int32_t k = deg[bc.v], base = row_ptr[bc.v], ns = bc.ns;
-    for (int j = threadIdx.x; j < kSuper; j += blockDim.x) {
-      const int32_t p = kSuper * b + j;
-      if (p >= k) break;
-      Acc<T> a;
-      for (int Q = b; Q < ns; ++Q) {
-        const int64_t t = bc.rec_base + (int64_t)b * ns - (int64_t)b * (b - 1) / 2 + (Q - b);
-        a.add_stored(rec, t * kRecEntries + j);
-      }
-      for (int P = 0; P < b; ++P) {
-        const int64_t t = bc.rec_base + (int64_t)P * ns - (int64_t)P * (P - 1) / 2 + (b - P);
-        a.add_stored(rec, t * kRecEntries + kSuper + j);
-      }
-      a.store(R, base + adjs[base + p].x);  // sorted position -> arc of the row
-    }
+    arc_reduce_item<T>(row_ptr, deg, adjs, big, item, rec, R);
   }
 }
 

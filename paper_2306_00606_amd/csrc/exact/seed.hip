@@ -177,6 +177,10 @@ __device__ __forceinline__ void fin_arcs(const int2 *__restrict__ adj2,
   }
 }
 
+// (Z, ZT and, in pass 2, D are read through plain pointers: in the persistent
+// batch kernel they are written earlier in the same launch, and a restricted
+// pointer read at a wavefront-uniform index could be served from the scalar
+// cache, which a device-scope acquire does not refresh.)
 // N and D of v in closed form from k, As = sum k_a, Q = sum k_a^2 and
 // A2 = sum asum[a] over the neighbours a (summing the per-arc identities
 // N_e = (k-1) + (k_a-1) and
@@ -186,7 +190,7 @@ template <typename T>
 __device__ __forceinline__ void fin_store(int32_t v, int32_t k, int64_t As, longlong2 qa,
                                           bool has_z, typename SumT<T>::type sacc, double tfix,
                                           int64_t Tc, const void *Z,
-                                          const int64_t *__restrict__ ZT, double *ef,
+                                          const int64_t *ZT, double *ef,
                                           int64_t *Dout, int64_t *Nout, uint8_t *fl) {
   using S = SumT<T>;
   typename S::type z = typename S::type();
@@ -275,11 +279,12 @@ template <> struct RVal<double> {
 };
 
 template <typename T>
-__device__ __forceinline__ void fin_lanes(const FinArgs &A, int32_t n, int64_t blk, int64_t nblk) {
+__device__ __forceinline__ void fin_lanes(const FinArgs &A, int64_t lo, int64_t hi, int64_t blk,
+                                          int64_t nblk) {
   using Acc = typename SumT<T>::type;
   constexpr int K = kFinLaneMax;
   const int64_t stride = nblk * (int64_t)blockDim.x;
-  for (int64_t v = blk * (int64_t)blockDim.x + threadIdx.x; v < n; v += stride) {
+  for (int64_t v = lo + blk * (int64_t)blockDim.x + threadIdx.x; v < hi; v += stride) {
     const int32_t k = A.deg[v];
     if (k > K) continue;
     Acc sacc = Acc();
@@ -319,22 +324,23 @@ __device__ __forceinline__ void fin_lanes(const FinArgs &A, int32_t n, int64_t b
   }
 }
 
-// one workgroup (4 wavefronts) per hub; partials combined in a fixed order
+// one workgroup (up to 16 wavefronts) per hub; partials combined in a fixed order
 template <typename T>
 __device__ __forceinline__ void fin_hubs(const FinArgs &A, const int32_t *nodes, int64_t count,
                                          int64_t blk, int64_t nblk) {
   using Acc = typename SumT<T>::type;
-  __shared__ Acc shS[4];
-  __shared__ double shT[4];
-  __shared__ int64_t shC[4];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  __shared__ Acc shS[16];
+  __shared__ double shT[16];
+  __shared__ int64_t shC[16];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = (int)(blockDim.x >> 6);
   for (int64_t it = blk; it < count; it += nblk) {
     const int32_t v = nodes[it];
     const int32_t k = A.deg[v];
     Acc sacc = Acc();
     double tfix = 0.0;
     int64_t Tc = 0;
-    fin_arcs<T>(A.adj2, A.rev, A.trec, A.R, A.Y, k, A.row_ptr[v], tid, 256, sacc, tfix, Tc);
+    fin_arcs<T>(A.adj2, A.rev, A.trec, A.R, A.Y, k, A.row_ptr[v], tid, (int32_t)blockDim.x, sacc,
+                tfix, Tc);
     sacc = wave_sum(sacc);
     tfix = wave_sum_f64(tfix);
     Tc = wave_sum_i64(Tc);
@@ -345,7 +351,7 @@ __device__ __forceinline__ void fin_hubs(const FinArgs &A, const int32_t *nodes,
     }
     __syncthreads();
     if (tid == 0) {
-      for (int w = 1; w < 4; ++w) {
+      for (int w = 1; w < nw; ++w) {
         acc_merge(sacc, shS[w]);
         tfix += shT[w];
         Tc += shC[w];
@@ -374,7 +380,7 @@ __global__ __launch_bounds__(256) void k_finalize_cluster(
   else if (b < b1) fin_groups<T, 64>(A, l_wave, n_wave, 0, b - b0, b1 - b0);
   else if (b < b2) fin_groups<T, 32>(A, l_half, n_half, 0, b - b1, b2 - b1);
   else if (b < b3) fin_groups<T, 8>(A, l_group, n_group, 0, b - b2, b3 - b2);
-  else fin_lanes<T>(A, n, b - b3, (int64_t)gridDim.x - b3);
+  else fin_lanes<T>(A, 0, n, b - b3, (int64_t)gridDim.x - b3);
 }
 
 static unsigned cap_blocks(int64_t b, int64_t cap) {
@@ -776,6 +782,71 @@ __device__ __forceinline__ int32_t find_sorted(const int32_t *a, int32_t len, in
 
 constexpr int kP2Max = 512;
 
+// FP32C pass 2 of one flagged seed s (output position pos) on a workgroup
+// (every thread calls it: it holds workgroup barriers). LDS: the seed's
+// neighbours and their pairwise adjacency bits for k <= kP2Max.
+struct Pass2Lds {
+  int32_t nid[kP2Max], nk[kP2Max];
+  uint32_t bits[kP2Max * (kP2Max / 32)];
+  DFv sh[16];
+};
+
+__device__ __forceinline__ void pass2_seed(const int32_t *__restrict__ row_ptr,
+                                           const int32_t *__restrict__ col,
+                                           const int32_t *__restrict__ deg,
+                                           const int2 *__restrict__ adj2, int32_t s, int32_t pos,
+                                           double *ef, const int64_t *Dv, Pass2Lds &L) {
+  const int tid = threadIdx.x, nt = (int)blockDim.x;
+  const int32_t k = deg[s], base = row_ptr[s];
+  const int64_t D = Dv[pos];
+  const bool lds = k <= kP2Max;
+  constexpr int W = kP2Max / 32;
+  if (lds) {
+    for (int i = tid; i < k; i += nt) {
+      const int2 ad = adj2[base + i];
+      L.nid[i] = ad.x;
+      L.nk[i] = ad.y;
+    }
+    for (int i = tid; i < k * W; i += nt) L.bits[i] = 0u;
+  }
+  __syncthreads();
+  DFv acc = DFv();
+  // paths s -> a -> b (one event order each)
+  for (int32_t i = 0; i < k; ++i) {
+    const int2 ad = adj2[base + i];
+    const int32_t a = ad.x, ka = ad.y;
+    for (int32_t f = row_ptr[a] + tid; f < row_ptr[a + 1]; f += nt) {
+      const int2 bd = adj2[f];
+      const int32_t b = bd.x;
+      if (b == s) continue;
+      const int32_t j = lds ? find_sorted(L.nid, k, b) : find_sorted(col + base, k, b);
+      if (j >= 0 && lds) atomicOr(&L.bits[i * W + (j >> 5)], 1u << (j & 31));
+      acc.add(term_nonneg(k + ka + bd.y - 4 - (j >= 0 ? 2 : 0), D));
+    }
+  }
+  __syncthreads();
+  // stars a - s - b (two event orders each)
+  for (int32_t i = 0; i < k; ++i) {
+    const int32_t a = lds ? L.nid[i] : adj2[base + i].x;
+    const int32_t ka = lds ? L.nk[i] : adj2[base + i].y;
+    for (int32_t j = i + 1 + tid; j < k; j += nt) {
+      const int32_t kb = lds ? L.nk[j] : adj2[base + j].y;
+      bool m;
+      if (lds) m = (L.bits[i * W + (j >> 5)] >> (j & 31)) & 1u;
+      else m = find_sorted(col + row_ptr[a], deg[a], col[base + j]) >= 0;
+      const float t = term_nonneg(k + ka + kb - 4 - (m ? 2 : 0), D);
+      acc.add(t);
+      acc.add(t);
+    }
+  }
+  acc = block_sum_acc(acc, L.sh);
+  if (tid == 0) {
+    const double e = acc.value() / (double)D;
+    ef[pos] = e > 0.0 ? e : 0.0;
+  }
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(256) void k_pass2(const int32_t *__restrict__ row_ptr,
                                                const int32_t *__restrict__ col,
                                                const int32_t *__restrict__ deg,
@@ -785,62 +856,11 @@ __global__ __launch_bounds__(256) void k_pass2(const int32_t *__restrict__ row_p
                                                const int32_t *__restrict__ flag_count,
                                                double *__restrict__ ef,
                                                const int64_t *__restrict__ Dv) {
-  __shared__ int32_t nid[kP2Max], nk[kP2Max];
-  __shared__ uint32_t bits[kP2Max * (kP2Max / 32)];
-  __shared__ DFv shA[4];
-  const int tid = threadIdx.x;
+  __shared__ Pass2Lds L;
   const int32_t count = *flag_count;
   for (int32_t it = blockIdx.x; it < count; it += gridDim.x) {
     const int32_t pos = flagged[it];
-    const int32_t s = seeds ? seeds[pos] : pos;
-    const int32_t k = deg[s], base = row_ptr[s];
-    const int64_t D = Dv[pos];
-    const bool lds = k <= kP2Max;
-    constexpr int W = kP2Max / 32;
-    if (lds) {
-      for (int i = tid; i < k; i += 256) {
-        const int2 ad = adj2[base + i];
-        nid[i] = ad.x;
-        nk[i] = ad.y;
-      }
-      for (int i = tid; i < k * W; i += 256) bits[i] = 0u;
-    }
-    __syncthreads();
-    DFv acc = DFv();
-    // paths s -> a -> b (one event order each)
-    for (int32_t i = 0; i < k; ++i) {
-      const int2 ad = adj2[base + i];
-      const int32_t a = ad.x, ka = ad.y;
-      for (int32_t f = row_ptr[a] + tid; f < row_ptr[a + 1]; f += 256) {
-        const int2 bd = adj2[f];
-        const int32_t b = bd.x;
-        if (b == s) continue;
-        const int32_t j = lds ? find_sorted(nid, k, b) : find_sorted(col + base, k, b);
-        if (j >= 0 && lds) atomicOr(&bits[i * W + (j >> 5)], 1u << (j & 31));
-        acc.add(term_nonneg(k + ka + bd.y - 4 - (j >= 0 ? 2 : 0), D));
-      }
-    }
-    __syncthreads();
-    // stars a - s - b (two event orders each)
-    for (int32_t i = 0; i < k; ++i) {
-      const int32_t a = lds ? nid[i] : adj2[base + i].x;
-      const int32_t ka = lds ? nk[i] : adj2[base + i].y;
-      for (int32_t j = i + 1 + tid; j < k; j += 256) {
-        const int32_t kb = lds ? nk[j] : adj2[base + j].y;
-        bool m;
-        if (lds) m = (bits[i * W + (j >> 5)] >> (j & 31)) & 1u;
-        else m = find_sorted(col + row_ptr[a], deg[a], col[base + j]) >= 0;
-        const float t = term_nonneg(k + ka + kb - 4 - (m ? 2 : 0), D);
-        acc.add(t);
-        acc.add(t);
-      }
-    }
-    acc = block_sum_acc(acc, shA);
-    if (tid == 0) {
-      const double e = acc.value() / (double)D;
-      ef[pos] = e > 0.0 ? e : 0.0;
-    }
-    __syncthreads();
+    pass2_seed(row_ptr, col, deg, adj2, seeds ? seeds[pos] : pos, pos, ef, Dv, L);
   }
 }
 

@@ -267,131 +267,162 @@ struct TriArgs {
   int64_t *ZT;
 };
 
-// One node w per wavefront (|up(w)| <= 64, short walk); WPB wavefronts per
-// workgroup, each with its own LDS state; chunks of 64 segments. The list
-// holds {w, first up slot, first segment, |up(w)| | segments << 16} per node:
-// the next node's record is loaded while this one runs, and this node's
-// up(w) and first segments are loaded together, so a short node waits on
-// one global round trip before its walk.
-template <typename T, int SLOTS, int MAXM, int WPB>
-__global__ __launch_bounds__(64 * WPB) void k_tri_wave(TriArgs A, const int4 *__restrict__ recs,
-                                                        int64_t count) {
+// One node w per wavefront (|up(w)| <= 64, short walk), chunks of 64
+// segments, with the wavefront's own LDS state. rc = {w, first up slot, first
+// segment, |up(w)| | segments << 16}. On entry the hash holds no key, flg is
+// zero and the credit slots are clear (tri_wave_init); on return too: each
+// lane empties the one hash slot it filled, so a short list does not pay for
+// the whole table.
+template <typename T, int SLOTS, int MAXM>
+__device__ __forceinline__ void tri_wave_node(const TriArgs &A, const int4 rc,
+                                              TriLds<T, SLOTS, MAXM, 64> &L, int32_t *flg,
+                                              int2 *hq) {
   using S = SumT<T>;
   using Acc = typename S::type;
   constexpr int MAXS = 64;
-  __shared__ TriLds<T, SLOTS, MAXM, MAXS> lds[WPB];
-  __shared__ int32_t flg_s[WPB][kFlg];
-  __shared__ int2 hq_s[WPB][kQueue];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  TriLds<T, SLOTS, MAXM, MAXS> &L = lds[wv];
-  int32_t *flg = flg_s[wv];
-  flg[lane] = 0;
-  const int64_t nwaves = (int64_t)gridDim.x * WPB;
-  // the hash is cleared once; afterwards each lane empties the one slot it
-  // filled (|up(w)| <= 64), so a short list does not pay for the whole table
   static_assert(MAXM <= 64, "one up(w) entry per lane");
+  const int lane = threadIdx.x & 63;
+  const int32_t w = rc.x, w0 = rc.y, d0 = rc.z, m = rc.w & 0xFFFF, nd = rc.w >> 16;
+  // m >= 1 and nd >= 1 for every listed node: clamped indices stay in
+  // w's rows, and every lane loads without a branch
+  const int32_t ui = w0 + (lane < m ? lane : m - 1);
+  const int32_t x = A.up_col[ui], kx = A.up_deg[ui];
+  int4 sg = A.dn[d0 + (lane < nd ? lane : nd - 1)];
+  wave_sync();
+  int32_t myslot = -1;
+  if (lane < m) {
+    myslot = LdsHash<SLOTS>::insert(L.hkey, x);
+    L.hval[myslot] = pack_kp(kx, lane);
+  }
+  Acc accw = Acc();
+  int64_t cntw = 0;
+  for (int32_t c0 = 0; c0 < nd; c0 += MAXS) {
+    const int32_t cnt = nd - c0 < MAXS ? nd - c0 : MAXS;
+    if (c0 > 0) sg = A.dn[d0 + c0 + (lane < cnt ? lane : cnt - 1)];
+    const int32_t total = tri_segs<64>(sg, cnt, lane, L, nullptr);
+    wave_sync();
+    tri_walk<T, SLOTS, MAXM, MAXS>(A.up_col, L, flg, hq, cnt, 0, total, accw, cntw);
+    tri_flush(L, cnt, w0, m, c0 == 0, lane, 64, A.nup, A.Y);
+  }
+  accw = wave_sum(accw);
+  cntw = wave_sum_i64(cntw);
+  if (lane == 0) {
+    S::store(accw, A.Z, w);
+    A.ZT[w] = cntw;
+  }
+  if (myslot >= 0) L.hkey[myslot] = -1;
+}
+
+template <typename T, int SLOTS, int MAXM>
+__device__ __forceinline__ void tri_wave_init(TriLds<T, SLOTS, MAXM, 64> &L, int32_t *flg) {
+  const int lane = threadIdx.x & 63;
+  flg[lane] = 0;
   for (int i = lane; i < SLOTS; i += 64) L.hkey[i] = -1;
   tri_clear_credits(L, lane, 64);
+}
+
+// WPB wavefronts per workgroup, each with its own LDS state; the list holds
+// the records above: the next node's record is loaded while this one runs,
+// and this node's up(w) and first segments are loaded together, so a short
+// node waits on one global round trip before its walk.
+template <typename T, int SLOTS, int MAXM, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_tri_wave(TriArgs A, const int4 *__restrict__ recs,
+                                                        int64_t count) {
+  __shared__ TriLds<T, SLOTS, MAXM, 64> lds[WPB];
+  __shared__ int32_t flg_s[WPB][kFlg];
+  __shared__ int2 hq_s[WPB][kQueue];
+  const int wv = threadIdx.x >> 6;
+  tri_wave_init(lds[wv], flg_s[wv]);
+  const int64_t nwaves = (int64_t)gridDim.x * WPB;
   int64_t it = (int64_t)blockIdx.x * WPB + wv;
   int4 nxt = it < count ? recs[it] : make_int4(0, 0, 0, 0);
   for (; it < count; it += nwaves) {
     const int4 rc = nxt;
     if (it + nwaves < count) nxt = recs[it + nwaves];
-    const int32_t w = rc.x, w0 = rc.y, d0 = rc.z, m = rc.w & 0xFFFF, nd = rc.w >> 16;
-    // m >= 1 and nd >= 1 for every listed node: clamped indices stay in
-    // w's rows, and every lane loads without a branch
-    const int32_t ui = w0 + (lane < m ? lane : m - 1);
-    const int32_t x = A.up_col[ui], kx = A.up_deg[ui];
-    int4 sg = A.dn[d0 + (lane < nd ? lane : nd - 1)];
-    wave_sync();
-    int32_t myslot = -1;
-    if (lane < m) {
-      myslot = LdsHash<SLOTS>::insert(L.hkey, x);
-      L.hval[myslot] = pack_kp(kx, lane);
-    }
-    Acc accw = Acc();
-    int64_t cntw = 0;
-    for (int32_t c0 = 0; c0 < nd; c0 += MAXS) {
-      const int32_t cnt = nd - c0 < MAXS ? nd - c0 : MAXS;
-      if (c0 > 0) sg = A.dn[d0 + c0 + (lane < cnt ? lane : cnt - 1)];
-      const int32_t total = tri_segs<64>(sg, cnt, lane, L, nullptr);
-      wave_sync();
-      tri_walk<T, SLOTS, MAXM, MAXS>(A.up_col, L, flg, hq_s[wv], cnt, 0, total, accw, cntw);
-      tri_flush(L, cnt, w0, m, c0 == 0, lane, 64, A.nup, A.Y);
-    }
-    accw = wave_sum(accw);
-    cntw = wave_sum_i64(cntw);
-    if (lane == 0) {
-      S::store(accw, A.Z, w);
-      A.ZT[w] = cntw;
-    }
-    if (myslot >= 0) L.hkey[myslot] = -1;
+    tri_wave_node<T, SLOTS, MAXM>(A, rc, lds[wv], flg_s[wv], hq_s[wv]);
   }
 }
 
 // One node w per workgroup of WPB wavefronts sharing one LDS state; chunks
 // of MAXS <= NT segments, each wavefront walking a contiguous share of a
-// chunk.
+// chunk. Every thread calls it (workgroup barriers). On entry flg (each
+// wavefront's) is zero and the credit slots are clear (tri_block_init); so
+// on return.
+template <typename T, int SLOTS, int MAXM, int WPB, int MAXS> struct TriBlockLds {
+  TriLds<T, SLOTS, MAXM, MAXS> L;
+  int32_t flg[WPB][kFlg];
+  int2 hq[WPB][kQueue];
+  int32_t part[WPB];
+  typename SumT<T>::type acc[WPB];
+  int64_t cnt[WPB];
+};
+
 template <typename T, int SLOTS, int MAXM, int WPB, int MAXS>
-__global__ __launch_bounds__(64 * WPB) void k_tri_block(TriArgs A,
-                                                         const int32_t *__restrict__ nodes,
-                                                         int64_t count) {
+__device__ __forceinline__ void tri_block_init(TriBlockLds<T, SLOTS, MAXM, WPB, MAXS> &B) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (wv < WPB) B.flg[wv][lane] = 0;
+  tri_clear_credits(B.L, tid, 64 * WPB);
+}
+
+template <typename T, int SLOTS, int MAXM, int WPB, int MAXS>
+__device__ __forceinline__ void tri_block_node(const TriArgs &A, int32_t w,
+                                               TriBlockLds<T, SLOTS, MAXM, WPB, MAXS> &B) {
   using S = SumT<T>;
   using Acc = typename S::type;
   constexpr int NT = 64 * WPB;
   static_assert(MAXS <= NT, "one segment per thread in the chunk setup");
-  __shared__ TriLds<T, SLOTS, MAXM, MAXS> L;
-  __shared__ int32_t flg_s[WPB][kFlg];
-  __shared__ int2 hq_s[WPB][kQueue];
-  __shared__ int32_t part[WPB];
-  __shared__ Acc sh_acc[WPB];
-  __shared__ int64_t sh_cnt[WPB];
+  auto &L = B.L;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  int32_t *flg = flg_s[wv];
-  flg[lane] = 0;
-  tri_clear_credits(L, tid, NT);
-  for (int64_t it = blockIdx.x; it < count; it += gridDim.x) {
-    const int32_t w = nodes[it];
-    const int32_t w0 = A.up_ptr[w], m = A.up_ptr[w + 1] - w0;
-    const int32_t d0 = A.dn_ptr[w], nd = A.dn_ptr[w + 1] - d0;
-    for (int i = tid; i < SLOTS; i += NT) L.hkey[i] = -1;
+  const int32_t w0 = A.up_ptr[w], m = A.up_ptr[w + 1] - w0;
+  const int32_t d0 = A.dn_ptr[w], nd = A.dn_ptr[w + 1] - d0;
+  for (int i = tid; i < SLOTS; i += NT) L.hkey[i] = -1;
+  __syncthreads();
+  tri_hash<SLOTS, NT>(A.up_col, A.up_deg, w0, m, tid, L.hkey, L.hval);
+  Acc accw = Acc();
+  int64_t cntw = 0;
+  for (int32_t c0 = 0; c0 < nd; c0 += MAXS) {
+    const int32_t cnt = nd - c0 < MAXS ? nd - c0 : MAXS;
+    const int4 sg = tid < cnt ? A.dn[d0 + c0 + tid] : make_int4(0, 0, 0, 0);
+    const int32_t total = tri_segs<NT>(sg, cnt, tid, L, B.part);
     __syncthreads();
-    tri_hash<SLOTS, NT>(A.up_col, A.up_deg, w0, m, tid, L.hkey, L.hval);
-    Acc accw = Acc();
-    int64_t cntw = 0;
-    for (int32_t c0 = 0; c0 < nd; c0 += MAXS) {
-      const int32_t cnt = nd - c0 < MAXS ? nd - c0 : MAXS;
-      const int4 sg = tid < cnt ? A.dn[d0 + c0 + tid] : make_int4(0, 0, 0, 0);
-      const int32_t total = tri_segs<NT>(sg, cnt, tid, L, part);
-      __syncthreads();
-      // contiguous shares, multiples of 64 entries
-      const int32_t steps = (total + 63) >> 6;
-      const int32_t beg = (int32_t)(((int64_t)steps * wv / WPB) << 6);
-      const int32_t fin = (int32_t)(((int64_t)steps * (wv + 1) / WPB) << 6);
-      tri_walk<T, SLOTS, MAXM, MAXS>(A.up_col, L, flg, hq_s[wv], cnt, beg,
-                                     fin < total ? fin : total, accw, cntw);
-      __syncthreads();
-      tri_flush(L, cnt, w0, m, c0 == 0, tid, NT, A.nup, A.Y);
-      __syncthreads();
-    }
-    accw = wave_sum(accw);
-    cntw = wave_sum_i64(cntw);
-    if (lane == 0) {
-      sh_acc[wv] = accw;
-      sh_cnt[wv] = cntw;
-    }
+    // contiguous shares, multiples of 64 entries
+    const int32_t steps = (total + 63) >> 6;
+    const int32_t beg = (int32_t)(((int64_t)steps * wv / WPB) << 6);
+    const int32_t fin = (int32_t)(((int64_t)steps * (wv + 1) / WPB) << 6);
+    tri_walk<T, SLOTS, MAXM, MAXS>(A.up_col, L, B.flg[wv], B.hq[wv], cnt, beg,
+                                   fin < total ? fin : total, accw, cntw);
     __syncthreads();
-    if (tid == 0) {
-      Acc a = sh_acc[0];
-      int64_t cs = sh_cnt[0];
-      for (int i = 1; i < WPB; ++i) {
-        acc_merge(a, sh_acc[i]);
-        cs += sh_cnt[i];
-      }
-      S::store(a, A.Z, w);
-      A.ZT[w] = cs;
-    }
+    tri_flush(L, cnt, w0, m, c0 == 0, tid, NT, A.nup, A.Y);
+    __syncthreads();
   }
+  accw = wave_sum(accw);
+  cntw = wave_sum_i64(cntw);
+  if (lane == 0) {
+    B.acc[wv] = accw;
+    B.cnt[wv] = cntw;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    Acc a = B.acc[0];
+    int64_t cs = B.cnt[0];
+    for (int i = 1; i < WPB; ++i) {
+      acc_merge(a, B.acc[i]);
+      cs += B.cnt[i];
+    }
+    S::store(a, A.Z, w);
+    A.ZT[w] = cs;
+  }
+  __syncthreads();
+}
+
+template <typename T, int SLOTS, int MAXM, int WPB, int MAXS>
+__global__ __launch_bounds__(64 * WPB) void k_tri_block(TriArgs A,
+                                                         const int32_t *__restrict__ nodes,
+                                                         int64_t count) {
+  __shared__ TriBlockLds<T, SLOTS, MAXM, WPB, MAXS> B;
+  tri_block_init(B);
+  for (int64_t it = blockIdx.x; it < count; it += gridDim.x)
+    tri_block_node<T, SLOTS, MAXM, WPB, MAXS>(A, nodes[it], B);
 }
 
 // |up(w)| too long for LDS: one wavefront per w, one segment per lane, and
@@ -400,51 +431,53 @@ __global__ __launch_bounds__(64 * WPB) void k_tri_block(TriArgs A,
 // still order-independent; the slots are cleared first), credits to u to the
 // lane's own lower-end slot.
 template <typename T>
-__global__ __launch_bounds__(64) void k_tri_long(TriArgs A, const int32_t *__restrict__ nodes,
-                                                 int64_t count) {
+__device__ __forceinline__ void tri_long_node(const TriArgs &A, int32_t w) {
   using S = SumT<T>;
   using Acc = typename S::type;
-  const int lane = threadIdx.x;
-  for (int64_t it = blockIdx.x; it < count; it += gridDim.x) {
-    const int32_t w = nodes[it];
-    const int32_t w0 = A.up_ptr[w], m = A.up_ptr[w + 1] - w0;
-    const int32_t d0 = A.dn_ptr[w], nd = A.dn_ptr[w + 1] - d0;
-    Acc accw = Acc();
-    int64_t cntw = 0;
-    for (int32_t base = 0; base < nd; base += 64) {
-      const int32_t i = base + lane;
-      if (i >= nd) continue;
-      const int4 sgm = A.dn[d0 + i];  // {slot of {u, w}, tail length, k_u + k_w, u}
-      long long accu = 0;
-      int32_t cntu = 0;
-      for (int32_t j = sgm.x + 1; j <= sgm.x + sgm.y; ++j) {
-        const int32_t x = A.up_col[j], kx = A.up_deg[j];
-        int32_t lo = 0, hi = m;  // first member of up(w) not ranked below x
-        while (lo < hi) {
-          const int32_t mid = (lo + hi) >> 1;
-          const int32_t y = A.up_col[w0 + mid], ky = A.up_deg[w0 + mid];
-          if (ky < kx || (ky == kx && y < x)) lo = mid + 1; else hi = mid;
-        }
-        if (lo < m && A.up_col[w0 + lo] == x) {
-          const T dl = tri_delta<T>(sgm.z + kx);
-          const long long f = to_fix(dl);
-          S::add_term(accw, dl);
-          ++cntw;
-          accu += f;
-          ++cntu;
-          atomicAdd((unsigned long long *)&A.Y[w0 + lo].y, (unsigned long long)f);
-          atomicAdd(&A.Y[w0 + lo].t, 1);
-        }
+  const int lane = threadIdx.x & 63;
+  const int32_t w0 = A.up_ptr[w], m = A.up_ptr[w + 1] - w0;
+  const int32_t d0 = A.dn_ptr[w], nd = A.dn_ptr[w + 1] - d0;
+  Acc accw = Acc();
+  int64_t cntw = 0;
+  for (int32_t base = 0; base < nd; base += 64) {
+    const int32_t i = base + lane;
+    if (i >= nd) continue;
+    const int4 sgm = A.dn[d0 + i];  // {slot of {u, w}, tail length, k_u + k_w, u}
+    long long accu = 0;
+    int32_t cntu = 0;
+    for (int32_t j = sgm.x + 1; j <= sgm.x + sgm.y; ++j) {
+      const int32_t x = A.up_col[j], kx = A.up_deg[j];
+      int32_t lo = 0, hi = m;  // first member of up(w) not ranked below x
+      while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        const int32_t y = A.up_col[w0 + mid], ky = A.up_deg[w0 + mid];
+        if (ky < kx || (ky == kx && y < x)) lo = mid + 1; else hi = mid;
       }
-      A.Y[A.nup + sgm.x] = TriSlot{accu, cntu, 0};
+      if (lo < m && A.up_col[w0 + lo] == x) {
+        const T dl = tri_delta<T>(sgm.z + kx);
+        const long long f = to_fix(dl);
+        S::add_term(accw, dl);
+        ++cntw;
+        accu += f;
+        ++cntu;
+        atomicAdd((unsigned long long *)&A.Y[w0 + lo].y, (unsigned long long)f);
+        atomicAdd(&A.Y[w0 + lo].t, 1);
+      }
     }
-    accw = wave_sum(accw);
-    cntw = wave_sum_i64(cntw);
-    if (lane == 0) {
-      S::store(accw, A.Z, w);
-      A.ZT[w] = cntw;
-    }
+    A.Y[A.nup + sgm.x] = TriSlot{accu, cntu, 0};
   }
+  accw = wave_sum(accw);
+  cntw = wave_sum_i64(cntw);
+  if (lane == 0) {
+    S::store(accw, A.Z, w);
+    A.ZT[w] = cntw;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_tri_long(TriArgs A, const int32_t *__restrict__ nodes,
+                                                 int64_t count) {
+  for (int64_t it = blockIdx.x; it < count; it += gridDim.x) tri_long_node<T>(A, nodes[it]);
 }
 
 // One node w per lane (|up(w)| <= M, a walk of at most kTriLaneWork entries),
@@ -480,56 +513,59 @@ template <> struct LaneSlot<TriCount> {
 };
 
 template <typename T, int M>
-__global__ __launch_bounds__(256) void k_tri_lane(TriArgs A, const int4 *__restrict__ recs,
-                                                  int64_t count) {
+__device__ __forceinline__ void tri_lane_node(const TriArgs &A, const int4 rc) {
   using S = SumT<T>;
   using Acc = typename S::type;
-  for (int64_t it = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; it < count;
-       it += (int64_t)gridDim.x * blockDim.x) {
-    const int4 rc = recs[it];
-    const int32_t w = rc.x, w0 = rc.y, d0 = rc.z;
-    const int32_t m = rc.w & 0xFF, nd = (rc.w >> 8) & 0xFF, walk = rc.w >> 16;
-    int32_t up[M];
+  const int32_t w = rc.x, w0 = rc.y, d0 = rc.z;
+  const int32_t m = rc.w & 0xFF, nd = (rc.w >> 8) & 0xFF, walk = rc.w >> 16;
+  int32_t up[M];
 #pragma unroll
-    for (int q = 0; q < M; ++q) up[q] = q < m ? A.up_col[w0 + q] : -1;
-    LaneSlot<T> acc[M];
-    LaneSlot<T> su;
-    Acc accw = Acc();
-    int64_t cntw = 0;
-    // every listed node has nd >= 1 segments, each non-empty; walk = their total
-    int32_t s = 0;
-    int4 sg = A.dn[d0];
-    int32_t j = sg.x + 1, jend = sg.x + sg.y;
-    for (int32_t t = 0; t < walk; ++t) {
-      const int32_t x = A.up_col[j], kx = A.up_deg[j];
-      int32_t p = -1;
+  for (int q = 0; q < M; ++q) up[q] = q < m ? A.up_col[w0 + q] : -1;
+  LaneSlot<T> acc[M];
+  LaneSlot<T> su;
+  Acc accw = Acc();
+  int64_t cntw = 0;
+  // every listed node has nd >= 1 segments, each non-empty; walk = their total
+  int32_t s = 0;
+  int4 sg = A.dn[d0];
+  int32_t j = sg.x + 1, jend = sg.x + sg.y;
+  for (int32_t t = 0; t < walk; ++t) {
+    const int32_t x = A.up_col[j], kx = A.up_deg[j];
+    int32_t p = -1;
 #pragma unroll
-      for (int q = 0; q < M; ++q) p = up[q] == x ? q : p;
-      if (p >= 0) {
-        const T dl = tri_delta<T>(sg.z + kx);
-        S::add_term(accw, dl);
-        ++cntw;
-        su.add(dl);
+    for (int q = 0; q < M; ++q) p = up[q] == x ? q : p;
+    if (p >= 0) {
+      const T dl = tri_delta<T>(sg.z + kx);
+      S::add_term(accw, dl);
+      ++cntw;
+      su.add(dl);
 #pragma unroll
-        for (int q = 0; q < M; ++q)
-          if (q == p) acc[q].add(dl);
-      }
-      if (++j > jend) {
-        A.Y[A.nup + sg.x] = su.slot();
-        su = LaneSlot<T>();
-        if (++s < nd) {
-          sg = A.dn[d0 + s];
-          j = sg.x + 1;
-          jend = sg.x + sg.y;
-        }
+      for (int q = 0; q < M; ++q)
+        if (q == p) acc[q].add(dl);
+    }
+    if (++j > jend) {
+      A.Y[A.nup + sg.x] = su.slot();
+      su = LaneSlot<T>();
+      if (++s < nd) {
+        sg = A.dn[d0 + s];
+        j = sg.x + 1;
+        jend = sg.x + sg.y;
       }
     }
-#pragma unroll
-    for (int q = 0; q < M; ++q)
-      if (q < m) A.Y[w0 + q] = acc[q].slot();
-    S::store(accw, A.Z, w);
-    A.ZT[w] = cntw;
   }
+#pragma unroll
+  for (int q = 0; q < M; ++q)
+    if (q < m) A.Y[w0 + q] = acc[q].slot();
+  S::store(accw, A.Z, w);
+  A.ZT[w] = cntw;
+}
+
+template <typename T, int M>
+__global__ __launch_bounds__(256) void k_tri_lane(TriArgs A, const int4 *__restrict__ recs,
+                                                  int64_t count) {
+  for (int64_t it = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; it < count;
+       it += (int64_t)gridDim.x * blockDim.x)
+    tri_lane_node<T, M>(A, recs[it]);
 }
 
 // Clear the listed records (upper-end records of long-list nodes, which
@@ -541,7 +577,7 @@ __global__ void k_tri_zero(TriSlot *__restrict__ Y, const int32_t *__restrict__ 
     Y[zl[i]] = TriSlot{0, 0, 0};
 }
 
-static unsigned cap_blocks(int64_t b, int64_t cap) {
+static unsigned cap_blocks_tri(int64_t b, int64_t cap) {
   if (b < 1) b = 1;
   return (unsigned)(b < cap ? b : cap);
 }
@@ -552,25 +588,25 @@ template <typename T>
 static hipError_t tri_impl(const Graph &g, TriSlot *Y, void *Z, int64_t *ZT, hipStream_t st) {
   const TriArgs A{g.up_ptr, g.up_col, g.up_deg, g.dn_ptr, g.dn, g.nnz / 2, Y, Z, ZT};
   if (g.n_tri_zero > 0)
-    hipLaunchKernelGGL(k_tri_zero, dim3(cap_blocks((g.n_tri_zero + 255) / 256, 1 << 16)),
+    hipLaunchKernelGGL(k_tri_zero, dim3(cap_blocks_tri((g.n_tri_zero + 255) / 256, 1 << 16)),
                        dim3(256), 0, st, Y, g.tri_zero, g.n_tri_zero);
   const int64_t *counts = g.n_tri;
   if (g.n_tri_lane > 0)
     hipLaunchKernelGGL((k_tri_lane<T, kTriLaneM>),
-                       dim3(cap_blocks((g.n_tri_lane + 255) / 256, 1 << 16)), dim3(256), 0, st,
+                       dim3(cap_blocks_tri((g.n_tri_lane + 255) / 256, 1 << 16)), dim3(256), 0, st,
                        A, g.tri_recL, g.n_tri_lane);
   if (counts[0] > 0)
-    hipLaunchKernelGGL((k_tri_wave<T, 256, 64, 4>), dim3(cap_blocks((counts[0] + 3) / 4, 1 << 20)),
+    hipLaunchKernelGGL((k_tri_wave<T, 256, 64, 4>), dim3(cap_blocks_tri((counts[0] + 3) / 4, 1 << 20)),
                        dim3(256), 0, st, A, g.tri_rec0, counts[0]);
   if (counts[1] > 0)
-    hipLaunchKernelGGL((k_tri_block<T, 2048, 512, 8, 512>), dim3(cap_blocks(counts[1], 1 << 20)),
+    hipLaunchKernelGGL((k_tri_block<T, 2048, 512, 8, 512>), dim3(cap_blocks_tri(counts[1], 1 << 20)),
                        dim3(512), 0, st, A, g.tri_list[1], counts[1]);
   if (counts[2] > 0)
     hipLaunchKernelGGL((k_tri_block<T, 8192, 2048, 16, 1024>),
-                       dim3(cap_blocks(counts[2], 1 << 20)), dim3(1024), 0, st, A, g.tri_list[2],
+                       dim3(cap_blocks_tri(counts[2], 1 << 20)), dim3(1024), 0, st, A, g.tri_list[2],
                        counts[2]);
   if (counts[3] > 0)
-    hipLaunchKernelGGL(k_tri_long<T>, dim3(cap_blocks(counts[3], 1 << 20)), dim3(64), 0, st, A,
+    hipLaunchKernelGGL(k_tri_long<T>, dim3(cap_blocks_tri(counts[3], 1 << 20)), dim3(64), 0, st, A,
                        g.tri_list[3], counts[3]);
   return hipGetLastError();
 }

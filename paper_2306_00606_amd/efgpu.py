@@ -29,6 +29,8 @@ EF_VALIDATE = 0x1
 EF_DEVICE_PTRS = 0x2
 EF_OUT_DEVICE = 0x4
 EF_PROFILE = 0x8
+EF_BATCH_PHASED = 0x10
+EF_BATCH_PERSISTENT = 0x20
 
 # every entry point declared in include/ef.h
 EXPORTS = [
@@ -79,11 +81,16 @@ class BatchStats(ctypes.Structure):
     _fields_ = [("n_graphs", ctypes.c_int32), ("n", ctypes.c_int32), ("nnz", ctypes.c_int64),
                 ("clusters", ctypes.c_int64), ("replay_ms", ctypes.c_double),
                 ("tune_ms", ctypes.c_float * 8), ("tuned_choice", ctypes.c_int32),
-                ("thr8", ctypes.c_int32), ("thr16", ctypes.c_int32), ("thr32", ctypes.c_int32)]
+                ("thr8", ctypes.c_int32), ("thr16", ctypes.c_int32), ("thr32", ctypes.c_int32),
+                ("persist_tune_ms", ctypes.c_float * 8), ("persist_choice", ctypes.c_int32),
+                ("design", ctypes.c_int32), ("items", ctypes.c_int32),
+                ("from_cache", ctypes.c_int32), ("size_class", ctypes.c_int32),
+                ("persist_pass2", ctypes.c_int32), ("persist_fp64", ctypes.c_int32)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_}
         d["tune_ms"] = list(self.tune_ms)
+        d["persist_tune_ms"] = list(self.persist_tune_ms)
         return d
 
 
@@ -422,7 +429,8 @@ def union_csr(graphs):
 
 class Batch:
     """Many graphs computed together (handle ``ef_batch``): one disjoint union,
-    one captured HIP graph replayed per call."""
+    computed by the phased or the persistent design, each captured once as a
+    HIP graph and replayed per call."""
 
     def __init__(self, graphs, validate: bool = False, stream=None):
         node_off, rp, ci = union_csr(graphs)
@@ -437,8 +445,11 @@ class Batch:
     def autotune(self, prec: str = "fp32c"):
         _check(lib().ef_batch_autotune(self._h, PREC[prec]))
 
-    def compute(self, prec: str = "fp32c", out=None, profile: bool = False, stream=None):
-        flags = EF_PROFILE if profile else 0
+    def compute(self, prec: str = "fp32c", out=None, profile: bool = False, stream=None,
+                design: str | None = None):
+        """design: None (the tuned one), "phased" or "persistent"."""
+        flags = (EF_PROFILE if profile else 0) | {None: 0, "phased": EF_BATCH_PHASED,
+                                                  "persistent": EF_BATCH_PERSISTENT}[design]
         if out is None:
             ef = np.zeros(max(self.n, 1), np.float64)
             D = np.zeros(max(self.n, 1), np.int64)

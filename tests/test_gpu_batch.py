@@ -1,6 +1,6 @@
-"""Batched computation (disjoint union, captured HIP graph, tuned thresholds)
-against the oracle and against one-graph-at-a-time computation (needs an
-MI355X)."""
+"""Batched computation (disjoint union, captured HIP graph, tuned thresholds;
+the phased design and the persistent kernel) against the oracle and against
+one-graph-at-a-time computation (needs an MI355X)."""
 import sys
 
 import numpy as np
@@ -26,11 +26,12 @@ def small_batch():
     return gen.batch_512(seed0=77, count=24, n_lo=50, n_hi=3000)
 
 
+@pytest.mark.parametrize("design", ["phased", "persistent"])
 @pytest.mark.parametrize("prec", ["fp32c", "fp64"])
-def test_batch_matches_oracle_and_single_graphs(prec):
+def test_batch_matches_oracle_and_single_graphs(prec, design):
     graphs = small_batch()
     with efgpu.Batch(graphs, validate=True) as b:
-        ef, D, N = b.compute(prec=prec)
+        ef, D, N = b.compute(prec=prec, design=design)
         st = b.stats()
         assert st["n_graphs"] == len(graphs) and st["n"] == ef.size
         for i, (rp, ci) in enumerate(graphs):
@@ -45,7 +46,8 @@ def test_batch_matches_oracle_and_single_graphs(prec):
             assert np.all(np.abs(e1 - ef[sl]) <= REL[prec] * np.abs(oE))
 
 
-def test_graph_replays_match_eager():
+@pytest.mark.parametrize("design", ["phased", "persistent"])
+def test_graph_replays_match_eager(design):
     """Replay the captured graph several times, with unrelated eager work and
     synchronisations in between; every replay must equal the first result
     bit for bit."""
@@ -53,7 +55,8 @@ def test_graph_replays_match_eager():
     graphs = small_batch()
     other = gen.rmat(11, 8, 3, perm_seed=4)
     with efgpu.Batch(graphs) as b, efgpu.Graph(*other) as g:
-        ref = b.compute(prec="fp32c")
+        b.autotune("fp32c")
+        ref = b.compute(prec="fp32c", design=design)
         dev = torch.device("cuda:0")
         ef_t = torch.empty(b.n, dtype=torch.float64, device=dev)
         D_t = torch.empty(b.n, dtype=torch.int64, device=dev)
@@ -62,19 +65,43 @@ def test_graph_replays_match_eager():
             g.compute(algo="per_seed", prec="fp64")  # eager work on the same device
             torch.cuda.synchronize()
             ef_t.fill_(-1.0)
-            b.compute(prec="fp32c", out=(ef_t, D_t, N_t), profile=(r == 4))
+            b.compute(prec="fp32c", out=(ef_t, D_t, N_t), profile=(r == 4), design=design)
             torch.cuda.synchronize()
             assert np.array_equal(ef_t.cpu().numpy().view(np.int64), ref[0].view(np.int64)), r
             assert np.array_equal(D_t.cpu().numpy(), ref[1])
             assert np.array_equal(N_t.cpu().numpy(), ref[2])
         st = b.stats()
         assert st["replay_ms"] > 0
-        assert 0 <= st["tuned_choice"] < 8
-        assert all(t > 0 for t in st["tune_ms"])
+        assert 0 <= st["tuned_choice"] < 8 and 0 <= st["persist_choice"] < 8
+        assert st["design"] in (0, 1)
+        if not st["from_cache"]:
+            assert all(t > 0 for t in st["tune_ms"]) and all(t > 0 for t in st["persist_tune_ms"])
+        if design == "persistent":
+            assert st["items"] > 0
 
 
+def test_tuning_cached_per_size_class():
+    """A second batch of the same size class takes the first one's tuning."""
+    graphs = small_batch()
+    with efgpu.Batch(graphs) as b:
+        b.autotune("fp64")
+        st1 = b.stats()
+    with efgpu.Batch(graphs) as b:
+        b.autotune("fp64")
+        st2 = b.stats()
+        ef, D, N = b.compute(prec="fp64")
+    assert st2["from_cache"] == 1 and st2["size_class"] == st1["size_class"]
+    for k in ("design", "tuned_choice", "persist_choice", "thr8", "thr16", "thr32"):
+        assert st2[k] == st1[k], k
+    rp, ci = graphs[3]
+    oN, oD, oE = oracle.ef(rp, ci)
+    sl = slice(int(b.node_off[3]), int(b.node_off[4]))
+    assert np.array_equal(N[sl], oN) and np.array_equal(D[sl], oD)
+
+
+@pytest.mark.parametrize("design", ["phased", "persistent"])
 @pytest.mark.parametrize("prec", ["fp32c", "fp64"])
-def test_config4_batch512_full_size_sampled(prec):
+def test_config4_batch512_full_size_sampled(prec, design):
     """The full 512-graph batch (half Watts-Strogatz, half erased configuration
     model with power-law degrees, n ~ U[1e3, 1e5]; 25.5M nodes). On every
     node: N against its closed form, the sum rule sum N = 4 W, and the
@@ -86,7 +113,12 @@ def test_config4_batch512_full_size_sampled(prec):
     n = rp.size - 1
     deg = np.diff(rp).astype(np.int64)
     with efgpu.Batch(graphs) as b:
-        ef, D, N = b.compute(prec=prec)
+        ef, D, N = b.compute(prec=prec, design=design)
+        if design == "persistent":
+            # the two designs: integers bit for bit, EF within the tolerance
+            e1, D1, N1 = b.compute(prec=prec, design="phased")
+            assert np.array_equal(D1, D) and np.array_equal(N1, N)
+            assert np.all(np.abs(e1 - ef) <= 2 * REL[prec] * np.abs(e1))
     src = np.repeat(np.arange(n), deg)
     A = np.bincount(src, weights=deg[ci], minlength=n).astype(np.int64)
     Nc = deg * deg - 2 * deg + A
@@ -109,5 +141,5 @@ def test_config4_batch512_full_size_sampled(prec):
     bad = np.flatnonzero(err > REL[prec] * np.abs(oE))
     assert bad.size == 0, (prec, seeds[bad[:5]], ef[seeds[bad[:5]]], oE[bad[:5]])
     pos = oE > 0
-    sys.stderr.write(f"[batch512] {prec}: {seeds.size} oracle seeds, max rel err "
+    sys.stderr.write(f"[batch512] {prec} {design}: {seeds.size} oracle seeds, max rel err "
                      f"{float((err[pos] / oE[pos]).max()):.3e}\n")
