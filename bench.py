@@ -61,10 +61,12 @@ TABLE_ENTRIES = 4096
 PAIRS_BIG_TRAFFIC_BYTES = 2.655e9
 # Hardware counters of k_pairs_big<float> at the same workload, per launch
 # (rocprofv3 --pmc, the counter summaries sit with the other rocprofv3
-# summaries): SQ_INSTS_VALU (wave64 VALU instructions) and VALUBusy (percent
-# of the kernel's time the VALUs were busy); None whenever the kernel changes.
-PAIRS_BIG_VALU_INSTS = None
-PAIRS_BIG_VALU_BUSY = None
+# summaries): SQ_INSTS_VALU (wave64 VALU instructions), of which
+# SQ_INSTS_VALU_TRANS_F32 transcendentals (v_log_f32) and SQ_INSTS_LDS.
+# None whenever the kernel changes.
+PAIRS_BIG_VALU_INSTS = 8.2716e9
+PAIRS_BIG_TRANS_INSTS = 4.830e8
+PAIRS_BIG_LDS_INSTS = 1.2132e9
 # VALU cost of one SIR attempt along an arc, in FP32-FMA-equivalent lane slots:
 # the counter (2e) K and SplitMix64's two multiplications are three 64-bit
 # products of three 32-bit multiplies each, at a quarter of the FMA rate
@@ -506,12 +508,16 @@ def main():
         counters = None
         if headline and PAIRS_BIG_VALU_INSTS:
             lane_insts = PAIRS_BIG_VALU_INSTS * 64 / t_launch
+            # issue slots: a transcendental occupies four
+            slots = (PAIRS_BIG_VALU_INSTS + 3 * PAIRS_BIG_TRANS_INSTS) * 64 / t_launch
             counters = {"valu_insts_per_launch": PAIRS_BIG_VALU_INSTS,
+                        "trans_insts_per_launch": PAIRS_BIG_TRANS_INSTS,
+                        "lds_insts_per_launch": PAIRS_BIG_LDS_INSTS,
                         "valu_insts_per_cluster": PAIRS_BIG_VALU_INSTS * 64 / st["pairs_big"],
                         "valu_lane_insts_per_s": lane_insts,
                         "issue_peak_lane_insts_per_s": VALU_LANE_OPS_PEAK,
                         "frac_of_issue_peak": lane_insts / VALU_LANE_OPS_PEAK,
-                        "valu_busy_pct": PAIRS_BIG_VALU_BUSY}
+                        "frac_of_issue_slots": slots / VALU_LANE_OPS_PEAK}
         roofline = {"bound": "alu", "kernel": "k_pairs_big<float>",
                     "achieved": achieved / 1e12, "peak": FP32_VECTOR_PEAK_FLOPS / 1e12,
                     "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_FLOPS,
