@@ -104,27 +104,79 @@ template <> struct Credit<TriCount> {
   }
 };
 
+// LDS hash set of up(w) for the walk: linear probing on single-word keys
+// (empty = -1), with slot SLOTS mirroring slot 0 in both arrays so a lookup
+// reads its first two slots with one two-word LDS read and no wrap. Home:
+// the 24-bit multiplicative hash of the id's low 24 bits (ids that agree
+// there share a home; lookups stay exact).
+template <int SLOTS> struct TriHash {
+  static_assert(SLOTS >= 2 && (SLOTS & (SLOTS - 1)) == 0, "SLOTS must be a power of two");
+  static constexpr int kBits = __builtin_ctz(SLOTS);
+  __device__ static __forceinline__ uint32_t home(int32_t x) {
+    // 24-bit operands: one v_mul_u32_u24, unsigned shift
+    return (((uint32_t)x & 0xFFFFFFu) * 0x9E3779u) >> (32 - kBits);
+  }
+  // x not yet in the set; stores x and its value v, returns the slot
+  __device__ static __forceinline__ int32_t insert(int32_t *keys, int32_t *vals, int32_t x,
+                                                   int32_t v) {
+    uint32_t h = home(x);
+    while (atomicCAS(&keys[h], -1, x) != -1) h = (h + 1) & (SLOTS - 1);
+    vals[h] = v;
+    if (h == 0) {
+      keys[SLOTS] = x;
+      vals[SLOTS] = v;
+    }
+    return (int32_t)h;
+  }
+  __device__ static __forceinline__ void erase(int32_t *keys, int32_t slot) {
+    keys[slot] = -1;
+    if (slot == 0) keys[SLOTS] = -1;
+  }
+  // a lookup in two parts, so several can have their first read in flight:
+  // probe() reads the first two slots of x's run, resolve() returns the slot
+  // of x (SLOTS for slot 0 reached as the second probe) or -1
+  __device__ static __forceinline__ int2 probe(const int32_t *keys, uint32_t h) {
+    return make_int2(keys[h], keys[h + 1]);
+  }
+  __device__ static __forceinline__ int32_t resolve(const int32_t *keys, int32_t x, uint32_t h,
+                                                    int2 ab) {
+    int32_t slot = ab.x == x ? (int32_t)h : (ab.x != -1 && ab.y == x) ? (int32_t)h + 1 : -1;
+    if (ab.x != x && ab.x != -1 && ab.y != x && ab.y != -1) {
+      uint32_t p = (h + 2) & (SLOTS - 1);
+      int32_t k;
+      while ((k = keys[p]) != x && k != -1) p = (p + 1) & (SLOTS - 1);
+      slot = k == x ? (int32_t)p : -1;
+    }
+    return slot;
+  }
+};
+
 // LDS state of one w:
-//   hkey[SLOTS]   ids x of up(w) (LdsHash), hval[slot] = k_x << kPosBits |
+//   hkey[SLOTS+1] ids x of up(w) (TriHash), hval[slot] = k_x << kPosBits |
 //                 position of x in up(w)
 //   seg[MAXS]     per segment of the chunk: {first index of the tail in up_col
-//                 minus its first index in the concatenated sequence, k_u + k_w}
+//                 minus its first index in the concatenated sequence,
+//                 (k_u + k_w) << 11 | segment}
 //   segp[MAXS+1]  first concatenated index of each segment; segp[nseg] = total
-//   sslot[MAXS]   slot of {u, w} in up(u): the segment's lower-end slot
 //   acc, cnt      credits to x by position in up(w)
-//   sacc, scnt    credits to u by segment
+//   sacc, scnt    credits to u by segment, kUCopies slots per segment
+//                 (by lane parity: the hits of one segment arrive in runs,
+//                 and adds to one LDS address serialise)
+constexpr int kSegBits = 11;
+constexpr int kUCopies = 2;
+static_assert(kMaxDegree < (1u << 20), "k_u + k_w must fit above the segment field");
 template <typename T, int SLOTS, int MAXM, int MAXS> struct TriLds {
   static_assert(SLOTS >= 2 * MAXM, "the hash set of up(w) must stay at most half full");
-  static_assert(MAXM <= (1 << 11) && MAXS <= (1 << 11), "credit slots hold at most 2^11 credits");
-  __align__(16) int32_t hkey[SLOTS];
-  int32_t hval[SLOTS];
+  static_assert(MAXM <= (1 << 11) && MAXS <= (1 << kSegBits),
+                "credit slots hold at most 2^11 credits; segment field");
+  __align__(16) int32_t hkey[SLOTS + 4];
+  int32_t hval[SLOTS + 4];
   int2 seg[MAXS];
   int32_t segp[MAXS + 1];
-  int32_t sslot[MAXS];
   unsigned long long acc[MAXM];
-  unsigned long long sacc[MAXS];
+  unsigned long long sacc[MAXS * kUCopies];
   int32_t cnt[Credit<T>::kPacked ? 1 : MAXM];
-  int32_t scnt[Credit<T>::kPacked ? 1 : MAXS];
+  int32_t scnt[Credit<T>::kPacked ? 1 : MAXS * kUCopies];
 };
 
 // Hash up(w) (m entries from w0) with NT threads; returns the slot this
@@ -134,11 +186,8 @@ __device__ __forceinline__ int32_t tri_hash(const int32_t *__restrict__ up_col,
                                             const int32_t *__restrict__ up_deg, int32_t w0,
                                             int32_t m, int tid, int32_t *hkey, int32_t *hval) {
   int32_t myslot = -1;
-  for (int32_t i = tid; i < m; i += NT) {
-    const int32_t x = up_col[w0 + i];
-    myslot = LdsHash<SLOTS>::insert(hkey, x);
-    hval[myslot] = pack_kp(up_deg[w0 + i], i);
-  }
+  for (int32_t i = tid; i < m; i += NT)
+    myslot = TriHash<SLOTS>::insert(hkey, hval, up_col[w0 + i], pack_kp(up_deg[w0 + i], i));
   return myslot;
 }
 
@@ -150,24 +199,121 @@ __device__ __forceinline__ int32_t tri_segs(int4 e, int32_t cnt, int tid, L &lds
   int32_t total;
   const int32_t start = group_excl_scan<NT>(tid < cnt ? e.y : 0, part, total);
   if (tid < cnt) {
-    lds.seg[tid] = make_int2(e.x + 1 - start, e.z);
+    lds.seg[tid] = make_int2(e.x + 1 - start, (e.z << kSegBits) | tid);
     lds.segp[tid] = start;
-    lds.sslot[tid] = e.x;
   }
   if (tid == 0) lds.segp[cnt] = total;
   return total;
 }
 
 // One wavefront walks entries [beg, end) of the chunk's concatenated tails,
-// 64 consecutive entries per step (segment of each lane: seg_walk). A hit
-// (x in up(w)) is appended to the wavefront's LDS queue as two words,
-// {sigma, segment | pos(x) << 16}; whenever 64 hits are queued they are
-// scored and credited with every lane busy, so the hit path does not run
-// divergently on almost every step.
+// 64 consecutive entries per step. A hit (x in up(w)) is appended to the
+// wavefront's LDS queue as two words, {sigma, segment | pos(x) << 16};
+// whenever 64 hits are queued they are scored and credited with every lane
+// busy, so the hit path does not run divergently on almost every step.
 constexpr int kQueue = 128;
 // tri_walk drains once the queue holds 64 hits, so up to 63 wait while a
 // wavefront appends up to 64 more: indices reach 126
 static_assert(kQueue >= 127, "the hit queue must hold 63 waiting + 64 new hits");
+
+// Segment of each lane's entry. Tails are long (tens to hundreds of
+// entries), so most steps lie inside one segment or cross one or two
+// segment starts. The starts of the next 64 segments sit in a register
+// window (lane j: start of segment wbase + 1 + j, INT32_MAX past the last),
+// refilled from LDS only when its last start falls inside the step. The
+// starts inside a step come from a ballot over the window; up to kScalarStarts
+// of them are applied one by one from scalar registers, more go through LDS
+// flags read back as a ballot (flg: 64 zero words on entry and on return).
+constexpr int kScalarStarts = 4;
+struct SegCursor {
+  int32_t s0;     // segment holding entry c (uniform)
+  int32_t wbase;  // window base (uniform)
+  int32_t vb;     // per lane: start of segment wbase + 1 + lane
+};
+
+__device__ __forceinline__ void seg_window(const int32_t *segp, int32_t nseg, SegCursor &cur) {
+  const int32_t s = cur.wbase + 1 + (int32_t)(threadIdx.x & 63);
+  cur.vb = s < nseg ? segp[s] : INT32_MAX;
+}
+
+__device__ __forceinline__ int32_t lanes_below(unsigned long long m) {
+  return (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                            __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// segment of entry c + lane (every lane: entries at or past the total get
+// the last segment; c < total, uniform); advances s0 to the segment of
+// entry c + 64
+__device__ __forceinline__ int32_t seg_of_step(const int32_t *segp, int32_t nseg, int32_t c,
+                                               SegCursor &cur, int32_t *flg) {
+  const int lane = threadIdx.x & 63;
+  // every start in (c, c + 64] must be in the window: at most 64 of them,
+  // the starts of segments s0 + 1 .. s0 + 64
+  if (__builtin_amdgcn_readlane(cur.vb, 63) <= c + 64 && cur.wbase != cur.s0) {
+    cur.wbase = cur.s0;
+    seg_window(segp, nseg, cur);
+  }
+  // window lanes below s0 - wbase hold starts <= c
+  const bool after = cur.vb > c;
+  const bool in = after && cur.vb < c + 64;
+  const unsigned long long m_in = __builtin_amdgcn_ballot_w64(in);
+  const unsigned long long m_adv = __builtin_amdgcn_ballot_w64(after && cur.vb <= c + 64);
+  int32_t sg = cur.s0;
+  if (m_in != 0ull) {
+    if (__popcll(m_in) <= kScalarStarts) {
+      unsigned long long m = m_in;
+      while (m != 0ull) {
+        const int j = __builtin_ctzll(m);
+        m &= m - 1ull;
+        sg += (c + lane >= __builtin_amdgcn_readlane(cur.vb, j)) ? 1 : 0;
+      }
+    } else {
+      wave_sync();
+      if (in) flg[cur.vb - c] = 1;
+      wave_sync();
+      const int32_t f = flg[lane];
+      flg[lane] = 0;
+      const unsigned long long starts = __builtin_amdgcn_ballot_w64(f != 0);
+      sg += lanes_below(starts) + (f != 0);
+    }
+  }
+  cur.s0 = __builtin_amdgcn_readfirstlane(cur.s0 + __popcll(m_adv));
+  return sg;
+}
+
+// One round of U steps at c, c + 64, ...: the member x of entry c + lane and
+// its segment word ((k_u + k_w) << 11 | segment). Lanes at or past the total
+// load its last entry, whole steps at or past end the last entry: every load
+// is valid and unconditional, so a round's loads stay in flight across the
+// previous round's work; the use masks lanes at or past end. The segments
+// of all U steps are found first, then their LDS reads and global loads are
+// issued together.
+template <int U, typename L>
+__device__ __forceinline__ void tri_fetch(const int32_t *__restrict__ up_col, const L &lds,
+                                          int32_t nseg, int32_t total, int32_t c, int32_t end,
+                                          SegCursor &cur, int32_t *flg, int32_t (&x)[U],
+                                          int32_t (&sy)[U]) {
+  const int lane = threadIdx.x & 63;
+  int32_t sg[U], idx[U];
+#pragma unroll
+  for (int q = 0; q < U; ++q) {
+    sg[q] = nseg - 1;
+    idx[q] = total - 1;
+    if (c + 64 * q < end) {
+      sg[q] = seg_of_step(lds.segp, nseg, c + 64 * q, cur, flg);
+      idx[q] = min(c + 64 * q + lane, total - 1);
+    }
+  }
+  int2 sv[U];
+#pragma unroll
+  for (int q = 0; q < U; ++q) sv[q] = lds.seg[sg[q]];
+  // unsigned 32-bit element offsets (up_col has fewer than 2^31 entries)
+#pragma unroll
+  for (int q = 0; q < U; ++q) {
+    x[q] = up_col[(uint32_t)(sv[q].x + idx[q])];
+    sy[q] = sv[q].y;
+  }
+}
 
 template <typename T, int SLOTS, int MAXM, int MAXS>
 __device__ __forceinline__ void tri_walk(const int32_t *__restrict__ up_col,
@@ -176,44 +322,79 @@ __device__ __forceinline__ void tri_walk(const int32_t *__restrict__ up_col,
                                          typename SumT<T>::type &accw, int64_t &cntw) {
   using S = SumT<T>;
   constexpr int32_t kPosMask = (1 << kPosBits) - 1;
+  constexpr int U = 4;
+  beg = __builtin_amdgcn_readfirstlane(beg);
+  end = __builtin_amdgcn_readfirstlane(end);
+  nseg = __builtin_amdgcn_readfirstlane(nseg);
+  if (beg >= end) return;
   const int lane = threadIdx.x & 63;
-  const int2 *seg = L.seg;
   const int32_t *hkey = L.hkey;
   const int32_t *hval = L.hval;
+  const int32_t total = __builtin_amdgcn_readfirstlane(L.segp[nseg]);
+  SegCursor cur;
+  cur.s0 = __builtin_amdgcn_readfirstlane(seg_find(L.segp, nseg, beg));
+  cur.wbase = cur.s0;
+  seg_window(L.segp, nseg, cur);
   int32_t qn = 0;  // queued hits (uniform)
-  // score and credit hq[qn - cnt .. qn) on lanes 0 .. cnt-1
+  // score and credit hq[qn - cnt .. qn) on lanes 0 .. cnt-1; a queued hit is
+  // {segment word, hval of x}
   auto drain = [&](int32_t cnt) {
     wave_sync();
     if (lane < cnt) {
       const int2 h = hq[qn - cnt + lane];
-      const T dl = tri_delta<T>(h.x);
+      const T dl = tri_delta<T>((h.x >> kSegBits) + unpack_k(h.y));
       S::add_term(accw, dl);
-      ++cntw;
-      Credit<T>::add(L.acc, L.cnt, h.y >> 16, dl);
-      Credit<T>::add(L.sacc, L.scnt, h.y & 0xFFFF, dl);
+      Credit<T>::add(L.acc, L.cnt, h.y & kPosMask, dl);
+      Credit<T>::add(L.sacc, L.scnt,
+                     (h.x & ((1 << kSegBits) - 1)) * kUCopies + (lane & (kUCopies - 1)), dl);
     }
+    cntw += cnt;
     qn -= cnt;
     wave_sync();
   };
-  seg_walk<4>(
-      L.segp, nseg, beg, end, flg,
-      [&](int32_t sg, int32_t idx) {
-        const int2 sv = seg[sg];
-        return make_int2(up_col[sv.x + idx], sv.y);
-      },
-      [&](int32_t sg, int32_t, int2 xv, bool ok) {
-        const int32_t slot = ok ? LdsHash<SLOTS>::find(hkey, xv.x) : -1;
-        const bool hit = slot >= 0;
-        const unsigned long long m = __ballot(hit);
-        if (hit) {
-          const int32_t ev = hval[slot];
-          const int32_t rank = (int32_t)__builtin_amdgcn_mbcnt_hi(
-              (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-          hq[qn + rank] = make_int2(xv.y + unpack_k(ev), sg | ((ev & kPosMask) << 16));
-        }
-        qn += __popcll(m);
-        if (qn >= 64) drain(64);
-      });
+  // a round: the U probes first, then the values of the hits, then the
+  // appends (and drains) step by step
+  auto use = [&](const int32_t (&x)[U], const int32_t (&sy)[U], int32_t c) {
+    int32_t slot[U], ev[U];
+    uint32_t h[U];
+    int2 ab[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      h[q] = TriHash<SLOTS>::home(x[q]);
+      ab[q] = TriHash<SLOTS>::probe(hkey, h[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q) slot[q] = TriHash<SLOTS>::resolve(hkey, x[q], h[q], ab[q]);
+    bool hit[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      hit[q] = slot[q] >= 0 && c + 64 * q + lane < end;
+      ev[q] = 0;
+      if (hit[q]) ev[q] = hval[slot[q]];
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const unsigned long long m = __builtin_amdgcn_ballot_w64(hit[q]);
+      if (hit[q]) hq[qn + lanes_below(m)] = make_int2(sy[q], ev[q]);
+      qn += __popcll(m);
+      if (qn >= 64) drain(64);
+    }
+  };
+  // two rounds in flight: round r + 1 is fetched before round r is used, so
+  // its loads overlap the hash probes and drains of round r
+  int32_t xa[U], ya[U], xb[U], yb[U];
+  tri_fetch<U>(up_col, L, nseg, total, beg, end, cur, flg, xa, ya);
+  for (int32_t c = beg;;) {
+    tri_fetch<U>(up_col, L, nseg, total, c + 64 * U, end, cur, flg, xb, yb);
+    use(xa, ya, c);
+    c += 64 * U;
+    if (c >= end) break;
+    tri_fetch<U>(up_col, L, nseg, total, c + 64 * U, end, cur, flg, xa, ya);
+    use(xb, yb, c);
+    c += 64 * U;
+    if (c >= end) break;
+  }
+  wave_sync();
   if (qn > 0) drain(qn);
 }
 
@@ -226,10 +407,18 @@ __device__ __forceinline__ void tri_flush(TriLds<T, SLOTS, MAXM, MAXS> &L, int32
                                           TriSlot *Y) {
   for (int32_t i = tid; i < cnt; i += nt) {
     TriSlot r{0, 0, 0};
-    Credit<T>::load(L.sacc, L.scnt, i, r.y, r.t);
-    Y[nup + L.sslot[i]] = r;
-    L.sacc[i] = 0ull;
-    if constexpr (!Credit<T>::kPacked) L.scnt[i] = 0;
+#pragma unroll
+    for (int k = 0; k < kUCopies; ++k) {
+      long long y;
+      int32_t t;
+      Credit<T>::load(L.sacc, L.scnt, i * kUCopies + k, y, t);
+      r.y += y;
+      r.t += t;
+      L.sacc[i * kUCopies + k] = 0ull;
+      if constexpr (!Credit<T>::kPacked) L.scnt[i * kUCopies + k] = 0;
+    }
+    // slot of {u, w} in up(u): the entry before the tail
+    Y[nup + L.seg[i].x + L.segp[i] - 1] = r;
   }
   for (int32_t i = tid; i < m; i += nt) {
     TriSlot r{0, 0, 0};
@@ -252,7 +441,7 @@ __device__ __forceinline__ void tri_clear_credits(TriLds<T, SLOTS, MAXM, MAXS> &
     L.acc[i] = 0ull;
     if constexpr (!Credit<T>::kPacked) L.cnt[i] = 0;
   }
-  for (int i = tid; i < MAXS; i += nt) {
+  for (int i = tid; i < MAXS * kUCopies; i += nt) {
     L.sacc[i] = 0ull;
     if constexpr (!Credit<T>::kPacked) L.scnt[i] = 0;
   }
@@ -290,10 +479,7 @@ __device__ __forceinline__ void tri_wave_node(const TriArgs &A, const int4 rc,
   int4 sg = A.dn[d0 + (lane < nd ? lane : nd - 1)];
   wave_sync();
   int32_t myslot = -1;
-  if (lane < m) {
-    myslot = LdsHash<SLOTS>::insert(L.hkey, x);
-    L.hval[myslot] = pack_kp(kx, lane);
-  }
+  if (lane < m) myslot = TriHash<SLOTS>::insert(L.hkey, L.hval, x, pack_kp(kx, lane));
   Acc accw = Acc();
   int64_t cntw = 0;
   for (int32_t c0 = 0; c0 < nd; c0 += MAXS) {
@@ -305,19 +491,18 @@ __device__ __forceinline__ void tri_wave_node(const TriArgs &A, const int4 rc,
     tri_flush(L, cnt, w0, m, c0 == 0, lane, 64, A.nup, A.Y);
   }
   accw = wave_sum(accw);
-  cntw = wave_sum_i64(cntw);
   if (lane == 0) {
     S::store(accw, A.Z, w);
-    A.ZT[w] = cntw;
+    A.ZT[w] = cntw;  // the walk counts hits per wavefront
   }
-  if (myslot >= 0) L.hkey[myslot] = -1;
+  if (myslot >= 0) TriHash<SLOTS>::erase(L.hkey, myslot);
 }
 
 template <typename T, int SLOTS, int MAXM>
 __device__ __forceinline__ void tri_wave_init(TriLds<T, SLOTS, MAXM, 64> &L, int32_t *flg) {
   const int lane = threadIdx.x & 63;
   flg[lane] = 0;
-  for (int i = lane; i < SLOTS; i += 64) L.hkey[i] = -1;
+  for (int i = lane; i <= SLOTS; i += 64) L.hkey[i] = -1;
   tri_clear_credits(L, lane, 64);
 }
 
@@ -375,7 +560,7 @@ __device__ __forceinline__ void tri_block_node(const TriArgs &A, int32_t w,
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int32_t w0 = A.up_ptr[w], m = A.up_ptr[w + 1] - w0;
   const int32_t d0 = A.dn_ptr[w], nd = A.dn_ptr[w + 1] - d0;
-  for (int i = tid; i < SLOTS; i += NT) L.hkey[i] = -1;
+  for (int i = tid; i <= SLOTS; i += NT) L.hkey[i] = -1;
   __syncthreads();
   tri_hash<SLOTS, NT>(A.up_col, A.up_deg, w0, m, tid, L.hkey, L.hval);
   Acc accw = Acc();
@@ -396,10 +581,9 @@ __device__ __forceinline__ void tri_block_node(const TriArgs &A, int32_t w,
     __syncthreads();
   }
   accw = wave_sum(accw);
-  cntw = wave_sum_i64(cntw);
   if (lane == 0) {
     B.acc[wv] = accw;
-    B.cnt[wv] = cntw;
+    B.cnt[wv] = cntw;  // the walk counts hits per wavefront
   }
   __syncthreads();
   if (tid == 0) {
@@ -415,8 +599,8 @@ __device__ __forceinline__ void tri_block_node(const TriArgs &A, int32_t w,
   __syncthreads();
 }
 
-template <typename T, int SLOTS, int MAXM, int WPB, int MAXS>
-__global__ __launch_bounds__(64 * WPB) void k_tri_block(TriArgs A,
+template <typename T, int SLOTS, int MAXM, int WPB, int MAXS, int WPE>
+__global__ __launch_bounds__(64 * WPB, WPE) void k_tri_block(TriArgs A,
                                                          const int32_t *__restrict__ nodes,
                                                          int64_t count) {
   __shared__ TriBlockLds<T, SLOTS, MAXM, WPB, MAXS> B;
@@ -599,10 +783,10 @@ static hipError_t tri_impl(const Graph &g, TriSlot *Y, void *Z, int64_t *ZT, hip
     hipLaunchKernelGGL((k_tri_wave<T, 256, 64, 4>), dim3(cap_blocks_tri((counts[0] + 3) / 4, 1 << 20)),
                        dim3(256), 0, st, A, g.tri_rec0, counts[0]);
   if (counts[1] > 0)
-    hipLaunchKernelGGL((k_tri_block<T, 2048, 512, 8, 512>), dim3(cap_blocks_tri(counts[1], 1 << 20)),
+    hipLaunchKernelGGL((k_tri_block<T, 2048, 512, 8, 512, 6>), dim3(cap_blocks_tri(counts[1], 1 << 20)),
                        dim3(512), 0, st, A, g.tri_list[1], counts[1]);
   if (counts[2] > 0)
-    hipLaunchKernelGGL((k_tri_block<T, 8192, 2048, 16, 1024>),
+    hipLaunchKernelGGL((k_tri_block<T, 4096, 2048, 16, 1024, 4>),
                        dim3(cap_blocks_tri(counts[2], 1 << 20)), dim3(1024), 0, st, A, g.tri_list[2],
                        counts[2]);
   if (counts[3] > 0)
