@@ -163,7 +163,7 @@ template <int SLOTS> struct TriHash {
 //                 (by lane parity: the hits of one segment arrive in runs,
 //                 and adds to one LDS address serialise)
 constexpr int kSegBits = 11;
-constexpr int kUCopies = 2;
+constexpr int kUCopies = 4;
 static_assert(kMaxDegree < (1u << 20), "k_u + k_w must fit above the segment field");
 template <typename T, int SLOTS, int MAXM, int MAXS> struct TriLds {
   static_assert(SLOTS >= 2 * MAXM, "the hash set of up(w) must stay at most half full");
@@ -217,81 +217,70 @@ constexpr int kQueue = 128;
 static_assert(kQueue >= 127, "the hit queue must hold 63 waiting + 64 new hits");
 
 // Segment of each lane's entry. Tails are long (tens to hundreds of
-// entries), so most steps lie inside one segment or cross one or two
-// segment starts. The starts of the next 64 segments sit in a register
-// window (lane j: start of segment wbase + 1 + j, INT32_MAX past the last),
-// refilled from LDS only when its last start falls inside the step. The
-// starts inside a step come from a ballot over the window; up to kScalarStarts
-// of them are applied one by one from scalar registers, more go through LDS
-// flags read back as a ballot (flg: 64 zero words on entry and on return).
-constexpr int kScalarStarts = 4;
-struct SegCursor {
-  int32_t s0;     // segment holding entry c (uniform)
-  int32_t wbase;  // window base (uniform)
-  int32_t vb;     // per lane: start of segment wbase + 1 + lane
-};
-
-__device__ __forceinline__ void seg_window(const int32_t *segp, int32_t nseg, SegCursor &cur) {
-  const int32_t s = cur.wbase + 1 + (int32_t)(threadIdx.x & 63);
-  cur.vb = s < nseg ? segp[s] : INT32_MAX;
-}
-
+// entries), so most steps lie inside one segment or cross one to three
+// segment starts. Once per 64 steps, each lane finds by binary search the
+// segment holding the first entry of one step and packs it with the starts
+// of the next three segments relative to the step (step word: segment in
+// bits 0-10, starts in bits 11-17, 18-24, 25-31; 64 and above: no start in
+// the step; 0 in the last field: four or more starts). A step then takes
+// its word from that lane and compares each lane with at most three
+// starts; a step with more starts flags them in LDS and reads them back as
+// a ballot (flg: 64 zero words on entry and on return).
 __device__ __forceinline__ int32_t lanes_below(unsigned long long m) {
   return (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
                                             __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
+// word of the step at c (< total) of a chunk with nseg segments
+__device__ __forceinline__ int32_t step_word(const int32_t *segp, int32_t nseg, int32_t c) {
+  const int32_t s0 = seg_find(segp, nseg, c);
+  int32_t w = s0;
+#pragma unroll
+  for (int k = 1; k <= 3; ++k) {
+    const int32_t b = s0 + k < nseg ? segp[s0 + k] - c : 127;
+    w |= (b < 127 ? b : 127) << (4 + 7 * k);
+  }
+  if (s0 + 4 < nseg && segp[s0 + 4] < c + 64) w &= 0x01FFFFFF;  // four or more starts
+  return w;
+}
+
 // segment of entry c + lane (every lane: entries at or past the total get
-// the last segment; c < total, uniform); advances s0 to the segment of
-// entry c + 64
-__device__ __forceinline__ int32_t seg_of_step(const int32_t *segp, int32_t nseg, int32_t c,
-                                               SegCursor &cur, int32_t *flg) {
-  const int lane = threadIdx.x & 63;
-  // every start in (c, c + 64] must be in the window: at most 64 of them,
-  // the starts of segments s0 + 1 .. s0 + 64
-  if (__builtin_amdgcn_readlane(cur.vb, 63) <= c + 64 && cur.wbase != cur.s0) {
-    cur.wbase = cur.s0;
-    seg_window(segp, nseg, cur);
+// the last segment, whose start is the last one counted) from the step word
+__device__ __forceinline__ int32_t step_seg(const int32_t *segp, int32_t nseg, int32_t c,
+                                            int32_t w, int32_t *flg) {
+  const int32_t lane = (int32_t)(threadIdx.x & 63);
+  const int32_t s0 = w & 0x7FF;
+  int32_t sg = s0;
+  if ((uint32_t)w >> 25) {
+#pragma unroll
+    for (int k = 1; k <= 3; ++k) sg += lane >= ((w >> (4 + 7 * k)) & 127) ? 1 : 0;
+  } else {
+    const int32_t s = s0 + 1 + lane;
+    const int32_t vb = s < nseg ? segp[s] : INT32_MAX;
+    const bool in = vb < c + 64;
+    wave_sync();
+    if (in) flg[vb - c] = 1;
+    wave_sync();
+    const int32_t f = flg[lane];
+    flg[lane] = 0;
+    const unsigned long long starts = __builtin_amdgcn_ballot_w64(f != 0);
+    sg += lanes_below(starts) + (f != 0);
   }
-  // window lanes below s0 - wbase hold starts <= c
-  const bool after = cur.vb > c;
-  const bool in = after && cur.vb < c + 64;
-  const unsigned long long m_in = __builtin_amdgcn_ballot_w64(in);
-  const unsigned long long m_adv = __builtin_amdgcn_ballot_w64(after && cur.vb <= c + 64);
-  int32_t sg = cur.s0;
-  if (m_in != 0ull) {
-    if (__popcll(m_in) <= kScalarStarts) {
-      unsigned long long m = m_in;
-      while (m != 0ull) {
-        const int j = __builtin_ctzll(m);
-        m &= m - 1ull;
-        sg += (c + lane >= __builtin_amdgcn_readlane(cur.vb, j)) ? 1 : 0;
-      }
-    } else {
-      wave_sync();
-      if (in) flg[cur.vb - c] = 1;
-      wave_sync();
-      const int32_t f = flg[lane];
-      flg[lane] = 0;
-      const unsigned long long starts = __builtin_amdgcn_ballot_w64(f != 0);
-      sg += lanes_below(starts) + (f != 0);
-    }
-  }
-  cur.s0 = __builtin_amdgcn_readfirstlane(cur.s0 + __popcll(m_adv));
   return sg;
 }
 
 // One round of U steps at c, c + 64, ...: the member x of entry c + lane and
 // its segment word ((k_u + k_w) << 11 | segment). Lanes at or past the total
-// load its last entry, whole steps at or past end the last entry: every load
-// is valid and unconditional, so a round's loads stay in flight across the
+// load its last entry, steps past the block the last entry: every load is
+// valid and unconditional, so a round's loads stay in flight across the
 // previous round's work; the use masks lanes at or past end. The segments
 // of all U steps are found first, then their LDS reads and global loads are
-// issued together.
+// issued together. win: the block's step words (lane j: step j of the
+// block), jn steps in the block, j the round's first step.
 template <int U, typename L>
 __device__ __forceinline__ void tri_fetch(const int32_t *__restrict__ up_col, const L &lds,
-                                          int32_t nseg, int32_t total, int32_t c, int32_t end,
-                                          SegCursor &cur, int32_t *flg, int32_t (&x)[U],
+                                          int32_t nseg, int32_t total, int32_t c, int32_t win,
+                                          int32_t j, int32_t jn, int32_t *flg, int32_t (&x)[U],
                                           int32_t (&sy)[U]) {
   const int lane = threadIdx.x & 63;
   int32_t sg[U], idx[U];
@@ -299,8 +288,8 @@ __device__ __forceinline__ void tri_fetch(const int32_t *__restrict__ up_col, co
   for (int q = 0; q < U; ++q) {
     sg[q] = nseg - 1;
     idx[q] = total - 1;
-    if (c + 64 * q < end) {
-      sg[q] = seg_of_step(lds.segp, nseg, c + 64 * q, cur, flg);
+    if (j + q < jn) {
+      sg[q] = step_seg(lds.segp, nseg, c + 64 * q, __builtin_amdgcn_readlane(win, j + q), flg);
       idx[q] = min(c + 64 * q + lane, total - 1);
     }
   }
@@ -331,10 +320,6 @@ __device__ __forceinline__ void tri_walk(const int32_t *__restrict__ up_col,
   const int32_t *hkey = L.hkey;
   const int32_t *hval = L.hval;
   const int32_t total = __builtin_amdgcn_readfirstlane(L.segp[nseg]);
-  SegCursor cur;
-  cur.s0 = __builtin_amdgcn_readfirstlane(seg_find(L.segp, nseg, beg));
-  cur.wbase = cur.s0;
-  seg_window(L.segp, nseg, cur);
   int32_t qn = 0;  // queued hits (uniform)
   // score and credit hq[qn - cnt .. qn) on lanes 0 .. cnt-1; a queued hit is
   // {segment word, hval of x}
@@ -380,19 +365,25 @@ __device__ __forceinline__ void tri_walk(const int32_t *__restrict__ up_col,
       if (qn >= 64) drain(64);
     }
   };
-  // two rounds in flight: round r + 1 is fetched before round r is used, so
-  // its loads overlap the hash probes and drains of round r
-  int32_t xa[U], ya[U], xb[U], yb[U];
-  tri_fetch<U>(up_col, L, nseg, total, beg, end, cur, flg, xa, ya);
-  for (int32_t c = beg;;) {
-    tri_fetch<U>(up_col, L, nseg, total, c + 64 * U, end, cur, flg, xb, yb);
-    use(xa, ya, c);
-    c += 64 * U;
-    if (c >= end) break;
-    tri_fetch<U>(up_col, L, nseg, total, c + 64 * U, end, cur, flg, xa, ya);
-    use(xb, yb, c);
-    c += 64 * U;
-    if (c >= end) break;
+  const int32_t nsteps = (end - beg + 63) >> 6;
+  for (int32_t jb = 0; jb < nsteps; jb += 64) {
+    const int32_t cb = beg + 64 * jb;
+    const int32_t jn = nsteps - jb < 64 ? nsteps - jb : 64;
+    const int32_t win = lane < jn ? step_word(L.segp, nseg, cb + 64 * lane) : 0;
+    // two rounds in flight: round r + 1 is fetched before round r is used,
+    // so its loads overlap the hash probes and drains of round r
+    int32_t xa[U], ya[U], xb[U], yb[U];
+    tri_fetch<U>(up_col, L, nseg, total, cb, win, 0, jn, flg, xa, ya);
+    for (int32_t j = 0;;) {
+      tri_fetch<U>(up_col, L, nseg, total, cb + 64 * (j + U), win, j + U, jn, flg, xb, yb);
+      use(xa, ya, cb + 64 * j);
+      j += U;
+      if (j >= jn) break;
+      tri_fetch<U>(up_col, L, nseg, total, cb + 64 * (j + U), win, j + U, jn, flg, xa, ya);
+      use(xb, yb, cb + 64 * j);
+      j += U;
+      if (j >= jn) break;
+    }
   }
   wave_sync();
   if (qn > 0) drain(qn);
