@@ -39,7 +39,6 @@ template <typename T> struct PersistPool {
   using TW = TriLds<T, kPTriWaveSlots, 64, 64>;
   struct TriWave {
     TW L[kPWaves];
-    int32_t flg[kPWaves][kFlg];
     int2 hq[kPWaves][kQueue];
   };
   using TB = TriBlockLds<T, 2048, 512, kPWaves, 1024>;
@@ -146,9 +145,9 @@ __device__ inline void persist_item(const PersistArgs &P, const int4 it, unsigne
       break;
     case PI_TRI_WAVE: {
       auto &W = *reinterpret_cast<typename PersistPool<T>::TriWave *>(pool);
-      tri_wave_init(W.L[wv], W.flg[wv]);
+      tri_wave_init(W.L[wv]);
       for (int32_t i = a + wv; i < b; i += kPWaves)
-        tri_wave_node<T, kPTriWaveSlots, 64>(P.tri, P.tri_wave[i], W.L[wv], W.flg[wv],
+        tri_wave_node<T, kPTriWaveSlots, 64>(P.tri, P.tri_wave[i], W.L[wv],
                                             W.hq[wv]);
       __syncthreads();  // the pool is shared: every wavefront is done with it
       break;

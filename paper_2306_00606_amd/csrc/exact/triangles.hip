@@ -159,11 +159,13 @@ template <int SLOTS> struct TriHash {
 //                 (k_u + k_w) << 11 | segment}
 //   segp[MAXS+1]  first concatenated index of each segment; segp[nseg] = total
 //   acc, cnt      credits to x by position in up(w)
-//   sacc, scnt    credits to u by segment, kUCopies slots per segment
+//   sacc, scnt    credits to u by segment, u_copies<MAXS>() slots per segment
 //                 (by lane parity: the hits of one segment arrive in runs,
 //                 and adds to one LDS address serialise)
 constexpr int kSegBits = 11;
-constexpr int kUCopies = 4;
+// credit slots per segment: 4 in the workgroup bins (long runs of hits per
+// segment), 1 in the wavefront bins (short runs; LDS decides occupancy there)
+template <int MAXS> constexpr int u_copies() { return MAXS <= 64 ? 1 : 4; }
 static_assert(kMaxDegree < (1u << 20), "k_u + k_w must fit above the segment field");
 template <typename T, int SLOTS, int MAXM, int MAXS> struct TriLds {
   static_assert(SLOTS >= 2 * MAXM, "the hash set of up(w) must stay at most half full");
@@ -174,6 +176,7 @@ template <typename T, int SLOTS, int MAXM, int MAXS> struct TriLds {
   int2 seg[MAXS];
   int32_t segp[MAXS + 1];
   unsigned long long acc[MAXM];
+  static constexpr int kUCopies = u_copies<MAXS>();
   unsigned long long sacc[MAXS * kUCopies];
   int32_t cnt[Credit<T>::kPacked ? 1 : MAXM];
   int32_t scnt[Credit<T>::kPacked ? 1 : MAXS * kUCopies];
@@ -225,7 +228,7 @@ static_assert(kQueue >= 127, "the hit queue must hold 63 waiting + 64 new hits")
 // the step; 0 in the last field: four or more starts). A step then takes
 // its word from that lane and compares each lane with at most three
 // starts; a step with more starts flags them in LDS and reads them back as
-// a ballot (flg: 64 zero words on entry and on return).
+// a ballot (flg: 64 words of scratch, cleared before each use).
 __device__ __forceinline__ int32_t lanes_below(unsigned long long m) {
   return (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
                                             __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
@@ -259,10 +262,11 @@ __device__ __forceinline__ int32_t step_seg(const int32_t *segp, int32_t nseg, i
     const int32_t vb = s < nseg ? segp[s] : INT32_MAX;
     const bool in = vb < c + 64;
     wave_sync();
+    flg[lane] = 0;
+    wave_sync();
     if (in) flg[vb - c] = 1;
     wave_sync();
     const int32_t f = flg[lane];
-    flg[lane] = 0;
     const unsigned long long starts = __builtin_amdgcn_ballot_w64(f != 0);
     sg += lanes_below(starts) + (f != 0);
   }
@@ -274,13 +278,13 @@ __device__ __forceinline__ int32_t step_seg(const int32_t *segp, int32_t nseg, i
 // load its last entry, steps past the block the last entry: every load is
 // valid and unconditional, so a round's loads stay in flight across the
 // previous round's work; the use masks lanes at or past end. The segments
-// of all U steps are found first, then their LDS reads and global loads are
-// issued together. win: the block's step words (lane j: step j of the
-// block), jn steps in the block, j the round's first step.
-template <int U, typename L>
+// of all U steps are found first (seg_of(step, c)), then their LDS reads
+// and global loads are issued together. jn steps in the block, j the
+// round's first step.
+template <int U, typename L, typename SegOf>
 __device__ __forceinline__ void tri_fetch(const int32_t *__restrict__ up_col, const L &lds,
-                                          int32_t nseg, int32_t total, int32_t c, int32_t win,
-                                          int32_t j, int32_t jn, int32_t *flg, int32_t (&x)[U],
+                                          int32_t nseg, int32_t total, int32_t c, int32_t j,
+                                          int32_t jn, SegOf seg_of, int32_t (&x)[U],
                                           int32_t (&sy)[U]) {
   const int lane = threadIdx.x & 63;
   int32_t sg[U], idx[U];
@@ -289,7 +293,7 @@ __device__ __forceinline__ void tri_fetch(const int32_t *__restrict__ up_col, co
     sg[q] = nseg - 1;
     idx[q] = total - 1;
     if (j + q < jn) {
-      sg[q] = step_seg(lds.segp, nseg, c + 64 * q, __builtin_amdgcn_readlane(win, j + q), flg);
+      sg[q] = seg_of(j + q, c + 64 * q);
       idx[q] = min(c + 64 * q + lane, total - 1);
     }
   }
@@ -306,12 +310,13 @@ __device__ __forceinline__ void tri_fetch(const int32_t *__restrict__ up_col, co
 
 template <typename T, int SLOTS, int MAXM, int MAXS>
 __device__ __forceinline__ void tri_walk(const int32_t *__restrict__ up_col,
-                                         TriLds<T, SLOTS, MAXM, MAXS> &L, int32_t *flg, int2 *hq,
+                                         TriLds<T, SLOTS, MAXM, MAXS> &L, int2 *hq,
                                          int32_t nseg, int32_t beg, int32_t end,
                                          typename SumT<T>::type &accw, int64_t &cntw) {
   using S = SumT<T>;
   constexpr int32_t kPosMask = (1 << kPosBits) - 1;
-  constexpr int U = 4;
+  // short walks (wavefront bins: a few steps per node) waste less with two
+  constexpr int U = MAXS <= 64 ? 2 : 4;
   beg = __builtin_amdgcn_readfirstlane(beg);
   end = __builtin_amdgcn_readfirstlane(end);
   nseg = __builtin_amdgcn_readfirstlane(nseg);
@@ -320,6 +325,10 @@ __device__ __forceinline__ void tri_walk(const int32_t *__restrict__ up_col,
   const int32_t *hkey = L.hkey;
   const int32_t *hval = L.hval;
   const int32_t total = __builtin_amdgcn_readfirstlane(L.segp[nseg]);
+  // the flags of steps with many segment starts use the queue's last 32
+  // entries: segments are found before a round's hits are appended, when at
+  // most 63 hits wait
+  int32_t *const flg = reinterpret_cast<int32_t *>(hq + (kQueue - 32));
   int32_t qn = 0;  // queued hits (uniform)
   // score and credit hq[qn - cnt .. qn) on lanes 0 .. cnt-1; a queued hit is
   // {segment word, hval of x}
@@ -330,8 +339,8 @@ __device__ __forceinline__ void tri_walk(const int32_t *__restrict__ up_col,
       const T dl = tri_delta<T>((h.x >> kSegBits) + unpack_k(h.y));
       S::add_term(accw, dl);
       Credit<T>::add(L.acc, L.cnt, h.y & kPosMask, dl);
-      Credit<T>::add(L.sacc, L.scnt,
-                     (h.x & ((1 << kSegBits) - 1)) * kUCopies + (lane & (kUCopies - 1)), dl);
+      constexpr int K = u_copies<MAXS>();
+      Credit<T>::add(L.sacc, L.scnt, (h.x & ((1 << kSegBits) - 1)) * K + (lane & (K - 1)), dl);
     }
     cntw += cnt;
     qn -= cnt;
@@ -365,24 +374,59 @@ __device__ __forceinline__ void tri_walk(const int32_t *__restrict__ up_col,
       if (qn >= 64) drain(64);
     }
   };
-  const int32_t nsteps = (end - beg + 63) >> 6;
-  for (int32_t jb = 0; jb < nsteps; jb += 64) {
-    const int32_t cb = beg + 64 * jb;
-    const int32_t jn = nsteps - jb < 64 ? nsteps - jb : 64;
-    const int32_t win = lane < jn ? step_word(L.segp, nseg, cb + 64 * lane) : 0;
-    // two rounds in flight: round r + 1 is fetched before round r is used,
-    // so its loads overlap the hash probes and drains of round r
+  // two rounds in flight: round r + 1 is fetched before round r is used, so
+  // its loads overlap the hash probes and drains of round r
+  auto rounds = [&](int32_t cb, int32_t jn, auto seg_of) {
     int32_t xa[U], ya[U], xb[U], yb[U];
-    tri_fetch<U>(up_col, L, nseg, total, cb, win, 0, jn, flg, xa, ya);
+    tri_fetch<U>(up_col, L, nseg, total, cb, 0, jn, seg_of, xa, ya);
     for (int32_t j = 0;;) {
-      tri_fetch<U>(up_col, L, nseg, total, cb + 64 * (j + U), win, j + U, jn, flg, xb, yb);
+      tri_fetch<U>(up_col, L, nseg, total, cb + 64 * (j + U), j + U, jn, seg_of, xb, yb);
       use(xa, ya, cb + 64 * j);
       j += U;
       if (j >= jn) break;
-      tri_fetch<U>(up_col, L, nseg, total, cb + 64 * (j + U), win, j + U, jn, flg, xa, ya);
+      tri_fetch<U>(up_col, L, nseg, total, cb + 64 * (j + U), j + U, jn, seg_of, xa, ya);
       use(xb, yb, cb + 64 * j);
       j += U;
       if (j >= jn) break;
+    }
+  };
+  const int32_t nsteps = (end - beg + 63) >> 6;
+  if constexpr (MAXS <= 64) {
+    // at most 64 segments: their starts sit in one register (lane s: start
+    // of segment s), and a step's segments come from ballots over it
+    const int32_t segv = lane < nseg ? L.segp[lane] : INT32_MAX;
+    rounds(beg, nsteps, [&](int32_t, int32_t c) {
+      const int32_t s0 = __popcll(__builtin_amdgcn_ballot_w64(segv <= c)) - 1;
+      const bool in = segv > c && segv < c + 64;
+      const unsigned long long m_in = __builtin_amdgcn_ballot_w64(in);
+      int32_t sg = s0;
+      if (__popcll(m_in) <= 3) {
+        unsigned long long m = m_in;
+        while (m != 0ull) {
+          const int j = __builtin_ctzll(m);
+          m &= m - 1ull;
+          sg += (c + lane >= __builtin_amdgcn_readlane(segv, j)) ? 1 : 0;
+        }
+      } else {
+        wave_sync();
+        flg[lane] = 0;
+        wave_sync();
+        if (in) flg[segv - c] = 1;
+        wave_sync();
+        const int32_t f = flg[lane];
+        const unsigned long long starts = __builtin_amdgcn_ballot_w64(f != 0);
+        sg += lanes_below(starts) + (f != 0);
+      }
+      return sg;
+    });
+  } else {
+    for (int32_t jb = 0; jb < nsteps; jb += 64) {
+      const int32_t cb = beg + 64 * jb;
+      const int32_t jn = nsteps - jb < 64 ? nsteps - jb : 64;
+      const int32_t win = lane < jn ? step_word(L.segp, nseg, cb + 64 * lane) : 0;
+      rounds(cb, jn, [&](int32_t j, int32_t c) {
+        return step_seg(L.segp, nseg, c, __builtin_amdgcn_readlane(win, j), flg);
+      });
     }
   }
   wave_sync();
@@ -396,6 +440,7 @@ template <typename T, int SLOTS, int MAXM, int MAXS>
 __device__ __forceinline__ void tri_flush(TriLds<T, SLOTS, MAXM, MAXS> &L, int32_t cnt, int32_t w0,
                                           int32_t m, bool first, int tid, int nt, int64_t nup,
                                           TriSlot *Y) {
+  constexpr int kUCopies = u_copies<MAXS>();
   for (int32_t i = tid; i < cnt; i += nt) {
     TriSlot r{0, 0, 0};
 #pragma unroll
@@ -432,7 +477,7 @@ __device__ __forceinline__ void tri_clear_credits(TriLds<T, SLOTS, MAXM, MAXS> &
     L.acc[i] = 0ull;
     if constexpr (!Credit<T>::kPacked) L.cnt[i] = 0;
   }
-  for (int i = tid; i < MAXS * kUCopies; i += nt) {
+  for (int i = tid; i < MAXS * u_copies<MAXS>(); i += nt) {
     L.sacc[i] = 0ull;
     if constexpr (!Credit<T>::kPacked) L.scnt[i] = 0;
   }
@@ -449,14 +494,13 @@ struct TriArgs {
 
 // One node w per wavefront (|up(w)| <= 64, short walk), chunks of 64
 // segments, with the wavefront's own LDS state. rc = {w, first up slot, first
-// segment, |up(w)| | segments << 16}. On entry the hash holds no key, flg is
-// zero and the credit slots are clear (tri_wave_init); on return too: each
+// segment, |up(w)| | segments << 16}. On entry the hash holds no key and the
+// credit slots are clear (tri_wave_init); on return too: each
 // lane empties the one hash slot it filled, so a short list does not pay for
 // the whole table.
 template <typename T, int SLOTS, int MAXM>
 __device__ __forceinline__ void tri_wave_node(const TriArgs &A, const int4 rc,
-                                              TriLds<T, SLOTS, MAXM, 64> &L, int32_t *flg,
-                                              int2 *hq) {
+                                              TriLds<T, SLOTS, MAXM, 64> &L, int2 *hq) {
   using S = SumT<T>;
   using Acc = typename S::type;
   constexpr int MAXS = 64;
@@ -478,7 +522,7 @@ __device__ __forceinline__ void tri_wave_node(const TriArgs &A, const int4 rc,
     if (c0 > 0) sg = A.dn[d0 + c0 + (lane < cnt ? lane : cnt - 1)];
     const int32_t total = tri_segs<64>(sg, cnt, lane, L, nullptr);
     wave_sync();
-    tri_walk<T, SLOTS, MAXM, MAXS>(A.up_col, L, flg, hq, cnt, 0, total, accw, cntw);
+    tri_walk<T, SLOTS, MAXM, MAXS>(A.up_col, L, hq, cnt, 0, total, accw, cntw);
     tri_flush(L, cnt, w0, m, c0 == 0, lane, 64, A.nup, A.Y);
   }
   accw = wave_sum(accw);
@@ -490,9 +534,8 @@ __device__ __forceinline__ void tri_wave_node(const TriArgs &A, const int4 rc,
 }
 
 template <typename T, int SLOTS, int MAXM>
-__device__ __forceinline__ void tri_wave_init(TriLds<T, SLOTS, MAXM, 64> &L, int32_t *flg) {
+__device__ __forceinline__ void tri_wave_init(TriLds<T, SLOTS, MAXM, 64> &L) {
   const int lane = threadIdx.x & 63;
-  flg[lane] = 0;
   for (int i = lane; i <= SLOTS; i += 64) L.hkey[i] = -1;
   tri_clear_credits(L, lane, 64);
 }
@@ -505,28 +548,25 @@ template <typename T, int SLOTS, int MAXM, int WPB>
 __global__ __launch_bounds__(64 * WPB) void k_tri_wave(TriArgs A, const int4 *__restrict__ recs,
                                                         int64_t count) {
   __shared__ TriLds<T, SLOTS, MAXM, 64> lds[WPB];
-  __shared__ int32_t flg_s[WPB][kFlg];
   __shared__ int2 hq_s[WPB][kQueue];
   const int wv = threadIdx.x >> 6;
-  tri_wave_init(lds[wv], flg_s[wv]);
+  tri_wave_init(lds[wv]);
   const int64_t nwaves = (int64_t)gridDim.x * WPB;
   int64_t it = (int64_t)blockIdx.x * WPB + wv;
   int4 nxt = it < count ? recs[it] : make_int4(0, 0, 0, 0);
   for (; it < count; it += nwaves) {
     const int4 rc = nxt;
     if (it + nwaves < count) nxt = recs[it + nwaves];
-    tri_wave_node<T, SLOTS, MAXM>(A, rc, lds[wv], flg_s[wv], hq_s[wv]);
+    tri_wave_node<T, SLOTS, MAXM>(A, rc, lds[wv], hq_s[wv]);
   }
 }
 
 // One node w per workgroup of WPB wavefronts sharing one LDS state; chunks
 // of MAXS <= NT segments, each wavefront walking a contiguous share of a
-// chunk. Every thread calls it (workgroup barriers). On entry flg (each
-// wavefront's) is zero and the credit slots are clear (tri_block_init); so
-// on return.
+// chunk. Every thread calls it (workgroup barriers). On entry the credit
+// slots are clear (tri_block_init); so on return.
 template <typename T, int SLOTS, int MAXM, int WPB, int MAXS> struct TriBlockLds {
   TriLds<T, SLOTS, MAXM, MAXS> L;
-  int32_t flg[WPB][kFlg];
   int2 hq[WPB][kQueue];
   int32_t part[WPB];
   typename SumT<T>::type acc[WPB];
@@ -535,8 +575,7 @@ template <typename T, int SLOTS, int MAXM, int WPB, int MAXS> struct TriBlockLds
 
 template <typename T, int SLOTS, int MAXM, int WPB, int MAXS>
 __device__ __forceinline__ void tri_block_init(TriBlockLds<T, SLOTS, MAXM, WPB, MAXS> &B) {
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  if (wv < WPB) B.flg[wv][lane] = 0;
+  const int tid = threadIdx.x;
   tri_clear_credits(B.L, tid, 64 * WPB);
 }
 
@@ -565,7 +604,7 @@ __device__ __forceinline__ void tri_block_node(const TriArgs &A, int32_t w,
     const int32_t steps = (total + 63) >> 6;
     const int32_t beg = (int32_t)(((int64_t)steps * wv / WPB) << 6);
     const int32_t fin = (int32_t)(((int64_t)steps * (wv + 1) / WPB) << 6);
-    tri_walk<T, SLOTS, MAXM, MAXS>(A.up_col, L, B.flg[wv], B.hq[wv], cnt, beg,
+    tri_walk<T, SLOTS, MAXM, MAXS>(A.up_col, L, B.hq[wv], cnt, beg,
                                    fin < total ? fin : total, accw, cntw);
     __syncthreads();
     tri_flush(L, cnt, w0, m, c0 == 0, tid, NT, A.nup, A.Y);
