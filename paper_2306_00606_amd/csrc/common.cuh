@@ -97,8 +97,18 @@ __device__ __forceinline__ float score_nn(float d) {
 }
 __device__ __forceinline__ double score_nn(double d) { return d * log(fmax(d, 1.0)); }
 
-template <typename T> __device__ __forceinline__ T tri_delta(int32_t sigma) {
-  return score_t<T>(sigma - 6) - score_t<T>(sigma - 4);
+// delta(sigma) = g(sigma - 6) - g(sigma - 4) for the degree sum sigma of a
+// triangle's members: each has degree >= 2, so sigma - 4 >= 2 needs no
+// guard and g(0) = 0 comes from the log of max(d, 1) (the same values as
+// score_t on every sigma >= 6)
+template <typename T> __device__ __forceinline__ T tri_delta(int32_t sigma);
+template <> __device__ __forceinline__ float tri_delta<float>(int32_t sigma) {
+  const float s = (float)sigma, a = s - 6.0f, b = s - 4.0f;
+  return a * __builtin_amdgcn_logf(fmaxf(a, 1.0f)) - b * __builtin_amdgcn_logf(b);
+}
+template <> __device__ __forceinline__ double tri_delta<double>(int32_t sigma) {
+  const double s = (double)sigma, a = s - 6.0, b = s - 4.0;
+  return a * log(fmax(a, 1.0)) - b * log(b);
 }
 
 // ---------------------------------------------------------------------------

@@ -162,7 +162,7 @@ ef_status ef_graph_free(ef_graph *h) {
   void *arrays[] = {g.deg, g.src, g.rev, g.adj2, g.adjs, g.asum, g.qa, g.up_ptr, g.up_col, g.trec,
                     g.up_deg, g.dn_ptr, g.dn, g.tri_zero, g.j3_seeds, g.j3_off,
                     g.tri_rec0, g.tri_recL, g.tri_list[0], g.tri_list[1], g.tri_list[2], g.tri_list[3],
-                    g.fin_list,
+                    g.tri_recB[1], g.tri_recB[2], g.fin_list,
                     g.ps_list[0], g.ps_list[1], g.ps_list[2], g.ps_list[3], g.ps_list[4],
                     g.d_counters};
   for (void *p : arrays)
@@ -504,6 +504,19 @@ ef_status graph_load(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32
     rec0[i] = make_int4(v, h_up_ptr[v], h_dn_ptr[v], m | (nd << 16));
   }
   ALLOC(g.tri_rec0, sizeof(int4) * std::max<size_t>(rec0.size(), 1), "triangle records");
+  // workgroup bins: |up(w)| <= kTriBin2 < 2^12, segments <= degree < 2^20
+  static_assert(kTriBin2 < (1 << 12) && kMaxDegree < (1 << 20), "workgroup-bin record packing");
+  std::vector<int4> recB[3];
+  for (int bin = 1; bin <= 2; ++bin) {
+    recB[bin].resize(tri[bin].size());
+    for (size_t i = 0; i < tri[bin].size(); ++i) {
+      const int32_t v = tri[bin][i];
+      const int32_t m = h_up_ptr[v + 1] - h_up_ptr[v], nd = h_dn_ptr[v + 1] - h_dn_ptr[v];
+      recB[bin][i] = make_int4(v, h_up_ptr[v], h_dn_ptr[v], m | (nd << 12));
+    }
+    ALLOC(g.tri_recB[bin], sizeof(int4) * std::max<size_t>(recB[bin].size(), 1),
+          "triangle records");
+  }
   g.n_tri_lane = (int64_t)recL.size();
   ALLOC(g.tri_recL, sizeof(int4) * std::max<size_t>(recL.size(), 1), "triangle lane records");
   // tiers by degree (descending), each graph by graph
@@ -537,6 +550,10 @@ ef_status graph_load(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32
                     hipMemcpyHostToDevice);
   if (e == hipSuccess && !rec0.empty())
     e = hipMemcpy(g.tri_rec0, rec0.data(), sizeof(int4) * rec0.size(), hipMemcpyHostToDevice);
+  for (int bin = 1; bin <= 2 && e == hipSuccess; ++bin)
+    if (!recB[bin].empty())
+      e = hipMemcpy(g.tri_recB[bin], recB[bin].data(), sizeof(int4) * recB[bin].size(),
+                    hipMemcpyHostToDevice);
   if (e == hipSuccess && !recL.empty())
     e = hipMemcpy(g.tri_recL, recL.data(), sizeof(int4) * recL.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess && !fin.empty())

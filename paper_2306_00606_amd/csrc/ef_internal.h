@@ -159,6 +159,8 @@ struct Graph {
   int4 *tri_recL = nullptr;
   int64_t n_tri_lane = 0;
   int32_t *tri_list[4] = {nullptr, nullptr, nullptr, nullptr};
+  // bins 1 and 2 as records too: {w, up_ptr[w], dn_ptr[w], |up(w)| | segments << 12}
+  int4 *tri_recB[3] = {nullptr, nullptr, nullptr};
   // nodes of degree > kFinGroupMax (finalized one wavefront each), by degree descending
   int32_t *fin_list = nullptr;
   int64_t n_fin = 0;

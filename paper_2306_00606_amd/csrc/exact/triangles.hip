@@ -154,8 +154,8 @@ template <int SLOTS> struct TriHash {
 // LDS state of one w:
 //   hkey[SLOTS+1] ids x of up(w) (TriHash), hval[slot] = k_x << kPosBits |
 //                 position of x in up(w)
-//   seg[MAXS]     per segment of the chunk: {first index of the tail in up_col
-//                 minus its first index in the concatenated sequence,
+//   seg[MAXS]     per segment of the chunk: {4 x (first index of the tail in
+//                 up_col minus its first index in the concatenated sequence),
 //                 (k_u + k_w) << 11 | segment}
 //   segp[MAXS+1]  first concatenated index of each segment; segp[nseg] = total
 //   acc, cnt      credits to x by position in up(w)
@@ -202,7 +202,7 @@ __device__ __forceinline__ int32_t tri_segs(int4 e, int32_t cnt, int tid, L &lds
   int32_t total;
   const int32_t start = group_excl_scan<NT>(tid < cnt ? e.y : 0, part, total);
   if (tid < cnt) {
-    lds.seg[tid] = make_int2(e.x + 1 - start, (e.z << kSegBits) | tid);
+    lds.seg[tid] = make_int2(4 * (e.x + 1 - start), (e.z << kSegBits) | tid);
     lds.segp[tid] = start;
   }
   if (tid == 0) lds.segp[cnt] = total;
@@ -253,24 +253,21 @@ __device__ __forceinline__ int32_t step_seg(const int32_t *segp, int32_t nseg, i
                                             int32_t w, int32_t *flg) {
   const int32_t lane = (int32_t)(threadIdx.x & 63);
   const int32_t s0 = w & 0x7FF;
-  int32_t sg = s0;
-  if ((uint32_t)w >> 25) {
-#pragma unroll
-    for (int k = 1; k <= 3; ++k) sg += lane >= ((w >> (4 + 7 * k)) & 127) ? 1 : 0;
-  } else {
-    const int32_t s = s0 + 1 + lane;
-    const int32_t vb = s < nseg ? segp[s] : INT32_MAX;
-    const bool in = vb < c + 64;
-    wave_sync();
-    flg[lane] = 0;
-    wave_sync();
-    if (in) flg[vb - c] = 1;
-    wave_sync();
-    const int32_t f = flg[lane];
-    const unsigned long long starts = __builtin_amdgcn_ballot_w64(f != 0);
-    sg += lanes_below(starts) + (f != 0);
-  }
-  return sg;
+  const int32_t b1 = (w >> 11) & 127, b2 = (w >> 18) & 127, b3 = (int32_t)((uint32_t)w >> 25);
+  if (b1 >= 64) return s0;  // inside one segment (most steps)
+  if (b2 >= 64) return s0 + (lane >= b1 ? 1 : 0);
+  if (b3 != 0) return s0 + (lane >= b1 ? 1 : 0) + (lane >= b2 ? 1 : 0) + (lane >= b3 ? 1 : 0);
+  const int32_t s = s0 + 1 + lane;
+  const int32_t vb = s < nseg ? segp[s] : INT32_MAX;
+  const bool in = vb < c + 64;
+  wave_sync();
+  flg[lane] = 0;
+  wave_sync();
+  if (in) flg[vb - c] = 1;
+  wave_sync();
+  const int32_t f = flg[lane];
+  const unsigned long long starts = __builtin_amdgcn_ballot_w64(f != 0);
+  return s0 + lanes_below(starts) + (f != 0);
 }
 
 // One round of U steps at c, c + 64, ...: the member x of entry c + lane and
@@ -280,30 +277,42 @@ __device__ __forceinline__ int32_t step_seg(const int32_t *segp, int32_t nseg, i
 // previous round's work; the use masks lanes at or past end. The segments
 // of all U steps are found first (seg_of(step, c)), then their LDS reads
 // and global loads are issued together. jn steps in the block, j the
-// round's first step.
+// round's first step. Loads address up_col by 32-bit byte offsets (the
+// segment table holds 4 x its element offsets; up_col has fewer than 2^29
+// entries).
 template <int U, typename L, typename SegOf>
 __device__ __forceinline__ void tri_fetch(const int32_t *__restrict__ up_col, const L &lds,
                                           int32_t nseg, int32_t total, int32_t c, int32_t j,
                                           int32_t jn, SegOf seg_of, int32_t (&x)[U],
                                           int32_t (&sy)[U]) {
-  const int lane = threadIdx.x & 63;
-  int32_t sg[U], idx[U];
+  const int32_t lane4 = (int32_t)(threadIdx.x & 63) * 4;
+  int32_t sg[U], boff[U];
+  if (j + U <= jn && c + 64 * U <= total) {
+    // (most rounds) every step in the block and inside the chunk
 #pragma unroll
-  for (int q = 0; q < U; ++q) {
-    sg[q] = nseg - 1;
-    idx[q] = total - 1;
-    if (j + q < jn) {
+    for (int q = 0; q < U; ++q) {
       sg[q] = seg_of(j + q, c + 64 * q);
-      idx[q] = min(c + 64 * q + lane, total - 1);
+      boff[q] = 4 * (c + 64 * q) + lane4;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int32_t cq = c + 64 * q;
+      sg[q] = nseg - 1;
+      boff[q] = 4 * (total - 1);
+      if (j + q < jn) {
+        sg[q] = seg_of(j + q, cq);
+        boff[q] = 4 * min(cq + lane4 / 4, total - 1);
+      }
     }
   }
   int2 sv[U];
 #pragma unroll
   for (int q = 0; q < U; ++q) sv[q] = lds.seg[sg[q]];
-  // unsigned 32-bit element offsets (up_col has fewer than 2^31 entries)
+  const char *base = reinterpret_cast<const char *>(up_col);
 #pragma unroll
   for (int q = 0; q < U; ++q) {
-    x[q] = up_col[(uint32_t)(sv[q].x + idx[q])];
+    x[q] = *reinterpret_cast<const int32_t *>(base + (uint32_t)(sv[q].x + boff[q]));
     sy[q] = sv[q].y;
   }
 }
@@ -322,8 +331,8 @@ __device__ __forceinline__ void tri_walk(const int32_t *__restrict__ up_col,
   nseg = __builtin_amdgcn_readfirstlane(nseg);
   if (beg >= end) return;
   const int lane = threadIdx.x & 63;
-  const int32_t *hkey = L.hkey;
-  const int32_t *hval = L.hval;
+  const char *hkey = reinterpret_cast<const char *>(L.hkey);
+  const char *hval = reinterpret_cast<const char *>(L.hval);
   const int32_t total = __builtin_amdgcn_readfirstlane(L.segp[nseg]);
   // the flags of steps with many segment starts use the queue's last 32
   // entries: segments are found before a round's hits are appended, when at
@@ -346,31 +355,69 @@ __device__ __forceinline__ void tri_walk(const int32_t *__restrict__ up_col,
     qn -= cnt;
     wave_sync();
   };
-  // a round: the U probes first, then the values of the hits, then the
-  // appends (and drains) step by step
+  // a round: the U probes first (the first two slots of each x's run in one
+  // two-word read, byte offsets throughout), then the values of the hits,
+  // then the appends (and drains) step by step. Hits are kept as wavefront
+  // lane masks (scalar registers) and turned back into lane predicates with
+  // inverse ballots.
   auto use = [&](const int32_t (&x)[U], const int32_t (&sy)[U], int32_t c) {
-    int32_t slot[U], ev[U];
-    uint32_t h[U];
+    uint32_t h4[U];
     int2 ab[U];
 #pragma unroll
     for (int q = 0; q < U; ++q) {
-      h[q] = TriHash<SLOTS>::home(x[q]);
-      ab[q] = TriHash<SLOTS>::probe(hkey, h[q]);
+      h4[q] = TriHash<SLOTS>::home(x[q]) << 2;
+      const int32_t *p = reinterpret_cast<const int32_t *>(hkey + h4[q]);
+      ab[q] = make_int2(p[0], p[1]);
     }
-#pragma unroll
-    for (int q = 0; q < U; ++q) slot[q] = TriHash<SLOTS>::resolve(hkey, x[q], h[q], ab[q]);
-    bool hit[U];
+    unsigned long long hm[U];
+    uint32_t s4[U];
 #pragma unroll
     for (int q = 0; q < U; ++q) {
-      hit[q] = slot[q] >= 0 && c + 64 * q + lane < end;
+      const unsigned long long fa = __builtin_amdgcn_ballot_w64(ab[q].x == x[q]);
+      const unsigned long long ea = __builtin_amdgcn_ballot_w64(ab[q].x == -1);
+      const unsigned long long fb = __builtin_amdgcn_ballot_w64(ab[q].y == x[q]);
+      const unsigned long long eb = __builtin_amdgcn_ballot_w64(ab[q].y == -1);
+      hm[q] = fa | (fb & ~ea);
+      s4[q] = h4[q] + (__builtin_amdgcn_inverse_ballot_w64(fa) ? 0u : 4u);
+      const unsigned long long more = ~(fa | ea | fb | eb);
+      if (more != 0ull) {
+        // rare: the run continues past its first two slots. The outcome is
+        // a slot value (kNoSlot: absent) and its ballot is taken once every
+        // lane has left the loop.
+        constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
+        uint32_t r = s4[q];
+        if (__builtin_amdgcn_inverse_ballot_w64(more)) {
+          uint32_t pp = (h4[q] + 8) & (4 * SLOTS - 4);
+          int32_t k;
+          while ((k = *reinterpret_cast<const int32_t *>(hkey + pp)) != x[q] && k != -1)
+            pp = (pp + 4) & (4 * SLOTS - 4);
+          r = k == x[q] ? pp : kNoSlot;
+        }
+        hm[q] |= __builtin_amdgcn_ballot_w64(r != kNoSlot) & more;
+        s4[q] = r;
+      }
+      // lanes at or past end (whole steps past it in the last round)
+    }
+    if (end - c < 64 * U) {
+      // the last round: lanes at or past end (whole steps past it)
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const int32_t left = end - (c + 64 * q);
+        if (left < 64) hm[q] &= left > 0 ? (1ull << left) - 1ull : 0ull;
+      }
+    }
+    int32_t ev[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
       ev[q] = 0;
-      if (hit[q]) ev[q] = hval[slot[q]];
+      if (__builtin_amdgcn_inverse_ballot_w64(hm[q]))
+        ev[q] = *reinterpret_cast<const int32_t *>(hval + s4[q]);
     }
 #pragma unroll
     for (int q = 0; q < U; ++q) {
-      const unsigned long long m = __builtin_amdgcn_ballot_w64(hit[q]);
-      if (hit[q]) hq[qn + lanes_below(m)] = make_int2(sy[q], ev[q]);
-      qn += __popcll(m);
+      if (__builtin_amdgcn_inverse_ballot_w64(hm[q]))
+        hq[qn + lanes_below(hm[q])] = make_int2(sy[q], ev[q]);
+      qn += __popcll(hm[q]);
       if (qn >= 64) drain(64);
     }
   };
@@ -400,6 +447,7 @@ __device__ __forceinline__ void tri_walk(const int32_t *__restrict__ up_col,
       const bool in = segv > c && segv < c + 64;
       const unsigned long long m_in = __builtin_amdgcn_ballot_w64(in);
       int32_t sg = s0;
+      if (m_in == 0ull) return sg;
       if (__popcll(m_in) <= 3) {
         unsigned long long m = m_in;
         while (m != 0ull) {
@@ -454,7 +502,7 @@ __device__ __forceinline__ void tri_flush(TriLds<T, SLOTS, MAXM, MAXS> &L, int32
       if constexpr (!Credit<T>::kPacked) L.scnt[i * kUCopies + k] = 0;
     }
     // slot of {u, w} in up(u): the entry before the tail
-    Y[nup + L.seg[i].x + L.segp[i] - 1] = r;
+    Y[nup + (L.seg[i].x >> 2) + L.segp[i] - 1] = r;
   }
   for (int32_t i = tid; i < m; i += nt) {
     TriSlot r{0, 0, 0};
@@ -563,8 +611,10 @@ __global__ __launch_bounds__(64 * WPB) void k_tri_wave(TriArgs A, const int4 *__
 
 // One node w per workgroup of WPB wavefronts sharing one LDS state; chunks
 // of MAXS <= NT segments, each wavefront walking a contiguous share of a
-// chunk. Every thread calls it (workgroup barriers). On entry the credit
-// slots are clear (tri_block_init); so on return.
+// chunk. Every thread calls it (workgroup barriers). rc = {w, first up slot,
+// first segment, |up(w)| | segments << 12}. On entry the hash holds no key
+// and the credit slots are clear (tri_block_init); so on return: each
+// thread empties the hash slots it filled.
 template <typename T, int SLOTS, int MAXM, int WPB, int MAXS> struct TriBlockLds {
   TriLds<T, SLOTS, MAXM, MAXS> L;
   int2 hq[WPB][kQueue];
@@ -576,28 +626,46 @@ template <typename T, int SLOTS, int MAXM, int WPB, int MAXS> struct TriBlockLds
 template <typename T, int SLOTS, int MAXM, int WPB, int MAXS>
 __device__ __forceinline__ void tri_block_init(TriBlockLds<T, SLOTS, MAXM, WPB, MAXS> &B) {
   const int tid = threadIdx.x;
+  for (int i = tid; i <= SLOTS; i += 64 * WPB) B.L.hkey[i] = -1;
   tri_clear_credits(B.L, tid, 64 * WPB);
+  __syncthreads();
 }
 
+// next: the record of the node this workgroup takes after rc (or null),
+// loaded into nrc together with rc's up(w) and first segments, so a node
+// waits on one global round trip before its walk
 template <typename T, int SLOTS, int MAXM, int WPB, int MAXS>
-__device__ __forceinline__ void tri_block_node(const TriArgs &A, int32_t w,
-                                               TriBlockLds<T, SLOTS, MAXM, WPB, MAXS> &B) {
+__device__ __forceinline__ void tri_block_node(const TriArgs &A, const int4 rc,
+                                               TriBlockLds<T, SLOTS, MAXM, WPB, MAXS> &B,
+                                               const int4 *next, int4 &nrc) {
   using S = SumT<T>;
   using Acc = typename S::type;
   constexpr int NT = 64 * WPB;
+  constexpr int R = (MAXM + NT - 1) / NT;  // up(w) entries per thread
   static_assert(MAXS <= NT, "one segment per thread in the chunk setup");
   auto &L = B.L;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int32_t w0 = A.up_ptr[w], m = A.up_ptr[w + 1] - w0;
-  const int32_t d0 = A.dn_ptr[w], nd = A.dn_ptr[w + 1] - d0;
-  for (int i = tid; i <= SLOTS; i += NT) L.hkey[i] = -1;
-  __syncthreads();
-  tri_hash<SLOTS, NT>(A.up_col, A.up_deg, w0, m, tid, L.hkey, L.hval);
+  const int32_t w = rc.x, w0 = rc.y, d0 = rc.z, m = rc.w & 0xFFF, nd = rc.w >> 12;
+  int32_t xs[R], ks[R], slots[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int32_t i = tid + r * NT;
+    xs[r] = i < m ? A.up_col[w0 + i] : 0;
+    ks[r] = i < m ? A.up_deg[w0 + i] : 0;
+  }
+  int4 sg = tid < nd && tid < MAXS ? A.dn[d0 + tid] : make_int4(0, 0, 0, 0);
+  if (next) nrc = *next;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int32_t i = tid + r * NT;
+    slots[r] = i < m ? TriHash<SLOTS>::insert(L.hkey, L.hval, xs[r], pack_kp(ks[r], i)) : -1;
+  }
   Acc accw = Acc();
   int64_t cntw = 0;
   for (int32_t c0 = 0; c0 < nd; c0 += MAXS) {
     const int32_t cnt = nd - c0 < MAXS ? nd - c0 : MAXS;
-    const int4 sg = tid < cnt ? A.dn[d0 + c0 + tid] : make_int4(0, 0, 0, 0);
+    if (c0 > 0) sg = tid < cnt ? A.dn[d0 + c0 + tid] : make_int4(0, 0, 0, 0);
+    // (the scan's barriers also publish the hash inserts)
     const int32_t total = tri_segs<NT>(sg, cnt, tid, L, B.part);
     __syncthreads();
     // contiguous shares, multiples of 64 entries
@@ -610,6 +678,9 @@ __device__ __forceinline__ void tri_block_node(const TriArgs &A, int32_t w,
     tri_flush(L, cnt, w0, m, c0 == 0, tid, NT, A.nup, A.Y);
     __syncthreads();
   }
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (slots[r] >= 0) TriHash<SLOTS>::erase(L.hkey, slots[r]);
   accw = wave_sum(accw);
   if (lane == 0) {
     B.acc[wv] = accw;
@@ -629,14 +700,31 @@ __device__ __forceinline__ void tri_block_node(const TriArgs &A, int32_t w,
   __syncthreads();
 }
 
+// the same for a node given by id (its record built from the row pointers)
+template <typename T, int SLOTS, int MAXM, int WPB, int MAXS>
+__device__ __forceinline__ void tri_block_node(const TriArgs &A, int32_t w,
+                                               TriBlockLds<T, SLOTS, MAXM, WPB, MAXS> &B) {
+  const int32_t w0 = A.up_ptr[w], d0 = A.dn_ptr[w];
+  const int4 rc = make_int4(w, w0, d0, (A.up_ptr[w + 1] - w0) | ((A.dn_ptr[w + 1] - d0) << 12));
+  int4 unused;
+  tri_block_node<T, SLOTS, MAXM, WPB, MAXS>(A, rc, B, nullptr, unused);
+}
+
 template <typename T, int SLOTS, int MAXM, int WPB, int MAXS, int WPE>
 __global__ __launch_bounds__(64 * WPB, WPE) void k_tri_block(TriArgs A,
-                                                         const int32_t *__restrict__ nodes,
-                                                         int64_t count) {
+                                                              const int4 *__restrict__ recs,
+                                                              int64_t count) {
   __shared__ TriBlockLds<T, SLOTS, MAXM, WPB, MAXS> B;
   tri_block_init(B);
-  for (int64_t it = blockIdx.x; it < count; it += gridDim.x)
-    tri_block_node<T, SLOTS, MAXM, WPB, MAXS>(A, nodes[it], B);
+  int64_t it = blockIdx.x;
+  if (it >= count) return;
+  int4 rc = recs[it];
+  for (; it < count; it += gridDim.x) {
+    const int64_t nx = it + gridDim.x;
+    int4 nrc = rc;
+    tri_block_node<T, SLOTS, MAXM, WPB, MAXS>(A, rc, B, nx < count ? recs + nx : nullptr, nrc);
+    rc = nrc;
+  }
 }
 
 // |up(w)| too long for LDS: one wavefront per w, one segment per lane, and
@@ -814,10 +902,10 @@ static hipError_t tri_impl(const Graph &g, TriSlot *Y, void *Z, int64_t *ZT, hip
                        dim3(256), 0, st, A, g.tri_rec0, counts[0]);
   if (counts[1] > 0)
     hipLaunchKernelGGL((k_tri_block<T, 2048, 512, 8, 512, 6>), dim3(cap_blocks_tri(counts[1], 1 << 20)),
-                       dim3(512), 0, st, A, g.tri_list[1], counts[1]);
+                       dim3(512), 0, st, A, g.tri_recB[1], counts[1]);
   if (counts[2] > 0)
     hipLaunchKernelGGL((k_tri_block<T, 4096, 2048, 16, 1024, 4>),
-                       dim3(cap_blocks_tri(counts[2], 1 << 20)), dim3(1024), 0, st, A, g.tri_list[2],
+                       dim3(cap_blocks_tri(counts[2], 1 << 20)), dim3(1024), 0, st, A, g.tri_recB[2],
                        counts[2]);
   if (counts[3] > 0)
     hipLaunchKernelGGL(k_tri_long<T>, dim3(cap_blocks_tri(counts[3], 1 << 20)), dim3(64), 0, st, A,
