@@ -26,6 +26,8 @@
 // and order-independent: results are bitwise reproducible. Segments are taken
 // in chunks of at most MAXS; the credits to x are added to their slots after
 // every chunk, which bounds the credits an LDS slot holds by 2^11.
+#include <type_traits>
+
 #include "common.cuh"
 
 namespace efi {
@@ -103,6 +105,18 @@ template <> struct Credit<TriCount> {
     yt = (int32_t)(acc[slot] >> 44);
   }
 };
+
+// In FP32C the credit of w (the middle node) is the sum of the credits of
+// the x's: it is taken from the exact x slots when they are flushed, instead
+// of a compensated sum per hit.
+template <typename T> constexpr bool kZFromSlots = std::is_same<T, float>::value;
+__device__ __forceinline__ DFv dfv_from_fix(long long y) {
+  const double d = (double)y * (1.0 / kTriFix);
+  DFv r;
+  r.hi = (float)d;
+  r.lo = (float)(d - (double)r.hi);
+  return r;
+}
 
 // LDS hash set of up(w) for the walk: linear probing on single-word keys
 // (empty = -1), with slot SLOTS mirroring slot 0 in both arrays so a lookup
@@ -346,7 +360,7 @@ __device__ __forceinline__ void tri_walk(const int32_t *__restrict__ up_col,
     if (lane < cnt) {
       const int2 h = hq[qn - cnt + lane];
       const T dl = tri_delta<T>((h.x >> kSegBits) + unpack_k(h.y));
-      S::add_term(accw, dl);
+      if constexpr (!kZFromSlots<T>) S::add_term(accw, dl);
       Credit<T>::add(L.acc, L.cnt, h.y & kPosMask, dl);
       constexpr int K = u_copies<MAXS>();
       Credit<T>::add(L.sacc, L.scnt, (h.x & ((1 << kSegBits) - 1)) * K + (lane & (K - 1)), dl);
@@ -482,12 +496,13 @@ __device__ __forceinline__ void tri_walk(const int32_t *__restrict__ up_col,
 }
 
 // After a chunk: the credits to u go to the segments' lower-end slots, the
-// credits to x are stored (first chunk) or added to w's upper-end slots.
-// Clears both for the next chunk.
+// credits to x are stored (first chunk) or added to w's upper-end slots, and
+// the x credits this thread flushed are added to zs (2^-36 units). Clears
+// both for the next chunk.
 template <typename T, int SLOTS, int MAXM, int MAXS>
 __device__ __forceinline__ void tri_flush(TriLds<T, SLOTS, MAXM, MAXS> &L, int32_t cnt, int32_t w0,
                                           int32_t m, bool first, int tid, int nt, int64_t nup,
-                                          TriSlot *Y) {
+                                          TriSlot *Y, long long &zs) {
   constexpr int kUCopies = u_copies<MAXS>();
   for (int32_t i = tid; i < cnt; i += nt) {
     TriSlot r{0, 0, 0};
@@ -507,6 +522,7 @@ __device__ __forceinline__ void tri_flush(TriLds<T, SLOTS, MAXM, MAXS> &L, int32
   for (int32_t i = tid; i < m; i += nt) {
     TriSlot r{0, 0, 0};
     Credit<T>::load(L.acc, L.cnt, i, r.y, r.t);
+    zs += r.y;
     if (!first) {
       const TriSlot o = Y[w0 + i];
       r.y += o.y;
@@ -565,15 +581,17 @@ __device__ __forceinline__ void tri_wave_node(const TriArgs &A, const int4 rc,
   if (lane < m) myslot = TriHash<SLOTS>::insert(L.hkey, L.hval, x, pack_kp(kx, lane));
   Acc accw = Acc();
   int64_t cntw = 0;
+  long long zs = 0;
   for (int32_t c0 = 0; c0 < nd; c0 += MAXS) {
     const int32_t cnt = nd - c0 < MAXS ? nd - c0 : MAXS;
     if (c0 > 0) sg = A.dn[d0 + c0 + (lane < cnt ? lane : cnt - 1)];
     const int32_t total = tri_segs<64>(sg, cnt, lane, L, nullptr);
     wave_sync();
     tri_walk<T, SLOTS, MAXM, MAXS>(A.up_col, L, hq, cnt, 0, total, accw, cntw);
-    tri_flush(L, cnt, w0, m, c0 == 0, lane, 64, A.nup, A.Y);
+    tri_flush(L, cnt, w0, m, c0 == 0, lane, 64, A.nup, A.Y, zs);
   }
-  accw = wave_sum(accw);
+  if constexpr (kZFromSlots<T>) accw = dfv_from_fix(wave_sum_i64(zs));
+  else accw = wave_sum(accw);
   if (lane == 0) {
     S::store(accw, A.Z, w);
     A.ZT[w] = cntw;  // the walk counts hits per wavefront
@@ -621,6 +639,7 @@ template <typename T, int SLOTS, int MAXM, int WPB, int MAXS> struct TriBlockLds
   int32_t part[WPB];
   typename SumT<T>::type acc[WPB];
   int64_t cnt[WPB];
+  long long zs[WPB];
 };
 
 template <typename T, int SLOTS, int MAXM, int WPB, int MAXS>
@@ -662,6 +681,7 @@ __device__ __forceinline__ void tri_block_node(const TriArgs &A, const int4 rc,
   }
   Acc accw = Acc();
   int64_t cntw = 0;
+  long long zs = 0;
   for (int32_t c0 = 0; c0 < nd; c0 += MAXS) {
     const int32_t cnt = nd - c0 < MAXS ? nd - c0 : MAXS;
     if (c0 > 0) sg = tid < cnt ? A.dn[d0 + c0 + tid] : make_int4(0, 0, 0, 0);
@@ -675,25 +695,30 @@ __device__ __forceinline__ void tri_block_node(const TriArgs &A, const int4 rc,
     tri_walk<T, SLOTS, MAXM, MAXS>(A.up_col, L, B.hq[wv], cnt, beg,
                                    fin < total ? fin : total, accw, cntw);
     __syncthreads();
-    tri_flush(L, cnt, w0, m, c0 == 0, tid, NT, A.nup, A.Y);
+    tri_flush(L, cnt, w0, m, c0 == 0, tid, NT, A.nup, A.Y, zs);
     __syncthreads();
   }
 #pragma unroll
   for (int r = 0; r < R; ++r)
     if (slots[r] >= 0) TriHash<SLOTS>::erase(L.hkey, slots[r]);
-  accw = wave_sum(accw);
+  if constexpr (kZFromSlots<T>) zs = wave_sum_i64(zs);
+  else accw = wave_sum(accw);
   if (lane == 0) {
     B.acc[wv] = accw;
+    B.zs[wv] = zs;
     B.cnt[wv] = cntw;  // the walk counts hits per wavefront
   }
   __syncthreads();
   if (tid == 0) {
     Acc a = B.acc[0];
+    long long z = B.zs[0];
     int64_t cs = B.cnt[0];
     for (int i = 1; i < WPB; ++i) {
       acc_merge(a, B.acc[i]);
+      z += B.zs[i];
       cs += B.cnt[i];
     }
+    if constexpr (kZFromSlots<T>) a = dfv_from_fix(z);
     S::store(a, A.Z, w);
     A.ZT[w] = cs;
   }
