@@ -153,18 +153,26 @@ __device__ __forceinline__ void tile(T cp, T kq, T &Rt, T &C) {
 // k_p - 2 for this lane's row, kq = degree of its column at step 0; every
 // index roff + kq of the tile must lie in the table (checked by the caller).
 // Same result layout as tile<T, false, false>; used by the FP32 path.
+// The table is addressed by byte offsets idx_s(l) = 4 (roff(l) + kq(l + s)).
+// The lane that reads column q at step s reads q + 1 at step s + 1, so
+// idx_{s+1} = rot(idx_s) + 4 (roff - rot(roff)): one integer add with the
+// rotation folded in (v_add_u32_dpp), as for the cluster degree of tile().
+// The difference 4 (roff - rot(roff)) is formed in FP32 (exact: below 2^24):
+// folded into an integer v_subrev_u32_dpp it came out negated on the device.
 template <typename T>
 __device__ __forceinline__ void tile_tab(int32_t roff, int32_t kq, const float *gt, T &Rt, T &C) {
   Rt = T(0);
   C = T(0);
-  // The column degree rotates on its own (an index recurrence in the style of
-  // tile() computed wrong table addresses on the device, so it is not used).
+  const char *base = reinterpret_cast<const char *>(gt);
+  const float r4 = (float)(4 * roff);
+  const int32_t D = (int32_t)(r4 - rot1(r4));
+  int32_t idx = 4 * (roff + kq);
 #pragma unroll 8
   for (int s = 0; s < 64; ++s) {
-    const T g = gt[roff + kq];
+    const T g = *reinterpret_cast<const float *>(base + idx);
     Rt += g;
     C = rot1(C) + g;
-    kq = rot1i(kq);
+    idx = rot1i(idx) + D;
   }
 }
 
