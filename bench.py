@@ -84,7 +84,9 @@ SIR_ATTEMPT_TRAFFIC_BYTES = 25.1e9
 
 def table_clusters(rp, ci):
     """Clusters of big centres (degree > 1024) that the FP32 super-tile loop
-    scores from its LDS table, by the kernel's rule on the degree-sorted rows."""
+    scores from its LDS table, by the kernel's rule on the degree-sorted rows:
+    full 64 x 64 tiles off the diagonal whose largest row and column degrees
+    fit, in the off-diagonal super-tiles and inside the diagonal ones."""
     import numpy as np
 
     deg = np.diff(rp).astype(np.int64)
@@ -95,8 +97,9 @@ def table_clusters(rp, ci):
         nb = (k + 63) // 64
         m = nbr[np.minimum(np.arange(nb) * 64 + 63, k - 1)]  # largest degree per block
         full = (np.arange(nb) + 1) * 64 <= k
-        rows_before = 16 * (np.arange(nb) // 16)  # row blocks of earlier super-blocks
-        fit = np.minimum(np.searchsorted(m, TABLE_ENTRIES + 2 - m, side="left"), rows_before)
+        # for a full column block j: the row blocks i < j (all full) with
+        # m[i] + m[j] - 2 < TABLE_ENTRIES, a prefix since the rows ascend
+        fit = np.minimum(np.searchsorted(m, TABLE_ENTRIES + 2 - m, side="left"), np.arange(nb))
         total += int(fit[full].sum()) * 64 * 64
     return total
 

@@ -147,6 +147,9 @@ __device__ __forceinline__ void tile(T cp, T kq, T &Rt, T &C) {
   }
 }
 
+// entries of a big centre's score table (FP32 path)
+constexpr int kGTab = 4096;
+
 // Full off-diagonal tile of a big centre with the scores read from the
 // centre's table: gt[i] = score(k_v - 2 + i), the same FP32 expression the
 // other tiles evaluate, so every cluster gets the same score bits. roff =
@@ -322,9 +325,12 @@ __device__ __forceinline__ T col_degree(const int2 *adj2, int32_t base, int32_t 
 // parts[c][delta][64]: column partials, zeroed by the caller.
 // On return (after the final barrier), wavefront w's lanes hold in `out` the
 // complete sum for index 64*(blk0+w)+lane over all pairs inside this range.
+// gtab (FP32, rows in ascending degree order, or null): the centre's score
+// table; full off-diagonal tiles whose largest degrees fit read it.
 template <typename T>
 __device__ void diag_super(const int2 *adj2, int32_t base, int32_t k, T kv4, int blk0, int nb,
-                           T (*parts)[9][64], int w, Acc<T> &out) {
+                           T (*parts)[9][64], int w, Acc<T> &out,
+                           const float *gtab = nullptr) {
   const int lane = threadIdx.x & 63;
   if (w < nb) {
     const int32_t p = 64 * (blk0 + w) + lane;
@@ -347,6 +353,8 @@ __device__ void diag_super(const int2 *adj2, int32_t base, int32_t k, T kv4, int
         const bool masked = ragged && (c == nb - 1 || w == nb - 1) && (blk0 + nb) * 64 > k;
         if (masked) {
           tile<T, false, true>(cp, kq, Rt, C);
+        } else if (gtab && __shfl((int32_t)kp, 63, 64) + __shfl((int32_t)kq, 63, 64) - 2 < kGTab) {
+          tile_tab<T>((int32_t)kp - 2, (int32_t)kq, gtab, Rt, C);
         } else {
           tile<T, false, false>(cp, kq, Rt, C);
         }
@@ -457,7 +465,6 @@ __global__ __launch_bounds__(256) void k_mid_split(const int32_t *__restrict__ d
 // workgroups fit on a compute unit (measured: one workgroup per CU with a
 // larger table is slower).
 // ---------------------------------------------------------------------------
-constexpr int kGTab = 4096;
 template <typename T> struct BigLds {
   static constexpr bool kTab = std::is_same<T, float>::value;
   static constexpr int kTabBytes = kTab ? kGTab * 4 : 0;
@@ -491,11 +498,18 @@ __device__ __forceinline__ void pairs_big_tile(const int32_t *__restrict__ row_p
   const int nbQ = min(kBlocksPerSuper, (k - kSuper * Q + 63) >> 6);
   const T kv4 = (T)(k - 4);
   if (P == Q) {
+    if (kTab && v != tab_v) {  // uniform: one centre per work item
+      const float d0 = (float)(k - 2);
+      for (int i = threadIdx.x; i < kGTab; i += blockDim.x) gtab[i] = score(d0 + (float)i);
+      tab_v = v;
+    }
     zero_parts(&parts[0][0][0], kBlocksPerSuper * 9 * 64);
     __syncthreads();
     Acc<T> out;
+    // the rows of a big centre ascend in degree, so its full off-diagonal
+    // tiles can read the score table here too
     diag_super<T>(adj2, base, k, kv4, kBlocksPerSuper * P, nbQ,
-                  reinterpret_cast<T(*)[9][64]>(&parts[0][0][0]), w, out);
+                  reinterpret_cast<T(*)[9][64]>(&parts[0][0][0]), w, out, kTab ? gtab : nullptr);
     if (w < nbQ) out.store(rec, rbase + 64 * w + lane);
   } else {
     // P < Q: all 16 row blocks of P are full
