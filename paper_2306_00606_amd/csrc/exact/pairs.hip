@@ -148,7 +148,7 @@ __device__ __forceinline__ void tile(T cp, T kq, T &Rt, T &C) {
 }
 
 // entries of a big centre's score table (FP32 path)
-constexpr int kGTab = 4096;
+constexpr int kGTab = 8192;
 
 // Full off-diagonal tile of a big centre with the scores read from the
 // centre's table: gt[i] = score(k_v - 2 + i), the same FP32 expression the
@@ -461,14 +461,34 @@ __global__ __launch_bounds__(256) void k_mid_split(const int32_t *__restrict__ d
 // table of score(k_v - 2 + i), i < kGTab, built once per centre and
 // workgroup: one LDS read in place of a v_log_f32 and a multiply. In
 // degree order that holds for most tiles; the others take the log.
-// LDS: the column partials (64 KB) and the table keep to 80 KB, so that two
-// workgroups fit on a compute unit (measured: one workgroup per CU with a
-// larger table is slower).
+// Column partials of an off-diagonal super-tile: in round dl wavefront w
+// takes column block c = (w + dl) mod nbQ, so within a window of kColWin
+// rounds the partial of (c, round, w / nbQ) has one writer; a barrier
+// between windows orders the adds into the same accumulator, and the
+// column sum adds the accumulators in a fixed order (reproducible).
+// LDS: table (32 KB) plus the larger of the diagonal partials (36 KB) and
+// the column accumulators (at most 30 KB), so that two workgroups fit on a
+// compute unit.
 // ---------------------------------------------------------------------------
+constexpr int kColWin = 4;  // rounds between the barriers of the column adds
+
+// most (column block, wavefront group) pairs of one round over nbQ <= 16
+// blocks: nbQ * ceil(16 / nbQ), largest at nbQ = 15
+__host__ __device__ constexpr int col_groups_max() {
+  int m = 0;
+  for (int nb = 1; nb <= kBlocksPerSuper; ++nb) {
+    const int g = nb * ((kBlocksPerSuper + nb - 1) / nb);
+    m = g > m ? g : m;
+  }
+  return m;
+}
+
 template <typename T> struct BigLds {
   static constexpr bool kTab = std::is_same<T, float>::value;
   static constexpr int kTabBytes = kTab ? kGTab * 4 : 0;
-  static constexpr int kPartBytes = kBlocksPerSuper * kBlocksPerSuper * 64 * (int)sizeof(T);
+  static constexpr int kDiagBytes = kBlocksPerSuper * 9 * 64 * (int)sizeof(T);
+  static constexpr int kColBytes = col_groups_max() * kColWin * 64 * (int)sizeof(T);
+  static constexpr int kPartBytes = kDiagBytes > kColBytes ? kDiagBytes : kColBytes;
   static constexpr int kBytes = kTabBytes + kPartBytes;
 };
 
@@ -486,8 +506,7 @@ __device__ __forceinline__ void pairs_big_tile(const int32_t *__restrict__ row_p
                                                unsigned char *lds, int32_t &tab_v) {
   constexpr bool kTab = BigLds<T>::kTab;
   float *gtab = reinterpret_cast<float *>(lds);
-  T(*parts)[kBlocksPerSuper][64] =
-      reinterpret_cast<T(*)[kBlocksPerSuper][64]>(lds + BigLds<T>::kTabBytes);
+  T(*parts)[9][64] = reinterpret_cast<T(*)[9][64]>(lds + BigLds<T>::kTabBytes);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int2 *adj2 = adjs;
   const BigCentre bc = big[ti.big];
@@ -519,13 +538,18 @@ __device__ __forceinline__ void pairs_big_tile(const int32_t *__restrict__ row_p
     const bool ragged_q = (kSuper * Q + 64 * nbQ) > k;
     // the largest row degree of this wavefront's block (rows ascend)
     const int32_t kp_max = __shfl(kp, 63, 64);
+    // G wavefronts share a column block in one round (G = 1 when nbQ = 16)
+    const int G = (kBlocksPerSuper + nbQ - 1) / nbQ;
+    T *cacc = &parts[0][0][0];
+    zero_parts(cacc, nbQ * G * kColWin * 64);
     if (kTab && v != tab_v) {  // uniform: one centre per work item
       const float d0 = (float)(k - 2);
       for (int i = threadIdx.x; i < kGTab; i += blockDim.x) gtab[i] = score(d0 + (float)i);
-      __syncthreads();
       tab_v = v;
     }
+    __syncthreads();
     Acc<T> out;
+    T *mine = cacc + ((w / nbQ) * kColWin) * 64 + ((lane + 63) & 63);
     for (int dl = 0; dl < nbQ; ++dl) {
       const int c = (w + dl) % nbQ;
       const int32_t q = kSuper * Q + 64 * c + lane;
@@ -538,8 +562,10 @@ __device__ __forceinline__ void pairs_big_tile(const int32_t *__restrict__ row_p
       } else {
         tile<T, false, false>(cp, kq, Rt, C);
       }
-      parts[c][w][(lane + 63) & 63] = C;
+      // accumulator (c, w / nbQ, dl mod kColWin): one writer in this window
+      mine[(c * G * kColWin + dl % kColWin) * 64] += C;
       out.add(Rt);
+      if (dl % kColWin == kColWin - 1 && dl + 1 < nbQ) __syncthreads();
     }
     out.store(rec, rbase + 64 * w + lane);
     __syncthreads();
@@ -547,7 +573,8 @@ __device__ __forceinline__ void pairs_big_tile(const int32_t *__restrict__ row_p
       const int c = threadIdx.x >> 6, j = threadIdx.x & 63;
       if (c < nbQ) {
         Acc<T> col;
-        for (int ww = 0; ww < kBlocksPerSuper; ++ww) col.add(parts[c][ww][j]);
+        const T *a = cacc + c * G * kColWin * 64 + j;
+        for (int i = 0; i < G * kColWin; ++i) col.add(a[64 * i]);
         col.store(rec, rbase + kSuper + 64 * c + j);
       }
     }
