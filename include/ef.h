@@ -348,6 +348,9 @@ typedef struct {
   float weight_decay;  /* decoupled weight decay per step (0 = none) */
   float val_fraction;  /* held-out share for early stopping, in [0, 0.9) */
   int32_t patience;    /* epochs without validation improvement before stopping */
+  float lr_end;        /* step size of the last step as a share of lr, in (0, 1]: the
+                          step size follows a half cosine from lr down to lr * lr_end
+                          over the configured epochs (1: constant) */
 } ef_train_cfg;
 
 typedef struct {
@@ -381,9 +384,12 @@ ef_status ef_surrogate_load(ef_surrogate *s, const char *path);
 /* The 16 raw per-node features (row-major n x 16) and ln N(s) per node:
  * ln(1+k), ln(1+A), ln(1+B), ln(1+T), clustering, ln(1+A-k), ln(1+N),
  * ln(1+D), ln(D/N), max/min/mean/std of ln(neighbour degree), ln(1+Q),
- * share of degree-1 neighbours, ln(1+max neighbour-degree sum); A, B = sums
- * of neighbour degrees and of their squares, T = triangles, Q = sum over
- * neighbours of their neighbour-degree sums, N and D in closed form.
+ * share of degree-1 neighbours, ln(1+r); A, B = sums of neighbour degrees
+ * and of their squares, T = triangles, Q = sum over neighbours of their
+ * neighbour-degree sums, N and D in closed form, r = max(0, E2 N / D^2 - 1)
+ * the relative variance of the cluster degrees, E2 = the sum of the squared
+ * cluster degrees over the N event sequences (closed form per arc; triangle
+ * clusters without their -2). To second order in r, ln N - EF = r / 2.
  * EF_OUT_DEVICE: X and lnN are device pointers. */
 ef_status ef_features(ef_graph *g, float *X, float *lnN, uint32_t flags, void *hip_stream);
 
@@ -403,7 +409,8 @@ ef_status ef_surrogate_forward(ef_surrogate *s, const float *X, int64_t rows, fl
 
 /* Train on host rows: X raw features (rows x 16), y targets (ln N - exact EF).
  * Standardises the features (stored with the surrogate), then runs Adam on the
- * GPU with early stopping on a held-out share. */
+ * GPU, its step size decaying along a half cosine (cfg->lr_end), with early
+ * stopping on a held-out share. */
 ef_status ef_surrogate_train(ef_surrogate *s, const float *X, const float *y, int64_t rows,
                              const ef_train_cfg *cfg, ef_train_report *rep, void *hip_stream);
 

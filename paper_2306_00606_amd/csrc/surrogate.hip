@@ -50,41 +50,50 @@ __device__ __forceinline__ float bf(float x) { return (float)(__bf16)x; }
 // features: G lanes per node (8 for degree <= kFinGroupMax, 32 for degree <=
 // kFinHalfMax, 64 up to kFinBlockMin), one workgroup per hub
 // ---------------------------------------------------------------------------
+// Per arc (s, a), with c = k_s + k_a - 4, the clusters through a have degree
+// c + k_b for b in N(s) \ {a} (stars) and b in N(a) \ {s} (paths), so their
+// squared degrees sum to
+//   (k_s + k_a - 2) c^2 + 2 c (A_s - k_a + A_a - k_s) + (B_s - k_a^2 + B_a - k_s^2)
+// with A = sum of neighbour degrees, B = sum of their squares (triangle
+// clusters counted without their -2). With the mean cluster degree D/N, the
+// relative variance r = E2 N / D^2 - 1 gives ln N - EF = r/2 to second order.
 struct FeatAcc {  // POD (lives in LDS); start from feat_zero()
-  int64_t B, Q, T, c1, smax;
+  int64_t B, Q, T, c1;
   float mx, mn;
-  double s1, s2;
-  __device__ void add(int2 ad, int64_t sa) {
+  double s1, s2, e2;
+  __device__ void add(int2 ad, int64_t sa, int64_t ba, int64_t k, int64_t As, int64_t Bs) {
     const int64_t ka = ad.y;
     B += ka * ka;
     Q += sa;
-    smax = sa > smax ? sa : smax;
     c1 += ka == 1;
     const float lk = logf((float)ka);
     mx = fmaxf(mx, lk);
     mn = fminf(mn, lk);
     s1 += lk;
     s2 += (double)lk * lk;
+    const double c = (double)(k + ka - 4);
+    e2 += (double)(k + ka - 2) * c * c + 2.0 * c * (double)(As - ka + sa - k) +
+          (double)(Bs - ka * ka + ba - k * k);
   }
   __device__ void merge(const FeatAcc &o) {
     B += o.B;
     Q += o.Q;
     T += o.T;
     c1 += o.c1;
-    smax = o.smax > smax ? o.smax : smax;
     mx = fmaxf(mx, o.mx);
     mn = fminf(mn, o.mn);
     s1 += o.s1;
     s2 += o.s2;
+    e2 += o.e2;
   }
 };
 
 __device__ __forceinline__ FeatAcc feat_zero() {
   FeatAcc a;
-  a.B = a.Q = a.T = a.c1 = a.smax = 0;
+  a.B = a.Q = a.T = a.c1 = 0;
   a.mx = -1e30f;
   a.mn = 1e30f;
-  a.s1 = a.s2 = 0.0;
+  a.s1 = a.s2 = a.e2 = 0.0;
   return a;
 }
 
@@ -95,24 +104,28 @@ template <int G> __device__ __forceinline__ FeatAcc feat_reduce(FeatAcc a) {
     o.Q = __shfl_xor(a.Q, off, G);
     o.T = __shfl_xor(a.T, off, G);
     o.c1 = __shfl_xor(a.c1, off, G);
-    o.smax = __shfl_xor(a.smax, off, G);
     o.mx = __shfl_xor(a.mx, off, G);
     o.mn = __shfl_xor(a.mn, off, G);
     o.s1 = __shfl_xor(a.s1, off, G);
     o.s2 = __shfl_xor(a.s2, off, G);
+    o.e2 = __shfl_xor(a.e2, off, G);
     a.merge(o);
   }
   return a;
 }
 
+// arcs first, first + stride, ... of node v (degree k, neighbour-degree sum As
+// and sum of squares Bs)
 __device__ __forceinline__ void feat_arcs(const int2 *__restrict__ adj2,
                                           const int64_t *__restrict__ asum,
+                                          const longlong2 *__restrict__ qa,
                                           const int32_t *__restrict__ trec,
                                           const TriSlot *__restrict__ Y, int32_t k, int32_t base,
-                                          int32_t first, int32_t stride, FeatAcc &f) {
+                                          int64_t As, int64_t Bs, int32_t first, int32_t stride,
+                                          FeatAcc &f) {
   for (int32_t e = base + first; e < base + k; e += stride) {
     const int2 ad = adj2[e];
-    f.add(ad, asum[ad.x]);
+    f.add(ad, asum[ad.x], qa[ad.x].x, k, As, Bs);
     // triangles credited to the node through this edge
     const int32_t r = trec[e];
     if (r >= 0) f.T += Y[r].t;
@@ -146,7 +159,10 @@ __device__ void feat_store(int32_t v, int32_t k, int64_t A, FeatAcc a, bool has_
   f[12] = k > 0 ? (float)sqrt(fmax(a.s2 / k - mean_lk * mean_lk, 0.0)) : 0.0f;
   f[13] = logf(1.0f + (float)Q);
   f[14] = k > 0 ? (float)a.c1 / (float)k : 0.0f;
-  f[15] = logf(1.0f + (float)a.smax);
+  const double rv = (Ns > 0 && Ds > 0)
+                        ? a.e2 * (double)Ns / ((double)Ds * (double)Ds) - 1.0
+                        : 0.0;
+  f[15] = (float)log1p(fmax(rv, 0.0));
   float *dst = X + (int64_t)v * kF;
 #pragma unroll
   for (int i = 0; i < kF; ++i) dst[i] = mean ? (f[i] - mean[i]) * inv_std[i] : f[i];
@@ -158,8 +174,8 @@ template <int G>
 __global__ __launch_bounds__(256) void k_features(
     const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ deg,
     const int2 *__restrict__ adj2, const int64_t *__restrict__ asum,
-    const int32_t *__restrict__ trec, const TriSlot *__restrict__ Y,
-    const int32_t *__restrict__ dn_ptr,
+    const longlong2 *__restrict__ qa, const int32_t *__restrict__ trec,
+    const TriSlot *__restrict__ Y, const int32_t *__restrict__ dn_ptr,
     const int64_t *__restrict__ ZT, const int32_t *__restrict__ nodes, int64_t count,
     int32_t kmax, const float *__restrict__ mean, const float *__restrict__ inv_std,
     float *__restrict__ X, float *__restrict__ lnN) {
@@ -177,7 +193,7 @@ __global__ __launch_bounds__(256) void k_features(
     }
     if (v < 0) k = 0;
     FeatAcc f = feat_zero();
-    if (v >= 0) feat_arcs(adj2, asum, trec, Y, k, row_ptr[v], sub, G, f);
+    if (v >= 0) feat_arcs(adj2, asum, qa, trec, Y, k, row_ptr[v], asum[v], qa[v].x, sub, G, f);
     f = feat_reduce<G>(f);
     if (v >= 0 && sub == 0)
       feat_store(v, k, asum[v], f, dn_ptr[v + 1] > dn_ptr[v], ZT, mean, inv_std, X, lnN);
@@ -187,8 +203,8 @@ __global__ __launch_bounds__(256) void k_features(
 __global__ __launch_bounds__(1024) void k_features_hub(
     const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ deg,
     const int2 *__restrict__ adj2, const int64_t *__restrict__ asum,
-    const int32_t *__restrict__ trec, const TriSlot *__restrict__ Y,
-    const int32_t *__restrict__ dn_ptr,
+    const longlong2 *__restrict__ qa, const int32_t *__restrict__ trec,
+    const TriSlot *__restrict__ Y, const int32_t *__restrict__ dn_ptr,
     const int64_t *__restrict__ ZT, const int32_t *__restrict__ nodes, int64_t count,
     const float *__restrict__ mean, const float *__restrict__ inv_std, float *__restrict__ X,
     float *__restrict__ lnN) {
@@ -198,7 +214,7 @@ __global__ __launch_bounds__(1024) void k_features_hub(
     const int32_t v = nodes[it];
     const int32_t k = deg[v];
     FeatAcc f = feat_zero();
-    feat_arcs(adj2, asum, trec, Y, k, row_ptr[v], tid, 1024, f);
+    feat_arcs(adj2, asum, qa, trec, Y, k, row_ptr[v], asum[v], qa[v].x, tid, 1024, f);
     f = feat_reduce<64>(f);
     if (lane == 0) sh[wv] = f;
     __syncthreads();
@@ -219,18 +235,18 @@ hipError_t launch_features(const Graph &g, const TriSlot *Y, const int64_t *ZT,
   const int32_t *l_wave = g.fin_list + g.n_fin_hub, *l_half = l_wave + n_wave;
   if (g.n_fin_hub > 0)
     hipLaunchKernelGGL(k_features_hub, dim3(cap(g.n_fin_hub, 1 << 16)), dim3(1024), 0, st,
-                       g.row_ptr, g.deg, g.adj2, g.asum, g.trec, Y, g.dn_ptr, ZT, g.fin_list,
+                       g.row_ptr, g.deg, g.adj2, g.asum, g.qa, g.trec, Y, g.dn_ptr, ZT, g.fin_list,
                        g.n_fin_hub, mean, inv_std, X, lnN);
   hipLaunchKernelGGL(k_features<8>, dim3(cap(((int64_t)g.n * 8 + 255) / 256, 1 << 20)), dim3(256),
-                     0, st, g.row_ptr, g.deg, g.adj2, g.asum, g.trec, Y, g.dn_ptr, ZT, nullptr,
+                     0, st, g.row_ptr, g.deg, g.adj2, g.asum, g.qa, g.trec, Y, g.dn_ptr, ZT, nullptr,
                      (int64_t)g.n, kFinGroupMax, mean, inv_std, X, lnN);
   if (n_wave > 0)
     hipLaunchKernelGGL(k_features<64>, dim3(cap((n_wave * 64 + 255) / 256, 1 << 20)), dim3(256),
-                       0, st, g.row_ptr, g.deg, g.adj2, g.asum, g.trec, Y, g.dn_ptr, ZT, l_wave, n_wave,
+                       0, st, g.row_ptr, g.deg, g.adj2, g.asum, g.qa, g.trec, Y, g.dn_ptr, ZT, l_wave, n_wave,
                        0, mean, inv_std, X, lnN);
   if (g.n_fin_half > 0)
     hipLaunchKernelGGL(k_features<32>, dim3(cap((g.n_fin_half * 32 + 255) / 256, 1 << 20)),
-                       dim3(256), 0, st, g.row_ptr, g.deg, g.adj2, g.asum, g.trec, Y, g.dn_ptr, ZT,
+                       dim3(256), 0, st, g.row_ptr, g.deg, g.adj2, g.asum, g.qa, g.trec, Y, g.dn_ptr, ZT,
                        l_half, g.n_fin_half, 0, mean, inv_std, X, lnN);
   return hipGetLastError();
 }

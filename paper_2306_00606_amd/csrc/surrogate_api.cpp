@@ -351,7 +351,8 @@ ef_status ef_surrogate_forward(ef_surrogate *s, const float *X, int64_t rows, fl
 ef_status ef_surrogate_train(ef_surrogate *s, const float *X, const float *y, int64_t rows,
                              const ef_train_cfg *cfg, ef_train_report *rep, void *hip_stream) {
   if (!s || !X || !y || rows < 64 || !cfg || cfg->epochs < 0 || cfg->batch < 32 ||
-      !(cfg->lr > 0.f) || cfg->val_fraction < 0.f || cfg->val_fraction >= 0.9f) {
+      !(cfg->lr > 0.f) || cfg->val_fraction < 0.f || cfg->val_fraction >= 0.9f ||
+      !(cfg->lr_end > 0.f && cfg->lr_end <= 1.f)) {
     set_error("ef_surrogate_train: bad arguments");
     return EF_ERR_ARG;
   }
@@ -404,6 +405,15 @@ ef_status ef_surrogate_train(ef_surrogate *s, const float *X, const float *y, in
   float best = INFINITY, last_train = 0.f, last_val = 0.f;
   int32_t since_best = 0, epochs_run = 0;
   const int64_t batch = cfg->batch;
+  // step size: a half cosine from lr (first step) to lr * lr_end (last step
+  // of the configured epochs)
+  const int64_t steps_total = (int64_t)cfg->epochs * ((ntr + batch - 1) / batch);
+  int64_t t_step = 0;
+  const auto step_lr = [&](int64_t t) {
+    const double u = steps_total > 1 ? (double)t / (double)(steps_total - 1) : 1.0;
+    const double f = cfg->lr_end + (1.0 - cfg->lr_end) * 0.5 * (1.0 + std::cos(M_PI * u));
+    return (float)(cfg->lr * f);
+  };
   for (int32_t ep = 0; ep < cfg->epochs && e == hipSuccess; ++ep) {
     std::shuffle(tr.begin(), tr.end(), rng);
     e = hipMemcpyAsync(dperm, tr.data(), sizeof(int32_t) * ntr, hipMemcpyHostToDevice, st);
@@ -415,7 +425,7 @@ ef_status ef_surrogate_train(ef_surrogate *s, const float *X, const float *y, in
       e = launch_mlp_grad(dX, dy, dperm, b0, nb, s->dP, s->dpack, s->dpart, s->dpart_loss,
                           nblocks, s->dgrad, s->dloss, st);
       if (e == hipSuccess)
-        e = launch_adam(s->dP, s->dM, s->dV, s->dgrad, cfg->lr, 0.9f, 0.999f, 1e-8f,
+        e = launch_adam(s->dP, s->dM, s->dV, s->dgrad, step_lr(t_step++), 0.9f, 0.999f, 1e-8f,
                         cfg->weight_decay, ++s->step, st);
       if (e == hipSuccess) e = launch_mlp_pack(s->dP, s->dpack, st);
     }

@@ -97,7 +97,8 @@ class BatchStats(ctypes.Structure):
 class TrainCfg(ctypes.Structure):
     _fields_ = [("lr", ctypes.c_float), ("epochs", ctypes.c_int32), ("batch", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("weight_decay", ctypes.c_float),
-                ("val_fraction", ctypes.c_float), ("patience", ctypes.c_int32)]
+                ("val_fraction", ctypes.c_float), ("patience", ctypes.c_int32),
+                ("lr_end", ctypes.c_float)]
 
 
 class TrainReport(ctypes.Structure):
@@ -534,10 +535,10 @@ class Surrogate:
         return y[:X.shape[0]]
 
     def train(self, X, y, lr=3e-3, epochs=30, batch=4096, seed=0, weight_decay=0.0,
-              val_fraction=0.05, patience=4):
+              val_fraction=0.05, patience=4, lr_end=0.05):
         X = np.ascontiguousarray(X, np.float32)
         y = np.ascontiguousarray(y, np.float32)
-        cfg = TrainCfg(lr, epochs, batch, seed, weight_decay, val_fraction, patience)
+        cfg = TrainCfg(lr, epochs, batch, seed, weight_decay, val_fraction, patience, lr_end)
         rep = TrainReport()
         _check(lib().ef_surrogate_train(self._h, X.ctypes.data, y.ctypes.data, len(y),
                                         ctypes.byref(cfg), ctypes.byref(rep), _stream_ptr(None)))

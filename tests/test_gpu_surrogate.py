@@ -124,7 +124,19 @@ def cpu_features(rp, ci):
             lk = np.log(k[nb])
             F[v, 9], F[v, 10], F[v, 11], F[v, 12] = lk.max(), lk.min(), lk.mean(), lk.std()
             F[v, 14] = np.mean(k[nb] == 1)
-            F[v, 15] = np.log1p(Asum[nb].max())
+            # squared cluster degrees over every event sequence, by brute force:
+            # stars (v, a, b) in both orders and paths v -> a -> b, each with
+            # degree k_v + k_a + k_b - 4 (no triangle correction)
+            e2 = 0.0
+            for a in nb:
+                for b in nb:
+                    if b != a:
+                        e2 += (k[v] + k[a] + k[b] - 4) ** 2
+                for b in ci[rp[a]:rp[a + 1]]:
+                    if b != v:
+                        e2 += (k[v] + k[a] + k[b] - 4) ** 2
+            if N[v] > 0 and D[v] > 0:
+                F[v, 15] = np.log1p(max(e2 * N[v] / float(D[v]) ** 2 - 1.0, 0.0))
     F[:, 13] = np.log1p(Q)
     return F, N
 
