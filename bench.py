@@ -37,16 +37,26 @@ sys.path.insert(0, ROOT)
 METRIC = "clusters/s & EF nodes/s (R-MAT 42M edges), % HBM peak; surrogate vs exact"
 
 # MI355X published FP32 vector peak: 157.3 TFLOP/s = 256 CUs x 2.4 GHz x 256
-# flops per CU and clock (128 FP32 lanes, an FMA counted as two flops).
+# flops per CU and clock: 64 lanes, packed FP32 (two values per lane) and an
+# FMA counted as two flops.
 FP32_VECTOR_PEAK_FLOPS = 157.3e12
-# VALU issue model of a CU: FP32 instructions issue over 128 lanes per clock,
-# two wave64 instructions per CU and clock, 78.6e12 FP32 lane-instructions per
-# second (256 x 2.4 GHz x 128); transcendentals at a quarter of that. On the
-# box, chains of non-packed FMAs reach 5.8e13 lane-instructions/s (74%).
-VALU_LANE_OPS_PEAK = 256 * 128 * 2.4e9
-# Algorithmic cost of one cluster, the scope table's figure: about 16 FP32
-# VALU operations (the degree, d log d, the two credits, the triangle test's
-# share), counted as flops against the FP32 vector peak.
+# VALU issue peak without packed FP32 (the library is built without it): one
+# wave64 instruction per CU and clock, 256 x 2.4 GHz x 64 = 3.93e13 lane
+# operations per second for an add, a multiply, an FMA or a DPP add alike.
+# On the device, loops of the pair kernel's table step (integer DPP add, add,
+# DPP add) issue 1.005 and chains of FMAs 0.98 wave64 instructions per CU and
+# clock; the pair kernel issues 1.0 counting each v_log_f32 once.
+VALU_LANE_OPS_PEAK = 256 * 64 * 2.4e9
+# Algorithmic VALU instructions per cluster of the super-tile pair loop as
+# built: a table-scored cluster takes the table index step, the row credit
+# and the column credit (3); a cluster scored with the log takes the degree
+# step, the log, the multiply and the two credits (5).
+VALU_OPS_TABLE_CLUSTER = 3
+VALU_OPS_LOG_CLUSTER = 5
+# The scope table's estimate of the cost of one cluster with a log per
+# cluster: about 16 FP32 VALU operations (the degree, d log d, the two
+# credits, the triangle test's share). Reported beside the roofline: the
+# score table removes most of them.
 OPS_PER_CLUSTER = 16
 # the kernel's rule: a full off-diagonal 64 x 64 tile of a big centre (rows in
 # an earlier super-block of 1024 than its columns) whose largest degrees
@@ -58,15 +68,15 @@ TABLE_ENTRIES = 8192
 # super-tile records the kernel writes. Taken on the current kernel (the
 # counter summaries sit with the other rocprofv3 summaries); set to None
 # whenever the kernel changes.
-PAIRS_BIG_TRAFFIC_BYTES = None
+PAIRS_BIG_TRAFFIC_BYTES = 2.655e9
 # Hardware counters of k_pairs_big<float> at the same workload, per launch
 # (rocprofv3 --pmc, the counter summaries sit with the other rocprofv3
 # summaries): SQ_INSTS_VALU (wave64 VALU instructions), of which
 # SQ_INSTS_VALU_TRANS_F32 transcendentals (v_log_f32) and SQ_INSTS_LDS.
 # None whenever the kernel changes.
-PAIRS_BIG_VALU_INSTS = None
-PAIRS_BIG_TRANS_INSTS = None
-PAIRS_BIG_LDS_INSTS = None
+PAIRS_BIG_VALU_INSTS = 6.092e9
+PAIRS_BIG_TRANS_INSTS = 1.335e8
+PAIRS_BIG_LDS_INSTS = 1.614e9
 # VALU cost of one SIR attempt along an arc, in FP32-FMA-equivalent lane slots:
 # the counter (2e) K and SplitMix64's two multiplications are three 64-bit
 # products of three 32-bit multiplies each, at a quarter of the FMA rate
@@ -507,28 +517,30 @@ def main():
     headline = (args.scale, args.edge_factor) == (22, 10)
     if args.algo == "cluster" and args.prec == "fp32c" and st["t_pairs_big_ms"] > 0:
         t_launch = st["t_pairs_big_ms"] * 1e-3
-        achieved = st["pairs_big"] * OPS_PER_CLUSTER / t_launch
+        w_launch = st["pairs_big"]
+        w_table = table_clusters(rp, ci)
+        ops = VALU_OPS_TABLE_CLUSTER * w_table + VALU_OPS_LOG_CLUSTER * (w_launch - w_table)
+        achieved = ops / t_launch
         counters = None
         if headline and PAIRS_BIG_VALU_INSTS:
             lane_insts = PAIRS_BIG_VALU_INSTS * 64 / t_launch
-            # issue slots: a transcendental occupies four
-            slots = (PAIRS_BIG_VALU_INSTS + 3 * PAIRS_BIG_TRANS_INSTS) * 64 / t_launch
             counters = {"valu_insts_per_launch": PAIRS_BIG_VALU_INSTS,
                         "trans_insts_per_launch": PAIRS_BIG_TRANS_INSTS,
                         "lds_insts_per_launch": PAIRS_BIG_LDS_INSTS,
-                        "valu_insts_per_cluster": PAIRS_BIG_VALU_INSTS * 64 / st["pairs_big"],
+                        "valu_insts_per_cluster": PAIRS_BIG_VALU_INSTS * 64 / w_launch,
                         "valu_lane_insts_per_s": lane_insts,
-                        "issue_peak_lane_insts_per_s": VALU_LANE_OPS_PEAK,
-                        "frac_of_issue_peak": lane_insts / VALU_LANE_OPS_PEAK,
-                        "frac_of_issue_slots": slots / VALU_LANE_OPS_PEAK}
+                        "frac_of_issue_peak": lane_insts / VALU_LANE_OPS_PEAK}
         roofline = {"bound": "alu", "kernel": "k_pairs_big<float>",
-                    "achieved": achieved / 1e12, "peak": FP32_VECTOR_PEAK_FLOPS / 1e12,
-                    "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_FLOPS,
+                    "achieved": achieved / 1e12, "peak": VALU_LANE_OPS_PEAK / 1e12,
+                    "unit": "T VALU lane-ops/s", "frac": achieved / VALU_LANE_OPS_PEAK,
                     "traffic": PAIRS_BIG_TRAFFIC_BYTES if headline else None,
-                    "ops_per_cluster": OPS_PER_CLUSTER,
-                    "clusters_per_launch": st["pairs_big"],
-                    "table_clusters": table_clusters(rp, ci),
-                    "avg_launch_ms": st["t_pairs_big_ms"], "counters": counters}
+                    "valu_ops_per_cluster": {"table": VALU_OPS_TABLE_CLUSTER,
+                                             "log": VALU_OPS_LOG_CLUSTER},
+                    "clusters_per_launch": w_launch, "table_clusters": w_table,
+                    "avg_launch_ms": st["t_pairs_big_ms"], "counters": counters,
+                    "scope_ops": {"ops_per_cluster": OPS_PER_CLUSTER,
+                                  "achieved_tops": w_launch * OPS_PER_CLUSTER / t_launch / 1e12,
+                                  "fp32_vector_peak_tflops": FP32_VECTOR_PEAK_FLOPS / 1e12}}
     else:
         roofline = None
     # the headline step's outputs, before any other section reuses the device

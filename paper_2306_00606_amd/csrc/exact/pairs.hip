@@ -96,6 +96,22 @@ template <> struct Acc<double> {
   __device__ void add_stored(const void *R, int64_t i) { v += reinterpret_cast<const double *>(R)[i]; }
 };
 
+// Full 64x64 tile (no masking) with the row step D = cp - rot(cp) given, so
+// that a caller running many tiles of one row block forms it once.
+template <typename T>
+__device__ __forceinline__ void tile_full(T cp, T kq, T D, T &Rt, T &C) {
+  Rt = T(0);
+  C = T(0);
+  T d = cp + kq;
+#pragma unroll 8
+  for (int s = 0; s < 64; ++s) {
+    T g = score(d);
+    Rt += g;
+    C = rot1(C) + g;
+    d = rot1(d) + D;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // one 64x64 tile on a wavefront
 //   cp : k_v + k_p - 4 for this lane's row (kNegF if the row is past k)
@@ -135,15 +151,7 @@ __device__ __forceinline__ void tile(T cp, T kq, T &Rt, T &C) {
     // holds column q + 1 at step s + 1, so d_{s+1} = rot(d_s) + cp - rot(cp):
     // one add with the rotation folded in. All values are integers below
     // 2^24, exact in either precision.
-    T d = cp + kq;
-    const T D = cp - rot1(cp);
-#pragma unroll 8
-    for (int s = 0; s < 64; ++s) {
-      T g = score(d);
-      Rt += g;
-      C = rot1(C) + g;
-      d = rot1(d) + D;
-    }
+    tile_full(cp, kq, cp - rot1(cp), Rt, C);
   }
 }
 
@@ -163,12 +171,11 @@ constexpr int kGTab = 8192;
 // The difference 4 (roff - rot(roff)) is formed in FP32 (exact: below 2^24):
 // folded into an integer v_subrev_u32_dpp it came out negated on the device.
 template <typename T>
-__device__ __forceinline__ void tile_tab(int32_t roff, int32_t kq, const float *gt, T &Rt, T &C) {
+__device__ __forceinline__ void tile_tab(int32_t roff, int32_t kq, int32_t D, const float *gt,
+                                         T &Rt, T &C) {
   Rt = T(0);
   C = T(0);
   const char *base = reinterpret_cast<const char *>(gt);
-  const float r4 = (float)(4 * roff);
-  const int32_t D = (int32_t)(r4 - rot1(r4));
   int32_t idx = 4 * (roff + kq);
 #pragma unroll 8
   for (int s = 0; s < 64; ++s) {
@@ -177,6 +184,15 @@ __device__ __forceinline__ void tile_tab(int32_t roff, int32_t kq, const float *
     C = rot1(C) + g;
     idx = rot1i(idx) + D;
   }
+}
+// the index step 4 (roff - rot(roff)) of tile_tab for this lane's row
+__device__ __forceinline__ int32_t tab_step(int32_t roff) {
+  const float r4 = (float)(4 * roff);
+  return (int32_t)(r4 - rot1(r4));
+}
+template <typename T>
+__device__ __forceinline__ void tile_tab(int32_t roff, int32_t kq, const float *gt, T &Rt, T &C) {
+  tile_tab<T>(roff, kq, tab_step(roff), gt, Rt, C);
 }
 
 // ---------------------------------------------------------------------------
@@ -466,9 +482,9 @@ __global__ __launch_bounds__(256) void k_mid_split(const int32_t *__restrict__ d
 // rounds the partial of (c, round, w / nbQ) has one writer; a barrier
 // between windows orders the adds into the same accumulator, and the
 // column sum adds the accumulators in a fixed order (reproducible).
-// LDS: table (32 KB) plus the larger of the diagonal partials (36 KB) and
-// the column accumulators (at most 30 KB), so that two workgroups fit on a
-// compute unit.
+// LDS: table (32 KB), the larger of the diagonal partials (36 KB) and the
+// column accumulators (at most 30 KB), and the super-tile's column degrees
+// (4 KB), so that two workgroups fit on a compute unit.
 // ---------------------------------------------------------------------------
 constexpr int kColWin = 4;  // rounds between the barriers of the column adds
 
@@ -489,8 +505,13 @@ template <typename T> struct BigLds {
   static constexpr int kDiagBytes = kBlocksPerSuper * 9 * 64 * (int)sizeof(T);
   static constexpr int kColBytes = col_groups_max() * kColWin * 64 * (int)sizeof(T);
   static constexpr int kPartBytes = kDiagBytes > kColBytes ? kDiagBytes : kColBytes;
-  static constexpr int kBytes = kTabBytes + kPartBytes;
+  static constexpr int kColDegBytes = kSuper * 4;  // column degrees of an off-diagonal super-tile
+  static constexpr int kBytes = kTabBytes + kPartBytes + kColDegBytes;
 };
+
+// column degree past the centre's row (as a float: kNegF)
+constexpr int32_t kNegI = -1000000000;
+static_assert((float)kNegI == kNegF, "kNegI must convert to kNegF");
 
 // One super-tile on a 16-wavefront workgroup (every thread calls it: it holds
 // workgroup barriers). lds: BigLds<T>::kBytes, the scores of the current
@@ -532,50 +553,68 @@ __device__ __forceinline__ void pairs_big_tile(const int32_t *__restrict__ row_p
     if (w < nbQ) out.store(rec, rbase + 64 * w + lane);
   } else {
     // P < Q: all 16 row blocks of P are full
+    const int ws = __builtin_amdgcn_readfirstlane(w);
     const int32_t p = kSuper * P + 64 * w + lane;
     const int32_t kp = adj2[base + p].y;
     const T cp = kv4 + (T)kp;
     const bool ragged_q = (kSuper * Q + 64 * nbQ) > k;
-    // the largest row degree of this wavefront's block (rows ascend)
-    const int32_t kp_max = __shfl(kp, 63, 64);
     // G wavefronts share a column block in one round (G = 1 when nbQ = 16)
     const int G = (kBlocksPerSuper + nbQ - 1) / nbQ;
     T *cacc = &parts[0][0][0];
+    int32_t *colk = reinterpret_cast<int32_t *>(lds + BigLds<T>::kTabBytes + BigLds<T>::kPartBytes);
     zero_parts(cacc, nbQ * G * kColWin * 64);
+    for (int i = threadIdx.x; i < 64 * nbQ; i += blockDim.x) {
+      const int32_t q = kSuper * Q + i;
+      colk[i] = q < k ? adj2[base + q].y : kNegI;
+    }
     if (kTab && v != tab_v) {  // uniform: one centre per work item
       const float d0 = (float)(k - 2);
       for (int i = threadIdx.x; i < kGTab; i += blockDim.x) gtab[i] = score(d0 + (float)i);
       tab_v = v;
     }
     __syncthreads();
+    // full column blocks 0 .. nfit-1 fit the table for this wavefront's rows:
+    // k_p + k_q - 2 < kGTab at the largest row and column degrees (the last
+    // lane of each block, as degrees ascend, so the blocks that fit are a
+    // prefix)
+    int nfit = 0;
+    if (kTab) {
+      const int32_t kp_max = __shfl(kp, 63, 64);
+      const int nfull = ragged_q ? nbQ - 1 : nbQ;
+      bool fit = false;
+      if (lane < nfull) fit = kp_max + colk[64 * lane + 63] - 2 < kGTab;
+      nfit = __popcll(__ballot(fit));
+    }
+    const int32_t Dt = kTab ? tab_step(kp - 2) : 0;
+    const T Dd = cp - rot1(cp);
     Acc<T> out;
     T *mine = cacc + ((w / nbQ) * kColWin) * 64 + ((lane + 63) & 63);
+    int c = ws % nbQ;  // column block of round dl: (w + dl) mod nbQ
     for (int dl = 0; dl < nbQ; ++dl) {
-      const int c = (w + dl) % nbQ;
-      const int32_t q = kSuper * Q + 64 * c + lane;
-      const T kq = col_degree<T>(adj2, base, k, q);
+      const int32_t kq = colk[64 * c + lane];
       T Rt, C;
       if (ragged_q && c == nbQ - 1) {
-        tile<T, false, true>(cp, kq, Rt, C);
-      } else if (kTab && kp_max + __shfl((int32_t)kq, 63, 64) - 2 < kGTab) {
-        tile_tab<T>(kp - 2, (int32_t)kq, gtab, Rt, C);
+        tile<T, false, true>(cp, (T)kq, Rt, C);
+      } else if (c < nfit) {
+        tile_tab<T>(kp - 2, kq, Dt, gtab, Rt, C);
       } else {
-        tile<T, false, false>(cp, kq, Rt, C);
+        tile_full<T>(cp, (T)kq, Dd, Rt, C);
       }
       // accumulator (c, w / nbQ, dl mod kColWin): one writer in this window
       mine[(c * G * kColWin + dl % kColWin) * 64] += C;
       out.add(Rt);
       if (dl % kColWin == kColWin - 1 && dl + 1 < nbQ) __syncthreads();
+      c = c + 1 == nbQ ? 0 : c + 1;
     }
     out.store(rec, rbase + 64 * w + lane);
     __syncthreads();
     {
-      const int c = threadIdx.x >> 6, j = threadIdx.x & 63;
-      if (c < nbQ) {
+      const int cc = threadIdx.x >> 6, j = threadIdx.x & 63;
+      if (cc < nbQ) {
         Acc<T> col;
-        const T *a = cacc + c * G * kColWin * 64 + j;
+        const T *a = cacc + cc * G * kColWin * 64 + j;
         for (int i = 0; i < G * kColWin; ++i) col.add(a[64 * i]);
-        col.store(rec, rbase + kSuper + 64 * c + j);
+        col.store(rec, rbase + kSuper + 64 * cc + j);
       }
     }
   }
