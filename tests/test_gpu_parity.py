@@ -170,6 +170,39 @@ def test_score_table_and_log_tiles(prec):
     assert_parity(ef, D, N, oN, oD, oE, prec, "score table edge")
 
 
+def short_superblock_graph():
+    """Centres whose last super-block of 1024 neighbours holds few 64-column
+    blocks: degrees 1025 (one ragged block), 1088 (one full block), 1152 (two
+    full), 1300 (five, ragged), 2100 (three super-blocks, the last one ragged
+    block) and 4160 (five, the last one full block), so that up to 16
+    wavefronts share a column block in one round of the super-tile loop. Each
+    centre is linked to hub H = 0 (degree about 9000), whose degree puts the
+    tiles holding it beyond the score table; random edges close triangles."""
+    rs = np.random.default_rng(29)
+    n = 12000
+    degs = [1025, 1088, 1152, 1300, 2100, 4160]
+    src = [np.zeros(9000, np.int32)]
+    dst = [np.arange(12, 9012, dtype=np.int32)]
+    for c, k in enumerate(degs, start=1):
+        others = rs.choice(np.arange(12, n), k - 1, replace=False).astype(np.int32)
+        src.append(np.full(k, c, np.int32))
+        dst.append(np.concatenate([[0], others]).astype(np.int32))
+    e = rs.integers(12, n, size=(3000, 2)).astype(np.int32)
+    src.append(e[:, 0])
+    dst.append(e[:, 1])
+    return gen.from_edges(n, np.concatenate(src), np.concatenate(dst)), degs
+
+
+@pytest.mark.parametrize("prec", ["fp32c", "fp64"])
+def test_short_last_superblocks(prec):
+    (rp, ci), degs = short_superblock_graph()
+    deg = np.diff(rp)
+    assert deg[1:7].tolist() == degs and deg[0] == 9006
+    ef, D, N = run_all(rp, ci, "cluster", prec)
+    oN, oD, oE = oracle.ef(rp, ci, threads=8)
+    assert_parity(ef, D, N, oN, oD, oE, prec, "short last super-blocks")
+
+
 def test_selected_seeds_with_duplicates():
     rp, ci = hub_graph()
     seeds = np.array([0, 1, 5, 0, 5999, 17, 1, 2, 3001], np.int32)
