@@ -137,6 +137,8 @@ struct Graph {
                                // when no centre has more than kSuper neighbours
   int64_t *asum = nullptr;     // sum of neighbour degrees per node
   longlong2 *qa = nullptr;     // per node: {sum of squared neighbour degrees, sum of neighbours' asum}
+  longlong2 *asq = nullptr;    // per node: {asum, sum of squared neighbour degrees}, one gather
+                               // per arc for the surrogate's features
   int32_t *up_ptr = nullptr;   // degree-oriented half adjacency: u -> {w : rank(w) > rank(u)}
   int32_t *up_col = nullptr;   // each up(u) in rank order
   int32_t *up_deg = nullptr;   // degree of every up_col entry

@@ -252,7 +252,8 @@ __global__ void k_dn_work(const int32_t *__restrict__ dn_ptr, const int4 *__rest
 // neighbours' neighbour-degree sums (with k and asum, they give N and D of
 // the node in closed form).
 __global__ void k_qa(const int32_t *__restrict__ row_ptr, const int2 *__restrict__ adj2,
-                     const int64_t *__restrict__ asum, int32_t n, longlong2 *__restrict__ qa) {
+                     const int64_t *__restrict__ asum, int32_t n, longlong2 *__restrict__ qa,
+                     longlong2 *__restrict__ asq) {
   const int lane = threadIdx.x & 63;
   const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -267,7 +268,10 @@ __global__ void k_qa(const int32_t *__restrict__ row_ptr, const int2 *__restrict
       q += __shfl_xor(q, off, 64);
       a2 += __shfl_xor(a2, off, 64);
     }
-    if (lane == 0) qa[v] = make_longlong2(q, a2);
+    if (lane == 0) {
+      qa[v] = make_longlong2(q, a2);
+      asq[v] = make_longlong2(asum[v], q);
+    }
   }
 }
 
@@ -460,7 +464,7 @@ hipError_t launch_graph_prep(Graph &g, int32_t *tmp, int64_t *work, bool &not_sy
     hipLaunchKernelGGL(k_asum, dim3(grid_for((int64_t)g.n * 64, T)), dim3(T), 0, st,
                        g.row_ptr, g.adj2, g.n, g.asum);
     hipLaunchKernelGGL(k_qa, dim3(grid_for((int64_t)g.n * 64, T)), dim3(T), 0, st, g.row_ptr,
-                       g.adj2, g.asum, g.n, g.qa);
+                       g.adj2, g.asum, g.n, g.qa, g.asq);
   } else {
     hipLaunchKernelGGL(k_up_fill, dim3(grid_for(g.n + 1, T)), dim3(T), 0, st, g.row_ptr,
                        g.col_idx, g.rev, tmp, tmp, g.n, (int64_t)0, g.up_ptr, g.up_col,
@@ -470,6 +474,7 @@ hipError_t launch_graph_prep(Graph &g, int32_t *tmp, int64_t *work, bool &not_sy
                        g.dn_ptr);
     (void)hipMemsetAsync(g.asum, 0, sizeof(int64_t) * (size_t)g.n, st);
     (void)hipMemsetAsync(g.qa, 0, sizeof(longlong2) * (size_t)g.n, st);
+    (void)hipMemsetAsync(g.asq, 0, sizeof(longlong2) * (size_t)g.n, st);
     (void)hipMemsetAsync(work, 0, sizeof(int64_t) * (size_t)g.n, st);
   }
   return hipGetLastError();

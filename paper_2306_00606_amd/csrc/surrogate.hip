@@ -115,17 +115,17 @@ template <int G> __device__ __forceinline__ FeatAcc feat_reduce(FeatAcc a) {
 }
 
 // arcs first, first + stride, ... of node v (degree k, neighbour-degree sum As
-// and sum of squares Bs)
+// and sum of squares Bs); asq: per node {neighbour-degree sum, sum of squares}
 __device__ __forceinline__ void feat_arcs(const int2 *__restrict__ adj2,
-                                          const int64_t *__restrict__ asum,
-                                          const longlong2 *__restrict__ qa,
+                                          const longlong2 *__restrict__ asq,
                                           const int32_t *__restrict__ trec,
                                           const TriSlot *__restrict__ Y, int32_t k, int32_t base,
                                           int64_t As, int64_t Bs, int32_t first, int32_t stride,
                                           FeatAcc &f) {
   for (int32_t e = base + first; e < base + k; e += stride) {
     const int2 ad = adj2[e];
-    f.add(ad, asum[ad.x], qa[ad.x].x, k, As, Bs);
+    const longlong2 t = asq[ad.x];
+    f.add(ad, t.x, t.y, k, As, Bs);
     // triangles credited to the node through this edge
     const int32_t r = trec[e];
     if (r >= 0) f.T += Y[r].t;
@@ -173,8 +173,8 @@ __device__ void feat_store(int32_t v, int32_t k, int64_t A, FeatAcc a, bool has_
 template <int G>
 __global__ __launch_bounds__(256) void k_features(
     const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ deg,
-    const int2 *__restrict__ adj2, const int64_t *__restrict__ asum,
-    const longlong2 *__restrict__ qa, const int32_t *__restrict__ trec,
+    const int2 *__restrict__ adj2, const longlong2 *__restrict__ asq,
+    const int32_t *__restrict__ trec,
     const TriSlot *__restrict__ Y, const int32_t *__restrict__ dn_ptr,
     const int64_t *__restrict__ ZT, const int32_t *__restrict__ nodes, int64_t count,
     int32_t kmax, const float *__restrict__ mean, const float *__restrict__ inv_std,
@@ -193,17 +193,21 @@ __global__ __launch_bounds__(256) void k_features(
     }
     if (v < 0) k = 0;
     FeatAcc f = feat_zero();
-    if (v >= 0) feat_arcs(adj2, asum, qa, trec, Y, k, row_ptr[v], asum[v], qa[v].x, sub, G, f);
+    longlong2 own = make_longlong2(0, 0);
+    if (v >= 0) {
+      own = asq[v];
+      feat_arcs(adj2, asq, trec, Y, k, row_ptr[v], own.x, own.y, sub, G, f);
+    }
     f = feat_reduce<G>(f);
     if (v >= 0 && sub == 0)
-      feat_store(v, k, asum[v], f, dn_ptr[v + 1] > dn_ptr[v], ZT, mean, inv_std, X, lnN);
+      feat_store(v, k, own.x, f, dn_ptr[v + 1] > dn_ptr[v], ZT, mean, inv_std, X, lnN);
   }
 }
 
 __global__ __launch_bounds__(1024) void k_features_hub(
     const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ deg,
-    const int2 *__restrict__ adj2, const int64_t *__restrict__ asum,
-    const longlong2 *__restrict__ qa, const int32_t *__restrict__ trec,
+    const int2 *__restrict__ adj2, const longlong2 *__restrict__ asq,
+    const int32_t *__restrict__ trec,
     const TriSlot *__restrict__ Y, const int32_t *__restrict__ dn_ptr,
     const int64_t *__restrict__ ZT, const int32_t *__restrict__ nodes, int64_t count,
     const float *__restrict__ mean, const float *__restrict__ inv_std, float *__restrict__ X,
@@ -214,14 +218,15 @@ __global__ __launch_bounds__(1024) void k_features_hub(
     const int32_t v = nodes[it];
     const int32_t k = deg[v];
     FeatAcc f = feat_zero();
-    feat_arcs(adj2, asum, qa, trec, Y, k, row_ptr[v], asum[v], qa[v].x, tid, 1024, f);
+    const longlong2 own = asq[v];
+    feat_arcs(adj2, asq, trec, Y, k, row_ptr[v], own.x, own.y, tid, 1024, f);
     f = feat_reduce<64>(f);
     if (lane == 0) sh[wv] = f;
     __syncthreads();
     if (tid == 0) {
       FeatAcc a = sh[0];
       for (int w = 1; w < 16; ++w) a.merge(sh[w]);
-      feat_store(v, k, asum[v], a, dn_ptr[v + 1] > dn_ptr[v], ZT, mean, inv_std, X, lnN);
+      feat_store(v, k, own.x, a, dn_ptr[v + 1] > dn_ptr[v], ZT, mean, inv_std, X, lnN);
     }
     __syncthreads();
   }
@@ -235,18 +240,18 @@ hipError_t launch_features(const Graph &g, const TriSlot *Y, const int64_t *ZT,
   const int32_t *l_wave = g.fin_list + g.n_fin_hub, *l_half = l_wave + n_wave;
   if (g.n_fin_hub > 0)
     hipLaunchKernelGGL(k_features_hub, dim3(cap(g.n_fin_hub, 1 << 16)), dim3(1024), 0, st,
-                       g.row_ptr, g.deg, g.adj2, g.asum, g.qa, g.trec, Y, g.dn_ptr, ZT, g.fin_list,
+                       g.row_ptr, g.deg, g.adj2, g.asq, g.trec, Y, g.dn_ptr, ZT, g.fin_list,
                        g.n_fin_hub, mean, inv_std, X, lnN);
   hipLaunchKernelGGL(k_features<8>, dim3(cap(((int64_t)g.n * 8 + 255) / 256, 1 << 20)), dim3(256),
-                     0, st, g.row_ptr, g.deg, g.adj2, g.asum, g.qa, g.trec, Y, g.dn_ptr, ZT, nullptr,
+                     0, st, g.row_ptr, g.deg, g.adj2, g.asq, g.trec, Y, g.dn_ptr, ZT, nullptr,
                      (int64_t)g.n, kFinGroupMax, mean, inv_std, X, lnN);
   if (n_wave > 0)
     hipLaunchKernelGGL(k_features<64>, dim3(cap((n_wave * 64 + 255) / 256, 1 << 20)), dim3(256),
-                       0, st, g.row_ptr, g.deg, g.adj2, g.asum, g.qa, g.trec, Y, g.dn_ptr, ZT, l_wave, n_wave,
+                       0, st, g.row_ptr, g.deg, g.adj2, g.asq, g.trec, Y, g.dn_ptr, ZT, l_wave, n_wave,
                        0, mean, inv_std, X, lnN);
   if (g.n_fin_half > 0)
     hipLaunchKernelGGL(k_features<32>, dim3(cap((g.n_fin_half * 32 + 255) / 256, 1 << 20)),
-                       dim3(256), 0, st, g.row_ptr, g.deg, g.adj2, g.asum, g.qa, g.trec, Y, g.dn_ptr, ZT,
+                       dim3(256), 0, st, g.row_ptr, g.deg, g.adj2, g.asq, g.trec, Y, g.dn_ptr, ZT,
                        l_half, g.n_fin_half, 0, mean, inv_std, X, lnN);
   return hipGetLastError();
 }

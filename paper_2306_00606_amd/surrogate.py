@@ -66,33 +66,40 @@ def spearman(a, b):
     return float(spearmanr(a, b).correlation)
 
 
+def _median_event_ms(fn, reps: int = 10) -> float:
+    """Median over `reps` calls of fn, each timed with HIP events on the
+    current stream (the library's calls run on it), after one warm-up call."""
+    import torch
+
+    fn()
+    times = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        b.synchronize()
+        times.append(a.elapsed_time(b))
+    return float(np.median(times))
+
+
 def evaluate(sur: efgpu.Surrogate, graph: efgpu.Graph, exact=None):
     """Spearman and top-1% overlap of the surrogate and of the non-learned
-    proxies ln N(s) and degree, against exact EF; and the speed of each."""
+    proxies ln N(s) and degree, against exact EF; and the time of each (median
+    of 10 event-timed calls, device outputs)."""
     import torch
 
     dev = torch.device("cuda:0")
     ef_d = torch.empty(graph.n, dtype=torch.float64, device=dev)
     D_d = torch.empty(graph.n, dtype=torch.int64, device=dev)
     N_d = torch.empty(graph.n, dtype=torch.int64, device=dev)
-    graph.compute(algo="cluster", prec="fp32c", out=(ef_d, D_d, N_d))  # warm
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    graph.compute(algo="cluster", prec="fp32c", out=(ef_d, D_d, N_d))
-    torch.cuda.synchronize()
-    t_exact = time.perf_counter() - t0
+    t_exact = 1e-3 * _median_event_ms(
+        lambda: graph.compute(algo="cluster", prec="fp32c", out=(ef_d, D_d, N_d)))
     if exact is None:
         exact = ef_d.cpu().numpy()
-    # timed prediction (features + MLP), device output
+    # prediction (features + MLP), device output
     out = torch.empty(graph.n, dtype=torch.float64, device="cuda:0")
-    sur.predict(graph, out=out)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    reps = 3
-    for _ in range(reps):
-        sur.predict(graph, out=out)
-    torch.cuda.synchronize()
-    t_pred = (time.perf_counter() - t0) / reps
+    t_pred = 1e-3 * _median_event_ms(lambda: sur.predict(graph, out=out))
     pred = out.cpu().numpy()
     X, lnN = graph.features()
     deg = np.expm1(X[:, 0].astype(np.float64))
