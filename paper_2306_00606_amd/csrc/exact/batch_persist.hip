@@ -49,7 +49,7 @@ template <typename T> struct PersistPool {
   };
   static constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
   static constexpr size_t kBytes =
-      cmax(cmax(cmax(sizeof(MidParts<T, 1>), (size_t)BigLds<T>::kBytes),
+      cmax(cmax(cmax(sizeof(MidLds<T, 1>), (size_t)BigLds<T>::kBytes),
                 cmax(sizeof(TriWave), sizeof(TB))),
            sizeof(Pass2));
 };
@@ -123,17 +123,17 @@ __device__ inline void persist_item(const PersistArgs &P, const int4 it, unsigne
     case PI_PAIR_M4:
       for (int64_t gi = 0; gi < (cnt + 3) / 4; ++gi)
         pairs_mid_group<T, 4>(P.row_ptr, P.deg, P.adj2, P.pair[4] + a, cnt, gi, P.R,
-                              *reinterpret_cast<MidParts<T, 4> *>(pool));
+                              *reinterpret_cast<MidLds<T, 4> *>(pool));
       break;
     case PI_PAIR_M2:
       for (int64_t gi = 0; gi < (cnt + 1) / 2; ++gi)
         pairs_mid_group<T, 2>(P.row_ptr, P.deg, P.adj2, P.pair[5] + a, cnt, gi, P.R,
-                              *reinterpret_cast<MidParts<T, 2> *>(pool));
+                              *reinterpret_cast<MidLds<T, 2> *>(pool));
       break;
     case PI_PAIR_M1:
       for (int64_t gi = 0; gi < cnt; ++gi)
         pairs_mid_group<T, 1>(P.row_ptr, P.deg, P.adj2, P.pair[6] + a, cnt, gi, P.R,
-                              *reinterpret_cast<MidParts<T, 1> *>(pool));
+                              *reinterpret_cast<MidLds<T, 1> *>(pool));
       break;
     case PI_PAIR_BIG:
       for (int32_t i = a; i < b; ++i)

@@ -30,6 +30,9 @@
 namespace efi {
 
 constexpr float kNegF = -1.0e9f;
+// a degree past the centre's row, as an integer (converts to kNegF)
+constexpr int32_t kNegI = -1000000000;
+static_assert((float)kNegI == kNegF, "kNegI must convert to kNegF");
 
 // ---------------------------------------------------------------------------
 // wave rotate: lane l receives the value of lane (l + 1) mod 64
@@ -338,51 +341,68 @@ __device__ __forceinline__ T col_degree(const int2 *adj2, int32_t base, int32_t 
 // centre's neighbour list; wavefront w (of the group working on this centre)
 // owns row block blk0 + w. Every thread of the workgroup calls it the same
 // number of times (it holds one workgroup barrier).
-// parts[c][delta][64]: column partials, zeroed by the caller.
+// parts[c][delta][64]: column partials, zeroed by the caller; colk: LDS for
+// the nb x 64 degrees of the blocks (filled here, behind a barrier).
 // On return (after the final barrier), wavefront w's lanes hold in `out` the
 // complete sum for index 64*(blk0+w)+lane over all pairs inside this range.
 // gtab (FP32, rows in ascending degree order, or null): the centre's score
 // table; full off-diagonal tiles whose largest degrees fit read it.
 template <typename T>
 __device__ void diag_super(const int2 *adj2, int32_t base, int32_t k, T kv4, int blk0, int nb,
-                           T (*parts)[9][64], int w, Acc<T> &out,
+                           T (*parts)[9][64], int w, Acc<T> &out, int32_t *colk,
                            const float *gtab = nullptr) {
   const int lane = threadIdx.x & 63;
-  if (w < nb) {
-    const int32_t p = 64 * (blk0 + w) + lane;
-    const bool rvalid = p < k;
-    const T kp = rvalid ? (T)adj2[base + p].y : T(0);
+  const int ws = __builtin_amdgcn_readfirstlane(w);
+  const int32_t p = 64 * (blk0 + ws) + lane;
+  const bool rvalid = ws < nb && p < k;
+  const int32_t kpi = rvalid ? adj2[base + p].y : kNegI;
+  // the row degrees of this block of blocks are also its column degrees
+  if (ws < nb) colk[64 * ws + lane] = kpi;
+  __syncthreads();
+  if (ws < nb) {
+    const T kp = rvalid ? (T)kpi : T(0);
     const T cp = rvalid ? kv4 + kp : (T)kNegF;
     const int half = nb >> 1;
     const bool ragged = (k & 63) != 0;
+    // full column blocks 0 .. nfit-1 fit the table with this row block (the
+    // rows of a big centre ascend in degree, so those blocks are a prefix)
+    int nfit = 0;
+    if (gtab) {
+      const int32_t kp_max = __builtin_amdgcn_readlane(kpi, 63);
+      bool fit = false;
+      if (lane < nb && 64 * (blk0 + lane + 1) <= k) fit = kp_max + colk[64 * lane + 63] - 2 < kGTab;
+      nfit = __popcll(__ballot(fit));
+    }
+    const int32_t Dt = gtab ? tab_step((rvalid ? kpi : 0) - 2) : 0;
+    const T Dd = cp - rot1(cp);
+    int c = ws;  // column block of round dl: (w + dl) mod nb
     for (int dl = 0; dl <= half; ++dl) {
-      if (dl > 0 && dl == half && (nb & 1) == 0 && w >= half) break;
-      const int c = (w + dl) % nb;
+      if (dl > 0 && dl == half && (nb & 1) == 0 && ws >= half) break;
       T Rt, C;
       if (dl == 0) {
         const T kq = rvalid ? kp : (T)kNegF;
         tile<T, true, true>(cp, kq, Rt, C);
         parts[c][0][(lane + 32) & 63] = C;
       } else {
-        const int32_t q = 64 * (blk0 + c) + lane;
-        const T kq = col_degree<T>(adj2, base, k, q);
-        const bool masked = ragged && (c == nb - 1 || w == nb - 1) && (blk0 + nb) * 64 > k;
+        const int32_t kq = colk[64 * c + lane];
+        const bool masked = ragged && (c == nb - 1 || ws == nb - 1) && (blk0 + nb) * 64 > k;
         if (masked) {
-          tile<T, false, true>(cp, kq, Rt, C);
-        } else if (gtab && __shfl((int32_t)kp, 63, 64) + __shfl((int32_t)kq, 63, 64) - 2 < kGTab) {
-          tile_tab<T>((int32_t)kp - 2, (int32_t)kq, gtab, Rt, C);
+          tile<T, false, true>(cp, (T)kq, Rt, C);
+        } else if (c < nfit) {
+          tile_tab<T>((rvalid ? kpi : 0) - 2, kq, Dt, gtab, Rt, C);
         } else {
-          tile<T, false, false>(cp, kq, Rt, C);
+          tile_full<T>(cp, (T)kq, Dd, Rt, C);
         }
         parts[c][dl][(lane + 63) & 63] = C;
       }
       out.add(Rt);
+      c = c + 1 == nb ? 0 : c + 1;
     }
   }
   __syncthreads();
-  if (w < nb) {
+  if (ws < nb) {
     const int half = nb >> 1;
-    for (int dl = 0; dl <= half; ++dl) out.add(parts[w][dl][lane]);
+    for (int dl = 0; dl <= half; ++dl) out.add(parts[ws][dl][lane]);
   }
 }
 
@@ -395,8 +415,10 @@ __device__ __forceinline__ void zero_parts(T *p, int count) {
 // mid centres (64 < k <= 1024): G centres per 16-wavefront workgroup, 16/G
 // wavefronts each (G = 4, 2, 1 for up to 4, 8, 16 blocks of 64 neighbours)
 // ---------------------------------------------------------------------------
-template <typename T, int G>
-using MidParts = T[G][kBlocksPerSuper / G][9][64];
+template <typename T, int G> struct MidLds {
+  T parts[G][kBlocksPerSuper / G][9][64];
+  int32_t colk[kBlocksPerSuper * 64];  // each group's degrees, 64 per wavefront
+};
 
 // centres gi*G .. gi*G+G-1 of the list on a 16-wavefront workgroup (every
 // thread calls it: it holds workgroup barriers)
@@ -406,7 +428,7 @@ __device__ __forceinline__ void pairs_mid_group(const int32_t *__restrict__ row_
                                                 const int2 *__restrict__ adj2,
                                                 const int32_t *__restrict__ list, int64_t count,
                                                 int64_t gi, void *__restrict__ R,
-                                                MidParts<T, G> &parts) {
+                                                MidLds<T, G> &lds) {
   constexpr int WPG = kBlocksPerSuper / G;  // wavefronts per centre
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int grp = w / WPG, wl = w % WPG;
@@ -416,10 +438,11 @@ __device__ __forceinline__ void pairs_mid_group(const int32_t *__restrict__ row_
   const int32_t k = have ? deg[v] : 0;
   const int32_t base = have ? row_ptr[v] : 0;
   const int nb = (k + 63) >> 6;
-  zero_parts(&parts[0][0][0][0], G * WPG * 9 * 64);
+  zero_parts(&lds.parts[0][0][0][0], G * WPG * 9 * 64);
   __syncthreads();
   Acc<T> out;
-  diag_super<T>(adj2, base, k, (T)(k - 4), 0, nb, parts[grp], wl, out);
+  diag_super<T>(adj2, base, k, (T)(k - 4), 0, nb, lds.parts[grp], wl, out,
+                lds.colk + 64 * WPG * grp);
   const int32_t p = 64 * wl + lane;
   if (wl < nb && p < k) out.store(R, base + p);
   __syncthreads();
@@ -431,10 +454,10 @@ __global__ __launch_bounds__(1024) void k_pairs_mid(const int32_t *__restrict__ 
                                                     const int2 *__restrict__ adj2,
                                                     const int32_t *__restrict__ list,
                                                     int64_t count, void *__restrict__ R) {
-  __shared__ MidParts<T, G> parts;
+  __shared__ MidLds<T, G> lds;
   const int64_t ngroups = (count + G - 1) / G;
   for (int64_t gi = blockIdx.x; gi < ngroups; gi += gridDim.x)
-    pairs_mid_group<T, G>(row_ptr, deg, adj2, list, count, gi, R, parts);
+    pairs_mid_group<T, G>(row_ptr, deg, adj2, list, count, gi, R, lds);
 }
 
 // mid centres into their classes (order within a class is not fixed; every
@@ -505,13 +528,10 @@ template <typename T> struct BigLds {
   static constexpr int kDiagBytes = kBlocksPerSuper * 9 * 64 * (int)sizeof(T);
   static constexpr int kColBytes = col_groups_max() * kColWin * 64 * (int)sizeof(T);
   static constexpr int kPartBytes = kDiagBytes > kColBytes ? kDiagBytes : kColBytes;
-  static constexpr int kColDegBytes = kSuper * 4;  // column degrees of an off-diagonal super-tile
+  static constexpr int kColDegBytes = kSuper * 4;  // column degrees of the super-tile
   static constexpr int kBytes = kTabBytes + kPartBytes + kColDegBytes;
 };
 
-// column degree past the centre's row (as a float: kNegF)
-constexpr int32_t kNegI = -1000000000;
-static_assert((float)kNegI == kNegF, "kNegI must convert to kNegF");
 
 // One super-tile on a 16-wavefront workgroup (every thread calls it: it holds
 // workgroup barriers). lds: BigLds<T>::kBytes, the scores of the current
@@ -549,7 +569,9 @@ __device__ __forceinline__ void pairs_big_tile(const int32_t *__restrict__ row_p
     // the rows of a big centre ascend in degree, so its full off-diagonal
     // tiles can read the score table here too
     diag_super<T>(adj2, base, k, kv4, kBlocksPerSuper * P, nbQ,
-                  reinterpret_cast<T(*)[9][64]>(&parts[0][0][0]), w, out, kTab ? gtab : nullptr);
+                  reinterpret_cast<T(*)[9][64]>(&parts[0][0][0]), w, out,
+                  reinterpret_cast<int32_t *>(lds + BigLds<T>::kTabBytes + BigLds<T>::kPartBytes),
+                  kTab ? gtab : nullptr);
     if (w < nbQ) out.store(rec, rbase + 64 * w + lane);
   } else {
     // P < Q: all 16 row blocks of P are full
