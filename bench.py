@@ -540,7 +540,9 @@ def main():
                     "avg_launch_ms": st["t_pairs_big_ms"], "counters": counters,
                     "scope_ops": {"ops_per_cluster": OPS_PER_CLUSTER,
                                   "achieved_tops": w_launch * OPS_PER_CLUSTER / t_launch / 1e12,
-                                  "fp32_vector_peak_tflops": FP32_VECTOR_PEAK_FLOPS / 1e12}}
+                                  "fp32_vector_peak_tflops": FP32_VECTOR_PEAK_FLOPS / 1e12,
+                                  "frac": w_launch * OPS_PER_CLUSTER / t_launch
+                                  / FP32_VECTOR_PEAK_FLOPS}}
     else:
         roofline = None
     # the headline step's outputs, before any other section reuses the device
