@@ -411,14 +411,79 @@ __device__ __forceinline__ void zero_parts(T *p, int count) {
   for (int i = threadIdx.x; i < count; i += blockDim.x) p[i] = T(0);
 }
 
+// The block pairs of diag_super dealt evenly over the nw wavefronts of a
+// group instead of one row block per wavefront: job (dl, r) is row block r
+// against column block (r + dl) mod nb, the jobs in dl-major order (the
+// dl = 0 jobs are the half-cost diagonal tiles), job j on wavefront j mod nw.
+// Row partials go to rowp[r][dl] and column partials to parts[c][dl], one
+// writer each; after the barrier wavefront r sums both for its block in a
+// fixed order. A centre of 10 blocks on 16 wavefronts takes 3.5 tile times
+// instead of 5.5. parts and rowp zeroed by the caller; colk as for
+// diag_super. No score table (the rows of mid centres are not in degree
+// order).
+template <typename T>
+__device__ void diag_super_dealt(const int2 *adj2, int32_t base, int32_t k, T kv4, int nb,
+                                 T (*parts)[9][64], T (*rowp)[9][64], int w, int nw,
+                                 Acc<T> &out, int32_t *colk) {
+  const int lane = threadIdx.x & 63;
+  const int ws = __builtin_amdgcn_readfirstlane(w);
+  if (ws < nb) {
+    const int32_t p = 64 * ws + lane;
+    colk[64 * ws + lane] = p < k ? adj2[base + p].y : kNegI;
+  }
+  __syncthreads();
+  const int half = nb >> 1;
+  const bool ragged = (k & 63) != 0;
+  // the even case's last round has only rows 0 .. half-1: the jobs it skips
+  // are the last ones of the order
+  const int njobs = nb * (half + 1) - ((nb & 1) == 0 ? half : 0);
+  for (int j = ws; j < njobs; j += nw) {
+    const int dl = j / nb, r = j - dl * nb;
+    const int c = r + dl < nb ? r + dl : r + dl - nb;
+    const int32_t kpi = colk[64 * r + lane];
+    const bool rvalid = 64 * r + lane < k;
+    const T kp = rvalid ? (T)kpi : T(0);
+    const T cp = rvalid ? kv4 + kp : (T)kNegF;
+    T Rt, C;
+    if (dl == 0) {
+      tile<T, true, true>(cp, rvalid ? kp : (T)kNegF, Rt, C);
+      parts[c][0][(lane + 32) & 63] = C;
+    } else {
+      const T kq = (T)colk[64 * c + lane];
+      if (ragged && (c == nb - 1 || r == nb - 1)) tile<T, false, true>(cp, kq, Rt, C);
+      else tile_full<T>(cp, kq, cp - rot1(cp), Rt, C);
+      parts[c][dl][(lane + 63) & 63] = C;
+    }
+    rowp[r][dl][lane] = Rt;
+  }
+  __syncthreads();
+  if (ws < nb) {
+    for (int dl = 0; dl <= half; ++dl) {
+      out.add(rowp[ws][dl][lane]);
+      out.add(parts[ws][dl][lane]);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // mid centres (64 < k <= 1024): G centres per 16-wavefront workgroup, 16/G
 // wavefronts each (G = 4, 2, 1 for up to 4, 8, 16 blocks of 64 neighbours)
 // ---------------------------------------------------------------------------
-template <typename T, int G> struct MidLds {
+template <typename T, int G> struct MidLdsPlain {
   T parts[G][kBlocksPerSuper / G][9][64];
   int32_t colk[kBlocksPerSuper * 64];  // each group's degrees, 64 per wavefront
 };
+// FP32: the block pairs dealt over the group's wavefronts (row partials in
+// LDS, 76 KB in all, two workgroups per CU); FP64 keeps one row block per
+// wavefront (the row partials would take its LDS to 148 KB)
+template <typename T, int G> struct MidLdsDealt {
+  T parts[G][kBlocksPerSuper / G][9][64];
+  T rowp[G][kBlocksPerSuper / G][9][64];
+  int32_t colk[kBlocksPerSuper * 64];
+};
+template <typename T> constexpr bool kMidDealt = std::is_same<T, float>::value;
+template <typename T, int G>
+using MidLds = typename std::conditional<kMidDealt<T>, MidLdsDealt<T, G>, MidLdsPlain<T, G>>::type;
 
 // centres gi*G .. gi*G+G-1 of the list on a 16-wavefront workgroup (every
 // thread calls it: it holds workgroup barriers)
@@ -439,10 +504,15 @@ __device__ __forceinline__ void pairs_mid_group(const int32_t *__restrict__ row_
   const int32_t base = have ? row_ptr[v] : 0;
   const int nb = (k + 63) >> 6;
   zero_parts(&lds.parts[0][0][0][0], G * WPG * 9 * 64);
+  if constexpr (kMidDealt<T>) zero_parts(&lds.rowp[0][0][0][0], G * WPG * 9 * 64);
   __syncthreads();
   Acc<T> out;
-  diag_super<T>(adj2, base, k, (T)(k - 4), 0, nb, lds.parts[grp], wl, out,
-                lds.colk + 64 * WPG * grp);
+  if constexpr (kMidDealt<T>)
+    diag_super_dealt<T>(adj2, base, k, (T)(k - 4), nb, lds.parts[grp], lds.rowp[grp], wl, WPG,
+                        out, lds.colk + 64 * WPG * grp);
+  else
+    diag_super<T>(adj2, base, k, (T)(k - 4), 0, nb, lds.parts[grp], wl, out,
+                  lds.colk + 64 * WPG * grp);
   const int32_t p = 64 * wl + lane;
   if (wl < nb && p < k) out.store(R, base + p);
   __syncthreads();
