@@ -91,12 +91,26 @@ template <> struct Acc<float> {
     df_add(v, x.x);
     df_add(v, x.y);
   }
+  // a stored sum read and added in two steps (several reads in flight)
+  using Raw = float2;
+  __device__ static Raw load(const void *R, int64_t i) {
+    return reinterpret_cast<const float2 *>(R)[i];
+  }
+  __device__ void add_raw(Raw x) {
+    df_add(v, x.x);
+    df_add(v, x.y);
+  }
 };
 template <> struct Acc<double> {
   double v = 0.0;
   __device__ void add(double x) { v += x; }
   __device__ void store(void *R, int64_t i) const { reinterpret_cast<double *>(R)[i] = v; }
   __device__ void add_stored(const void *R, int64_t i) { v += reinterpret_cast<const double *>(R)[i]; }
+  using Raw = double;
+  __device__ static Raw load(const void *R, int64_t i) {
+    return reinterpret_cast<const double *>(R)[i];
+  }
+  __device__ void add_raw(Raw x) { v += x; }
 };
 
 // Full 64x64 tile (no masking) with the row step D = cp - rot(cp) given, so
@@ -883,18 +897,39 @@ __device__ __forceinline__ void arc_reduce_item(const int32_t *__restrict__ row_
   const BigCentre bc = big[item.x];
   const int b = item.y;
   const int32_t k = deg[bc.v], base = row_ptr[bc.v], ns = bc.ns;
+  // entry j of the row part of (b, Q) and of the column part of (P, b)
+  const int64_t row0 = (bc.rec_base + (int64_t)b * ns - (int64_t)b * (b - 1) / 2 - b) * kRecEntries;
+  auto rowi = [&](int Q, int j) { return row0 + (int64_t)Q * kRecEntries + j; };
+  auto coli = [&](int P, int j) {
+    return (bc.rec_base + (int64_t)P * ns - (int64_t)P * (P - 1) / 2 + (b - P)) * kRecEntries +
+           kSuper + j;
+  };
+  using Raw = typename Acc<T>::Raw;
   for (int j = threadIdx.x; j < kSuper; j += blockDim.x) {
     const int32_t p = kSuper * b + j;
     if (p >= k) break;
     Acc<T> a;
-    for (int Q = b; Q < ns; ++Q) {
-      const int64_t t = bc.rec_base + (int64_t)b * ns - (int64_t)b * (b - 1) / 2 + (Q - b);
-      a.add_stored(rec, t * kRecEntries + j);
+    // four reads in flight, added in the same order
+    int Q = b;
+    for (; Q + 3 < ns; Q += 4) {
+      const Raw r0 = Acc<T>::load(rec, rowi(Q, j)), r1 = Acc<T>::load(rec, rowi(Q + 1, j)),
+                r2 = Acc<T>::load(rec, rowi(Q + 2, j)), r3 = Acc<T>::load(rec, rowi(Q + 3, j));
+      a.add_raw(r0);
+      a.add_raw(r1);
+      a.add_raw(r2);
+      a.add_raw(r3);
     }
-    for (int P = 0; P < b; ++P) {
-      const int64_t t = bc.rec_base + (int64_t)P * ns - (int64_t)P * (P - 1) / 2 + (b - P);
-      a.add_stored(rec, t * kRecEntries + kSuper + j);
+    for (; Q < ns; ++Q) a.add_stored(rec, rowi(Q, j));
+    int P = 0;
+    for (; P + 3 < b; P += 4) {
+      const Raw r0 = Acc<T>::load(rec, coli(P, j)), r1 = Acc<T>::load(rec, coli(P + 1, j)),
+                r2 = Acc<T>::load(rec, coli(P + 2, j)), r3 = Acc<T>::load(rec, coli(P + 3, j));
+      a.add_raw(r0);
+      a.add_raw(r1);
+      a.add_raw(r2);
+      a.add_raw(r3);
     }
+    for (; P < b; ++P) a.add_stored(rec, coli(P, j));
     a.store(R, base + adjs[base + p].x);  // sorted position -> arc of the row
   }
 }
