@@ -923,9 +923,27 @@ extern "C" ef_status ef_compute(ef_graph *h, ef_algo algo, ef_prec prec, const i
     }
   }
 
+  // whole-graph calls bin every node with the graph's thresholds: their
+  // lists are kept and reused (not while the stream is being captured, so
+  // that a captured graph bins by itself)
+  const int32_t *centres = per_seed ? d_useeds : nullptr;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cap) != hipSuccess) {
+    (void)hipGetLastError();
+    cap = hipStreamCaptureStatusActive;
+  }
+  const bool whole = centres == nullptr && cap == hipStreamCaptureStatusNone;
+  const bool reuse = whole && g.bins_kept && g.bins_buf == g.ws[WS_BINS].p &&
+                     g.bins_thr.t8 == b.thr.t8 && g.bins_thr.t16 == b.thr.t16 &&
+                     g.bins_thr.t32 == b.thr.t32;
   prof.mark(0);
-  e = launch_bin_centres(g, per_seed ? d_useeds : nullptr, n_work, b, st);
-  if (e != hipSuccess) return hip_status(e, "binning");
+  if (!reuse) {
+    e = launch_bin_centres(g, centres, n_work, b, st);
+    if (e != hipSuccess) return hip_status(e, "binning");
+  }
+  g.bins_kept = whole;
+  g.bins_thr = b.thr;
+  g.bins_buf = g.ws[WS_BINS].p;
   prof.mark(1);
   e = launch_pairs(g, prec, b, g.ws[WS_R].p, g.ws[WS_REC].p, st, prof.ev(2), prof.ev(3),
                    prof.ev(4), algo == EF_ALGO_CLUSTER_AGG ? b.agg_done : nullptr);

@@ -190,6 +190,12 @@ struct Graph {
   int64_t all_midc[3] = {0, 0, 0};
   int64_t all_small_deg[kSmallMax + 1] = {};  // centres of each degree <= 64
   SmallThr thr;                               // current small-bin thresholds
+  // the work lists of a whole-graph call depend only on the graph and thr:
+  // built on first use and kept in the work-list buffer (bins_buf) until a
+  // call bins other centres, other thresholds, or under stream capture
+  bool bins_kept = false;
+  SmallThr bins_thr;
+  void *bins_buf = nullptr;
   int64_t all_pairs_small = 0, all_pairs_mid = 0, all_pairs_big = 0;
   int64_t all_sblocks = 0;  // sum of super-blocks over big centres
   int64_t owned_bytes = 0;  // device bytes held by this handle
