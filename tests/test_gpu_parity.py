@@ -213,6 +213,33 @@ def test_selected_seeds_with_duplicates():
             assert_parity(ef, D, N, oN, oD, oE, prec, "selected seeds")
 
 
+def test_work_lists_kept_across_calls():
+    """A handle keeps the pair loop's work lists of a whole-graph call; calls
+    that bin a seed subset in between, and either formulation or precision
+    after them, still give the results of a fresh handle (whole-graph
+    cluster-centric calls bit for bit)."""
+    rp, ci = hub_graph()
+    seeds = np.array([0, 1, 5, 17, 3001], np.int32)
+    with efgpu.Graph(rp, ci) as fresh:
+        ref32 = fresh.compute(algo="cluster", prec="fp32c")
+    with efgpu.Graph(rp, ci) as fresh:
+        ref64 = fresh.compute(algo="cluster", prec="fp64")
+    with efgpu.Graph(rp, ci) as g:
+        runs = [("cluster", "fp32c", None), ("cluster", "fp32c", seeds), ("cluster", "fp32c", None),
+                ("per_seed", "fp64", None), ("cluster", "fp64", None), ("cluster", "fp64", seeds),
+                ("cluster", "fp32c", None)]
+        for algo, prec, sd in runs:
+            got = g.compute(algo=algo, prec=prec, seeds=sd)
+            ref = ref32 if prec == "fp32c" else ref64
+            idx = slice(None) if sd is None else seeds
+            assert np.array_equal(got[1], ref[1][idx]) and np.array_equal(got[2], ref[2][idx])
+            if algo == "cluster" and sd is None:
+                assert np.array_equal(got[0], ref[0]), (algo, prec)
+            else:  # a seed subset runs the per-seed formulation
+                tol = 1e-5 if prec == "fp32c" else 1e-9
+                assert np.allclose(got[0], ref[0][idx], rtol=tol, atol=0), (algo, prec)
+
+
 def test_per_seed_equals_cluster_bitexact_integers_and_determinism():
     rp, ci = gen.rmat(14, 12, 21, perm_seed=4)
     with efgpu.Graph(rp, ci) as g:
