@@ -382,14 +382,16 @@ ef_status ef_surrogate_save(ef_surrogate *s, const char *path);
 ef_status ef_surrogate_load(ef_surrogate *s, const char *path);
 
 /* The 16 raw per-node features (row-major n x 16) and ln N(s) per node:
- * ln(1+k), ln(1+A), ln(1+B), ln(1+T), clustering, ln(1+A-k), ln(1+N),
- * ln(1+D), ln(D/N), max/min/mean/std of ln(neighbour degree), ln(1+Q),
- * share of degree-1 neighbours, ln(1+r); A, B = sums of neighbour degrees
- * and of their squares, T = triangles, Q = sum over neighbours of their
- * neighbour-degree sums, N and D in closed form, r = max(0, E2 N / D^2 - 1)
- * the relative variance of the cluster degrees, E2 = the sum of the squared
- * cluster degrees over the N event sequences (closed form per arc; triangle
- * clusters without their -2). To second order in r, ln N - EF = r / 2.
+ * ln(1+k), ln(1+A), ln(1+B), asinh(m3), asinh(m4), ln(1+A-k), ln(1+N),
+ * ln(1+D'), ln(D'/N), max/min/mean/std of ln(neighbour degree), ln(1+Q),
+ * share of degree-1 neighbours, ln(1+max(m2, 0)); A, B = sums of neighbour
+ * degrees and of their squares, Q = sum over neighbours of their
+ * neighbour-degree sums, N in closed form, D' the sum of the cluster degrees
+ * taken without the triangle term, and m_j = E[x^j] over the node's N event
+ * sequences with x = d / (D'/N) - 1 (sums of d^2, d^3, d^4 in closed form
+ * per arc, triangle clusters without their -2). ln N - EF =
+ * m2/2 - m3/6 + m4/12 - ... when the triangle terms are left out. No
+ * triangle pass is run: a call costs the arcs' neighbour-sum gathers.
  * EF_OUT_DEVICE: X and lnN are device pointers. */
 ef_status ef_features(ef_graph *g, float *X, float *lnN, uint32_t flags, void *hip_stream);
 

@@ -159,7 +159,7 @@ ef_status ef_graph_free(ef_graph *h) {
     (void)hipFree(g.row_ptr);
     (void)hipFree(g.col_idx);
   }
-  void *arrays[] = {g.deg, g.src, g.rev, g.adj2, g.adjs, g.asum, g.qa, g.asq, g.up_ptr, g.up_col, g.trec,
+  void *arrays[] = {g.deg, g.src, g.rev, g.adj2, g.adjs, g.asum, g.qa, g.nbm, g.up_ptr, g.up_col, g.trec,
                     g.up_deg, g.dn_ptr, g.dn, g.tri_zero, g.j3_seeds, g.j3_off,
                     g.tri_rec0, g.tri_recL, g.tri_list[0], g.tri_list[1], g.tri_list[2], g.tri_list[3],
                     g.tri_recB[1], g.tri_recB[2], g.fin_list,
@@ -303,7 +303,7 @@ ef_status graph_load(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32
   ALLOC(g.adj2, sizeof(int2) * NNZ, "adj2");
   ALLOC(g.asum, sizeof(int64_t) * std::max<size_t>(n, 1), "asum");
   ALLOC(g.qa, sizeof(longlong2) * std::max<size_t>(n, 1), "qa");
-  ALLOC(g.asq, sizeof(longlong2) * std::max<size_t>(n, 1), "asq");
+  ALLOC(g.nbm, sizeof(NbrMoments) * std::max<size_t>(n, 1), "neighbour degree moments");
   ALLOC(g.up_ptr, sizeof(int32_t) * N1, "up_ptr");
   ALLOC(g.up_col, sizeof(int32_t) * NUP, "up_col");
   ALLOC(g.up_deg, sizeof(int32_t) * NUP, "up_deg");

@@ -120,6 +120,13 @@ struct alignas(16) TriSlot {
 };
 constexpr double kTriFix = 68719476736.0;  // 2^36
 
+// sums over a node's neighbours b of k_b, k_b^2 (exact) and k_b^3, k_b^4
+// (FP64: they can pass 2^63)
+struct NbrMoments {
+  long long s1, s2;
+  double s3, s4;
+};
+
 struct Graph {
   int dev = 0;
   int32_t n = 0;
@@ -137,8 +144,8 @@ struct Graph {
                                // when no centre has more than kSuper neighbours
   int64_t *asum = nullptr;     // sum of neighbour degrees per node
   longlong2 *qa = nullptr;     // per node: {sum of squared neighbour degrees, sum of neighbours' asum}
-  longlong2 *asq = nullptr;    // per node: {asum, sum of squared neighbour degrees}, one gather
-                               // per arc for the surrogate's features
+  NbrMoments *nbm = nullptr;   // per node: sums of its neighbours' degrees to the powers 1..4,
+                               // one 32-byte gather per arc for the surrogate's features
   int32_t *up_ptr = nullptr;   // degree-oriented half adjacency: u -> {w : rank(w) > rank(u)}
   int32_t *up_col = nullptr;   // each up(u) in rank order
   int32_t *up_deg = nullptr;   // degree of every up_col entry
@@ -302,8 +309,6 @@ hipError_t launch_pairs(const Graph &g, ef_prec prec, const Bins &b, void *R, vo
 // the up-arc slot, lower end at nup + slot), Z / ZT per node.
 hipError_t launch_triangles(const Graph &g, ef_prec prec, TriSlot *Y, void *Z, int64_t *ZT,
                             hipStream_t st);
-// triangle counts only: the counts of Y (sums zero) and ZT, no Z
-hipError_t launch_triangles_count(const Graph &g, TriSlot *Y, int64_t *ZT, hipStream_t st);
 
 // per-node sums + Eq. 1 (cluster-centric); per-node flag bytes in fl.
 hipError_t launch_finalize_cluster(const Graph &g, ef_prec prec, const void *R, const TriSlot *Y,

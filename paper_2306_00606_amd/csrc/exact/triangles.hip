@@ -81,31 +81,6 @@ template <> struct Credit<double> {
   }
 };
 
-// Count-only pass (triangle counts per node and up-arc, no score terms): a
-// tag type whose sums, deltas and credits reduce to counting.
-struct TriCount {};
-struct NoSum {};
-__device__ __forceinline__ NoSum wave_sum(NoSum x) { return x; }
-__device__ __forceinline__ void acc_merge(NoSum &, NoSum) {}
-template <> struct SumT<TriCount> {
-  using type = NoSum;
-  __device__ static void add_term(NoSum &, TriCount) {}
-  __device__ static void store(const NoSum &, void *, int64_t) {}
-};
-template <> __device__ __forceinline__ TriCount tri_delta<TriCount>(int32_t) { return TriCount{}; }
-__device__ __forceinline__ long long to_fix(TriCount) { return 0; }
-template <> struct Credit<TriCount> {
-  static constexpr bool kPacked = true;
-  __device__ static void add(unsigned long long *acc, int32_t *, int32_t slot, TriCount) {
-    atomicAdd(&acc[slot], 1ull << 44);
-  }
-  __device__ static void load(const unsigned long long *acc, const int32_t *, int32_t slot,
-                              long long &y, int32_t &yt) {
-    y = 0;
-    yt = (int32_t)(acc[slot] >> 44);
-  }
-};
-
 // In FP32C the credit of w (the middle node) is the sum of the credits of
 // the x's: it is taken from the exact x slots when they are flushed, instead
 // of a compensated sum per hit.
@@ -833,11 +808,6 @@ template <> struct LaneSlot<double> {
   }
   __device__ TriSlot slot() const { return TriSlot{y, t, 0}; }
 };
-template <> struct LaneSlot<TriCount> {
-  int32_t t = 0;
-  __device__ void add(TriCount) { ++t; }
-  __device__ TriSlot slot() const { return TriSlot{0, t, 0}; }
-};
 
 template <typename T, int M>
 __device__ __forceinline__ void tri_lane_node(const TriArgs &A, const int4 rc) {
@@ -936,10 +906,6 @@ static hipError_t tri_impl(const Graph &g, TriSlot *Y, void *Z, int64_t *ZT, hip
     hipLaunchKernelGGL(k_tri_long<T>, dim3(cap_blocks_tri(counts[3], 1 << 20)), dim3(64), 0, st, A,
                        g.tri_list[3], counts[3]);
   return hipGetLastError();
-}
-
-hipError_t launch_triangles_count(const Graph &g, TriSlot *Y, int64_t *ZT, hipStream_t st) {
-  return tri_impl<TriCount>(g, Y, nullptr, ZT, st);
 }
 
 hipError_t launch_triangles(const Graph &g, ef_prec prec, TriSlot *Y, void *Z, int64_t *ZT,

@@ -253,24 +253,30 @@ __global__ void k_dn_work(const int32_t *__restrict__ dn_ptr, const int4 *__rest
 // the node in closed form).
 __global__ void k_qa(const int32_t *__restrict__ row_ptr, const int2 *__restrict__ adj2,
                      const int64_t *__restrict__ asum, int32_t n, longlong2 *__restrict__ qa,
-                     longlong2 *__restrict__ asq) {
+                     NbrMoments *__restrict__ nbm) {
   const int lane = threadIdx.x & 63;
   const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   for (int64_t v = wave; v < n; v += nwaves) {
     int64_t q = 0, a2 = 0;
+    double c3 = 0.0, c4 = 0.0;
     for (int32_t e = row_ptr[v] + lane; e < row_ptr[v + 1]; e += 64) {
       const int2 ad = adj2[e];
       q += (int64_t)ad.y * ad.y;
       a2 += asum[ad.x];
+      const double kb = (double)ad.y, kb2 = kb * kb;
+      c3 += kb2 * kb;
+      c4 += kb2 * kb2;
     }
     for (int off = 32; off > 0; off >>= 1) {
       q += __shfl_xor(q, off, 64);
       a2 += __shfl_xor(a2, off, 64);
+      c3 += __shfl_xor(c3, off, 64);
+      c4 += __shfl_xor(c4, off, 64);
     }
     if (lane == 0) {
       qa[v] = make_longlong2(q, a2);
-      asq[v] = make_longlong2(asum[v], q);
+      nbm[v] = NbrMoments{asum[v], q, c3, c4};
     }
   }
 }
@@ -464,7 +470,7 @@ hipError_t launch_graph_prep(Graph &g, int32_t *tmp, int64_t *work, bool &not_sy
     hipLaunchKernelGGL(k_asum, dim3(grid_for((int64_t)g.n * 64, T)), dim3(T), 0, st,
                        g.row_ptr, g.adj2, g.n, g.asum);
     hipLaunchKernelGGL(k_qa, dim3(grid_for((int64_t)g.n * 64, T)), dim3(T), 0, st, g.row_ptr,
-                       g.adj2, g.asum, g.n, g.qa, g.asq);
+                       g.adj2, g.asum, g.n, g.qa, g.nbm);
   } else {
     hipLaunchKernelGGL(k_up_fill, dim3(grid_for(g.n + 1, T)), dim3(T), 0, st, g.row_ptr,
                        g.col_idx, g.rev, tmp, tmp, g.n, (int64_t)0, g.up_ptr, g.up_col,
@@ -474,7 +480,7 @@ hipError_t launch_graph_prep(Graph &g, int32_t *tmp, int64_t *work, bool &not_sy
                        g.dn_ptr);
     (void)hipMemsetAsync(g.asum, 0, sizeof(int64_t) * (size_t)g.n, st);
     (void)hipMemsetAsync(g.qa, 0, sizeof(longlong2) * (size_t)g.n, st);
-    (void)hipMemsetAsync(g.asq, 0, sizeof(longlong2) * (size_t)g.n, st);
+    (void)hipMemsetAsync(g.nbm, 0, sizeof(NbrMoments) * (size_t)g.n, st);
     (void)hipMemsetAsync(work, 0, sizeof(int64_t) * (size_t)g.n, st);
   }
   return hipGetLastError();

@@ -50,50 +50,63 @@ __device__ __forceinline__ float bf(float x) { return (float)(__bf16)x; }
 // features: G lanes per node (8 for degree <= kFinGroupMax, 32 for degree <=
 // kFinHalfMax, 64 up to kFinBlockMin), one workgroup per hub
 // ---------------------------------------------------------------------------
-// Per arc (s, a), with c = k_s + k_a - 4, the clusters through a have degree
-// c + k_b for b in N(s) \ {a} (stars) and b in N(a) \ {s} (paths), so their
-// squared degrees sum to
-//   (k_s + k_a - 2) c^2 + 2 c (A_s - k_a + A_a - k_s) + (B_s - k_a^2 + B_a - k_s^2)
-// with A = sum of neighbour degrees, B = sum of their squares (triangle
-// clusters counted without their -2). With the mean cluster degree D/N, the
-// relative variance r = E2 N / D^2 - 1 gives ln N - EF = r/2 to second order.
+// Moments of the cluster degrees. Per arc (s, a), with c = k_s + k_a - 4,
+// the clusters through a have degree c + k_b for the n = k_s + k_a - 2
+// nodes b in N(s) \ {a} (stars) and N(a) \ {s} (paths), so with P_j the
+// sum of k_b^j over those b (from the sums of both nodes' neighbour degrees
+// to the power j, less k_a^j and k_s^j),
+//   sum d^2 = n c^2 + 2 c P_1 + P_2
+//   sum d^3 = n c^3 + 3 c^2 P_1 + 3 c P_2 + P_3
+//   sum d^4 = n c^4 + 4 c^3 P_1 + 6 c^2 P_2 + 4 c P_3 + P_4
+// (triangle clusters taken without their -2). With x = d / mean - 1 over the
+// node's event sequences, ln N - EF = E[(1 + x) ln(1 + x)]
+// = m2 / 2 - m3 / 6 + m4 / 12 - ..., m_j = E[x^j]; the features carry m2,
+// m3 and m4. No triangle pass is needed.
 struct FeatAcc {  // POD (lives in LDS); start from feat_zero()
-  int64_t B, Q, T, c1;
+  int64_t B, Q, c1;
   float mx, mn;
-  double s1, s2, e2;
-  __device__ void add(int2 ad, int64_t sa, int64_t ba, int64_t k, int64_t As, int64_t Bs) {
+  double s1, s2, e2, e3, e4;
+  __device__ void add(int2 ad, const NbrMoments &t, int64_t k, const NbrMoments &own) {
     const int64_t ka = ad.y;
     B += ka * ka;
-    Q += sa;
+    Q += t.s1;
     c1 += ka == 1;
     const float lk = logf((float)ka);
     mx = fmaxf(mx, lk);
     mn = fminf(mn, lk);
     s1 += lk;
     s2 += (double)lk * lk;
-    const double c = (double)(k + ka - 4);
-    e2 += (double)(k + ka - 2) * c * c + 2.0 * c * (double)(As - ka + sa - k) +
-          (double)(Bs - ka * ka + ba - k * k);
+    const double n = (double)(k + ka - 2), c = (double)(k + ka - 4);
+    const double dk = (double)k, da = (double)ka, dk2 = dk * dk, da2 = da * da;
+    const double p1 = (double)(own.s1 - ka + t.s1 - k);
+    const double p2 = (double)(own.s2 - ka * ka + t.s2 - k * k);
+    const double p3 = own.s3 - da2 * da + t.s3 - dk2 * dk;
+    const double p4 = own.s4 - da2 * da2 + t.s4 - dk2 * dk2;
+    const double c2 = c * c;
+    e2 += n * c2 + 2.0 * c * p1 + p2;
+    e3 += n * c2 * c + 3.0 * c2 * p1 + 3.0 * c * p2 + p3;
+    e4 += n * c2 * c2 + 4.0 * c2 * c * p1 + 6.0 * c2 * p2 + 4.0 * c * p3 + p4;
   }
   __device__ void merge(const FeatAcc &o) {
     B += o.B;
     Q += o.Q;
-    T += o.T;
     c1 += o.c1;
     mx = fmaxf(mx, o.mx);
     mn = fminf(mn, o.mn);
     s1 += o.s1;
     s2 += o.s2;
     e2 += o.e2;
+    e3 += o.e3;
+    e4 += o.e4;
   }
 };
 
 __device__ __forceinline__ FeatAcc feat_zero() {
   FeatAcc a;
-  a.B = a.Q = a.T = a.c1 = 0;
+  a.B = a.Q = a.c1 = 0;
   a.mx = -1e30f;
   a.mn = 1e30f;
-  a.s1 = a.s2 = a.e2 = 0.0;
+  a.s1 = a.s2 = a.e2 = a.e3 = a.e4 = 0.0;
   return a;
 }
 
@@ -102,52 +115,54 @@ template <int G> __device__ __forceinline__ FeatAcc feat_reduce(FeatAcc a) {
     FeatAcc o = feat_zero();
     o.B = __shfl_xor(a.B, off, G);
     o.Q = __shfl_xor(a.Q, off, G);
-    o.T = __shfl_xor(a.T, off, G);
     o.c1 = __shfl_xor(a.c1, off, G);
     o.mx = __shfl_xor(a.mx, off, G);
     o.mn = __shfl_xor(a.mn, off, G);
     o.s1 = __shfl_xor(a.s1, off, G);
     o.s2 = __shfl_xor(a.s2, off, G);
     o.e2 = __shfl_xor(a.e2, off, G);
+    o.e3 = __shfl_xor(a.e3, off, G);
+    o.e4 = __shfl_xor(a.e4, off, G);
     a.merge(o);
   }
   return a;
 }
 
-// arcs first, first + stride, ... of node v (degree k, neighbour-degree sum As
-// and sum of squares Bs); asq: per node {neighbour-degree sum, sum of squares}
+// arcs first, first + stride, ... of node v (degree k, own sums own)
 __device__ __forceinline__ void feat_arcs(const int2 *__restrict__ adj2,
-                                          const longlong2 *__restrict__ asq,
-                                          const int32_t *__restrict__ trec,
-                                          const TriSlot *__restrict__ Y, int32_t k, int32_t base,
-                                          int64_t As, int64_t Bs, int32_t first, int32_t stride,
-                                          FeatAcc &f) {
+                                          const NbrMoments *__restrict__ nbm, int32_t k,
+                                          int32_t base, const NbrMoments &own, int32_t first,
+                                          int32_t stride, FeatAcc &f) {
   for (int32_t e = base + first; e < base + k; e += stride) {
     const int2 ad = adj2[e];
-    const longlong2 t = asq[ad.x];
-    f.add(ad, t.x, t.y, k, As, Bs);
-    // triangles credited to the node through this edge
-    const int32_t r = trec[e];
-    if (r >= 0) f.T += Y[r].t;
+    f.add(ad, nbm[ad.x], k, own);
   }
 }
 
-// ZT[v] is written by the triangle walk of nodes with segments (has_z)
-__device__ void feat_store(int32_t v, int32_t k, int64_t A, FeatAcc a, bool has_z,
-                           const int64_t *__restrict__ ZT, const float *__restrict__ mean,
-                           const float *__restrict__ inv_std, float *__restrict__ X,
-                           float *__restrict__ lnN) {
-  const int64_t T = a.T + (has_z ? ZT[v] : 0);
+__device__ void feat_store(int32_t v, int32_t k, int64_t A, FeatAcc a,
+                           const float *__restrict__ mean, const float *__restrict__ inv_std,
+                           float *__restrict__ X, float *__restrict__ lnN) {
   const int64_t kk = k, B = a.B, Q = a.Q;
   const int64_t Ns = kk * kk - 2 * kk + A;
+  // D without the triangle term
   const int64_t Ds = kk * (kk - 1) * (kk - 4) + 2 * (kk - 1) * A + (kk - 4) * (A - kk) +
-                     (B - A) + (Q - kk * kk) - 8 * T;
+                     (B - A) + (Q - kk * kk);
+  // raw moments of d / mean, then the central moments of x = d / mean - 1
+  double m2 = 0.0, m3 = 0.0, m4 = 0.0;
+  if (Ns > 0 && Ds > 0) {
+    const double q = (double)Ns / (double)Ds;  // 1 / mean
+    const double r2 = a.e2 * q * q / (double)Ns, r3 = a.e3 * q * q * q / (double)Ns,
+                 r4 = a.e4 * q * q * q * q / (double)Ns;
+    m2 = r2 - 1.0;
+    m3 = r3 - 3.0 * r2 + 2.0;
+    m4 = r4 - 4.0 * r3 + 6.0 * r2 - 3.0;
+  }
   float f[kF];
   f[0] = logf(1.0f + (float)kk);
   f[1] = logf(1.0f + (float)A);
   f[2] = logf(1.0f + (float)B);
-  f[3] = logf(1.0f + (float)T);
-  f[4] = kk >= 2 ? (float)(2.0 * (double)T / (double)(kk * (kk - 1))) : 0.0f;
+  f[3] = (float)asinh(m3);
+  f[4] = (float)asinh(m4);
   f[5] = logf(1.0f + (float)(A - kk));
   f[6] = logf(1.0f + (float)Ns);
   f[7] = logf(1.0f + (float)Ds);
@@ -159,10 +174,7 @@ __device__ void feat_store(int32_t v, int32_t k, int64_t A, FeatAcc a, bool has_
   f[12] = k > 0 ? (float)sqrt(fmax(a.s2 / k - mean_lk * mean_lk, 0.0)) : 0.0f;
   f[13] = logf(1.0f + (float)Q);
   f[14] = k > 0 ? (float)a.c1 / (float)k : 0.0f;
-  const double rv = (Ns > 0 && Ds > 0)
-                        ? a.e2 * (double)Ns / ((double)Ds * (double)Ds) - 1.0
-                        : 0.0;
-  f[15] = (float)log1p(fmax(rv, 0.0));
+  f[15] = (float)log1p(fmax(m2, 0.0));
   float *dst = X + (int64_t)v * kF;
 #pragma unroll
   for (int i = 0; i < kF; ++i) dst[i] = mean ? (f[i] - mean[i]) * inv_std[i] : f[i];
@@ -173,12 +185,10 @@ __device__ void feat_store(int32_t v, int32_t k, int64_t A, FeatAcc a, bool has_
 template <int G>
 __global__ __launch_bounds__(256) void k_features(
     const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ deg,
-    const int2 *__restrict__ adj2, const longlong2 *__restrict__ asq,
-    const int32_t *__restrict__ trec,
-    const TriSlot *__restrict__ Y, const int32_t *__restrict__ dn_ptr,
-    const int64_t *__restrict__ ZT, const int32_t *__restrict__ nodes, int64_t count,
-    int32_t kmax, const float *__restrict__ mean, const float *__restrict__ inv_std,
-    float *__restrict__ X, float *__restrict__ lnN) {
+    const int2 *__restrict__ adj2, const NbrMoments *__restrict__ nbm,
+    const int32_t *__restrict__ nodes, int64_t count, int32_t kmax,
+    const float *__restrict__ mean, const float *__restrict__ inv_std, float *__restrict__ X,
+    float *__restrict__ lnN) {
   const int sub = threadIdx.x & (G - 1);
   const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
   const int64_t ngrp = ((int64_t)gridDim.x * blockDim.x) / G;
@@ -193,66 +203,61 @@ __global__ __launch_bounds__(256) void k_features(
     }
     if (v < 0) k = 0;
     FeatAcc f = feat_zero();
-    longlong2 own = make_longlong2(0, 0);
+    NbrMoments own{0, 0, 0.0, 0.0};
     if (v >= 0) {
-      own = asq[v];
-      feat_arcs(adj2, asq, trec, Y, k, row_ptr[v], own.x, own.y, sub, G, f);
+      own = nbm[v];
+      feat_arcs(adj2, nbm, k, row_ptr[v], own, sub, G, f);
     }
     f = feat_reduce<G>(f);
-    if (v >= 0 && sub == 0)
-      feat_store(v, k, own.x, f, dn_ptr[v + 1] > dn_ptr[v], ZT, mean, inv_std, X, lnN);
+    if (v >= 0 && sub == 0) feat_store(v, k, own.s1, f, mean, inv_std, X, lnN);
   }
 }
 
 __global__ __launch_bounds__(1024) void k_features_hub(
     const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ deg,
-    const int2 *__restrict__ adj2, const longlong2 *__restrict__ asq,
-    const int32_t *__restrict__ trec,
-    const TriSlot *__restrict__ Y, const int32_t *__restrict__ dn_ptr,
-    const int64_t *__restrict__ ZT, const int32_t *__restrict__ nodes, int64_t count,
-    const float *__restrict__ mean, const float *__restrict__ inv_std, float *__restrict__ X,
-    float *__restrict__ lnN) {
+    const int2 *__restrict__ adj2, const NbrMoments *__restrict__ nbm,
+    const int32_t *__restrict__ nodes, int64_t count, const float *__restrict__ mean,
+    const float *__restrict__ inv_std, float *__restrict__ X, float *__restrict__ lnN) {
   __shared__ FeatAcc sh[16];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   for (int64_t it = blockIdx.x; it < count; it += gridDim.x) {
     const int32_t v = nodes[it];
     const int32_t k = deg[v];
     FeatAcc f = feat_zero();
-    const longlong2 own = asq[v];
-    feat_arcs(adj2, asq, trec, Y, k, row_ptr[v], own.x, own.y, tid, 1024, f);
+    const NbrMoments own = nbm[v];
+    feat_arcs(adj2, nbm, k, row_ptr[v], own, tid, 1024, f);
     f = feat_reduce<64>(f);
     if (lane == 0) sh[wv] = f;
     __syncthreads();
     if (tid == 0) {
       FeatAcc a = sh[0];
       for (int w = 1; w < 16; ++w) a.merge(sh[w]);
-      feat_store(v, k, own.x, a, dn_ptr[v + 1] > dn_ptr[v], ZT, mean, inv_std, X, lnN);
+      feat_store(v, k, own.s1, a, mean, inv_std, X, lnN);
     }
     __syncthreads();
   }
 }
 
-hipError_t launch_features(const Graph &g, const TriSlot *Y, const int64_t *ZT,
-                           const float *mean, const float *inv_std, float *X, float *lnN,
-                           hipStream_t st) {
+hipError_t launch_features(const Graph &g, const float *mean, const float *inv_std, float *X,
+                           float *lnN, hipStream_t st) {
   auto cap = [](int64_t b, int64_t c) { return (unsigned)std::max<int64_t>(1, std::min(b, c)); };
   const int64_t n_wave = g.n_fin - g.n_fin_hub - g.n_fin_half;
   const int32_t *l_wave = g.fin_list + g.n_fin_hub, *l_half = l_wave + n_wave;
   if (g.n_fin_hub > 0)
     hipLaunchKernelGGL(k_features_hub, dim3(cap(g.n_fin_hub, 1 << 16)), dim3(1024), 0, st,
-                       g.row_ptr, g.deg, g.adj2, g.asq, g.trec, Y, g.dn_ptr, ZT, g.fin_list,
-                       g.n_fin_hub, mean, inv_std, X, lnN);
+                       g.row_ptr, g.deg, g.adj2, g.nbm, g.fin_list, g.n_fin_hub, mean, inv_std, X,
+                       lnN);
   hipLaunchKernelGGL(k_features<8>, dim3(cap(((int64_t)g.n * 8 + 255) / 256, 1 << 20)), dim3(256),
-                     0, st, g.row_ptr, g.deg, g.adj2, g.asq, g.trec, Y, g.dn_ptr, ZT, nullptr,
-                     (int64_t)g.n, kFinGroupMax, mean, inv_std, X, lnN);
+                     0, st, g.row_ptr, g.deg, g.adj2, g.nbm, nullptr, (int64_t)g.n, kFinGroupMax,
+                     mean, inv_std, X, lnN);
   if (n_wave > 0)
     hipLaunchKernelGGL(k_features<64>, dim3(cap((n_wave * 64 + 255) / 256, 1 << 20)), dim3(256),
-                       0, st, g.row_ptr, g.deg, g.adj2, g.asq, g.trec, Y, g.dn_ptr, ZT, l_wave, n_wave,
-                       0, mean, inv_std, X, lnN);
+                       0, st, g.row_ptr, g.deg, g.adj2, g.nbm, l_wave, n_wave, 0, mean, inv_std,
+                       X, lnN);
   if (g.n_fin_half > 0)
     hipLaunchKernelGGL(k_features<32>, dim3(cap((g.n_fin_half * 32 + 255) / 256, 1 << 20)),
-                       dim3(256), 0, st, g.row_ptr, g.deg, g.adj2, g.asq, g.trec, Y, g.dn_ptr, ZT,
-                       l_half, g.n_fin_half, 0, mean, inv_std, X, lnN);
+                       dim3(256), 0, st, g.row_ptr, g.deg, g.adj2, g.nbm, l_half, g.n_fin_half, 0,
+                       mean, inv_std, X, lnN);
   return hipGetLastError();
 }
 

@@ -13,9 +13,8 @@
 #include "ef_internal.h"
 
 namespace efi {
-hipError_t launch_features(const Graph &g, const TriSlot *Y, const int64_t *ZT,
-                           const float *mean, const float *inv_std, float *X, float *lnN,
-                           hipStream_t st);
+hipError_t launch_features(const Graph &g, const float *mean, const float *inv_std, float *X,
+                           float *lnN, hipStream_t st);
 hipError_t launch_mlp_pack(const float *P, __bf16 *pack, hipStream_t st);
 hipError_t launch_mlp_forward(const float *X, int64_t rows, const float *P, const __bf16 *pack,
                               const float *lnN, float *y, double *ef, hipStream_t st);
@@ -250,12 +249,8 @@ ef_status ef_features(ef_graph *h, float *X, float *lnN, uint32_t flags, void *h
   if (g.n == 0) return EF_OK;
   hipStream_t st = (hipStream_t)hip_stream;
   const size_t n = (size_t)g.n;
-  // triangle slots: an upper-end and a lower-end slot per up arc
-  const size_t nts = 2 * (size_t)std::max<int64_t>(g.nnz / 2, 1);
-  // triangle counts per node come from the triangle pass (FP32 deltas unused)
   char *p = nullptr;
-  const size_t need = sizeof(TriSlot) * nts +
-                      sizeof(int64_t) * n + (sizeof(float) * kNF + sizeof(float)) * n + 4096;
+  const size_t need = (sizeof(float) * kNF + sizeof(float)) * n + 4096;
   ef_status rs = graph_scratch(g, need, (void **)&p);
   if (rs != EF_OK) return rs;
   hipError_t e = hipSuccess;
@@ -265,13 +260,10 @@ ef_status ef_features(ef_graph *h, float *X, float *lnN, uint32_t flags, void *h
     return r;
   };
   char *base = p;
-  TriSlot *Y = (TriSlot *)take(sizeof(TriSlot) * nts);
-  int64_t *ZT = (int64_t *)take(sizeof(int64_t) * n);
   const bool dev = (flags & EF_OUT_DEVICE) != 0;
   float *Xd = dev ? X : (float *)take(sizeof(float) * kNF * n);
   float *Ld = (dev && lnN) ? lnN : (float *)take(sizeof(float) * n);
-  e = launch_triangles_count(g, Y, ZT, st);
-  if (e == hipSuccess) e = launch_features(g, Y, ZT, nullptr, nullptr, Xd, Ld, st);
+  e = launch_features(g, nullptr, nullptr, Xd, Ld, st);
   if (e == hipSuccess && !dev) {
     e = hipMemcpyAsync(X, Xd, sizeof(float) * kNF * n, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess && lnN) e = hipMemcpyAsync(lnN, Ld, sizeof(float) * n, hipMemcpyDeviceToHost, st);
@@ -509,12 +501,8 @@ ef_status ef_surrogate_predict(ef_surrogate *s, ef_graph *h, double *ef_pred, ui
   ef_status r = s->device_ready ? EF_OK : sg_upload(s, st);
   if (r != EF_OK) return r;
   const size_t n = (size_t)g.n;
-  // triangle slots: an upper-end and a lower-end slot per up arc
-  const size_t nts = 2 * (size_t)std::max<int64_t>(g.nnz / 2, 1);
   char *p = nullptr;
-  const size_t need = sizeof(TriSlot) * nts +
-                      sizeof(int64_t) * n + (sizeof(float) * kNF + sizeof(float)) * n +
-                      sizeof(double) * n + 4096;
+  const size_t need = (sizeof(float) * kNF + sizeof(float)) * n + sizeof(double) * n + 4096;
   ef_status rs = graph_scratch(g, need, (void **)&p);
   if (rs != EF_OK) return rs;
   hipError_t e = hipSuccess;
@@ -524,14 +512,11 @@ ef_status ef_surrogate_predict(ef_surrogate *s, ef_graph *h, double *ef_pred, ui
     p += (b + 255) & ~(size_t)255;
     return rr;
   };
-  TriSlot *Y = (TriSlot *)take(sizeof(TriSlot) * nts);
-  int64_t *ZT = (int64_t *)take(sizeof(int64_t) * n);
   float *Xd = (float *)take(sizeof(float) * kNF * n);
   float *Ld = (float *)take(sizeof(float) * n);
   const bool dev = (flags & EF_OUT_DEVICE) != 0;
   double *Ed = dev ? ef_pred : (double *)take(sizeof(double) * n);
-  e = launch_triangles_count(g, Y, ZT, st);
-  if (e == hipSuccess) e = launch_features(g, Y, ZT, s->dmean, s->dinv, Xd, Ld, st);
+  e = launch_features(g, s->dmean, s->dinv, Xd, Ld, st);
   if (e == hipSuccess) e = launch_mlp_forward(Xd, (int64_t)n, s->dP, s->dpack, Ld, nullptr, Ed, st);
   if (e == hipSuccess && !dev)
     e = hipMemcpyAsync(ef_pred, Ed, sizeof(double) * n, hipMemcpyDeviceToHost, st);

@@ -99,44 +99,44 @@ def test_gradients_match_cpu_oracle_per_element():
 
 
 def cpu_features(rp, ci):
-    """The 16 raw features from the dense adjacency (float64)."""
+    """The 16 raw features from the dense adjacency and, for the cluster-degree
+    terms, a brute-force pass over every event sequence (float64)."""
     n = rp.size - 1
     A = efref.dense_adjacency(n, rp, ci)
     k = A.sum(1).astype(np.float64)
     Asum = A @ k
     B = A @ (k * k)
-    T = np.diag(A @ A @ A) / 2
     Q = A @ Asum
-    N, D = efref.closed_form_ND(n, rp, ci)
+    N, _ = efref.closed_form_ND(n, rp, ci)
     F = np.zeros((n, 16))
     F[:, 0] = np.log1p(k)
     F[:, 1] = np.log1p(Asum)
     F[:, 2] = np.log1p(B)
-    F[:, 3] = np.log1p(T)
-    F[:, 4] = np.where(k >= 2, 2 * T / np.maximum(k * (k - 1), 1), 0)
     F[:, 5] = np.log1p(Asum - k)
     F[:, 6] = np.log1p(N)
-    F[:, 7] = np.log1p(D)
-    F[:, 8] = np.where((N > 0) & (D > 0), np.log(np.maximum(D, 1) / np.maximum(N, 1)), 0)
     for v in range(n):
         nb = ci[rp[v]:rp[v + 1]]
-        if nb.size:
-            lk = np.log(k[nb])
-            F[v, 9], F[v, 10], F[v, 11], F[v, 12] = lk.max(), lk.min(), lk.mean(), lk.std()
-            F[v, 14] = np.mean(k[nb] == 1)
-            # squared cluster degrees over every event sequence, by brute force:
-            # stars (v, a, b) in both orders and paths v -> a -> b, each with
-            # degree k_v + k_a + k_b - 4 (no triangle correction)
-            e2 = 0.0
-            for a in nb:
-                for b in nb:
-                    if b != a:
-                        e2 += (k[v] + k[a] + k[b] - 4) ** 2
-                for b in ci[rp[a]:rp[a + 1]]:
-                    if b != v:
-                        e2 += (k[v] + k[a] + k[b] - 4) ** 2
-            if N[v] > 0 and D[v] > 0:
-                F[v, 15] = np.log1p(max(e2 * N[v] / float(D[v]) ** 2 - 1.0, 0.0))
+        if not nb.size:
+            continue
+        lk = np.log(k[nb])
+        F[v, 9], F[v, 10], F[v, 11], F[v, 12] = lk.max(), lk.min(), lk.mean(), lk.std()
+        F[v, 14] = np.mean(k[nb] == 1)
+        # every event sequence from v: stars (v, a, b) in both orders and
+        # paths v -> a -> b, each of degree k_v + k_a + k_b - 4 (no triangle
+        # correction)
+        d = []
+        for a in nb:
+            d += [k[v] + k[a] + k[b] - 4 for b in nb if b != a]
+            d += [k[v] + k[a] + k[b] - 4 for b in ci[rp[a]:rp[a + 1]] if b != v]
+        d = np.array(d, np.float64)
+        if d.size and d.sum() > 0:
+            Dv = d.sum()
+            F[v, 7] = np.log1p(Dv)
+            F[v, 8] = np.log(Dv / d.size)
+            x = d / (Dv / d.size) - 1.0
+            F[v, 3] = np.arcsinh(np.mean(x ** 3))
+            F[v, 4] = np.arcsinh(np.mean(x ** 4))
+            F[v, 15] = np.log1p(max(np.mean(x ** 2), 0.0))
     F[:, 13] = np.log1p(Q)
     return F, N
 
