@@ -4,7 +4,9 @@ its gradients, written out by hand in float64 with NumPy (no autograd).
 TEST INFRASTRUCTURE ONLY (imported by tests/ and never by the GPU library).
 
 Network: x (16) -> z1 = x W1 + b1 -> h1 = gelu(z1) (64) -> z2 = h1 W2 + b2 ->
-h2 = gelu(z2) (64) -> y = h2 w3 + b3 (1), gelu(z) = z/2 (1 + erf(z / sqrt 2)).
+h2 = gelu(z2) (64) -> y = h2 w3 + b3 (1), with the tanh form of GELU
+(Hendrycks and Gimpel, "Gaussian Error Linear Units", 2016):
+gelu(z) = z/2 (1 + tanh(sqrt(2/pi) (z + 0.044715 z^3))).
 Loss L = mean_i (y_i - t_i)^2.
 
 With bf16=True the operands that the GPU kernels round to bfloat16 (x, the
@@ -32,15 +34,17 @@ def bf16_round(a):
     return r.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
-_erf = np.vectorize(math.erf, otypes=[np.float64])
+_C = math.sqrt(2.0 / math.pi)
+_A = 0.044715
 
 
 def gelu(z):
-    return 0.5 * z * (1.0 + _erf(z / math.sqrt(2.0)))
+    return 0.5 * z * (1.0 + np.tanh(_C * (z + _A * z * z * z)))
 
 
 def gelu_grad(z):
-    return 0.5 * (1.0 + _erf(z / math.sqrt(2.0))) + z * np.exp(-0.5 * z * z) / math.sqrt(2.0 * math.pi)
+    t = np.tanh(_C * (z + _A * z * z * z))
+    return 0.5 * (1.0 + t) + 0.5 * z * (1.0 - t * t) * _C * (1.0 + 3.0 * _A * z * z)
 
 
 def flatten(p):

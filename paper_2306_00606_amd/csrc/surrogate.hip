@@ -1,5 +1,5 @@
 // Learned surrogate for Expected Force: per-node features, and a small MLP
-// (16 -> 64 -> GELU -> 64 -> GELU -> 1) with BF16 operands and FP32
+// (16 -> 64 -> GELU -> 64 -> GELU -> 1, GELU in its tanh form) with BF16 operands and FP32
 // accumulation on the gfx950 matrix cores (v_mfma_f32_32x32x16_bf16), trained
 // on the GPU by its own forward and backward kernels and an Adam step.
 //
@@ -37,12 +37,23 @@ __device__ __forceinline__ int c_row(int r, int lane) {
 __device__ __forceinline__ f32x16 mfma(bf16x8 a, bf16x8 b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
+// GELU in its tanh form (Hendrycks and Gimpel, 2016), the tanh from one
+// exponential and one hardware reciprocal (v_rcp_f32, 1 ulp; the GELUs feed
+// BF16 operands): tanh(u) = 1 - 2 / (1 + e^{2u}) (e^{2u} overflowing to inf
+// gives 1, underflowing to 0 gives -1)
+__device__ __forceinline__ float gelu_tanh_arg(float z) {
+  return 0.7978845608028654f * (z + 0.044715f * z * z * z);
+}
+__device__ __forceinline__ float fast_tanh(float u) {
+  return 1.0f - 2.0f * __builtin_amdgcn_rcpf(1.0f + __expf(2.0f * u));
+}
 __device__ __forceinline__ float gelu(float z) {
-  return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
+  return 0.5f * z * (1.0f + fast_tanh(gelu_tanh_arg(z)));
 }
 __device__ __forceinline__ float gelu_grad(float z) {
-  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) +
-         z * 0.39894228040143268f * expf(-0.5f * z * z);
+  const float t = fast_tanh(gelu_tanh_arg(z));
+  return 0.5f * (1.0f + t) +
+         0.5f * z * (1.0f - t * t) * 0.7978845608028654f * (1.0f + 0.134145f * z * z);
 }
 __device__ __forceinline__ float bf(float x) { return (float)(__bf16)x; }
 

@@ -351,7 +351,10 @@ def test_mlp_oracle_gelu_and_bf16_rounding():
     assert abs(mlp_ref.gelu(np.array([10.0]))[0] - 10.0) < 1e-12
     assert abs(mlp_ref.gelu(np.array([-10.0]))[0]) < 1e-12
     assert abs(mlp_ref.gelu_grad(np.array([0.0]))[0] - 0.5) < 1e-15
-    assert abs(mlp_ref.gelu(np.array([1.0]))[0] - 0.5 * (1 + math.erf(1 / math.sqrt(2)))) < 1e-15
+    # the tanh form stays within 1e-3 of the erf form (its published accuracy)
+    z = np.linspace(-6, 6, 241)
+    exact = 0.5 * z * (1 + np.vectorize(math.erf)(z / math.sqrt(2)))
+    assert np.max(np.abs(mlp_ref.gelu(z) - exact)) < 1e-3
     # bfloat16 keeps 8 significant bits, ties to even
     assert mlp_ref.bf16_round(np.array([1.0]))[0] == 1.0
     assert mlp_ref.bf16_round(np.array([1.0 + 2 ** -8]))[0] == 1.0          # tie -> even
