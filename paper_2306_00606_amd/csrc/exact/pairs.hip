@@ -55,10 +55,13 @@ __device__ __forceinline__ double rot1(double x) {
 __device__ __forceinline__ float score(float d) { return d * __builtin_amdgcn_logf(d); }
 __device__ __forceinline__ double score(double d) { return d * log(d); }
 
-template <typename T>
-__device__ __forceinline__ T score_masked(T d) {
-  return d > T(0) ? score(d) : T(0);
+// score(d) for d >= 1 and +-0 for any d < 1 (masked lanes carry large
+// negative degrees), without a branch: integer degrees below 1 give
+// log(max(d, 1)) = 0, and adding -0 leaves every sum unchanged
+__device__ __forceinline__ float score_masked(float d) {
+  return d * __builtin_amdgcn_logf(fmaxf(d, 1.0f));
 }
+__device__ __forceinline__ double score_masked(double d) { return d * log(fmax(d, 1.0)); }
 
 // ---------------------------------------------------------------------------
 // double-float accumulation for the FP32 path
