@@ -29,10 +29,15 @@
 
 namespace efi {
 
-constexpr float kNegF = -1.0e9f;
-// a degree past the centre's row, as an integer (converts to kNegF)
-constexpr int32_t kNegI = -1000000000;
+// the degree of a row or column past the centre's row: -2^21, so that every
+// cluster degree d = cp + kq with a masked end stays below 1 (its score is
+// +-0) while every value of the degree recurrence, masked or not, is an
+// integer of magnitude below 2^24 (exact in FP32)
+constexpr float kNegF = -2097152.0f;
+constexpr int32_t kNegI = -2097152;  // the same as an integer
 static_assert((float)kNegI == kNegF, "kNegI must convert to kNegF");
+static_assert(2 * kMaxDegree - 4 + kNegI < 1, "a masked column must give d < 1");
+static_assert(3 * kMaxDegree - 2 * kNegI < (1 << 24), "the recurrence must stay exact in FP32");
 
 // ---------------------------------------------------------------------------
 // wave rotate: lane l receives the value of lane (l + 1) mod 64
@@ -140,7 +145,10 @@ __device__ __forceinline__ void tile_full(T cp, T kq, T D, T &Rt, T &C) {
 //   last step only on lanes 0..31. On return C holds the partial of column
 //   (lane + 32) & 63.
 // otherwise steps 0..63; on return C holds the partial of column (lane+63)&63.
-// MASKED: some rows/columns may be invalid, or d may be 0.
+// MASKED: some rows/columns may be invalid, or d may be 0. Every form steps
+//   the cluster degree with the same DPP recurrence; an invalid row or
+//   column carries kNegF, which keeps its d below 1 at every step, so its
+//   score is zero.
 // ---------------------------------------------------------------------------
 template <typename T, bool DIAG, bool MASKED>
 __device__ __forceinline__ void tile(T cp, T kq, T &Rt, T &C) {
@@ -148,23 +156,26 @@ __device__ __forceinline__ void tile(T cp, T kq, T &Rt, T &C) {
   Rt = T(0);
   C = T(0);
   if (DIAG) {
+    // the degree recurrence of the full tiles (below), from step 1
+    T d = cp + kq;
+    const T D = cp - rot1(cp);
 #pragma unroll 4
     for (int s = 1; s <= 32; ++s) {
-      kq = rot1(kq);
-      T d = cp + kq;
+      d = rot1(d) + D;
       T g = score_masked(d);
       if (s == 32) g = lane < 32 ? g : T(0);
       Rt += g;
       C = rot1(C) + g;
     }
   } else if (MASKED) {
+    T d = cp + kq;
+    const T D = cp - rot1(cp);
 #pragma unroll 8
     for (int s = 0; s < 64; ++s) {
-      T d = cp + kq;
       T g = score_masked(d);
       Rt += g;
       C = rot1(C) + g;
-      kq = rot1(kq);
+      d = rot1(d) + D;
     }
   } else {
     // d_s(l) = cp(l) + kq(l + s). The lane that holds column q at step s
