@@ -74,7 +74,7 @@ PAIRS_BIG_TRAFFIC_BYTES = 2.655e9
 # summaries): SQ_INSTS_VALU (wave64 VALU instructions), of which
 # SQ_INSTS_VALU_TRANS_F32 transcendentals (v_log_f32) and SQ_INSTS_LDS.
 # None whenever the kernel changes.
-PAIRS_BIG_VALU_INSTS = 5.989e9
+PAIRS_BIG_VALU_INSTS = 5.911e9
 PAIRS_BIG_TRANS_INSTS = 1.330e8
 PAIRS_BIG_LDS_INSTS = 1.612e9
 # VALU cost of one SIR attempt along an arc, in FP32-FMA-equivalent lane slots:
