@@ -266,8 +266,10 @@ hipError_t launch_check_cols(const int32_t *col, int64_t nnz, int32_t n, int32_t
 hipError_t launch_zero_i32(int32_t *p, int32_t count, hipStream_t st);
 
 // work lists
-// Mid centres are packed by their number of 64-neighbour blocks: up to 4
-// blocks, 4 centres per 16-wavefront workgroup; 5-8 blocks, 2; 9-16, 1.
+// Mid centres are classed by their number of 64-neighbour blocks: up to 4,
+// 5-8, 9-16. The pair kernels give each centre a workgroup of 4, 8 or 16
+// wavefronts by class; the persistent batch kernel packs 4, 2 or 1 centres
+// into a 16-wavefront workgroup.
 __host__ __device__ inline int mid_class(int32_t k) {
   const int nb = (k + 63) >> 6;
   return nb <= 4 ? 0 : nb <= 8 ? 1 : 2;

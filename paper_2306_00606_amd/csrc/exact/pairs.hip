@@ -494,35 +494,41 @@ __device__ void diag_super_dealt(const int2 *adj2, int32_t base, int32_t k, T kv
 }
 
 // ---------------------------------------------------------------------------
-// mid centres (64 < k <= 1024): G centres per 16-wavefront workgroup, 16/G
-// wavefronts each (G = 4, 2, 1 for up to 4, 8, 16 blocks of 64 neighbours)
+// mid centres (64 < k <= 1024): G centres per workgroup, WPG wavefronts each,
+// at least one per block of 64 neighbours. The stand-alone kernels give each
+// centre a workgroup of its own (4, 8 or 16 wavefronts for up to 4, 8 or 16
+// blocks), so its barriers wait for no other centre and small workgroups
+// fill a compute unit eight at a time; the persistent batch kernel packs
+// G = 4, 2 or 1 centres into its 16-wavefront workgroups.
 // ---------------------------------------------------------------------------
-template <typename T, int G> struct MidLdsPlain {
-  T parts[G][kBlocksPerSuper / G][9][64];
-  int32_t colk[kBlocksPerSuper * 64];  // each group's degrees, 64 per wavefront
+template <typename T, int G, int WPG = kBlocksPerSuper / G> struct MidLdsPlain {
+  T parts[G][WPG][9][64];
+  int32_t colk[G * WPG * 64];  // each group's degrees, 64 per wavefront
 };
 // FP32: the block pairs dealt over the group's wavefronts (row partials in
-// LDS, 76 KB in all, two workgroups per CU); FP64 keeps one row block per
-// wavefront (the row partials would take its LDS to 148 KB)
-template <typename T, int G> struct MidLdsDealt {
-  T parts[G][kBlocksPerSuper / G][9][64];
-  T rowp[G][kBlocksPerSuper / G][9][64];
-  int32_t colk[kBlocksPerSuper * 64];
+// LDS: 76 KB for 16 wavefronts, two workgroups per CU; 19.5 KB for 4); FP64
+// keeps one row block per wavefront (the row partials would take its LDS to
+// 148 KB)
+template <typename T, int G, int WPG = kBlocksPerSuper / G> struct MidLdsDealt {
+  T parts[G][WPG][9][64];
+  T rowp[G][WPG][9][64];
+  int32_t colk[G * WPG * 64];
 };
 template <typename T> constexpr bool kMidDealt = std::is_same<T, float>::value;
-template <typename T, int G>
-using MidLds = typename std::conditional<kMidDealt<T>, MidLdsDealt<T, G>, MidLdsPlain<T, G>>::type;
+template <typename T, int G, int WPG = kBlocksPerSuper / G>
+using MidLds = typename std::conditional<kMidDealt<T>, MidLdsDealt<T, G, WPG>,
+                                         MidLdsPlain<T, G, WPG>>::type;
 
-// centres gi*G .. gi*G+G-1 of the list on a 16-wavefront workgroup (every
-// thread calls it: it holds workgroup barriers)
-template <typename T, int G>
+// centres gi*G .. gi*G+G-1 of the list on a workgroup of G * WPG wavefronts
+// (every thread calls it: it holds workgroup barriers); every centre has at
+// most WPG blocks of 64 neighbours
+template <typename T, int G, int WPG = kBlocksPerSuper / G>
 __device__ __forceinline__ void pairs_mid_group(const int32_t *__restrict__ row_ptr,
                                                 const int32_t *__restrict__ deg,
                                                 const int2 *__restrict__ adj2,
                                                 const int32_t *__restrict__ list, int64_t count,
                                                 int64_t gi, void *__restrict__ R,
-                                                MidLds<T, G> &lds) {
-  constexpr int WPG = kBlocksPerSuper / G;  // wavefronts per centre
+                                                MidLds<T, G, WPG> &lds) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int grp = w / WPG, wl = w % WPG;
   const int64_t it = gi * G + grp;
@@ -546,16 +552,16 @@ __device__ __forceinline__ void pairs_mid_group(const int32_t *__restrict__ row_
   __syncthreads();
 }
 
-template <typename T, int G>
-__global__ __launch_bounds__(1024) void k_pairs_mid(const int32_t *__restrict__ row_ptr,
-                                                    const int32_t *__restrict__ deg,
-                                                    const int2 *__restrict__ adj2,
-                                                    const int32_t *__restrict__ list,
-                                                    int64_t count, void *__restrict__ R) {
-  __shared__ MidLds<T, G> lds;
-  const int64_t ngroups = (count + G - 1) / G;
-  for (int64_t gi = blockIdx.x; gi < ngroups; gi += gridDim.x)
-    pairs_mid_group<T, G>(row_ptr, deg, adj2, list, count, gi, R, lds);
+// one centre per workgroup of WPG wavefronts
+template <typename T, int WPG>
+__global__ __launch_bounds__(64 * WPG) void k_pairs_mid(const int32_t *__restrict__ row_ptr,
+                                                        const int32_t *__restrict__ deg,
+                                                        const int2 *__restrict__ adj2,
+                                                        const int32_t *__restrict__ list,
+                                                        int64_t count, void *__restrict__ R) {
+  __shared__ MidLds<T, 1, WPG> lds;
+  for (int64_t gi = blockIdx.x; gi < count; gi += gridDim.x)
+    pairs_mid_group<T, 1, WPG>(row_ptr, deg, adj2, list, count, gi, R, lds);
 }
 
 // mid centres into their classes (order within a class is not fixed; every
@@ -1133,14 +1139,16 @@ static hipError_t pairs_impl(const Graph &g, const Bins &b, void *R, void *recor
     hipLaunchKernelGGL((k_pairs_small<T, 64>), dim3(capped((b.n_smallb[3] + 3) / 4, 1 << 20)),
                        dim3(256), 0, st, g.row_ptr, g.deg, g.adj2, b.small[3], b.n_smallb[3], R);
   if (ev_small) (void)hipEventRecord(ev_small, st);
+  // class c holds centres of up to 4 << c blocks: one workgroup of that
+  // many wavefronts each
   if (b.n_midc[0] > 0)
-    hipLaunchKernelGGL((k_pairs_mid<T, 4>), dim3(capped((b.n_midc[0] + 3) / 4, 1 << 20)),
-                       dim3(1024), 0, st, g.row_ptr, g.deg, g.adj2, b.midc[0], b.n_midc[0], R);
+    hipLaunchKernelGGL((k_pairs_mid<T, 4>), dim3(capped(b.n_midc[0], 1 << 20)), dim3(256), 0,
+                       st, g.row_ptr, g.deg, g.adj2, b.midc[0], b.n_midc[0], R);
   if (b.n_midc[1] > 0)
-    hipLaunchKernelGGL((k_pairs_mid<T, 2>), dim3(capped((b.n_midc[1] + 1) / 2, 1 << 20)),
-                       dim3(1024), 0, st, g.row_ptr, g.deg, g.adj2, b.midc[1], b.n_midc[1], R);
+    hipLaunchKernelGGL((k_pairs_mid<T, 8>), dim3(capped(b.n_midc[1], 1 << 20)), dim3(512), 0,
+                       st, g.row_ptr, g.deg, g.adj2, b.midc[1], b.n_midc[1], R);
   if (b.n_midc[2] > 0)
-    hipLaunchKernelGGL((k_pairs_mid<T, 1>), dim3(capped(b.n_midc[2], 1 << 20)), dim3(1024), 0,
+    hipLaunchKernelGGL((k_pairs_mid<T, 16>), dim3(capped(b.n_midc[2], 1 << 20)), dim3(1024), 0,
                        st, g.row_ptr, g.deg, g.adj2, b.midc[2], b.n_midc[2], R);
   if (ev_mid) (void)hipEventRecord(ev_mid, st);
   if (agg_done && b.n_big > 0)
