@@ -809,7 +809,9 @@ extern "C" ef_status ef_compute(ef_graph *h, ef_algo algo, ef_prec prec, const i
   }
   if ((s = alloc_bins(g, b)) != EF_OK) return s;
   if ((s = ws_ensure(g, WS_R, tsz * (size_t)nnz, "arc sums")) != EF_OK) return s;
-  if ((s = ws_ensure(g, WS_REC, tsz * (size_t)kRecEntries * (size_t)std::max<int64_t>(b.n_tiles, 1),
+  // super-tile record entries: one float (FP32C) or double each
+  const size_t rsz = prec == EF_PREC_FP64 ? sizeof(double) : sizeof(float);
+  if ((s = ws_ensure(g, WS_REC, rsz * (size_t)kRecEntries * (size_t)std::max<int64_t>(b.n_tiles, 1),
                      "super-tile records")) != EF_OK)
     return s;
   if ((s = ws_ensure(g, WS_FLAG, (sizeof(int32_t) + 1) * (size_t)std::max<int32_t>(n_work, 1),

@@ -99,26 +99,30 @@ template <> struct Acc<float> {
     df_add(v, x.x);
     df_add(v, x.y);
   }
-  // a stored sum read and added in two steps (several reads in flight)
-  using Raw = float2;
-  __device__ static Raw load(const void *R, int64_t i) {
-    return reinterpret_cast<const float2 *>(R)[i];
+  // a super-tile record entry (a partial over at most 1024 clusters): the
+  // compensated sum rounded to one float, half the bytes of a stored pair;
+  // the reduction over the records adds the entries compensated again, so a
+  // per-arc sum carries one rounding per record entry
+  using Rec = float;
+  __device__ void store_rec(void *P, int64_t i) const {
+    reinterpret_cast<float *>(P)[i] = v.hi + v.lo;
   }
-  __device__ void add_raw(Raw x) {
-    df_add(v, x.x);
-    df_add(v, x.y);
+  __device__ static Rec load_rec(const void *P, int64_t i) {
+    return reinterpret_cast<const float *>(P)[i];
   }
+  __device__ void add_rec(Rec x) { df_add(v, x); }
 };
 template <> struct Acc<double> {
   double v = 0.0;
   __device__ void add(double x) { v += x; }
   __device__ void store(void *R, int64_t i) const { reinterpret_cast<double *>(R)[i] = v; }
   __device__ void add_stored(const void *R, int64_t i) { v += reinterpret_cast<const double *>(R)[i]; }
-  using Raw = double;
-  __device__ static Raw load(const void *R, int64_t i) {
-    return reinterpret_cast<const double *>(R)[i];
+  using Rec = double;
+  __device__ void store_rec(void *P, int64_t i) const { reinterpret_cast<double *>(P)[i] = v; }
+  __device__ static Rec load_rec(const void *P, int64_t i) {
+    return reinterpret_cast<const double *>(P)[i];
   }
-  __device__ void add_raw(Raw x) { v += x; }
+  __device__ void add_rec(Rec x) { v += x; }
 };
 
 // Full 64x64 tile (no masking) with the row step D = cp - rot(cp) given, so
@@ -676,7 +680,7 @@ __device__ __forceinline__ void pairs_big_tile(const int32_t *__restrict__ row_p
                   reinterpret_cast<T(*)[9][64]>(&parts[0][0][0]), w, out,
                   reinterpret_cast<int32_t *>(lds + BigLds<T>::kTabBytes + BigLds<T>::kPartBytes),
                   kTab ? gtab : nullptr);
-    if (w < nbQ) out.store(rec, rbase + 64 * w + lane);
+    if (w < nbQ) out.store_rec(rec, rbase + 64 * w + lane);
   } else {
     // P < Q: all 16 row blocks of P are full
     const int ws = __builtin_amdgcn_readfirstlane(w);
@@ -732,7 +736,7 @@ __device__ __forceinline__ void pairs_big_tile(const int32_t *__restrict__ row_p
       if (dl % kColWin == kColWin - 1 && dl + 1 < nbQ) __syncthreads();
       c = c + 1 == nbQ ? 0 : c + 1;
     }
-    out.store(rec, rbase + 64 * w + lane);
+    out.store_rec(rec, rbase + 64 * w + lane);
     __syncthreads();
     {
       const int cc = threadIdx.x >> 6, j = threadIdx.x & 63;
@@ -740,7 +744,7 @@ __device__ __forceinline__ void pairs_big_tile(const int32_t *__restrict__ row_p
         Acc<T> col;
         const T *a = cacc + cc * G * kColWin * 64 + j;
         for (int i = 0; i < G * kColWin; ++i) col.add(a[64 * i]);
-        col.store(rec, rbase + kSuper + 64 * cc + j);
+        col.store_rec(rec, rbase + kSuper + 64 * cc + j);
       }
     }
   }
@@ -924,7 +928,7 @@ __device__ __forceinline__ void arc_reduce_item(const int32_t *__restrict__ row_
     return (bc.rec_base + (int64_t)P * ns - (int64_t)P * (P - 1) / 2 + (b - P)) * kRecEntries +
            kSuper + j;
   };
-  using Raw = typename Acc<T>::Raw;
+  using Rec = typename Acc<T>::Rec;
   for (int j = threadIdx.x; j < kSuper; j += blockDim.x) {
     const int32_t p = kSuper * b + j;
     if (p >= k) break;
@@ -932,24 +936,26 @@ __device__ __forceinline__ void arc_reduce_item(const int32_t *__restrict__ row_
     // four reads in flight, added in the same order
     int Q = b;
     for (; Q + 3 < ns; Q += 4) {
-      const Raw r0 = Acc<T>::load(rec, rowi(Q, j)), r1 = Acc<T>::load(rec, rowi(Q + 1, j)),
-                r2 = Acc<T>::load(rec, rowi(Q + 2, j)), r3 = Acc<T>::load(rec, rowi(Q + 3, j));
-      a.add_raw(r0);
-      a.add_raw(r1);
-      a.add_raw(r2);
-      a.add_raw(r3);
+      const Rec r0 = Acc<T>::load_rec(rec, rowi(Q, j)), r1 = Acc<T>::load_rec(rec, rowi(Q + 1, j)),
+                r2 = Acc<T>::load_rec(rec, rowi(Q + 2, j)),
+                r3 = Acc<T>::load_rec(rec, rowi(Q + 3, j));
+      a.add_rec(r0);
+      a.add_rec(r1);
+      a.add_rec(r2);
+      a.add_rec(r3);
     }
-    for (; Q < ns; ++Q) a.add_stored(rec, rowi(Q, j));
+    for (; Q < ns; ++Q) a.add_rec(Acc<T>::load_rec(rec, rowi(Q, j)));
     int P = 0;
     for (; P + 3 < b; P += 4) {
-      const Raw r0 = Acc<T>::load(rec, coli(P, j)), r1 = Acc<T>::load(rec, coli(P + 1, j)),
-                r2 = Acc<T>::load(rec, coli(P + 2, j)), r3 = Acc<T>::load(rec, coli(P + 3, j));
-      a.add_raw(r0);
-      a.add_raw(r1);
-      a.add_raw(r2);
-      a.add_raw(r3);
+      const Rec r0 = Acc<T>::load_rec(rec, coli(P, j)), r1 = Acc<T>::load_rec(rec, coli(P + 1, j)),
+                r2 = Acc<T>::load_rec(rec, coli(P + 2, j)),
+                r3 = Acc<T>::load_rec(rec, coli(P + 3, j));
+      a.add_rec(r0);
+      a.add_rec(r1);
+      a.add_rec(r2);
+      a.add_rec(r3);
     }
-    for (; P < b; ++P) a.add_stored(rec, coli(P, j));
+    for (; P < b; ++P) a.add_rec(Acc<T>::load_rec(rec, coli(P, j)));
     a.store(R, base + adjs[base + p].x);  // sorted position -> arc of the row
   }
 }
