@@ -65,18 +65,18 @@ TABLE_ENTRIES = 8192
 # HBM bytes per launch of k_pairs_big<float> at this workload (R-MAT scale 22,
 # edge factor 10): FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 from two rocprofv3
 # counter runs, each counter scaled by its reading on a 1 GiB copy; mostly the
-# super-tile records the kernel writes. Taken on the current kernel (the
+# super-tile records the kernel writes (one float per entry). Taken on the current kernel (the
 # counter summaries sit with the other rocprofv3 summaries); set to None
 # whenever the kernel changes.
-PAIRS_BIG_TRAFFIC_BYTES = None
+PAIRS_BIG_TRAFFIC_BYTES = 1.821e9
 # Hardware counters of k_pairs_big<float> at the same workload, per launch
 # (rocprofv3 --pmc, the counter summaries sit with the other rocprofv3
 # summaries): SQ_INSTS_VALU (wave64 VALU instructions), of which
 # SQ_INSTS_VALU_TRANS_F32 transcendentals (v_log_f32) and SQ_INSTS_LDS.
 # None whenever the kernel changes.
-PAIRS_BIG_VALU_INSTS = None
-PAIRS_BIG_TRANS_INSTS = None
-PAIRS_BIG_LDS_INSTS = None
+PAIRS_BIG_VALU_INSTS = 5.904e9
+PAIRS_BIG_TRANS_INSTS = 1.330e8
+PAIRS_BIG_LDS_INSTS = 1.612e9
 # VALU cost of one SIR attempt along an arc, in FP32-FMA-equivalent lane slots:
 # the counter (2e) K and SplitMix64's two multiplications are three 64-bit
 # products of three 32-bit multiplies each, at a quarter of the FMA rate
