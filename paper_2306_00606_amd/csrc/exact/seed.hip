@@ -11,7 +11,7 @@
 //   per arc v->a:  N = k_v - 1,   D = (k_v - 1)(k_v + k_a - 4) + (A_v - k_a)
 // (A_v = sum of v's neighbour degrees), minus 8 per triangle at s for D.
 // Then EF(s) = ln D - S / D (Eq. 1 with p_c = d_c / D).
-#include "common.cuh"
+#include "device_common.h"
 
 namespace efi {
 

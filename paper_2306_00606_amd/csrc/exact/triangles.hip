@@ -28,7 +28,7 @@
 // every chunk, which bounds the credits an LDS slot holds by 2^11.
 #include <type_traits>
 
-#include "common.cuh"
+#include "device_common.h"
 
 namespace efi {
 

@@ -36,7 +36,7 @@
 // v_log_f32 and sums them in double; the seed's EF is taken in double.
 // Seeds whose EF cancels (kappa = (S/D) / EF > 16, or EF <= 0) are flagged,
 // and the caller recomputes their items in FP64.
-#include "common.cuh"
+#include "device_common.h"
 
 namespace efi {
 

@@ -13,7 +13,7 @@
 //   C[i][n]  for n = l % 32, i = 8 (r / 4) + 4 (l / 32) + r % 4  (16 fp32, r = 0..15)
 // Weights are kept as FP32 masters and re-packed into the B layout (bf16)
 // after every optimiser step.
-#include "common.cuh"
+#include "device_common.h"
 
 namespace efi {
 
