@@ -40,6 +40,11 @@ template <> struct SumT<float> {
   }
   __device__ static void add_term(DFv &a, float x) { a.add(x); }
   __device__ static double value(const DFv &a) { return a.value(); }
+  // a per-arc score sum R[e]: one float (the pair kernels round their
+  // compensated sums once when they store them)
+  __device__ static void add_arc(DFv &a, const void *R, int64_t i) {
+    a.add(reinterpret_cast<const float *>(R)[i]);
+  }
 };
 template <> struct SumT<double> {
   using type = double;
@@ -51,6 +56,9 @@ template <> struct SumT<double> {
   }
   __device__ static void add_term(double &a, double x) { a += x; }
   __device__ static double value(const double &a) { return a; }
+  __device__ static void add_arc(double &a, const void *R, int64_t i) {
+    a += reinterpret_cast<const double *>(R)[i];
+  }
 };
 
 // wavefront reductions with a fixed butterfly order

@@ -808,7 +808,9 @@ extern "C" ef_status ef_compute(ef_graph *h, ef_algo algo, ef_prec prec, const i
     host_bins(g, useeds.data(), (int64_t)useeds.size(), b);
   }
   if ((s = alloc_bins(g, b)) != EF_OK) return s;
-  if ((s = ws_ensure(g, WS_R, tsz * (size_t)nnz, "arc sums")) != EF_OK) return s;
+  // per-arc sums: one float (FP32C) or double each
+  const size_t asz = prec == EF_PREC_FP64 ? sizeof(double) : sizeof(float);
+  if ((s = ws_ensure(g, WS_R, asz * (size_t)nnz, "arc sums")) != EF_OK) return s;
   // super-tile record entries: one float (FP32C) or double each
   const size_t rsz = prec == EF_PREC_FP64 ? sizeof(double) : sizeof(float);
   if ((s = ws_ensure(g, WS_REC, rsz * (size_t)kRecEntries * (size_t)std::max<int64_t>(b.n_tiles, 1),

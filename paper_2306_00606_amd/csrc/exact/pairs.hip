@@ -99,6 +99,12 @@ template <> struct Acc<float> {
     df_add(v, x.x);
     df_add(v, x.y);
   }
+  // a per-arc sum R[e]: the compensated sum rounded to one float (every term
+  // is >= 0, so a node's sum over its arcs keeps a relative error of at most
+  // one float rounding from these stores)
+  __device__ void store_arc(void *R, int64_t i) const {
+    reinterpret_cast<float *>(R)[i] = v.hi + v.lo;
+  }
   // a super-tile record entry (a partial over at most 1024 clusters): the
   // compensated sum rounded to one float, half the bytes of a stored pair;
   // the reduction over the records adds the entries compensated again, so a
@@ -117,6 +123,7 @@ template <> struct Acc<double> {
   __device__ void add(double x) { v += x; }
   __device__ void store(void *R, int64_t i) const { reinterpret_cast<double *>(R)[i] = v; }
   __device__ void add_stored(const void *R, int64_t i) { v += reinterpret_cast<const double *>(R)[i]; }
+  __device__ void store_arc(void *R, int64_t i) const { reinterpret_cast<double *>(R)[i] = v; }
   using Rec = double;
   __device__ void store_rec(void *P, int64_t i) const { reinterpret_cast<double *>(P)[i] = v; }
   __device__ static Rec load_rec(const void *P, int64_t i) {
@@ -292,7 +299,7 @@ __device__ __forceinline__ void pairs_seg_group(const int32_t *__restrict__ row_
     Acc<T> a;
     a.add(Rt);
     a.add(Cl);
-    a.store(R, base + j);
+    a.store_arc(R, base + j);
   }
 }
 
@@ -344,7 +351,7 @@ __device__ __forceinline__ void pairs_lane_one(const int32_t *__restrict__ row_p
     if (p < k) {
       Acc<T> a;
       a.add(r[p]);
-      a.store(R, base + p);
+      a.store_arc(R, base + p);
     }
   }
 }
@@ -552,7 +559,7 @@ __device__ __forceinline__ void pairs_mid_group(const int32_t *__restrict__ row_
     diag_super<T>(adj2, base, k, (T)(k - 4), 0, nb, lds.parts[grp], wl, out,
                   lds.colk + 64 * WPG * grp);
   const int32_t p = 64 * wl + lane;
-  if (wl < nb && p < k) out.store(R, base + p);
+  if (wl < nb && p < k) out.store_arc(R, base + p);
   __syncthreads();
 }
 
@@ -900,7 +907,7 @@ __global__ __launch_bounds__(1024) void k_pairs_agg(const int32_t *__restrict__ 
       Acc<T> a;
       a.add_stored(tsum, hval[h]);
       a.add(-score(c + (T)(2 * kap)));
-      a.store(R, e);
+      a.store_arc(R, e);
     }
     if (tid == 0) agg_done[bi] = 1;
     __syncthreads();
@@ -956,7 +963,7 @@ __device__ __forceinline__ void arc_reduce_item(const int32_t *__restrict__ row_
       a.add_rec(r3);
     }
     for (; P < b; ++P) a.add_rec(Acc<T>::load_rec(rec, coli(P, j)));
-    a.store(R, base + adjs[base + p].x);  // sorted position -> arc of the row
+    a.store_arc(R, base + adjs[base + p].x);  // sorted position -> arc of the row
   }
 }
 

@@ -166,8 +166,8 @@ __device__ __forceinline__ void fin_arcs(const int2 *__restrict__ adj2,
   using S = SumT<T>;
   for (int32_t e = base + first; e < base + k; e += stride) {
     // a centre of degree 1 has no pairs: its row sums were never written
-    if (k >= 2) S::add_stored(sacc, R, e);
-    if (adj2[e].y >= 2) S::add_stored(sacc, R, rev[e]);
+    if (k >= 2) S::add_arc(sacc, R, e);
+    if (adj2[e].y >= 2) S::add_arc(sacc, R, rev[e]);
     const int32_t r = trec[e];
     if (r >= 0) {
       const TriSlot t = Y[r];
@@ -263,13 +263,10 @@ __device__ __forceinline__ void fin_groups(const FinArgs &A, const int32_t *node
 // contributions past k masked), so a node costs two dependent round trips
 template <typename T> struct RVal;
 template <> struct RVal<float> {
-  __device__ static float2 load(const void *R, int64_t i) {
-    return reinterpret_cast<const float2 *>(R)[i];
+  __device__ static float load(const void *R, int64_t i) {
+    return reinterpret_cast<const float *>(R)[i];
   }
-  __device__ static void add(DFv &a, float2 x, bool on) {
-    a.add(on ? x.x : 0.0f);
-    a.add(on ? x.y : 0.0f);
-  }
+  __device__ static void add(DFv &a, float x, bool on) { a.add(on ? x : 0.0f); }
 };
 template <> struct RVal<double> {
   __device__ static double load(const void *R, int64_t i) {
@@ -600,7 +597,7 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_wave(
     int32_t myslot = -1;
     if (lane < k) {
       myslot = hash_insert<SLOTS>(hkey, adj2[base + lane].x);
-      if (k >= 2) S::add_stored(sacc, R, base + lane);
+      if (k >= 2) S::add_arc(sacc, R, base + lane);
     }
     const int32_t total =
         seed_chunk_setup<64>(row_ptr, adj2, base, 0, k, lane, seg_s[wv], segp_s[wv], nullptr);
@@ -663,7 +660,7 @@ __global__ __launch_bounds__(64 * WPB, seed_block_min_waves(SLOTS)) void k_seed_
     int64_t Dd = 0, Nn = 0;
     for (int32_t j = tid; j < k; j += NT) {
       if constexpr (!BITMAP) hash_insert<SLOTS>(hkey, adj2[base + j].x);
-      if (k >= 2) S::add_stored(sacc, R, base + j);
+      if (k >= 2) S::add_arc(sacc, R, base + j);
     }
     for (int32_t c0 = 0; c0 < k; c0 += MAXK) {
       const int32_t cnt = min(MAXK, k - c0);
