@@ -159,7 +159,7 @@ ef_status ef_graph_free(ef_graph *h) {
     (void)hipFree(g.row_ptr);
     (void)hipFree(g.col_idx);
   }
-  void *arrays[] = {g.deg, g.src, g.rev, g.adj2, g.adjs, g.asum, g.qa, g.nbm, g.up_ptr, g.up_col, g.trec,
+  void *arrays[] = {g.deg, g.src, g.rev, g.rrev, g.adj2, g.adjs, g.asum, g.qa, g.nbm, g.up_ptr, g.up_col, g.trec,
                     g.up_deg, g.dn_ptr, g.dn, g.tri_zero, g.j3_seeds, g.j3_off,
                     g.tri_rec0, g.tri_recL, g.tri_list[0], g.tri_list[1], g.tri_list[2], g.tri_list[3],
                     g.tri_recB[1], g.tri_recB[2], g.fin_list,
@@ -300,6 +300,7 @@ ef_status graph_load(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32
   ALLOC(g.deg, sizeof(int32_t) * std::max<size_t>(n, 1), "deg");
   ALLOC(g.src, sizeof(int32_t) * NNZ, "src");
   ALLOC(g.rev, sizeof(int32_t) * NNZ, "rev");
+  ALLOC(g.rrev, sizeof(int32_t) * NNZ, "reverse sum index");
   ALLOC(g.adj2, sizeof(int2) * NNZ, "adj2");
   ALLOC(g.asum, sizeof(int64_t) * std::max<size_t>(n, 1), "asum");
   ALLOC(g.qa, sizeof(longlong2) * std::max<size_t>(n, 1), "qa");
@@ -345,6 +346,10 @@ ef_status graph_load(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32
     }
     bool not_symmetric = false;
     hipError_t e = launch_graph_prep(g, tmp, work, not_symmetric, stream);
+    // the reverse-sum index starts as rev; big centres' rows remap it below
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(g.rrev, g.rev, sizeof(int32_t) * (size_t)nnz, hipMemcpyDeviceToDevice,
+                         stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e == hipSuccess && not_symmetric) {
       dev_free(g, work, work_bytes);

@@ -138,6 +138,9 @@ struct Graph {
   int32_t *deg = nullptr;      // k_v
   int32_t *src = nullptr;      // source node of every arc
   int32_t *rev = nullptr;      // index of the reverse arc
+  int32_t *rrev = nullptr;     // where the per-arc sums hold each arc's reverse: rev[e], or,
+                               // for an arc into a centre of more than kSuper neighbours, the
+                               // sorted position (adjs) at which that centre stores its sums
   int2 *adj2 = nullptr;        // (neighbour id, neighbour degree) per arc
   int2 *adjs = nullptr;        // rows of big centres ordered by neighbour degree (stable):
                                // (offset of the arc in its row, neighbour degree); null

@@ -301,7 +301,7 @@ static hipError_t persist_impl(const Graph &g, const PersistPlan &pl, void *R, v
   P.adj2 = g.adj2;
   P.adjs = g.adjs ? g.adjs : g.adj2;
   P.tri = TriArgs{g.up_ptr, g.up_col, g.up_deg, g.dn_ptr, g.dn, g.nnz / 2, Y, Z, ZT};
-  P.fin = FinArgs{g.row_ptr, g.deg, g.adj2, g.rev, g.trec, g.dn_ptr, g.asum, g.qa,
+  P.fin = FinArgs{g.row_ptr, g.deg, g.adj2, g.rrev, g.trec, g.dn_ptr, g.asum, g.qa,
                   R,         Y,     Z,      ZT,    ef,     D,      N,        fl};
   P.R = R;
   P.rec = rec;

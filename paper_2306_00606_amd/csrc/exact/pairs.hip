@@ -797,7 +797,7 @@ constexpr int kAggSlots = 8192;  // hash slots (load factor <= 1/2)
 template <typename T>
 __global__ __launch_bounds__(1024) void k_pairs_agg(const int32_t *__restrict__ row_ptr,
                                                     const int32_t *__restrict__ deg,
-                                                    const int2 *__restrict__ adj2,
+                                                    const int2 *__restrict__ adjs,
                                                     const BigCentre *__restrict__ big,
                                                     const int32_t *__restrict__ counters,
                                                     int32_t *__restrict__ agg_done,
@@ -826,7 +826,7 @@ __global__ __launch_bounds__(1024) void k_pairs_agg(const int32_t *__restrict__ 
     __syncthreads();
     // 1. histogram (find-or-insert; a probe gives up after kAggSlots slots)
     for (int32_t e = base + tid; e < base + k; e += 1024) {
-      const int32_t kap = adj2[e].y;
+      const int32_t kap = adjs[e].y;
       uint32_t h = ((uint32_t)kap * 0x9E3779u) & kMask;
       for (int t = 0; t < kAggSlots; ++t) {
         const int32_t cur = atomicCAS(&hkey[h], -1, kap);
@@ -899,9 +899,10 @@ __global__ __launch_bounds__(1024) void k_pairs_agg(const int32_t *__restrict__ 
       a.store(tsum, i);
     }
     __syncthreads();
-    // 4. R[e] = T(k_p) - g(c + 2 k_p)
+    // 4. R = T(k_p) - g(c + 2 k_p), stored by sorted position like the
+    // super-tile sums of a big centre
     for (int32_t e = base + tid; e < base + k; e += 1024) {
-      const int32_t kap = adj2[e].y;
+      const int32_t kap = adjs[e].y;
       uint32_t h = ((uint32_t)kap * 0x9E3779u) & kMask;
       while (hkey[h] != kap) h = (h + 1) & kMask;
       Acc<T> a;
@@ -963,7 +964,7 @@ __device__ __forceinline__ void arc_reduce_item(const int32_t *__restrict__ row_
       a.add_rec(r3);
     }
     for (; P < b; ++P) a.add_rec(Acc<T>::load_rec(rec, coli(P, j)));
-    a.store_arc(R, base + adjs[base + p].x);  // sorted position -> arc of the row
+    a.store_arc(R, base + p);  // by sorted position (a big centre's row layout)
   }
 }
 
@@ -1166,7 +1167,7 @@ static hipError_t pairs_impl(const Graph &g, const Bins &b, void *R, void *recor
   if (ev_mid) (void)hipEventRecord(ev_mid, st);
   if (agg_done && b.n_big > 0)
     hipLaunchKernelGGL(k_pairs_agg<T>, dim3(capped(b.n_big, 1 << 16)), dim3(1024), 0, st,
-                       g.row_ptr, g.deg, g.adj2, b.big, b.counters, agg_done, R);
+                       g.row_ptr, g.deg, g.adjs, b.big, b.counters, agg_done, R);
   if (b.n_tiles > 0)
     hipLaunchKernelGGL(k_pairs_big<T>, dim3(capped(b.n_tiles, 1 << 20)), dim3(1024), 0, st,
                        g.row_ptr, g.deg, g.adjs, b.big, b.tiles, b.n_tiles, records, agg_done);

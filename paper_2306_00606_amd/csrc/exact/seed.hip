@@ -157,7 +157,7 @@ template <int G> __device__ __forceinline__ DFv group_sum(DFv x) {
 // edges (record trec[e]; -1: no walk wrote one, nothing to add)
 template <typename T>
 __device__ __forceinline__ void fin_arcs(const int2 *__restrict__ adj2,
-                                         const int32_t *__restrict__ rev,
+                                         const int32_t *__restrict__ rrev,
                                          const int32_t *__restrict__ trec, const void *R,
                                          const TriSlot *__restrict__ Y, int32_t k, int32_t base,
                                          int32_t first, int32_t stride,
@@ -167,7 +167,7 @@ __device__ __forceinline__ void fin_arcs(const int2 *__restrict__ adj2,
   for (int32_t e = base + first; e < base + k; e += stride) {
     // a centre of degree 1 has no pairs: its row sums were never written
     if (k >= 2) S::add_arc(sacc, R, e);
-    if (adj2[e].y >= 2) S::add_arc(sacc, R, rev[e]);
+    if (adj2[e].y >= 2) S::add_arc(sacc, R, rrev[e]);
     const int32_t r = trec[e];
     if (r >= 0) {
       const TriSlot t = Y[r];
@@ -212,7 +212,7 @@ __device__ __forceinline__ void fin_store(int32_t v, int32_t k, int64_t As, long
 struct FinArgs {
   const int32_t *row_ptr, *deg;
   const int2 *adj2;
-  const int32_t *rev, *trec, *dn_ptr;
+  const int32_t *rrev, *trec, *dn_ptr;  // rrev: where R holds each arc's reverse sum
   const int64_t *asum;
   const longlong2 *qa;
   const void *R;
@@ -248,7 +248,7 @@ __device__ __forceinline__ void fin_groups(const FinArgs &A, const int32_t *node
     double tfix = 0.0;
     int64_t Tc = 0;
     if (v >= 0)
-      fin_arcs<T>(A.adj2, A.rev, A.trec, A.R, A.Y, k, A.row_ptr[v], sub, G, sacc, tfix, Tc);
+      fin_arcs<T>(A.adj2, A.rrev, A.trec, A.R, A.Y, k, A.row_ptr[v], sub, G, sacc, tfix, Tc);
     sacc = group_sum<G>(sacc);
     tfix = group_sum<G>(tfix);
     Tc = group_sum<G>(Tc);
@@ -294,7 +294,7 @@ __device__ __forceinline__ void fin_lanes(const FinArgs &A, int64_t lo, int64_t 
       for (int i = 0; i < K; ++i) {
         const int32_t e = base + (i < k ? i : k - 1);
         ka[i] = A.adj2[e].y;
-        rv[i] = A.rev[e];
+        rv[i] = A.rrev[e];
         tr[i] = A.trec[e];
       }
       decltype(RVal<T>::load(A.R, 0)) own[K], back[K];
@@ -336,7 +336,7 @@ __device__ __forceinline__ void fin_hubs(const FinArgs &A, const int32_t *nodes,
     Acc sacc = Acc();
     double tfix = 0.0;
     int64_t Tc = 0;
-    fin_arcs<T>(A.adj2, A.rev, A.trec, A.R, A.Y, k, A.row_ptr[v], tid, (int32_t)blockDim.x, sacc,
+    fin_arcs<T>(A.adj2, A.rrev, A.trec, A.R, A.Y, k, A.row_ptr[v], tid, (int32_t)blockDim.x, sacc,
                 tfix, Tc);
     sacc = wave_sum(sacc);
     tfix = wave_sum_f64(tfix);
@@ -398,7 +398,7 @@ hipError_t launch_finalize_cluster(const Graph &g, ef_prec prec, const void *R, 
   const int64_t bc = g.n_fin_half > 0 ? cap_blocks((g.n_fin_half * 32 + 255) / 256, 1 << 18) : 0;
   const int64_t bg = g.n_fin_group > 0 ? cap_blocks((g.n_fin_group * 8 + 255) / 256, 1 << 18) : 0;
   const int64_t bl = cap_blocks(((int64_t)g.n + 255) / 256, 1 << 17);
-  const FinArgs A{g.row_ptr, g.deg, g.adj2, g.rev, g.trec, g.dn_ptr, g.asum, g.qa,
+  const FinArgs A{g.row_ptr, g.deg, g.adj2, g.rrev, g.trec, g.dn_ptr, g.asum, g.qa,
                   R,         Y,     Z,      ZT,    ef,     D,      N,        fl};
   const unsigned grid = (unsigned)(bh + bw + bc + bg + bl);
   if (prec == EF_PREC_FP64)

@@ -539,6 +539,17 @@ __global__ void k_big_pack(const int32_t *__restrict__ row_ptr, const int32_t *_
   }
 }
 
+// a big centre stores the per-arc sums of its row by sorted position: the
+// reverse of the arc at sorted position x of its row finds its sum at x
+__global__ void k_rrev_big(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ big,
+                           int32_t nbig, const int32_t *__restrict__ rev,
+                           const int2 *__restrict__ adjs, int32_t *__restrict__ rrev) {
+  for (int32_t i = blockIdx.x; i < nbig; i += gridDim.x) {
+    const int32_t v = big[i], b = row_ptr[v], e = row_ptr[v + 1];
+    for (int32_t x = b + threadIdx.x; x < e; x += blockDim.x) rrev[rev[b + adjs[x].x]] = x;
+  }
+}
+
 hipError_t launch_big_sort(Graph &g, const int32_t *big, int32_t nbig, int32_t *scratch,
                            int32_t *seg, void *temp, size_t &temp_bytes, hipStream_t st) {
   const int64_t nnz = g.nnz;
@@ -560,6 +571,8 @@ hipError_t launch_big_sort(Graph &g, const int32_t *big, int32_t nbig, int32_t *
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_big_pack, dim3(grid), dim3(256), 0, st, g.row_ptr, big, nbig, kout, vout,
                      g.adjs);
+  hipLaunchKernelGGL(k_rrev_big, dim3(grid), dim3(256), 0, st, g.row_ptr, big, nbig, g.rev,
+                     g.adjs, g.rrev);
   return hipGetLastError();
 }
 
