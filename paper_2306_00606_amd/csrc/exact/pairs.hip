@@ -916,7 +916,8 @@ __global__ __launch_bounds__(1024) void k_pairs_agg(const int32_t *__restrict__ 
 }
 
 // Per-arc sum of the super-tile records of big centres, fixed order, for the
-// neighbour at sorted position p (stored at its arc, offset adjs[base + p].x):
+// neighbour at sorted position p (stored at base + p: a big centre keeps its
+// row's sums in sorted order; Graph::rrev points each reverse arc there):
 // R = sum_{Q >= b} row part of (b, Q)  +  sum_{P < b} column part of (P, b)
 // One workgroup per (big centre, super-block b): the 1024 arcs of block b.
 template <typename T>
