@@ -154,8 +154,9 @@ template <int G> __device__ __forceinline__ DFv group_sum(DFv x) {
 
 // arcs first, first + stride, ... of node v: its own row sums R[e], the
 // reverse arcs' sums R[rrev e] (a big centre keeps its row's sums in sorted
-// order, so its own sum over the row is the same set), and the triangle credits to v kept with each of its
-// edges (record trec[e]; -1: no walk wrote one, nothing to add)
+// order, so its own sum over the row is the same set), and the triangle
+// credits to v kept with each of its edges (record trec[e]; -1: no walk wrote
+// one, nothing to add)
 template <typename T>
 __device__ __forceinline__ void fin_arcs(const int2 *__restrict__ adj2,
                                          const int32_t *__restrict__ rrev,
