@@ -408,11 +408,12 @@ ef_status graph_load(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32
   inf.nnz = nnz;
   inf.max_degree = kmax;
   inf.up_arcs = nnz / 2;
-  // degree-ordered rows of the big centres (the super-tile pair loop)
+  // degree-ordered rows of the mid and big centres (the tile pair loops,
+  // which store their per-arc sums by sorted position)
   {
     std::vector<int32_t> hb;
     for (int32_t v = 0; v < n; ++v)
-      if (g.h_deg[v] > kSuper) hb.push_back(v);
+      if (g.h_deg[v] > kSmallMax) hb.push_back(v);
     if (!hb.empty()) {
       ALLOC(g.adjs, sizeof(int2) * NNZ, "degree-ordered rows");
       const int32_t nbig = (int32_t)hb.size();

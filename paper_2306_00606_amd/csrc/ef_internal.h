@@ -139,12 +139,12 @@ struct Graph {
   int32_t *src = nullptr;      // source node of every arc
   int32_t *rev = nullptr;      // index of the reverse arc
   int32_t *rrev = nullptr;     // where the per-arc sums hold each arc's reverse: rev[e], or,
-                               // for an arc into a centre of more than kSuper neighbours, the
-                               // sorted position (adjs) at which that centre stores its sums
+                               // for an arc into a centre of more than kSmallMax neighbours,
+                               // the sorted position (adjs) at which that centre stores its sums
   int2 *adj2 = nullptr;        // (neighbour id, neighbour degree) per arc
-  int2 *adjs = nullptr;        // rows of big centres ordered by neighbour degree (stable):
-                               // (offset of the arc in its row, neighbour degree); null
-                               // when no centre has more than kSuper neighbours
+  int2 *adjs = nullptr;        // rows of mid and big centres ordered by neighbour degree
+                               // (stable): (offset of the arc in its row, neighbour degree);
+                               // null when no centre has more than kSmallMax neighbours
   int64_t *asum = nullptr;     // sum of neighbour degrees per node
   longlong2 *qa = nullptr;     // per node: {sum of squared neighbour degrees, sum of neighbours' asum}
   NbrMoments *nbm = nullptr;   // per node: sums of its neighbours' degrees to the powers 1..4,

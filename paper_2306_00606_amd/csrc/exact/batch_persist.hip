@@ -122,17 +122,17 @@ __device__ inline void persist_item(const PersistArgs &P, const int4 it, unsigne
       break;
     case PI_PAIR_M4:
       for (int64_t gi = 0; gi < (cnt + 3) / 4; ++gi)
-        pairs_mid_group<T, 4>(P.row_ptr, P.deg, P.adj2, P.pair[4] + a, cnt, gi, P.R,
+        pairs_mid_group<T, 4>(P.row_ptr, P.deg, P.adjs, P.pair[4] + a, cnt, gi, P.R,
                               *reinterpret_cast<MidLds<T, 4> *>(pool));
       break;
     case PI_PAIR_M2:
       for (int64_t gi = 0; gi < (cnt + 1) / 2; ++gi)
-        pairs_mid_group<T, 2>(P.row_ptr, P.deg, P.adj2, P.pair[5] + a, cnt, gi, P.R,
+        pairs_mid_group<T, 2>(P.row_ptr, P.deg, P.adjs, P.pair[5] + a, cnt, gi, P.R,
                               *reinterpret_cast<MidLds<T, 2> *>(pool));
       break;
     case PI_PAIR_M1:
       for (int64_t gi = 0; gi < cnt; ++gi)
-        pairs_mid_group<T, 1>(P.row_ptr, P.deg, P.adj2, P.pair[6] + a, cnt, gi, P.R,
+        pairs_mid_group<T, 1>(P.row_ptr, P.deg, P.adjs, P.pair[6] + a, cnt, gi, P.R,
                               *reinterpret_cast<MidLds<T, 1> *>(pool));
       break;
     case PI_PAIR_BIG:

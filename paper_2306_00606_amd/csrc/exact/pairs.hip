@@ -1155,16 +1155,17 @@ static hipError_t pairs_impl(const Graph &g, const Bins &b, void *R, void *recor
                        dim3(256), 0, st, g.row_ptr, g.deg, g.adj2, b.small[3], b.n_smallb[3], R);
   if (ev_small) (void)hipEventRecord(ev_small, st);
   // class c holds centres of up to 4 << c blocks: one workgroup of that
-  // many wavefronts each
+  // many wavefronts each, over the degree-ordered rows (adjs), so that the
+  // per-arc sums go out by sorted position like a big centre's
   if (b.n_midc[0] > 0)
     hipLaunchKernelGGL((k_pairs_mid<T, 4>), dim3(capped(b.n_midc[0], 1 << 20)), dim3(256), 0,
-                       st, g.row_ptr, g.deg, g.adj2, b.midc[0], b.n_midc[0], R);
+                       st, g.row_ptr, g.deg, g.adjs, b.midc[0], b.n_midc[0], R);
   if (b.n_midc[1] > 0)
     hipLaunchKernelGGL((k_pairs_mid<T, 8>), dim3(capped(b.n_midc[1], 1 << 20)), dim3(512), 0,
-                       st, g.row_ptr, g.deg, g.adj2, b.midc[1], b.n_midc[1], R);
+                       st, g.row_ptr, g.deg, g.adjs, b.midc[1], b.n_midc[1], R);
   if (b.n_midc[2] > 0)
     hipLaunchKernelGGL((k_pairs_mid<T, 16>), dim3(capped(b.n_midc[2], 1 << 20)), dim3(1024), 0,
-                       st, g.row_ptr, g.deg, g.adj2, b.midc[2], b.n_midc[2], R);
+                       st, g.row_ptr, g.deg, g.adjs, b.midc[2], b.n_midc[2], R);
   if (ev_mid) (void)hipEventRecord(ev_mid, st);
   if (agg_done && b.n_big > 0)
     hipLaunchKernelGGL(k_pairs_agg<T>, dim3(capped(b.n_big, 1 << 16)), dim3(1024), 0, st,
