@@ -154,8 +154,15 @@ ef_status ef_graph_load_csr(int32_t n, int64_t nnz, const int32_t *row_ptr,
 ef_status ef_graph_from_edges(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
                               void *hip_stream, ef_graph **out);
 
+/* Release a graph handle and every device array the library allocated for it
+ * (host-loaded CSR copies included; borrowed EF_DEVICE_PTRS arrays stay the
+ * caller's). hipFree waits for work still queued on the graph, so the handle
+ * may be freed right after an asynchronous ef_compute. Bookkeeping only: no
+ * step of the method. EF_ERR_ARG for a null handle; g is invalid afterwards. */
 ef_status ef_graph_free(ef_graph *g);
 
+/* Copy the load-time figures of g (sizes, W of Algorithm 1, degree sums) into
+ * the caller's *out. Host only, no device work. EF_ERR_ARG if g or out is null. */
 ef_status ef_graph_info_get(const ef_graph *g, ef_graph_info *out);
 
 /* Expected Force (Eq. 1) of all nodes (seeds == NULL: outputs indexed by node
@@ -325,8 +332,14 @@ ef_status ef_batch_autotune(ef_batch *b, ef_prec prec);
 ef_status ef_batch_compute(ef_batch *b, ef_prec prec, double *ef, int64_t *D, int64_t *N,
                            uint32_t flags, void *hip_stream);
 
+/* Copy the batch's sizes, tuning record and last replay time into the
+ * caller's *out. Host only, no device work. EF_ERR_ARG if b or out is null. */
 ef_status ef_batch_stats_get(const ef_batch *b, ef_batch_stats *out);
 
+/* Release a batch: its captured graph, persistent-kernel schedule, device
+ * arrays, events and own stream. hipFree waits for queued work. Bookkeeping
+ * only: no step of the method. EF_ERR_ARG for a null handle; b is invalid
+ * afterwards. */
 ef_status ef_batch_free(ef_batch *b);
 
 /* ---------------------------------------------------------------------------
@@ -432,7 +445,9 @@ ef_status ef_topk_surrogate(ef_graph *g, ef_surrogate *s, int32_t k, int32_t rer
                             int32_t *nodes, double *ef_exact, ef_judge_report *rep,
                             void *hip_stream);
 
-/* Counters and (with EF_PROFILE) phase times of the last ef_compute on g. */
+/* Copy the counters and (with EF_PROFILE) phase times of the last ef_compute
+ * on g into the caller's *out. Host only: the figures are those the call left
+ * after its stream was synchronised. EF_ERR_ARG if g or out is null. */
 ef_status ef_stats(const ef_graph *g, ef_run_stats *out);
 
 #ifdef __cplusplus
